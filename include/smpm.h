@@ -1,0 +1,189 @@
+/*
+ * libsmpm — deflated Schur complement solver for the SMPM discretization of the
+ * 2-D Poisson-Neumann problem (Joshi & Diamessis, arXiv 1601.03432), on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. 1.2, Eq. poisson): lap u = f on a Cartesian domain split into
+ * m_y x m_x rectangular elements with n Gauss-Lobatto-Legendre points per
+ * direction, n.grad u = g on the boundary.  The SMPM operator L (Eq.
+ * smpm_poisson) is split as L = A + E B (Sec. 1.3) and the interface system
+ * S x = b with S = I + B A^{-1} E (Eq. schur_complement_system) is solved by
+ * right-preconditioned GMRES with block-Jacobi preconditioning and deflation
+ * (Sec. 2, Algorithm 3, Eq. deflated_schur).
+ *
+ * Sign convention.  Writing the augmented system of Eq. blocksystem as a 2x2
+ * block system with A_II = A, A_IG = E, A_GI = B, A_GG = -I, the textbook Schur
+ * complement A_GG - A_GI A_II^{-1} A_IG equals -S.  This library uses the
+ * paper's S = I + B A^{-1} E throughout.
+ *
+ * Data layouts (all FP64 unless stated; multi-RHS data is column-blocked, the
+ * right-hand-side index outermost: v[i + len*col]):
+ *   r-vectors (f, u; r = n^2 m_x m_y): node (p, q) of element e = iy*m_x + ix
+ *     at e*n^2 + q*n + p, p the x index.
+ *   g (boundary data, 2n(m_x + m_y) per column): south edge (m_x*n values,
+ *     x ascending), north edge (m_x*n), west edge (m_y*n, y ascending), east
+ *     edge (m_y*n).  g is the outward normal derivative n.grad u.
+ *   k-vectors (interface grid Gamma, k = 2 n d): one slot per node of every
+ *     inter-element side.  Slot = side_index*n + t, sides numbered
+ *     element-major and within an element W, E, S, N (inter-element sides
+ *     only); t runs along the side (q for W/E sides, p for S/N sides).  An
+ *     element-corner node on two inter-element sides owns two slots.
+ *   d-vectors (interfaces): vertical interfaces (between (iy,ix) and
+ *     (iy,ix+1)) row-major, then horizontal ones (between (iy,ix), (iy+1,ix)).
+ *
+ * Penalty (Sec. 1.2 leaves its value open): tau = 2*penalty/(omega_0*h_perp)
+ * on every element side, omega_0 = 2/(N(N+1)) the GLL end weight and h_perp
+ * the element's extent normal to the side.  Recommended penalty: -32.
+ *
+ * Ownership and streams.  A context owns its setup data and device workspace;
+ * smpm_destroy releases them.  The caller owns every vector argument.  Device
+ * pointers must be device memory of the current HIP device; `stream` is a
+ * hipStream_t passed as void* (NULL = the default stream).  Apply/project
+ * calls are asynchronous and stream-ordered; smpm_setup and smpm_solve
+ * synchronize the stream before returning.  A context is used by one host
+ * thread at a time.
+ *
+ * Errors.  Every int-returning call returns SMPM_OK (0) or a negative
+ * smpm_status; smpm_last_error() gives a thread-local message.  A failed call
+ * leaves outputs unspecified and the context valid.  Input and output
+ * pointers must not alias (smpm_project may run in place).
+ */
+#ifndef SMPM_H
+#define SMPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smpm_ctx smpm_ctx;
+
+enum smpm_status {
+  SMPM_OK = 0,
+  SMPM_EINVAL = -1,      /* invalid argument or grid */
+  SMPM_ENOMEM = -2,      /* device or host allocation failed */
+  SMPM_EHIP = -3,        /* a HIP runtime call failed */
+  SMPM_ENOCONV = -4,     /* GMRES / refinement did not reach the tolerance */
+  SMPM_ESINGULAR = -5,   /* an element, block or coarse factorization failed */
+  SMPM_ENODEVICE = -6    /* the context was built without a device (smpm_plan) */
+};
+
+enum smpm_precision {
+  SMPM_FP64 = 0,         /* everything in FP64 */
+  SMPM_MIXED_FP32 = 1,   /* FP32 Schur/preconditioner applies inside FP64 refinement */
+  SMPM_MIXED_BF16 = 2    /* BF16 operators, FP32 accumulation, FP64 refinement */
+};
+
+enum smpm_projection {
+  SMPM_PROJ_L = 0,       /* r-vector: x - u_L (u_L^T x)            (Eq. regularize_poisson) */
+  SMPM_PROJ_S = 1,       /* k-vector: x - u_S (u_S^T x)            (Eq. regularize_schur)   */
+  SMPM_PROJ_P = 2,       /* k-vector: x - S Z G Z^T x, G = C^+      (Eq. projection1)        */
+  SMPM_PROJ_Q = 3,       /* k-vector: x - Z G Z^T S x               (Eq. projection2)        */
+  SMPM_PROJ_MEAN = 4     /* r-vector: x - (w^T x / w^T 1) 1, w = GLL quadrature weights     */
+};
+
+enum smpm_export_what {
+  SMPM_EXPORT_SCHUR = 0,        /* S, k x k, COO                          */
+  SMPM_EXPORT_FLUX_SOLVE = 1,   /* B A^{-1}, k x r, COO                   */
+  SMPM_EXPORT_PRECOND_INV = 2,  /* M^{-1}, k x k, COO                     */
+  SMPM_EXPORT_COARSE = 3,       /* C = Z^T S Z, d x d dense row-major     */
+  SMPM_EXPORT_COARSE_PINV = 4   /* G = C^+ (C^{-1} if C is nonsingular)   */
+};
+
+typedef struct smpm_solve_opts {
+  double tol;         /* GMRES stop: least-squares residual <= tol * ||P b_hat|| (default 1e-10) */
+  int maxit;          /* maximum GMRES iterations per solve or refinement cycle (default 400)    */
+  int precision;      /* smpm_precision (default SMPM_FP64)                                      */
+  int transpose;      /* 1: solve the adjoint system L^T mu = c instead (default 0)               */
+  int variant;        /* 3: deflated + block-Jacobi (Algorithm 3), 2: block-Jacobi only
+                         (Algorithm 2), 1: unpreconditioned (Algorithm 1); default 3               */
+  double inner_tol;   /* mixed precision: inner GMRES tolerance (default 1e-6)                   */
+  int max_refine;     /* mixed precision: maximum refinement cycles (default 20)                 */
+} smpm_solve_opts;
+
+typedef struct smpm_solve_info {
+  int iterations;           /* GMRES iterations, summed over refinement cycles, max over columns */
+  int refinements;          /* refinement cycles (1 for FP64)                                    */
+  double rel_residual;      /* max over columns of the FP64 ||b_hat - S x|| / ||b_hat||          */
+  double removed_component; /* u_L^T (f + T g) of column 0 (the projected-out incompatibility)   */
+} smpm_solve_info;
+
+/* Fills `opts` with the defaults listed above. */
+void smpm_default_opts(smpm_solve_opts *opts);
+
+/* Builds the host-side plan only (no device use): GLL grid, element operators,
+ * block-Jacobi inverses and the coarse matrix, all FP64 (Secs. 1.2-2).
+ * x_breaks (m_x+1) and y_breaks (m_y+1) are host arrays of strictly increasing
+ * element breakpoints.  Requires m_x*m_y >= 2, 3 <= n <= 32, penalty finite and
+ * nonzero, d <= 4096.  The context supports sizes/exports only; device calls
+ * on it return SMPM_ENODEVICE.  *out is set only on success. */
+int smpm_plan(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
+              double penalty, smpm_ctx **out);
+
+/* smpm_plan + upload to the current device + computation of the null vectors
+ * u_S (left null vector of S) and u_L (left null vector of L, Sec. 1.4) by an
+ * adjoint deflated GMRES solve.  Synchronous. */
+int smpm_setup(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
+               double penalty, void *stream, smpm_ctx **out);
+
+/* Releases everything the context owns (NULL is ignored). */
+void smpm_destroy(smpm_ctx *ctx);
+
+/* r = n^2 m_x m_y nodes, k = 2 n d interface slots, d interfaces. */
+int smpm_sizes(const smpm_ctx *ctx, int64_t *r, int64_t *k, int64_t *d);
+
+/* Host array slot_to_node[k]: the node (r-index) each slot sits on (E as a map). */
+int smpm_slot_map(const smpm_ctx *ctx, int64_t *slot_to_node);
+
+/* Host arrays x[r], y[r]: node coordinates, as computed by the library. */
+int smpm_node_coords(const smpm_ctx *ctx, double *x, double *y);
+
+/* Host array w[r]: GLL quadrature weights omega_p omega_q w_e h_e / 4. */
+int smpm_quadrature_weights(const smpm_ctx *ctx, double *w);
+
+/* Host copies of the setup operators for inspection (see smpm_export_what).
+ * COO kinds: call with rows/cols/vals NULL to get *count, then again with
+ * arrays of that length.  Dense kinds: *count = d*d, vals receives them. */
+int smpm_export(const smpm_ctx *ctx, int what, int64_t *count, int64_t *rows, int64_t *cols,
+                double *vals);
+
+/* Host copies of the unit null vectors computed at setup: uL[r], uS[k]
+ * (either may be NULL).  SMPM_ENODEVICE for a plan-only context. */
+int smpm_null_vectors(const smpm_ctx *ctx, double *uL, double *uS);
+
+/* Sv = S v (transpose = 0) or S^T v (transpose = 1) for nrhs k-vectors
+ * (Eq. schur_complement_system).  Device pointers, column-blocked. */
+int smpm_schur_apply(smpm_ctx *ctx, const double *v, double *Sv, int nrhs, int transpose,
+                     void *stream);
+
+/* y = M^{-1} x (or M^{-T} x): the block-Jacobi preconditioner of Sec. 2 with
+ * checkerboard blocks (red element slots plus the neighbours' facing slots). */
+int smpm_precond_apply(smpm_ctx *ctx, const double *x, double *y, int nrhs, int transpose,
+                       void *stream);
+
+/* One of the projections of smpm_projection on nrhs vectors (r- or k-length).
+ * transpose = 1 gives the transposed projection (P^T, Q^T; L, S, MEAN are
+ * replaced by their adjoint counterparts: 1/sqrt(r), v0/|v0| and w/|w| as
+ * the projected directions, see the design notes).  in == out is allowed. */
+int smpm_project(smpm_ctx *ctx, int which, const double *in, double *out, int nrhs,
+                 int transpose, void *stream);
+
+/* Solves L u = f~ for nrhs right-hand sides by Algorithm 3 (Sec. 2):
+ * f~ = (I - u_L u_L^T)(f + T g), b_S = B A^{-1} f~ projected out of u_S, GMRES
+ * on P S M^{-1}, x = Q M^{-1} x_1 + Z G Z^T b_hat, u = A^{-1}(f~ - E x), and the
+ * additive constant fixed by w^T u = 0.  f, u: device r x nrhs; g: device
+ * 2n(m_x+m_y) x nrhs or NULL (zero Neumann data).  opts/info may be NULL.
+ * Returns SMPM_ENOCONV if some column missed the tolerance (u still holds the
+ * last iterate).  Synchronizes the stream. */
+int smpm_solve(smpm_ctx *ctx, const double *f, const double *g, double *u, int nrhs,
+               const smpm_solve_opts *opts, smpm_solve_info *info, void *stream);
+
+/* Thread-local text of the last error ("" if none). */
+const char *smpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMPM_H */

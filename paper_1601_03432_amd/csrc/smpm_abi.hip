@@ -1,0 +1,789 @@
+// C ABI of libsmpm: context lifetime, device upload, operator applies,
+// projections and the Algorithm 3 GMRES driver.  Every numerical step runs in
+// the kernels of smpm_kernels.hip; the host only sequences launches and reads
+// per-column residual estimates to decide convergence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/smpm.h"
+#include "smpm_kernels.h"
+#include "smpm_plan.h"
+
+using namespace smpm;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(SMPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Solver workspace sized for (nrhs, maxit); grown on demand.
+struct Workspace {
+  int nrhs = 0, maxit = 0;
+  double *rhs = nullptr, *ft = nullptr, *bS = nullptr, *bhat = nullptr, *x = nullptr;
+  double *z = nullptr, *t = nullptr, *w = nullptr, *c = nullptr, *c2 = nullptr;
+  double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+  double *h1 = nullptr, *h2 = nullptr, *scal = nullptr, *scal2 = nullptr, *res = nullptr, *y = nullptr;
+  double* part = nullptr;
+  int *active = nullptr, *jcount = nullptr;
+  std::vector<void*> mem;
+};
+
+}  // namespace
+
+struct smpm_ctx {
+  Plan plan;
+  bool device = false;
+  int dev_id = -1;
+  DevPlan dp{};
+  std::vector<void*> mem;                    // setup allocations
+  double *uL = nullptr, *uS = nullptr, *v0hat = nullptr, *wq = nullptr, *ones = nullptr;
+  double *rhat = nullptr;                    // 1/sqrt(r) vector (left null vector of L^T)
+  double wsum = 0;
+  std::vector<double> h_uL, h_uS;
+  Workspace ws;
+  ~smpm_ctx() {
+    if (device) {
+      for (void* p : ws.mem) (void)hipFree(p);
+      for (void* p : mem) (void)hipFree(p);
+    }
+  }
+};
+
+namespace {
+
+template <class T>
+int upload(smpm_ctx* c, const std::vector<T>& v, const T** out, hipStream_t s) {
+  if (v.empty()) {
+    *out = nullptr;
+    return SMPM_OK;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) return fail(SMPM_ENOMEM, "hipMalloc failed in setup");
+  c->mem.push_back(p);
+  HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  *out = static_cast<const T*>(p);
+  return SMPM_OK;
+}
+
+int dalloc(std::vector<void*>& mem, double** p, size_t count) {
+  if (count == 0) count = 1;
+  if (hipMalloc((void**)p, count * sizeof(double)) != hipSuccess) return fail(SMPM_ENOMEM, "hipMalloc failed");
+  mem.push_back(*p);
+  return SMPM_OK;
+}
+
+int ialloc(std::vector<void*>& mem, int** p, size_t count) {
+  if (count == 0) count = 1;
+  if (hipMalloc((void**)p, count * sizeof(int)) != hipSuccess) return fail(SMPM_ENOMEM, "hipMalloc failed");
+  mem.push_back(*p);
+  return SMPM_OK;
+}
+
+int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
+  Workspace& w = c->ws;
+  if (w.nrhs >= nrhs && w.maxit >= maxit) return SMPM_OK;
+  nrhs = std::max(nrhs, w.nrhs);
+  maxit = std::max(maxit, w.maxit);
+  for (void* p : w.mem) (void)hipFree(p);
+  w = Workspace();
+  const Plan& P = c->plan;
+  const size_t r = P.r, k = P.k, d = std::max<int64_t>(P.d, 1), R = nrhs, ldh = maxit + 1;
+  int rc = SMPM_OK;
+  rc |= dalloc(w.mem, &w.rhs, r * R);
+  rc |= dalloc(w.mem, &w.ft, r * R);
+  rc |= dalloc(w.mem, &w.bS, k * R);
+  rc |= dalloc(w.mem, &w.bhat, k * R);
+  rc |= dalloc(w.mem, &w.x, k * R);
+  rc |= dalloc(w.mem, &w.z, k * R);
+  rc |= dalloc(w.mem, &w.t, k * R);
+  rc |= dalloc(w.mem, &w.w, k * R);
+  rc |= dalloc(w.mem, &w.c, d * R);
+  rc |= dalloc(w.mem, &w.c2, d * R);
+  rc |= dalloc(w.mem, &w.V, k * ldh * R);
+  rc |= dalloc(w.mem, &w.H, ldh * maxit * R);
+  rc |= dalloc(w.mem, &w.cs, ldh * R);
+  rc |= dalloc(w.mem, &w.sn, ldh * R);
+  rc |= dalloc(w.mem, &w.g, ldh * R);
+  rc |= dalloc(w.mem, &w.h1, ldh * R);
+  rc |= dalloc(w.mem, &w.h2, ldh * R);
+  rc |= dalloc(w.mem, &w.scal, 4 * R);
+  rc |= dalloc(w.mem, &w.scal2, 4 * R);
+  rc |= dalloc(w.mem, &w.res, R);
+  rc |= dalloc(w.mem, &w.y, maxit * R);
+  const size_t nch = reduce_chunks(std::max<int64_t>(P.r, P.k));
+  rc |= dalloc(w.mem, &w.part, nch * ldh * R);
+  rc |= ialloc(w.mem, &w.active, R);
+  rc |= ialloc(w.mem, &w.jcount, R);
+  if (rc != SMPM_OK) return SMPM_ENOMEM;
+  w.nrhs = nrhs;
+  w.maxit = maxit;
+  return SMPM_OK;
+}
+
+int check_device(const smpm_ctx* c) {
+  if (!c) return fail(SMPM_EINVAL, "null context");
+  if (!c->device) return fail(SMPM_ENODEVICE, "context has no device data (built by smpm_plan)");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != c->dev_id)
+    return fail(SMPM_EINVAL, "current HIP device differs from the context's device");
+  return SMPM_OK;
+}
+
+// ---------------------------------------------------------------- operator pieces
+
+enum OpKind { OP_S = 1, OP_SM = 2, OP_PSM = 3, OP_RANK1 = 4 };
+
+// w = op(v) for the chosen operator; transpose selects the adjoint pieces.
+void apply_op(smpm_ctx* c, int kind, bool tr, const double* v, double* w, int nrhs, const int* act,
+              hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  if (kind == OP_S) {
+    launch_schur(P, v, w, nrhs, tr, act, s);
+    return;
+  }
+  launch_precond(P, v, W.z, nrhs, tr, act, s);
+  if (kind == OP_SM) {
+    launch_schur(P, W.z, w, nrhs, tr, act, s);
+    return;
+  }
+  if (kind == OP_RANK1) {
+    // (S^T + v0hat v0hat^T) M^{-T} v: nonsingular, its inverse transpose maps v0hat to u_S
+    launch_schur(P, W.z, w, nrhs, true, act, s);
+    launch_mdot(c->v0hat, 0, 0, 1, W.z, P.k, nullptr, P.k, nrhs, W.part, W.scal2, act, s);
+    launch_axpy_shared(w, P.k, c->v0hat, W.scal2, -1.0, w, P.k, nrhs, s);
+    return;
+  }
+  launch_schur(P, W.z, W.t, nrhs, tr, act, s);
+  launch_iface_sum(P, W.t, W.c, nrhs, act, s);
+  launch_coarse(P, W.c, W.c2, nrhs, tr, act, s);
+  launch_prolong(P, W.t, W.c2, w, nrhs, tr ? 2 : 1, -1.0, act, s);
+}
+
+// Right-preconditioned GMRES from x0 = 0 (Algorithm 3 step 4 and 5-8 for OP_PSM):
+// Arnoldi with classical Gram-Schmidt applied twice, Givens rotations, per-column
+// stopping |g_{j+1}| <= tol * beta.  b, x: k x nrhs.  Returns iterations (max over
+// columns) or a negative status.
+int gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, double tol, int maxit,
+          std::vector<int>& iters, hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  const int64_t k = P.k;
+  const int ldh = W.maxit + 1;
+  const int64_t vcs = (int64_t)k * ldh;  // V column stride
+  iters.assign(nrhs, 0);
+  std::vector<int> act(nrhs, 1);
+  HIPCHK(hipMemcpyAsync(W.active, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(W.H, 0, sizeof(double) * (size_t)ldh * W.maxit * nrhs, s));
+  HIPCHK(hipMemsetAsync(W.g, 0, sizeof(double) * (size_t)ldh * nrhs, s));
+  // r0 = P b (deflated) or b
+  double* r0 = W.w;
+  if (kind == OP_PSM) {
+    launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
+    launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
+    launch_prolong(P, b, W.c2, r0, nrhs, tr ? 2 : 1, -1.0, nullptr, s);
+  } else {
+    HIPCHK(hipMemcpyAsync(r0, b, sizeof(double) * k * nrhs, hipMemcpyDeviceToDevice, s));
+  }
+  launch_mdot(r0, 0, k, 1, r0, k, nullptr, k, nrhs, W.part, W.scal, nullptr, s);
+  std::vector<double> beta2(nrhs);
+  HIPCHK(hipMemcpyAsync(beta2.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> beta(nrhs), gi(nrhs * (size_t)ldh, 0.0);
+  for (int col = 0; col < nrhs; ++col) {
+    beta[col] = std::sqrt(beta2[col]);
+    if (!(beta[col] > 0.0)) act[col] = 0;
+  }
+  for (int col = 0; col < nrhs; ++col) gi[(size_t)col * ldh] = beta[col];
+  HIPCHK(hipMemcpyAsync(W.g, gi.data(), gi.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(W.active, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+  launch_scale_inv(r0, k, W.scal, true, W.V, vcs, k, nrhs, nullptr, s);
+  int jmax = 0;
+  std::vector<double> res(nrhs);
+  int nact = 0;
+  for (int col = 0; col < nrhs; ++col) nact += act[col];
+  for (int j = 0; j < maxit && nact > 0; ++j) {
+    double* vj = W.V + (int64_t)j * k;
+    apply_op(c, kind, tr, vj, W.w, nrhs, W.active, s);
+    // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2
+    launch_mdot(W.V, k, vcs, j + 1, W.w, k, nullptr, k, nrhs, W.part, W.h1, W.active, s);
+    launch_mupdate(W.w, k, W.V, k, vcs, j + 1, W.h1, 1.0, k, nrhs, W.active, s);
+    launch_mdot(W.V, k, vcs, j + 1, W.w, k, nullptr, k, nrhs, W.part, W.h2, W.active, s);
+    launch_mupdate(W.w, k, W.V, k, vcs, j + 1, W.h2, 1.0, k, nrhs, W.active, s);
+    launch_add(W.h1, W.h2, 1.0, W.h1, (int64_t)(j + 1) * nrhs, 1, s);
+    launch_mdot(W.w, 0, k, 1, W.w, k, nullptr, k, nrhs, W.part, W.scal, W.active, s);
+    launch_givens(W.H, ldh, W.cs, W.sn, W.g, W.h1, W.scal, j, nrhs, W.res, W.active, s);
+    launch_scale_inv(W.w, k, W.scal, true, W.V + (int64_t)(j + 1) * k, vcs, k, nrhs, W.active, s);
+    HIPCHK(hipMemcpyAsync(res.data(), W.res, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool changed = false;
+    for (int col = 0; col < nrhs; ++col) {
+      if (!act[col]) continue;
+      iters[col] = j + 1;
+      if (!(res[col] > tol * beta[col]) || j + 1 == maxit) {
+        act[col] = 0;
+        --nact;
+        changed = true;
+      }
+    }
+    jmax = j + 1;
+    if (changed) HIPCHK(hipMemcpyAsync(W.active, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  // y = H^{-1} g, x1 = V y
+  HIPCHK(hipMemcpyAsync(W.jcount, iters.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+  launch_lsq(W.H, ldh, W.g, W.jcount, W.y, nrhs, s);
+  HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * k * nrhs, s));
+  // the coefficient array of column col starts at y + col*maxit; mupdate reads coef + col*nvec
+  for (int col = 0; col < nrhs; ++col)
+    if (iters[col] > 0)
+      launch_mupdate(x + (int64_t)col * k, k, W.V + (int64_t)col * vcs, k, 0, iters[col],
+                     W.y + (int64_t)col * W.maxit, -1.0, k, 1, nullptr, s);
+  return jmax;
+}
+
+int solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, int nrhs, double tol, int maxit,
+                std::vector<int>& iters, hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  double* x1 = W.x;  // note: x may not alias W.x
+  int rc = gmres(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s);
+  if (rc < 0) return rc;
+  if (kind == OP_S) {
+    HIPCHK(hipMemcpyAsync(x, x1, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
+  } else if (kind == OP_SM) {
+    launch_precond(P, x1, x, nrhs, tr, nullptr, s);
+  } else {
+    // x = z + Z G Z^T (b_hat - S z), z = M^{-1} x1   (Algorithm 3 steps 5-8)
+    launch_precond(P, x1, W.z, nrhs, tr, nullptr, s);
+    launch_schur(P, W.z, W.t, nrhs, tr, nullptr, s);
+    launch_add(bhat, W.t, -1.0, W.w, P.k, nrhs, s);
+    launch_iface_sum(P, W.w, W.c, nrhs, nullptr, s);
+    launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
+    launch_prolong(P, W.z, W.c2, x, nrhs, 0, 1.0, nullptr, s);
+  }
+  return rc;
+}
+
+// ||b - S x|| / ||b|| per column (FP64), returned on the host.
+int true_residual(smpm_ctx* c, bool tr, const double* b, const double* x, int nrhs, std::vector<double>& out,
+                  hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  launch_schur(P, x, W.t, nrhs, tr, nullptr, s);
+  launch_add(b, W.t, -1.0, W.w, P.k, nrhs, s);
+  launch_mdot(W.w, 0, P.k, 1, W.w, P.k, nullptr, P.k, nrhs, W.part, W.scal, nullptr, s);
+  launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2, nullptr, s);
+  std::vector<double> a(nrhs), bb(nrhs);
+  HIPCHK(hipMemcpyAsync(a.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(bb.data(), W.scal2, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out.resize(nrhs);
+  for (int i = 0; i < nrhs; ++i) out[i] = bb[i] > 0 ? std::sqrt(a[i] / bb[i]) : std::sqrt(a[i]);
+  return SMPM_OK;
+}
+
+// u_S: (S + v0hat v0hat^T) is nonsingular and its transpose maps u_S to a multiple of
+// v0hat, so u_S = normalize((S + v0hat v0hat^T)^{-T} v0hat).  u_L = normalize(A^{-T} B^T u_S)
+// up to sign, since u_L^T L = 0 and E^T u_L is parallel to u_S (Sec. 1.4).
+int compute_null_vectors(smpm_ctx* c, hipStream_t s) {
+  const Plan& Pl = c->plan;
+  const DevPlan& P = c->dp;
+  int rc = ensure_ws(c, 1, 600);
+  if (rc) return rc;
+  Workspace& W = c->ws;
+  std::vector<int> it;
+  double* y = W.bS;
+  // GMRES on (S^T + v0hat v0hat^T) M^{-T}, then y <- M^{-T} y
+  int j = gmres(c, OP_RANK1, true, c->v0hat, W.x, 1, 1e-14, 600, it, s);
+  if (j < 0) return j;
+  launch_precond(P, W.x, y, 1, true, nullptr, s);
+  std::vector<double> hy(Pl.k);
+  HIPCHK(hipMemcpyAsync(hy.data(), y, Pl.k * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double nn = 0, sum = 0;
+  for (double v : hy) {
+    nn += v * v;
+    sum += v;
+  }
+  nn = std::sqrt(nn);
+  if (!(nn > 0) || !std::isfinite(nn)) return fail(SMPM_ESINGULAR, "null vector computation failed");
+  const double sg = sum < 0 ? -1.0 : 1.0;
+  for (double& v : hy) v *= sg / nn;
+  c->h_uS = hy;
+  HIPCHK(hipMemcpyAsync(c->uS, hy.data(), Pl.k * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_flux_adj(P, c->uS, W.rhs, 1, s);
+  std::vector<double> hl(Pl.r);
+  HIPCHK(hipMemcpyAsync(hl.data(), W.rhs, Pl.r * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  nn = 0;
+  sum = 0;
+  for (double v : hl) {
+    nn += v * v;
+    sum += v;
+  }
+  nn = std::sqrt(nn);
+  if (!(nn > 0) || !std::isfinite(nn)) return fail(SMPM_ESINGULAR, "null vector computation failed");
+  const double sl = sum < 0 ? -1.0 : 1.0;
+  for (double& v : hl) v *= sl / nn;
+  c->h_uL = hl;
+  HIPCHK(hipMemcpyAsync(c->uL, hl.data(), Pl.r * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return SMPM_OK;
+}
+
+int do_upload(smpm_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  DevPlan& d = c->dp;
+  d.n = p.n;
+  d.n2 = p.n * p.n;
+  d.nel = p.nel;
+  d.d = (int)p.d;
+  d.nblk = p.nblk;
+  d.ncls = (int)p.classes.size();
+  d.mx = p.mx;
+  d.my = p.my;
+  d.r = p.r;
+  d.k = p.k;
+  d.nsides = p.nsides;
+  d.nbdry = 2LL * p.n * (p.mx + p.my);
+  std::vector<int> nslots, sidecol;
+  for (const auto& cl : p.classes) {
+    nslots.push_back(cl.nslots);
+    for (int s2 = 0; s2 < 4; ++s2) sidecol.push_back(cl.side_col[s2]);
+  }
+  // column sums of W for S^T Z
+  const int n = p.n;
+  std::vector<double> wzc((size_t)d.ncls * 4 * 4 * n, 0.0);
+  for (int J = 0; J < d.ncls; ++J)
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int64_t o = p.W_off[(size_t)J * 4 + s2];
+      if (o < 0) continue;
+      const int ns = p.classes[J].nslots;
+      for (int cc = 0; cc < ns; ++cc) {
+        double acc = 0;
+        for (int i = 0; i < n; ++i) acc += p.Wr[o + (size_t)i * ns + cc];
+        wzc[((size_t)J * 4 + s2) * 4 * n + cc] = acc;
+      }
+    }
+  std::vector<double> GT(p.G.size());
+  for (int64_t i = 0; i < p.d; ++i)
+    for (int64_t j = 0; j < p.d; ++j) GT[(size_t)j * p.d + i] = p.G[(size_t)i * p.d + j];
+  // boundary data map: south, north, west, east
+  std::vector<int> bnode;
+  std::vector<double> btau;
+  const double omega0 = p.omega[0];
+  for (int edge = 0; edge < 4; ++edge) {
+    const int cnt = edge < 2 ? p.mx : p.my;
+    for (int q = 0; q < cnt; ++q)
+      for (int t = 0; t < n; ++t) {
+        int e, s2;
+        if (edge == 0) { e = q; s2 = SS; }
+        else if (edge == 1) { e = (p.my - 1) * p.mx + q; s2 = SN; }
+        else if (edge == 2) { e = q * p.mx; s2 = SW; }
+        else { e = q * p.mx + p.mx - 1; s2 = SE; }
+        const int ix = e % p.mx, iy = e / p.mx;
+        const double hp = (s2 == SW || s2 == SE) ? p.wx[ix] : p.hy[iy];
+        int l = s2 == SW ? t * n : s2 == SE ? t * n + n - 1 : s2 == SS ? t : (n - 1) * n + t;
+        bnode.push_back(e * n * n + l);
+        btau.push_back(2.0 * p.alpha / (omega0 * hp));
+      }
+  }
+  int rc = SMPM_OK;
+  rc |= upload(c, p.nbr, &d.nbr, s);
+  rc |= upload(c, p.cls, &d.cls, s);
+  rc |= upload(c, p.slot_off, &d.slot_off, s);
+  rc |= upload(c, p.side_slot, &d.side_slot, s);
+  rc |= upload(c, p.iface, &d.iface, s);
+  rc |= upload(c, p.side_elem, &d.side_elem, s);
+  rc |= upload(c, p.side_dir, &d.side_dir, s);
+  rc |= upload(c, p.iface_side, &d.iface_side, s);
+  rc |= upload(c, nslots, &d.cls_nslots, s);
+  rc |= upload(c, sidecol, &d.cls_sidecol, s);
+  rc |= upload(c, p.W_off, &d.W_off, s);
+  rc |= upload(c, p.H_off, &d.H_off, s);
+  rc |= upload(c, p.Wc, &d.Wc, s);
+  rc |= upload(c, p.Wr, &d.Wr, s);
+  rc |= upload(c, p.Hc, &d.Hc, s);
+  rc |= upload(c, p.Hr, &d.Hr, s);
+  rc |= upload(c, p.WZ, &d.WZ, s);
+  rc |= upload(c, wzc, &d.WZc, s);
+  rc |= upload(c, p.Ainv, &d.Ainv, s);
+  rc |= upload(c, p.AinvT, &d.AinvT, s);
+  rc |= upload(c, p.blk_off, &d.blk_off, s);
+  rc |= upload(c, p.blk_slots, &d.blk_slots, s);
+  rc |= upload(c, p.blk_cls, &d.blk_cls, s);
+  rc |= upload(c, p.bcls_off, &d.bcls_off, s);
+  rc |= upload(c, p.bcls_size, &d.bcls_size, s);
+  rc |= upload(c, p.MinvC, &d.MinvC, s);
+  rc |= upload(c, p.MinvR, &d.MinvR, s);
+  rc |= upload(c, p.G, &d.G, s);
+  rc |= upload(c, GT, &d.GT, s);
+  rc |= upload(c, bnode, &d.bdry_node, s);
+  rc |= upload(c, btau, &d.bdry_tau, s);
+  if (rc != SMPM_OK) return SMPM_ENOMEM;
+  // vectors: quadrature weights, ones, unit v0, 1/sqrt(r), null vectors
+  std::vector<double> wq(p.r), ones(p.r, 1.0), v0h(p.v0), rh(p.r, 1.0 / std::sqrt((double)p.r));
+  double wsum = 0;
+  for (int e = 0; e < p.nel; ++e) {
+    const int ix = e % p.mx, iy = e / p.mx;
+    const double we = p.xb[ix + 1] - p.xb[ix], he = p.yb[iy + 1] - p.yb[iy];
+    for (int q = 0; q < n; ++q)
+      for (int pp = 0; pp < n; ++pp) {
+        const double v = p.omega[pp] * p.omega[q] * we * he / 4.0;
+        wq[(size_t)e * n * n + q * n + pp] = v;
+        wsum += v;
+      }
+  }
+  double nv = 0;
+  for (double v : v0h) nv += v * v;
+  nv = std::sqrt(nv);
+  for (double& v : v0h) v /= nv;
+  c->wsum = wsum;
+  const double* tmp = nullptr;
+  rc |= upload(c, wq, &tmp, s);
+  c->wq = const_cast<double*>(tmp);
+  rc |= upload(c, ones, &tmp, s);
+  c->ones = const_cast<double*>(tmp);
+  rc |= upload(c, v0h, &tmp, s);
+  c->v0hat = const_cast<double*>(tmp);
+  rc |= upload(c, rh, &tmp, s);
+  c->rhat = const_cast<double*>(tmp);
+  rc |= dalloc(c->mem, &c->uL, p.r);
+  rc |= dalloc(c->mem, &c->uS, p.k);
+  if (rc != SMPM_OK) return SMPM_ENOMEM;
+  HIPCHK(hipStreamSynchronize(s));
+  return SMPM_OK;
+}
+
+bool aliases(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+
+extern "C" {
+
+void smpm_default_opts(smpm_solve_opts* o) {
+  if (!o) return;
+  o->tol = 1e-10;
+  o->maxit = 400;
+  o->precision = SMPM_FP64;
+  o->transpose = 0;
+  o->variant = 3;
+  o->inner_tol = 1e-6;
+  o->max_refine = 20;
+}
+
+const char* smpm_last_error(void) { return g_err.c_str(); }
+
+int smpm_plan(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, smpm_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(SMPM_EINVAL, "null output pointer");
+  smpm_ctx* c = new (std::nothrow) smpm_ctx();
+  if (!c) return fail(SMPM_ENOMEM, "host allocation failed");
+  std::string msg;
+  try {
+    msg = build_plan(c->plan, m_y, m_x, n, xb, yb, penalty);
+  } catch (const std::bad_alloc&) {
+    delete c;
+    return fail(SMPM_ENOMEM, "host allocation failed in setup");
+  }
+  if (!msg.empty()) {
+    delete c;
+    const bool sing = msg.find("singular") != std::string::npos;
+    return fail(sing ? SMPM_ESINGULAR : SMPM_EINVAL, msg);
+  }
+  *out = c;
+  return SMPM_OK;
+}
+
+int smpm_setup(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, void* stream,
+               smpm_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(SMPM_EINVAL, "null output pointer");
+  smpm_ctx* c = nullptr;
+  int rc = smpm_plan(m_y, m_x, n, xb, yb, penalty, &c);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&c->dev_id) != hipSuccess) {
+    delete c;
+    return fail(SMPM_EHIP, "no HIP device");
+  }
+  c->device = true;
+  rc = do_upload(c, s);
+  if (!rc) rc = compute_null_vectors(c, s);
+  if (rc) {
+    std::string keep = g_err;
+    delete c;
+    g_err = keep;
+    return rc;
+  }
+  *out = c;
+  return SMPM_OK;
+}
+
+void smpm_destroy(smpm_ctx* c) { delete c; }
+
+int smpm_sizes(const smpm_ctx* c, int64_t* r, int64_t* k, int64_t* d) {
+  if (!c) return fail(SMPM_EINVAL, "null context");
+  if (r) *r = c->plan.r;
+  if (k) *k = c->plan.k;
+  if (d) *d = c->plan.d;
+  return SMPM_OK;
+}
+
+int smpm_slot_map(const smpm_ctx* c, int64_t* out) {
+  if (!c || !out) return fail(SMPM_EINVAL, "null argument");
+  const Plan& p = c->plan;
+  const int n = p.n;
+  for (int64_t si = 0; si < p.nsides; ++si) {
+    const int e = p.side_elem[si], s = p.side_dir[si];
+    for (int t = 0; t < n; ++t) {
+      const int l = s == SW ? t * n : s == SE ? t * n + n - 1 : s == SS ? t : (n - 1) * n + t;
+      out[si * n + t] = (int64_t)e * n * n + l;
+    }
+  }
+  return SMPM_OK;
+}
+
+int smpm_node_coords(const smpm_ctx* c, double* x, double* y) {
+  if (!c || !x || !y) return fail(SMPM_EINVAL, "null argument");
+  const Plan& p = c->plan;
+  const int n = p.n;
+  for (int e = 0; e < p.nel; ++e) {
+    const int ix = e % p.mx, iy = e / p.mx;
+    const double we = p.xb[ix + 1] - p.xb[ix], he = p.yb[iy + 1] - p.yb[iy];
+    for (int q = 0; q < n; ++q)
+      for (int pp = 0; pp < n; ++pp) {
+        x[(size_t)e * n * n + q * n + pp] = p.xb[ix] + (p.xi[pp] + 1.0) * we / 2.0;
+        y[(size_t)e * n * n + q * n + pp] = p.yb[iy] + (p.xi[q] + 1.0) * he / 2.0;
+      }
+  }
+  return SMPM_OK;
+}
+
+int smpm_quadrature_weights(const smpm_ctx* c, double* w) {
+  if (!c || !w) return fail(SMPM_EINVAL, "null argument");
+  const Plan& p = c->plan;
+  const int n = p.n;
+  for (int e = 0; e < p.nel; ++e) {
+    const int ix = e % p.mx, iy = e / p.mx;
+    const double we = p.xb[ix + 1] - p.xb[ix], he = p.yb[iy + 1] - p.yb[iy];
+    for (int q = 0; q < n; ++q)
+      for (int pp = 0; pp < n; ++pp) w[(size_t)e * n * n + q * n + pp] = p.omega[pp] * p.omega[q] * we * he / 4.0;
+  }
+  return SMPM_OK;
+}
+
+int smpm_export(const smpm_ctx* c, int what, int64_t* count, int64_t* rows, int64_t* cols, double* vals) {
+  if (!c || !count) return fail(SMPM_EINVAL, "null argument");
+  const Plan& p = c->plan;
+  if (what == SMPM_EXPORT_COARSE || what == SMPM_EXPORT_COARSE_PINV) {
+    *count = p.d * p.d;
+    if (vals) {
+      const std::vector<double>& src = what == SMPM_EXPORT_COARSE ? p.C : p.G;
+      std::copy(src.begin(), src.end(), vals);
+    }
+    return SMPM_OK;
+  }
+  std::vector<int64_t> ri, ci;
+  std::vector<double> v;
+  if (what == SMPM_EXPORT_SCHUR)
+    export_schur_coo(p, ri, ci, v);
+  else if (what == SMPM_EXPORT_FLUX_SOLVE)
+    export_flux_solve_coo(p, ri, ci, v);
+  else if (what == SMPM_EXPORT_PRECOND_INV)
+    export_precond_inv_coo(p, ri, ci, v);
+  else
+    return fail(SMPM_EINVAL, "unknown export kind");
+  if (rows || cols || vals) {
+    if ((int64_t)v.size() > *count) return fail(SMPM_EINVAL, "export buffer too small");
+    if (rows) std::copy(ri.begin(), ri.end(), rows);
+    if (cols) std::copy(ci.begin(), ci.end(), cols);
+    if (vals) std::copy(v.begin(), v.end(), vals);
+  }
+  *count = (int64_t)v.size();
+  return SMPM_OK;
+}
+
+int smpm_null_vectors(const smpm_ctx* c, double* uL, double* uS) {
+  if (!c) return fail(SMPM_EINVAL, "null context");
+  if (!c->device) return fail(SMPM_ENODEVICE, "context has no device data (built by smpm_plan)");
+  if (uL) std::copy(c->h_uL.begin(), c->h_uL.end(), uL);
+  if (uS) std::copy(c->h_uS.begin(), c->h_uS.end(), uS);
+  return SMPM_OK;
+}
+
+int smpm_schur_apply(smpm_ctx* c, const double* v, double* Sv, int nrhs, int transpose, void* stream) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!v || !Sv || nrhs < 1) return fail(SMPM_EINVAL, "bad vector arguments");
+  const size_t bytes = sizeof(double) * c->plan.k * nrhs;
+  if (aliases(v, bytes, Sv, bytes)) return fail(SMPM_EINVAL, "input and output alias");
+  launch_schur(c->dp, v, Sv, nrhs, transpose != 0, nullptr, static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return SMPM_OK;
+}
+
+int smpm_precond_apply(smpm_ctx* c, const double* x, double* y, int nrhs, int transpose, void* stream) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!x || !y || nrhs < 1) return fail(SMPM_EINVAL, "bad vector arguments");
+  const size_t bytes = sizeof(double) * c->plan.k * nrhs;
+  if (aliases(x, bytes, y, bytes)) return fail(SMPM_EINVAL, "input and output alias");
+  launch_precond(c->dp, x, y, nrhs, transpose != 0, nullptr, static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return SMPM_OK;
+}
+
+int smpm_project(smpm_ctx* c, int which, const double* in, double* out, int nrhs, int transpose, void* stream) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!in || !out || nrhs < 1) return fail(SMPM_EINVAL, "bad vector arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = ensure_ws(c, nrhs, 1);
+  if (rc) return rc;
+  Workspace& W = c->ws;
+  const DevPlan& P = c->dp;
+  const bool tr = transpose != 0;
+  switch (which) {
+    case SMPM_PROJ_L: {
+      const double* u = tr ? c->rhat : c->uL;
+      launch_mdot(u, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, W.part, W.scal, nullptr, s);
+      launch_axpy_shared(in, P.r, u, W.scal, 1.0, out, P.r, nrhs, s);
+      break;
+    }
+    case SMPM_PROJ_S: {
+      const double* u = tr ? c->v0hat : c->uS;
+      launch_mdot(u, 0, 0, 1, in, P.k, nullptr, P.k, nrhs, W.part, W.scal, nullptr, s);
+      launch_axpy_shared(in, P.k, u, W.scal, 1.0, out, P.k, nrhs, s);
+      break;
+    }
+    case SMPM_PROJ_MEAN: {
+      // x - 1 (w^T x)/(w^T 1); transposed: x - w (1^T x)/(w^T 1)
+      if (!tr) {
+        launch_mdot(c->wq, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, W.part, W.scal, nullptr, s);
+        launch_axpy_shared(in, P.r, c->ones, W.scal, 1.0 / c->wsum, out, P.r, nrhs, s);
+      } else {
+        launch_mdot(c->ones, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, W.part, W.scal, nullptr, s);
+        launch_axpy_shared(in, P.r, c->wq, W.scal, 1.0 / c->wsum, out, P.r, nrhs, s);
+      }
+      break;
+    }
+    case SMPM_PROJ_P: {
+      // P x = x - S Z G Z^T x;  P^T x = x - Z G^T Z^T S^T x
+      if (!tr) {
+        launch_iface_sum(P, in, W.c, nrhs, nullptr, s);
+        launch_coarse(P, W.c, W.c2, nrhs, false, nullptr, s);
+        launch_prolong(P, in, W.c2, out, nrhs, 1, -1.0, nullptr, s);
+      } else {
+        launch_schur(P, in, W.t, nrhs, true, nullptr, s);
+        launch_iface_sum(P, W.t, W.c, nrhs, nullptr, s);
+        launch_coarse(P, W.c, W.c2, nrhs, true, nullptr, s);
+        launch_prolong(P, in, W.c2, out, nrhs, 0, -1.0, nullptr, s);
+      }
+      break;
+    }
+    case SMPM_PROJ_Q: {
+      // Q x = x - Z G Z^T S x;  Q^T x = x - S^T Z G^T Z^T x
+      if (!tr) {
+        launch_schur(P, in, W.t, nrhs, false, nullptr, s);
+        launch_iface_sum(P, W.t, W.c, nrhs, nullptr, s);
+        launch_coarse(P, W.c, W.c2, nrhs, false, nullptr, s);
+        launch_prolong(P, in, W.c2, out, nrhs, 0, -1.0, nullptr, s);
+      } else {
+        launch_iface_sum(P, in, W.c, nrhs, nullptr, s);
+        launch_coarse(P, W.c, W.c2, nrhs, true, nullptr, s);
+        launch_prolong(P, in, W.c2, out, nrhs, 2, -1.0, nullptr, s);
+      }
+      break;
+    }
+    default:
+      return fail(SMPM_EINVAL, "unknown projection");
+  }
+  HIPCHK(hipGetLastError());
+  return SMPM_OK;
+}
+
+int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrhs, const smpm_solve_opts* opts_in,
+               smpm_solve_info* info, void* stream) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!f || !u || nrhs < 1) return fail(SMPM_EINVAL, "bad vector arguments");
+  smpm_solve_opts o;
+  smpm_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (o.maxit < 1 || !(o.tol > 0) || o.variant < 1 || o.variant > 3)
+    return fail(SMPM_EINVAL, "bad solve options");
+  if (o.precision != SMPM_FP64) return fail(SMPM_EINVAL, "precision not supported by this build");
+  if (o.transpose) return fail(SMPM_EINVAL, "adjoint solve not supported by this build");
+  const Plan& Pl = c->plan;
+  const DevPlan& P = c->dp;
+  const size_t rb = sizeof(double) * Pl.r * nrhs;
+  if (aliases(f, rb, u, rb)) return fail(SMPM_EINVAL, "f and u alias");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = ensure_ws(c, nrhs, o.maxit);
+  if (rc) return rc;
+  Workspace& W = c->ws;
+  // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
+  launch_rhs(P, f, g, W.rhs, nrhs, s);
+  launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
+  std::vector<double> removed(nrhs);
+  HIPCHK(hipMemcpyAsync(removed.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  launch_axpy_shared(W.rhs, Pl.r, c->uL, W.scal, 1.0, W.ft, Pl.r, nrhs, s);
+  launch_flux(P, W.ft, W.bS, nrhs, s);
+  launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
+  launch_axpy_shared(W.bS, Pl.k, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, s);
+  // steps 4-8
+  std::vector<int> iters;
+  const int kind = o.variant == 3 ? OP_PSM : o.variant == 2 ? OP_SM : OP_S;
+  // x lands in W.bS (free after b_hat is formed)
+  rc = solve_schur(c, kind, false, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s);
+  if (rc < 0) return rc;
+  std::vector<double> tres;
+  rc = true_residual(c, false, W.bhat, W.bS, nrhs, tres, s);
+  if (rc) return rc;
+  // step 9 and the constant: u = A^{-1}(f~ - E x); u -= (w^T u / w^T 1)
+  launch_backsub(P, W.ft, W.bS, u, nrhs, s);
+  launch_mdot(c->wq, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
+  launch_axpy_shared(u, Pl.r, c->ones, W.scal, 1.0 / c->wsum, u, Pl.r, nrhs, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  int itmax = 0;
+  double resmax = 0;
+  for (int i = 0; i < nrhs; ++i) {
+    itmax = std::max(itmax, iters[i]);
+    resmax = std::max(resmax, tres[i]);
+  }
+  if (info) {
+    info->iterations = itmax;
+    info->refinements = 1;
+    info->rel_residual = resmax;
+    info->removed_component = removed[0];
+  }
+  bool conv = true;
+  for (int i = 0; i < nrhs; ++i)
+    if (iters[i] >= o.maxit) conv = false;
+  if (!conv) return fail(SMPM_ENOCONV, "GMRES reached maxit before the tolerance");
+  return SMPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Device-side view of the plan and the launchers of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace smpm {
+
+constexpr int kMaxN = 32;
+
+// Plain-old-data view of the device copy of a Plan; passed to kernels by value.
+struct DevPlan {
+  int n, n2, nel, d, nblk, ncls, mx, my;
+  int64_t r, k, nsides, nbdry;
+  const int* nbr;          // nel*4
+  const int* cls;          // nel
+  const int* slot_off;     // nel+1
+  const int* side_slot;    // nel*4
+  const int* iface;        // nel*4
+  const int* side_elem;    // nsides
+  const int* side_dir;     // nsides
+  const int* iface_side;   // d*2
+  const int* cls_nslots;   // ncls
+  const int* cls_sidecol;  // ncls*4
+  const int64_t* W_off;    // ncls*4
+  const int64_t* H_off;    // ncls*4
+  const double* Wc;        // [c][i]
+  const double* Wr;        // [i][c]
+  const double* Hc;        // [l][i]
+  const double* Hr;        // [i][l]
+  const double* WZ;        // [cls][s'][t][s'']
+  const double* WZc;       // [cls][s'][c]  column sums of W over its rows
+  const double* Ainv;      // [cls][l][m]
+  const double* AinvT;     // [cls][m][l]
+  const int* blk_off;
+  const int* blk_slots;
+  const int* blk_cls;
+  const int64_t* bcls_off;
+  const int* bcls_size;
+  const double* MinvC;     // [c][r]
+  const double* MinvR;     // [r][c]
+  const double* G;         // d x d row-major
+  const double* GT;        // its transpose
+  const int* bdry_node;    // nbdry
+  const double* bdry_tau;  // nbdry
+};
+
+// ---- operator applies; nrhs columns, column-blocked with the natural lengths
+void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
+                  const int* active, hipStream_t s);
+void launch_flux(const DevPlan& P, const double* f, double* b, int nrhs, hipStream_t s);      // b = B A^{-1} f
+void launch_flux_adj(const DevPlan& P, const double* x, double* y, int nrhs, hipStream_t s);  // y = A^{-T} B^T x
+void launch_backsub(const DevPlan& P, const double* f, const double* x, double* u, int nrhs,
+                    hipStream_t s);                                                             // u = A^{-1}(f - E x)
+void launch_local_adj(const DevPlan& P, const double* c, double* out, int nrhs, bool to_slots,
+                      hipStream_t s);                         // out = A^{-T} c (r) or E^T A^{-T} c (k)
+void launch_precond(const DevPlan& P, const double* x, double* y, int nrhs, bool transpose,
+                    const int* active, hipStream_t s);
+void launch_iface_sum(const DevPlan& P, const double* t, double* c, int nrhs, const int* active,
+                      hipStream_t s);                                                           // c = Z^T t
+void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool transpose,
+                   const int* active, hipStream_t s);                                          // c2 = G c
+// w = t + sign * (Z c2 + SZ c2) with sz = 0: no S term, 1: S Z, 2: S^T Z
+void launch_prolong(const DevPlan& P, const double* t, const double* c2, double* w, int nrhs, int sz,
+                    double sign, const int* active, hipStream_t s);
+void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, hipStream_t s);
+void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, hipStream_t s);  // dg = T^T mu
+
+// ---- vector kernels over nrhs columns of length len (column stride ld)
+int reduce_chunks(int64_t len);
+// out[col*nvec + i] = sum_x A_i(col)[x] * b(col)[x] * (wt ? wt[x] : 1)
+// A_i(col) = A + col*a_cs + i*a_vs.  part: scratch of nrhs*nvec*reduce_chunks(len)
+void launch_mdot(const double* A, int64_t a_vs, int64_t a_cs, int nvec, const double* b, int64_t b_cs,
+                 const double* wt, int64_t len, int nrhs, double* part, double* out, const int* active,
+                 hipStream_t s);
+// w(col) = w(col) - sum_i coef[col*nvec + i] * A_i(col)     (coef scaled by `scale`)
+void launch_mupdate(double* w, int64_t w_cs, const double* A, int64_t a_vs, int64_t a_cs, int nvec,
+                    const double* coef, double scale, int64_t len, int nrhs, const int* active, hipStream_t s);
+// y(col) = x(col) - (dot[col] * scale) * u   (u shared by all columns); y may alias x
+void launch_axpy_shared(const double* x, int64_t x_cs, const double* u, const double* dot, double scale,
+                        double* y, int64_t len, int nrhs, hipStream_t s);
+// y(col) = x(col) * (1/ nrm[col])  where nrm holds squared norms when sq=true
+void launch_scale_inv(const double* x, int64_t x_cs, const double* nrm, bool sq, double* y, int64_t y_cs,
+                      int64_t len, int nrhs, const int* active, hipStream_t s);
+void launch_add(const double* a, const double* b, double sb, double* y, int64_t len, int nrhs, hipStream_t s);
+
+// ---- GMRES small dense work (one thread per column)
+// H(col) (ldh x maxit col-major: H[j*ldh + i]), cs, sn, g of length ldh; hnew: j+1 coefficients,
+// nrm2: squared norm of the orthogonalized vector.  Writes res[col] = |g[j+1]|.
+void launch_givens(double* H, int ldh, double* cs, double* sn, double* g, const double* hnew,
+                   const double* nrm2, int j, int nrhs, double* res, const int* active, hipStream_t s);
+void launch_lsq(const double* H, int ldh, const double* g, const int* jcount, double* y, int nrhs,
+                hipStream_t s);
+
+}  // namespace smpm

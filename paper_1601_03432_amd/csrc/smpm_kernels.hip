@@ -1,0 +1,563 @@
+// gfx950 kernels of the SMPM deflated Schur complement solver (FP64 path).
+//
+// Mapping.  Element-local operators run one 64-lane wavefront per element:
+// lanes index the outputs (side x node along the side), the operator is stored
+// with that index fastest so each step of the contraction is one coalesced
+// read, and the neighbour data the contraction needs is staged in LDS.  Vector
+// reductions are two-stage (per-chunk partials, then a fixed-order sum), so
+// every FP64 result is deterministic from run to run.
+#include <hip/hip_runtime.h>
+
+#include "smpm_kernels.h"
+
+namespace smpm {
+
+namespace {
+
+__device__ __forceinline__ int side_node(int n, int s, int t) {
+  return s == 0 ? t * n : s == 1 ? t * n + (n - 1) : s == 2 ? t : (n - 1) * n + t;
+}
+
+// ------------------------------------------------------------------ Schur apply
+
+// t = y + B A^{-1} E y (Eq. schur_complement_system).  Receiver e, side s gets the
+// flux of its neighbour j through j's facing side: W_{cls(j), s^1} y_j.
+__global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __restrict__ y,
+                                                   double* __restrict__ t, const int* __restrict__ active) {
+  __shared__ double ys[4][4][4 * kMaxN];
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + wave;
+  const int n = P.n;
+  const double* yc = y + (int64_t)col * P.k;
+  double* tc = t + (int64_t)col * P.k;
+  if (e < P.nel) {
+    for (int s = 0; s < 4; ++s) {
+      const int j = P.nbr[e * 4 + s];
+      if (j < 0) continue;
+      const int ns = P.cls_nslots[P.cls[j]];
+      const int base = P.slot_off[j];
+      for (int c = lane; c < ns; c += 64) ys[wave][s][c] = yc[base + c];
+    }
+  }
+  __syncthreads();
+  if (e >= P.nel) return;
+  for (int o = lane; o < 4 * n; o += 64) {
+    const int s = o / n, i = o - s * n;
+    const int j = P.nbr[e * 4 + s];
+    if (j < 0) continue;
+    const int J = P.cls[j];
+    const int ns = P.cls_nslots[J];
+    const double* Wp = P.Wc + P.W_off[J * 4 + (s ^ 1)];
+    double acc = 0.0;
+    for (int c = 0; c < ns; ++c) acc = fma(Wp[c * n + i], ys[wave][s][c], acc);
+    const int slot = P.side_slot[e * 4 + s] + i;
+    tc[slot] = yc[slot] + acc;
+  }
+}
+
+// t = y + E^T A^{-T} B^T y: element J collects the slots its fluxes feed.
+__global__ __launch_bounds__(256) void k_schur_adj(DevPlan P, const double* __restrict__ y,
+                                                   double* __restrict__ t, const int* __restrict__ active) {
+  __shared__ double yr[4][4][kMaxN];
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + wave;
+  const int n = P.n;
+  const double* yc = y + (int64_t)col * P.k;
+  double* tc = t + (int64_t)col * P.k;
+  if (e < P.nel) {
+    for (int s = 0; s < 4; ++s) {
+      const int j = P.nbr[e * 4 + s];
+      if (j < 0) continue;
+      const int base = P.side_slot[j * 4 + (s ^ 1)];
+      for (int i = lane; i < n; i += 64) yr[wave][s][i] = yc[base + i];
+    }
+  }
+  __syncthreads();
+  if (e >= P.nel) return;
+  const int J = P.cls[e];
+  const int ns = P.cls_nslots[J];
+  for (int c = lane; c < ns; c += 64) {
+    double acc = 0.0;
+    for (int s = 0; s < 4; ++s) {
+      if (P.nbr[e * 4 + s] < 0) continue;
+      const double* Wp = P.Wr + P.W_off[J * 4 + s];
+      for (int i = 0; i < n; ++i) acc = fma(Wp[i * ns + c], yr[wave][s][i], acc);
+    }
+    const int slot = P.slot_off[e] + c;
+    tc[slot] = yc[slot] + acc;
+  }
+}
+
+// ------------------------------------------------------------------ B A^{-1} and its transpose
+
+__global__ __launch_bounds__(64) void k_flux(DevPlan P, const double* __restrict__ f, double* __restrict__ b) {
+  extern __shared__ double fs[];  // 4 * n2
+  const int e = blockIdx.x, col = blockIdx.y, lane = threadIdx.x;
+  const int n = P.n, n2 = P.n2;
+  const double* fc = f + (int64_t)col * P.r;
+  double* bc = b + (int64_t)col * P.k;
+  for (int s = 0; s < 4; ++s) {
+    const int j = P.nbr[e * 4 + s];
+    if (j < 0) continue;
+    for (int l = lane; l < n2; l += 64) fs[s * n2 + l] = fc[(int64_t)j * n2 + l];
+  }
+  __syncthreads();
+  for (int o = lane; o < 4 * n; o += 64) {
+    const int s = o / n, i = o - s * n;
+    const int j = P.nbr[e * 4 + s];
+    if (j < 0) continue;
+    const double* Hp = P.Hc + P.H_off[P.cls[j] * 4 + (s ^ 1)];
+    double acc = 0.0;
+    for (int l = 0; l < n2; ++l) acc = fma(Hp[l * n + i], fs[s * n2 + l], acc);
+    bc[P.side_slot[e * 4 + s] + i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_flux_adj(DevPlan P, const double* __restrict__ x, double* __restrict__ y) {
+  __shared__ double xr[4][kMaxN];
+  const int e = blockIdx.x, col = blockIdx.y, tid = threadIdx.x;
+  const int n = P.n, n2 = P.n2;
+  const double* xc = x + (int64_t)col * P.k;
+  double* yc = y + (int64_t)col * P.r;
+  if (tid < 4 * n) {
+    const int s = tid / n, i = tid - s * n;
+    const int j = P.nbr[e * 4 + s];
+    xr[s][i] = j >= 0 ? xc[P.side_slot[j * 4 + (s ^ 1)] + i] : 0.0;
+  }
+  __syncthreads();
+  const int J = P.cls[e];
+  for (int l = tid; l < n2; l += 256) {
+    double acc = 0.0;
+    for (int s = 0; s < 4; ++s) {
+      if (P.nbr[e * 4 + s] < 0) continue;
+      const double* Hp = P.Hr + P.H_off[J * 4 + s];
+      for (int i = 0; i < n; ++i) acc = fma(Hp[i * n2 + l], xr[s][i], acc);
+    }
+    yc[(int64_t)e * n2 + l] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ element solves
+
+// u_e = A_e^{-1} (f_e - E_e x): corner nodes on two inter-element sides lose both slots.
+__global__ __launch_bounds__(256) void k_backsub(DevPlan P, const double* __restrict__ f, const double* __restrict__ x,
+                                                 double* __restrict__ u) {
+  extern __shared__ double zs[];  // n2
+  const int e = blockIdx.x, col = blockIdx.y, tid = threadIdx.x;
+  const int n = P.n, n2 = P.n2;
+  const double* fc = f + (int64_t)col * P.r;
+  const double* xc = x + (int64_t)col * P.k;
+  double* uc = u + (int64_t)col * P.r;
+  for (int l = tid; l < n2; l += 256) zs[l] = fc[(int64_t)e * n2 + l];
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {  // W/E sides touch disjoint nodes, then S/N
+    for (int q = tid; q < 2 * n; q += 256) {
+      const int s = 2 * pass + q / n, tt = q % n;
+      const int base = P.side_slot[e * 4 + s];
+      if (base >= 0) zs[side_node(n, s, tt)] -= xc[base + tt];
+    }
+    __syncthreads();
+  }
+  const double* Ap = P.AinvT + (int64_t)P.cls[e] * n2 * n2;
+  for (int l = tid; l < n2; l += 256) {
+    double acc = 0.0;
+    for (int m = 0; m < n2; ++m) acc = fma(Ap[(int64_t)m * n2 + l], zs[m], acc);
+    uc[(int64_t)e * n2 + l] = acc;
+  }
+}
+
+// out = A^{-T} c  (to_slots = 0, r-vector) or E^T A^{-T} c (to_slots = 1, k-vector).
+__global__ __launch_bounds__(256) void k_local_adj(DevPlan P, const double* __restrict__ c, double* __restrict__ out,
+                                                   int to_slots) {
+  extern __shared__ double sm[];  // 2 * n2
+  const int e = blockIdx.x, col = blockIdx.y, tid = threadIdx.x;
+  const int n = P.n, n2 = P.n2;
+  double* cs = sm;
+  double* ws = sm + n2;
+  const double* cc = c + (int64_t)col * P.r;
+  for (int l = tid; l < n2; l += 256) cs[l] = cc[(int64_t)e * n2 + l];
+  __syncthreads();
+  const double* Ap = P.Ainv + (int64_t)P.cls[e] * n2 * n2;
+  for (int l = tid; l < n2; l += 256) {
+    double acc = 0.0;
+    for (int m = 0; m < n2; ++m) acc = fma(Ap[(int64_t)m * n2 + l], cs[m], acc);
+    if (to_slots)
+      ws[l] = acc;
+    else
+      out[(int64_t)col * P.r + (int64_t)e * n2 + l] = acc;
+  }
+  if (!to_slots) return;
+  __syncthreads();
+  for (int s = 0; s < 4; ++s) {
+    const int base = P.side_slot[e * 4 + s];
+    if (base < 0) continue;
+    for (int tt = tid; tt < n; tt += 256) out[(int64_t)col * P.k + base + tt] = ws[side_node(n, s, tt)];
+  }
+}
+
+// ------------------------------------------------------------------ block-Jacobi
+
+__global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __restrict__ x, double* __restrict__ y,
+                                                 int transpose, const int* __restrict__ active) {
+  __shared__ double xs[8 * kMaxN];
+  const int b = blockIdx.x, col = blockIdx.y, tid = threadIdx.x;
+  if (active && !active[col]) return;
+  const double* xc = x + (int64_t)col * P.k;
+  double* yc = y + (int64_t)col * P.k;
+  const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
+  const int bc = P.blk_cls[b];
+  for (int i = tid; i < sb; i += 256) xs[i] = xc[P.blk_slots[o + i]];
+  __syncthreads();
+  const double* Mp = (transpose ? P.MinvR : P.MinvC) + P.bcls_off[bc];
+  for (int r = tid; r < sb; r += 256) {
+    double acc = 0.0;
+    for (int c = 0; c < sb; ++c) acc = fma(Mp[c * sb + r], xs[c], acc);
+    yc[P.blk_slots[o + r]] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ deflation
+
+__global__ void k_iface_sum(DevPlan P, const double* __restrict__ t, double* __restrict__ c,
+                            const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P.d) return;
+  const double* tc = t + (int64_t)col * P.k;
+  const int n = P.n;
+  double acc = 0.0;
+  for (int h = 0; h < 2; ++h) {
+    const int64_t base = (int64_t)P.iface_side[2 * j + h] * n;
+    for (int i = 0; i < n; ++i) acc += tc[base + i];
+  }
+  c[(int64_t)col * P.d + j] = acc;
+}
+
+__global__ void k_coarse(DevPlan P, const double* __restrict__ c, double* __restrict__ c2, int transpose,
+                         const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int d = P.d;
+  if (i >= d) return;
+  const double* Gp = transpose ? P.G : P.GT;  // element [j][i] of the transposed storage
+  const double* cc = c + (int64_t)col * d;
+  double acc = 0.0;
+  for (int j = 0; j < d; ++j) acc = fma(Gp[(int64_t)j * d + i], cc[j], acc);
+  c2[(int64_t)col * d + i] = acc;
+}
+
+// w = t + sign * (Z c2 + {0, S Z c2, S^T Z c2})
+__global__ void k_prolong(DevPlan P, const double* __restrict__ t, const double* __restrict__ c2,
+                          double* __restrict__ w, int sz, double sign, const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= P.k) return;
+  const int n = P.n;
+  const int si = (int)(slot / n), tt = (int)(slot - (int64_t)si * n);
+  const int e = P.side_elem[si], s = P.side_dir[si];
+  const double* cc = c2 + (int64_t)col * P.d;
+  double acc = cc[P.iface[e * 4 + s]];
+  if (sz == 1) {
+    const int J = P.nbr[e * 4 + s], cJ = P.cls[J], so = s ^ 1;
+    const double* wz = P.WZ + (((int64_t)cJ * 4 + so) * n + tt) * 4;
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int j2 = P.iface[J * 4 + s2];
+      if (j2 >= 0) acc = fma(wz[s2], cc[j2], acc);
+    }
+  } else if (sz == 2) {
+    const int ce = P.cls[e];
+    const int cidx = (int)(slot - P.slot_off[e]);
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int j2 = P.iface[e * 4 + s2];
+      if (j2 >= 0) acc = fma(P.WZc[((int64_t)ce * 4 + s2) * 4 * n + cidx], cc[j2], acc);
+    }
+  }
+  const int64_t o = (int64_t)col * P.k + slot;
+  w[o] = t[o] + sign * acc;
+}
+
+// ------------------------------------------------------------------ boundary data
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) b[i] = a[i];
+}
+
+// rhs[node] += tau g over boundary entries [b0, b1) (a range whose nodes are distinct)
+__global__ void k_bdry_add(DevPlan P, const double* __restrict__ g, double* __restrict__ rhs, int64_t b0, int64_t b1) {
+  const int col = blockIdx.y;
+  const int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= b1) return;
+  rhs[(int64_t)col * P.r + P.bdry_node[b]] += P.bdry_tau[b] * g[(int64_t)col * P.nbdry + b];
+}
+
+__global__ void k_bdry_adj(DevPlan P, const double* __restrict__ mu, double* __restrict__ dg) {
+  const int col = blockIdx.y;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= P.nbdry) return;
+  dg[(int64_t)col * P.nbdry + b] = P.bdry_tau[b] * mu[(int64_t)col * P.r + P.bdry_node[b]];
+}
+
+// ------------------------------------------------------------------ vector kernels
+
+constexpr int kChunk = 2048;   // elements per reduction chunk (256 threads x 8)
+constexpr int kVecGroup = 8;   // vectors per block in the multi-dot
+
+__device__ __forceinline__ double block_sum_256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_mdot_part(const double* __restrict__ A, int64_t a_vs, int64_t a_cs, int nvec,
+                                                   const double* __restrict__ b, int64_t b_cs,
+                                                   const double* __restrict__ wt, int64_t len, int nchunks,
+                                                   double* __restrict__ part, const int* __restrict__ active) {
+  __shared__ double red[4];
+  const int chunk = blockIdx.x, grp = blockIdx.y, col = blockIdx.z;
+  if (active && !active[col]) return;
+  const int64_t x0 = (int64_t)chunk * kChunk;
+  double bv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t x = x0 + q * 256 + threadIdx.x;
+    double v = x < len ? b[(int64_t)col * b_cs + x] : 0.0;
+    if (wt && x < len) v *= wt[x];
+    bv[q] = v;
+  }
+  const int i0 = grp * kVecGroup;
+  const int i1 = min(nvec, i0 + kVecGroup);
+  for (int i = i0; i < i1; ++i) {
+    const double* a = A + (int64_t)col * a_cs + (int64_t)i * a_vs;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t x = x0 + q * 256 + threadIdx.x;
+      if (x < len) acc = fma(a[x], bv[q], acc);
+    }
+    const double s = block_sum_256(acc, red);
+    if (threadIdx.x == 0) part[((int64_t)col * nvec + i) * nchunks + chunk] = s;
+  }
+}
+
+__global__ void k_mdot_final(const double* __restrict__ part, int nvec, int nchunks, int nrhs,
+                             double* __restrict__ out, const int* __restrict__ active) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nvec * nrhs) return;
+  const int col = idx / nvec;
+  if (active && !active[col]) return;
+  const double* p = part + (int64_t)idx * nchunks;
+  double acc = 0.0;
+  for (int c = 0; c < nchunks; ++c) acc += p[c];
+  out[idx] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_mupdate(double* __restrict__ w, int64_t w_cs, const double* __restrict__ A,
+                                                 int64_t a_vs, int64_t a_cs, int nvec, const double* __restrict__ coef,
+                                                 double scale, int64_t len, const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= len) return;
+  const double* a = A + (int64_t)col * a_cs + x;
+  const double* cf = coef + (int64_t)col * nvec;
+  double acc = 0.0;
+  for (int i = 0; i < nvec; ++i) acc = fma(cf[i], a[(int64_t)i * a_vs], acc);
+  w[(int64_t)col * w_cs + x] -= scale * acc;
+}
+
+__global__ void k_axpy_shared(const double* __restrict__ x, int64_t x_cs, const double* __restrict__ u,
+                              const double* __restrict__ dot, double scale, double* __restrict__ y, int64_t len) {
+  const int col = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  y[(int64_t)col * len + i] = x[(int64_t)col * x_cs + i] - dot[col] * scale * u[i];
+}
+
+__global__ void k_scale_inv(const double* __restrict__ x, int64_t x_cs, const double* __restrict__ nrm, int sq,
+                            double* __restrict__ y, int64_t y_cs, int64_t len, const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const double v = sq ? sqrt(nrm[col]) : nrm[col];
+  y[(int64_t)col * y_cs + i] = v > 0.0 ? x[(int64_t)col * x_cs + i] / v : 0.0;
+}
+
+__global__ void k_add(const double* __restrict__ a, const double* __restrict__ b, double sb,
+                      double* __restrict__ y, int64_t len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) y[i] = a[i] + sb * b[i];
+}
+
+// ------------------------------------------------------------------ GMRES small work
+
+__global__ void k_givens(double* H, int ldh, int maxit, double* cs, double* sn, double* g, const double* hnew,
+                         const double* nrm2, int j, int nrhs, double* res, const int* active) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= nrhs) return;
+  if (active && !active[col]) return;
+  double* Hc = H + (int64_t)col * ldh * maxit + (int64_t)j * ldh;
+  double* csc = cs + (int64_t)col * ldh;
+  double* snc = sn + (int64_t)col * ldh;
+  double* gc = g + (int64_t)col * ldh;
+  for (int i = 0; i <= j; ++i) Hc[i] = hnew[(int64_t)col * (j + 1) + i];
+  Hc[j + 1] = sqrt(nrm2[col]);
+  for (int i = 0; i < j; ++i) {
+    const double a = Hc[i], b = Hc[i + 1];
+    Hc[i] = csc[i] * a + snc[i] * b;
+    Hc[i + 1] = -snc[i] * a + csc[i] * b;
+  }
+  const double a = Hc[j], b = Hc[j + 1];
+  const double rr = hypot(a, b);
+  const double c = rr > 0.0 ? a / rr : 1.0;
+  const double s = rr > 0.0 ? b / rr : 0.0;
+  csc[j] = c;
+  snc[j] = s;
+  Hc[j] = rr;
+  Hc[j + 1] = 0.0;
+  gc[j + 1] = -s * gc[j];
+  gc[j] = c * gc[j];
+  res[col] = fabs(gc[j + 1]);
+}
+
+__global__ void k_lsq(const double* H, int ldh, int maxit, const double* g, const int* jcount, double* y, int nrhs) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= nrhs) return;
+  const int J = jcount[col];
+  const double* Hc = H + (int64_t)col * ldh * maxit;
+  const double* gc = g + (int64_t)col * ldh;
+  double* yc = y + (int64_t)col * maxit;
+  for (int i = J; i < maxit; ++i) yc[i] = 0.0;
+  for (int i = J - 1; i >= 0; --i) {
+    double acc = gc[i];
+    for (int m = i + 1; m < J; ++m) acc -= Hc[(int64_t)m * ldh + i] * yc[m];
+    yc[i] = acc / Hc[(int64_t)i * ldh + i];
+  }
+}
+
+inline dim3 grid1(int64_t len, int bs, int ny = 1) { return dim3((unsigned)((len + bs - 1) / bs), ny); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
+                  hipStream_t s) {
+  dim3 g((P.nel + 3) / 4, nrhs);
+  if (transpose)
+    hipLaunchKernelGGL(k_schur_adj, g, dim3(256), 0, s, P, y, t, active);
+  else
+    hipLaunchKernelGGL(k_schur_fwd, g, dim3(256), 0, s, P, y, t, active);
+}
+
+void launch_flux(const DevPlan& P, const double* f, double* b, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_flux, dim3(P.nel, nrhs), dim3(64), 4 * P.n2 * sizeof(double), s, P, f, b);
+}
+
+void launch_flux_adj(const DevPlan& P, const double* x, double* y, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_flux_adj, dim3(P.nel, nrhs), dim3(256), 0, s, P, x, y);
+}
+
+void launch_backsub(const DevPlan& P, const double* f, const double* x, double* u, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsub, dim3(P.nel, nrhs), dim3(256), P.n2 * sizeof(double), s, P, f, x, u);
+}
+
+void launch_local_adj(const DevPlan& P, const double* c, double* out, int nrhs, bool to_slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_local_adj, dim3(P.nel, nrhs), dim3(256), 2 * P.n2 * sizeof(double), s, P, c, out,
+                     to_slots ? 1 : 0);
+}
+
+void launch_precond(const DevPlan& P, const double* x, double* y, int nrhs, bool transpose, const int* active,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_precond, dim3(P.nblk, nrhs), dim3(256), 0, s, P, x, y, transpose ? 1 : 0, active);
+}
+
+void launch_iface_sum(const DevPlan& P, const double* t, double* c, int nrhs, const int* active, hipStream_t s) {
+  if (P.d == 0) return;
+  hipLaunchKernelGGL(k_iface_sum, grid1(P.d, 128, nrhs), dim3(128), 0, s, P, t, c, active);
+}
+
+void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool transpose, const int* active,
+                   hipStream_t s) {
+  if (P.d == 0) return;
+  hipLaunchKernelGGL(k_coarse, grid1(P.d, 128, nrhs), dim3(128), 0, s, P, c, c2, transpose ? 1 : 0, active);
+}
+
+void launch_prolong(const DevPlan& P, const double* t, const double* c2, double* w, int nrhs, int sz, double sign,
+                    const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_prolong, grid1(P.k, 256, nrhs), dim3(256), 0, s, P, t, c2, w, sz, sign, active);
+}
+
+void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, hipStream_t s) {
+  const int64_t len = P.r * nrhs;
+  hipLaunchKernelGGL(k_copy, grid1(len, 256), dim3(256), 0, s, f, rhs, len);
+  if (!g) return;
+  // south + north edges first (distinct nodes), then west + east edges (distinct nodes);
+  // a domain-corner node receives one term from each launch
+  const int64_t sn = 2 * (int64_t)P.mx * P.n;
+  hipLaunchKernelGGL(k_bdry_add, grid1(sn, 256, nrhs), dim3(256), 0, s, P, g, rhs, (int64_t)0, sn);
+  hipLaunchKernelGGL(k_bdry_add, grid1(P.nbdry - sn, 256, nrhs), dim3(256), 0, s, P, g, rhs, sn, P.nbdry);
+}
+
+void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_bdry_adj, grid1(P.nbdry, 256, nrhs), dim3(256), 0, s, P, mu, dg);
+}
+
+int reduce_chunks(int64_t len) { return (int)((len + kChunk - 1) / kChunk); }
+
+void launch_mdot(const double* A, int64_t a_vs, int64_t a_cs, int nvec, const double* b, int64_t b_cs,
+                 const double* wt, int64_t len, int nrhs, double* part, double* out, const int* active,
+                 hipStream_t s) {
+  const int nch = reduce_chunks(len);
+  dim3 g(nch, (nvec + kVecGroup - 1) / kVecGroup, nrhs);
+  hipLaunchKernelGGL(k_mdot_part, g, dim3(256), 0, s, A, a_vs, a_cs, nvec, b, b_cs, wt, len, nch, part, active);
+  hipLaunchKernelGGL(k_mdot_final, grid1((int64_t)nvec * nrhs, 128), dim3(128), 0, s, part, nvec, nch, nrhs, out,
+                     active);
+}
+
+void launch_mupdate(double* w, int64_t w_cs, const double* A, int64_t a_vs, int64_t a_cs, int nvec,
+                    const double* coef, double scale, int64_t len, int nrhs, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_mupdate, grid1(len, 256, nrhs), dim3(256), 0, s, w, w_cs, A, a_vs, a_cs, nvec, coef, scale,
+                     len, active);
+}
+
+void launch_axpy_shared(const double* x, int64_t x_cs, const double* u, const double* dot, double scale, double* y,
+                        int64_t len, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_shared, grid1(len, 256, nrhs), dim3(256), 0, s, x, x_cs, u, dot, scale, y, len);
+}
+
+void launch_scale_inv(const double* x, int64_t x_cs, const double* nrm, bool sq, double* y, int64_t y_cs,
+                      int64_t len, int nrhs, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_inv, grid1(len, 256, nrhs), dim3(256), 0, s, x, x_cs, nrm, sq ? 1 : 0, y, y_cs, len,
+                     active);
+}
+
+void launch_add(const double* a, const double* b, double sb, double* y, int64_t len, int nrhs, hipStream_t s) {
+  const int64_t tot = len * nrhs;
+  hipLaunchKernelGGL(k_add, grid1(tot, 256), dim3(256), 0, s, a, b, sb, y, tot);
+}
+
+void launch_givens(double* H, int ldh, double* cs, double* sn, double* g, const double* hnew, const double* nrm2,
+                   int j, int nrhs, double* res, const int* active, hipStream_t s) {
+  const int maxit = ldh - 1;
+  hipLaunchKernelGGL(k_givens, grid1(nrhs, 64), dim3(64), 0, s, H, ldh, maxit, cs, sn, g, hnew, nrm2, j, nrhs, res,
+                     active);
+}
+
+void launch_lsq(const double* H, int ldh, const double* g, const int* jcount, double* y, int nrhs, hipStream_t s) {
+  const int maxit = ldh - 1;
+  hipLaunchKernelGGL(k_lsq, grid1(nrhs, 64), dim3(64), 0, s, H, ldh, maxit, g, jcount, y, nrhs);
+}
+
+}  // namespace smpm

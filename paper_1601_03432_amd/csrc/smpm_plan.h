@@ -1,0 +1,90 @@
+// Host-side plan of the SMPM Schur complement solver: geometry, interface slot
+// layout, per-class element operators, block-Jacobi blocks and the coarse
+// deflation matrix.  Everything here is FP64 and built once by smpm_setup.
+//
+// Layouts (all row indices run fastest where a kernel's lanes read them):
+//   r-vectors   node (p,q) of element e = iy*m_x + ix at e*n^2 + q*n + p
+//   k-vectors   slot = side_index*n + t; side_index enumerates inter-element
+//               sides element-major, sides W,E,S,N; t runs along the side
+//               (q for W/E, p for S/N)
+//   d-vectors   interfaces: vertical (iy, ix|ix+1) row-major, then horizontal
+//               (iy|iy+1, ix) row-major
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace smpm {
+
+enum Side { SW = 0, SE = 1, SS = 2, SN = 3 };
+inline int opposite(int s) { return s ^ 1; }
+
+struct ElementClass {
+  double w = 0, h = 0;
+  int mask = 0;            // bit s set: side s is an inter-element side
+  double tau_own[4] = {0, 0, 0, 0};   // penalty of this element's sides
+  double tau_recv[4] = {0, 0, 0, 0};  // penalty of the neighbour side facing side s
+  int nslots = 0;          // slots owned by an element of this class
+  int side_col[4] = {-1, -1, -1, -1};  // first slot column of side s within the element
+};
+
+struct Plan {
+  int n = 0, mx = 0, my = 0, nel = 0;
+  int64_t r = 0, k = 0, d = 0, nsides = 0;
+  double alpha = 0;
+  std::vector<double> xb, yb;
+  std::vector<double> wx, hy;  // element widths / heights (equal within 1e-12 relative -> identical)
+  // GLL
+  std::vector<double> xi, omega, D;  // D row-major n x n
+  // elements
+  std::vector<int> mask, nbr, cls, side_slot, iface;  // nbr/side_slot/iface: nel*4
+  std::vector<int> slot_off;                           // nel+1
+  std::vector<int> side_elem, side_dir;                // per inter-element side
+  std::vector<int> iface_side;                         // d*2: side indices of the two sides
+  // classes and their operators
+  std::vector<ElementClass> classes;
+  std::vector<double> Ainv;     // per class n2 x n2 row-major  [l][m]
+  std::vector<double> AinvT;    // per class transposed         [m][l]
+  std::vector<int64_t> W_off;   // class*4: offset of side s' operator, -1 if absent
+  std::vector<double> Wc;       // outgoing flux of side s': [c][i] (nslots x n)
+  std::vector<double> Wr;       //                            [i][c] (n x nslots)
+  std::vector<int64_t> H_off;   // class*4
+  std::vector<double> Hc;       // flux of A^{-1} f through side s': [l][i] (n2 x n)
+  std::vector<double> Hr;       //                                    [i][l] (n x n2)
+  std::vector<double> WZ;       // class*4*n*4: [s'][t][s''] row sums of W over side s''
+  // block-Jacobi
+  int nblk = 0;
+  std::vector<int> blk_red;          // red element of each block
+  std::vector<int> blk_off;          // nblk+1 offsets into blk_slots
+  std::vector<int> blk_slots;        // slot list of every block
+  std::vector<int> blk_cls;          // block class of each block
+  std::vector<int> bcls_size;        // size of each block class
+  std::vector<int64_t> bcls_off;     // offset of each block class inverse
+  std::vector<double> MinvC;         // [c][r] per block class
+  std::vector<double> MinvR;         // [r][c] per block class
+  // coarse space
+  bool coarse_singular = false;
+  std::vector<double> C, G;          // d x d row-major
+  std::vector<double> tau_hat, uC;   // right / left null vectors of C when singular
+  // v0 = B 1, the right null vector of S
+  std::vector<double> v0;
+};
+
+// Builds the plan.  Returns an empty string on success, else the error text.
+std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* x_breaks,
+                       const double* y_breaks, double alpha);
+
+// Host export helpers used by the CPU tests of the setup.
+void export_schur_coo(const Plan& p, std::vector<int64_t>& ri, std::vector<int64_t>& ci,
+                      std::vector<double>& v);
+void export_flux_solve_coo(const Plan& p, std::vector<int64_t>& ri, std::vector<int64_t>& ci,
+                           std::vector<double>& v);
+void export_precond_inv_coo(const Plan& p, std::vector<int64_t>& ri, std::vector<int64_t>& ci,
+                            std::vector<double>& v);
+
+// Dense LU with partial pivoting (row-major, in place).  Returns false if singular.
+bool lu_factor(std::vector<double>& a, int m, std::vector<int>& piv);
+void lu_solve(const std::vector<double>& a, int m, const std::vector<int>& piv, double* b);
+bool dense_inverse(const std::vector<double>& a, int m, std::vector<double>& inv);
+
+}  // namespace smpm

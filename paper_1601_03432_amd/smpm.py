@@ -1,0 +1,260 @@
+"""Python binding of libsmpm (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module converts torch
+tensors (device memory and streams) and numpy arrays (host-side setup data)
+into the C ABI declared in include/smpm.h.  Importing it never computes
+anything; constructing a Context loads libsmpm.so and fails loudly if the
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmpm.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESINGULAR, ENODEVICE = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+PROJ_L, PROJ_S, PROJ_P, PROJ_Q, PROJ_MEAN = 0, 1, 2, 3, 4
+EXPORT_SCHUR, EXPORT_FLUX_SOLVE, EXPORT_PRECOND_INV, EXPORT_COARSE, EXPORT_COARSE_PINV = 0, 1, 2, 3, 4
+
+# every symbol include/smpm.h declares
+ABI_SYMBOLS = (
+    "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_slot_map",
+    "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
+    "smpm_schur_apply", "smpm_precond_apply", "smpm_project", "smpm_solve", "smpm_last_error",
+)
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("transpose", C.c_int),
+                ("variant", C.c_int), ("inner_tol", C.c_double), ("max_refine", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("refinements", C.c_int), ("rel_residual", C.c_double),
+                ("removed_component", C.c_double)]
+
+
+class SmpmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsmpm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libsmpm.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1601_03432_amd.build`")
+    lib = C.CDLL(path)
+    vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    lib.smpm_last_error.restype = C.c_char_p
+    lib.smpm_default_opts.argtypes = [C.POINTER(SolveOpts)]
+    lib.smpm_default_opts.restype = None
+    lib.smpm_plan.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, C.POINTER(vp)]
+    lib.smpm_setup.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, vp, C.POINTER(vp)]
+    lib.smpm_destroy.argtypes = [vp]
+    lib.smpm_destroy.restype = None
+    lib.smpm_sizes.argtypes = [vp, i64p, i64p, i64p]
+    lib.smpm_slot_map.argtypes = [vp, i64p]
+    lib.smpm_node_coords.argtypes = [vp, dp, dp]
+    lib.smpm_quadrature_weights.argtypes = [vp, dp]
+    lib.smpm_export.argtypes = [vp, C.c_int, i64p, i64p, i64p, dp]
+    lib.smpm_null_vectors.argtypes = [vp, dp, dp]
+    lib.smpm_schur_apply.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp]
+    lib.smpm_precond_apply.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp]
+    lib.smpm_project.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
+    lib.smpm_solve.argtypes = [vp, vp, vp, vp, C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+    for name in ABI_SYMBOLS:
+        if name not in ("smpm_destroy", "smpm_default_opts", "smpm_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise SmpmError(rc, _lib.smpm_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i64ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _stream(torch, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class Info:
+    iterations: int
+    refinements: int
+    rel_residual: float
+    removed_component: float
+    status: int
+
+
+class Context:
+    """One grid: m_y x m_x elements with breakpoints, n GLL points, penalty alpha.
+
+    device=False builds the host plan only (smpm_plan); device=True also uploads
+    it and computes the null vectors on the current GPU (smpm_setup).
+    """
+
+    def __init__(self, m_y, m_x, n, x_breaks, y_breaks, penalty=-32.0, device=True, stream=None):
+        lib = load_library()
+        xb = np.ascontiguousarray(x_breaks, np.float64)
+        yb = np.ascontiguousarray(y_breaks, np.float64)
+        if xb.size != m_x + 1 or yb.size != m_y + 1:
+            raise ValueError("breakpoint arrays must have m_x+1 and m_y+1 entries")
+        h = C.c_void_p()
+        if device:
+            import torch
+            rc = lib.smpm_setup(m_y, m_x, n, _dptr(xb), _dptr(yb), float(penalty), _stream(torch, stream),
+                                C.byref(h))
+        else:
+            rc = lib.smpm_plan(m_y, m_x, n, _dptr(xb), _dptr(yb), float(penalty), C.byref(h))
+        _check(rc)
+        self._h = h
+        self._lib = lib
+        self.device = device
+        self.m_x, self.m_y, self.n = m_x, m_y, n
+        r, k, d = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib.smpm_sizes(h, C.byref(r), C.byref(k), C.byref(d)))
+        self.r, self.k, self.d = r.value, k.value, d.value
+        self.nbdry = 2 * n * (m_x + m_y)
+
+    @classmethod
+    def from_workload(cls, w, penalty=-32.0, device=True):
+        return cls(w.m_y, w.m_x, w.n, w.x_breaks, w.y_breaks, penalty, device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.smpm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- host queries
+    def slot_map(self) -> np.ndarray:
+        out = np.zeros(self.k, np.int64)
+        _check(self._lib.smpm_slot_map(self._h, _i64ptr(out)))
+        return out
+
+    def node_coords(self):
+        x = np.zeros(self.r)
+        y = np.zeros(self.r)
+        _check(self._lib.smpm_node_coords(self._h, _dptr(x), _dptr(y)))
+        return x, y
+
+    def quadrature_weights(self) -> np.ndarray:
+        w = np.zeros(self.r)
+        _check(self._lib.smpm_quadrature_weights(self._h, _dptr(w)))
+        return w
+
+    def boundary_arc(self):
+        """Coordinates along the four edges in the boundary-data layout (S, N, W, E)."""
+        x, y = self.node_coords()
+        n, mx, my = self.n, self.m_x, self.m_y
+        xs = np.concatenate([x[ix * n * n:ix * n * n + n] for ix in range(mx)])
+        ys = np.concatenate([y[iy * mx * n * n:iy * mx * n * n + n * n:n] for iy in range(my)])
+        return xs, xs.copy(), ys, ys.copy()
+
+    def export(self, what):
+        """Host copy of a setup operator: scipy COO for sparse kinds, dense array for C/G."""
+        cnt = C.c_int64(0)
+        _check(self._lib.smpm_export(self._h, what, C.byref(cnt), None, None, None))
+        if what in (EXPORT_COARSE, EXPORT_COARSE_PINV):
+            v = np.zeros(cnt.value)
+            _check(self._lib.smpm_export(self._h, what, C.byref(cnt), None, None, _dptr(v)))
+            return v.reshape(self.d, self.d)
+        rows = np.zeros(cnt.value, np.int64)
+        cols = np.zeros(cnt.value, np.int64)
+        vals = np.zeros(cnt.value)
+        _check(self._lib.smpm_export(self._h, what, C.byref(cnt), _i64ptr(rows), _i64ptr(cols), _dptr(vals)))
+        import scipy.sparse as sp
+        shape = (self.k, self.r) if what == EXPORT_FLUX_SOLVE else (self.k, self.k)
+        return sp.coo_matrix((vals, (rows, cols)), shape=shape).tocsr()
+
+    def null_vectors(self):
+        uL = np.zeros(self.r)
+        uS = np.zeros(self.k)
+        _check(self._lib.smpm_null_vectors(self._h, _dptr(uL), _dptr(uS)))
+        return uL, uS
+
+    # ---------------------------------------------------------------- device calls
+    @staticmethod
+    def _as_cols(t, length):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+            raise TypeError("expected a CUDA float64 tensor")
+        if t.dim() == 1:
+            t = t.reshape(1, -1)
+        if t.shape[-1] != length:
+            raise ValueError(f"last dimension must be {length}")
+        return t.contiguous()
+
+    def schur_apply(self, v, transpose=False, stream=None):
+        import torch
+        v = self._as_cols(v, self.k)
+        out = torch.empty_like(v)
+        _check(self._lib.smpm_schur_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr()),
+                                          v.shape[0], int(transpose), _stream(torch, stream)))
+        return out
+
+    def precond_apply(self, x, transpose=False, stream=None):
+        import torch
+        x = self._as_cols(x, self.k)
+        out = torch.empty_like(x)
+        _check(self._lib.smpm_precond_apply(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                            x.shape[0], int(transpose), _stream(torch, stream)))
+        return out
+
+    def project(self, which, x, transpose=False, stream=None):
+        import torch
+        length = self.r if which in (PROJ_L, PROJ_MEAN) else self.k
+        x = self._as_cols(x, length)
+        out = torch.empty_like(x)
+        _check(self._lib.smpm_project(self._h, which, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                      x.shape[0], int(transpose), _stream(torch, stream)))
+        return out
+
+    def solve(self, f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64, transpose=False,
+              inner_tol=1e-6, max_refine=20, stream=None, raise_on_noconv=True):
+        import torch
+        f = self._as_cols(f, self.r)
+        nrhs = f.shape[0]
+        gp = None
+        if g is not None:
+            g = self._as_cols(g, self.nbdry)
+            if g.shape[0] != nrhs:
+                raise ValueError("g must have as many columns as f")
+            gp = C.c_void_p(g.data_ptr())
+        u = torch.empty_like(f)
+        opts = SolveOpts(tol, maxit, precision, int(transpose), variant, inner_tol, max_refine)
+        info = SolveInfo()
+        rc = self._lib.smpm_solve(self._h, C.c_void_p(f.data_ptr()), gp, C.c_void_p(u.data_ptr()), nrhs,
+                                  C.byref(opts), C.byref(info), _stream(torch, stream))
+        if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
+            _check(rc)
+        return u, Info(info.iterations, info.refinements, info.rel_residual, info.removed_component, rc)
