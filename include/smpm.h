@@ -33,7 +33,9 @@
  *
  * Penalty (Sec. 1.2 leaves its value open): tau = 2*penalty/(omega_0*h_perp)
  * on every element side, omega_0 = 2/(N(N+1)) the GLL end weight and h_perp
- * the element's extent normal to the side.  Recommended penalty: -32.
+ * the element's extent normal to the side.  Recommended penalty: +32 (it gives the
+ * fewest GMRES iterations among the values studied; any finite nonzero value
+ * is accepted).
  *
  * Ownership and streams.  A context owns its setup data and device workspace;
  * smpm_destroy releases them.  The caller owns every vector argument.  Device
@@ -109,6 +111,17 @@ typedef struct smpm_solve_info {
   double removed_component; /* u_L^T (f + T g) of column 0 (the projected-out incompatibility)   */
 } smpm_solve_info;
 
+typedef struct smpm_plan_stats {
+  int64_t element_classes;        /* distinct element operators (shared by equal elements)      */
+  int64_t block_classes;          /* distinct block-Jacobi inverses                             */
+  int64_t schur_operator_bytes;   /* FP64 bytes of all distinct Schur side-flux operators        */
+  int64_t precond_operator_bytes; /* FP64 bytes of all distinct block-Jacobi inverses            */
+  int64_t flux_operator_bytes;    /* FP64 bytes of all distinct B A^{-1} side operators          */
+  int64_t coarse_bytes;           /* FP64 bytes of the dense coarse pseudo-inverse (0 if none)   */
+  int32_t coarse_singular;        /* 1 if C is singular (pseudo-inverse), 0 otherwise            */
+  int32_t has_coarse;             /* 1 if the deflated solve is available                        */
+} smpm_plan_stats;
+
 /* Fills `opts` with the defaults listed above. */
 void smpm_default_opts(smpm_solve_opts *opts);
 
@@ -116,14 +129,17 @@ void smpm_default_opts(smpm_solve_opts *opts);
  * block-Jacobi inverses and the coarse matrix, all FP64 (Secs. 1.2-2).
  * x_breaks (m_x+1) and y_breaks (m_y+1) are host arrays of strictly increasing
  * element breakpoints.  Requires m_x*m_y >= 2, 3 <= n <= 32, penalty finite and
- * nonzero, d <= 4096.  The context supports sizes/exports only; device calls
- * on it return SMPM_ENODEVICE.  *out is set only on success. */
+ * nonzero.  Grids with more than 4096 interfaces get no coarse space: the
+ * deflated solve (variant 3) and the P/Q projections then return SMPM_EINVAL.
+ * The context supports sizes/exports only; device calls on it return
+ * SMPM_ENODEVICE.  *out is set only on success. */
 int smpm_plan(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
               double penalty, smpm_ctx **out);
 
-/* smpm_plan + upload to the current device + computation of the null vectors
- * u_S (left null vector of S) and u_L (left null vector of L, Sec. 1.4) by an
- * adjoint deflated GMRES solve.  Synchronous. */
+/* smpm_plan + upload to the current device.  Synchronous.  The null vectors
+ * u_S (left null vector of S) and u_L (left null vector of L, Sec. 1.4) are
+ * computed on first use (smpm_solve, smpm_project L/S, smpm_null_vectors) by a
+ * GMRES solve with the transposed Schur complement. */
 int smpm_setup(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
                double penalty, void *stream, smpm_ctx **out);
 
@@ -132,6 +148,9 @@ void smpm_destroy(smpm_ctx *ctx);
 
 /* r = n^2 m_x m_y nodes, k = 2 n d interface slots, d interfaces. */
 int smpm_sizes(const smpm_ctx *ctx, int64_t *r, int64_t *k, int64_t *d);
+
+/* Sizes of the setup operators (used for algorithmic byte counts). */
+int smpm_stats(const smpm_ctx *ctx, smpm_plan_stats *out);
 
 /* Host array slot_to_node[k]: the node (r-index) each slot sits on (E as a map). */
 int smpm_slot_map(const smpm_ctx *ctx, int64_t *slot_to_node);
@@ -148,9 +167,10 @@ int smpm_quadrature_weights(const smpm_ctx *ctx, double *w);
 int smpm_export(const smpm_ctx *ctx, int what, int64_t *count, int64_t *rows, int64_t *cols,
                 double *vals);
 
-/* Host copies of the unit null vectors computed at setup: uL[r], uS[k]
- * (either may be NULL).  SMPM_ENODEVICE for a plan-only context. */
-int smpm_null_vectors(const smpm_ctx *ctx, double *uL, double *uS);
+/* Host copies of the unit null vectors uL[r], uS[k] (either may be NULL),
+ * computing them on the default stream if needed.  SMPM_ENODEVICE for a
+ * plan-only context. */
+int smpm_null_vectors(smpm_ctx *ctx, double *uL, double *uS);
 
 /* Sv = S v (transpose = 0) or S^T v (transpose = 1) for nrhs k-vectors
  * (Eq. schur_complement_system).  Device pointers, column-blocked. */

@@ -31,7 +31,7 @@ Readings where the paper is silent or at odds with itself:
   corner node).
 * Penalty.  Sec. 1.2 leaves tau to a heuristic.  tau_{e,s} = 2 alpha /
   (omega_0 h_perp) with omega_0 = 2/(N(N+1)) the GLL end weight and h_perp the
-  element's extent normal to side s; alpha = -32 on all sides by default (the
+  element's extent normal to side s; alpha = +32 on all sides by default (the
   oracle accepts any alpha_int / alpha_phys).
 * Element-corner nodes receive the penalty terms of both sides containing them.
 * Block-Jacobi blocks follow the checkerboard: the block of a "red" element
@@ -54,7 +54,7 @@ from numpy.polynomial import legendre as leg
 W, E, S, N = 0, 1, 2, 3
 SIDES = (W, E, S, N)
 OPPOSITE = {W: E, E: W, S: N, N: S}
-DEFAULT_ALPHA = -32.0
+DEFAULT_ALPHA = 32.0
 
 
 # ---------------------------------------------------------------------------

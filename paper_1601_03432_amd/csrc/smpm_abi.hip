@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/smpm.h"
+#include "smpm_gmres.h"
 #include "smpm_kernels.h"
 #include "smpm_plan.h"
 
@@ -39,6 +40,13 @@ struct Workspace {
   double *h1 = nullptr, *h2 = nullptr, *scal = nullptr, *scal2 = nullptr, *res = nullptr, *y = nullptr;
   double* part = nullptr;
   int *active = nullptr, *jcount = nullptr;
+  // device-resident GMRES state
+  double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr;
+  double *beta_cur = nullptr, *beta0 = nullptr, *tolb = nullptr;
+  int *iters = nullptr, *counter = nullptr;
+  int* pinned = nullptr;  // 2 x nrhs host-visible activity flags
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int nch = 0, rows = 0;
   std::vector<void*> mem;
 };
 
@@ -53,11 +61,16 @@ struct smpm_ctx {
   double *uL = nullptr, *uS = nullptr, *v0hat = nullptr, *wq = nullptr, *ones = nullptr;
   double *rhat = nullptr;                    // 1/sqrt(r) vector (left null vector of L^T)
   double wsum = 0;
+  bool precond_regular = true;               // false when the single block is all of S
+  bool have_null = false;                    // u_L, u_S computed (on first use)
   std::vector<double> h_uL, h_uS;
   Workspace ws;
   ~smpm_ctx() {
     if (device) {
       for (void* p : ws.mem) (void)hipFree(p);
+      if (ws.pinned) (void)hipHostFree(ws.pinned);
+      for (hipEvent_t e : ws.ev)
+        if (e) (void)hipEventDestroy(e);
       for (void* p : mem) (void)hipFree(p);
     }
   }
@@ -99,6 +112,9 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   nrhs = std::max(nrhs, w.nrhs);
   maxit = std::max(maxit, w.maxit);
   for (void* p : w.mem) (void)hipFree(p);
+  if (w.pinned) (void)hipHostFree(w.pinned);
+  for (hipEvent_t e : w.ev)
+    if (e) (void)hipEventDestroy(e);
   w = Workspace();
   const Plan& P = c->plan;
   const size_t r = P.r, k = P.k, d = std::max<int64_t>(P.d, 1), R = nrhs, ldh = maxit + 1;
@@ -123,12 +139,29 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.scal, 4 * R);
   rc |= dalloc(w.mem, &w.scal2, 4 * R);
   rc |= dalloc(w.mem, &w.res, R);
-  rc |= dalloc(w.mem, &w.y, maxit * R);
+  rc |= dalloc(w.mem, &w.y, ldh * R);
   const size_t nch = reduce_chunks(std::max<int64_t>(P.r, P.k));
   rc |= dalloc(w.mem, &w.part, nch * ldh * R);
   rc |= ialloc(w.mem, &w.active, R);
   rc |= ialloc(w.mem, &w.jcount, R);
+  w.rows = gm_rows_per_chunk(P.k);
+  w.nch = (int)((P.k + w.rows - 1) / w.rows);
+  rc |= dalloc(w.mem, &w.part1, (size_t)w.nch * ldh * R);
+  rc |= dalloc(w.mem, &w.part2, (size_t)w.nch * ldh * R);
+  rc |= dalloc(w.mem, &w.part3, (size_t)w.nch * R);
+  rc |= dalloc(w.mem, &w.beta_cur, R);
+  rc |= dalloc(w.mem, &w.beta0, R);
+  rc |= dalloc(w.mem, &w.tolb, R);
+  rc |= ialloc(w.mem, &w.iters, R);
+  rc |= ialloc(w.mem, &w.counter, 4 * R);
   if (rc != SMPM_OK) return SMPM_ENOMEM;
+  if (hipHostMalloc((void**)&w.pinned, 2 * R * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return fail(SMPM_ENOMEM, "hipHostMalloc failed");
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&w.ev[i], hipEventDisableTiming) != hipSuccess)
+      return fail(SMPM_EHIP, "hipEventCreate failed");
+  if (hipMemset(w.counter, 0, 4 * R * sizeof(int)) != hipSuccess) return fail(SMPM_EHIP, "hipMemset failed");
+  if (hipDeviceSynchronize() != hipSuccess) return fail(SMPM_EHIP, "hipDeviceSynchronize failed");
   w.nrhs = nrhs;
   w.maxit = maxit;
   return SMPM_OK;
@@ -156,15 +189,17 @@ void apply_op(smpm_ctx* c, int kind, bool tr, const double* v, double* w, int nr
     launch_schur(P, v, w, nrhs, tr, act, s);
     return;
   }
-  launch_precond(P, v, W.z, nrhs, tr, act, s);
+  if (kind != OP_RANK1 || c->precond_regular) launch_precond(P, v, W.z, nrhs, tr, act, s);
   if (kind == OP_SM) {
     launch_schur(P, W.z, w, nrhs, tr, act, s);
     return;
   }
   if (kind == OP_RANK1) {
-    // (S^T + v0hat v0hat^T) M^{-T} v: nonsingular, its inverse transpose maps v0hat to u_S
-    launch_schur(P, W.z, w, nrhs, true, act, s);
-    launch_mdot(c->v0hat, 0, 0, 1, W.z, P.k, nullptr, P.k, nrhs, W.part, W.scal2, act, s);
+    // (S^T + v0hat v0hat^T) M^{-T} v: nonsingular, its inverse transpose maps v0hat to u_S.
+    // On a two-element grid M = S is singular and the operator runs unpreconditioned.
+    const double* zin = c->precond_regular ? W.z : v;
+    launch_schur(P, zin, w, nrhs, true, act, s);
+    launch_mdot(c->v0hat, 0, 0, 1, zin, P.k, nullptr, P.k, nrhs, W.part, W.scal2, act, s);
     launch_axpy_shared(w, P.k, c->v0hat, W.scal2, -1.0, w, P.k, nrhs, s);
     return;
   }
@@ -184,7 +219,9 @@ int gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, 
   Workspace& W = c->ws;
   const int64_t k = P.k;
   const int ldh = W.maxit + 1;
-  const int64_t vcs = (int64_t)k * ldh;  // V column stride
+  // Krylov basis V[j][col][0..k): the j-th vectors of all columns are contiguous so the
+  // operator kernels see an ordinary column-blocked block of nrhs k-vectors
+  const int64_t vvs = (int64_t)k * nrhs;  // stride between basis vectors
   iters.assign(nrhs, 0);
   std::vector<int> act(nrhs, 1);
   HIPCHK(hipMemcpyAsync(W.active, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
@@ -211,23 +248,23 @@ int gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, 
   for (int col = 0; col < nrhs; ++col) gi[(size_t)col * ldh] = beta[col];
   HIPCHK(hipMemcpyAsync(W.g, gi.data(), gi.size() * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(W.active, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-  launch_scale_inv(r0, k, W.scal, true, W.V, vcs, k, nrhs, nullptr, s);
+  launch_scale_inv(r0, k, W.scal, true, W.V, k, k, nrhs, nullptr, s);
   int jmax = 0;
   std::vector<double> res(nrhs);
   int nact = 0;
   for (int col = 0; col < nrhs; ++col) nact += act[col];
   for (int j = 0; j < maxit && nact > 0; ++j) {
-    double* vj = W.V + (int64_t)j * k;
+    double* vj = W.V + (int64_t)j * vvs;
     apply_op(c, kind, tr, vj, W.w, nrhs, W.active, s);
     // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2
-    launch_mdot(W.V, k, vcs, j + 1, W.w, k, nullptr, k, nrhs, W.part, W.h1, W.active, s);
-    launch_mupdate(W.w, k, W.V, k, vcs, j + 1, W.h1, 1.0, k, nrhs, W.active, s);
-    launch_mdot(W.V, k, vcs, j + 1, W.w, k, nullptr, k, nrhs, W.part, W.h2, W.active, s);
-    launch_mupdate(W.w, k, W.V, k, vcs, j + 1, W.h2, 1.0, k, nrhs, W.active, s);
+    launch_mdot(W.V, vvs, k, j + 1, W.w, k, nullptr, k, nrhs, W.part, W.h1, W.active, s);
+    launch_mupdate(W.w, k, W.V, vvs, k, j + 1, W.h1, 1.0, k, nrhs, W.active, s);
+    launch_mdot(W.V, vvs, k, j + 1, W.w, k, nullptr, k, nrhs, W.part, W.h2, W.active, s);
+    launch_mupdate(W.w, k, W.V, vvs, k, j + 1, W.h2, 1.0, k, nrhs, W.active, s);
     launch_add(W.h1, W.h2, 1.0, W.h1, (int64_t)(j + 1) * nrhs, 1, s);
     launch_mdot(W.w, 0, k, 1, W.w, k, nullptr, k, nrhs, W.part, W.scal, W.active, s);
     launch_givens(W.H, ldh, W.cs, W.sn, W.g, W.h1, W.scal, j, nrhs, W.res, W.active, s);
-    launch_scale_inv(W.w, k, W.scal, true, W.V + (int64_t)(j + 1) * k, vcs, k, nrhs, W.active, s);
+    launch_scale_inv(W.w, k, W.scal, true, W.V + (int64_t)(j + 1) * vvs, k, k, nrhs, W.active, s);
     HIPCHK(hipMemcpyAsync(res.data(), W.res, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     bool changed = false;
@@ -250,8 +287,83 @@ int gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, 
   // the coefficient array of column col starts at y + col*maxit; mupdate reads coef + col*nvec
   for (int col = 0; col < nrhs; ++col)
     if (iters[col] > 0)
-      launch_mupdate(x + (int64_t)col * k, k, W.V + (int64_t)col * vcs, k, 0, iters[col],
+      launch_mupdate(x + (int64_t)col * k, k, W.V + (int64_t)col * k, vvs, 0, iters[col],
                      W.y + (int64_t)col * W.maxit, -1.0, k, 1, nullptr, s);
+  return jmax;
+}
+
+GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
+  Workspace& W = c->ws;
+  GmState S;
+  S.V = W.V;
+  S.vvs = c->plan.k * nrhs;
+  S.w = W.w;
+  S.z = W.z;
+  S.t = W.t;
+  S.c = W.c;
+  S.c2 = W.c2;
+  S.part1 = W.part1;
+  S.part2 = W.part2;
+  S.part3 = W.part3;
+  S.h1 = W.h1;
+  S.h2 = W.h2;
+  S.H = W.H;
+  S.cs = W.cs;
+  S.sn = W.sn;
+  S.g = W.g;
+  S.y = W.y;
+  S.beta_cur = W.beta_cur;
+  S.beta0 = W.beta0;
+  S.tolb = W.tolb;
+  S.res = W.res;
+  S.active = W.active;
+  S.iters = W.iters;
+  S.counter = W.counter;
+  S.ldv = W.maxit + 1;
+  S.maxit = maxit;
+  S.nch = W.nch;
+  S.rows = W.rows;
+  return S;
+}
+
+// Device-resident GMRES from x0 = 0 on S (kind 1), S M^{-1} (2) or P S M^{-1} (3).
+// The host enqueues Arnoldi steps in chunks and polls per-column activity flags
+// one chunk behind, so the device never waits for the host.
+int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, double tol, int maxit,
+              std::vector<int>& iters, hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  GmState S = gm_state(c, nrhs, maxit);
+  if (kind == 3) {
+    launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
+    launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
+    launch_prolong(P, b, W.c2, W.w, nrhs, tr ? 2 : 1, -1.0, nullptr, s);
+  } else {
+    HIPCHK(hipMemcpyAsync(W.w, b, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
+  }
+  gm_start(P, S, nrhs, tol, s);
+  constexpr int kChunkIters = 8;
+  int chunk = 0;
+  for (int j0 = 0; j0 < maxit; j0 += kChunkIters, ++chunk) {
+    const int j1 = std::min(maxit, j0 + kChunkIters);
+    for (int j = j0; j < j1; ++j) gm_step(P, S, nrhs, j, kind, tr, s);
+    int* flags = W.pinned + (chunk & 1) * W.nrhs;
+    HIPCHK(hipMemcpyAsync(flags, W.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(W.ev[chunk & 1], s));
+    if (chunk >= 1) {
+      HIPCHK(hipEventSynchronize(W.ev[(chunk - 1) & 1]));
+      const int* prev = W.pinned + ((chunk - 1) & 1) * W.nrhs;
+      bool any = false;
+      for (int i = 0; i < nrhs; ++i) any |= prev[i] != 0;
+      if (!any) break;
+    }
+  }
+  gm_finish(P, S, nrhs, x, s);
+  iters.assign(nrhs, 0);
+  HIPCHK(hipMemcpyAsync(iters.data(), W.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int jmax = 0;
+  for (int v : iters) jmax = std::max(jmax, v);
   return jmax;
 }
 
@@ -260,7 +372,7 @@ int solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, i
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   double* x1 = W.x;  // note: x may not alias W.x
-  int rc = gmres(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s);
+  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s);
   if (rc < 0) return rc;
   if (kind == OP_S) {
     HIPCHK(hipMemcpyAsync(x, x1, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
@@ -300,6 +412,7 @@ int true_residual(smpm_ctx* c, bool tr, const double* b, const double* x, int nr
 // v0hat, so u_S = normalize((S + v0hat v0hat^T)^{-T} v0hat).  u_L = normalize(A^{-T} B^T u_S)
 // up to sign, since u_L^T L = 0 and E^T u_L is parallel to u_S (Sec. 1.4).
 int compute_null_vectors(smpm_ctx* c, hipStream_t s) {
+  if (c->have_null) return SMPM_OK;
   const Plan& Pl = c->plan;
   const DevPlan& P = c->dp;
   int rc = ensure_ws(c, 1, 600);
@@ -310,7 +423,10 @@ int compute_null_vectors(smpm_ctx* c, hipStream_t s) {
   // GMRES on (S^T + v0hat v0hat^T) M^{-T}, then y <- M^{-T} y
   int j = gmres(c, OP_RANK1, true, c->v0hat, W.x, 1, 1e-14, 600, it, s);
   if (j < 0) return j;
-  launch_precond(P, W.x, y, 1, true, nullptr, s);
+  if (c->precond_regular)
+    launch_precond(P, W.x, y, 1, true, nullptr, s);
+  else
+    HIPCHK(hipMemcpyAsync(y, W.x, sizeof(double) * Pl.k, hipMemcpyDeviceToDevice, s));
   std::vector<double> hy(Pl.k);
   HIPCHK(hipMemcpyAsync(hy.data(), y, Pl.k * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -342,6 +458,7 @@ int compute_null_vectors(smpm_ctx* c, hipStream_t s) {
   c->h_uL = hl;
   HIPCHK(hipMemcpyAsync(c->uL, hl.data(), Pl.r * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
+  c->have_null = true;
   return SMPM_OK;
 }
 
@@ -380,8 +497,10 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
       }
     }
   std::vector<double> GT(p.G.size());
-  for (int64_t i = 0; i < p.d; ++i)
-    for (int64_t j = 0; j < p.d; ++j) GT[(size_t)j * p.d + i] = p.G[(size_t)i * p.d + j];
+  if (p.has_coarse)
+    for (int64_t i = 0; i < p.d; ++i)
+      for (int64_t j = 0; j < p.d; ++j) GT[(size_t)j * p.d + i] = p.G[(size_t)i * p.d + j];
+  d.has_coarse = p.has_coarse ? 1 : 0;
   // boundary data map: south, north, west, east
   std::vector<int> bnode;
   std::vector<double> btau;
@@ -432,6 +551,10 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   rc |= upload(c, p.MinvR, &d.MinvR, s);
   rc |= upload(c, p.G, &d.G, s);
   rc |= upload(c, GT, &d.GT, s);
+  d.ngrp = p.ngrp;
+  d.grp_size = p.grp_size;
+  rc |= upload(c, p.grp_cls, &d.grp_cls, s);
+  rc |= upload(c, p.grp_elem, &d.grp_elem, s);
   rc |= upload(c, bnode, &d.bdry_node, s);
   rc |= upload(c, btau, &d.bdry_tau, s);
   if (rc != SMPM_OK) return SMPM_ENOMEM;
@@ -453,6 +576,7 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   nv = std::sqrt(nv);
   for (double& v : v0h) v /= nv;
   c->wsum = wsum;
+  c->precond_regular = !(p.nblk == 1 && (int64_t)p.blk_off[1] == p.k);
   const double* tmp = nullptr;
   rc |= upload(c, wq, &tmp, s);
   c->wq = const_cast<double*>(tmp);
@@ -529,7 +653,6 @@ int smpm_setup(int m_y, int m_x, int n, const double* xb, const double* yb, doub
   }
   c->device = true;
   rc = do_upload(c, s);
-  if (!rc) rc = compute_null_vectors(c, s);
   if (rc) {
     std::string keep = g_err;
     delete c;
@@ -547,6 +670,20 @@ int smpm_sizes(const smpm_ctx* c, int64_t* r, int64_t* k, int64_t* d) {
   if (r) *r = c->plan.r;
   if (k) *k = c->plan.k;
   if (d) *d = c->plan.d;
+  return SMPM_OK;
+}
+
+int smpm_stats(const smpm_ctx* c, smpm_plan_stats* o) {
+  if (!c || !o) return fail(SMPM_EINVAL, "null argument");
+  const Plan& p = c->plan;
+  o->element_classes = (int64_t)p.classes.size();
+  o->block_classes = (int64_t)p.bcls_size.size();
+  o->schur_operator_bytes = (int64_t)(p.Wc.size() * sizeof(double));
+  o->precond_operator_bytes = (int64_t)(p.MinvC.size() * sizeof(double));
+  o->flux_operator_bytes = (int64_t)(p.Hc.size() * sizeof(double));
+  o->coarse_bytes = (int64_t)(p.G.size() * sizeof(double));
+  o->coarse_singular = p.coarse_singular ? 1 : 0;
+  o->has_coarse = p.has_coarse ? 1 : 0;
   return SMPM_OK;
 }
 
@@ -624,9 +761,11 @@ int smpm_export(const smpm_ctx* c, int what, int64_t* count, int64_t* rows, int6
   return SMPM_OK;
 }
 
-int smpm_null_vectors(const smpm_ctx* c, double* uL, double* uS) {
-  if (!c) return fail(SMPM_EINVAL, "null context");
-  if (!c->device) return fail(SMPM_ENODEVICE, "context has no device data (built by smpm_plan)");
+int smpm_null_vectors(smpm_ctx* c, double* uL, double* uS) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  rc = compute_null_vectors(c, nullptr);
+  if (rc) return rc;
   if (uL) std::copy(c->h_uL.begin(), c->h_uL.end(), uL);
   if (uS) std::copy(c->h_uS.begin(), c->h_uS.end(), uS);
   return SMPM_OK;
@@ -664,6 +803,12 @@ int smpm_project(smpm_ctx* c, int which, const double* in, double* out, int nrhs
   Workspace& W = c->ws;
   const DevPlan& P = c->dp;
   const bool tr = transpose != 0;
+  if ((which == SMPM_PROJ_L || which == SMPM_PROJ_S) && !tr) {
+    rc = compute_null_vectors(c, s);
+    if (rc) return rc;
+  }
+  if ((which == SMPM_PROJ_P || which == SMPM_PROJ_Q) && !c->plan.has_coarse)
+    return fail(SMPM_EINVAL, "no coarse space on this grid (d > 4096)");
   switch (which) {
     case SMPM_PROJ_L: {
       const double* u = tr ? c->rhat : c->uL;
@@ -731,15 +876,19 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   smpm_solve_opts o;
   smpm_default_opts(&o);
   if (opts_in) o = *opts_in;
-  if (o.maxit < 1 || !(o.tol > 0) || o.variant < 1 || o.variant > 3)
-    return fail(SMPM_EINVAL, "bad solve options");
+  if (o.maxit < 1 || o.maxit > kMaxIt || !(o.tol > 0) || o.variant < 1 || o.variant > 3)
+    return fail(SMPM_EINVAL, "bad solve options (1 <= maxit <= 1000, tol > 0, variant 1..3)");
   if (o.precision != SMPM_FP64) return fail(SMPM_EINVAL, "precision not supported by this build");
   if (o.transpose) return fail(SMPM_EINVAL, "adjoint solve not supported by this build");
+  if (o.variant == 3 && !c->plan.has_coarse)
+    return fail(SMPM_EINVAL, "no coarse space on this grid (d > 4096): use variant 1 or 2");
   const Plan& Pl = c->plan;
   const DevPlan& P = c->dp;
   const size_t rb = sizeof(double) * Pl.r * nrhs;
   if (aliases(f, rb, u, rb)) return fail(SMPM_EINVAL, "f and u alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = compute_null_vectors(c, s);
+  if (rc) return rc;
   rc = ensure_ws(c, nrhs, o.maxit);
   if (rc) return rc;
   Workspace& W = c->ws;

@@ -1,0 +1,53 @@
+// Device-resident GMRES state and launchers (see smpm_gmres.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "smpm_kernels.h"
+
+namespace smpm {
+
+constexpr int kMaxIt = 1000;     // largest Krylov dimension per solve
+constexpr int kRowsMax = 2048;   // rows of a k-vector handled by one block
+
+struct GmState {
+  double* V;        // basis: V + i*vvs + col*k
+  int64_t vvs;      // stride between basis vectors (= k * nrhs)
+  double* w;        // working vector, col*k
+  double* z;        // M^{-1} v_j
+  double* t;        // S z
+  double* c;        // Z^T t
+  double* c2;       // G c
+  double* part1;    // partial dots, col*ldv*nch + i*nch + chunk
+  double* part2;
+  double* part3;    // partial squared norms, col*nch + chunk
+  double* h1;       // first-pass coefficients, col*ldv
+  double* h2;       // second-pass coefficients
+  double* H;        // rotated Hessenberg R, col*ldv*maxit_alloc + j*ldv + i
+  double* cs;       // Givens cosines, col*ldv
+  double* sn;       // Givens sines
+  double* g;        // rotated right-hand side
+  double* y;        // least-squares solution
+  double* beta_cur; // norm of the vector being normalized
+  double* beta0;    // initial residual norm
+  double* tolb;     // tol * beta0
+  double* res;      // residual estimate |g_{j+1}|
+  int* active;      // 1 while the column iterates
+  int* iters;       // completed Arnoldi steps
+  int* counter;     // last-block tickets, col*4
+  int ldv;          // leading dimension (allocated maxit + 1)
+  int maxit;        // iteration limit of this solve
+  int nch;          // row chunks of a k-vector
+  int rows;         // rows per chunk
+};
+
+void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStream_t s);
+// kind: 1 = S, 2 = S M^{-1}, 3 = P S M^{-1}; tr selects the transposed operators
+void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s);
+void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s);
+void gm_reset_counters(int* counter, int n, hipStream_t s);
+int gm_rows_per_chunk(int64_t k);
+
+}  // namespace smpm

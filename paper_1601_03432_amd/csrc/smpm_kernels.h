@@ -11,6 +11,7 @@ constexpr int kMaxN = 32;
 // Plain-old-data view of the device copy of a Plan; passed to kernels by value.
 struct DevPlan {
   int n, n2, nel, d, nblk, ncls, mx, my;
+  int has_coarse;          // 1 if G is built (deflation available)
   int64_t r, k, nsides, nbdry;
   const int* nbr;          // nel*4
   const int* cls;          // nel
@@ -43,7 +44,13 @@ struct DevPlan {
   const double* GT;        // its transpose
   const int* bdry_node;    // nbdry
   const double* bdry_tau;  // nbdry
+  int ngrp;                // element groups (same class, up to grp_size elements)
+  int grp_size;            // 1, 2, 4 or 8
+  const int* grp_cls;      // ngrp
+  const int* grp_elem;     // ngrp*kGroup, -1 padded
 };
+
+constexpr int kGroup = 8;
 
 // ---- operator applies; nrhs columns, column-blocked with the natural lengths
 void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,

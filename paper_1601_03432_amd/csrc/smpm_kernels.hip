@@ -20,75 +20,134 @@ __device__ __forceinline__ int side_node(int n, int s, int t) {
 
 // ------------------------------------------------------------------ Schur apply
 
-// t = y + B A^{-1} E y (Eq. schur_complement_system).  Receiver e, side s gets the
-// flux of its neighbour j through j's facing side: W_{cls(j), s^1} y_j.
+// Blocks are mapped so that each of the 8 XCDs (which receive block ids
+// round-robin) works on one contiguous range of groups: neighbouring elements
+// then share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
+
+constexpr int kPrefetch = 8;  // independent operator loads in flight per lane
+
+// t = y + B A^{-1} E y (Eq. schur_complement_system), pushed from senders.
+// One wavefront takes a group of up to kGroup elements of one class J: their
+// slots are staged in LDS, lane (s, i) holds row i of J's outgoing flux W_{J,s}
+// and accumulates it against all elements of the group, so each operator entry
+// is read once per group.  Sender e's side-s flux lands in the facing slots of
+// its neighbour, which have no other writer.
+template <int G>
 __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __restrict__ y,
                                                    double* __restrict__ t, const int* __restrict__ active) {
-  __shared__ double ys[4][4][4 * kMaxN];
+  extern __shared__ double lds[];
   const int col = blockIdx.y;
   if (active && !active[col]) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int e = blockIdx.x * 4 + wave;
-  const int n = P.n;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
+  const int n = P.n, ld = 4 * n;
+  double* ys = lds + (size_t)wave * G * ld;
   const double* yc = y + (int64_t)col * P.k;
   double* tc = t + (int64_t)col * P.k;
-  if (e < P.nel) {
-    for (int s = 0; s < 4; ++s) {
-      const int j = P.nbr[e * 4 + s];
-      if (j < 0) continue;
-      const int ns = P.cls_nslots[P.cls[j]];
-      const int base = P.slot_off[j];
-      for (int c = lane; c < ns; c += 64) ys[wave][s][c] = yc[base + c];
+  int elem[G];
+  int J = 0, ns = 0;
+  if (g < P.ngrp) {
+    J = P.grp_cls[g];
+    ns = P.cls_nslots[J];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      elem[u] = P.grp_elem[g * kGroup + u];
+      if (elem[u] >= 0) {
+        const int base = P.slot_off[elem[u]];
+        for (int c = lane; c < ns; c += 64) ys[u * ld + c] = yc[base + c];
+      }
     }
   }
   __syncthreads();
-  if (e >= P.nel) return;
+  if (g >= P.ngrp) return;
   for (int o = lane; o < 4 * n; o += 64) {
     const int s = o / n, i = o - s * n;
-    const int j = P.nbr[e * 4 + s];
-    if (j < 0) continue;
-    const int J = P.cls[j];
-    const int ns = P.cls_nslots[J];
-    const double* Wp = P.Wc + P.W_off[J * 4 + (s ^ 1)];
-    double acc = 0.0;
-    for (int c = 0; c < ns; ++c) acc = fma(Wp[c * n + i], ys[wave][s][c], acc);
-    const int slot = P.side_slot[e * 4 + s] + i;
-    tc[slot] = yc[slot] + acc;
+    if (P.cls_sidecol[J * 4 + s] < 0) continue;
+    const double* Wp = P.Wc + P.W_off[J * 4 + s];
+    double acc[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) acc[u] = 0.0;
+    // operator loads are issued kPrefetch at a time so they overlap
+    for (int c0 = 0; c0 < ns; c0 += kPrefetch) {
+      double wv[kPrefetch];
+#pragma unroll
+      for (int q = 0; q < kPrefetch; ++q) wv[q] = c0 + q < ns ? Wp[(c0 + q) * n + i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kPrefetch; ++q) {
+        if (c0 + q >= ns) break;
+#pragma unroll
+        for (int u = 0; u < G; ++u) acc[u] = fma(wv[q], ys[u * ld + c0 + q], acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (elem[u] < 0) break;
+      const int recv = P.nbr[elem[u] * 4 + s];
+      const int slot = P.side_slot[recv * 4 + (s ^ 1)] + i;
+      tc[slot] = yc[slot] + acc[u];
+    }
   }
 }
 
-// t = y + E^T A^{-T} B^T y: element J collects the slots its fluxes feed.
+// t = y + E^T A^{-T} B^T y for a group of same-class elements: element e collects
+// W_{J,s}^T applied to the slots its side-s flux feeds.  Lane = slot column c.
+template <int G>
 __global__ __launch_bounds__(256) void k_schur_adj(DevPlan P, const double* __restrict__ y,
                                                    double* __restrict__ t, const int* __restrict__ active) {
-  __shared__ double yr[4][4][kMaxN];
+  extern __shared__ double lds[];
   const int col = blockIdx.y;
   if (active && !active[col]) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int e = blockIdx.x * 4 + wave;
-  const int n = P.n;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
+  const int n = P.n, ld = 4 * n;
+  double* yr = lds + (size_t)wave * G * ld;  // [u][s*n + i]
   const double* yc = y + (int64_t)col * P.k;
   double* tc = t + (int64_t)col * P.k;
-  if (e < P.nel) {
-    for (int s = 0; s < 4; ++s) {
-      const int j = P.nbr[e * 4 + s];
-      if (j < 0) continue;
-      const int base = P.side_slot[j * 4 + (s ^ 1)];
-      for (int i = lane; i < n; i += 64) yr[wave][s][i] = yc[base + i];
+  int elem[G];
+  int J = 0, ns = 0;
+  if (g < P.ngrp) {
+    J = P.grp_cls[g];
+    ns = P.cls_nslots[J];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      elem[u] = P.grp_elem[g * kGroup + u];
+      if (elem[u] >= 0) {
+        for (int q = lane; q < ld; q += 64) {
+          const int s = q / n, i = q - s * n;
+          const int j = P.nbr[elem[u] * 4 + s];
+          yr[u * ld + q] = j >= 0 ? yc[P.side_slot[j * 4 + (s ^ 1)] + i] : 0.0;
+        }
+      }
     }
   }
   __syncthreads();
-  if (e >= P.nel) return;
-  const int J = P.cls[e];
-  const int ns = P.cls_nslots[J];
+  if (g >= P.ngrp) return;
   for (int c = lane; c < ns; c += 64) {
-    double acc = 0.0;
+    double acc[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) acc[u] = 0.0;
     for (int s = 0; s < 4; ++s) {
-      if (P.nbr[e * 4 + s] < 0) continue;
+      if (P.cls_sidecol[J * 4 + s] < 0) continue;
       const double* Wp = P.Wr + P.W_off[J * 4 + s];
-      for (int i = 0; i < n; ++i) acc = fma(Wp[i * ns + c], yr[wave][s][i], acc);
+      for (int i0 = 0; i0 < n; i0 += kPrefetch) {
+        double wv[kPrefetch];
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) wv[q] = i0 + q < n ? Wp[(i0 + q) * ns + c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+          if (i0 + q >= n) break;
+#pragma unroll
+          for (int u = 0; u < G; ++u) acc[u] = fma(wv[q], yr[u * ld + s * n + i0 + q], acc[u]);
+        }
+      }
     }
-    const int slot = P.slot_off[e] + c;
-    tc[slot] = yc[slot] + acc;
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (elem[u] < 0) break;
+      const int slot = P.slot_off[elem[u]] + c;
+      tc[slot] = yc[slot] + acc[u];
+    }
   }
 }
 
@@ -112,6 +171,7 @@ __global__ __launch_bounds__(64) void k_flux(DevPlan P, const double* __restrict
     if (j < 0) continue;
     const double* Hp = P.Hc + P.H_off[P.cls[j] * 4 + (s ^ 1)];
     double acc = 0.0;
+#pragma unroll 8
     for (int l = 0; l < n2; ++l) acc = fma(Hp[l * n + i], fs[s * n2 + l], acc);
     bc[P.side_slot[e * 4 + s] + i] = acc;
   }
@@ -135,6 +195,7 @@ __global__ __launch_bounds__(256) void k_flux_adj(DevPlan P, const double* __res
     for (int s = 0; s < 4; ++s) {
       if (P.nbr[e * 4 + s] < 0) continue;
       const double* Hp = P.Hr + P.H_off[J * 4 + s];
+#pragma unroll 8
       for (int i = 0; i < n; ++i) acc = fma(Hp[i * n2 + l], xr[s][i], acc);
     }
     yc[(int64_t)e * n2 + l] = acc;
@@ -165,6 +226,7 @@ __global__ __launch_bounds__(256) void k_backsub(DevPlan P, const double* __rest
   const double* Ap = P.AinvT + (int64_t)P.cls[e] * n2 * n2;
   for (int l = tid; l < n2; l += 256) {
     double acc = 0.0;
+#pragma unroll 8
     for (int m = 0; m < n2; ++m) acc = fma(Ap[(int64_t)m * n2 + l], zs[m], acc);
     uc[(int64_t)e * n2 + l] = acc;
   }
@@ -184,6 +246,7 @@ __global__ __launch_bounds__(256) void k_local_adj(DevPlan P, const double* __re
   const double* Ap = P.Ainv + (int64_t)P.cls[e] * n2 * n2;
   for (int l = tid; l < n2; l += 256) {
     double acc = 0.0;
+#pragma unroll 8
     for (int m = 0; m < n2; ++m) acc = fma(Ap[(int64_t)m * n2 + l], cs[m], acc);
     if (to_slots)
       ws[l] = acc;
@@ -215,6 +278,7 @@ __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __rest
   const double* Mp = (transpose ? P.MinvR : P.MinvC) + P.bcls_off[bc];
   for (int r = tid; r < sb; r += 256) {
     double acc = 0.0;
+#pragma unroll 8
     for (int c = 0; c < sb; ++c) acc = fma(Mp[c * sb + r], xs[c], acc);
     yc[P.blk_slots[o + r]] = acc;
   }
@@ -222,34 +286,41 @@ __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __rest
 
 // ------------------------------------------------------------------ deflation
 
-__global__ void k_iface_sum(DevPlan P, const double* __restrict__ t, double* __restrict__ c,
-                            const int* __restrict__ active) {
+// c_j = sum of t over the 2n slots of interface j: one wavefront per interface,
+// lanes over slots, fixed shuffle tree.
+__global__ __launch_bounds__(256) void k_iface_sum(DevPlan P, const double* __restrict__ t, double* __restrict__ c,
+                                                   const int* __restrict__ active) {
   const int col = blockIdx.y;
   if (active && !active[col]) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= P.d) return;
   const double* tc = t + (int64_t)col * P.k;
   const int n = P.n;
   double acc = 0.0;
-  for (int h = 0; h < 2; ++h) {
-    const int64_t base = (int64_t)P.iface_side[2 * j + h] * n;
-    for (int i = 0; i < n; ++i) acc += tc[base + i];
+  for (int q = lane; q < 2 * n; q += 64) {
+    const int h = q / n, i = q - h * n;
+    acc += tc[(int64_t)P.iface_side[2 * j + h] * n + i];
   }
-  c[(int64_t)col * P.d + j] = acc;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) c[(int64_t)col * P.d + j] = acc;
 }
 
-__global__ void k_coarse(DevPlan P, const double* __restrict__ c, double* __restrict__ c2, int transpose,
-                         const int* __restrict__ active) {
+// c2 = G c (or G^T c): one wavefront per row, lanes over the row, fixed shuffle tree.
+__global__ __launch_bounds__(256) void k_coarse(DevPlan P, const double* __restrict__ c, double* __restrict__ c2,
+                                                int transpose, const int* __restrict__ active) {
   const int col = blockIdx.y;
   if (active && !active[col]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int d = P.d;
   if (i >= d) return;
-  const double* Gp = transpose ? P.G : P.GT;  // element [j][i] of the transposed storage
+  const double* Gp = (transpose ? P.GT : P.G) + (int64_t)i * d;  // row i of G (or of G^T)
   const double* cc = c + (int64_t)col * d;
   double acc = 0.0;
-  for (int j = 0; j < d; ++j) acc = fma(Gp[(int64_t)j * d + i], cc[j], acc);
-  c2[(int64_t)col * d + i] = acc;
+  for (int j = lane; j < d; j += 64) acc = fma(Gp[j], cc[j], acc);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) c2[(int64_t)col * d + i] = acc;
 }
 
 // w = t + sign * (Z c2 + {0, S Z c2, S^T Z c2})
@@ -454,11 +525,21 @@ inline dim3 grid1(int64_t len, int bs, int ny = 1) { return dim3((unsigned)((len
 
 void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
                   hipStream_t s) {
-  dim3 g((P.nel + 3) / 4, nrhs);
-  if (transpose)
-    hipLaunchKernelGGL(k_schur_adj, g, dim3(256), 0, s, P, y, t, active);
-  else
-    hipLaunchKernelGGL(k_schur_fwd, g, dim3(256), 0, s, P, y, t, active);
+  const int blocks = ((P.ngrp + 3) / 4 + 7) / 8 * 8;  // a multiple of the 8 XCDs
+  const size_t lds = (size_t)4 * P.grp_size * 4 * P.n * sizeof(double);
+  dim3 g(blocks, nrhs);
+#define SMPM_SCHUR_LAUNCH(G)                                                     \
+  if (transpose)                                                                 \
+    hipLaunchKernelGGL(k_schur_adj<G>, g, dim3(256), lds, s, P, y, t, active);   \
+  else                                                                           \
+    hipLaunchKernelGGL(k_schur_fwd<G>, g, dim3(256), lds, s, P, y, t, active);
+  switch (P.grp_size) {
+    case 1: SMPM_SCHUR_LAUNCH(1) break;
+    case 2: SMPM_SCHUR_LAUNCH(2) break;
+    case 4: SMPM_SCHUR_LAUNCH(4) break;
+    default: SMPM_SCHUR_LAUNCH(8) break;
+  }
+#undef SMPM_SCHUR_LAUNCH
 }
 
 void launch_flux(const DevPlan& P, const double* f, double* b, int nrhs, hipStream_t s) {
@@ -484,14 +565,14 @@ void launch_precond(const DevPlan& P, const double* x, double* y, int nrhs, bool
 }
 
 void launch_iface_sum(const DevPlan& P, const double* t, double* c, int nrhs, const int* active, hipStream_t s) {
-  if (P.d == 0) return;
-  hipLaunchKernelGGL(k_iface_sum, grid1(P.d, 128, nrhs), dim3(128), 0, s, P, t, c, active);
+  if (P.d == 0 || !P.has_coarse) return;
+  hipLaunchKernelGGL(k_iface_sum, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, t, c, active);
 }
 
 void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool transpose, const int* active,
                    hipStream_t s) {
-  if (P.d == 0) return;
-  hipLaunchKernelGGL(k_coarse, grid1(P.d, 128, nrhs), dim3(128), 0, s, P, c, c2, transpose ? 1 : 0, active);
+  if (P.d == 0 || !P.has_coarse) return;
+  hipLaunchKernelGGL(k_coarse, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, c, c2, transpose ? 1 : 0, active);
 }
 
 void launch_prolong(const DevPlan& P, const double* t, const double* c2, double* w, int nrhs, int sz, double sign,

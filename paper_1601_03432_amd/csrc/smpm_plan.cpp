@@ -380,6 +380,24 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
     p.cls[e] = it->second;
   }
 
+  // element groups: elements sorted by (class, id), cut into runs of kGroup
+  {
+    std::vector<int> order(p.nel);
+    for (int e = 0; e < p.nel; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p.cls[a] < p.cls[b]; });
+    // enough groups to occupy the chip (about 2048 wavefronts), at most kGroup per group
+    p.grp_size = Plan::kGroup;
+    while (p.grp_size > 1 && (p.nel + p.grp_size - 1) / p.grp_size < 2048) p.grp_size /= 2;
+    for (int i = 0; i < p.nel;) {
+      const int J = p.cls[order[i]];
+      int cnt = 0;
+      p.grp_cls.push_back(J);
+      for (; i < p.nel && cnt < p.grp_size && p.cls[order[i]] == J; ++i, ++cnt) p.grp_elem.push_back(order[i]);
+      for (int u = cnt; u < Plan::kGroup; ++u) p.grp_elem.push_back(-1);
+    }
+    p.ngrp = (int)p.grp_cls.size();
+  }
+
   // class operators
   const int ncls = (int)p.classes.size();
   p.Ainv.assign((size_t)ncls * n2 * n2, 0.0);
@@ -533,7 +551,9 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
   }
 
   // coarse matrix C = Z^T S Z (dense) and its (pseudo-)inverse
-  if (d > 4096) return "coarse space larger than the dense coarse solve supports (d > 4096)";
+  // (the dense coarse solve is built for d <= 4096; larger grids get no deflation)
+  if (d > 4096) return "";
+  p.has_coarse = true;
   p.C.assign((size_t)d * d, 0.0);
   for (int64_t i = 0; i < d; ++i) {
     p.C[(size_t)i * d + i] += 2.0 * n;

@@ -52,6 +52,12 @@ struct Plan {
   std::vector<double> Hc;       // flux of A^{-1} f through side s': [l][i] (n2 x n)
   std::vector<double> Hr;       //                                    [i][l] (n x n2)
   std::vector<double> WZ;       // class*4*n*4: [s'][t][s''] row sums of W over side s''
+  // groups of up to kGroup elements of one class (element operators shared inside a group)
+  static constexpr int kGroup = 8;
+  int grp_size = 8;                  // elements per group (1..8): fewer on small grids
+  int ngrp = 0;
+  std::vector<int> grp_cls;          // class of each group
+  std::vector<int> grp_elem;         // ngrp*kGroup element ids, -1 padded
   // block-Jacobi
   int nblk = 0;
   std::vector<int> blk_red;          // red element of each block
@@ -63,6 +69,7 @@ struct Plan {
   std::vector<double> MinvC;         // [c][r] per block class
   std::vector<double> MinvR;         // [r][c] per block class
   // coarse space
+  bool has_coarse = false;           // dense coarse solve built (d <= 4096)
   bool coarse_singular = false;
   std::vector<double> C, G;          // d x d row-major
   std::vector<double> tau_hat, uC;   // right / left null vectors of C when singular

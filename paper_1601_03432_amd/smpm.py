@@ -24,7 +24,7 @@ EXPORT_SCHUR, EXPORT_FLUX_SOLVE, EXPORT_PRECOND_INV, EXPORT_COARSE, EXPORT_COARS
 
 # every symbol include/smpm.h declares
 ABI_SYMBOLS = (
-    "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_slot_map",
+    "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_stats", "smpm_slot_map",
     "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
     "smpm_schur_apply", "smpm_precond_apply", "smpm_project", "smpm_solve", "smpm_last_error",
 )
@@ -38,6 +38,13 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("refinements", C.c_int), ("rel_residual", C.c_double),
                 ("removed_component", C.c_double)]
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("element_classes", C.c_int64), ("block_classes", C.c_int64),
+                ("schur_operator_bytes", C.c_int64), ("precond_operator_bytes", C.c_int64),
+                ("flux_operator_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
+                ("coarse_singular", C.c_int32), ("has_coarse", C.c_int32)]
 
 
 class SmpmError(RuntimeError):
@@ -66,6 +73,7 @@ def load_library(path: str = LIB_PATH):
     lib.smpm_destroy.argtypes = [vp]
     lib.smpm_destroy.restype = None
     lib.smpm_sizes.argtypes = [vp, i64p, i64p, i64p]
+    lib.smpm_stats.argtypes = [vp, C.POINTER(PlanStats)]
     lib.smpm_slot_map.argtypes = [vp, i64p]
     lib.smpm_node_coords.argtypes = [vp, dp, dp]
     lib.smpm_quadrature_weights.argtypes = [vp, dp]
@@ -117,7 +125,7 @@ class Context:
     it and computes the null vectors on the current GPU (smpm_setup).
     """
 
-    def __init__(self, m_y, m_x, n, x_breaks, y_breaks, penalty=-32.0, device=True, stream=None):
+    def __init__(self, m_y, m_x, n, x_breaks, y_breaks, penalty=32.0, device=True, stream=None):
         lib = load_library()
         xb = np.ascontiguousarray(x_breaks, np.float64)
         yb = np.ascontiguousarray(y_breaks, np.float64)
@@ -141,7 +149,7 @@ class Context:
         self.nbdry = 2 * n * (m_x + m_y)
 
     @classmethod
-    def from_workload(cls, w, penalty=-32.0, device=True):
+    def from_workload(cls, w, penalty=32.0, device=True):
         return cls(w.m_y, w.m_x, w.n, w.x_breaks, w.y_breaks, penalty, device)
 
     def close(self):
@@ -156,6 +164,11 @@ class Context:
             pass
 
     # ---------------------------------------------------------------- host queries
+    def stats(self) -> dict:
+        st = PlanStats()
+        _check(self._lib.smpm_stats(self._h, C.byref(st)))
+        return {name: getattr(st, name) for name, _ in PlanStats._fields_}
+
     def slot_map(self) -> np.ndarray:
         out = np.zeros(self.k, np.int64)
         _check(self._lib.smpm_slot_map(self._h, _i64ptr(out)))
@@ -218,6 +231,13 @@ class Context:
         import torch
         v = self._as_cols(v, self.k)
         out = torch.empty_like(v)
+        _check(self._lib.smpm_schur_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr()),
+                                          v.shape[0], int(transpose), _stream(torch, stream)))
+        return out
+
+    def schur_apply_into(self, v, out, transpose=False, stream=None):
+        """S v written into a preallocated tensor `out` (same shape as v)."""
+        import torch
         _check(self._lib.smpm_schur_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr()),
                                           v.shape[0], int(transpose), _stream(torch, stream)))
         return out

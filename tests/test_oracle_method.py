@@ -19,7 +19,7 @@ def grid(m_x, m_y, n, Lx=1.0, Ly=1.0, **kw):
 
 # ---------------------------------------------------------------- operator L
 
-@pytest.mark.parametrize("alpha", [-32.0, -0.5, 3.0])
+@pytest.mark.parametrize("alpha", [32.0, -32.0, -0.5, 3.0])
 def test_polynomial_exactness(alpha):
     """For a global polynomial of degree <= N per variable the interface jumps vanish,
     so L p = lap p at every node not on the physical boundary, and
@@ -100,11 +100,13 @@ def _manufactured_error(n, m, lam=1, Lx=1.0, Ly=1.0):
 
 
 def test_manufactured_spectral_convergence():
-    """Error decays exponentially in n on a fixed 4x4 grid (Sec. 3.1)."""
-    errs = [_manufactured_error(n, 4)[0] for n in (4, 6, 8, 10, 12)]
-    for a, b in zip(errs, errs[1:]):
-        assert b < a / 8.0, errs
-    assert errs[-1] < 1e-10
+    """Error decays exponentially in n on a fixed 4x4 grid until it meets the rounding
+    plateau of the ill-conditioned spectral operators (Sec. 3.1 notes the same
+    non-monotone floor at the largest orders)."""
+    errs = [_manufactured_error(n, 4)[0] for n in (4, 6, 8, 10, 12, 14)]
+    for a, b in zip(errs[:4], errs[1:4]):
+        assert b < a / 100.0, errs
+    assert max(errs[3:]) < 1e-10, errs
 
 
 def test_manufactured_non_square_and_h_convergence():
@@ -156,7 +158,8 @@ def test_schur_null_spaces(c1_method):
     assert sv[-1] <= 1e-13 * sv[0] and sv[-2] >= 1e-8 * sv[0]
     eu = sys.split.E.T @ sys.uL
     eu /= np.linalg.norm(eu)
-    assert np.abs(sys.uS - eu).max() < 1e-10
+    # null vectors are fixed only up to sign
+    assert min(np.abs(sys.uS - eu).max(), np.abs(sys.uS + eu).max()) < 1e-10
 
 
 def test_block_elimination_identity(c1_method):
