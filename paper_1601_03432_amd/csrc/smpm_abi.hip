@@ -41,7 +41,7 @@ struct Workspace {
   double* part = nullptr;
   int *active = nullptr, *jcount = nullptr;
   // device-resident GMRES state
-  double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr;
+  double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr, *sides = nullptr;
   double *beta_cur = nullptr, *beta0 = nullptr, *tolb = nullptr;
   int *iters = nullptr, *counter = nullptr;
   int* pinned = nullptr;  // 2 x nrhs host-visible activity flags
@@ -149,6 +149,7 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.part1, (size_t)w.nch * ldh * R);
   rc |= dalloc(w.mem, &w.part2, (size_t)w.nch * ldh * R);
   rc |= dalloc(w.mem, &w.part3, (size_t)w.nch * R);
+  rc |= dalloc(w.mem, &w.sides, (size_t)P.nsides * R);
   rc |= dalloc(w.mem, &w.beta_cur, R);
   rc |= dalloc(w.mem, &w.beta0, R);
   rc |= dalloc(w.mem, &w.tolb, R);
@@ -301,6 +302,7 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.z = W.z;
   S.t = W.t;
   S.c = W.c;
+  S.sides = W.sides;
   S.c2 = W.c2;
   S.part1 = W.part1;
   S.part2 = W.part2;
@@ -323,6 +325,7 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.maxit = maxit;
   S.nch = W.nch;
   S.rows = W.rows;
+  S.tol = 0.0;
   return S;
 }
 
@@ -334,6 +337,7 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   GmState S = gm_state(c, nrhs, maxit);
+  S.tol = tol;
   if (kind == 3) {
     launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
@@ -341,12 +345,13 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
   } else {
     HIPCHK(hipMemcpyAsync(W.w, b, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
   }
-  gm_start(P, S, nrhs, tol, s);
+  gm_start(P, S, nrhs, s);
   constexpr int kChunkIters = 8;
-  int chunk = 0;
+  int chunk = 0, launched = 0;
   for (int j0 = 0; j0 < maxit; j0 += kChunkIters, ++chunk) {
     const int j1 = std::min(maxit, j0 + kChunkIters);
     for (int j = j0; j < j1; ++j) gm_step(P, S, nrhs, j, kind, tr, s);
+    launched = j1;
     int* flags = W.pinned + (chunk & 1) * W.nrhs;
     HIPCHK(hipMemcpyAsync(flags, W.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(W.ev[chunk & 1], s));
@@ -358,6 +363,7 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
       if (!any) break;
     }
   }
+  gm_close(P, S, nrhs, launched, kind, tr, s);
   gm_finish(P, S, nrhs, x, s);
   iters.assign(nrhs, 0);
   HIPCHK(hipMemcpyAsync(iters.data(), W.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));

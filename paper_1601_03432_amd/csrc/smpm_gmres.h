@@ -19,6 +19,7 @@ struct GmState {
   double* z;        // M^{-1} v_j
   double* t;        // S z
   double* c;        // Z^T t
+  double* sides;    // per-side sums of t (nsides per column), for Z^T t
   double* c2;       // G c
   double* part1;    // partial dots, col*ldv*nch + i*nch + chunk
   double* part2;
@@ -41,13 +42,15 @@ struct GmState {
   int maxit;        // iteration limit of this solve
   int nch;          // row chunks of a k-vector
   int rows;         // rows per chunk
+  double tol;       // relative stopping tolerance
 };
 
-void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStream_t s);
+void gm_start(const DevPlan& P, const GmState& S, int nrhs, hipStream_t s);
 // kind: 1 = S, 2 = S M^{-1}, 3 = P S M^{-1}; tr selects the transposed operators
 void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s);
+// Givens step for the last column after `j` steps were enqueued
+void gm_close(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s);
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s);
-void gm_reset_counters(int* counter, int n, hipStream_t s);
 int gm_rows_per_chunk(int64_t k);
 
 }  // namespace smpm

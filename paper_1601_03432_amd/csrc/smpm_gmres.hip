@@ -1,19 +1,20 @@
 // Device-resident GMRES iteration for the deflated Schur complement system.
 //
 // One Arnoldi step j of right-preconditioned GMRES on P S M^{-1} (Algorithm 3,
-// step 4) is six kernels, all reading j as a plain argument and per-column
-// state from device memory, so the host never waits inside the loop:
-//   gm_precond  v_j = w / beta (written into V), z = M^{-1} v_j
-//   (Schur apply t = S z, coarse c2 = G Z^T t: operator kernels)
+// step 4) is six kernels that take j as a plain argument and keep every scalar
+// on the device, so the host never waits inside the loop:
+//   gm_precond  beta_j = |w| from the previous step's partials; block 0 applies
+//               the Givens rotations to Hessenberg column j-1 and retires the
+//               column once its residual estimate reaches tol * beta_0;
+//               v_j = w / beta_j (into V), z = M^{-1} v_j
+//   Schur       t = S z, with the per-side sums of t for Z^T t
+//   coarse      c2 = G Z^T t
 //   gm_orth1    w = t - Z c2 - S Z c2 (deflation), partial dots V^T w
 //   gm_orth2    h1 = sum of partials; w -= V h1; partial dots V^T w
-//   gm_orth3    h2 = ...; w -= V h2; partial |w|^2; the last block to finish
-//               forms beta, the Hessenberg column h1 + h2, applies the Givens
-//               rotations and retires the column when its residual estimate
-//               reaches tol * beta_0.
-// Partial sums are reduced by the last block of each kernel (atomic ticket per
-// column) in a fixed order, so results are deterministic.  Each block handles
-// a chunk of rows; its vectors' partial dots are reduced within a wavefront.
+//   gm_orth3    h2 = sum of partials; w -= V h2; partial |w|^2
+// Each block handles a chunk of rows.  Every block that needs a reduced value
+// sums the previous kernel's per-chunk partials itself, in one fixed order, so
+// results are deterministic and no inter-block fence is needed.
 #include <hip/hip_runtime.h>
 
 #include "smpm_gmres.h"
@@ -24,6 +25,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kDotUnroll = 8;
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -39,37 +41,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Partial sums written by other blocks are read after last_block()'s acquire
-// fence, so ordinary loads see them.
-__device__ __forceinline__ double load_agent(const double* p) { return *p; }
-
-// Returns true in exactly one block per column: the last to arrive.  Partial
-// results written before the call are visible to that block afterwards.
-__device__ bool last_block(int* counter) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int t = atomicAdd(counter, 1);
-    is_last = (t == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
-
-// Sum over chunks of part[i*nch + c] for i < nvec into out[i].  Wave q owns
-// vector groups of eight; lanes take chunks lane, lane+64, ... and a fixed
-// shuffle tree combines them, so the order of additions never changes.  Eight
-// vectors are in flight per wave to hide the load latency.
-__device__ void reduce_partials(const double* part, int nvec, int nch, double* out) {
+// out[i] = sum_c part[i*nch + c], i < nvec, into LDS.  Wave q owns groups of
+// eight vectors; lanes take chunks lane, lane+64, ... and a fixed shuffle tree
+// combines them, so every block obtains bit-identical sums.
+__device__ void reduce_partials(const double* __restrict__ part, int nvec, int nch, double* out) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i0 = wave * 8; i0 < nvec; i0 += kWaves * 8) {
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int c = lane; c < nch; c += 64) {
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (i0 + u < nvec) acc[u] += load_agent(part + (int64_t)(i0 + u) * nch + c);
+        if (i0 + u < nvec) acc[u] += part[(int64_t)(i0 + u) * nch + c];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -79,10 +61,21 @@ __device__ void reduce_partials(const double* part, int nvec, int nch, double* o
   }
 }
 
+// sqrt(sum_c part[c]) computed by wave 0 (same order in every block).
+__device__ double reduce_norm(const double* __restrict__ part, int nch, double* red) {
+  if (threadIdx.x < 64) {
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < nch; c += 64) acc += part[c];
+    acc = wave_sum(acc);
+    if (threadIdx.x == 0) red[0] = sqrt(acc);
+  }
+  __syncthreads();
+  return red[0];
+}
+
 // Partial dots of the chunk held in LDS (wv, `rows` rows) with V_0..V_{nvec-1}:
-// wave q handles vector groups q, q+4, ... of kDotUnroll vectors whose loads are
-// all issued before the shuffle reductions; lanes run over rows.
-constexpr int kDotUnroll = 8;
+// wave q handles groups of kDotUnroll vectors whose loads are all issued before
+// the shuffle reductions; lanes run over rows.
 __device__ void chunk_dots(const double* __restrict__ V, int64_t vvs, int64_t x0, int rows, const double* wv,
                            int nvec, double* part, int nch, int chunk) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -104,16 +97,84 @@ __device__ void chunk_dots(const double* __restrict__ V, int64_t vvs, int64_t x0
   }
 }
 
+// Givens step for Hessenberg column jc = j-1 of one right-hand side, run by
+// block 0 of gm_precond: H(:, jc) = h1 + h2 with beta below the diagonal,
+// rotated by the previous rotations; a new rotation zeroes beta.
+__device__ void givens_column(const GmState& S, int col, int j, double beta) {
+  __shared__ double hc[kMaxIt + 2];
+  __shared__ double csl[kMaxIt + 1], snl[kMaxIt + 1];
+  const int tid = threadIdx.x;
+  const int jc = j - 1;
+  const double* h1 = S.h1 + (int64_t)col * S.ldv;
+  const double* h2 = S.h2 + (int64_t)col * S.ldv;
+  double* csg = S.cs + (int64_t)col * S.ldv;
+  double* sng = S.sn + (int64_t)col * S.ldv;
+  for (int i = tid; i <= jc; i += kThreads) hc[i] = h1[i] + h2[i];
+  for (int i = tid; i < jc; i += kThreads) {
+    csl[i] = csg[i];
+    snl[i] = sng[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    hc[jc + 1] = beta;
+    for (int i = 0; i < jc; ++i) {
+      const double a = hc[i], b = hc[i + 1];
+      hc[i] = csl[i] * a + snl[i] * b;
+      hc[i + 1] = -snl[i] * a + csl[i] * b;
+    }
+    const double a = hc[jc], b = hc[jc + 1];
+    const double rr = hypot(a, b);
+    const double c = rr > 0.0 ? a / rr : 1.0;
+    const double s = rr > 0.0 ? b / rr : 0.0;
+    hc[jc] = rr;
+    csg[jc] = c;
+    sng[jc] = s;
+    double* gc = S.g + (int64_t)col * S.ldv;
+    const double gj = gc[jc];
+    gc[jc + 1] = -s * gj;
+    gc[jc] = c * gj;
+    const double res = fabs(gc[jc + 1]);
+    S.res[col] = res;
+    if (!(res > S.tolb[col]) || j >= S.maxit || !(beta > 0.0)) {
+      S.active[col] = 0;
+      S.iters[col] = j;
+    }
+  }
+  __syncthreads();
+  double* Hcol = S.H + (int64_t)col * S.ldv * S.maxit + (int64_t)jc * S.ldv;
+  for (int i = tid; i <= jc; i += kThreads) Hcol[i] = hc[i];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ kernels
 
-// Finalizes v_j = w / beta into V_j and applies z = M^{-1} v_j (or z = v_j).
-__global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int j, int use_precond, int transpose) {
+// beta_j, Givens for column j-1 (block 0), v_j = w / beta_j into V_j and
+// z = M^{-1} v_j (or z = v_j).  givens_only: stop after the Givens step.
+__global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int j, int use_precond, int transpose,
+                                                    int givens_only) {
   __shared__ double xs[8 * kMaxN];
+  __shared__ double red[kWaves];
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
-  const double inv = 1.0 / S.beta_cur[col];
+  const double beta = reduce_norm(S.part3 + (int64_t)col * S.nch, S.nch, red);
+  if (blockIdx.x == 0) {
+    if (j == 0) {
+      if (tid == 0) {
+        S.tolb[col] = S.tol * beta;
+        S.g[(int64_t)col * S.ldv] = beta;
+        S.res[col] = beta;
+        if (!(beta > 0.0)) {
+          S.active[col] = 0;
+          S.iters[col] = 0;
+        }
+      }
+    } else {
+      givens_column(S, col, j, beta);
+    }
+  }
+  if (givens_only) return;
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
   const int64_t k = P.k;
   const double* wc = S.w + (int64_t)col * k;
   double* vj = S.V + (int64_t)j * S.vvs + (int64_t)col * k;
@@ -148,7 +209,7 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int j,
 }
 
 // w = t - (Z c2 + {S Z c2 | S^T Z c2}) on this block's rows (or w = t), then
-// partial dots with V_0..V_j; the last block reduces them into h1.
+// partial dots with V_0..V_j.
 __global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int j, int defl, int transpose) {
   __shared__ double wv[kRowsMax];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
@@ -187,16 +248,13 @@ __global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int j, i
     wv[q] = v;
   }
   __syncthreads();
-  double* part = S.part1 + (int64_t)col * S.ldv * S.nch;
-  chunk_dots(S.V + (int64_t)col * k, S.vvs, x0, rows, wv, j + 1, part, S.nch, chunk);
-  if (last_block(S.counter + col * 4 + 0)) {
-    reduce_partials(part, j + 1, S.nch, S.h1 + (int64_t)col * S.ldv);
-    if (tid == 0) S.counter[col * 4 + 0] = 0;
-  }
+  chunk_dots(S.V + (int64_t)col * k, S.vvs, x0, rows, wv, j + 1, S.part1 + (int64_t)col * S.ldv * S.nch, S.nch,
+             chunk);
 }
 
-// w -= V h (h = h1 for pass 2, h2 for pass 3).  Pass 2 then forms partial dots
-// (reduced into h2 by the last block); pass 3 forms |w|^2 and finishes the step.
+// PASS 2: h1 = sum of part1; w -= V h1; partial dots into part2.
+// PASS 3: h2 = sum of part2; w -= V h2; partial |w|^2 into part3.
+// Block 0 stores h1 / h2 for the Givens step.
 template <int PASS>
 __global__ __launch_bounds__(256) void k_gm_orth(DevPlan P, GmState S, int j) {
   __shared__ double wv[kRowsMax];
@@ -207,9 +265,13 @@ __global__ __launch_bounds__(256) void k_gm_orth(DevPlan P, GmState S, int j) {
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const int nvec = j + 1;
-  const double* hsrc = (PASS == 2 ? S.h1 : S.h2) + (int64_t)col * S.ldv;
-  for (int i = tid; i < nvec; i += kThreads) hs[i] = hsrc[i];
+  const double* part_in = (PASS == 2 ? S.part1 : S.part2) + (int64_t)col * S.ldv * S.nch;
+  reduce_partials(part_in, nvec, S.nch, hs);
   __syncthreads();
+  if (chunk == 0) {
+    double* hdst = (PASS == 2 ? S.h1 : S.h2) + (int64_t)col * S.ldv;
+    for (int i = tid; i < nvec; i += kThreads) hdst[i] = hs[i];
+  }
   double* wc = S.w + (int64_t)col * k;
   const double* Vc = S.V + (int64_t)col * k;
   double nrm = 0.0;
@@ -225,71 +287,15 @@ __global__ __launch_bounds__(256) void k_gm_orth(DevPlan P, GmState S, int j) {
   }
   __syncthreads();
   if (PASS == 2) {
-    double* part = S.part2 + (int64_t)col * S.ldv * S.nch;
-    chunk_dots(Vc, S.vvs, x0, rows, wv, nvec, part, S.nch, chunk);
-    if (last_block(S.counter + col * 4 + 1)) {
-      reduce_partials(part, nvec, S.nch, S.h2 + (int64_t)col * S.ldv);
-      if (tid == 0) S.counter[col * 4 + 1] = 0;
-    }
+    chunk_dots(Vc, S.vvs, x0, rows, wv, nvec, S.part2 + (int64_t)col * S.ldv * S.nch, S.nch, chunk);
     return;
   }
   const double bs = block_sum(nrm, red);
-  double* part = S.part3 + (int64_t)col * S.nch;
-  if (tid == 0) part[chunk] = bs;
-  if (!last_block(S.counter + col * 4 + 2)) return;
-  // ---- last block: beta, Hessenberg column, Givens rotations, convergence
-  __shared__ double hc[kMaxIt + 2];
-  __shared__ double csl[kMaxIt + 1], snl[kMaxIt + 1];
-  __shared__ double beta_s;
-  if (tid < 64) {
-    double acc = 0.0;
-    for (int c = tid; c < S.nch; c += 64) acc += load_agent(part + c);
-    acc = wave_sum(acc);
-    if (tid == 0) beta_s = sqrt(acc);
-  }
-  const double* h1 = S.h1 + (int64_t)col * S.ldv;
-  double* csg = S.cs + (int64_t)col * S.ldv;
-  double* sng = S.sn + (int64_t)col * S.ldv;
-  for (int i = tid; i < nvec; i += kThreads) hc[i] = h1[i] + hs[i];
-  for (int i = tid; i < j; i += kThreads) {
-    csl[i] = csg[i];
-    snl[i] = sng[i];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const double beta = beta_s;
-    hc[j + 1] = beta;
-    for (int i = 0; i < j; ++i) {
-      const double a = hc[i], b = hc[i + 1];
-      hc[i] = csl[i] * a + snl[i] * b;
-      hc[i + 1] = -snl[i] * a + csl[i] * b;
-    }
-    const double a = hc[j], b = hc[j + 1];
-    const double rr = hypot(a, b);
-    const double c = rr > 0.0 ? a / rr : 1.0;
-    const double s = rr > 0.0 ? b / rr : 0.0;
-    hc[j] = rr;
-    hc[j + 1] = 0.0;
-    csg[j] = c;
-    sng[j] = s;
-    double* gc = S.g + (int64_t)col * S.ldv;
-    const double gj = gc[j];
-    gc[j + 1] = -s * gj;
-    gc[j] = c * gj;
-    const double res = fabs(gc[j + 1]);
-    S.res[col] = res;
-    S.iters[col] = j + 1;
-    S.beta_cur[col] = beta;
-    if (!(res > S.tolb[col]) || j + 1 >= S.maxit || !(beta > 0.0)) S.active[col] = 0;
-    S.counter[col * 4 + 2] = 0;
-  }
-  __syncthreads();
-  double* Hcol = S.H + (int64_t)col * S.ldv * S.maxit + (int64_t)j * S.ldv;
-  for (int i = tid; i <= j; i += kThreads) Hcol[i] = hc[i];
+  if (tid == 0) S.part3[(int64_t)col * S.nch + chunk] = bs;
 }
 
-// Start of a solve: beta_0 = |w|, g = beta_0 e_1, per-column activity.
-__global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S, double tol) {
+// Start of a solve: partial |w|^2 of the initial residual; all columns active.
+__global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S) {
   __shared__ double red[kWaves];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
@@ -298,23 +304,10 @@ __global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S, double t
   double nrm = 0.0;
   for (int q = tid; q < rows; q += kThreads) nrm = fma(wc[x0 + q], wc[x0 + q], nrm);
   const double bs = block_sum(nrm, red);
-  double* part = S.part3 + (int64_t)col * S.nch;
-  if (tid == 0) part[chunk] = bs;
-  if (!last_block(S.counter + col * 4 + 3)) return;
-  if (tid < 64) {
-    double acc = 0.0;
-    for (int c = tid; c < S.nch; c += 64) acc += load_agent(part + c);
-    acc = wave_sum(acc);
-    if (tid != 0) return;
-    const double beta = sqrt(acc);
-    S.beta_cur[col] = beta;
-    S.beta0[col] = beta;
-    S.tolb[col] = tol * beta;
-    S.res[col] = beta;
+  if (tid == 0) S.part3[(int64_t)col * S.nch + chunk] = bs;
+  if (chunk == 0 && tid == 0) {
+    S.active[col] = 1;
     S.iters[col] = 0;
-    S.active[col] = beta > 0.0 ? 1 : 0;
-    S.g[(int64_t)col * S.ldv] = beta;
-    S.counter[col * 4 + 3] = 0;
   }
 }
 
@@ -354,25 +347,28 @@ __global__ __launch_bounds__(256) void k_gm_combine(DevPlan P, GmState S, double
   }
 }
 
-__global__ void k_fill_int(int* p, int v, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 // ------------------------------------------------------------------ launchers
 
-void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_start, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, tol);
+void gm_start(const DevPlan& P, const GmState& S, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_start, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S);
+}
+
+static int precond_grid(const DevPlan& P, const GmState& S, int kind) {
+  return kind == 1 ? S.nch : std::max(1, std::min(P.nblk, 1024));
 }
 
 void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s) {
-  const int pre_grid = kind == 1 ? S.nch : std::max(1, std::min(P.nblk, 1024));
-  hipLaunchKernelGGL(k_gm_precond, dim3(pre_grid, nrhs), dim3(kThreads), 0, s, P, S, j, kind == 1 ? 0 : 1,
-                     tr ? 1 : 0);
-  launch_schur(P, S.z, S.t, nrhs, tr, S.active, s);
+  hipLaunchKernelGGL(k_gm_precond, dim3(precond_grid(P, S, kind), nrhs), dim3(kThreads), 0, s, P, S, j,
+                     kind == 1 ? 0 : 1, tr ? 1 : 0, 0);
+  const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P);
+  launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s);
   if (kind == 3) {
-    launch_iface_sum(P, S.t, S.c, nrhs, S.active, s);
-    launch_coarse(P, S.c, S.c2, nrhs, tr, S.active, s);
+    if (fused_sums) {
+      launch_coarse_sides(P, S.sides, S.c2, nrhs, tr, S.active, s);
+    } else {
+      launch_iface_sum(P, S.t, S.c, nrhs, S.active, s);
+      launch_coarse(P, S.c, S.c2, nrhs, tr, S.active, s);
+    }
   }
   hipLaunchKernelGGL(k_gm_orth1, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, j, kind == 3 ? 1 : 0,
                      tr ? 1 : 0);
@@ -380,14 +376,14 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool
   hipLaunchKernelGGL(k_gm_orth<3>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, j);
 }
 
+void gm_close(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_precond, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, j, kind == 1 ? 0 : 1, tr ? 1 : 0, 1);
+}
+
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_gm_lsq, dim3(nrhs), dim3(kThreads), 0, s, S);
   const int64_t blocks = std::min<int64_t>((P.k + kThreads - 1) / kThreads, 2048);
   hipLaunchKernelGGL(k_gm_combine, dim3((unsigned)blocks, nrhs), dim3(kThreads), 0, s, P, S, x);
-}
-
-void gm_reset_counters(int* counter, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, counter, 0, n);
 }
 
 int gm_rows_per_chunk(int64_t k) {

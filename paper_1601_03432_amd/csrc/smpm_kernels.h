@@ -55,6 +55,14 @@ constexpr int kGroup = 8;
 // ---- operator applies; nrhs columns, column-blocked with the natural lengths
 void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
                   const int* active, hipStream_t s);
+// as launch_schur; if side_sums != nullptr (forward, n <= 16 only) it also writes the
+// sum of t over every inter-element side (nsides per column)
+void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
+                     const int* active, double* side_sums, hipStream_t s);
+bool schur_has_side_sums(const DevPlan& P);
+// c2 = G c with c_j = side_sums of interface j's two sides
+void launch_coarse_sides(const DevPlan& P, const double* side_sums, double* c2, int nrhs, bool transpose,
+                         const int* active, hipStream_t s);
 void launch_flux(const DevPlan& P, const double* f, double* b, int nrhs, hipStream_t s);      // b = B A^{-1} f
 void launch_flux_adj(const DevPlan& P, const double* x, double* y, int nrhs, hipStream_t s);  // y = A^{-T} B^T x
 void launch_backsub(const DevPlan& P, const double* f, const double* x, double* u, int nrhs,

@@ -35,7 +35,8 @@ constexpr int kPrefetch = 8;  // independent operator loads in flight per lane
 // its neighbour, which have no other writer.
 template <int G>
 __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __restrict__ y,
-                                                   double* __restrict__ t, const int* __restrict__ active) {
+                                                   double* __restrict__ t, const int* __restrict__ active,
+                                                   double* __restrict__ side_sums) {
   extern __shared__ double lds[];
   const int col = blockIdx.y;
   if (active && !active[col]) return;
@@ -60,8 +61,11 @@ __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __re
     }
   }
   __syncthreads();
-  if (g >= P.ngrp) return;
-  for (int o = lane; o < 4 * n; o += 64) {
+  const bool valid = g < P.ngrp;
+  double tv[G];
+#pragma unroll
+  for (int u = 0; u < G; ++u) tv[u] = 0.0;
+  for (int o = lane; o < 4 * n && valid; o += 64) {
     const int s = o / n, i = o - s * n;
     if (P.cls_sidecol[J * 4 + s] < 0) continue;
     const double* Wp = P.Wc + P.W_off[J * 4 + s];
@@ -85,7 +89,33 @@ __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __re
       if (elem[u] < 0) break;
       const int recv = P.nbr[elem[u] * 4 + s];
       const int slot = P.side_slot[recv * 4 + (s ^ 1)] + i;
-      tc[slot] = yc[slot] + acc[u];
+      tv[u] = yc[slot] + acc[u];
+      tc[slot] = tv[u];
+    }
+  }
+  if (!side_sums) return;
+  // Sum of t over each receiving side (4n <= 64: lane o = s*n + i owns one row).
+  // The values go through this wave's LDS region, then lane s adds its side's n
+  // entries in order.
+  __syncthreads();
+  if (valid && lane < 4 * n) {
+    const int s = lane / n;
+    if (P.cls_sidecol[J * 4 + s] >= 0) {
+#pragma unroll
+      for (int u = 0; u < G; ++u) ys[u * ld + lane] = tv[u];
+    }
+  }
+  __syncthreads();
+  if (valid && lane < 4 && P.cls_sidecol[J * 4 + lane] >= 0) {
+    const int s = lane;
+    double* ss = side_sums + (int64_t)col * P.nsides;
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (elem[u] < 0) break;
+      double acc = 0.0;
+      for (int i = 0; i < n; ++i) acc += ys[u * ld + s * n + i];
+      const int recv = P.nbr[elem[u] * 4 + s];
+      ss[P.side_slot[recv * 4 + (s ^ 1)] / n] = acc;
     }
   }
 }
@@ -323,6 +353,24 @@ __global__ __launch_bounds__(256) void k_coarse(DevPlan P, const double* __restr
   if (lane == 0) c2[(int64_t)col * d + i] = acc;
 }
 
+// c2 = G c with c_j = side_sums[a_j] + side_sums[b_j] (the two sides of interface j).
+__global__ __launch_bounds__(256) void k_coarse_sides(DevPlan P, const double* __restrict__ ss,
+                                                      double* __restrict__ c2, int transpose,
+                                                      const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int d = P.d;
+  if (i >= d) return;
+  const double* Gp = (transpose ? P.GT : P.G) + (int64_t)i * d;
+  const double* sc = ss + (int64_t)col * P.nsides;
+  double acc = 0.0;
+  for (int j = lane; j < d; j += 64) acc = fma(Gp[j], sc[P.iface_side[2 * j]] + sc[P.iface_side[2 * j + 1]], acc);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) c2[(int64_t)col * d + i] = acc;
+}
+
 // w = t + sign * (Z c2 + {0, S Z c2, S^T Z c2})
 __global__ void k_prolong(DevPlan P, const double* __restrict__ t, const double* __restrict__ c2,
                           double* __restrict__ w, int sz, double sign, const int* __restrict__ active) {
@@ -523,8 +571,16 @@ inline dim3 grid1(int64_t len, int bs, int ny = 1) { return dim3((unsigned)((len
 
 // ------------------------------------------------------------------ launchers
 
+bool schur_has_side_sums(const DevPlan& P) { return 4 * P.n <= 64; }
+
 void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
                   hipStream_t s) {
+  launch_schur_ex(P, y, t, nrhs, transpose, active, nullptr, s);
+}
+
+void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
+                     double* side_sums, hipStream_t s) {
+  if (transpose || !schur_has_side_sums(P)) side_sums = nullptr;
   const int blocks = ((P.ngrp + 3) / 4 + 7) / 8 * 8;  // a multiple of the 8 XCDs
   const size_t lds = (size_t)4 * P.grp_size * 4 * P.n * sizeof(double);
   dim3 g(blocks, nrhs);
@@ -532,7 +588,7 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
   if (transpose)                                                                 \
     hipLaunchKernelGGL(k_schur_adj<G>, g, dim3(256), lds, s, P, y, t, active);   \
   else                                                                           \
-    hipLaunchKernelGGL(k_schur_fwd<G>, g, dim3(256), lds, s, P, y, t, active);
+    hipLaunchKernelGGL(k_schur_fwd<G>, g, dim3(256), lds, s, P, y, t, active, side_sums);
   switch (P.grp_size) {
     case 1: SMPM_SCHUR_LAUNCH(1) break;
     case 2: SMPM_SCHUR_LAUNCH(2) break;
@@ -573,6 +629,13 @@ void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool
                    hipStream_t s) {
   if (P.d == 0 || !P.has_coarse) return;
   hipLaunchKernelGGL(k_coarse, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, c, c2, transpose ? 1 : 0, active);
+}
+
+void launch_coarse_sides(const DevPlan& P, const double* side_sums, double* c2, int nrhs, bool transpose,
+                         const int* active, hipStream_t s) {
+  if (P.d == 0 || !P.has_coarse) return;
+  hipLaunchKernelGGL(k_coarse_sides, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, side_sums, c2, transpose ? 1 : 0,
+                     active);
 }
 
 void launch_prolong(const DevPlan& P, const double* t, const double* c2, double* w, int nrhs, int sz, double sign,
