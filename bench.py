@@ -52,7 +52,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="form timed as the headline step (the other form is reported beside it)")
+    ap.add_argument("--batch", type=int, default=32, help="right-hand sides of the batched measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--cpu-solves", type=int, default=2)
@@ -74,18 +76,42 @@ def main():
     f_host = wl.eval_fourier(params, x, y, w.Lx, w.Ly)
     f = torch.tensor(f_host, device="cuda").reshape(1, -1)
 
-    # warmup (also computes the null vectors once)
-    info = None
-    for _ in range(max(1, args.warmup)):
-        u, info = ctx.solve(f, tol=1e-10, maxit=600)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        u, info = ctx.solve(f, tol=1e-10, maxit=600)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    solves_per_s = args.steps / (t1 - t0)
+    def solve_fp64(rhs):
+        return ctx.solve(rhs, tol=1e-10, maxit=600)
+
+    def solve_mixed(rhs):
+        return ctx.solve(rhs, tol=1e-10, maxit=600, precision=smpm.MIXED_FP32, inner_tol=1e-4, max_refine=30)
+
+    def timed(fn, rhs, steps, warmup):
+        info = None
+        for _ in range(max(1, warmup)):
+            u, info = fn(rhs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            u, info = fn(rhs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) / steps, info, u
+
+    # the headline form is timed as the benchmark step; the other form beside it
+    forms = {"fp64": solve_fp64, "mixed": solve_mixed}
+    other = "mixed" if args.precision == "fp64" else "fp64"
+    sec, info, u_main = timed(forms[args.precision], f, args.steps, args.warmup)
+    ms_per_step = sec * 1e3
+    solves_per_s = 1.0 / sec
+    sec_o, info_o, u_o = timed(forms[other], f, max(3, args.steps // 2), 1)
+    u64 = u_main if args.precision == "fp64" else u_o
+    umx = u_o if args.precision == "fp64" else u_main
+    mixed_err = float(torch.linalg.norm(umx - u64) / torch.linalg.norm(u64))
+    # batched: `batch` right-hand sides (seeded random-Fourier sources) in one call, both forms
+    fb = []
+    for i in range(args.batch):
+        pb = wl.random_fourier_params(wl.SEED_BASE + 200 + i, 20, 8)
+        fb.append(wl.eval_fourier(pb, x, y, w.Lx, w.Ly))
+    fb = torch.tensor(np.stack(fb), device="cuda")
+    secb64, infob64, _ = timed(solve_fp64, fb, 3, 1)
+    secbmx, infobmx, _ = timed(solve_mixed, fb, 3, 1)
 
     # dominant kernel: the Schur apply, timed on the solve's stream with HIP events
     v = torch.randn(1, ctx.k, dtype=torch.float64, device="cuda")
@@ -106,12 +132,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": "c2: 16x16 elements, n=16, [0,2]^2, r=65536, k=15360, random-Fourier source "
                                "(20 modes, k<=8, seed 160103434), g=0, FP64, tol 1e-10",
-                   "gmres_iterations": info.iterations, "true_rel_residual": info.rel_residual,
+                   "form": args.precision, "gmres_iterations": info.iterations,
+                   "refinements": info.refinements, "true_rel_residual": info.rel_residual,
                    "penalty": 32.0, "parallelism": "single GPU"},
+        "forms": {
+            args.precision: {"solves_per_s": solves_per_s, "iterations": info.iterations,
+                             "refinements": info.refinements, "true_rel_residual": info.rel_residual},
+            other: {"solves_per_s": 1.0 / sec_o, "iterations": info_o.iterations,
+                    "refinements": info_o.refinements, "true_rel_residual": info_o.rel_residual},
+            "mixed_vs_fp64_rel_l2": mixed_err,
+            f"batched{args.batch}_fp64": {"solves_per_s": args.batch / secb64, "ms_per_call": secb64 * 1e3,
+                                          "iterations_max": infob64.iterations,
+                                          "true_rel_residual_max": infob64.rel_residual},
+            f"batched{args.batch}_mixed": {"solves_per_s": args.batch / secbmx, "ms_per_call": secbmx * 1e3,
+                                           "iterations_max": infobmx.iterations,
+                                           "refinements": infobmx.refinements,
+                                           "true_rel_residual_max": infobmx.rel_residual},
+        },
         "roofline": {"kernel": "k_schur_fwd (c2 grid)", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": sch_ms * 1e3},

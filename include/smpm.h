@@ -94,13 +94,15 @@ enum smpm_export_what {
 };
 
 typedef struct smpm_solve_opts {
-  double tol;         /* GMRES stop: least-squares residual <= tol * ||P b_hat|| (default 1e-10) */
+  double tol;         /* stop when the GMRES least-squares residual (= the Schur residual
+                         |b_hat - S x|) <= tol * |b_hat| (default 1e-10); mixed precision:
+                         refinement stops when the FP64 true residual meets the same bound  */
   int maxit;          /* maximum GMRES iterations per solve or refinement cycle (default 400)    */
   int precision;      /* smpm_precision (default SMPM_FP64)                                      */
   int transpose;      /* 1: solve the adjoint system L^T mu = c instead (default 0)               */
   int variant;        /* 3: deflated + block-Jacobi (Algorithm 3), 2: block-Jacobi only
                          (Algorithm 2), 1: unpreconditioned (Algorithm 1); default 3               */
-  double inner_tol;   /* mixed precision: inner GMRES tolerance (default 1e-6)                   */
+  double inner_tol;   /* mixed precision: inner GMRES tolerance per refinement cycle (1e-4)      */
   int max_refine;     /* mixed precision: maximum refinement cycles (default 20)                 */
 } smpm_solve_opts;
 

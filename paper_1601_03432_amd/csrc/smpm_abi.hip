@@ -42,6 +42,7 @@ struct Workspace {
   int *active = nullptr, *jcount = nullptr;
   // device-resident GMRES state
   double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr, *sides = nullptr;
+  double *xacc = nullptr, *rho = nullptr;  // iterative refinement: solution and residual
   double *beta_cur = nullptr, *beta0 = nullptr, *tolb = nullptr;
   int *iters = nullptr, *counter = nullptr;
   int* pinned = nullptr;  // 2 x nrhs host-visible activity flags
@@ -77,6 +78,26 @@ struct smpm_ctx {
 };
 
 namespace {
+
+// float -> bf16 with round-to-nearest-even on the discarded 16 bits
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, sizeof u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+std::vector<float> to_f32(const std::vector<double>& v) {
+  std::vector<float> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+  return o;
+}
+
+std::vector<uint16_t> to_b16(const std::vector<double>& v) {
+  std::vector<uint16_t> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = to_bf16((float)v[i]);
+  return o;
+}
 
 template <class T>
 int upload(smpm_ctx* c, const std::vector<T>& v, const T** out, hipStream_t s) {
@@ -150,6 +171,8 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.part2, (size_t)w.nch * ldh * R);
   rc |= dalloc(w.mem, &w.part3, (size_t)w.nch * R);
   rc |= dalloc(w.mem, &w.sides, (size_t)P.nsides * R);
+  rc |= dalloc(w.mem, &w.xacc, k * R);
+  rc |= dalloc(w.mem, &w.rho, k * R);
   rc |= dalloc(w.mem, &w.beta_cur, R);
   rc |= dalloc(w.mem, &w.beta0, R);
   rc |= dalloc(w.mem, &w.tolb, R);
@@ -326,6 +349,7 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.nch = W.nch;
   S.rows = W.rows;
   S.tol = 0.0;
+  S.bref2 = nullptr;
   return S;
 }
 
@@ -333,11 +357,15 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
 // The host enqueues Arnoldi steps in chunks and polls per-column activity flags
 // one chunk behind, so the device never waits for the host.
 int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, double tol, int maxit,
-              std::vector<int>& iters, hipStream_t s) {
+              std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   GmState S = gm_state(c, nrhs, maxit);
   S.tol = tol;
+  // the stopping rule is relative to |b| (the Schur right-hand side), the quantity
+  // the FP64 true residual is accepted against
+  launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
+  S.bref2 = W.scal2 + 2 * nrhs;
   if (kind == 3) {
     launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
@@ -350,7 +378,7 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
   int chunk = 0, launched = 0;
   for (int j0 = 0; j0 < maxit; j0 += kChunkIters, ++chunk) {
     const int j1 = std::min(maxit, j0 + kChunkIters);
-    for (int j = j0; j < j1; ++j) gm_step(P, S, nrhs, j, kind, tr, s);
+    for (int j = j0; j < j1; ++j) gm_step(P, S, nrhs, j, kind, tr, s, sprec, mprec);
     launched = j1;
     int* flags = W.pinned + (chunk & 1) * W.nrhs;
     HIPCHK(hipMemcpyAsync(flags, W.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -374,20 +402,22 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
 }
 
 int solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, int nrhs, double tol, int maxit,
-                std::vector<int>& iters, hipStream_t s) {
+                std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   double* x1 = W.x;  // note: x may not alias W.x
-  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s);
+  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s, sprec, mprec);
   if (rc < 0) return rc;
+  // the post-processing uses the operators (and precisions) of the GMRES operator, so
+  // that x = M^{-1} x1 reproduces the preconditioned iterate exactly
   if (kind == OP_S) {
     HIPCHK(hipMemcpyAsync(x, x1, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
   } else if (kind == OP_SM) {
-    launch_precond(P, x1, x, nrhs, tr, nullptr, s);
+    launch_precond(P, x1, x, nrhs, tr, nullptr, s, mprec);
   } else {
     // x = z + Z G Z^T (b_hat - S z), z = M^{-1} x1   (Algorithm 3 steps 5-8)
-    launch_precond(P, x1, W.z, nrhs, tr, nullptr, s);
-    launch_schur(P, W.z, W.t, nrhs, tr, nullptr, s);
+    launch_precond(P, x1, W.z, nrhs, tr, nullptr, s, mprec);
+    launch_schur_ex(P, W.z, W.t, nrhs, tr, nullptr, nullptr, s, sprec);
     launch_add(bhat, W.t, -1.0, W.w, P.k, nrhs, s);
     launch_iface_sum(P, W.w, W.c, nrhs, nullptr, s);
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
@@ -557,6 +587,15 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   rc |= upload(c, p.MinvR, &d.MinvR, s);
   rc |= upload(c, p.G, &d.G, s);
   rc |= upload(c, GT, &d.GT, s);
+  rc |= upload(c, to_f32(p.Wc), &d.WcF, s);
+  rc |= upload(c, to_f32(p.Wr), &d.WrF, s);
+  rc |= upload(c, to_f32(p.MinvC), &d.MinvCF, s);
+  rc |= upload(c, to_f32(p.MinvR), &d.MinvRF, s);
+  rc |= upload(c, to_b16(p.Wc), &d.WcB, s);
+  rc |= upload(c, to_b16(p.Wr), &d.WrB, s);
+  rc |= upload(c, to_b16(p.MinvC), &d.MinvCB, s);
+  rc |= upload(c, to_b16(p.MinvR), &d.MinvRB, s);
+  HIPCHK(hipStreamSynchronize(s));  // the converted host copies are temporaries
   d.ngrp = p.ngrp;
   d.grp_size = p.grp_size;
   rc |= upload(c, p.grp_cls, &d.grp_cls, s);
@@ -618,7 +657,7 @@ void smpm_default_opts(smpm_solve_opts* o) {
   o->precision = SMPM_FP64;
   o->transpose = 0;
   o->variant = 3;
-  o->inner_tol = 1e-6;
+  o->inner_tol = 1e-4;
   o->max_refine = 20;
 }
 
@@ -884,7 +923,9 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   if (opts_in) o = *opts_in;
   if (o.maxit < 1 || o.maxit > kMaxIt || !(o.tol > 0) || o.variant < 1 || o.variant > 3)
     return fail(SMPM_EINVAL, "bad solve options (1 <= maxit <= 1000, tol > 0, variant 1..3)");
-  if (o.precision != SMPM_FP64) return fail(SMPM_EINVAL, "precision not supported by this build");
+  if (o.precision < SMPM_FP64 || o.precision > SMPM_MIXED_BF16) return fail(SMPM_EINVAL, "unknown precision");
+  if (o.precision != SMPM_FP64 && (!(o.inner_tol > 0) || o.inner_tol >= 1 || o.max_refine < 1))
+    return fail(SMPM_EINVAL, "mixed precision needs 0 < inner_tol < 1 and max_refine >= 1");
   if (o.transpose) return fail(SMPM_EINVAL, "adjoint solve not supported by this build");
   if (o.variant == 3 && !c->plan.has_coarse)
     return fail(SMPM_EINVAL, "no coarse space on this grid (d > 4096): use variant 1 or 2");
@@ -910,14 +951,77 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   // steps 4-8
   std::vector<int> iters;
   const int kind = o.variant == 3 ? OP_PSM : o.variant == 2 ? OP_SM : OP_S;
-  // x lands in W.bS (free after b_hat is formed)
-  rc = solve_schur(c, kind, false, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s);
-  if (rc < 0) return rc;
   std::vector<double> tres;
-  rc = true_residual(c, false, W.bhat, W.bS, nrhs, tres, s);
-  if (rc) return rc;
+  int cycles = 1;
+  bool conv = true;
+  double* xsol = W.bS;
+  if (o.precision == SMPM_FP64) {
+    // x lands in W.bS (free after b_hat is formed)
+    rc = solve_schur(c, kind, false, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s);
+    if (rc < 0) return rc;
+    rc = true_residual(c, false, W.bhat, W.bS, nrhs, tres, s);
+    if (rc) return rc;
+    for (int i = 0; i < nrhs; ++i)
+      if (iters[i] >= o.maxit) conv = false;
+  } else {
+    // Iterative refinement: rho = b_hat - S x in FP64; delta from the deflated GMRES with
+    // FP32 (or BF16) Schur and block-Jacobi operators to inner_tol; x += delta.
+    // MIXED_BF16 starts with BF16 Schur and block-Jacobi operators; a refinement cycle
+    // that contracts the FP64 residual by less than 2x switches the Schur operator to
+    // FP32 for the remaining cycles (the preconditioner precision only affects the
+    // convergence rate, not the attainable accuracy)
+    int sprec = o.precision == SMPM_MIXED_FP32 ? PREC_F32 : PREC_BF16;
+    const int mprec = sprec;
+    xsol = W.xacc;
+    HIPCHK(hipMemsetAsync(W.xacc, 0, sizeof(double) * Pl.k * nrhs, s));
+    HIPCHK(hipMemcpyAsync(W.rho, W.bhat, sizeof(double) * Pl.k * nrhs, hipMemcpyDeviceToDevice, s));
+    iters.assign(nrhs, 0);
+    std::vector<double> prev(nrhs, 2.0);
+    int stall = 0;
+    tres.assign(nrhs, 1.0);
+    conv = false;
+    for (cycles = 0; cycles <= o.max_refine; ++cycles) {
+      if (cycles > 0) {
+        launch_schur(P, W.xacc, W.t, nrhs, false, nullptr, s);
+        launch_add(W.bhat, W.t, -1.0, W.rho, Pl.k, nrhs, s);
+      }
+      launch_mdot(W.rho, 0, Pl.k, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
+      launch_mdot(W.bhat, 0, Pl.k, 1, W.bhat, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal2, nullptr, s);
+      std::vector<double> a(nrhs), bb(nrhs);
+      HIPCHK(hipMemcpyAsync(a.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(bb.data(), W.scal2, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool all = true, weak = false, slow = false;
+      for (int i = 0; i < nrhs; ++i) {
+        tres[i] = bb[i] > 0 ? std::sqrt(a[i] / bb[i]) : std::sqrt(a[i]);
+        if (tres[i] <= o.tol) {
+          // converged column: zero residual so the inner solve leaves it alone
+          HIPCHK(hipMemsetAsync(W.rho + (size_t)i * Pl.k, 0, sizeof(double) * Pl.k, s));
+        } else {
+          all = false;
+          if (cycles >= 1 && tres[i] > 0.05 * prev[i]) weak = true;
+          if (cycles >= 1 && tres[i] > 0.5 * prev[i]) slow = true;
+        }
+        prev[i] = tres[i];
+      }
+      if (all) {
+        conv = true;
+        break;
+      }
+      // a BF16 Schur operator that contracts the residual by less than 20x per cycle
+      // is replaced by the FP32 one; two cycles without a 2x contraction end the loop
+      if (weak && sprec == PREC_BF16) sprec = PREC_F32;
+      stall = slow ? stall + 1 : 0;
+      if (stall >= 2 || cycles == o.max_refine) break;
+      std::vector<int> it;
+      rc = solve_schur(c, kind, false, W.rho, W.bS, nrhs, o.inner_tol, o.maxit, it, s, sprec, mprec);
+      if (rc < 0) return rc;
+      for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
+      launch_add(W.xacc, W.bS, 1.0, W.xacc, Pl.k, nrhs, s);
+    }
+  }
   // step 9 and the constant: u = A^{-1}(f~ - E x); u -= (w^T u / w^T 1)
-  launch_backsub(P, W.ft, W.bS, u, nrhs, s);
+  launch_backsub(P, W.ft, xsol, u, nrhs, s);
   launch_mdot(c->wq, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
   launch_axpy_shared(u, Pl.r, c->ones, W.scal, 1.0 / c->wsum, u, Pl.r, nrhs, s);
   HIPCHK(hipGetLastError());
@@ -930,14 +1034,13 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   }
   if (info) {
     info->iterations = itmax;
-    info->refinements = 1;
+    info->refinements = o.precision == SMPM_FP64 ? 1 : cycles;
     info->rel_residual = resmax;
     info->removed_component = removed[0];
   }
-  bool conv = true;
-  for (int i = 0; i < nrhs; ++i)
-    if (iters[i] >= o.maxit) conv = false;
-  if (!conv) return fail(SMPM_ENOCONV, "GMRES reached maxit before the tolerance");
+  if (!conv)
+    return fail(SMPM_ENOCONV, o.precision == SMPM_FP64 ? "GMRES reached maxit before the tolerance"
+                                                        : "iterative refinement did not reach the tolerance");
   return SMPM_OK;
 }
 

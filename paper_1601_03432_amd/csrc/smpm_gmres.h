@@ -43,11 +43,14 @@ struct GmState {
   int nch;          // row chunks of a k-vector
   int rows;         // rows per chunk
   double tol;       // relative stopping tolerance
+  const double* bref2;  // squared reference norm per column (|b|^2): stop when |g| <= tol |b|
 };
 
 void gm_start(const DevPlan& P, const GmState& S, int nrhs, hipStream_t s);
 // kind: 1 = S, 2 = S M^{-1}, 3 = P S M^{-1}; tr selects the transposed operators
-void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s);
+// sprec / mprec: OpPrec of the Schur and block-Jacobi operators
+void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s,
+             int sprec = PREC_F64, int mprec = PREC_F64);
 // Givens step for the last column after `j` steps were enqueued
 void gm_close(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s);
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s);

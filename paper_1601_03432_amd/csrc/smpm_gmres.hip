@@ -151,9 +151,11 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta) {
 
 // beta_j, Givens for column j-1 (block 0), v_j = w / beta_j into V_j and
 // z = M^{-1} v_j (or z = v_j).  givens_only: stop after the Givens step.
+template <typename OpT>
 __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int j, int use_precond, int transpose,
                                                     int givens_only) {
-  __shared__ double xs[8 * kMaxN];
+  using Acc = typename AccOf<OpT>::type;
+  __shared__ Acc xs[8 * kMaxN];
   __shared__ double red[kWaves];
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int j,
   if (blockIdx.x == 0) {
     if (j == 0) {
       if (tid == 0) {
-        S.tolb[col] = S.tol * beta;
+        S.tolb[col] = S.tol * (S.bref2 ? sqrt(S.bref2[col]) : beta);
         S.g[(int64_t)col * S.ldv] = beta;
         S.res[col] = beta;
         if (!(beta > 0.0)) {
@@ -194,16 +196,16 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int j,
     for (int i = tid; i < sb; i += kThreads) {
       const int slot = P.blk_slots[o + i];
       const double v = wc[slot] * inv;
-      xs[i] = v;
+      xs[i] = (Acc)v;
       vj[slot] = v;
     }
     __syncthreads();
-    const double* Mp = (transpose ? P.MinvR : P.MinvC) + P.bcls_off[bc];
+    const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
     for (int r = tid; r < sb; r += kThreads) {
-      double acc = 0.0;
+      Acc acc = 0;
 #pragma unroll 8
-      for (int c = 0; c < sb; ++c) acc = fma(Mp[c * sb + r], xs[c], acc);
-      zc[P.blk_slots[o + r]] = acc;
+      for (int c = 0; c < sb; ++c) acc = fma(to_acc(Mp[c * sb + r]), xs[c], acc);
+      zc[P.blk_slots[o + r]] = (double)acc;
     }
   }
 }
@@ -357,11 +359,18 @@ static int precond_grid(const DevPlan& P, const GmState& S, int kind) {
   return kind == 1 ? S.nch : std::max(1, std::min(P.nblk, 1024));
 }
 
-void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_precond, dim3(precond_grid(P, S, kind), nrhs), dim3(kThreads), 0, s, P, S, j,
-                     kind == 1 ? 0 : 1, tr ? 1 : 0, 0);
+void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s, int sprec,
+             int mprec) {
+  const dim3 pg(precond_grid(P, S, kind), nrhs);
+  const int up = kind == 1 ? 0 : 1, trn = tr ? 1 : 0;
+  if (mprec == PREC_F32)
+    hipLaunchKernelGGL(k_gm_precond<float>, pg, dim3(kThreads), 0, s, P, S, j, up, trn, 0);
+  else if (mprec == PREC_BF16)
+    hipLaunchKernelGGL(k_gm_precond<bf16s>, pg, dim3(kThreads), 0, s, P, S, j, up, trn, 0);
+  else
+    hipLaunchKernelGGL(k_gm_precond<double>, pg, dim3(kThreads), 0, s, P, S, j, up, trn, 0);
   const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P);
-  launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s);
+  launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s, sprec);
   if (kind == 3) {
     if (fused_sums) {
       launch_coarse_sides(P, S.sides, S.c2, nrhs, tr, S.active, s);
@@ -377,7 +386,8 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool
 }
 
 void gm_close(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_precond, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, j, kind == 1 ? 0 : 1, tr ? 1 : 0, 1);
+  hipLaunchKernelGGL(k_gm_precond<double>, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, j, kind == 1 ? 0 : 1,
+                     tr ? 1 : 0, 1);
 }
 
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s) {

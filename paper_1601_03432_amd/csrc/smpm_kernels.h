@@ -44,6 +44,15 @@ struct DevPlan {
   const double* GT;        // its transpose
   const int* bdry_node;    // nbdry
   const double* bdry_tau;  // nbdry
+  // low-precision copies of the Schur side fluxes and block-Jacobi inverses
+  const float* WcF;
+  const float* WrF;
+  const float* MinvCF;
+  const float* MinvRF;
+  const unsigned short* WcB;     // bf16 bit patterns (upper half of an IEEE float)
+  const unsigned short* WrB;
+  const unsigned short* MinvCB;
+  const unsigned short* MinvRB;
   int ngrp;                // element groups (same class, up to grp_size elements)
   int grp_size;            // 1, 2, 4 or 8
   const int* grp_cls;      // ngrp
@@ -52,13 +61,58 @@ struct DevPlan {
 
 constexpr int kGroup = 8;
 
+// operator precision of the Schur / block-Jacobi applies
+enum OpPrec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
+struct bf16s {
+  unsigned short v;
+};
+
+template <typename T>
+struct AccOf {
+  using type = float;
+};
+template <>
+struct AccOf<double> {
+  using type = double;
+};
+
+__device__ __forceinline__ double to_acc(double v) { return v; }
+__device__ __forceinline__ float to_acc(float v) { return v; }
+__device__ __forceinline__ float to_acc(bf16s v) { return __uint_as_float((unsigned)v.v << 16); }
+
+template <typename T>
+__device__ __forceinline__ const T* schur_op(const DevPlan& P, bool rows_fast);
+template <>
+__device__ __forceinline__ const double* schur_op<double>(const DevPlan& P, bool c) { return c ? P.Wc : P.Wr; }
+template <>
+__device__ __forceinline__ const float* schur_op<float>(const DevPlan& P, bool c) { return c ? P.WcF : P.WrF; }
+template <>
+__device__ __forceinline__ const bf16s* schur_op<bf16s>(const DevPlan& P, bool c) {
+  return reinterpret_cast<const bf16s*>(c ? P.WcB : P.WrB);
+}
+template <typename T>
+__device__ __forceinline__ const T* minv_op(const DevPlan& P, bool transpose);
+template <>
+__device__ __forceinline__ const double* minv_op<double>(const DevPlan& P, bool tr) {
+  return tr ? P.MinvR : P.MinvC;
+}
+template <>
+__device__ __forceinline__ const float* minv_op<float>(const DevPlan& P, bool tr) {
+  return tr ? P.MinvRF : P.MinvCF;
+}
+template <>
+__device__ __forceinline__ const bf16s* minv_op<bf16s>(const DevPlan& P, bool tr) {
+  return reinterpret_cast<const bf16s*>(tr ? P.MinvRB : P.MinvCB);
+}
+
 // ---- operator applies; nrhs columns, column-blocked with the natural lengths
 void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
                   const int* active, hipStream_t s);
 // as launch_schur; if side_sums != nullptr (forward, n <= 16 only) it also writes the
 // sum of t over every inter-element side (nsides per column)
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
-                     const int* active, double* side_sums, hipStream_t s);
+                     const int* active, double* side_sums, hipStream_t s, int prec = PREC_F64);
 bool schur_has_side_sums(const DevPlan& P);
 // c2 = G c with c_j = side_sums of interface j's two sides
 void launch_coarse_sides(const DevPlan& P, const double* side_sums, double* c2, int nrhs, bool transpose,
@@ -70,7 +124,7 @@ void launch_backsub(const DevPlan& P, const double* f, const double* x, double* 
 void launch_local_adj(const DevPlan& P, const double* c, double* out, int nrhs, bool to_slots,
                       hipStream_t s);                         // out = A^{-T} c (r) or E^T A^{-T} c (k)
 void launch_precond(const DevPlan& P, const double* x, double* y, int nrhs, bool transpose,
-                    const int* active, hipStream_t s);
+                    const int* active, hipStream_t s, int prec = 0);
 void launch_iface_sum(const DevPlan& P, const double* t, double* c, int nrhs, const int* active,
                       hipStream_t s);                                                           // c = Z^T t
 void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool transpose,

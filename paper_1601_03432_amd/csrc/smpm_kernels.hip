@@ -33,17 +33,19 @@ constexpr int kPrefetch = 8;  // independent operator loads in flight per lane
 // and accumulates it against all elements of the group, so each operator entry
 // is read once per group.  Sender e's side-s flux lands in the facing slots of
 // its neighbour, which have no other writer.
-template <int G>
+template <int G, typename OpT>
 __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __restrict__ y,
                                                    double* __restrict__ t, const int* __restrict__ active,
                                                    double* __restrict__ side_sums) {
+  using Acc = typename AccOf<OpT>::type;
   extern __shared__ double lds[];
   const int col = blockIdx.y;
   if (active && !active[col]) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
   const int n = P.n, ld = 4 * n;
-  double* ys = lds + (size_t)wave * G * ld;
+  double* ysd = lds + (size_t)wave * G * ld;   // this wave's region (G*ld doubles)
+  Acc* ys = reinterpret_cast<Acc*>(ysd);
   const double* yc = y + (int64_t)col * P.k;
   double* tc = t + (int64_t)col * P.k;
   int elem[G];
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __re
       elem[u] = P.grp_elem[g * kGroup + u];
       if (elem[u] >= 0) {
         const int base = P.slot_off[elem[u]];
-        for (int c = lane; c < ns; c += 64) ys[u * ld + c] = yc[base + c];
+        for (int c = lane; c < ns; c += 64) ys[u * ld + c] = (Acc)yc[base + c];
       }
     }
   }
@@ -68,15 +70,15 @@ __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __re
   for (int o = lane; o < 4 * n && valid; o += 64) {
     const int s = o / n, i = o - s * n;
     if (P.cls_sidecol[J * 4 + s] < 0) continue;
-    const double* Wp = P.Wc + P.W_off[J * 4 + s];
-    double acc[G];
+    const OpT* Wp = schur_op<OpT>(P, true) + P.W_off[J * 4 + s];
+    Acc acc[G];
 #pragma unroll
-    for (int u = 0; u < G; ++u) acc[u] = 0.0;
+    for (int u = 0; u < G; ++u) acc[u] = 0;
     // operator loads are issued kPrefetch at a time so they overlap
     for (int c0 = 0; c0 < ns; c0 += kPrefetch) {
-      double wv[kPrefetch];
+      Acc wv[kPrefetch];
 #pragma unroll
-      for (int q = 0; q < kPrefetch; ++q) wv[q] = c0 + q < ns ? Wp[(c0 + q) * n + i] : 0.0;
+      for (int q = 0; q < kPrefetch; ++q) wv[q] = c0 + q < ns ? to_acc(Wp[(c0 + q) * n + i]) : Acc(0);
 #pragma unroll
       for (int q = 0; q < kPrefetch; ++q) {
         if (c0 + q >= ns) break;
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __re
       if (elem[u] < 0) break;
       const int recv = P.nbr[elem[u] * 4 + s];
       const int slot = P.side_slot[recv * 4 + (s ^ 1)] + i;
-      tv[u] = yc[slot] + acc[u];
+      tv[u] = yc[slot] + (double)acc[u];
       tc[slot] = tv[u];
     }
   }
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __re
     const int s = lane / n;
     if (P.cls_sidecol[J * 4 + s] >= 0) {
 #pragma unroll
-      for (int u = 0; u < G; ++u) ys[u * ld + lane] = tv[u];
+      for (int u = 0; u < G; ++u) ysd[u * ld + lane] = tv[u];
     }
   }
   __syncthreads();
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __re
     for (int u = 0; u < G; ++u) {
       if (elem[u] < 0) break;
       double acc = 0.0;
-      for (int i = 0; i < n; ++i) acc += ys[u * ld + s * n + i];
+      for (int i = 0; i < n; ++i) acc += ysd[u * ld + s * n + i];
       const int recv = P.nbr[elem[u] * 4 + s];
       ss[P.side_slot[recv * 4 + (s ^ 1)] / n] = acc;
     }
@@ -122,16 +124,17 @@ __global__ __launch_bounds__(256) void k_schur_fwd(DevPlan P, const double* __re
 
 // t = y + E^T A^{-T} B^T y for a group of same-class elements: element e collects
 // W_{J,s}^T applied to the slots its side-s flux feeds.  Lane = slot column c.
-template <int G>
+template <int G, typename OpT>
 __global__ __launch_bounds__(256) void k_schur_adj(DevPlan P, const double* __restrict__ y,
                                                    double* __restrict__ t, const int* __restrict__ active) {
+  using Acc = typename AccOf<OpT>::type;
   extern __shared__ double lds[];
   const int col = blockIdx.y;
   if (active && !active[col]) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
   const int n = P.n, ld = 4 * n;
-  double* yr = lds + (size_t)wave * G * ld;  // [u][s*n + i]
+  Acc* yr = reinterpret_cast<Acc*>(lds + (size_t)wave * G * ld);  // [u][s*n + i]
   const double* yc = y + (int64_t)col * P.k;
   double* tc = t + (int64_t)col * P.k;
   int elem[G];
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(256) void k_schur_adj(DevPlan P, const double* __re
         for (int q = lane; q < ld; q += 64) {
           const int s = q / n, i = q - s * n;
           const int j = P.nbr[elem[u] * 4 + s];
-          yr[u * ld + q] = j >= 0 ? yc[P.side_slot[j * 4 + (s ^ 1)] + i] : 0.0;
+          yr[u * ld + q] = j >= 0 ? (Acc)yc[P.side_slot[j * 4 + (s ^ 1)] + i] : Acc(0);
         }
       }
     }
@@ -154,16 +157,16 @@ __global__ __launch_bounds__(256) void k_schur_adj(DevPlan P, const double* __re
   __syncthreads();
   if (g >= P.ngrp) return;
   for (int c = lane; c < ns; c += 64) {
-    double acc[G];
+    Acc acc[G];
 #pragma unroll
-    for (int u = 0; u < G; ++u) acc[u] = 0.0;
+    for (int u = 0; u < G; ++u) acc[u] = 0;
     for (int s = 0; s < 4; ++s) {
       if (P.cls_sidecol[J * 4 + s] < 0) continue;
-      const double* Wp = P.Wr + P.W_off[J * 4 + s];
+      const OpT* Wp = schur_op<OpT>(P, false) + P.W_off[J * 4 + s];
       for (int i0 = 0; i0 < n; i0 += kPrefetch) {
-        double wv[kPrefetch];
+        Acc wv[kPrefetch];
 #pragma unroll
-        for (int q = 0; q < kPrefetch; ++q) wv[q] = i0 + q < n ? Wp[(i0 + q) * ns + c] : 0.0;
+        for (int q = 0; q < kPrefetch; ++q) wv[q] = i0 + q < n ? to_acc(Wp[(i0 + q) * ns + c]) : Acc(0);
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q) {
           if (i0 + q >= n) break;
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(256) void k_schur_adj(DevPlan P, const double* __re
     for (int u = 0; u < G; ++u) {
       if (elem[u] < 0) break;
       const int slot = P.slot_off[elem[u]] + c;
-      tc[slot] = yc[slot] + acc[u];
+      tc[slot] = yc[slot] + (double)acc[u];
     }
   }
 }
@@ -294,23 +297,25 @@ __global__ __launch_bounds__(256) void k_local_adj(DevPlan P, const double* __re
 
 // ------------------------------------------------------------------ block-Jacobi
 
+template <typename OpT>
 __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __restrict__ x, double* __restrict__ y,
                                                  int transpose, const int* __restrict__ active) {
-  __shared__ double xs[8 * kMaxN];
+  using Acc = typename AccOf<OpT>::type;
+  __shared__ Acc xs[8 * kMaxN];
   const int b = blockIdx.x, col = blockIdx.y, tid = threadIdx.x;
   if (active && !active[col]) return;
   const double* xc = x + (int64_t)col * P.k;
   double* yc = y + (int64_t)col * P.k;
   const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
   const int bc = P.blk_cls[b];
-  for (int i = tid; i < sb; i += 256) xs[i] = xc[P.blk_slots[o + i]];
+  for (int i = tid; i < sb; i += 256) xs[i] = (Acc)xc[P.blk_slots[o + i]];
   __syncthreads();
-  const double* Mp = (transpose ? P.MinvR : P.MinvC) + P.bcls_off[bc];
+  const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
   for (int r = tid; r < sb; r += 256) {
-    double acc = 0.0;
+    Acc acc = 0;
 #pragma unroll 8
-    for (int c = 0; c < sb; ++c) acc = fma(Mp[c * sb + r], xs[c], acc);
-    yc[P.blk_slots[o + r]] = acc;
+    for (int c = 0; c < sb; ++c) acc = fma(to_acc(Mp[c * sb + r]), xs[c], acc);
+    yc[P.blk_slots[o + r]] = (double)acc;
   }
 }
 
@@ -579,22 +584,31 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
 }
 
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
-                     double* side_sums, hipStream_t s) {
+                     double* side_sums, hipStream_t s, int prec) {
   if (transpose || !schur_has_side_sums(P)) side_sums = nullptr;
   const int blocks = ((P.ngrp + 3) / 4 + 7) / 8 * 8;  // a multiple of the 8 XCDs
   const size_t lds = (size_t)4 * P.grp_size * 4 * P.n * sizeof(double);
   dim3 g(blocks, nrhs);
-#define SMPM_SCHUR_LAUNCH(G)                                                     \
-  if (transpose)                                                                 \
-    hipLaunchKernelGGL(k_schur_adj<G>, g, dim3(256), lds, s, P, y, t, active);   \
-  else                                                                           \
-    hipLaunchKernelGGL(k_schur_fwd<G>, g, dim3(256), lds, s, P, y, t, active, side_sums);
-  switch (P.grp_size) {
-    case 1: SMPM_SCHUR_LAUNCH(1) break;
-    case 2: SMPM_SCHUR_LAUNCH(2) break;
-    case 4: SMPM_SCHUR_LAUNCH(4) break;
-    default: SMPM_SCHUR_LAUNCH(8) break;
+#define SMPM_SCHUR_LAUNCH(G, T)                                                       \
+  if (transpose)                                                                      \
+    hipLaunchKernelGGL((k_schur_adj<G, T>), g, dim3(256), lds, s, P, y, t, active);   \
+  else                                                                                \
+    hipLaunchKernelGGL((k_schur_fwd<G, T>), g, dim3(256), lds, s, P, y, t, active, side_sums);
+#define SMPM_SCHUR_PREC(G)                                  \
+  if (prec == PREC_F32) {                                   \
+    SMPM_SCHUR_LAUNCH(G, float)                             \
+  } else if (prec == PREC_BF16) {                           \
+    SMPM_SCHUR_LAUNCH(G, bf16s)                             \
+  } else {                                                  \
+    SMPM_SCHUR_LAUNCH(G, double)                            \
   }
+  switch (P.grp_size) {
+    case 1: SMPM_SCHUR_PREC(1) break;
+    case 2: SMPM_SCHUR_PREC(2) break;
+    case 4: SMPM_SCHUR_PREC(4) break;
+    default: SMPM_SCHUR_PREC(8) break;
+  }
+#undef SMPM_SCHUR_PREC
 #undef SMPM_SCHUR_LAUNCH
 }
 
@@ -616,8 +630,14 @@ void launch_local_adj(const DevPlan& P, const double* c, double* out, int nrhs, 
 }
 
 void launch_precond(const DevPlan& P, const double* x, double* y, int nrhs, bool transpose, const int* active,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_precond, dim3(P.nblk, nrhs), dim3(256), 0, s, P, x, y, transpose ? 1 : 0, active);
+                    hipStream_t s, int prec) {
+  const dim3 g(P.nblk, nrhs);
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_precond<float>, g, dim3(256), 0, s, P, x, y, transpose ? 1 : 0, active);
+  else if (prec == PREC_BF16)
+    hipLaunchKernelGGL(k_precond<bf16s>, g, dim3(256), 0, s, P, x, y, transpose ? 1 : 0, active);
+  else
+    hipLaunchKernelGGL(k_precond<double>, g, dim3(256), 0, s, P, x, y, transpose ? 1 : 0, active);
 }
 
 void launch_iface_sum(const DevPlan& P, const double* t, double* c, int nrhs, const int* active, hipStream_t s) {

@@ -260,7 +260,7 @@ class Context:
         return out
 
     def solve(self, f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64, transpose=False,
-              inner_tol=1e-6, max_refine=20, stream=None, raise_on_noconv=True):
+              inner_tol=1e-4, max_refine=20, stream=None, raise_on_noconv=True):
         import torch
         f = self._as_cols(f, self.r)
         nrhs = f.shape[0]
