@@ -162,26 +162,32 @@ def main():
         # Schur-apply bandwidth on a large grid with rotated cold buffers (> 256 MB MALL)
         big = smpm.Context(128, 128, 16, wl.uniform_breaks(128), wl.uniform_breaks(128))
         kb = big.k
-        nbuf = max(2, int(np.ceil(600e6 / (2 * kb * 8))))
-        ins = [torch.randn(1, kb, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
-        outs = [torch.empty(1, kb, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
-        it = {"i": 0}
+        op_big = big.stats()["schur_operator_bytes"]
 
-        def one():
-            i = it["i"] % nbuf
-            big.schur_apply_into(ins[i], outs[i], stream=stream)
-            it["i"] += 1
+        def large(nrhs):
+            nbuf = max(2, int(np.ceil(600e6 / (2 * nrhs * kb * 8))))
+            ins = [torch.randn(nrhs, kb, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+            outs = [torch.empty(nrhs, kb, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+            it = {"i": 0}
 
-        for _ in range(nbuf):
-            one()
-        ms_big = event_time_ms(one, stream, 5 * nbuf)
-        bbytes = 2 * kb * 8 + big.stats()["schur_operator_bytes"]
-        out["schur_large"] = {"grid": "128x128 elements, n=16, [0,1]^2, k=%d" % kb,
-                              "buffers_rotated": nbuf, "avg_launch_us": ms_big * 1e3,
-                              "alg_bytes_per_launch": bbytes,
-                              "GB_s": bbytes / (ms_big * 1e-3) / 1e9,
-                              "frac_of_8TBs": bbytes / (ms_big * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        del ins, outs, big
+            def one():
+                i = it["i"] % nbuf
+                big.schur_apply_into(ins[i], outs[i], stream=stream)
+                it["i"] += 1
+
+            for _ in range(nbuf):
+                one()
+            ms_big = event_time_ms(one, stream, max(20, 5 * nbuf))
+            bbytes = 2 * nrhs * kb * 8 + op_big
+            return {"grid": "128x128 elements, n=16, [0,1]^2, k=%d" % kb, "columns": nrhs,
+                    "buffers_rotated": nbuf, "avg_launch_us": ms_big * 1e3,
+                    "alg_bytes_per_launch": bbytes,
+                    "GB_s": bbytes / (ms_big * 1e-3) / 1e9,
+                    "frac_of_8TBs": bbytes / (ms_big * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+        out["schur_large"] = large(1)
+        out["schur_large_batched8"] = large(8)
+        del big
 
     if not args.no_cpu_baseline:
         from oracle import smpm_oracle as O

@@ -600,6 +600,18 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   d.grp_size = p.grp_size;
   rc |= upload(c, p.grp_cls, &d.grp_cls, s);
   rc |= upload(c, p.grp_elem, &d.grp_elem, s);
+  d.ntile = p.ntile;
+  rc |= upload(c, p.tile_cls, &d.tile_cls, s);
+  rc |= upload(c, p.tile_elem, &d.tile_elem, s);
+  rc |= upload(c, p.tile_src, &d.tile_src, s);
+  rc |= upload(c, p.tile_dst, &d.tile_dst, s);
+  d.mma_mt = p.mma_mt;
+  rc |= upload(c, p.Afwd, &d.Afwd, s);
+  rc |= upload(c, p.Aadj, &d.Aadj, s);
+  rc |= upload(c, to_f32(p.Afwd), &d.AfwdF, s);
+  rc |= upload(c, to_f32(p.Aadj), &d.AadjF, s);
+  rc |= upload(c, to_b16(p.Afwd), &d.AfwdB, s);
+  rc |= upload(c, to_b16(p.Aadj), &d.AadjB, s);
   rc |= upload(c, bnode, &d.bdry_node, s);
   rc |= upload(c, btau, &d.bdry_tau, s);
   if (rc != SMPM_OK) return SMPM_ENOMEM;

@@ -57,9 +57,22 @@ struct DevPlan {
   int grp_size;            // 1, 2, 4 or 8
   const int* grp_cls;      // ngrp
   const int* grp_elem;     // ngrp*kGroup, -1 padded
+  int ntile;               // matrix-core tiles (same class, up to kTile elements)
+  const int* tile_cls;     // ntile
+  const int* tile_elem;    // ntile*kTile, -1 padded
+  const int* tile_src;     // ntile*kTile: first slot of the element, -1 if none
+  const int* tile_dst;     // ntile*kTile*4: first slot facing side s, -1 if none
+  int mma_mt;              // 16-row tiles of the matrix-core operator fragments (0: n > 16)
+  const double* Afwd;      // [cls][w][q][lane] fragments of W (forward) and W^T (transpose)
+  const double* Aadj;
+  const float* AfwdF;
+  const float* AadjF;
+  const unsigned short* AfwdB;
+  const unsigned short* AadjB;
 };
 
 constexpr int kGroup = 8;
+constexpr int kTile = 16;
 
 // operator precision of the Schur / block-Jacobi applies
 enum OpPrec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
@@ -90,6 +103,16 @@ __device__ __forceinline__ const float* schur_op<float>(const DevPlan& P, bool c
 template <>
 __device__ __forceinline__ const bf16s* schur_op<bf16s>(const DevPlan& P, bool c) {
   return reinterpret_cast<const bf16s*>(c ? P.WcB : P.WrB);
+}
+template <typename T>
+__device__ __forceinline__ const T* mma_op(const DevPlan& P, bool adj);
+template <>
+__device__ __forceinline__ const double* mma_op<double>(const DevPlan& P, bool adj) { return adj ? P.Aadj : P.Afwd; }
+template <>
+__device__ __forceinline__ const float* mma_op<float>(const DevPlan& P, bool adj) { return adj ? P.AadjF : P.AfwdF; }
+template <>
+__device__ __forceinline__ const bf16s* mma_op<bf16s>(const DevPlan& P, bool adj) {
+  return reinterpret_cast<const bf16s*>(adj ? P.AadjB : P.AfwdB);
 }
 template <typename T>
 __device__ __forceinline__ const T* minv_op(const DevPlan& P, bool transpose);

@@ -184,6 +184,201 @@ __global__ __launch_bounds__(256) void k_schur_adj(DevPlan P, const double* __re
   }
 }
 
+// ------------------------------------------------------------------ Schur apply on matrix cores
+//
+// For a class J the element-local part of S is one dense map per element, from its
+// ns slots to the 4n nodes of the sides its fluxes reach (rows o = s*n + i).  A tile
+// of up to 16 same-class elements turns it into the product
+//     T[o][u] = sum_c W_J[o][c] Y[c][u]         (forward; u = element of the tile)
+//     T[c][u] = sum_o W_J[o][c] Y[o][u]         (transpose: Y gathered from the
+//                                                neighbours' facing slots)
+// done with 16x16x4 MFMA tiles: wavefront w of the workgroup owns output rows
+// 16w..16w+15, the operator fragments come from the class copy (L2-resident, shared
+// by every tile of the class) and the Y tile is staged in LDS as [k][u].
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename Acc>
+struct Mma;
+template <>
+struct Mma<double> {
+  using V = v4d;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16x16 result held in register v of lane l (column = l % 16)
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct Mma<float> {
+  using V = v4f;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+constexpr int kTileLd = kTile + 1;  // LDS row stride of the staged Y tile
+
+// KT = 4-deep steps (4*KT >= 4n, KT = 4 * row tiles), workgroup = 16*KT threads,
+// NC right-hand-side columns per workgroup (the operator fragments, held in
+// registers, serve all of them).  Every index the tile needs comes from its slot
+// tables, so each gather is one load after one table load, and all of a thread's
+// loads are issued before the first wait.  The 16x16 results go back through LDS
+// so that 16 lanes write 16 consecutive rows (one receiving side, or the element's
+// own slots) with one coalesced store.
+template <bool ADJ, int KT, int NC, typename OpT>
+__global__ __launch_bounds__(256) void k_schur_mfma(DevPlan P, const double* __restrict__ y,
+                                                    double* __restrict__ t, int nrhs,
+                                                    const int* __restrict__ active,
+                                                    double* __restrict__ side_sums) {
+  using Acc = typename AccOf<OpT>::type;
+  using M = Mma<Acc>;
+  constexpr int kRows = 4 * KT;                    // staged Y rows (contraction index, zero padded)
+  constexpr int kPer = kTile * kRows / (16 * KT);  // staged values per thread and column (= 4)
+  constexpr int kWaves = KT / 4;
+  extern __shared__ double lds[];
+  const int c0 = blockIdx.y * NC;
+  bool on[NC];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    on[c] = c0 + c < nrhs && (!active || active[c0 + c]);
+    any = any || on[c];
+  }
+  if (!any) return;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= P.ntile) return;
+  const int n = P.n, no = 4 * n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int J = P.tile_cls[tile];
+  const int ns = P.cls_nslots[J];
+  const int kdim = ADJ ? no : ns;
+  // ys: the staged Y tiles [NC][kRows][kTileLd]; after the products the same space
+  // holds the result tiles [NC][kWaves][kTile][kTileLd] (as many entries)
+  Acc* ys = reinterpret_cast<Acc*>(lds);
+  double* part = lds + (NC * kRows * kTileLd * sizeof(Acc) + 7) / 8;  // [NC][kTile][4][kWaves]
+  const int* src = P.tile_src + tile * kTile;
+  const int* dst = P.tile_dst + tile * kTile * 4;
+
+  // operator fragments: one coalesced load per step
+  const OpT* Af = mma_op<OpT>(P, ADJ) + ((int64_t)(J * P.mma_mt + wave) * KT) * 64 + lane;
+  Acc a[KT];
+#pragma unroll
+  for (int q = 0; q < KT; ++q) a[q] = to_acc(Af[q * 64]);
+
+  // Output mapping after the transpose: lane l writes row mr = 16*wave + l%16 of
+  // tile columns (elements) uu = l/16 + 4v.  Table entries are loaded first
+  // (unconditional, in-bounds), then every y gather at once; an invalid gather
+  // reads y[0] and is masked, so no load waits on a branch.
+  const int row = lane & 15, mr = wave * 16 + row;
+  const int srow = min(mr / n, 3);
+  int tb[4], sb[kPer];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int uu = (lane >> 4) + 4 * v;
+    tb[v] = ADJ ? src[uu] : dst[uu * 4 + srow];
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int q = tid + j * 16 * KT;
+    const int uu = q / kRows, kk = q - uu * kRows;
+    sb[j] = ADJ ? dst[uu * 4 + min(kk / n, 3)] : src[uu];
+  }
+  const bool row_ok = ADJ ? mr < ns : mr < no;
+  int slot[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) slot[v] = row_ok && tb[v] >= 0 ? tb[v] + (ADJ ? mr : mr - srow * n) : -1;
+  // the Y tile as [kk][u]: forward gathers the element's own slots, transpose the
+  // neighbours' slots facing it
+  int gi[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int q = tid + j * 16 * KT;
+    const int uu = q / kRows, kk = q - uu * kRows;
+    const int s = kk / n;
+    const bool ok = sb[j] >= 0 && kk < kdim;
+    gi[j] = ok ? sb[j] + (ADJ ? kk - s * n : kk) : -1;
+  }
+  double yv[NC][4], st[NC][kPer];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double* yc = y + (int64_t)(on[c] ? c0 + c : 0) * P.k;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) st[c][j] = yc[max(gi[j], 0)];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) yv[c][v] = yc[max(slot[v], 0)];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int q = tid + j * 16 * KT;
+      const int uu = q / kRows, kk = q - uu * kRows;
+      ys[(c * kRows + kk) * kTileLd + uu] = gi[j] >= 0 ? (Acc)st[c][j] : Acc(0);
+    }
+  __syncthreads();
+
+  typename M::V acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    acc[c] = typename M::V{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < KT; ++q)
+      acc[c] = M::mma(a[q], ys[(c * kRows + 4 * q + (lane >> 4)) * kTileLd + (lane & 15)], acc[c]);
+  }
+  __syncthreads();  // every wave is done reading ys
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      ys[((c * kWaves + wave) * kTile + (lane & 15)) * kTileLd + M::row(lane, v)] = acc[c][v];
+  __syncthreads();
+
+  // receiving sides met by this wave's 16 rows (several when n < 16)
+  const int s_lo = min((wave * 16) / n, 3), s_hi = min((wave * 16 + 15) / n, 3);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (!on[c]) continue;
+    double* tc = t + (int64_t)(c0 + c) * P.k;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int uu = (lane >> 4) + 4 * v;
+      const double tv = yv[c][v] + (double)ys[((c * kWaves + wave) * kTile + uu) * kTileLd + row];
+      if (slot[v] >= 0) tc[slot[v]] = tv;
+      if (!ADJ && side_sums) {
+        // sums over the rows of each receiving side: 16-lane butterflies, fixed order
+        double* pp = part + (c * kTile + uu) * 4 * kWaves;
+        if (row == 0)
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (s < s_lo || s > s_hi) pp[s * kWaves + wave] = 0.0;
+        for (int s = s_lo; s <= s_hi; ++s) {
+          double x = slot[v] >= 0 && srow == s ? tv : 0.0;
+#pragma unroll
+          for (int m = 1; m < 16; m <<= 1) x += __shfl_xor(x, m);
+          if (row == 0) pp[s * kWaves + wave] = x;
+        }
+      }
+    }
+  }
+  if (ADJ || !side_sums) return;
+  __syncthreads();
+  if (tid < 4 * kTile) {
+    const int uu = tid >> 2, s = tid & 3;
+    const int b = dst[uu * 4 + s];
+    if (b >= 0)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (!on[c]) continue;
+        double sum = 0.0;
+        for (int w = 0; w < kWaves; ++w) sum += part[((c * kTile + uu) * 4 + s) * kWaves + w];
+        side_sums[(int64_t)(c0 + c) * P.nsides + b / n] = sum;
+      }
+  }
+}
+
 // ------------------------------------------------------------------ B A^{-1} and its transpose
 
 __global__ __launch_bounds__(64) void k_flux(DevPlan P, const double* __restrict__ f, double* __restrict__ b) {
@@ -586,6 +781,47 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
                      double* side_sums, hipStream_t s, int prec) {
   if (transpose || !schur_has_side_sums(P)) side_sums = nullptr;
+  if (P.mma_mt > 0) {
+    // matrix-core path: one workgroup per tile and NC columns, one wavefront per 16 rows
+    const int kt = 4 * P.mma_mt;
+    const int nc = nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
+    const size_t acc = prec == PREC_F64 ? sizeof(double) : sizeof(float);
+    const size_t lds = ((size_t)nc * 4 * kt * kTileLd * acc + 7) / 8 * 8 +
+                       (size_t)nc * kTile * 4 * (kt / 4) * sizeof(double);
+    const dim3 g((P.ntile + 7) / 8 * 8, (nrhs + nc - 1) / nc);
+    const dim3 b(16 * kt);
+#define SMPM_MFMA_LAUNCH(KT, NC, T)                                                                       \
+  if (transpose)                                                                                          \
+    hipLaunchKernelGGL((k_schur_mfma<true, KT, NC, T>), g, b, lds, s, P, y, t, nrhs, active, nullptr);    \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_schur_mfma<false, KT, NC, T>), g, b, lds, s, P, y, t, nrhs, active, side_sums);
+#define SMPM_MFMA_NC(KT, T)                 \
+  if (nc == 4) {                            \
+    SMPM_MFMA_LAUNCH(KT, 4, T)              \
+  } else if (nc == 2) {                     \
+    SMPM_MFMA_LAUNCH(KT, 2, T)              \
+  } else {                                  \
+    SMPM_MFMA_LAUNCH(KT, 1, T)              \
+  }
+#define SMPM_MFMA_PREC(KT)           \
+  if (prec == PREC_F32) {            \
+    SMPM_MFMA_NC(KT, float)          \
+  } else if (prec == PREC_BF16) {    \
+    SMPM_MFMA_NC(KT, bf16s)          \
+  } else {                           \
+    SMPM_MFMA_NC(KT, double)         \
+  }
+    switch (kt) {
+      case 4: SMPM_MFMA_PREC(4) break;
+      case 8: SMPM_MFMA_PREC(8) break;
+      case 12: SMPM_MFMA_PREC(12) break;
+      default: SMPM_MFMA_PREC(16) break;
+    }
+#undef SMPM_MFMA_PREC
+#undef SMPM_MFMA_NC
+#undef SMPM_MFMA_LAUNCH
+    return;
+  }
   const int blocks = ((P.ngrp + 3) / 4 + 7) / 8 * 8;  // a multiple of the 8 XCDs
   const size_t lds = (size_t)4 * P.grp_size * 4 * P.n * sizeof(double);
   dim3 g(blocks, nrhs);

@@ -380,22 +380,30 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
     p.cls[e] = it->second;
   }
 
-  // element groups: elements sorted by (class, id), cut into runs of kGroup
+  // element groups: elements sorted by (class, id), cut into runs of one class
   {
     std::vector<int> order(p.nel);
     for (int e = 0; e < p.nel; ++e) order[e] = e;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p.cls[a] < p.cls[b]; });
-    // enough groups to occupy the chip (about 2048 wavefronts), at most kGroup per group
+    auto cut = [&](int stride, int size, std::vector<int>& gcls, std::vector<int>& gelem) {
+      for (int i = 0; i < p.nel;) {
+        const int J = p.cls[order[i]];
+        int cnt = 0;
+        gcls.push_back(J);
+        for (; i < p.nel && cnt < size && p.cls[order[i]] == J; ++i, ++cnt) gelem.push_back(order[i]);
+        for (int u = cnt; u < stride; ++u) gelem.push_back(-1);
+      }
+      return (int)gcls.size();
+    };
+    // vector kernels: enough groups to occupy the chip (about 2048 wavefronts)
     p.grp_size = Plan::kGroup;
     while (p.grp_size > 1 && (p.nel + p.grp_size - 1) / p.grp_size < 2048) p.grp_size /= 2;
-    for (int i = 0; i < p.nel;) {
-      const int J = p.cls[order[i]];
-      int cnt = 0;
-      p.grp_cls.push_back(J);
-      for (; i < p.nel && cnt < p.grp_size && p.cls[order[i]] == J; ++i, ++cnt) p.grp_elem.push_back(order[i]);
-      for (int u = cnt; u < Plan::kGroup; ++u) p.grp_elem.push_back(-1);
-    }
-    p.ngrp = (int)p.grp_cls.size();
+    p.ngrp = cut(Plan::kGroup, p.grp_size, p.grp_cls, p.grp_elem);
+    // matrix-core tiles: 16 elements form the N side of a 16x16 product; small grids
+    // take narrower tiles (down to 4) to spread over more workgroups
+    p.tile_size = Plan::kTile;
+    while (p.tile_size > 4 && (p.nel + p.tile_size - 1) / p.tile_size < 1024) p.tile_size /= 2;
+    p.ntile = cut(Plan::kTile, p.tile_size, p.tile_cls, p.tile_elem);
   }
 
   // class operators
@@ -467,6 +475,46 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
         }
     }
   }
+
+  // matrix-core fragments of the class operators and the tiles' slot tables
+  if (n <= 16) {
+    p.mma_mt = (4 * n + 15) / 16;
+    p.mma_kt = 4 * p.mma_mt;
+    const int mt = p.mma_mt, kt = p.mma_kt;
+    p.Afwd.assign((size_t)ncls * mt * kt * 64, 0.0);
+    p.Aadj.assign((size_t)ncls * mt * kt * 64, 0.0);
+    for (int J = 0; J < ncls; ++J) {
+      const int ns = p.classes[J].nslots;
+      for (int w = 0; w < mt; ++w)
+        for (int q = 0; q < kt; ++q)
+          for (int l = 0; l < 64; ++l) {
+            const int m = 16 * w + l % 16, kk = 4 * q + l / 16;
+            const size_t at = (((size_t)J * mt + w) * kt + q) * 64 + l;
+            // forward: row m = node (s, i) of a receiving side, column kk = slot
+            if (m < 4 * n && kk < ns) {
+              const int64_t wo = p.W_off[(size_t)J * 4 + m / n];
+              if (wo >= 0) p.Afwd[at] = p.Wc[wo + (size_t)kk * n + m % n];
+            }
+            // transpose: row m = slot, column kk = node (s, i)
+            if (m < ns && kk < 4 * n) {
+              const int64_t wo = p.W_off[(size_t)J * 4 + kk / n];
+              if (wo >= 0) p.Aadj[at] = p.Wc[wo + (size_t)m * n + kk % n];
+            }
+          }
+    }
+  }
+  p.tile_src.assign((size_t)p.ntile * Plan::kTile, -1);
+  p.tile_dst.assign((size_t)p.ntile * Plan::kTile * 4, -1);
+  for (int t = 0; t < p.ntile; ++t)
+    for (int u = 0; u < Plan::kTile; ++u) {
+      const int e = p.tile_elem[(size_t)t * Plan::kTile + u];
+      if (e < 0) continue;
+      p.tile_src[(size_t)t * Plan::kTile + u] = p.slot_off[e];
+      for (int s = 0; s < 4; ++s) {
+        const int j = p.nbr[(size_t)e * 4 + s];
+        if (j >= 0) p.tile_dst[((size_t)t * Plan::kTile + u) * 4 + s] = p.side_slot[(size_t)j * 4 + (s ^ 1)];
+      }
+    }
 
   // v0 = B 1: every slot of side s of element e holds -tau_{e,s}
   p.v0.assign(p.k, 0.0);

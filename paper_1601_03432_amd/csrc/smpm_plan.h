@@ -58,6 +58,19 @@ struct Plan {
   int ngrp = 0;
   std::vector<int> grp_cls;          // class of each group
   std::vector<int> grp_elem;         // ngrp*kGroup element ids, -1 padded
+  // tiles of up to kTile elements of one class: the columns of the matrix-core products
+  static constexpr int kTile = 16;
+  int tile_size = 16;                // 4, 8 or 16
+  int ntile = 0;
+  std::vector<int> tile_cls;
+  std::vector<int> tile_elem;        // ntile*kTile element ids, -1 padded
+  std::vector<int> tile_src;         // ntile*kTile: first slot of the element, -1 if none
+  std::vector<int> tile_dst;         // ntile*kTile*4: first slot facing side s, -1 if none
+  // class operators in matrix-core fragment order (n <= 16): [cls][row tile w][step q][lane],
+  // lane l of step q holds A[16w + l%16][4q + l/16]; A = W (forward) or W^T (transpose)
+  int mma_mt = 0;                    // 16-row tiles covering 4n rows
+  int mma_kt = 0;                    // 4-deep steps covering 4n columns (a multiple of 4)
+  std::vector<double> Afwd, Aadj;
   // block-Jacobi
   int nblk = 0;
   std::vector<int> blk_red;          // red element of each block

@@ -236,8 +236,15 @@ class Context:
         return out
 
     def schur_apply_into(self, v, out, transpose=False, stream=None):
-        """S v written into a preallocated tensor `out` (same shape as v)."""
+        """S v written into a preallocated tensor `out` (same shape as v, both
+        contiguous (columns, k) CUDA float64)."""
         import torch
+        for t in (v, out):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                    and t.dim() == 2 and t.shape[1] == self.k and t.is_contiguous()):
+                raise ValueError(f"expected contiguous CUDA float64 tensors of shape (columns, {self.k})")
+        if out.shape != v.shape or out.data_ptr() == v.data_ptr():
+            raise ValueError("out must match v in shape and must not alias it")
         _check(self._lib.smpm_schur_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr()),
                                           v.shape[0], int(transpose), _stream(torch, stream)))
         return out
