@@ -99,7 +99,7 @@ typedef struct smpm_solve_opts {
                          refinement stops when the FP64 true residual meets the same bound  */
   int maxit;          /* maximum GMRES iterations per solve or refinement cycle (default 400)    */
   int precision;      /* smpm_precision (default SMPM_FP64)                                      */
-  int transpose;      /* 1: solve the adjoint system L^T mu = c instead (default 0)               */
+  int transpose;      /* 1: adjoint of the solution map (see smpm_solve; g must be NULL)           */
   int variant;        /* 3: deflated + block-Jacobi (Algorithm 3), 2: block-Jacobi only
                          (Algorithm 2), 1: unpreconditioned (Algorithm 1); default 3               */
   double inner_tol;   /* mixed precision: inner GMRES tolerance per refinement cycle (1e-4)      */
@@ -110,7 +110,8 @@ typedef struct smpm_solve_info {
   int iterations;           /* GMRES iterations, summed over refinement cycles, max over columns */
   int refinements;          /* refinement cycles (1 for FP64)                                    */
   double rel_residual;      /* max over columns of the FP64 ||b_hat - S x|| / ||b_hat||          */
-  double removed_component; /* u_L^T (f + T g) of column 0 (the projected-out incompatibility)   */
+  double removed_component; /* column 0: u_L^T (f + T g), the projected-out incompatibility;
+                               adjoint: (1^T c)/(w^T 1), the removed multiple of w            */
 } smpm_solve_info;
 
 typedef struct smpm_plan_stats {
@@ -185,9 +186,10 @@ int smpm_precond_apply(smpm_ctx *ctx, const double *x, double *y, int nrhs, int 
                        void *stream);
 
 /* One of the projections of smpm_projection on nrhs vectors (r- or k-length).
- * transpose = 1 gives the transposed projection (P^T, Q^T; L, S, MEAN are
- * replaced by their adjoint counterparts: 1/sqrt(r), v0/|v0| and w/|w| as
- * the projected directions, see the design notes).  in == out is allowed. */
+ * transpose = 1 gives the projections of the adjoint solve: P^T and Q^T; for L
+ * and S the orthogonal projection off the null vector of the transposed
+ * operator (1/sqrt(r) for L^T, v0/|v0| for S^T); for MEAN the transpose
+ * x - w (1^T x)/(w^T 1).  in == out is allowed. */
 int smpm_project(smpm_ctx *ctx, int which, const double *in, double *out, int nrhs,
                  int transpose, void *stream);
 
@@ -200,6 +202,21 @@ int smpm_project(smpm_ctx *ctx, int which, const double *in, double *out, int nr
  * last iterate).  Synchronizes the stream. */
 int smpm_solve(smpm_ctx *ctx, const double *f, const double *g, double *u, int nrhs,
                const smpm_solve_opts *opts, smpm_solve_info *info, void *stream);
+/* With opts->transpose = 1 the same call applies the transpose of that linear
+ * solution map u = K (f + T g): f holds a cotangent c (e.g. dLoss/du), g must be
+ * NULL, and u receives mu = K^T c, i.e. the solution of L^T mu = c~ with
+ * c~ = c - w (1^T c)/(w^T 1) and u_L^T mu = 0.  It runs Algorithm 3 on the
+ * transposed system: S^T xi = E^T A^{-T} c~ (projected off v0), deflated GMRES
+ * on P'S^T M^{-T} with P' = Q^T, Q' = P^T and G^T, then mu = A^{-T}(c~ - B^T xi).
+ * Then dLoss/df = mu and dLoss/dg = T^T mu (smpm_boundary_transpose).  The
+ * stopping rule and the precision options are those of the forward solve. */
+
+/* dg = T^T mu for nrhs r-vectors mu: the gradient with respect to the Neumann
+ * data (layout of g: south, north, west, east edges, 2n(m_x+m_y) per column)
+ * given the gradient mu with respect to f + T g.  T places tau_i g_i on the
+ * physical-boundary nodes (Eq. smpm_poisson), so dg_b = tau_b mu[node(b)].
+ * Device pointers; mu and dg must not alias. */
+int smpm_boundary_transpose(smpm_ctx *ctx, const double *mu, double *dg, int nrhs, void *stream);
 
 /* Thread-local text of the last error ("" if none). */
 const char *smpm_last_error(void);

@@ -436,6 +436,34 @@ def solve_unreduced(split: Split, f, g=None):
     return sol[:-1], sol[-1], uL, ft
 
 
+def solve_adjoint_unreduced(split: Split, c):
+    """mu = K^T c for the linear map u = K (f + T g) that solve_unreduced computes.
+
+    The paper solves only the forward problem; its adjoint is the transpose of that
+    map.  Forward: u = Pi_w L^- Pi_L b with Pi_L = I - u_L u_L^T (Sec. 1.4: the
+    right-hand side projected onto range L) and Pi_w = I - 1 w^T / (w^T 1) (the
+    constant fixed by w^T u = 0).  Transposed: c~ = c - w (1^T c)/(w^T 1) lies in
+    range(L^T) = 1-perp, and mu is the solution of L^T mu = c~ orthogonal to u_L,
+    the null vector of L^T.  Solved with the nonsingular bordered matrix
+    [[L^T, 1], [u_L^T, 0]].  For a loss with dLoss/du = c: dLoss/df = mu and
+    dLoss/dg = T^T mu.  Returns (mu, lam, c~); lam ~ 0 confirms consistency.
+    """
+    grid = split.grid
+    uL = left_null_vector(split.L, np.ones(grid.r))
+    w = grid.quad_weights()
+    c = np.asarray(c, np.float64)
+    ct = c - w * (c.sum() / w.sum())
+    K = sp.bmat([[split.L.T, sp.csr_matrix(np.ones((grid.r, 1)))],
+                 [sp.csr_matrix(uL.reshape(1, -1)), None]], format="csc")
+    sol = spla.spsolve(K, np.concatenate([ct, [0.0]]))
+    return sol[:-1], sol[-1], ct
+
+
+def boundary_adjoint(split: Split, mu):
+    """T^T mu: the gradient with respect to the Neumann data g given dLoss/d(f + T g) = mu."""
+    return split.T.T @ np.asarray(mu, np.float64)
+
+
 class SchurSystem:
     """Everything the Schur route needs, built from a Split (Secs. 1.3-1.4)."""
 

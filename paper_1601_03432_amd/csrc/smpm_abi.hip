@@ -839,6 +839,17 @@ int smpm_schur_apply(smpm_ctx* c, const double* v, double* Sv, int nrhs, int tra
   return SMPM_OK;
 }
 
+int smpm_boundary_transpose(smpm_ctx* c, const double* mu, double* dg, int nrhs, void* stream) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!mu || !dg || nrhs < 1) return fail(SMPM_EINVAL, "bad vector arguments");
+  if (aliases(mu, sizeof(double) * c->plan.r * nrhs, dg, sizeof(double) * c->dp.nbdry * nrhs))
+    return fail(SMPM_EINVAL, "input and output alias");
+  launch_bdry_adj(c->dp, mu, dg, nrhs, static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return SMPM_OK;
+}
+
 int smpm_precond_apply(smpm_ctx* c, const double* x, double* y, int nrhs, int transpose, void* stream) {
   int rc = check_device(c);
   if (rc) return rc;
@@ -938,7 +949,8 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   if (o.precision < SMPM_FP64 || o.precision > SMPM_MIXED_BF16) return fail(SMPM_EINVAL, "unknown precision");
   if (o.precision != SMPM_FP64 && (!(o.inner_tol > 0) || o.inner_tol >= 1 || o.max_refine < 1))
     return fail(SMPM_EINVAL, "mixed precision needs 0 < inner_tol < 1 and max_refine >= 1");
-  if (o.transpose) return fail(SMPM_EINVAL, "adjoint solve not supported by this build");
+  const bool tr = o.transpose != 0;
+  if (tr && g) return fail(SMPM_EINVAL, "the adjoint solve takes no boundary data (g must be NULL)");
   if (o.variant == 3 && !c->plan.has_coarse)
     return fail(SMPM_EINVAL, "no coarse space on this grid (d > 4096): use variant 1 or 2");
   const Plan& Pl = c->plan;
@@ -951,15 +963,26 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   rc = ensure_ws(c, nrhs, o.maxit);
   if (rc) return rc;
   Workspace& W = c->ws;
-  // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
-  launch_rhs(P, f, g, W.rhs, nrhs, s);
-  launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
   std::vector<double> removed(nrhs);
-  HIPCHK(hipMemcpyAsync(removed.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-  launch_axpy_shared(W.rhs, Pl.r, c->uL, W.scal, 1.0, W.ft, Pl.r, nrhs, s);
-  launch_flux(P, W.ft, W.bS, nrhs, s);
-  launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
-  launch_axpy_shared(W.bS, Pl.k, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, s);
+  if (!tr) {
+    // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
+    launch_rhs(P, f, g, W.rhs, nrhs, s);
+    launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
+    HIPCHK(hipMemcpyAsync(removed.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    launch_axpy_shared(W.rhs, Pl.r, c->uL, W.scal, 1.0, W.ft, Pl.r, nrhs, s);
+    launch_flux(P, W.ft, W.bS, nrhs, s);
+    launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
+    launch_axpy_shared(W.bS, Pl.k, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, s);
+  } else {
+    // adjoint of the solution map: c~ = c - w (1^T c)/(w^T 1); S^T xi = E^T A^{-T} c~
+    // (consistent: v0^T E^T A^{-T} c~ = -1^T c~ = 0), projected off v0 against rounding
+    launch_mdot(c->ones, 0, 0, 1, f, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
+    HIPCHK(hipMemcpyAsync(removed.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    launch_axpy_shared(f, Pl.r, c->wq, W.scal, 1.0 / c->wsum, W.ft, Pl.r, nrhs, s);
+    launch_local_adj(P, W.ft, W.bS, nrhs, true, s);
+    launch_mdot(c->v0hat, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
+    launch_axpy_shared(W.bS, Pl.k, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, s);
+  }
   // steps 4-8
   std::vector<int> iters;
   const int kind = o.variant == 3 ? OP_PSM : o.variant == 2 ? OP_SM : OP_S;
@@ -969,9 +992,9 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   double* xsol = W.bS;
   if (o.precision == SMPM_FP64) {
     // x lands in W.bS (free after b_hat is formed)
-    rc = solve_schur(c, kind, false, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s);
+    rc = solve_schur(c, kind, tr, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s);
     if (rc < 0) return rc;
-    rc = true_residual(c, false, W.bhat, W.bS, nrhs, tres, s);
+    rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
     if (rc) return rc;
     for (int i = 0; i < nrhs; ++i)
       if (iters[i] >= o.maxit) conv = false;
@@ -994,7 +1017,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     conv = false;
     for (cycles = 0; cycles <= o.max_refine; ++cycles) {
       if (cycles > 0) {
-        launch_schur(P, W.xacc, W.t, nrhs, false, nullptr, s);
+        launch_schur(P, W.xacc, W.t, nrhs, tr, nullptr, s);
         launch_add(W.bhat, W.t, -1.0, W.rho, Pl.k, nrhs, s);
       }
       launch_mdot(W.rho, 0, Pl.k, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
@@ -1026,16 +1049,26 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       stall = slow ? stall + 1 : 0;
       if (stall >= 2 || cycles == o.max_refine) break;
       std::vector<int> it;
-      rc = solve_schur(c, kind, false, W.rho, W.bS, nrhs, o.inner_tol, o.maxit, it, s, sprec, mprec);
+      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, o.inner_tol, o.maxit, it, s, sprec, mprec);
       if (rc < 0) return rc;
       for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
       launch_add(W.xacc, W.bS, 1.0, W.xacc, Pl.k, nrhs, s);
     }
   }
-  // step 9 and the constant: u = A^{-1}(f~ - E x); u -= (w^T u / w^T 1)
-  launch_backsub(P, W.ft, xsol, u, nrhs, s);
-  launch_mdot(c->wq, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
-  launch_axpy_shared(u, Pl.r, c->ones, W.scal, 1.0 / c->wsum, u, Pl.r, nrhs, s);
+  if (!tr) {
+    // step 9 and the constant: u = A^{-1}(f~ - E x); u -= (w^T u / w^T 1)
+    launch_backsub(P, W.ft, xsol, u, nrhs, s);
+    launch_mdot(c->wq, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
+    launch_axpy_shared(u, Pl.r, c->ones, W.scal, 1.0 / c->wsum, u, Pl.r, nrhs, s);
+  } else {
+    // mu = A^{-T}(c~ - B^T xi), then the u_L component (null space of L^T) removed
+    launch_local_adj(P, W.ft, u, nrhs, false, s);
+    launch_flux_adj(P, xsol, W.rhs, nrhs, s);
+    launch_add(u, W.rhs, -1.0, u, Pl.r, nrhs, s);
+    launch_mdot(c->uL, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
+    launch_axpy_shared(u, Pl.r, c->uL, W.scal, 1.0, u, Pl.r, nrhs, s);
+    for (double& v : removed) v /= c->wsum;
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   int itmax = 0;

@@ -26,7 +26,8 @@ EXPORT_SCHUR, EXPORT_FLUX_SOLVE, EXPORT_PRECOND_INV, EXPORT_COARSE, EXPORT_COARS
 ABI_SYMBOLS = (
     "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_stats", "smpm_slot_map",
     "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
-    "smpm_schur_apply", "smpm_precond_apply", "smpm_project", "smpm_solve", "smpm_last_error",
+    "smpm_schur_apply", "smpm_precond_apply", "smpm_project", "smpm_solve", "smpm_boundary_transpose",
+    "smpm_last_error",
 )
 
 
@@ -83,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     lib.smpm_precond_apply.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp]
     lib.smpm_project.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
     lib.smpm_solve.argtypes = [vp, vp, vp, vp, C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+    lib.smpm_boundary_transpose.argtypes = [vp, vp, vp, C.c_int, vp]
     for name in ABI_SYMBOLS:
         if name not in ("smpm_destroy", "smpm_default_opts", "smpm_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -273,6 +275,8 @@ class Context:
         nrhs = f.shape[0]
         gp = None
         if g is not None:
+            if transpose:
+                raise ValueError("the adjoint solve takes no boundary data")
             g = self._as_cols(g, self.nbdry)
             if g.shape[0] != nrhs:
                 raise ValueError("g must have as many columns as f")
@@ -285,3 +289,56 @@ class Context:
         if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
             _check(rc)
         return u, Info(info.iterations, info.refinements, info.rel_residual, info.removed_component, rc)
+
+    def boundary_transpose(self, mu, stream=None):
+        """T^T mu: the gradient with respect to the Neumann data (columns of length
+        2n(m_x+m_y), edges south, north, west, east) given mu = dLoss/d(f + T g)."""
+        import torch
+        mu = self._as_cols(mu, self.r)
+        out = torch.empty(mu.shape[0], self.nbdry, dtype=torch.float64, device=mu.device)
+        _check(self._lib.smpm_boundary_transpose(self._h, C.c_void_p(mu.data_ptr()), C.c_void_p(out.data_ptr()),
+                                                 mu.shape[0], _stream(torch, stream)))
+        return out
+
+
+_SchurSolve = None
+
+
+def _schur_solve_function():
+    """torch.autograd.Function: forward u = solve(f, g); backward by the adjoint solve
+    (transpose = 1) giving dLoss/df = mu and dLoss/dg = T^T mu."""
+    global _SchurSolve
+    if _SchurSolve is not None:
+        return _SchurSolve
+    import torch
+
+    class SchurSolve(torch.autograd.Function):
+        @staticmethod
+        def forward(actx, solver, opts, f, g):
+            u, _ = solver.solve(f.detach(), None if g is None else g.detach(), **opts)
+            actx.solver, actx.opts = solver, opts
+            actx.f_shape = f.shape
+            actx.g_shape = None if g is None else g.shape
+            return u.reshape(f.shape)
+
+        @staticmethod
+        def backward(actx, gu):
+            mu, _ = actx.solver.solve(gu.detach().contiguous(), transpose=True, **actx.opts)
+            dg = None
+            if actx.g_shape is not None and actx.needs_input_grad[3]:
+                dg = actx.solver.boundary_transpose(mu).reshape(actx.g_shape)
+            df = mu.reshape(actx.f_shape) if actx.needs_input_grad[2] else None
+            return None, None, df, dg
+
+    _SchurSolve = SchurSolve
+    return SchurSolve
+
+
+def solve_differentiable(solver: "Context", f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64,
+                         inner_tol=1e-4, max_refine=20):
+    """u = solver.solve(f, g) as a differentiable torch operation: its backward pass is
+    the adjoint solve of the library (transposed Algorithm 3), so autograd gives
+    dLoss/df and dLoss/dg.  f: (r,) or (nrhs, r); g: None or matching (.., nbdry)."""
+    opts = dict(tol=tol, maxit=maxit, variant=variant, precision=precision, inner_tol=inner_tol,
+                max_refine=max_refine)
+    return _schur_solve_function().apply(solver, opts, f, g)
