@@ -138,7 +138,7 @@ def main():
                                "(20 modes, k<=8, seed 160103434), g=0, FP64, tol 1e-10",
                    "form": args.precision, "gmres_iterations": info.iterations,
                    "refinements": info.refinements, "true_rel_residual": info.rel_residual,
-                   "penalty": 32.0, "parallelism": "single GPU"},
+                   "penalty": smpm.DEFAULT_PENALTY, "parallelism": "single GPU"},
         "forms": {
             args.precision: {"solves_per_s": solves_per_s, "iterations": info.iterations,
                              "refinements": info.refinements, "true_rel_residual": info.rel_residual},

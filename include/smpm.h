@@ -31,11 +31,15 @@
  *   d-vectors (interfaces): vertical interfaces (between (iy,ix) and
  *     (iy,ix+1)) row-major, then horizontal ones (between (iy,ix), (iy+1,ix)).
  *
- * Penalty (Sec. 1.2 leaves its value open): tau = 2*penalty/(omega_0*h_perp)
- * on every element side, omega_0 = 2/(N(N+1)) the GLL end weight and h_perp
- * the element's extent normal to the side.  Recommended penalty: +32 (it gives the
- * fewest GMRES iterations among the values studied; any finite nonzero value
- * is accepted).
+ * Discretization (Sec. 1.2, Eq. smpm_poisson).  At the nodes of an element side
+ * the row of L adds tau (R u_i - R u_j) across an inter-element side and
+ * tau sigma n.grad u_i on a physical side (right-hand side tau sigma g), with
+ * the Robin operator R = I + sigma n_i.grad, sigma = h_e/2, tau = 2*penalty/
+ * (omega_0*h_e^2), omega_0 = 2/(N(N+1)) the GLL end weight and h_e the smaller
+ * extent of the element whose row it is (its values serve u_i and u_j alike;
+ * on a square element sigma n.grad is the normal derivative in the reference
+ * coordinates [-1,1]^2).  Sec. 1.2 leaves tau to a heuristic; recommended
+ * penalty: 8 (any finite nonzero value is accepted).
  *
  * Ownership and streams.  A context owns its setup data and device workspace;
  * smpm_destroy releases them.  The caller owns every vector argument.  Device
@@ -132,8 +136,13 @@ void smpm_default_opts(smpm_solve_opts *opts);
  * block-Jacobi inverses and the coarse matrix, all FP64 (Secs. 1.2-2).
  * x_breaks (m_x+1) and y_breaks (m_y+1) are host arrays of strictly increasing
  * element breakpoints.  Requires m_x*m_y >= 2, 3 <= n <= 32, penalty finite and
- * nonzero.  Grids with more than 4096 interfaces get no coarse space: the
- * deflated solve (variant 3) and the P/Q projections then return SMPM_EINVAL.
+ * nonzero.  The coarse solve with C = Z^T S Z is a dense G = C^+ for up to
+ * 4096 interfaces (environment SMPM_DENSE_COARSE_MAX overrides the limit);
+ * larger grids solve with C exactly by one level of substructuring: patches of
+ * 8 x 8 elements (SMPM_COARSE_PATCH overrides; doubled while the separator
+ * system would exceed 8192 unknowns), dense inverses of the patch-interior
+ * blocks and of the separator Schur complement (bordered by u_C and tau_hat
+ * when C is singular, which yields the Moore-Penrose inverse).
  * The context supports sizes/exports only; device calls on it return
  * SMPM_ENODEVICE.  *out is set only on success. */
 int smpm_plan(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,

@@ -29,9 +29,13 @@ Readings where the paper is silent or at odds with itself:
   sides owns two slots, one per side, each holding that side's flux.  E maps a
   slot to its node (so E^T E = I holds except between the two slots of such a
   corner node).
-* Penalty.  Sec. 1.2 leaves tau to a heuristic.  tau_{e,s} = 2 alpha /
-  (omega_0 h_perp) with omega_0 = 2/(N(N+1)) the GLL end weight and h_perp the
-  element's extent normal to side s; alpha = +32 on all sides by default (the
+* Robin operator and penalty.  Sec. 1.2 writes R_ij = I + n_i.grad and leaves
+  tau to a heuristic.  R = I + sigma n_i.grad with sigma = h_e/2 and
+  tau_e = 2 alpha / (omega_0 h_e^2), h_e the smaller extent of element i (the
+  element whose row it is; its sigma and tau serve u_i and u_j alike) and
+  omega_0 = 2/(N(N+1)) the GLL end weight.  On a square element sigma n.grad is
+  the normal derivative in the reference coordinates.  A physical side carries
+  tau sigma n.grad u and tau sigma g.  alpha = 8 on all sides by default (the
   oracle accepts any alpha_int / alpha_phys).
 * Element-corner nodes receive the penalty terms of both sides containing them.
 * Block-Jacobi blocks follow the checkerboard: the block of a "red" element
@@ -54,7 +58,7 @@ from numpy.polynomial import legendre as leg
 W, E, S, N = 0, 1, 2, 3
 SIDES = (W, E, S, N)
 OPPOSITE = {W: E, E: W, S: N, N: S}
-DEFAULT_ALPHA = 32.0
+DEFAULT_ALPHA = 8.0
 
 
 # ---------------------------------------------------------------------------
@@ -144,12 +148,22 @@ class Grid:
             return jy, jx
         return None
 
+    def elem_len(self, iy, ix):
+        """h_e: the smaller extent of element (iy, ix)."""
+        return min(self.width(ix), self.height(iy))
+
     def tau(self, iy, ix, side):
-        """Penalty of one side of one element (reading stated in the module header)."""
+        """Penalty of one side of one element: 2 alpha / (omega_0 h_e^2) (reading
+        stated in the module header)."""
         omega0 = 2.0 / (self.Np * (self.Np + 1))
-        hperp = self.width(ix) if side in (W, E) else self.height(iy)
         alpha = self.alpha_int if self.neighbor(iy, ix, side) is not None else self.alpha_phys
-        return 2.0 * alpha / (omega0 * hperp)
+        return 2.0 * alpha / (omega0 * self.elem_len(iy, ix) ** 2)
+
+    def sigma(self, iy, ix, side):
+        """Length scale of the Robin operator R = I + sigma n.grad on one side of
+        element (iy, ix): h_e / 2 (on a square element sigma n.grad is the normal
+        derivative in the element's reference coordinates)."""
+        return 0.5 * self.elem_len(iy, ix)
 
     def side_nodes(self, side):
         """Local indices (q*n + p) of a side's nodes, ordered along the side."""
@@ -257,32 +271,33 @@ def outward_derivative_rows(grid: Grid, side, w, h):
 def local_block(grid: Grid, iy, ix):
     """A_e: the part of Eq. smpm_poisson local to element (iy, ix) (Sec. 1.3).
 
-    Laplacian + tau (u + n.grad u) on every inter-element side (the R_ii term)
-    + tau n.grad u on every physical side; corner nodes get both sides' terms.
+    Laplacian + tau (u + sigma n.grad u) on every inter-element side (the R_ii
+    term) + tau sigma n.grad u on every physical side; corner nodes get both
+    sides' terms.
     """
     w, h = grid.width(ix), grid.height(iy)
     A = laplacian_block(grid, w, h)
     for s in SIDES:
         rows = grid.side_nodes(s)
-        tau = grid.tau(iy, ix, s)
+        tau, sig = grid.tau(iy, ix, s), grid.sigma(iy, ix, s)
         dn = outward_derivative_rows(grid, s, w, h)
         if grid.neighbor(iy, ix, s) is None:
-            A[rows, :] += tau * dn
+            A[rows, :] += tau * sig * dn
         else:
-            A[rows, :] += tau * (trace_rows(grid, s) + dn)
+            A[rows, :] += tau * (trace_rows(grid, s) + sig * dn)
     return A
 
 
 def flux_rows(grid: Grid, iy, ix, s):
     """The neighbour term of side s of element i=(iy,ix) in Eq. smpm_poisson:
-    -tau_{i,s} R_ij u_j = -tau_{i,s} (u_j + n_i.grad u_j) at the nodes of the
-    neighbour's facing side, as an n x n^2 matrix over the neighbour's nodes.
-    n_i = -n_j, so n_i.grad u_j = -(n_j.grad u_j)."""
+    -tau_{i,s} R_ij u_j = -tau_{i,s} (u_j + sigma_{i,s} n_i.grad u_j) at the nodes
+    of the neighbour's facing side, as an n x n^2 matrix over the neighbour's
+    nodes (element i's tau and sigma).  n_i = -n_j, so n_i.grad u_j = -(n_j.grad u_j)."""
     jy, jx = grid.neighbor(iy, ix, s)
     so = OPPOSITE[s]
-    tau = grid.tau(iy, ix, s)
+    tau, sig = grid.tau(iy, ix, s), grid.sigma(iy, ix, s)
     dn_nb = outward_derivative_rows(grid, so, grid.width(jx), grid.height(jy))
-    return -tau * (trace_rows(grid, so) - dn_nb)
+    return -tau * (trace_rows(grid, so) - sig * dn_nb)
 
 
 def element_rows(grid: Grid, iy, ix):
@@ -298,7 +313,8 @@ def element_rows(grid: Grid, iy, ix):
 
 
 def boundary_operator(grid: Grid):
-    """T (r x nbdry): rhs = f + T g, the tau_i g_i term of Eq. smpm_poisson."""
+    """T (r x nbdry): rhs = f + T g, the tau_i g_i term of Eq. smpm_poisson (its
+    coefficient is the physical side's tau sigma, that of n.grad u in the row)."""
     ti, tj, tv = [], [], []
     for iy in range(grid.m_y):
         for ix in range(grid.m_x):
@@ -306,11 +322,11 @@ def boundary_operator(grid: Grid):
             for s in SIDES:
                 if grid.neighbor(iy, ix, s) is not None:
                     continue
-                tau = grid.tau(iy, ix, s)
+                coef = grid.tau(iy, ix, s) * grid.sigma(iy, ix, s)
                 for t, l in enumerate(grid.side_nodes(s)):
                     ti.append(e * grid.n2 + int(l))
                     tj.append(grid.bdry_index(iy, ix, s, t))
-                    tv.append(tau)
+                    tv.append(coef)
     return sp.csr_matrix((np.array(tv), (np.array(ti, dtype=np.int64), np.array(tj, dtype=np.int64))),
                          shape=(grid.r, grid.nbdry))
 

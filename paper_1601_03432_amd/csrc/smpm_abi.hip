@@ -43,6 +43,7 @@ struct Workspace {
   // device-resident GMRES state
   double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr, *sides = nullptr;
   double *xacc = nullptr, *rho = nullptr;  // iterative refinement: solution and residual
+  double* cws = nullptr;                    // substructured coarse solve scratch
   double *beta_cur = nullptr, *beta0 = nullptr, *tolb = nullptr;
   int *iters = nullptr, *counter = nullptr;
   int* pinned = nullptr;  // 2 x nrhs host-visible activity flags
@@ -178,7 +179,14 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.tolb, R);
   rc |= ialloc(w.mem, &w.iters, R);
   rc |= ialloc(w.mem, &w.counter, 4 * R);
+  // scratch of the substructured coarse solve: [patch parts | separator rhs | lambda]
+  int64_t cstride = 0;
+  if (P.coarse_mode == 2)
+    cstride = (int64_t)P.sub.B.size() + (int64_t)P.sub.npatch * P.sub.border + P.sub.nsep + P.sub.border + 1;
+  rc |= dalloc(w.mem, &w.cws, (size_t)std::max<int64_t>(cstride, 1) * R);
   if (rc != SMPM_OK) return SMPM_ENOMEM;
+  c->dp.cws = w.cws;
+  c->dp.cws_stride = cstride;
   if (hipHostMalloc((void**)&w.pinned, 2 * R * sizeof(int), hipHostMallocDefault) != hipSuccess)
     return fail(SMPM_ENOMEM, "hipHostMalloc failed");
   for (int i = 0; i < 2; ++i)
@@ -533,10 +541,23 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
       }
     }
   std::vector<double> GT(p.G.size());
-  if (p.has_coarse)
+  if (p.coarse_mode == 1)
     for (int64_t i = 0; i < p.d; ++i)
       for (int64_t j = 0; j < p.d; ++j) GT[(size_t)j * p.d + i] = p.G[(size_t)i * p.d + j];
   d.has_coarse = p.has_coarse ? 1 : 0;
+  d.coarse_mode = p.coarse_mode;
+  {
+    const CoarseSub& q = p.sub;
+    d.sub_npatch = q.npatch;
+    d.sub_nsep = q.nsep;
+    d.sub_border = q.border;
+    int lmax = 1;
+    for (int pp = 0; pp < q.npatch; ++pp)
+      lmax = std::max({lmax, q.I_off[pp + 1] - q.I_off[pp], q.B_off[pp + 1] - q.B_off[pp] + q.border});
+    d.sub_lds_max = lmax;
+    d.cws = nullptr;
+    d.cws_stride = 0;
+  }
   // boundary data map: south, north, west, east
   std::vector<int> bnode;
   std::vector<double> btau;
@@ -551,10 +572,10 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
         else if (edge == 2) { e = q * p.mx; s2 = SW; }
         else { e = q * p.mx + p.mx - 1; s2 = SE; }
         const int ix = e % p.mx, iy = e / p.mx;
-        const double hp = (s2 == SW || s2 == SE) ? p.wx[ix] : p.hy[iy];
+        const double hp = std::min(p.wx[ix], p.hy[iy]);  // the element's smaller extent
         int l = s2 == SW ? t * n : s2 == SE ? t * n + n - 1 : s2 == SS ? t : (n - 1) * n + t;
         bnode.push_back(e * n * n + l);
-        btau.push_back(2.0 * p.alpha / (omega0 * hp));
+        btau.push_back(p.alpha / (omega0 * hp));  // tau sigma = (2 alpha/(omega0 h_e^2)) (h_e/2)
       }
   }
   int rc = SMPM_OK;
@@ -587,6 +608,22 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   rc |= upload(c, p.MinvR, &d.MinvR, s);
   rc |= upload(c, p.G, &d.G, s);
   rc |= upload(c, GT, &d.GT, s);
+  rc |= upload(c, p.sub.I_off, &d.sub_I_off, s);
+  rc |= upload(c, p.sub.I, &d.sub_I, s);
+  rc |= upload(c, p.sub.B_off, &d.sub_B_off, s);
+  rc |= upload(c, p.sub.B, &d.sub_B, s);
+  rc |= upload(c, p.sub.K_off, &d.sub_K_off, s);
+  rc |= upload(c, p.sub.FR_off, &d.sub_FR_off, s);
+  rc |= upload(c, p.sub.Kc, &d.sub_Kc, s);
+  rc |= upload(c, p.sub.Kr, &d.sub_Kr, s);
+  rc |= upload(c, p.sub.Fc, &d.sub_Fc, s);
+  rc |= upload(c, p.sub.Fr, &d.sub_Fr, s);
+  rc |= upload(c, p.sub.Rc, &d.sub_Rc, s);
+  rc |= upload(c, p.sub.Rr, &d.sub_Rr, s);
+  rc |= upload(c, p.sub.sep_iface, &d.sub_sep_iface, s);
+  rc |= upload(c, p.sub.sep_pl, &d.sub_sep_pl, s);
+  rc |= upload(c, p.sub.Si, &d.sub_Si, s);
+  rc |= upload(c, p.sub.SiT, &d.sub_SiT, s);
   rc |= upload(c, to_f32(p.Wc), &d.WcF, s);
   rc |= upload(c, to_f32(p.Wr), &d.WrF, s);
   rc |= upload(c, to_f32(p.MinvC), &d.MinvCF, s);
@@ -738,7 +775,11 @@ int smpm_stats(const smpm_ctx* c, smpm_plan_stats* o) {
   o->schur_operator_bytes = (int64_t)(p.Wc.size() * sizeof(double));
   o->precond_operator_bytes = (int64_t)(p.MinvC.size() * sizeof(double));
   o->flux_operator_bytes = (int64_t)(p.Hc.size() * sizeof(double));
-  o->coarse_bytes = (int64_t)(p.G.size() * sizeof(double));
+  // bytes one coarse solve reads: the dense G, or the patch matrices and S_B^{-1}
+  o->coarse_bytes = p.coarse_mode == 2
+                        ? (int64_t)((p.sub.Kc.size() + p.sub.Fc.size() + p.sub.Rc.size() + p.sub.Si.size()) *
+                                    sizeof(double))
+                        : (int64_t)(p.G.size() * sizeof(double));
   o->coarse_singular = p.coarse_singular ? 1 : 0;
   o->has_coarse = p.has_coarse ? 1 : 0;
   return SMPM_OK;
@@ -791,10 +832,30 @@ int smpm_export(const smpm_ctx* c, int what, int64_t* count, int64_t* rows, int6
   if (!c || !count) return fail(SMPM_EINVAL, "null argument");
   const Plan& p = c->plan;
   if (what == SMPM_EXPORT_COARSE || what == SMPM_EXPORT_COARSE_PINV) {
+    if (!p.has_coarse) return fail(SMPM_EINVAL, "no coarse space on this grid");
     *count = p.d * p.d;
-    if (vals) {
+    if (!vals) return SMPM_OK;
+    if (p.coarse_mode == 1) {
       const std::vector<double>& src = what == SMPM_EXPORT_COARSE ? p.C : p.G;
       std::copy(src.begin(), src.end(), vals);
+      return SMPM_OK;
+    }
+    // substructured mode: dense copies on request (d <= 8192)
+    if (p.d > 8192) return fail(SMPM_EINVAL, "dense coarse export limited to d <= 8192");
+    const int64_t d = p.d;
+    std::fill(vals, vals + d * d, 0.0);
+    if (what == SMPM_EXPORT_COARSE) {
+      for (int64_t i = 0; i < d; ++i)
+        for (int64_t z = p.C_off[i]; z < p.C_off[i + 1]; ++z) vals[i * d + p.C_col[z]] = p.C_val[z];
+      return SMPM_OK;
+    }
+    // G e_j column by column with the host substructured solve
+    std::vector<double> e(d, 0.0), col(d, 0.0);
+    for (int64_t j = 0; j < d; ++j) {
+      e[j] = 1.0;
+      sub_solve_host(p, e.data(), 0.0, col.data(), false);
+      e[j] = 0.0;
+      for (int64_t i = 0; i < d; ++i) vals[i * d + j] = col[i];
     }
     return SMPM_OK;
   }
@@ -876,7 +937,7 @@ int smpm_project(smpm_ctx* c, int which, const double* in, double* out, int nrhs
     if (rc) return rc;
   }
   if ((which == SMPM_PROJ_P || which == SMPM_PROJ_Q) && !c->plan.has_coarse)
-    return fail(SMPM_EINVAL, "no coarse space on this grid (d > 4096)");
+    return fail(SMPM_EINVAL, "no coarse space on this grid");
   switch (which) {
     case SMPM_PROJ_L: {
       const double* u = tr ? c->rhat : c->uL;
@@ -952,7 +1013,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   const bool tr = o.transpose != 0;
   if (tr && g) return fail(SMPM_EINVAL, "the adjoint solve takes no boundary data (g must be NULL)");
   if (o.variant == 3 && !c->plan.has_coarse)
-    return fail(SMPM_EINVAL, "no coarse space on this grid (d > 4096): use variant 1 or 2");
+    return fail(SMPM_EINVAL, "no coarse space on this grid: use variant 1 or 2");
   const Plan& Pl = c->plan;
   const DevPlan& P = c->dp;
   const size_t rb = sizeof(double) * Pl.r * nrhs;

@@ -369,7 +369,7 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool
     hipLaunchKernelGGL(k_gm_precond<bf16s>, pg, dim3(kThreads), 0, s, P, S, j, up, trn, 0);
   else
     hipLaunchKernelGGL(k_gm_precond<double>, pg, dim3(kThreads), 0, s, P, S, j, up, trn, 0);
-  const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P);
+  const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P) && P.coarse_mode == 1;
   launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s, sprec);
   if (kind == 3) {
     if (fused_sums) {

@@ -11,7 +11,8 @@ constexpr int kMaxN = 32;
 // Plain-old-data view of the device copy of a Plan; passed to kernels by value.
 struct DevPlan {
   int n, n2, nel, d, nblk, ncls, mx, my;
-  int has_coarse;          // 1 if G is built (deflation available)
+  int has_coarse;          // 1 if the coarse solve is built (deflation available)
+  int coarse_mode;         // 1: dense G, 2: substructured
   int64_t r, k, nsides, nbdry;
   const int* nbr;          // nel*4
   const int* cls;          // nel
@@ -42,6 +43,27 @@ struct DevPlan {
   const double* MinvR;     // [r][c]
   const double* G;         // d x d row-major
   const double* GT;        // its transpose
+  // substructured coarse solve (patch interiors + separator Schur complement)
+  int sub_npatch, sub_nsep, sub_border;
+  const int* sub_I_off;    // npatch+1
+  const int* sub_I;        // interior interfaces of each patch
+  const int* sub_B_off;    // npatch+1
+  const int* sub_B;        // separators touching each patch
+  const int64_t* sub_K_off;
+  const int64_t* sub_FR_off;
+  const double* sub_Kc;    // K_pp^{-1} column-major / row-major
+  const double* sub_Kr;
+  const double* sub_Fc;    // F_p = K_pp^{-1} K_{I,B}  (ni x nbb)
+  const double* sub_Fr;
+  const double* sub_Rc;    // R_p = K_{B,I} K_pp^{-1}  (nbb x ni)
+  const double* sub_Rr;
+  const int* sub_sep_iface;  // nsep
+  const int* sub_sep_pl;     // nsep*4: (patch, local) of both patches
+  const double* sub_Si;    // separator system inverse, row-major, and its transpose
+  const double* sub_SiT;
+  int sub_lds_max;         // max over patches of max(ni, nbb): LDS doubles of the patch kernels
+  double* cws;             // per-column scratch of the substructured solve
+  int64_t cws_stride;
   const int* bdry_node;    // nbdry
   const double* bdry_tau;  // nbdry
   // low-precision copies of the Schur side fluxes and block-Jacobi inverses
@@ -137,6 +159,7 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
                      const int* active, double* side_sums, hipStream_t s, int prec = PREC_F64);
 bool schur_has_side_sums(const DevPlan& P);
+
 // c2 = G c with c_j = side_sums of interface j's two sides
 void launch_coarse_sides(const DevPlan& P, const double* side_sums, double* c2, int nrhs, bool transpose,
                          const int* active, hipStream_t s);

@@ -553,6 +553,115 @@ __global__ __launch_bounds__(256) void k_coarse(DevPlan P, const double* __restr
   if (lane == 0) c2[(int64_t)col * d + i] = acc;
 }
 
+// ---- substructured coarse solve: per-column scratch = [patch parts | r | lambda]
+
+__device__ __forceinline__ int64_t sub_part_len(const DevPlan& P) {
+  return P.sub_B_off[P.sub_npatch] + (int64_t)P.sub_npatch * P.sub_border;
+}
+
+// y_p = K_pp^{-1} c_p into c2 (interior interfaces); q_p = R_p c_p (transpose:
+// K_pp^{-T} c_p and F_p^T c_p) into the patch's part of the scratch.
+__global__ __launch_bounds__(256) void k_sub_patch1(DevPlan P, const double* __restrict__ c, double* __restrict__ c2,
+                                                    int transpose, const int* __restrict__ active) {
+  extern __shared__ double cl[];
+  const int pp = blockIdx.x, col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int i0 = P.sub_I_off[pp], ni = P.sub_I_off[pp + 1] - i0;
+  const int nb = P.sub_B_off[pp + 1] - P.sub_B_off[pp], nbb = nb + P.sub_border;
+  const double* cc = c + (int64_t)col * P.d;
+  for (int j = threadIdx.x; j < ni; j += blockDim.x) cl[j] = cc[P.sub_I[i0 + j]];
+  __syncthreads();
+  const double* K = (transpose ? P.sub_Kr : P.sub_Kc) + P.sub_K_off[pp];
+  const double* M = (transpose ? P.sub_Fr : P.sub_Rc) + P.sub_FR_off[pp];
+  double* part = P.cws + (int64_t)col * P.cws_stride + P.sub_B_off[pp] + (int64_t)pp * P.sub_border;
+  for (int row = threadIdx.x; row < ni + nbb; row += blockDim.x) {
+    double acc = 0.0;
+    if (row < ni) {
+      for (int j = 0; j < ni; ++j) acc = fma(K[(int64_t)j * ni + row], cl[j], acc);
+      c2[(int64_t)col * P.d + P.sub_I[i0 + row]] = acc;
+    } else {
+      const int l = row - ni;
+      for (int j = 0; j < ni; ++j) acc = fma(M[(int64_t)j * nbb + l], cl[j], acc);
+      part[l] = acc;
+    }
+  }
+}
+
+// r = c_B - (parts of the two patches of each separator); r_lambda = -(sum of the patches'
+// lambda parts, in patch order)
+__global__ __launch_bounds__(256) void k_sub_rhs(DevPlan P, const double* __restrict__ c,
+                                                 const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nS = P.sub_nsep + P.sub_border;
+  if (b >= nS) return;
+  const double* ws = P.cws + (int64_t)col * P.cws_stride;
+  double* r = P.cws + (int64_t)col * P.cws_stride + sub_part_len(P);
+  if (b < P.sub_nsep) {
+    const int* pl = P.sub_sep_pl + (int64_t)b * 4;
+    const double qa = ws[P.sub_B_off[pl[0]] + (int64_t)pl[0] * P.sub_border + pl[1]];
+    const double qb = ws[P.sub_B_off[pl[2]] + (int64_t)pl[2] * P.sub_border + pl[3]];
+    r[b] = c[(int64_t)col * P.d + P.sub_sep_iface[b]] - qa - qb;
+  } else {
+    double acc = 0.0;
+    for (int pp = 0; pp < P.sub_npatch; ++pp)
+      acc += ws[P.sub_B_off[pp + 1] + (int64_t)pp * P.sub_border];  // lambda part = last of the patch
+    r[b] = -acc;
+  }
+}
+
+// x_B = S_B^{-1} r (transpose: S_B^{-T} r): wave per row, r staged in LDS.
+__global__ __launch_bounds__(256) void k_sub_sep(DevPlan P, double* __restrict__ c2, int transpose,
+                                                 const int* __restrict__ active) {
+  extern __shared__ double rl[];
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int nS = P.sub_nsep + P.sub_border;
+  double* ws = P.cws + (int64_t)col * P.cws_stride;
+  const double* r = ws + sub_part_len(P);
+  for (int j = threadIdx.x; j < nS; j += blockDim.x) rl[j] = r[j];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double* Si = transpose ? P.sub_SiT : P.sub_Si;
+  for (int q = 0; q < 4; ++q) {
+    const int a = (blockIdx.x * 4 + wave) * 4 + q;
+    if (a >= nS) break;
+    const double* row = Si + (int64_t)a * nS;
+    double acc = 0.0;
+    for (int j = lane; j < nS; j += 64) acc = fma(row[j], rl[j], acc);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) {
+      if (a < P.sub_nsep)
+        c2[(int64_t)col * P.d + P.sub_sep_iface[a]] = acc;
+      else
+        ws[sub_part_len(P) + nS] = acc;  // lambda
+    }
+  }
+}
+
+// x_p = y_p - F_p [x_B; lambda] (transpose: - R_p^T [x_B; lambda]) over the interior.
+__global__ __launch_bounds__(256) void k_sub_patch2(DevPlan P, double* __restrict__ c2, int transpose,
+                                                    const int* __restrict__ active) {
+  extern __shared__ double xl[];
+  const int pp = blockIdx.x, col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int i0 = P.sub_I_off[pp], ni = P.sub_I_off[pp + 1] - i0;
+  const int b0 = P.sub_B_off[pp], nb = P.sub_B_off[pp + 1] - b0, nbb = nb + P.sub_border;
+  double* cc = c2 + (int64_t)col * P.d;
+  const double* ws = P.cws + (int64_t)col * P.cws_stride;
+  for (int l = threadIdx.x; l < nbb; l += blockDim.x)
+    xl[l] = l < nb ? cc[P.sub_sep_iface[P.sub_B[b0 + l]]]
+                   : ws[sub_part_len(P) + P.sub_nsep + P.sub_border];
+  __syncthreads();
+  const double* M = (transpose ? P.sub_Rr : P.sub_Fc) + P.sub_FR_off[pp];
+  for (int row = threadIdx.x; row < ni; row += blockDim.x) {
+    double acc = cc[P.sub_I[i0 + row]];
+    for (int l = 0; l < nbb; ++l) acc = fma(-M[(int64_t)l * ni + row], xl[l], acc);
+    cc[P.sub_I[i0 + row]] = acc;
+  }
+}
+
 // c2 = G c with c_j = side_sums[a_j] + side_sums[b_j] (the two sides of interface j).
 __global__ __launch_bounds__(256) void k_coarse_sides(DevPlan P, const double* __restrict__ ss,
                                                       double* __restrict__ c2, int transpose,
@@ -771,6 +880,8 @@ inline dim3 grid1(int64_t len, int bs, int ny = 1) { return dim3((unsigned)((len
 
 // ------------------------------------------------------------------ launchers
 
+size_t sub_patch_lds(const DevPlan& P) { return (size_t)P.sub_lds_max * sizeof(double); }
+
 bool schur_has_side_sums(const DevPlan& P) { return 4 * P.n <= 64; }
 
 void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
@@ -884,12 +995,26 @@ void launch_iface_sum(const DevPlan& P, const double* t, double* c, int nrhs, co
 void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool transpose, const int* active,
                    hipStream_t s) {
   if (P.d == 0 || !P.has_coarse) return;
-  hipLaunchKernelGGL(k_coarse, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, c, c2, transpose ? 1 : 0, active);
+  const int tr = transpose ? 1 : 0;
+  if (P.coarse_mode == 2) {
+    const int nS = P.sub_nsep + P.sub_border;
+    hipLaunchKernelGGL(k_sub_patch1, dim3(P.sub_npatch, nrhs), dim3(256), sub_patch_lds(P), s, P, c, c2, tr,
+                       active);
+    if (nS > 0) {
+      hipLaunchKernelGGL(k_sub_rhs, dim3((nS + 255) / 256, nrhs), dim3(256), 0, s, P, c, active);
+      hipLaunchKernelGGL(k_sub_sep, dim3((nS + 15) / 16, nrhs), dim3(256), (size_t)nS * sizeof(double), s, P, c2,
+                         tr, active);
+      hipLaunchKernelGGL(k_sub_patch2, dim3(P.sub_npatch, nrhs), dim3(256), sub_patch_lds(P), s, P, c2, tr,
+                         active);
+    }
+    return;
+  }
+  hipLaunchKernelGGL(k_coarse, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, c, c2, tr, active);
 }
 
 void launch_coarse_sides(const DevPlan& P, const double* side_sums, double* c2, int nrhs, bool transpose,
                          const int* active, hipStream_t s) {
-  if (P.d == 0 || !P.has_coarse) return;
+  if (P.d == 0 || !P.has_coarse || P.coarse_mode != 1) return;
   hipLaunchKernelGGL(k_coarse_sides, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, side_sums, c2, transpose ? 1 : 0,
                      active);
 }

@@ -1,12 +1,14 @@
 // Host FP64 setup of the SMPM Schur complement solver.
 //
 // Discretization (Sec. 1.2, Eq. smpm_poisson): on each element the collocated
-// Laplacian plus, at the nodes of each side, tau (u + n.grad u) - tau (u_j +
-// n.grad u_j) across an inter-element side, or tau n.grad u on a physical side.
+// Laplacian plus, at the nodes of each side, tau (u + sigma n.grad u) - tau (u_j +
+// sigma n.grad u_j) across an inter-element side, or tau sigma n.grad u on a
+// physical side; sigma = h_e/2 and tau = 2 alpha / (omega_0 h_e^2) with h_e the
+// element's smaller extent (receiving element's values for both u_i and u_j).
 // Split (Sec. 1.3): A = the element-local part, B = the neighbour flux of each
 // side slot, E = slot -> node inclusion, S = I + B A^{-1} E.  Each distinct
 // element class stores A^{-1} and the outgoing side fluxes W = R A^{-1} E
-// (R = -tau_recv (trace - n_own.grad)) used by the Schur apply.
+// (R = -tau_recv (trace - sigma_recv n_own.grad)) used by the Schur apply.
 #include "smpm_plan.h"
 
 #include <algorithm>
@@ -19,7 +21,7 @@ namespace smpm {
 
 // ---------------------------------------------------------------- dense LU
 
-bool lu_factor(std::vector<double>& a, int m, std::vector<int>& piv) {
+bool lu_factor(std::vector<double>& a, int m, std::vector<int>& piv, double min_pivot) {
   piv.assign(m, 0);
   for (int k = 0; k < m; ++k) {
     int p = k;
@@ -29,7 +31,7 @@ bool lu_factor(std::vector<double>& a, int m, std::vector<int>& piv) {
       if (v > best) { best = v; p = i; }
     }
     piv[k] = p;
-    if (!(best > 0.0) || !std::isfinite(best)) return false;
+    if (!(best > min_pivot) || !std::isfinite(best)) return false;
     if (p != k)
       for (int j = 0; j < m; ++j) std::swap(a[(size_t)k * m + j], a[(size_t)p * m + j]);
     const double inv = 1.0 / a[(size_t)k * m + k];
@@ -61,10 +63,12 @@ void lu_solve(const std::vector<double>& a, int m, const std::vector<int>& piv, 
   }
 }
 
-bool dense_inverse(const std::vector<double>& a_in, int m, std::vector<double>& inv) {
+bool dense_inverse(const std::vector<double>& a_in, int m, std::vector<double>& inv, double min_rel_pivot) {
   std::vector<double> a = a_in;
   std::vector<int> piv;
-  if (!lu_factor(a, m, piv)) return false;
+  double amax = 0.0;
+  for (double v : a) amax = std::max(amax, std::fabs(v));
+  if (!lu_factor(a, m, piv, min_rel_pivot * amax)) return false;
   inv.assign((size_t)m * m, 0.0);
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if ((int64_t)m * m * m < (int64_t)1 << 24) nth = 1;
@@ -234,11 +238,11 @@ static std::vector<double> local_matrix(const Plan& p, const ElementClass& c) {
   std::vector<double> val;
   for (int s = 0; s < 4; ++s) {
     const bool inter = (c.mask >> s) & 1;
-    const double tau = c.tau_own[s];
+    const double tau = c.tau_own[s], tsig = c.tau_own[s] * c.sig_own[s];
     for (int t = 0; t < n; ++t) {
       const int l = side_node(n, s, t);
       outward_derivative(p, c.w, c.h, s, t, col, val);
-      for (int a = 0; a < n; ++a) A[(size_t)l * n2 + col[a]] += tau * val[a];
+      for (int a = 0; a < n; ++a) A[(size_t)l * n2 + col[a]] += tsig * val[a];
       if (inter) A[(size_t)l * n2 + l] += tau;
     }
   }
@@ -342,12 +346,16 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
     }
   p.d = d;
 
-  // penalty of each element side: tau = 2 alpha / (omega_0 h_perp)
-  auto tau_of = [&](int e, int s) {
-    const int ix = e % m_x, iy = e / m_x;
-    const double hp = (s == SW || s == SE) ? p.wx[ix] : p.hy[iy];
-    return 2.0 * alpha / (omega0 * hp);
+  // penalty of an element's sides, tau = 2 alpha / (omega_0 h_e^2), and the length
+  // scale of its Robin operator R = I + sigma n.grad, sigma = h_e / 2, with h_e the
+  // element's smaller extent (on a square element sigma n.grad is the normal
+  // derivative in reference coordinates)
+  auto elem_len = [&](int e) { return std::min(p.wx[e % m_x], p.hy[e / m_x]); };
+  auto tau_of = [&](int e, int) {
+    const double he = elem_len(e);
+    return 2.0 * alpha / (omega0 * he * he);
   };
+  auto sig_of = [&](int e, int) { return 0.5 * elem_len(e); };
 
   // element classes
   std::map<std::tuple<double, double, int, double, double, double, double>, int> key2cls;
@@ -360,8 +368,10 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
     c.mask = p.mask[e];
     for (int s = 0; s < 4; ++s) {
       c.tau_own[s] = tau_of(e, s);
+      c.sig_own[s] = sig_of(e, s);
       const int j = p.nbr[(size_t)e * 4 + s];
       c.tau_recv[s] = j >= 0 ? tau_of(j, opposite(s)) : 0.0;
+      c.sig_recv[s] = j >= 0 ? sig_of(j, opposite(s)) : 0.0;
     }
     auto key = std::make_tuple(c.w, c.h, c.mask, c.tau_recv[0], c.tau_recv[1], c.tau_recv[2],
                                c.tau_recv[3]);
@@ -446,13 +456,13 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
         }
     for (int so = 0; so < 4; ++so) {
       if (!((c.mask >> so) & 1)) continue;
-      // R = -tau_recv (trace - n_own.grad) at the nodes of side so; H = R A^{-1}
+      // R = -tau_recv (trace - sigma_recv n_own.grad) at the nodes of side so; H = R A^{-1}
       std::vector<double> H((size_t)n * n2, 0.0);
       for (int i = 0; i < n; ++i) {
         std::vector<double> row(n2, 0.0);
         row[side_node(n, so, i)] += -c.tau_recv[so];
         outward_derivative(p, c.w, c.h, so, i, col, val);
-        for (int a = 0; a < n; ++a) row[col[a]] += c.tau_recv[so] * val[a];
+        for (int a = 0; a < n; ++a) row[col[a]] += c.tau_recv[so] * c.sig_recv[so] * val[a];
         for (int l = 0; l < n2; ++l) {
           double acc = 0;
           for (int m = 0; m < n2; ++m) acc += row[m] * Ai[(size_t)m * n2 + l];
@@ -598,27 +608,8 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
       }
   }
 
-  // coarse matrix C = Z^T S Z (dense) and its (pseudo-)inverse
-  // (the dense coarse solve is built for d <= 4096; larger grids get no deflation)
-  if (d > 4096) return "";
-  p.has_coarse = true;
-  p.C.assign((size_t)d * d, 0.0);
-  for (int64_t i = 0; i < d; ++i) {
-    p.C[(size_t)i * d + i] += 2.0 * n;
-    for (int h = 0; h < 2; ++h) {
-      const int si = p.iface_side[(size_t)i * 2 + h];
-      const int e = p.side_elem[si], s = p.side_dir[si];
-      const int J = p.nbr[(size_t)e * 4 + s], so = opposite(s);
-      const int cJ = p.cls[J];
-      for (int s2 = 0; s2 < 4; ++s2) {
-        const int j2 = p.iface[(size_t)J * 4 + s2];
-        if (j2 < 0) continue;
-        double sum = 0;
-        for (int t = 0; t < n; ++t) sum += p.WZ[(((size_t)cJ * 4 + so) * n + t) * 4 + s2];
-        p.C[(size_t)i * d + j2] += sum;
-      }
-    }
-  }
+  // coarse matrix C = Z^T S Z (sparse rows) and its (pseudo-)inverse
+  build_coarse_rows(p, p.C_off, p.C_col, p.C_val);
   bool singular = true;
   p.tau_hat.assign(d, 0.0);
   for (int64_t i = 0; i < d; ++i) {
@@ -629,11 +620,23 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
     p.tau_hat[i] = ta;
   }
   p.coarse_singular = singular;
-  if (singular) {
-    if (!bordered_pinv(p.C, (int)d, p.tau_hat, p.G, p.uC)) return "coarse bordered system singular";
+  p.has_coarse = true;
+  if (d <= dense_coarse_limit()) {
+    p.coarse_mode = 1;
+    p.C.assign((size_t)d * d, 0.0);
+    for (int64_t i = 0; i < d; ++i)
+      for (int64_t z = p.C_off[i]; z < p.C_off[i + 1]; ++z) p.C[(size_t)i * d + p.C_col[z]] = p.C_val[z];
+    if (singular) {
+      if (!bordered_pinv(p.C, (int)d, p.tau_hat, p.G, p.uC)) return "coarse bordered system singular";
+    } else {
+      p.tau_hat.clear();
+      if (!dense_inverse(p.C, (int)d, p.G)) return "coarse matrix singular";
+    }
   } else {
-    p.tau_hat.clear();
-    if (!dense_inverse(p.C, (int)d, p.G)) return "coarse matrix singular";
+    p.coarse_mode = 2;
+    const std::string err = build_coarse_sub(p, p.C_off, p.C_col, p.C_val);
+    if (!err.empty()) return err;
+    if (!singular) p.tau_hat.clear();
   }
   (void)N;
   return "";

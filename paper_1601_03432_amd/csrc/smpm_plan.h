@@ -24,8 +24,28 @@ struct ElementClass {
   int mask = 0;            // bit s set: side s is an inter-element side
   double tau_own[4] = {0, 0, 0, 0};   // penalty of this element's sides
   double tau_recv[4] = {0, 0, 0, 0};  // penalty of the neighbour side facing side s
+  double sig_own[4] = {0, 0, 0, 0};   // Robin length scale h_e/2 of this element's sides
+  double sig_recv[4] = {0, 0, 0, 0};  // ... of the neighbour side facing side s
   int nslots = 0;          // slots owned by an element of this class
   int side_col[4] = {-1, -1, -1, -1};  // first slot column of side s within the element
+};
+
+// Substructured coarse solve (grids with many interfaces): patch-interior inverses and
+// the dense separator Schur complement.  All matrices FP64; *_r row-major, *_c
+// column-major copies of the same matrices.
+struct CoarseSub {
+  int P = 0;                         // patch size in elements
+  int npatch = 0, nsep = 0;
+  int border = 0;                    // 1 if C is singular: the bordered unknown lambda
+  std::vector<int> role;             // d: local interior index (>= 0) or -(separator + 1)
+  std::vector<int> I_off, I;         // interior interfaces of each patch
+  std::vector<int> B_off, B;         // separators touching each patch (lambda implied last)
+  std::vector<int64_t> K_off;        // offsets of K_pp^{-1} (ni x ni)
+  std::vector<int64_t> FR_off;       // offsets of F_p (ni x nbb) and R_p (nbb x ni)
+  std::vector<double> Kr, Kc, Fr, Fc, Rr, Rc;
+  std::vector<int> sep_iface;        // nsep: interface of each separator
+  std::vector<int> sep_pl;           // nsep*4: (patch, local index) for both patches
+  std::vector<double> Si, SiT;       // (nsep+border)^2 row-major: S_B^{-1} and its transpose
 };
 
 struct Plan {
@@ -82,9 +102,14 @@ struct Plan {
   std::vector<double> MinvC;         // [c][r] per block class
   std::vector<double> MinvR;         // [r][c] per block class
   // coarse space
-  bool has_coarse = false;           // dense coarse solve built (d <= 4096)
+  bool has_coarse = false;           // coarse solve built (deflation available)
+  int coarse_mode = 0;               // 1: dense G, 2: substructured
   bool coarse_singular = false;
-  std::vector<double> C, G;          // d x d row-major
+  std::vector<double> C, G;          // d x d row-major (dense mode)
+  std::vector<int64_t> C_off;        // sparse C rows (both modes)
+  std::vector<int> C_col;
+  std::vector<double> C_val;
+  CoarseSub sub;                     // substructured mode
   std::vector<double> tau_hat, uC;   // right / left null vectors of C when singular
   // v0 = B 1, the right null vector of S
   std::vector<double> v0;
@@ -102,9 +127,21 @@ void export_flux_solve_coo(const Plan& p, std::vector<int64_t>& ri, std::vector<
 void export_precond_inv_coo(const Plan& p, std::vector<int64_t>& ri, std::vector<int64_t>& ci,
                             std::vector<double>& v);
 
-// Dense LU with partial pivoting (row-major, in place).  Returns false if singular.
-bool lu_factor(std::vector<double>& a, int m, std::vector<int>& piv);
+// Coarse solve helpers (smpm_coarse.cpp).  Grids with more interfaces than
+// dense_coarse_limit() (default 4096, environment SMPM_DENSE_COARSE_MAX) use the
+// substructured solve with patches of SMPM_COARSE_PATCH (default 8) elements a side.
+int dense_coarse_limit();
+void build_coarse_rows(const Plan& p, std::vector<int64_t>& row_off, std::vector<int>& cols,
+                       std::vector<double>& vals);
+std::string build_coarse_sub(Plan& p, const std::vector<int64_t>& row_off, const std::vector<int>& cols,
+                             const std::vector<double>& vals);
+double sub_solve_host(const Plan& p, const double* c, double c_lambda, double* x, bool tr);
+
+// Dense LU with partial pivoting (row-major, in place).  Returns false if a pivot is
+// not above min_pivot (singular).  dense_inverse rejects pivots at or below
+// min_rel_pivot times the largest entry.
+bool lu_factor(std::vector<double>& a, int m, std::vector<int>& piv, double min_pivot = 0.0);
 void lu_solve(const std::vector<double>& a, int m, const std::vector<int>& piv, double* b);
-bool dense_inverse(const std::vector<double>& a, int m, std::vector<double>& inv);
+bool dense_inverse(const std::vector<double>& a, int m, std::vector<double>& inv, double min_rel_pivot = 0.0);
 
 }  // namespace smpm

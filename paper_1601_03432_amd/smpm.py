@@ -23,6 +23,9 @@ PROJ_L, PROJ_S, PROJ_P, PROJ_Q, PROJ_MEAN = 0, 1, 2, 3, 4
 EXPORT_SCHUR, EXPORT_FLUX_SOLVE, EXPORT_PRECOND_INV, EXPORT_COARSE, EXPORT_COARSE_PINV = 0, 1, 2, 3, 4
 
 # every symbol include/smpm.h declares
+# recommended penalty alpha: tau = 2 alpha / (omega_0 h_perp^2)
+DEFAULT_PENALTY = 8.0
+
 ABI_SYMBOLS = (
     "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_stats", "smpm_slot_map",
     "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
@@ -127,7 +130,7 @@ class Context:
     it and computes the null vectors on the current GPU (smpm_setup).
     """
 
-    def __init__(self, m_y, m_x, n, x_breaks, y_breaks, penalty=32.0, device=True, stream=None):
+    def __init__(self, m_y, m_x, n, x_breaks, y_breaks, penalty=DEFAULT_PENALTY, device=True, stream=None):
         lib = load_library()
         xb = np.ascontiguousarray(x_breaks, np.float64)
         yb = np.ascontiguousarray(y_breaks, np.float64)
@@ -151,7 +154,7 @@ class Context:
         self.nbdry = 2 * n * (m_x + m_y)
 
     @classmethod
-    def from_workload(cls, w, penalty=32.0, device=True):
+    def from_workload(cls, w, penalty=DEFAULT_PENALTY, device=True):
         return cls(w.m_y, w.m_x, w.n, w.x_breaks, w.y_breaks, penalty, device)
 
     def close(self):

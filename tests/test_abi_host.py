@@ -36,9 +36,9 @@ def test_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("args", [
-    (1, 1, 5, [0, 1], [0, 1], 32.0),          # one element: no interface
-    (2, 2, 2, [0, .5, 1], [0, .5, 1], 32.0),  # n < 3
-    (2, 2, 5, [0, .5, .4], [0, .5, 1], 32.0),  # non-increasing breaks
+    (1, 1, 5, [0, 1], [0, 1], 8.0),          # one element: no interface
+    (2, 2, 2, [0, .5, 1], [0, .5, 1], O.DEFAULT_ALPHA),  # n < 3
+    (2, 2, 5, [0, .5, .4], [0, .5, 1], O.DEFAULT_ALPHA),  # non-increasing breaks
     (2, 2, 5, [0, .5, 1], [0, .5, 1], 0.0),     # zero penalty
 ])
 def test_plan_rejects_bad_input(args):
@@ -70,7 +70,7 @@ def test_setup_operators_match_oracle(name):
     _lib()
     n, xb, yb = GRIDS[name]()
     xb, yb = np.asarray(xb, float), np.asarray(yb, float)
-    ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, 32.0, device=False)
+    ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, O.DEFAULT_ALPHA, device=False)
     g = O.Grid(n, xb, yb)
     m = O.Method(g)
     assert (ctx.r, ctx.k, ctx.d) == (g.r, m.split.k, m.defl.d)
@@ -102,7 +102,25 @@ def test_stretched_grid_has_nonsingular_coarse_matrix():
     _lib()
     xb = np.array([0.0, 0.1, 0.25, 0.5, 1.0])
     yb = np.array([0.0, 0.3, 0.6, 1.0])
-    ctx = smpm.Context(3, 4, 6, xb, yb, 32.0, device=False)
+    ctx = smpm.Context(3, 4, 6, xb, yb, O.DEFAULT_ALPHA, device=False)
     Cl = ctx.export(smpm.EXPORT_COARSE)
     Gl = ctx.export(smpm.EXPORT_COARSE_PINV)
     assert np.abs(Cl @ Gl - np.eye(ctx.d)).max() < 1e-9
+
+
+@pytest.mark.parametrize("name", sorted(GRIDS))
+@pytest.mark.parametrize("patch", [1, 2, 3])
+def test_substructured_coarse_matches_oracle(name, patch, monkeypatch):
+    """The substructured coarse solve (forced on small grids; patch 1 makes every
+    interface a separator) reproduces C^+ (C^{-1} when nonsingular) column by column."""
+    _lib()
+    monkeypatch.setenv("SMPM_DENSE_COARSE_MAX", "0")
+    monkeypatch.setenv("SMPM_COARSE_PATCH", str(patch))
+    n, xb, yb = GRIDS[name]()
+    xb, yb = np.asarray(xb, float), np.asarray(yb, float)
+    ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, O.DEFAULT_ALPHA, device=False)
+    m = O.Method(O.Grid(n, xb, yb))
+    Cl = ctx.export(smpm.EXPORT_COARSE)
+    Gl = ctx.export(smpm.EXPORT_COARSE_PINV)
+    assert np.abs(Cl - m.defl.C).max() <= 1e-11 * max(1.0, np.abs(m.defl.C).max())
+    assert np.abs(Gl - m.defl.G).max() <= 1e-9 * max(1e-300, np.abs(m.defl.G).max()) + 1e-14

@@ -36,7 +36,7 @@ def setup(name):
     if name not in _cache:
         n, xb, yb = GRIDS[name]
         print(f"[gpu-adjoint] setup {name}", flush=True)
-        ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, 32.0, device=True)
+        ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, O.DEFAULT_ALPHA, device=True)
         _cache[name] = (ctx, O.Split(O.Grid(n, xb, yb)))
     return _cache[name]
 
@@ -118,7 +118,7 @@ def test_central_differences_32x32_n10():
     """The differentiation workload: 32 x 32 elements, n = 10 on [0,1]^2, FP64; 50
     seeded unit directions in (f, g), h = 1e-6, against the adjoint gradient."""
     n, m = 10, 32
-    ctx = smpm.Context(m, m, n, wl.uniform_breaks(m), wl.uniform_breaks(m), 32.0)
+    ctx = smpm.Context(m, m, n, wl.uniform_breaks(m), wl.uniform_breaks(m), O.DEFAULT_ALPHA)
     x, y = ctx.node_coords()
     f = wl.eval_fourier(wl.random_fourier_params(wl.SEED_BASE + 40, 20, 8), x, y, 1.0, 1.0)
     gb = wl.eval_edge(wl.random_edge_params(wl.SEED_BASE + 41), *ctx.boundary_arc(), 1.0, 1.0)

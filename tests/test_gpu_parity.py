@@ -34,7 +34,7 @@ def setup(name):
     if name not in _cache:
         n, xb, yb = GRIDS[name]
         print(f"[gpu-parity] setup {name} n={n} m_x={len(xb) - 1} m_y={len(yb) - 1}", flush=True)
-        ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, 32.0, device=True)
+        ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, O.DEFAULT_ALPHA, device=True)
         m = O.Method(O.Grid(n, xb, yb))
         _cache[name] = (ctx, m)
     return _cache[name]

@@ -19,11 +19,11 @@ def grid(m_x, m_y, n, Lx=1.0, Ly=1.0, **kw):
 
 # ---------------------------------------------------------------- operator L
 
-@pytest.mark.parametrize("alpha", [32.0, -32.0, -0.5, 3.0])
+@pytest.mark.parametrize("alpha", [8.0, -8.0, -1.0, 3.0])
 def test_polynomial_exactness(alpha):
     """For a global polynomial of degree <= N per variable the interface jumps vanish,
     so L p = lap p at every node not on the physical boundary, and
-    lap p + tau dp/dn there (Eq. smpm_poisson)."""
+    lap p + tau sigma dp/dn there (Eq. smpm_poisson)."""
     g = O.Grid(6, [0.0, 0.3, 1.0, 1.2], [0.0, 0.5, 1.1], alpha_int=alpha, alpha_phys=alpha)
     L, _ = O.assemble(g)
     x, y = g.node_coords()
@@ -39,11 +39,11 @@ def test_polynomial_exactness(alpha):
             for s in O.SIDES:
                 if g.neighbor(iy, ix, s) is not None:
                     continue
-                tau = g.tau(iy, ix, s)
+                coef = g.tau(iy, ix, s) * g.sigma(iy, ix, s)
                 for l in g.side_nodes(s):
                     i = e * g.n2 + l
                     dn = {O.W: -px[i], O.E: px[i], O.S: -py[i], O.N: py[i]}[s]
-                    want[i] += tau * dn
+                    want[i] += coef * dn
     got = L @ p
     assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
 
@@ -60,11 +60,14 @@ def test_constant_right_null_space_and_rank(dims):
     assert sv[-2] >= 1e-9 * sv[0]
 
 
-def test_conservation_at_half_penalty():
-    """With alpha = -1/2 on interfaces and -1 on physical sides, GLL summation by parts
-    makes the weighted column sums vanish: w^T L = 0.  This pins the tau scaling
-    (omega_0, h_perp) and the corner treatment independently of the default penalty."""
-    g = O.Grid(7, [0.0, 0.4, 1.0, 1.3], [0.0, 0.25, 0.8], alpha_int=-0.5, alpha_phys=-1.0)
+def test_conservation_at_special_penalty():
+    """On a grid of equal square elements (non-square domain), alpha = -1 on
+    interfaces and -2 on physical sides make GLL summation by parts cancel the
+    Laplacian's boundary fluxes: the weighted column sums vanish, w^T L = 0 (the
+    value jumps cancel pairwise because tau is equal on both sides).  This pins the
+    tau scaling (omega_0, h_e^2), the Robin length sigma = h_e/2 and the corner
+    treatment independently of the default penalty."""
+    g = O.Grid(7, wl.uniform_breaks(3, 1.2), wl.uniform_breaks(2, 0.8), alpha_int=-1.0, alpha_phys=-2.0)
     L, T = O.assemble(g)
     w = g.quad_weights()
     Ld = L.toarray()
@@ -72,7 +75,7 @@ def test_conservation_at_half_penalty():
     # discrete compatibility is the quadrature form of int f = oint g
     gb = np.arange(g.nbdry, dtype=float) % 5 - 2.0
     xs, xn, yw, ye = g.boundary_arc()
-    # w^T T g = tau_phys * (GLL side quadrature) = -oint g
+    # w^T T g = (tau sigma)_phys * (GLL side quadrature) = -oint g
     qx = np.concatenate([g.omega * g.width(ix) / 2 for ix in range(g.m_x)])
     qy = np.concatenate([g.omega * g.height(iy) / 2 for iy in range(g.m_y)])
     oint = qx @ gb[:g.m_x * g.n] + qx @ gb[g.m_x * g.n:2 * g.m_x * g.n] \
