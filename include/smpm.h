@@ -108,6 +108,9 @@ typedef struct smpm_solve_opts {
                          (Algorithm 2), 1: unpreconditioned (Algorithm 1); default 3               */
   double inner_tol;   /* mixed precision: inner GMRES tolerance per refinement cycle (1e-4)      */
   int max_refine;     /* mixed precision: maximum refinement cycles (default 20)                 */
+  int graph;          /* 1: the Arnoldi steps run as replays of a captured hipGraph of 8 steps
+                         (captured once per solve shape and context); 0: launched one by one.
+                         Results are identical (default 1)                                        */
 } smpm_solve_opts;
 
 typedef struct smpm_solve_info {

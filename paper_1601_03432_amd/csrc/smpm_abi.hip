@@ -44,6 +44,8 @@ struct Workspace {
   double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr, *sides = nullptr;
   double *xacc = nullptr, *rho = nullptr;  // iterative refinement: solution and residual
   double* cws = nullptr;                    // substructured coarse solve scratch
+  double* tolv = nullptr;                   // device GMRES: tolerance and step counter
+  int* jdev = nullptr;
   double *beta_cur = nullptr, *beta0 = nullptr, *tolb = nullptr;
   int *iters = nullptr, *counter = nullptr;
   int* pinned = nullptr;  // 2 x nrhs host-visible activity flags
@@ -67,8 +69,22 @@ struct smpm_ctx {
   bool have_null = false;                    // u_L, u_S computed (on first use)
   std::vector<double> h_uL, h_uS;
   Workspace ws;
+  // captured chunks of Arnoldi steps, keyed by the solve's shape; they hold workspace
+  // pointers, so a workspace reallocation drops them
+  struct GraphEntry {
+    int nrhs, kind, tr, sprec, mprec, maxit;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;          // capture-only stream (default priority)
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   ~smpm_ctx() {
     if (device) {
+      drop_graphs();
+      if (cap_stream) (void)hipStreamDestroy(cap_stream);
       for (void* p : ws.mem) (void)hipFree(p);
       if (ws.pinned) (void)hipHostFree(ws.pinned);
       for (hipEvent_t e : ws.ev)
@@ -131,6 +147,7 @@ int ialloc(std::vector<void*>& mem, int** p, size_t count) {
 int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   Workspace& w = c->ws;
   if (w.nrhs >= nrhs && w.maxit >= maxit) return SMPM_OK;
+  c->drop_graphs();
   nrhs = std::max(nrhs, w.nrhs);
   maxit = std::max(maxit, w.maxit);
   for (void* p : w.mem) (void)hipFree(p);
@@ -184,6 +201,8 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   if (P.coarse_mode == 2)
     cstride = (int64_t)P.sub.B.size() + (int64_t)P.sub.npatch * P.sub.border + P.sub.nsep + P.sub.border + 1;
   rc |= dalloc(w.mem, &w.cws, (size_t)std::max<int64_t>(cstride, 1) * R);
+  rc |= dalloc(w.mem, &w.tolv, 1);
+  rc |= ialloc(w.mem, &w.jdev, 1);
   if (rc != SMPM_OK) return SMPM_ENOMEM;
   c->dp.cws = w.cws;
   c->dp.cws_stride = cstride;
@@ -356,24 +375,60 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.maxit = maxit;
   S.nch = W.nch;
   S.rows = W.rows;
-  S.tol = 0.0;
-  S.bref2 = nullptr;
+  S.tolv = W.tolv;
+  S.jdev = W.jdev;
+  S.bref2 = W.scal2 + 2 * nrhs;
   return S;
+}
+
+// The executable graph of kChunkIters Arnoldi steps for this solve shape (captured on
+// first use on the context's capture stream; nothing runs during the capture).
+constexpr int kChunkIters = 8;
+int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int sprec, int mprec,
+                hipGraphExec_t* out) {
+  for (const auto& g : c->graphs)
+    if (g.nrhs == nrhs && g.kind == kind && g.tr == (int)tr && g.sprec == sprec && g.mprec == mprec &&
+        g.maxit == S.maxit) {
+      *out = g.exec;
+      return SMPM_OK;
+    }
+  if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int q = 0; q < kChunkIters; ++q) gm_step(c->dp, S, nrhs, kind, tr, c->cap_stream, sprec, mprec);
+  const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &graph);
+  if (e1 != hipSuccess || !graph) return fail(SMPM_EHIP, "hipStreamEndCapture failed");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(SMPM_EHIP, "hipGraphInstantiate failed");
+  if (c->graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, exec});
+  *out = exec;
+  return SMPM_OK;
 }
 
 // Device-resident GMRES from x0 = 0 on S (kind 1), S M^{-1} (2) or P S M^{-1} (3).
 // The host enqueues Arnoldi steps in chunks and polls per-column activity flags
 // one chunk behind, so the device never waits for the host.
 int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, double tol, int maxit,
-              std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64) {
+              std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64,
+              bool use_graph = true) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   GmState S = gm_state(c, nrhs, maxit);
-  S.tol = tol;
   // the stopping rule is relative to |b| (the Schur right-hand side), the quantity
-  // the FP64 true residual is accepted against
+  // the FP64 true residual is accepted against; S is complete before any capture
   launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
   S.bref2 = W.scal2 + 2 * nrhs;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    const int rc = chunk_graph(c, S, nrhs, kind, tr, sprec, mprec, &exec);
+    if (rc) return rc;
+  }
   if (kind == 3) {
     launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
@@ -381,13 +436,15 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
   } else {
     HIPCHK(hipMemcpyAsync(W.w, b, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
   }
-  gm_start(P, S, nrhs, s);
-  constexpr int kChunkIters = 8;
-  int chunk = 0, launched = 0;
+  gm_start(P, S, nrhs, tol, s);
+  // steps past maxit (the last chunk's tail) find every column retired and do nothing
+  int chunk = 0;
   for (int j0 = 0; j0 < maxit; j0 += kChunkIters, ++chunk) {
-    const int j1 = std::min(maxit, j0 + kChunkIters);
-    for (int j = j0; j < j1; ++j) gm_step(P, S, nrhs, j, kind, tr, s, sprec, mprec);
-    launched = j1;
+    if (exec) {
+      HIPCHK(hipGraphLaunch(exec, s));
+    } else {
+      for (int q = 0; q < kChunkIters; ++q) gm_step(P, S, nrhs, kind, tr, s, sprec, mprec);
+    }
     int* flags = W.pinned + (chunk & 1) * W.nrhs;
     HIPCHK(hipMemcpyAsync(flags, W.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(W.ev[chunk & 1], s));
@@ -399,7 +456,7 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
       if (!any) break;
     }
   }
-  gm_close(P, S, nrhs, launched, kind, tr, s);
+  gm_close(P, S, nrhs, kind, tr, s);
   gm_finish(P, S, nrhs, x, s);
   iters.assign(nrhs, 0);
   HIPCHK(hipMemcpyAsync(iters.data(), W.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -410,11 +467,12 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
 }
 
 int solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, int nrhs, double tol, int maxit,
-                std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64) {
+                std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64,
+                bool use_graph = true) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   double* x1 = W.x;  // note: x may not alias W.x
-  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s, sprec, mprec);
+  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s, sprec, mprec, use_graph);
   if (rc < 0) return rc;
   // the post-processing uses the operators (and precisions) of the GMRES operator, so
   // that x = M^{-1} x1 reproduces the preconditioned iterate exactly
@@ -708,6 +766,7 @@ void smpm_default_opts(smpm_solve_opts* o) {
   o->variant = 3;
   o->inner_tol = 1e-4;
   o->max_refine = 20;
+  o->graph = 1;
 }
 
 const char* smpm_last_error(void) { return g_err.c_str(); }
@@ -1053,7 +1112,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   double* xsol = W.bS;
   if (o.precision == SMPM_FP64) {
     // x lands in W.bS (free after b_hat is formed)
-    rc = solve_schur(c, kind, tr, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s);
+    rc = solve_schur(c, kind, tr, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s, PREC_F64, PREC_F64, o.graph != 0);
     if (rc < 0) return rc;
     rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
     if (rc) return rc;
@@ -1110,7 +1169,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       stall = slow ? stall + 1 : 0;
       if (stall >= 2 || cycles == o.max_refine) break;
       std::vector<int> it;
-      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, o.inner_tol, o.maxit, it, s, sprec, mprec);
+      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, o.inner_tol, o.maxit, it, s, sprec, mprec, o.graph != 0);
       if (rc < 0) return rc;
       for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
       launch_add(W.xacc, W.bS, 1.0, W.xacc, Pl.k, nrhs, s);

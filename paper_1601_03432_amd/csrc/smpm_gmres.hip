@@ -1,8 +1,9 @@
 // Device-resident GMRES iteration for the deflated Schur complement system.
 //
 // One Arnoldi step j of right-preconditioned GMRES on P S M^{-1} (Algorithm 3,
-// step 4) is six kernels that take j as a plain argument and keep every scalar
-// on the device, so the host never waits inside the loop:
+// step 4) is six kernels that read j from a device counter and keep every scalar
+// on the device, so the host never waits inside the loop and a captured chunk of
+// steps (hipGraph) replays for any j:
 //   gm_precond  beta_j = |w| from the previous step's partials; block 0 applies
 //               the Givens rotations to Hessenberg column j-1 and retires the
 //               column once its residual estimate reaches tol * beta_0;
@@ -12,6 +13,7 @@
 //   gm_orth1    w = t - Z c2 - S Z c2 (deflation), partial dots V^T w
 //   gm_orth2    h1 = sum of partials; w -= V h1; partial dots V^T w
 //   gm_orth3    h2 = sum of partials; w -= V h2; partial |w|^2
+//   gm_advance  j += 1
 // Each block handles a chunk of rows.  Every block that needs a reduced value
 // sums the previous kernel's per-chunk partials itself, in one fixed order, so
 // results are deterministic and no inter-block fence is needed.
@@ -152,18 +154,20 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta) {
 // beta_j, Givens for column j-1 (block 0), v_j = w / beta_j into V_j and
 // z = M^{-1} v_j (or z = v_j).  givens_only: stop after the Givens step.
 template <typename OpT>
-__global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int j, int use_precond, int transpose,
+__global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int use_precond, int transpose,
                                                     int givens_only) {
   using Acc = typename AccOf<OpT>::type;
   __shared__ Acc xs[8 * kMaxN];
   __shared__ double red[kWaves];
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
+  const int j = *S.jdev;
+  if (j > S.maxit) return;
   const double beta = reduce_norm(S.part3 + (int64_t)col * S.nch, S.nch, red);
   if (blockIdx.x == 0) {
     if (j == 0) {
       if (tid == 0) {
-        S.tolb[col] = S.tol * (S.bref2 ? sqrt(S.bref2[col]) : beta);
+        S.tolb[col] = S.tolv[0] * (S.bref2 ? sqrt(S.bref2[col]) : beta);
         S.g[(int64_t)col * S.ldv] = beta;
         S.res[col] = beta;
         if (!(beta > 0.0)) {
@@ -212,10 +216,11 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int j,
 
 // w = t - (Z c2 + {S Z c2 | S^T Z c2}) on this block's rows (or w = t), then
 // partial dots with V_0..V_j.
-__global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int j, int defl, int transpose) {
+__global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int defl, int transpose) {
   __shared__ double wv[kRowsMax];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
   if (!S.active[col]) return;
+  const int j = *S.jdev;
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const double* tc = S.t + (int64_t)col * k;
@@ -258,12 +263,13 @@ __global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int j, i
 // PASS 3: h2 = sum of part2; w -= V h2; partial |w|^2 into part3.
 // Block 0 stores h1 / h2 for the Givens step.
 template <int PASS>
-__global__ __launch_bounds__(256) void k_gm_orth(DevPlan P, GmState S, int j) {
+__global__ __launch_bounds__(256) void k_gm_orth(DevPlan P, GmState S) {
   __shared__ double wv[kRowsMax];
   __shared__ double hs[kMaxIt + 1];
   __shared__ double red[kWaves];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
   if (!S.active[col]) return;
+  const int j = *S.jdev;
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const int nvec = j + 1;
@@ -296,8 +302,14 @@ __global__ __launch_bounds__(256) void k_gm_orth(DevPlan P, GmState S, int j) {
   if (tid == 0) S.part3[(int64_t)col * S.nch + chunk] = bs;
 }
 
-// Start of a solve: partial |w|^2 of the initial residual; all columns active.
-__global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S) {
+// j += 1 (one thread; kernel order makes it the only access in flight)
+__global__ void k_gm_advance(GmState S) {
+  if (threadIdx.x == 0) S.jdev[0] = S.jdev[0] + 1;
+}
+
+// Start of a solve: partial |w|^2 of the initial residual; all columns active;
+// j = 0 and the tolerance.
+__global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S, double tol) {
   __shared__ double red[kWaves];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
@@ -310,6 +322,10 @@ __global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S) {
   if (chunk == 0 && tid == 0) {
     S.active[col] = 1;
     S.iters[col] = 0;
+    if (col == 0) {
+      S.jdev[0] = 0;
+      S.tolv[0] = tol;
+    }
   }
 }
 
@@ -351,24 +367,24 @@ __global__ __launch_bounds__(256) void k_gm_combine(DevPlan P, GmState S, double
 
 // ------------------------------------------------------------------ launchers
 
-void gm_start(const DevPlan& P, const GmState& S, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_start, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S);
+void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_start, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, tol);
 }
 
 static int precond_grid(const DevPlan& P, const GmState& S, int kind) {
   return kind == 1 ? S.nch : std::max(1, std::min(P.nblk, 1024));
 }
 
-void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s, int sprec,
+void gm_step(const DevPlan& P, const GmState& S, int nrhs, int kind, bool tr, hipStream_t s, int sprec,
              int mprec) {
   const dim3 pg(precond_grid(P, S, kind), nrhs);
   const int up = kind == 1 ? 0 : 1, trn = tr ? 1 : 0;
   if (mprec == PREC_F32)
-    hipLaunchKernelGGL(k_gm_precond<float>, pg, dim3(kThreads), 0, s, P, S, j, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_precond<float>, pg, dim3(kThreads), 0, s, P, S, up, trn, 0);
   else if (mprec == PREC_BF16)
-    hipLaunchKernelGGL(k_gm_precond<bf16s>, pg, dim3(kThreads), 0, s, P, S, j, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_precond<bf16s>, pg, dim3(kThreads), 0, s, P, S, up, trn, 0);
   else
-    hipLaunchKernelGGL(k_gm_precond<double>, pg, dim3(kThreads), 0, s, P, S, j, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_precond<double>, pg, dim3(kThreads), 0, s, P, S, up, trn, 0);
   const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P) && P.coarse_mode == 1;
   launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s, sprec);
   if (kind == 3) {
@@ -379,14 +395,14 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool
       launch_coarse(P, S.c, S.c2, nrhs, tr, S.active, s);
     }
   }
-  hipLaunchKernelGGL(k_gm_orth1, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, j, kind == 3 ? 1 : 0,
-                     tr ? 1 : 0);
-  hipLaunchKernelGGL(k_gm_orth<2>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, j);
-  hipLaunchKernelGGL(k_gm_orth<3>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, j);
+  hipLaunchKernelGGL(k_gm_orth1, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, kind == 3 ? 1 : 0, tr ? 1 : 0);
+  hipLaunchKernelGGL(k_gm_orth<2>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S);
+  hipLaunchKernelGGL(k_gm_orth<3>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S);
+  hipLaunchKernelGGL(k_gm_advance, dim3(1), dim3(64), 0, s, S);
 }
 
-void gm_close(const DevPlan& P, const GmState& S, int nrhs, int j, int kind, bool tr, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_precond<double>, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, j, kind == 1 ? 0 : 1,
+void gm_close(const DevPlan& P, const GmState& S, int nrhs, int kind, bool tr, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_precond<double>, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, kind == 1 ? 0 : 1,
                      tr ? 1 : 0, 1);
 }
 

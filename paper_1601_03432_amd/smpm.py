@@ -36,7 +36,7 @@ ABI_SYMBOLS = (
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("transpose", C.c_int),
-                ("variant", C.c_int), ("inner_tol", C.c_double), ("max_refine", C.c_int)]
+                ("variant", C.c_int), ("inner_tol", C.c_double), ("max_refine", C.c_int), ("graph", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -272,7 +272,7 @@ class Context:
         return out
 
     def solve(self, f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64, transpose=False,
-              inner_tol=1e-4, max_refine=20, stream=None, raise_on_noconv=True):
+              inner_tol=1e-4, max_refine=20, stream=None, raise_on_noconv=True, graph=True):
         import torch
         f = self._as_cols(f, self.r)
         nrhs = f.shape[0]
@@ -285,7 +285,7 @@ class Context:
                 raise ValueError("g must have as many columns as f")
             gp = C.c_void_p(g.data_ptr())
         u = torch.empty_like(f)
-        opts = SolveOpts(tol, maxit, precision, int(transpose), variant, inner_tol, max_refine)
+        opts = SolveOpts(tol, maxit, precision, int(transpose), variant, inner_tol, max_refine, int(graph))
         info = SolveInfo()
         rc = self._lib.smpm_solve(self._h, C.c_void_p(f.data_ptr()), gp, C.c_void_p(u.data_ptr()), nrhs,
                                   C.byref(opts), C.byref(info), _stream(torch, stream))

@@ -208,3 +208,26 @@ def test_batched_columns_match_single():
     for i in range(5):
         us, _ = ctx.solve(dev(F[i]), tol=1e-12, maxit=600)
         assert rel(ub[i], us.cpu().numpy()[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed_fp32", "adjoint"])
+def test_graph_replays_match_eager(mode):
+    """Arnoldi steps replayed from the captured hipGraph give, bit for bit, the solutions
+    of the same steps launched one by one, over repeated solves with eager work (other
+    solves, Schur applies, synchronizations) in between."""
+    ctx, m = setup("ragged_9x7")
+    g = m.grid
+    F = dev(np.stack([_problem(g, 60 + i, with_g=False)[0] for i in range(3)]))
+    kw = dict(tol=1e-11, maxit=600)
+    if mode == "mixed_fp32":
+        kw.update(precision=smpm.MIXED_FP32, inner_tol=1e-6, max_refine=30)
+    if mode == "adjoint":
+        kw.update(transpose=True)
+    ref, info_ref = ctx.solve(F, graph=False, **kw)
+    for rep in range(3):
+        u, info = ctx.solve(F, graph=True, **kw)
+        assert torch.equal(u, ref), (mode, rep)
+        assert info.iterations == info_ref.iterations
+        ctx.schur_apply(dev(wl.random_vectors(70 + rep, 2, ctx.k)))
+        ctx.solve(F[:1], graph=False, **kw)
+        torch.cuda.synchronize()
