@@ -48,7 +48,10 @@ struct Workspace {
   int* jdev = nullptr;
   double *beta_cur = nullptr, *beta0 = nullptr, *tolb = nullptr;
   int *iters = nullptr, *counter = nullptr;
-  int* pinned = nullptr;  // 2 x nrhs host-visible activity flags
+  int* pinned = nullptr;  // pinned host block: flags (2 x nrhs ints), then hres / hout
+  double* hres = nullptr;  // 2 x nrhs residual-estimate ratios (per chunk slot)
+  double* hout = nullptr;  // 4 x nrhs small results
+  int* hiters = nullptr;   // nrhs iteration counts
   hipEvent_t ev[2] = {nullptr, nullptr};
   int nch = 0, rows = 0;
   std::vector<void*> mem;
@@ -202,12 +205,20 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
     cstride = (int64_t)P.sub.B.size() + (int64_t)P.sub.npatch * P.sub.border + P.sub.nsep + P.sub.border + 1;
   rc |= dalloc(w.mem, &w.cws, (size_t)std::max<int64_t>(cstride, 1) * R);
   rc |= dalloc(w.mem, &w.tolv, 1);
-  rc |= ialloc(w.mem, &w.jdev, 1);
+  rc |= ialloc(w.mem, &w.jdev, 2);
   if (rc != SMPM_OK) return SMPM_ENOMEM;
   c->dp.cws = w.cws;
   c->dp.cws_stride = cstride;
-  if (hipHostMalloc((void**)&w.pinned, 2 * R * sizeof(int), hipHostMallocDefault) != hipSuccess)
-    return fail(SMPM_ENOMEM, "hipHostMalloc failed");
+  {
+    // [flags 2R ints | iters R ints | pad] [hres 2R doubles] [hout 4R doubles]
+    const size_t ibytes = ((3 * R * sizeof(int) + 63) / 64) * 64;
+    const size_t bytes = ibytes + 6 * R * sizeof(double);
+    if (hipHostMalloc((void**)&w.pinned, bytes, hipHostMallocCoherent) != hipSuccess)
+      return fail(SMPM_ENOMEM, "hipHostMalloc failed");
+    w.hiters = w.pinned + 2 * R;
+    w.hres = reinterpret_cast<double*>(reinterpret_cast<char*>(w.pinned) + ibytes);
+    w.hout = w.hres + 2 * R;
+  }
   for (int i = 0; i < 2; ++i)
     if (hipEventCreateWithFlags(&w.ev[i], hipEventDisableTiming) != hipSuccess)
       return fail(SMPM_EHIP, "hipEventCreate failed");
@@ -395,7 +406,7 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
   if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int q = 0; q < kChunkIters; ++q) gm_step(c->dp, S, nrhs, kind, tr, c->cap_stream, sprec, mprec);
+  for (int q = 0; q < kChunkIters; ++q) gm_step(c->dp, S, nrhs, q & 1, kind, tr, c->cap_stream, sprec, mprec);
   const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &graph);
   if (e1 != hipSuccess || !graph) return fail(SMPM_EHIP, "hipStreamEndCapture failed");
   hipGraphExec_t exec = nullptr;
@@ -437,30 +448,63 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
     HIPCHK(hipMemcpyAsync(W.w, b, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
   }
   gm_start(P, S, nrhs, tol, s);
-  // steps past maxit (the last chunk's tail) find every column retired and do nothing
-  int chunk = 0;
-  for (int j0 = 0; j0 < maxit; j0 += kChunkIters, ++chunk) {
+  // Chunks of kChunkIters steps; after each, a kernel publishes the activity flags and
+  // residual ratios (estimate / threshold) into pinned slot chunk % 2.  The host keeps
+  // one chunk queued ahead of the one it waits for, except when the observed
+  // convergence rate says the queued chunk will finish the solve: then it waits for
+  // that chunk instead of queueing steps that would find every column retired.  Steps
+  // past maxit (the last chunk's tail) do nothing.
+  const int nchunks = (maxit + kChunkIters - 1) / kChunkIters;
+  auto launch_chunk = [&](int ch) -> int {
     if (exec) {
       HIPCHK(hipGraphLaunch(exec, s));
     } else {
-      for (int q = 0; q < kChunkIters; ++q) gm_step(P, S, nrhs, kind, tr, s, sprec, mprec);
+      for (int q = 0; q < kChunkIters; ++q) gm_step(P, S, nrhs, q & 1, kind, tr, s, sprec, mprec);
     }
-    int* flags = W.pinned + (chunk & 1) * W.nrhs;
-    HIPCHK(hipMemcpyAsync(flags, W.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipEventRecord(W.ev[chunk & 1], s));
-    if (chunk >= 1) {
-      HIPCHK(hipEventSynchronize(W.ev[(chunk - 1) & 1]));
-      const int* prev = W.pinned + ((chunk - 1) & 1) * W.nrhs;
-      bool any = false;
-      for (int i = 0; i < nrhs; ++i) any |= prev[i] != 0;
-      if (!any) break;
+    launch_publish_flags(W.active, W.res, W.tolb, nrhs, W.pinned + (ch & 1) * W.nrhs, W.hres + (ch & 1) * W.nrhs,
+                         s);
+    HIPCHK(hipEventRecord(W.ev[ch & 1], s));
+    return SMPM_OK;
+  };
+  std::vector<double> prev_ratio(nrhs, -1.0);
+  int launched = 0;
+  bool finishing = false;  // the chunk in flight is predicted to complete every column
+  int rc0 = launch_chunk(launched++);
+  if (rc0) return rc0;
+  for (int c = 0; c < nchunks; ++c) {
+    if (!finishing && launched == c + 1 && launched < nchunks) {
+      rc0 = launch_chunk(launched++);
+      if (rc0) return rc0;
+    }
+    HIPCHK(hipEventSynchronize(W.ev[c & 1]));
+    const int* fl = W.pinned + (c & 1) * W.nrhs;
+    const double* ra = W.hres + (c & 1) * W.nrhs;
+    bool any = false;
+    double steps_left = 0.0;
+    for (int i = 0; i < nrhs; ++i) {
+      if (!fl[i]) continue;
+      any = true;
+      const double r = ra[i], rp = prev_ratio[i];
+      // steps to reach ratio 1 at the rate seen over the last chunk (unknown: far)
+      double left = 1e30;
+      if (rp > 0.0 && r > 0.0 && r < rp) left = kChunkIters * std::log(r) / std::log(rp / r);
+      steps_left = std::max(steps_left, left);
+      prev_ratio[i] = r;
+    }
+    if (!any || c + 1 >= nchunks) break;
+    // the chunk queued after c covers the next kChunkIters steps
+    finishing = steps_left <= kChunkIters;
+    if (launched == c + 1) {
+      rc0 = launch_chunk(launched++);
+      if (rc0) return rc0;
     }
   }
-  gm_close(P, S, nrhs, kind, tr, s);
+  gm_close(P, S, nrhs, 0, kind, tr, s);  // chunks hold an even number of steps
   gm_finish(P, S, nrhs, x, s);
   iters.assign(nrhs, 0);
-  HIPCHK(hipMemcpyAsync(iters.data(), W.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+  launch_publish_i(W.iters, nrhs, W.hiters, s);
   HIPCHK(hipStreamSynchronize(s));
+  std::copy(W.hiters, W.hiters + nrhs, iters.begin());
   int jmax = 0;
   for (int v : iters) jmax = std::max(jmax, v);
   return jmax;
@@ -501,10 +545,11 @@ int true_residual(smpm_ctx* c, bool tr, const double* b, const double* x, int nr
   launch_add(b, W.t, -1.0, W.w, P.k, nrhs, s);
   launch_mdot(W.w, 0, P.k, 1, W.w, P.k, nullptr, P.k, nrhs, W.part, W.scal, nullptr, s);
   launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2, nullptr, s);
-  std::vector<double> a(nrhs), bb(nrhs);
-  HIPCHK(hipMemcpyAsync(a.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(bb.data(), W.scal2, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  launch_publish(W.scal, nrhs, W.hout, s);
+  launch_publish(W.scal2, nrhs, W.hout + nrhs, s);
   HIPCHK(hipStreamSynchronize(s));
+  const double* a = W.hout;
+  const double* bb = W.hout + nrhs;
   out.resize(nrhs);
   for (int i = 0; i < nrhs; ++i) out[i] = bb[i] > 0 ? std::sqrt(a[i] / bb[i]) : std::sqrt(a[i]);
   return SMPM_OK;
@@ -1083,12 +1128,11 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   rc = ensure_ws(c, nrhs, o.maxit);
   if (rc) return rc;
   Workspace& W = c->ws;
-  std::vector<double> removed(nrhs);
   if (!tr) {
     // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
     launch_rhs(P, f, g, W.rhs, nrhs, s);
     launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
-    HIPCHK(hipMemcpyAsync(removed.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, s);  // read after the final synchronization
     launch_axpy_shared(W.rhs, Pl.r, c->uL, W.scal, 1.0, W.ft, Pl.r, nrhs, s);
     launch_flux(P, W.ft, W.bS, nrhs, s);
     launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
@@ -1097,7 +1141,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     // adjoint of the solution map: c~ = c - w (1^T c)/(w^T 1); S^T xi = E^T A^{-T} c~
     // (consistent: v0^T E^T A^{-T} c~ = -1^T c~ = 0), projected off v0 against rounding
     launch_mdot(c->ones, 0, 0, 1, f, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
-    HIPCHK(hipMemcpyAsync(removed.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, s);  // read after the final synchronization
     launch_axpy_shared(f, Pl.r, c->wq, W.scal, 1.0 / c->wsum, W.ft, Pl.r, nrhs, s);
     launch_local_adj(P, W.ft, W.bS, nrhs, true, s);
     launch_mdot(c->v0hat, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
@@ -1142,10 +1186,11 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       }
       launch_mdot(W.rho, 0, Pl.k, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
       launch_mdot(W.bhat, 0, Pl.k, 1, W.bhat, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal2, nullptr, s);
-      std::vector<double> a(nrhs), bb(nrhs);
-      HIPCHK(hipMemcpyAsync(a.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(bb.data(), W.scal2, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      launch_publish(W.scal, nrhs, W.hout, s);
+      launch_publish(W.scal2, nrhs, W.hout + nrhs, s);
       HIPCHK(hipStreamSynchronize(s));
+      const double* a = W.hout;
+      const double* bb = W.hout + nrhs;
       bool all = true, weak = false, slow = false;
       for (int i = 0; i < nrhs; ++i) {
         tres[i] = bb[i] > 0 ? std::sqrt(a[i] / bb[i]) : std::sqrt(a[i]);
@@ -1187,7 +1232,6 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     launch_add(u, W.rhs, -1.0, u, Pl.r, nrhs, s);
     launch_mdot(c->uL, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
     launch_axpy_shared(u, Pl.r, c->uL, W.scal, 1.0, u, Pl.r, nrhs, s);
-    for (double& v : removed) v /= c->wsum;
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -1201,7 +1245,8 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     info->iterations = itmax;
     info->refinements = o.precision == SMPM_FP64 ? 1 : cycles;
     info->rel_residual = resmax;
-    info->removed_component = removed[0];
+    // published before the synchronization above; the adjoint removes a multiple of w
+    info->removed_component = W.hout[2 * nrhs] / (tr ? c->wsum : 1.0);
   }
   if (!conv)
     return fail(SMPM_ENOCONV, o.precision == SMPM_FP64 ? "GMRES reached maxit before the tolerance"

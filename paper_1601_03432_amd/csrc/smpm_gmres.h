@@ -43,21 +43,22 @@ struct GmState {
   int nch;          // row chunks of a k-vector
   int rows;         // rows per chunk
   double* tolv;     // relative stopping tolerance (device scalar, set by gm_start)
-  int* jdev;        // index j of the next Arnoldi step (device counter)
+  int* jdev;        // index j of the next Arnoldi step (device counter, two slots)
   const double* bref2;  // squared reference norm per column (|b|^2): stop when |g| <= tol |b|
 };
 
 // initial residual norms, all columns active, j = 0 and the tolerance on the device
 void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStream_t s);
-// One Arnoldi step with j read from the device counter (advanced at its end), so a
-// captured sequence of steps replays for any j.  Steps past maxit do nothing: every
-// column retires at j = maxit.
+// One Arnoldi step with j read from slot `par` of the device counter (its last kernel
+// writes j + 1 into slot par ^ 1; the q-th step after gm_start uses par = q % 2), so
+// a captured sequence of steps replays for any j.  Steps past maxit do nothing:
+// every column retires at j = maxit.
 // kind: 1 = S, 2 = S M^{-1}, 3 = P S M^{-1}; tr selects the transposed operators
 // sprec / mprec: OpPrec of the Schur and block-Jacobi operators
-void gm_step(const DevPlan& P, const GmState& S, int nrhs, int kind, bool tr, hipStream_t s,
+void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s,
              int sprec = PREC_F64, int mprec = PREC_F64);
-// Givens step for the last column of the steps enqueued so far
-void gm_close(const DevPlan& P, const GmState& S, int nrhs, int kind, bool tr, hipStream_t s);
+// Givens step for the last column of the steps enqueued so far (par = steps % 2)
+void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s);
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s);
 int gm_rows_per_chunk(int64_t k);
 

@@ -1,19 +1,25 @@
 // Device-resident GMRES iteration for the deflated Schur complement system.
 //
 // One Arnoldi step j of right-preconditioned GMRES on P S M^{-1} (Algorithm 3,
-// step 4) is six kernels that read j from a device counter and keep every scalar
+// step 4) is five kernels that read j from a device counter and keep every scalar
 // on the device, so the host never waits inside the loop and a captured chunk of
-// steps (hipGraph) replays for any j:
-//   gm_precond  beta_j = |w| from the previous step's partials; block 0 applies
+// steps (hipGraph) replays for any j.  The counter is double-buffered: step q of a
+// chunk reads slot q % 2 and its last kernel writes j + 1 into the other slot, so
+// no kernel reads a value another block of it may be changing:
+//   gm_precond  h2 and beta_j from the previous step's partials; block 0 applies
 //               the Givens rotations to Hessenberg column j-1 and retires the
-//               column once its residual estimate reaches tol * beta_0;
-//               v_j = w / beta_j (into V), z = M^{-1} v_j
+//               column once its residual estimate reaches tol * |b|;
+//               v_j = (w - V h2) / beta_j (into V), z = M^{-1} v_j
 //   Schur       t = S z, with the per-side sums of t for Z^T t
 //   coarse      c2 = G Z^T t
 //   gm_orth1    w = t - Z c2 - S Z c2 (deflation), partial dots V^T w
-//   gm_orth2    h1 = sum of partials; w -= V h1; partial dots V^T w
-//   gm_orth3    h2 = sum of partials; w -= V h2; partial |w|^2
-//   gm_advance  j += 1
+//   gm_orth2    h1 = sum of partials; w -= V h1; partial dots V^T w and |w|^2;
+//               next j
+// Classical Gram-Schmidt is applied twice, the second pass delayed into the next
+// step's gm_precond: h2 = V^T w from gm_orth2's partials, beta^2 = |w|^2 - |h2|^2
+// (Pythagoras), v = (w - V h2) / beta per slot.  One reduction fewer per step, as
+// in the low-synchronization CGS2 variants of Swirydowicz, Bielich, Langou,
+// Thomas et al.
 // Each block handles a chunk of rows.  Every block that needs a reduced value
 // sums the previous kernel's per-chunk partials itself, in one fixed order, so
 // results are deterministic and no inter-block fence is needed.
@@ -63,18 +69,6 @@ __device__ void reduce_partials(const double* __restrict__ part, int nvec, int n
   }
 }
 
-// sqrt(sum_c part[c]) computed by wave 0 (same order in every block).
-__device__ double reduce_norm(const double* __restrict__ part, int nch, double* red) {
-  if (threadIdx.x < 64) {
-    double acc = 0.0;
-    for (int c = threadIdx.x; c < nch; c += 64) acc += part[c];
-    acc = wave_sum(acc);
-    if (threadIdx.x == 0) red[0] = sqrt(acc);
-  }
-  __syncthreads();
-  return red[0];
-}
-
 // Partial dots of the chunk held in LDS (wv, `rows` rows) with V_0..V_{nvec-1}:
 // wave q handles groups of kDotUnroll vectors whose loads are all issued before
 // the shuffle reductions; lanes run over rows.
@@ -102,13 +96,12 @@ __device__ void chunk_dots(const double* __restrict__ V, int64_t vvs, int64_t x0
 // Givens step for Hessenberg column jc = j-1 of one right-hand side, run by
 // block 0 of gm_precond: H(:, jc) = h1 + h2 with beta below the diagonal,
 // rotated by the previous rotations; a new rotation zeroes beta.
-__device__ void givens_column(const GmState& S, int col, int j, double beta) {
+__device__ void givens_column(const GmState& S, int col, int j, double beta, const double* h2) {
   __shared__ double hc[kMaxIt + 2];
   __shared__ double csl[kMaxIt + 1], snl[kMaxIt + 1];
   const int tid = threadIdx.x;
   const int jc = j - 1;
   const double* h1 = S.h1 + (int64_t)col * S.ldv;
-  const double* h2 = S.h2 + (int64_t)col * S.ldv;
   double* csg = S.cs + (int64_t)col * S.ldv;
   double* sng = S.sn + (int64_t)col * S.ldv;
   for (int i = tid; i <= jc; i += kThreads) hc[i] = h1[i] + h2[i];
@@ -154,16 +147,33 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta) {
 // beta_j, Givens for column j-1 (block 0), v_j = w / beta_j into V_j and
 // z = M^{-1} v_j (or z = v_j).  givens_only: stop after the Givens step.
 template <typename OpT>
-__global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int use_precond, int transpose,
+__global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int par, int use_precond, int transpose,
                                                     int givens_only) {
   using Acc = typename AccOf<OpT>::type;
   __shared__ Acc xs[8 * kMaxN];
   __shared__ double red[kWaves];
+  __shared__ double h2s[kMaxIt + 1];
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
-  const int j = *S.jdev;
+  const int j = S.jdev[par];
   if (j > S.maxit) return;
-  const double beta = reduce_norm(S.part3 + (int64_t)col * S.nch, S.nch, red);
+  // second Gram-Schmidt pass of the previous step: h2 and beta (see the file header)
+  const int nh = j;  // h2 has j entries (none before the first step)
+  if (nh > 0) reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, nh, S.nch, h2s);
+  __syncthreads();
+  double beta;
+  {
+    if (tid < 64) {
+      double acc = 0.0, hh = 0.0;
+      for (int c = tid; c < S.nch; c += 64) acc += S.part3[(int64_t)col * S.nch + c];
+      for (int i = tid; i < nh; i += 64) hh = fma(h2s[i], h2s[i], hh);
+      acc = wave_sum(acc);
+      hh = wave_sum(hh);
+      if (tid == 0) red[0] = sqrt(fmax(acc - hh, 0.0));
+    }
+    __syncthreads();
+    beta = red[0];
+  }
   if (blockIdx.x == 0) {
     if (j == 0) {
       if (tid == 0) {
@@ -176,18 +186,26 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int us
         }
       }
     } else {
-      givens_column(S, col, j, beta);
+      givens_column(S, col, j, beta, h2s);
     }
   }
   if (givens_only) return;
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
   const int64_t k = P.k;
   const double* wc = S.w + (int64_t)col * k;
+  const double* Vc = S.V + (int64_t)col * k;
   double* vj = S.V + (int64_t)j * S.vvs + (int64_t)col * k;
   double* zc = S.z + (int64_t)col * k;
+  // v_j = (w - V h2) / beta at one slot
+  auto vnew = [&](int64_t x) {
+    double acc = wc[x];
+#pragma unroll 8
+    for (int i = 0; i < nh; ++i) acc = fma(-h2s[i], Vc[(int64_t)i * S.vvs + x], acc);
+    return acc * inv;
+  };
   if (!use_precond) {
     for (int64_t x = (int64_t)blockIdx.x * kThreads + tid; x < k; x += (int64_t)gridDim.x * kThreads) {
-      const double v = wc[x] * inv;
+      const double v = vnew(x);
       vj[x] = v;
       zc[x] = v;
     }
@@ -199,7 +217,7 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int us
     __syncthreads();
     for (int i = tid; i < sb; i += kThreads) {
       const int slot = P.blk_slots[o + i];
-      const double v = wc[slot] * inv;
+      const double v = vnew(slot);
       xs[i] = (Acc)v;
       vj[slot] = v;
     }
@@ -216,11 +234,11 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int us
 
 // w = t - (Z c2 + {S Z c2 | S^T Z c2}) on this block's rows (or w = t), then
 // partial dots with V_0..V_j.
-__global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int defl, int transpose) {
+__global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int par, int defl, int transpose) {
   __shared__ double wv[kRowsMax];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
   if (!S.active[col]) return;
-  const int j = *S.jdev;
+  const int j = S.jdev[par];
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const double* tc = S.t + (int64_t)col * k;
@@ -259,25 +277,25 @@ __global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int defl
              chunk);
 }
 
-// PASS 2: h1 = sum of part1; w -= V h1; partial dots into part2.
-// PASS 3: h2 = sum of part2; w -= V h2; partial |w|^2 into part3.
-// Block 0 stores h1 / h2 for the Givens step.
-template <int PASS>
-__global__ __launch_bounds__(256) void k_gm_orth(DevPlan P, GmState S) {
+// h1 = sum of part1 (block 0 stores it for the Givens step); w -= V h1; partial dots
+// V^T w into part2 and partial |w|^2 into part3; the next step's index.
+__global__ __launch_bounds__(256) void k_gm_orth2(DevPlan P, GmState S, int par) {
   __shared__ double wv[kRowsMax];
   __shared__ double hs[kMaxIt + 1];
   __shared__ double red[kWaves];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
+  const int j = S.jdev[par];
+  // the step's last kernel sets the next step's index in the other slot (whatever the
+  // columns' activity, so steps keep counting)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) S.jdev[par ^ 1] = j + 1;
   if (!S.active[col]) return;
-  const int j = *S.jdev;
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const int nvec = j + 1;
-  const double* part_in = (PASS == 2 ? S.part1 : S.part2) + (int64_t)col * S.ldv * S.nch;
-  reduce_partials(part_in, nvec, S.nch, hs);
+  reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, nvec, S.nch, hs);
   __syncthreads();
   if (chunk == 0) {
-    double* hdst = (PASS == 2 ? S.h1 : S.h2) + (int64_t)col * S.ldv;
+    double* hdst = S.h1 + (int64_t)col * S.ldv;
     for (int i = tid; i < nvec; i += kThreads) hdst[i] = hs[i];
   }
   double* wc = S.w + (int64_t)col * k;
@@ -294,17 +312,9 @@ __global__ __launch_bounds__(256) void k_gm_orth(DevPlan P, GmState S) {
     nrm = fma(v, v, nrm);
   }
   __syncthreads();
-  if (PASS == 2) {
-    chunk_dots(Vc, S.vvs, x0, rows, wv, nvec, S.part2 + (int64_t)col * S.ldv * S.nch, S.nch, chunk);
-    return;
-  }
+  chunk_dots(Vc, S.vvs, x0, rows, wv, nvec, S.part2 + (int64_t)col * S.ldv * S.nch, S.nch, chunk);
   const double bs = block_sum(nrm, red);
   if (tid == 0) S.part3[(int64_t)col * S.nch + chunk] = bs;
-}
-
-// j += 1 (one thread; kernel order makes it the only access in flight)
-__global__ void k_gm_advance(GmState S) {
-  if (threadIdx.x == 0) S.jdev[0] = S.jdev[0] + 1;
 }
 
 // Start of a solve: partial |w|^2 of the initial residual; all columns active;
@@ -375,16 +385,16 @@ static int precond_grid(const DevPlan& P, const GmState& S, int kind) {
   return kind == 1 ? S.nch : std::max(1, std::min(P.nblk, 1024));
 }
 
-void gm_step(const DevPlan& P, const GmState& S, int nrhs, int kind, bool tr, hipStream_t s, int sprec,
+void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s, int sprec,
              int mprec) {
   const dim3 pg(precond_grid(P, S, kind), nrhs);
   const int up = kind == 1 ? 0 : 1, trn = tr ? 1 : 0;
   if (mprec == PREC_F32)
-    hipLaunchKernelGGL(k_gm_precond<float>, pg, dim3(kThreads), 0, s, P, S, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_precond<float>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
   else if (mprec == PREC_BF16)
-    hipLaunchKernelGGL(k_gm_precond<bf16s>, pg, dim3(kThreads), 0, s, P, S, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_precond<bf16s>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
   else
-    hipLaunchKernelGGL(k_gm_precond<double>, pg, dim3(kThreads), 0, s, P, S, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_precond<double>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
   const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P) && P.coarse_mode == 1;
   launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s, sprec);
   if (kind == 3) {
@@ -395,14 +405,13 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int kind, bool tr, hi
       launch_coarse(P, S.c, S.c2, nrhs, tr, S.active, s);
     }
   }
-  hipLaunchKernelGGL(k_gm_orth1, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, kind == 3 ? 1 : 0, tr ? 1 : 0);
-  hipLaunchKernelGGL(k_gm_orth<2>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S);
-  hipLaunchKernelGGL(k_gm_orth<3>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S);
-  hipLaunchKernelGGL(k_gm_advance, dim3(1), dim3(64), 0, s, S);
+  hipLaunchKernelGGL(k_gm_orth1, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
+                     tr ? 1 : 0);
+  hipLaunchKernelGGL(k_gm_orth2, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par);
 }
 
-void gm_close(const DevPlan& P, const GmState& S, int nrhs, int kind, bool tr, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_precond<double>, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, kind == 1 ? 0 : 1,
+void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_precond<double>, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 1 ? 0 : 1,
                      tr ? 1 : 0, 1);
 }
 

@@ -181,6 +181,13 @@ void launch_prolong(const DevPlan& P, const double* t, const double* c2, double*
 void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, hipStream_t s);
 void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, hipStream_t s);  // dg = T^T mu
 
+// ---- small results into pinned (mapped, coherent) host memory by a kernel
+void launch_publish(const double* src, int n, double* host_dst, hipStream_t s);
+void launch_publish_i(const int* src, int n, int* host_dst, hipStream_t s);
+// hflag[i] = active[i], hratio[i] = res[i] / tolb[i]
+void launch_publish_flags(const int* active, const double* res, const double* tolb, int n, int* hflag,
+                          double* hratio, hipStream_t s);
+
 // ---- vector kernels over nrhs columns of length len (column stride ld)
 int reduce_chunks(int64_t len);
 // out[col*nvec + i] = sum_x A_i(col)[x] * b(col)[x] * (wt ? wt[x] : 1)

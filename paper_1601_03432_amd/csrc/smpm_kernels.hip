@@ -733,6 +733,27 @@ __global__ void k_bdry_adj(DevPlan P, const double* __restrict__ mu, double* __r
   dg[(int64_t)col * P.nbdry + b] = P.bdry_tau[b] * mu[(int64_t)col * P.r + P.bdry_node[b]];
 }
 
+// ------------------------------------------------------------------ results to pinned host memory
+
+// Device values copied by a kernel into pinned host memory (mapped, coherent): one
+// small launch instead of a DMA copy.  The host reads them after an event/stream wait.
+__global__ void k_publish(const double* __restrict__ src, int n, double* dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+__global__ void k_publish_i(const int* __restrict__ src, int n, int* dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+// per column: activity flag and residual estimate / threshold
+__global__ void k_publish_flags(const int* __restrict__ active, const double* __restrict__ res,
+                                const double* __restrict__ tolb, int n, int* hflag, double* hratio) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  hflag[i] = active[i];
+  hratio[i] = tolb[i] > 0.0 ? res[i] / tolb[i] : 0.0;
+}
+
 // ------------------------------------------------------------------ vector kernels
 
 constexpr int kChunk = 2048;   // elements per reduction chunk (256 threads x 8)
@@ -1040,6 +1061,17 @@ void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, h
 }
 
 int reduce_chunks(int64_t len) { return (int)((len + kChunk - 1) / kChunk); }
+
+void launch_publish(const double* src, int n, double* host_dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish, dim3((n + 255) / 256), dim3(256), 0, s, src, n, host_dst);
+}
+void launch_publish_i(const int* src, int n, int* host_dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish_i, dim3((n + 255) / 256), dim3(256), 0, s, src, n, host_dst);
+}
+void launch_publish_flags(const int* active, const double* res, const double* tolb, int n, int* hflag,
+                          double* hratio, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish_flags, dim3((n + 255) / 256), dim3(256), 0, s, active, res, tolb, n, hflag, hratio);
+}
 
 void launch_mdot(const double* A, int64_t a_vs, int64_t a_cs, int nvec, const double* b, int64_t b_cs,
                  const double* wt, int64_t len, int nrhs, double* part, double* out, const int* active,
