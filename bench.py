@@ -33,17 +33,47 @@ import smpm_workloads as wl  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-def event_time_ms(fn, stream, reps):
+# HBM traffic of the Schur kernel on the c2 grid, from two rocprofv3 --pmc runs of
+# `python bench.py --steps 3 --warmup 1 --no-large --no-cpu-baseline` (FETCH_SIZE,
+# then WRITE_SIZE; KiB per dispatch of the single-column forward launch), each
+# scaled by the counter's reading for a plain kernel of known size (FETCH_SIZE reads
+# half of a 64 MiB elementwise read, so x2.0; WRITE_SIZE matches a 64 MiB fill, x1.0).
+# Valid only for the kernel source it was measured on (sha256 below); otherwise null.
+SCHUR_TRAFFIC = None  # {"fetch_kib": ..., "write_kib": ..., "kernels_sha256": "..."}
+
+
+def kernels_sha256():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1601_03432_amd", "csrc", "smpm_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def graph_time_us(launch, launches, replays=20):
+    """Average duration of one launch: `launches` calls of `launch` captured in a HIP
+    graph, replayed `replays` times between HIP events on the replaying stream."""
     import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            launch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(launches):
+            launch()
+    g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        start.record(stream)
-        for _ in range(reps):
-            fn()
-        end.record(stream)
+    start.record(stream)
+    for _ in range(replays):
+        g.replay()
+    end.record(stream)
     end.synchronize()
-    return start.elapsed_time(end) / reps
+    return start.elapsed_time(end) * 1e3 / (replays * launches)
 
 
 def main():
@@ -57,6 +87,7 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="right-hand sides of the batched measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 64x64, n=12 batched measurement")
     ap.add_argument("--cpu-solves", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -80,7 +111,7 @@ def main():
         return ctx.solve(rhs, tol=1e-10, maxit=600)
 
     def solve_mixed(rhs):
-        return ctx.solve(rhs, tol=1e-10, maxit=600, precision=smpm.MIXED_FP32, inner_tol=1e-4, max_refine=30)
+        return ctx.solve(rhs, tol=1e-10, maxit=600, precision=smpm.MIXED_FP32, inner_tol=1e-5, max_refine=30)
 
     def timed(fn, rhs, steps, warmup):
         info = None
@@ -113,13 +144,17 @@ def main():
     secb64, infob64, _ = timed(solve_fp64, fb, 3, 1)
     secbmx, infobmx, _ = timed(solve_mixed, fb, 3, 1)
 
-    # dominant kernel: the Schur apply, timed on the solve's stream with HIP events
+    # metric kernel: the Schur apply (forward, FP64, one column) on the c2 grid, timed
+    # with HIP events around replays of a captured graph of launches
     v = torch.randn(1, ctx.k, dtype=torch.float64, device="cuda")
-    reps = 200
-    sch_ms = event_time_ms(lambda: ctx.schur_apply(v, stream=stream), stream, reps)
+    sv = torch.empty_like(v)
+    sch_us = graph_time_us(lambda: ctx.schur_apply_into(v, sv), 100)
     op_bytes = ctx.stats()["schur_operator_bytes"]
     alg_bytes = 2 * ctx.k * 8 + op_bytes
-    achieved = alg_bytes / (sch_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (sch_us * 1e-6) / 1e9
+    traffic = None
+    if SCHUR_TRAFFIC and SCHUR_TRAFFIC.get("kernels_sha256") == kernels_sha256():
+        traffic = 1024 * (2.0 * SCHUR_TRAFFIC["fetch_kib"] + 1.0 * SCHUR_TRAFFIC["write_kib"])
 
     out = {
         "metric": "solves/s to 1e-10 rel. residual (FP64 vs mixed-prec); Schur-matvec HBM GB/s",
@@ -153,10 +188,40 @@ def main():
                                            "refinements": infobmx.refinements,
                                            "true_rel_residual_max": infobmx.rel_residual},
         },
-        "roofline": {"kernel": "k_schur_fwd (c2 grid)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": sch_ms * 1e3},
+        "roofline": {"kernel": "k_schur_mfma<false,16,1,double> (Schur apply, c2 grid, 1 column)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": sch_us},
     }
+
+    if not args.no_c3:
+        # batched workload: 64x64 elements, n = 12, 32 advected sources; plain FP64 one
+        # right-hand side at a time vs FP64 and mixed FP32 batched, all to 1e-10
+        w3 = wl.workload("c3")
+        c3 = smpm.Context.from_workload(w3)
+        x3, y3 = c3.node_coords()
+        F3 = torch.tensor(wl.advected_sources(wl.SEED_BASE + 3, x3, y3, count=w3.nrhs), device="cuda")
+
+        def s3_fp64(rhs):
+            return c3.solve(rhs, tol=1e-10, maxit=600)
+
+        def s3_mixed(rhs):
+            return c3.solve(rhs, tol=1e-10, maxit=600, precision=smpm.MIXED_FP32, inner_tol=1e-5, max_refine=30)
+
+        t1, i1, _ = timed(s3_fp64, F3[:1].contiguous(), 5, 1)
+        tb, ib, _ = timed(s3_fp64, F3, 3, 1)
+        tm, im, _ = timed(s3_mixed, F3, 3, 1)
+        out["batched_c3"] = {
+            "workload": "c3: 64x64 elements, n=12, [0,1]^2, r=589824, k=193536, d=8064 (substructured coarse "
+                        "solve), 32 advected random-Fourier sources + noise (std 1e-3), tol 1e-10",
+            "fp64_single_solves_per_s": 1.0 / t1, "fp64_single_iterations": i1.iterations,
+            "fp64_batched32_solves_per_s": w3.nrhs / tb, "fp64_batched32_iterations_max": ib.iterations,
+            "fp64_batched32_true_rel_residual_max": ib.rel_residual,
+            "mixed_fp32_batched32_solves_per_s": w3.nrhs / tm, "mixed_batched32_iterations": im.iterations,
+            "mixed_batched32_refinements": im.refinements, "mixed_batched32_true_rel_residual_max": im.rel_residual,
+            "mixed_batched_vs_fp64_single": (w3.nrhs / tm) * t1,
+        }
+        del c3, F3
 
     if not args.no_large:
         # Schur-apply bandwidth on a large grid with rotated cold buffers (> 256 MB MALL)
@@ -172,18 +237,14 @@ def main():
 
             def one():
                 i = it["i"] % nbuf
-                big.schur_apply_into(ins[i], outs[i], stream=stream)
+                big.schur_apply_into(ins[i], outs[i])
                 it["i"] += 1
 
-            for _ in range(nbuf):
-                one()
-            ms_big = event_time_ms(one, stream, max(20, 5 * nbuf))
+            us = graph_time_us(one, nbuf, replays=max(4, 200 // nbuf))
             bbytes = 2 * nrhs * kb * 8 + op_big
             return {"grid": "128x128 elements, n=16, [0,1]^2, k=%d" % kb, "columns": nrhs,
-                    "buffers_rotated": nbuf, "avg_launch_us": ms_big * 1e3,
-                    "alg_bytes_per_launch": bbytes,
-                    "GB_s": bbytes / (ms_big * 1e-3) / 1e9,
-                    "frac_of_8TBs": bbytes / (ms_big * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                    "buffers_rotated": nbuf, "avg_launch_us": us, "alg_bytes_per_launch": bbytes,
+                    "GB_s": bbytes / (us * 1e-6) / 1e9, "frac_of_8TBs": bbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
 
         out["schur_large"] = large(1)
         out["schur_large_batched8"] = large(8)

@@ -106,10 +106,13 @@ typedef struct smpm_solve_opts {
   int transpose;      /* 1: adjoint of the solution map (see smpm_solve; g must be NULL)           */
   int variant;        /* 3: deflated + block-Jacobi (Algorithm 3), 2: block-Jacobi only
                          (Algorithm 2), 1: unpreconditioned (Algorithm 1); default 3               */
-  double inner_tol;   /* mixed precision: inner GMRES tolerance per refinement cycle (1e-4)      */
+  double inner_tol;   /* mixed precision: inner GMRES tolerance per refinement cycle (1e-5: two
+                         cycles reach 1e-10 with about the FP64 iteration count)               */
   int max_refine;     /* mixed precision: maximum refinement cycles (default 20)                 */
   int graph;          /* 1: the Arnoldi steps run as replays of a captured hipGraph of 8 steps
                          (captured once per solve shape and context); 0: launched one by one.
+                         (Environment SMPM_PREREDUCE=0/1 forces how the orthogonalization
+                         sums are reduced: once per column or in every block.)
                          Results are identical (default 1)                                        */
 } smpm_solve_opts;
 

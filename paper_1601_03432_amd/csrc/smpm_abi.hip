@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -75,7 +76,7 @@ struct smpm_ctx {
   // captured chunks of Arnoldi steps, keyed by the solve's shape; they hold workspace
   // pointers, so a workspace reallocation drops them
   struct GraphEntry {
-    int nrhs, kind, tr, sprec, mprec, maxit;
+    int nrhs, kind, tr, sprec, mprec, maxit, prereduce;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
@@ -388,6 +389,10 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.rows = W.rows;
   S.tolv = W.tolv;
   S.jdev = W.jdev;
+  // redundant per-block reductions cost (blocks x chunks x vectors) loads; past about
+  // a thousand blocks per kernel they are done once per column by small kernels
+  S.prereduce = (int64_t)S.nch * nrhs > 1024 ? 1 : 0;
+  if (const char* e = std::getenv("SMPM_PREREDUCE")) S.prereduce = e[0] == '1' ? 1 : e[0] == '0' ? 0 : S.prereduce;
   S.bref2 = W.scal2 + 2 * nrhs;
   return S;
 }
@@ -399,7 +404,7 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
                 hipGraphExec_t* out) {
   for (const auto& g : c->graphs)
     if (g.nrhs == nrhs && g.kind == kind && g.tr == (int)tr && g.sprec == sprec && g.mprec == mprec &&
-        g.maxit == S.maxit) {
+        g.maxit == S.maxit && g.prereduce == S.prereduce) {
       *out = g.exec;
       return SMPM_OK;
     }
@@ -417,7 +422,7 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
     (void)hipGraphExecDestroy(c->graphs.front().exec);
     c->graphs.erase(c->graphs.begin());
   }
-  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, exec});
+  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, S.prereduce, exec});
   *out = exec;
   return SMPM_OK;
 }
@@ -809,7 +814,7 @@ void smpm_default_opts(smpm_solve_opts* o) {
   o->precision = SMPM_FP64;
   o->transpose = 0;
   o->variant = 3;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 1e-5;
   o->max_refine = 20;
   o->graph = 1;
 }

@@ -44,6 +44,9 @@ struct GmState {
   int rows;         // rows per chunk
   double* tolv;     // relative stopping tolerance (device scalar, set by gm_start)
   int* jdev;        // index j of the next Arnoldi step (device counter, two slots)
+  int prereduce;    // 1: h1, h2 and beta are reduced once per column by small kernels
+                    // (large grids x many columns); 0: every consumer block reduces
+                    // the partials itself (fewer launches).  Same summation order.
   const double* bref2;  // squared reference norm per column (|b|^2): stop when |g| <= tol |b|
 };
 

@@ -159,10 +159,14 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int pa
   if (j > S.maxit) return;
   // second Gram-Schmidt pass of the previous step: h2 and beta (see the file header)
   const int nh = j;  // h2 has j entries (none before the first step)
-  if (nh > 0) reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, nh, S.nch, h2s);
-  __syncthreads();
   double beta;
-  {
+  if (S.prereduce && nh > 0) {
+    for (int i = tid; i < nh; i += kThreads) h2s[i] = S.h2[(int64_t)col * S.ldv + i];
+    __syncthreads();
+    beta = S.beta_cur[col];
+  } else {
+    if (nh > 0) reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, nh, S.nch, h2s);
+    __syncthreads();
     if (tid < 64) {
       double acc = 0.0, hh = 0.0;
       for (int c = tid; c < S.nch; c += 64) acc += S.part3[(int64_t)col * S.nch + c];
@@ -292,11 +296,16 @@ __global__ __launch_bounds__(256) void k_gm_orth2(DevPlan P, GmState S, int par)
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const int nvec = j + 1;
-  reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, nvec, S.nch, hs);
-  __syncthreads();
-  if (chunk == 0) {
-    double* hdst = S.h1 + (int64_t)col * S.ldv;
-    for (int i = tid; i < nvec; i += kThreads) hdst[i] = hs[i];
+  if (S.prereduce) {
+    for (int i = tid; i < nvec; i += kThreads) hs[i] = S.h1[(int64_t)col * S.ldv + i];
+    __syncthreads();
+  } else {
+    reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, nvec, S.nch, hs);
+    __syncthreads();
+    if (chunk == 0) {
+      double* hdst = S.h1 + (int64_t)col * S.ldv;
+      for (int i = tid; i < nvec; i += kThreads) hdst[i] = hs[i];
+    }
   }
   double* wc = S.w + (int64_t)col * k;
   const double* Vc = S.V + (int64_t)col * k;
@@ -315,6 +324,37 @@ __global__ __launch_bounds__(256) void k_gm_orth2(DevPlan P, GmState S, int par)
   chunk_dots(Vc, S.vvs, x0, rows, wv, nvec, S.part2 + (int64_t)col * S.ldv * S.nch, S.nch, chunk);
   const double bs = block_sum(nrm, red);
   if (tid == 0) S.part3[(int64_t)col * S.nch + chunk] = bs;
+}
+
+// Pre-reduction (one block per column): h1 from gm_orth1's partials.
+__global__ __launch_bounds__(256) void k_gm_reduce_h1(GmState S, int par) {
+  __shared__ double hs[kMaxIt + 1];
+  const int col = blockIdx.y;
+  if (!S.active[col]) return;
+  const int nvec = S.jdev[par] + 1;
+  reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, nvec, S.nch, hs);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nvec; i += kThreads) S.h1[(int64_t)col * S.ldv + i] = hs[i];
+}
+
+// Pre-reduction after gm_orth2: h2 and beta for the next step, summed exactly as
+// gm_precond sums them itself.
+__global__ __launch_bounds__(256) void k_gm_reduce_beta(GmState S, int par) {
+  __shared__ double hs[kMaxIt + 1];
+  const int col = blockIdx.y, tid = threadIdx.x;
+  if (!S.active[col]) return;
+  const int nh = S.jdev[par] + 1;
+  reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, nh, S.nch, hs);
+  __syncthreads();
+  for (int i = tid; i < nh; i += kThreads) S.h2[(int64_t)col * S.ldv + i] = hs[i];
+  if (tid < 64) {
+    double acc = 0.0, hh = 0.0;
+    for (int c = tid; c < S.nch; c += 64) acc += S.part3[(int64_t)col * S.nch + c];
+    for (int i = tid; i < nh; i += 64) hh = fma(hs[i], hs[i], hh);
+    acc = wave_sum(acc);
+    hh = wave_sum(hh);
+    if (tid == 0) S.beta_cur[col] = sqrt(fmax(acc - hh, 0.0));
+  }
 }
 
 // Start of a solve: partial |w|^2 of the initial residual; all columns active;
@@ -407,7 +447,9 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
   }
   hipLaunchKernelGGL(k_gm_orth1, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
                      tr ? 1 : 0);
+  if (S.prereduce) hipLaunchKernelGGL(k_gm_reduce_h1, dim3(1, nrhs), dim3(kThreads), 0, s, S, par);
   hipLaunchKernelGGL(k_gm_orth2, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par);
+  if (S.prereduce) hipLaunchKernelGGL(k_gm_reduce_beta, dim3(1, nrhs), dim3(kThreads), 0, s, S, par);
 }
 
 void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s) {

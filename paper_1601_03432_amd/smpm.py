@@ -272,7 +272,7 @@ class Context:
         return out
 
     def solve(self, f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64, transpose=False,
-              inner_tol=1e-4, max_refine=20, stream=None, raise_on_noconv=True, graph=True):
+              inner_tol=1e-5, max_refine=20, stream=None, raise_on_noconv=True, graph=True):
         import torch
         f = self._as_cols(f, self.r)
         nrhs = f.shape[0]
@@ -338,7 +338,7 @@ def _schur_solve_function():
 
 
 def solve_differentiable(solver: "Context", f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64,
-                         inner_tol=1e-4, max_refine=20):
+                         inner_tol=1e-5, max_refine=20):
     """u = solver.solve(f, g) as a differentiable torch operation: its backward pass is
     the adjoint solve of the library (transposed Algorithm 3), so autograd gives
     dLoss/df and dLoss/dg.  f: (r,) or (nrhs, r); g: None or matching (.., nbdry)."""

@@ -231,3 +231,18 @@ def test_graph_replays_match_eager(mode):
         ctx.schur_apply(dev(wl.random_vectors(70 + rep, 2, ctx.k)))
         ctx.solve(F[:1], graph=False, **kw)
         torch.cuda.synchronize()
+
+
+def test_prereduced_sums_match_per_block_sums(monkeypatch):
+    """The orthogonalization sums reduced once per column (large batched grids) and
+    reduced by every consumer block (small grids) add the same partials in the same
+    order: the solutions agree bit for bit."""
+    ctx, m = setup("ragged_9x7")
+    g = m.grid
+    F = dev(np.stack([_problem(g, 80 + i, with_g=False)[0] for i in range(4)]))
+    sols = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("SMPM_PREREDUCE", flag)
+        u, info = ctx.solve(F, tol=1e-11, maxit=600)
+        sols.append((u, info.iterations))
+    assert torch.equal(sols[0][0], sols[1][0]) and sols[0][1] == sols[1][1]
