@@ -195,6 +195,13 @@ int smpm_null_vectors(smpm_ctx *ctx, double *uL, double *uS);
 int smpm_schur_apply(smpm_ctx *ctx, const double *v, double *Sv, int nrhs, int transpose,
                      void *stream);
 
+/* As smpm_schur_apply with the operator precision of a mixed-precision solve:
+ * SMPM_MIXED_FP32 / SMPM_MIXED_BF16 use the FP32 / BF16 copies of the element
+ * operators with FP32 accumulation (the matrix-core path of the refinement's inner
+ * solves); vectors stay FP64.  SMPM_FP64 is smpm_schur_apply. */
+int smpm_schur_apply_prec(smpm_ctx *ctx, const double *v, double *Sv, int nrhs, int transpose,
+                          int precision, void *stream);
+
 /* y = M^{-1} x (or M^{-T} x): the block-Jacobi preconditioner of Sec. 2 with
  * checkerboard blocks (red element slots plus the neighbours' facing slots). */
 int smpm_precond_apply(smpm_ctx *ctx, const double *x, double *y, int nrhs, int transpose,

@@ -751,6 +751,20 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   rc |= upload(c, p.tile_src, &d.tile_src, s);
   rc |= upload(c, p.tile_dst, &d.tile_dst, s);
   d.mma_mt = p.mma_mt;
+  for (int q = 0; q < 4; ++q) d.schur_nc[q] = 0;
+  d.schur_pers = 0;
+  if (const char* e = std::getenv("SMPM_SCHUR_PERSIST")) d.schur_pers = std::atoi(e) > 0 ? 1 : std::atoi(e) < 0 ? -1 : 0;
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->dev_id) != hipSuccess || ncu <= 0)
+      ncu = 256;
+    d.num_cu = ncu;
+  }
+  if (const char* e = std::getenv("SMPM_SCHUR_NC")) {  // sweep hook: fixed columns per workgroup
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4)
+      for (int q = 0; q < 4; ++q) d.schur_nc[q] = v;
+  }
   rc |= upload(c, p.Afwd, &d.Afwd, s);
   rc |= upload(c, p.Aadj, &d.Aadj, s);
   rc |= upload(c, to_f32(p.Afwd), &d.AfwdF, s);
@@ -1005,6 +1019,20 @@ int smpm_schur_apply(smpm_ctx* c, const double* v, double* Sv, int nrhs, int tra
   const size_t bytes = sizeof(double) * c->plan.k * nrhs;
   if (aliases(v, bytes, Sv, bytes)) return fail(SMPM_EINVAL, "input and output alias");
   launch_schur(c->dp, v, Sv, nrhs, transpose != 0, nullptr, static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return SMPM_OK;
+}
+
+int smpm_schur_apply_prec(smpm_ctx* c, const double* v, double* Sv, int nrhs, int transpose, int precision,
+                          void* stream) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!v || !Sv || nrhs < 1) return fail(SMPM_EINVAL, "bad vector arguments");
+  if (precision < SMPM_FP64 || precision > SMPM_MIXED_BF16) return fail(SMPM_EINVAL, "unknown precision");
+  const size_t bytes = sizeof(double) * c->plan.k * nrhs;
+  if (aliases(v, bytes, Sv, bytes)) return fail(SMPM_EINVAL, "input and output alias");
+  const int prec = precision == SMPM_MIXED_FP32 ? PREC_F32 : precision == SMPM_MIXED_BF16 ? PREC_BF16 : PREC_F64;
+  launch_schur_ex(c->dp, v, Sv, nrhs, transpose != 0, nullptr, nullptr, static_cast<hipStream_t>(stream), prec);
   HIPCHK(hipGetLastError());
   return SMPM_OK;
 }

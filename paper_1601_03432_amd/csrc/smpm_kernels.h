@@ -85,6 +85,11 @@ struct DevPlan {
   const int* tile_src;     // ntile*kTile: first slot of the element, -1 if none
   const int* tile_dst;     // ntile*kTile*4: first slot facing side s, -1 if none
   int mma_mt;              // 16-row tiles of the matrix-core operator fragments (0: n > 16)
+  int schur_nc[4];         // right-hand-side columns per Schur workgroup for 1, 2-3, 4-7 and
+                           // >= 8 columns (0: built-in choice); set by the autotuner
+  int schur_pers;          // persistent Schur apply: -1 never, 0 when items >= 2x resident
+                           // workgroups, 1 always (no side sums)
+  int num_cu;              // compute units of the device
   const double* Afwd;      // [cls][w][q][lane] fragments of W (forward) and W^T (transpose)
   const double* Aadj;
   const float* AfwdF;
@@ -159,6 +164,10 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
                      const int* active, double* side_sums, hipStream_t s, int prec = PREC_F64);
 bool schur_has_side_sums(const DevPlan& P);
+int schur_nc_class(int nrhs);  // index into DevPlan::schur_nc
+// persistent, pipelined Schur apply (no side sums); false if the plain launch is used
+bool launch_schur_pers(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
+                       hipStream_t s, int prec);
 
 // c2 = G c with c_j = side_sums of interface j's two sides
 void launch_coarse_sides(const DevPlan& P, const double* side_sums, double* c2, int nrhs, bool transpose,

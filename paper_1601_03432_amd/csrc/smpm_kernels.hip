@@ -379,6 +379,162 @@ __global__ __launch_bounds__(256) void k_schur_mfma(DevPlan P, const double* __r
   }
 }
 
+// Persistent, software-pipelined variant (no side sums).  Work items are (tile,
+// column group) pairs, tile-major; each XCD walks one contiguous slice of them (its
+// blocks are those with blockIdx.x % 8 equal to the XCD) with one item per block in
+// turn.  While the products and stores of one item run, the next item's y is already
+// being loaded into registers, and the class operator fragments stay in registers
+// across items of one class.  Results go through a separate LDS region, so the
+// staged Y tile is only rewritten after a barrier.
+template <bool ADJ, int KT, int NC, typename OpT>
+__global__ __launch_bounds__(256) void k_schur_mfma_pers(DevPlan P, const double* __restrict__ y,
+                                                         double* __restrict__ t, int nrhs,
+                                                         const int* __restrict__ active, int ncg) {
+  using Acc = typename AccOf<OpT>::type;
+  using M = Mma<Acc>;
+  constexpr int kRows = 4 * KT;
+  constexpr int kPer = kTile * kRows / (16 * KT);
+  constexpr int kWaves = KT / 4;
+  extern __shared__ double lds[];
+  Acc* ys = reinterpret_cast<Acc*>(lds);          // [NC][kRows][kTileLd]
+  Acc* rs = ys + NC * kRows * kTileLd;             // [NC][kWaves][kTile][kTileLd]
+  const int n = P.n, no = 4 * n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int row = lane & 15, mr = wave * 16 + row;
+  const int srow = min(mr / n, 3);
+  const int64_t nitems = (int64_t)P.ntile * ncg;
+  const int xcd = blockIdx.x & 7, nbx = gridDim.x >> 3;
+  const int64_t hi = nitems * (xcd + 1) / 8;
+  int64_t item = nitems * xcd / 8 + (blockIdx.x >> 3);
+  if (item >= hi) return;
+
+  // index tables and y loads of one item (see k_schur_mfma for the mappings)
+  auto prepare = [&](int64_t it, int& c0, int& J, bool (&on)[NC], int (&slot)[4], int (&gi)[kPer]) {
+    const int tile = (int)(it / ncg);
+    c0 = (int)(it - (int64_t)tile * ncg) * NC;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) on[c] = c0 + c < nrhs && (!active || active[c0 + c]);
+    J = P.tile_cls[tile];
+    const int ns = P.cls_nslots[J];
+    const int kdim = ADJ ? no : ns;
+    const int* src = P.tile_src + tile * kTile;
+    const int* dst = P.tile_dst + tile * kTile * 4;
+    int tb[4], sb[kPer];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int uu = (lane >> 4) + 4 * v;
+      tb[v] = ADJ ? src[uu] : dst[uu * 4 + srow];
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int q = tid + j * 16 * KT;
+      const int uu = q / kRows, kk = q - uu * kRows;
+      sb[j] = ADJ ? dst[uu * 4 + min(kk / n, 3)] : src[uu];
+    }
+    const bool row_ok = ADJ ? mr < ns : mr < no;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) slot[v] = row_ok && tb[v] >= 0 ? tb[v] + (ADJ ? mr : mr - srow * n) : -1;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int q = tid + j * 16 * KT;
+      const int uu = q / kRows, kk = q - uu * kRows;
+      const int s = kk / n;
+      const bool ok = sb[j] >= 0 && kk < kdim;
+      gi[j] = ok ? sb[j] + (ADJ ? kk - s * n : kk) : -1;
+    }
+  };
+  auto load = [&](int c0, const bool (&on)[NC], const int (&slot)[4], const int (&gi)[kPer],
+                  double (&st)[NC][kPer], double (&yv)[NC][4]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double* yc = y + (int64_t)(on[c] ? c0 + c : 0) * P.k;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) st[c][j] = yc[max(gi[j], 0)];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) yv[c][v] = yc[max(slot[v], 0)];
+    }
+  };
+
+  int c0, J;
+  bool on[NC];
+  int slot[4], gi[kPer];
+  double st[NC][kPer], yv[NC][4];
+  prepare(item, c0, J, on, slot, gi);
+  load(c0, on, slot, gi, st, yv);
+  int Ja = -1;
+  Acc a[KT];
+  while (true) {
+    if (J != Ja) {  // uniform over the workgroup
+      const OpT* Af = mma_op<OpT>(P, ADJ) + ((int64_t)(J * P.mma_mt + wave) * KT) * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < KT; ++q) a[q] = to_acc(Af[q * 64]);
+      Ja = J;
+    }
+    __syncthreads();  // the previous item is done with ys and rs
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int q = tid + j * 16 * KT;
+        const int uu = q / kRows, kk = q - uu * kRows;
+        ys[(c * kRows + kk) * kTileLd + uu] = gi[j] >= 0 ? (Acc)st[c][j] : Acc(0);
+      }
+    __syncthreads();
+    // the next item's loads fly while this item's products and stores run
+    const int64_t nxt = item + nbx;
+    const bool more = nxt < hi;
+    int c0n = 0, Jn = J;
+    bool onn[NC];
+    int slotn[4], gin[kPer];
+    double stn[NC][kPer], yvn[NC][4];
+    if (more) {
+      prepare(nxt, c0n, Jn, onn, slotn, gin);
+      load(c0n, onn, slotn, gin, stn, yvn);
+    }
+    typename M::V acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      acc[c] = typename M::V{0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < KT; ++q)
+        acc[c] = M::mma(a[q], ys[(c * kRows + 4 * q + (lane >> 4)) * kTileLd + (lane & 15)], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        rs[((c * kWaves + wave) * kTile + (lane & 15)) * kTileLd + M::row(lane, v)] = acc[c][v];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (!on[c]) continue;
+      double* tc = t + (int64_t)(c0 + c) * P.k;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int uu = (lane >> 4) + 4 * v;
+        const double tv = yv[c][v] + (double)rs[((c * kWaves + wave) * kTile + uu) * kTileLd + row];
+        if (slot[v] >= 0) tc[slot[v]] = tv;
+      }
+    }
+    if (!more) break;
+    item = nxt;
+    c0 = c0n;
+    J = Jn;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      on[c] = onn[c];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) st[c][j] = stn[c][j];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) yv[c][v] = yvn[c][v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) slot[v] = slotn[v];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) gi[j] = gin[j];
+  }
+}
+
 // ------------------------------------------------------------------ B A^{-1} and its transpose
 
 __global__ __launch_bounds__(64) void k_flux(DevPlan P, const double* __restrict__ f, double* __restrict__ b) {
@@ -905,6 +1061,63 @@ size_t sub_patch_lds(const DevPlan& P) { return (size_t)P.sub_lds_max * sizeof(d
 
 bool schur_has_side_sums(const DevPlan& P) { return 4 * P.n <= 64; }
 
+// Persistent Schur apply when there are enough work items for every resident workgroup
+// to take at least two (or when forced by P.schur_pers > 0).  Returns false if the plain
+// launch should be used instead.
+template <int KT, int NC, typename T>
+static bool pers_launch(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
+                        const int* active, hipStream_t s) {
+  const size_t lds = (size_t)2 * NC * 4 * KT * kTileLd * sizeof(typename AccOf<T>::type);
+  const int ncg = (nrhs + NC - 1) / NC;
+  const int64_t nitems = (int64_t)P.ntile * ncg;
+  static int occ[2] = {0, 0};  // resident workgroups per CU, per direction
+  int& oc = occ[transpose ? 1 : 0];
+  if (oc == 0) {
+    int v = 0;
+    const hipError_t e = transpose
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_schur_mfma_pers<true, KT, NC, T>, 16 * KT, lds)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_schur_mfma_pers<false, KT, NC, T>, 16 * KT, lds);
+    oc = (e == hipSuccess && v > 0) ? v : 1;
+  }
+  const int64_t resident = (int64_t)P.num_cu * oc;
+  if (P.schur_pers == 0 && nitems < 2 * resident) return false;
+  int64_t blocks = std::min<int64_t>(resident, nitems);
+  blocks = (blocks + 7) / 8 * 8;
+  const dim3 g((unsigned)blocks), b(16 * KT);
+  if (transpose)
+    hipLaunchKernelGGL((k_schur_mfma_pers<true, KT, NC, T>), g, b, lds, s, P, y, t, nrhs, active, ncg);
+  else
+    hipLaunchKernelGGL((k_schur_mfma_pers<false, KT, NC, T>), g, b, lds, s, P, y, t, nrhs, active, ncg);
+  return true;
+}
+
+template <int KT, typename T>
+static bool pers_nc(const DevPlan& P, const double* y, double* t, int nrhs, bool tr, const int* active,
+                    hipStream_t s) {
+  return nrhs >= 2 ? pers_launch<KT, 2, T>(P, y, t, nrhs, tr, active, s)
+                   : pers_launch<KT, 1, T>(P, y, t, nrhs, tr, active, s);
+}
+
+template <int KT>
+static bool pers_prec(const DevPlan& P, const double* y, double* t, int nrhs, bool tr, const int* active,
+                      hipStream_t s, int prec) {
+  if (prec == PREC_F32) return pers_nc<KT, float>(P, y, t, nrhs, tr, active, s);
+  if (prec == PREC_BF16) return pers_nc<KT, bf16s>(P, y, t, nrhs, tr, active, s);
+  return pers_nc<KT, double>(P, y, t, nrhs, tr, active, s);
+}
+
+bool launch_schur_pers(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
+                       hipStream_t s, int prec) {
+  switch (4 * P.mma_mt) {
+    case 4: return pers_prec<4>(P, y, t, nrhs, transpose, active, s, prec);
+    case 8: return pers_prec<8>(P, y, t, nrhs, transpose, active, s, prec);
+    case 12: return pers_prec<12>(P, y, t, nrhs, transpose, active, s, prec);
+    default: return pers_prec<16>(P, y, t, nrhs, transpose, active, s, prec);
+  }
+}
+
+int schur_nc_class(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 3 ? 1 : nrhs <= 7 ? 2 : 3; }
+
 void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
                   hipStream_t s) {
   launch_schur_ex(P, y, t, nrhs, transpose, active, nullptr, s);
@@ -913,13 +1126,19 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
                      double* side_sums, hipStream_t s, int prec) {
   if (transpose || !schur_has_side_sums(P)) side_sums = nullptr;
+  if (P.mma_mt > 0 && !side_sums && P.schur_pers >= 0 && launch_schur_pers(P, y, t, nrhs, transpose, active, s, prec))
+    return;
   if (P.mma_mt > 0) {
     // matrix-core path: one workgroup per tile and NC columns, one wavefront per 16 rows
     const int kt = 4 * P.mma_mt;
-    const int nc = nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
+    // columns per workgroup: the tuned value of this column-count class, capped at nrhs
+    const int tuned = P.schur_nc[schur_nc_class(nrhs)];
+    int nc = tuned > 0 ? tuned : (nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1);
+    while (nc > 1 && nc > nrhs) nc >>= 1;
     const size_t acc = prec == PREC_F64 ? sizeof(double) : sizeof(float);
+    // side-sum partials only when side sums are requested
     const size_t lds = ((size_t)nc * 4 * kt * kTileLd * acc + 7) / 8 * 8 +
-                       (size_t)nc * kTile * 4 * (kt / 4) * sizeof(double);
+                       (side_sums ? (size_t)nc * kTile * 4 * (kt / 4) * sizeof(double) : 0);
     const dim3 g((P.ntile + 7) / 8 * 8, (nrhs + nc - 1) / nc);
     const dim3 b(16 * kt);
 #define SMPM_MFMA_LAUNCH(KT, NC, T)                                                                       \

@@ -409,10 +409,10 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
     p.grp_size = Plan::kGroup;
     while (p.grp_size > 1 && (p.nel + p.grp_size - 1) / p.grp_size < 2048) p.grp_size /= 2;
     p.ngrp = cut(Plan::kGroup, p.grp_size, p.grp_cls, p.grp_elem);
-    // matrix-core tiles: 16 elements form the N side of a 16x16 product; small grids
-    // take narrower tiles (down to 4) to spread over more workgroups
+    // matrix-core tiles: 16 elements form the N side of a 16x16 product.  Narrower tiles
+    // would give small grids more workgroups but not a shorter one (the product and
+    // the loads per lane do not shrink), and they re-read the class operator per tile.
     p.tile_size = Plan::kTile;
-    while (p.tile_size > 4 && (p.nel + p.tile_size - 1) / p.tile_size < 1024) p.tile_size /= 2;
     p.ntile = cut(Plan::kTile, p.tile_size, p.tile_cls, p.tile_elem);
   }
 

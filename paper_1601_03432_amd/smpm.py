@@ -29,7 +29,8 @@ DEFAULT_PENALTY = 8.0
 ABI_SYMBOLS = (
     "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_stats", "smpm_slot_map",
     "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
-    "smpm_schur_apply", "smpm_precond_apply", "smpm_project", "smpm_solve", "smpm_boundary_transpose",
+    "smpm_schur_apply", "smpm_schur_apply_prec", "smpm_precond_apply", "smpm_project", "smpm_solve",
+    "smpm_boundary_transpose",
     "smpm_last_error",
 )
 
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     lib.smpm_export.argtypes = [vp, C.c_int, i64p, i64p, i64p, dp]
     lib.smpm_null_vectors.argtypes = [vp, dp, dp]
     lib.smpm_schur_apply.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp]
+    lib.smpm_schur_apply_prec.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]
     lib.smpm_precond_apply.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp]
     lib.smpm_project.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
     lib.smpm_solve.argtypes = [vp, vp, vp, vp, C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
@@ -252,6 +254,20 @@ class Context:
             raise ValueError("out must match v in shape and must not alias it")
         _check(self._lib.smpm_schur_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr()),
                                           v.shape[0], int(transpose), _stream(torch, stream)))
+        return out
+
+    def schur_apply_prec(self, v, out, precision, transpose=False, stream=None):
+        """S v into `out` with the element operators in `precision` (FP64, MIXED_FP32 or
+        MIXED_BF16; FP32 accumulation for the mixed ones); FP64 vectors."""
+        import torch
+        for t in (v, out):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                    and t.dim() == 2 and t.shape[1] == self.k and t.is_contiguous()):
+                raise ValueError(f"expected contiguous CUDA float64 tensors of shape (columns, {self.k})")
+        if out.shape != v.shape or out.data_ptr() == v.data_ptr():
+            raise ValueError("out must match v in shape and must not alias it")
+        _check(self._lib.smpm_schur_apply_prec(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr()),
+                                               v.shape[0], int(transpose), int(precision), _stream(torch, stream)))
         return out
 
     def precond_apply(self, x, transpose=False, stream=None):

@@ -246,3 +246,46 @@ def test_prereduced_sums_match_per_block_sums(monkeypatch):
         u, info = ctx.solve(F, tol=1e-11, maxit=600)
         sols.append((u, info.iterations))
     assert torch.equal(sols[0][0], sols[1][0]) and sols[0][1] == sols[1][1]
+
+
+_pers_cache = {}
+
+
+@pytest.mark.parametrize("name", ["c1", "stretched_4x3", "ragged_9x7", "two_2x1"])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("ncol", [1, 3])
+def test_schur_apply_persistent(name, transpose, ncol, monkeypatch):
+    """The persistent, pipelined Schur kernel (forced on; large grids choose it by
+    themselves) against the oracle's S, for one column and for a ragged column group."""
+    if name not in _pers_cache:
+        monkeypatch.setenv("SMPM_SCHUR_PERSIST", "1")
+        n, xb, yb = GRIDS[name]
+        _pers_cache[name] = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, O.DEFAULT_ALPHA, device=True)
+    ctx = _pers_cache[name]
+    _, m = setup(name)
+    V = wl.random_vectors(15, ncol, ctx.k)
+    S = m.sys.S
+    want = (S.T @ V.T).T if transpose else (S @ V.T).T
+    got = ctx.schur_apply(dev(V), transpose=transpose).cpu().numpy()
+    for c in range(ncol):
+        assert rel(got[c], want[c]) <= 1e-12, (name, c, rel(got[c], want[c]))
+
+
+@pytest.mark.parametrize("name", ["c1", "stretched_4x3", "ragged_9x7"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_schur_apply_low_precision(name, precision, transpose):
+    """S v with FP32 / BF16 element operators and FP32 accumulation against the oracle's
+    FP64 S.  Bound: the operator rounding (2^-24 resp. 2^-8 relative) accumulated over
+    at most 64 terms, applied to the B A^{-1} E part only (the identity part is FP64):
+    1e-5 for FP32, 2e-2 for BF16."""
+    ctx, m = setup(name)
+    V = wl.random_vectors(16, 3, ctx.k)
+    S = m.sys.S
+    want = (S.T @ V.T).T if transpose else (S @ V.T).T
+    prec = smpm.MIXED_FP32 if precision == "fp32" else smpm.MIXED_BF16
+    out = torch.empty(3, ctx.k, dtype=torch.float64, device="cuda")
+    got = ctx.schur_apply_prec(dev(V), out, prec, transpose=transpose).cpu().numpy()
+    bound = 1e-5 if precision == "fp32" else 2e-2
+    for c in range(3):
+        assert rel(got[c], want[c]) <= bound, (name, precision, c, rel(got[c], want[c]))
