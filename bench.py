@@ -76,6 +76,25 @@ def graph_time_us(launch, launches, replays=20):
     return start.elapsed_time(end) * 1e3 / (replays * launches)
 
 
+def schur_roofline(ctx):
+    """The metric kernel: the Schur apply (forward, FP64, one column) on the c2 grid,
+    timed with HIP events around replays of a captured graph of launches."""
+    import torch
+    v = torch.randn(1, ctx.k, dtype=torch.float64, device="cuda")
+    sv = torch.empty_like(v)
+    sch_us = graph_time_us(lambda: ctx.schur_apply_into(v, sv), 100)
+    op_bytes = ctx.stats()["schur_operator_bytes"]
+    alg_bytes = 2 * ctx.k * 8 + op_bytes
+    achieved = alg_bytes / (sch_us * 1e-6) / 1e9
+    traffic = None
+    if SCHUR_TRAFFIC and SCHUR_TRAFFIC.get("kernels_sha256") == kernels_sha256():
+        traffic = 1024 * (2.0 * SCHUR_TRAFFIC["fetch_kib"] + 1.0 * SCHUR_TRAFFIC["write_kib"])
+    return {"kernel": "k_schur_mfma<false,16,1,double> (Schur apply, c2 grid, 1 column)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes, "avg_launch_us": sch_us}
+
+
 def main():
     faulthandler.enable()
     ap = argparse.ArgumentParser()
@@ -89,6 +108,8 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 64x64, n=12 batched measurement")
     ap.add_argument("--cpu-solves", type=int, default=2)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="time only the metric kernel (no solves), e.g. for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
@@ -106,6 +127,9 @@ def main():
     params = wl.random_fourier_params(wl.SEED_BASE + 2, 20, 8)
     f_host = wl.eval_fourier(params, x, y, w.Lx, w.Ly)
     f = torch.tensor(f_host, device="cuda").reshape(1, -1)
+    if args.roofline_only:
+        print(json.dumps({"roofline": schur_roofline(ctx)}), flush=True)
+        return
 
     def solve_fp64(rhs):
         return ctx.solve(rhs, tol=1e-10, maxit=600)
@@ -125,6 +149,8 @@ def main():
         t1 = time.perf_counter()
         return (t1 - t0) / steps, info, u
 
+    # launch shapes chosen by the library's autotuner for one column and for the batch
+    tuned = {"1": ctx.autotune(1), str(args.batch): ctx.autotune(args.batch)}
     # the headline form is timed as the benchmark step; the other form beside it
     forms = {"fp64": solve_fp64, "mixed": solve_mixed}
     other = "mixed" if args.precision == "fp64" else "fp64"
@@ -144,17 +170,6 @@ def main():
     secb64, infob64, _ = timed(solve_fp64, fb, 3, 1)
     secbmx, infobmx, _ = timed(solve_mixed, fb, 3, 1)
 
-    # metric kernel: the Schur apply (forward, FP64, one column) on the c2 grid, timed
-    # with HIP events around replays of a captured graph of launches
-    v = torch.randn(1, ctx.k, dtype=torch.float64, device="cuda")
-    sv = torch.empty_like(v)
-    sch_us = graph_time_us(lambda: ctx.schur_apply_into(v, sv), 100)
-    op_bytes = ctx.stats()["schur_operator_bytes"]
-    alg_bytes = 2 * ctx.k * 8 + op_bytes
-    achieved = alg_bytes / (sch_us * 1e-6) / 1e9
-    traffic = None
-    if SCHUR_TRAFFIC and SCHUR_TRAFFIC.get("kernels_sha256") == kernels_sha256():
-        traffic = 1024 * (2.0 * SCHUR_TRAFFIC["fetch_kib"] + 1.0 * SCHUR_TRAFFIC["write_kib"])
 
     out = {
         "metric": "solves/s to 1e-10 rel. residual (FP64 vs mixed-prec); Schur-matvec HBM GB/s",
@@ -187,11 +202,9 @@ def main():
                                            "iterations_max": infobmx.iterations,
                                            "refinements": infobmx.refinements,
                                            "true_rel_residual_max": infobmx.rel_residual},
+            "autotuned": tuned,
         },
-        "roofline": {"kernel": "k_schur_mfma<false,16,1,double> (Schur apply, c2 grid, 1 column)",
-                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": sch_us},
+        "roofline": schur_roofline(ctx),
     }
 
     if not args.no_c3:
@@ -208,6 +221,7 @@ def main():
         def s3_mixed(rhs):
             return c3.solve(rhs, tol=1e-10, maxit=600, precision=smpm.MIXED_FP32, inner_tol=1e-5, max_refine=30)
 
+        tuned3 = {"1": c3.autotune(1), str(w3.nrhs): c3.autotune(w3.nrhs)}
         t1, i1, _ = timed(s3_fp64, F3[:1].contiguous(), 5, 1)
         tb, ib, _ = timed(s3_fp64, F3, 3, 1)
         tm, im, _ = timed(s3_mixed, F3, 3, 1)
@@ -220,6 +234,7 @@ def main():
             "mixed_fp32_batched32_solves_per_s": w3.nrhs / tm, "mixed_batched32_iterations": im.iterations,
             "mixed_batched32_refinements": im.refinements, "mixed_batched32_true_rel_residual_max": im.rel_residual,
             "mixed_batched_vs_fp64_single": (w3.nrhs / tm) * t1,
+            "autotuned": tuned3,
         }
         del c3, F3
 

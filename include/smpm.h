@@ -135,6 +135,17 @@ typedef struct smpm_plan_stats {
   int32_t has_coarse;             /* 1 if the deflated solve is available                        */
 } smpm_plan_stats;
 
+typedef struct smpm_tune_result {
+  int nrhs;                          /* column count the choice was made for (its class:
+                                        1, 2-3, 4-7 or >= 8 columns)                         */
+  int schur_columns_per_workgroup;   /* right-hand-side columns one Schur workgroup takes     */
+  int schur_persistent;              /* 1: persistent pipelined Schur kernel                  */
+  int prereduce;                     /* 1: Gram-Schmidt sums reduced once per column; 0: in
+                                        every consumer block; -1: not tuned (no coarse space) */
+  double schur_us;                   /* measured Schur apply time of the choice               */
+  double step_us;                    /* measured time per deflated Arnoldi step of the choice */
+} smpm_tune_result;
+
 /* Fills `opts` with the defaults listed above. */
 void smpm_default_opts(smpm_solve_opts *opts);
 
@@ -232,6 +243,16 @@ int smpm_solve(smpm_ctx *ctx, const double *f, const double *g, double *u, int n
  * on P'S^T M^{-T} with P' = Q^T, Q' = P^T and G^T, then mu = A^{-T}(c~ - B^T xi).
  * Then dLoss/df = mu and dLoss/dg = T^T mu (smpm_boundary_transpose).  The
  * stopping rule and the precision options are those of the forward solve. */
+
+/* Autotuner: times, on `stream`, the candidate launch shapes of the Schur apply
+ * (1, 2 or 4 right-hand-side columns per workgroup of the plain matrix-core kernel,
+ * or the persistent pipelined kernel) and the two ways of reducing the Gram-Schmidt
+ * sums (24 deflated Arnoldi steps each) for `nrhs` columns on this context's grid,
+ * and keeps the fastest for every later call with a column count of the same class.
+ * Every candidate computes each column with the same arithmetic in the same order,
+ * so results do not change.  Synchronous; allocates the solve workspace for nrhs.
+ * out may be NULL. */
+int smpm_autotune(smpm_ctx *ctx, int nrhs, void *stream, smpm_tune_result *out);
 
 /* dg = T^T mu for nrhs r-vectors mu: the gradient with respect to the Neumann
  * data (layout of g: south, north, west, east edges, 2n(m_x+m_y) per column)

@@ -81,6 +81,7 @@ struct smpm_ctx {
   };
   std::vector<GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;          // capture-only stream (default priority)
+  int prereduce_choice[4] = {-1, -1, -1, -1};  // per column-count class: -1 built-in rule, 0/1 tuned
   void drop_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     graphs.clear();
@@ -392,6 +393,7 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   // redundant per-block reductions cost (blocks x chunks x vectors) loads; past about
   // a thousand blocks per kernel they are done once per column by small kernels
   S.prereduce = (int64_t)S.nch * nrhs > 1024 ? 1 : 0;
+  if (c->prereduce_choice[schur_nc_class(nrhs)] >= 0) S.prereduce = c->prereduce_choice[schur_nc_class(nrhs)];
   if (const char* e = std::getenv("SMPM_PREREDUCE")) S.prereduce = e[0] == '1' ? 1 : e[0] == '0' ? 0 : S.prereduce;
   S.bref2 = W.scal2 + 2 * nrhs;
   return S;
@@ -752,8 +754,9 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   rc |= upload(c, p.tile_dst, &d.tile_dst, s);
   d.mma_mt = p.mma_mt;
   for (int q = 0; q < 4; ++q) d.schur_nc[q] = 0;
-  d.schur_pers = 0;
-  if (const char* e = std::getenv("SMPM_SCHUR_PERSIST")) d.schur_pers = std::atoi(e) > 0 ? 1 : std::atoi(e) < 0 ? -1 : 0;
+  for (int q = 0; q < 4; ++q) d.schur_pers[q] = 0;
+  if (const char* e = std::getenv("SMPM_SCHUR_PERSIST"))  // sweep hook
+    for (int q = 0; q < 4; ++q) d.schur_pers[q] = std::atoi(e) > 0 ? 1 : std::atoi(e) < 0 ? -1 : 0;
   {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->dev_id) != hipSuccess || ncu <= 0)
@@ -1034,6 +1037,95 @@ int smpm_schur_apply_prec(smpm_ctx* c, const double* v, double* Sv, int nrhs, in
   const int prec = precision == SMPM_MIXED_FP32 ? PREC_F32 : precision == SMPM_MIXED_BF16 ? PREC_BF16 : PREC_F64;
   launch_schur_ex(c->dp, v, Sv, nrhs, transpose != 0, nullptr, nullptr, static_cast<hipStream_t>(stream), prec);
   HIPCHK(hipGetLastError());
+  return SMPM_OK;
+}
+
+int smpm_autotune(smpm_ctx* c, int nrhs, void* stream, smpm_tune_result* out) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (nrhs < 1) return fail(SMPM_EINVAL, "nrhs must be positive");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  constexpr int kTuneIters = 24;
+  rc = ensure_ws(c, nrhs, kTuneIters);
+  if (rc) return rc;
+  Workspace& W = c->ws;
+  DevPlan& P = c->dp;
+  const int cls = schur_nc_class(nrhs);
+  const int64_t k = c->plan.k;
+  launch_fill_pattern(W.xacc, k * nrhs, s);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(SMPM_EHIP, "hipEventCreate failed");
+  }
+  auto time_us = [&](auto&& body, int reps) -> float {
+    for (int r = 0; r < 2; ++r) body();
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) body();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms * 1e3f / reps;
+  };
+  // 1. Schur launch shape, timed as the deflated Arnoldi step launches it (with the
+  //    fused per-side sums where the dense coarse solve consumes them): the plain
+  //    kernel with 1, 2 or 4 columns per workgroup, or the persistent kernel
+  const bool fused = schur_has_side_sums(P) && P.coarse_mode == 1;
+  struct Cand { int pers, nc; };
+  const Cand cands[] = {{-1, 1}, {-1, 2}, {-1, 4}, {1, 0}};
+  float best = 1e30f;
+  Cand pick{P.schur_pers[cls], P.schur_nc[cls]};
+  if (P.mma_mt > 0) {
+    for (const Cand& cd : cands) {
+      if (cd.nc > nrhs) continue;
+      if (cd.pers > 0 && fused) continue;  // the persistent kernel has no side sums
+      P.schur_pers[cls] = cd.pers;
+      P.schur_nc[cls] = cd.nc;
+      const float us =
+          time_us([&] { launch_schur_ex(P, W.xacc, W.t, nrhs, false, nullptr, fused ? W.sides : nullptr, s); }, 20);
+      if (us < best) {
+        best = us;
+        pick = cd;
+      }
+    }
+    P.schur_pers[cls] = pick.pers;
+    P.schur_nc[cls] = pick.nc;
+  }
+  c->drop_graphs();  // captured steps hold the launch shapes they were recorded with
+  rc = hipGetLastError() == hipSuccess ? SMPM_OK : fail(SMPM_EHIP, "Schur timing launch failed");
+  // 2. reduction of the Gram-Schmidt sums: kTuneIters deflated Arnoldi steps each way
+  float best_step = 1e30f;
+  int pre_pick = -1;
+  if (rc == SMPM_OK && c->plan.has_coarse) {
+    for (int pre = 0; pre < 2 && rc == SMPM_OK; ++pre) {
+      c->prereduce_choice[cls] = pre;
+      std::vector<int> it;
+      const float total = time_us(
+          [&] {
+            const int r = solve_schur(c, OP_PSM, false, W.xacc, W.bS, nrhs, 1e-300, kTuneIters, it, s);
+            if (r < 0 && rc == SMPM_OK) rc = r;
+          },
+          2);
+      if (total / kTuneIters < best_step) {
+        best_step = total / kTuneIters;
+        pre_pick = pre;
+      }
+    }
+    c->prereduce_choice[cls] = rc == SMPM_OK ? pre_pick : -1;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SMPM_OK) return rc;
+  if (out) {
+    out->nrhs = nrhs;
+    out->schur_columns_per_workgroup = pick.pers > 0 ? (nrhs >= 2 ? 2 : 1) : (pick.nc > 0 ? pick.nc : 1);
+    out->schur_persistent = pick.pers > 0 ? 1 : 0;
+    out->prereduce = pre_pick;
+    out->schur_us = best < 1e29f ? best : 0.0;
+    out->step_us = best_step < 1e29f ? best_step : 0.0;
+  }
   return SMPM_OK;
 }
 

@@ -87,8 +87,8 @@ struct DevPlan {
   int mma_mt;              // 16-row tiles of the matrix-core operator fragments (0: n > 16)
   int schur_nc[4];         // right-hand-side columns per Schur workgroup for 1, 2-3, 4-7 and
                            // >= 8 columns (0: built-in choice); set by the autotuner
-  int schur_pers;          // persistent Schur apply: -1 never, 0 when items >= 2x resident
-                           // workgroups, 1 always (no side sums)
+  int schur_pers[4];       // persistent Schur apply per column-count class: -1 never, 0 when
+                           // items >= 2x resident workgroups, 1 always (no side sums)
   int num_cu;              // compute units of the device
   const double* Afwd;      // [cls][w][q][lane] fragments of W (forward) and W^T (transpose)
   const double* Aadj;
@@ -189,6 +189,8 @@ void launch_prolong(const DevPlan& P, const double* t, const double* c2, double*
                     double sign, const int* active, hipStream_t s);
 void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, hipStream_t s);
 void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, hipStream_t s);  // dg = T^T mu
+
+void launch_fill_pattern(double* b, int64_t len, hipStream_t s);  // values in (-1, 1) for timing runs
 
 // ---- small results into pinned (mapped, coherent) host memory by a kernel
 void launch_publish(const double* src, int n, double* host_dst, hipStream_t s);

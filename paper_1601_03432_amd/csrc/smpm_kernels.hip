@@ -874,6 +874,17 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int
   if (i < len) b[i] = a[i];
 }
 
+// deterministic test pattern in (-1, 1) (hash of the index), for timing runs
+__global__ void k_fill_pattern(double* __restrict__ b, int64_t len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  b[i] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
 // rhs[node] += tau g over boundary entries [b0, b1) (a range whose nodes are distinct)
 __global__ void k_bdry_add(DevPlan P, const double* __restrict__ g, double* __restrict__ rhs, int64_t b0, int64_t b1) {
   const int col = blockIdx.y;
@@ -1062,7 +1073,7 @@ size_t sub_patch_lds(const DevPlan& P) { return (size_t)P.sub_lds_max * sizeof(d
 bool schur_has_side_sums(const DevPlan& P) { return 4 * P.n <= 64; }
 
 // Persistent Schur apply when there are enough work items for every resident workgroup
-// to take at least two (or when forced by P.schur_pers > 0).  Returns false if the plain
+// to take at least two (or when forced by a positive P.schur_pers of the class).  Returns false if the plain
 // launch should be used instead.
 template <int KT, int NC, typename T>
 static bool pers_launch(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
@@ -1080,7 +1091,7 @@ static bool pers_launch(const DevPlan& P, const double* y, double* t, int nrhs, 
     oc = (e == hipSuccess && v > 0) ? v : 1;
   }
   const int64_t resident = (int64_t)P.num_cu * oc;
-  if (P.schur_pers == 0 && nitems < 2 * resident) return false;
+  if (P.schur_pers[schur_nc_class(nrhs)] == 0 && nitems < 2 * resident) return false;
   int64_t blocks = std::min<int64_t>(resident, nitems);
   blocks = (blocks + 7) / 8 * 8;
   const dim3 g((unsigned)blocks), b(16 * KT);
@@ -1126,7 +1137,7 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
                      double* side_sums, hipStream_t s, int prec) {
   if (transpose || !schur_has_side_sums(P)) side_sums = nullptr;
-  if (P.mma_mt > 0 && !side_sums && P.schur_pers >= 0 && launch_schur_pers(P, y, t, nrhs, transpose, active, s, prec))
+  if (P.mma_mt > 0 && !side_sums && P.schur_pers[schur_nc_class(nrhs)] >= 0 && launch_schur_pers(P, y, t, nrhs, transpose, active, s, prec))
     return;
   if (P.mma_mt > 0) {
     // matrix-core path: one workgroup per tile and NC columns, one wavefront per 16 rows
@@ -1280,6 +1291,10 @@ void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, h
 }
 
 int reduce_chunks(int64_t len) { return (int)((len + kChunk - 1) / kChunk); }
+
+void launch_fill_pattern(double* b, int64_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_pattern, grid1(len, 256), dim3(256), 0, s, b, len);
+}
 
 void launch_publish(const double* src, int n, double* host_dst, hipStream_t s) {
   hipLaunchKernelGGL(k_publish, dim3((n + 255) / 256), dim3(256), 0, s, src, n, host_dst);

@@ -30,7 +30,7 @@ ABI_SYMBOLS = (
     "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_stats", "smpm_slot_map",
     "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
     "smpm_schur_apply", "smpm_schur_apply_prec", "smpm_precond_apply", "smpm_project", "smpm_solve",
-    "smpm_boundary_transpose",
+    "smpm_boundary_transpose", "smpm_autotune",
     "smpm_last_error",
 )
 
@@ -43,6 +43,11 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("refinements", C.c_int), ("rel_residual", C.c_double),
                 ("removed_component", C.c_double)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("nrhs", C.c_int), ("schur_columns_per_workgroup", C.c_int), ("schur_persistent", C.c_int),
+                ("prereduce", C.c_int), ("schur_us", C.c_double), ("step_us", C.c_double)]
 
 
 class PlanStats(C.Structure):
@@ -90,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     lib.smpm_project.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
     lib.smpm_solve.argtypes = [vp, vp, vp, vp, C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     lib.smpm_boundary_transpose.argtypes = [vp, vp, vp, C.c_int, vp]
+    lib.smpm_autotune.argtypes = [vp, C.c_int, vp, C.POINTER(TuneResult)]
     for name in ABI_SYMBOLS:
         if name not in ("smpm_destroy", "smpm_default_opts", "smpm_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -308,6 +314,14 @@ class Context:
         if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
             _check(rc)
         return u, Info(info.iterations, info.refinements, info.rel_residual, info.removed_component, rc)
+
+    def autotune(self, nrhs, stream=None):
+        """Time the launch-shape candidates for `nrhs` columns and keep the fastest
+        (see smpm_autotune); returns the choice as a dict."""
+        import torch
+        r = TuneResult()
+        _check(self._lib.smpm_autotune(self._h, int(nrhs), _stream(torch, stream), C.byref(r)))
+        return {name: getattr(r, name) for name, _ in TuneResult._fields_}
 
     def boundary_transpose(self, mu, stream=None):
         """T^T mu: the gradient with respect to the Neumann data (columns of length
