@@ -9,9 +9,11 @@ on [0,2]^2 (r = 65,536 nodes, k = 15,360 interface slots) with a seeded
 random-Fourier source.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line.  Besides the headline solves/s it reports the roofline of
-the dominant kernel (timed with HIP events on the stream the solve runs on),
-the Schur-apply HBM bandwidth on a 128 x 128, n = 16 grid with rotated cold
-buffers, and the CPU oracle timed on a bounded sample.
+the metric kernel, the Schur apply on the 128 x 128, n = 16 stretched grid with
+8 right-hand sides over rotated cold buffers (timed with HIP events around graph
+replays on the stream it is launched on), the batched and mixed-precision forms,
+the concurrent solve of the three side grids, and the CPU oracle timed on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -33,12 +35,12 @@ import smpm_workloads as wl  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-# HBM traffic of the Schur kernel on the c2 grid, from two rocprofv3 --pmc runs of
-# `python bench.py --steps 3 --warmup 1 --no-large --no-cpu-baseline` (FETCH_SIZE,
-# then WRITE_SIZE; KiB per dispatch of the single-column forward launch), each
-# scaled by the counter's reading for a plain kernel of known size (FETCH_SIZE reads
-# half of a 64 MiB elementwise read, so x2.0; WRITE_SIZE matches a 64 MiB fill, x1.0).
-# Valid only for the kernel source it was measured on (sha256 below); otherwise null.
+# HBM traffic of the metric kernel per launch, from two rocprofv3 --pmc runs of
+# `python bench.py --roofline-only` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch,
+# averaged over the timed launches), each scaled by the counter's reading for a
+# plain kernel of known size (FETCH_SIZE reads half of a 64 MiB elementwise read,
+# so x2.0; WRITE_SIZE matches a 64 MiB fill, x1.0).  Valid only for the kernel
+# source it was measured on (sha256 below); otherwise null.
 SCHUR_TRAFFIC = None  # {"fetch_kib": ..., "write_kib": ..., "kernels_sha256": "..."}
 
 
@@ -76,23 +78,57 @@ def graph_time_us(launch, launches, replays=20):
     return start.elapsed_time(end) * 1e3 / (replays * launches)
 
 
-def schur_roofline(ctx):
-    """The metric kernel: the Schur apply (forward, FP64, one column) on the c2 grid,
-    timed with HIP events around replays of a captured graph of launches."""
+def rotated_schur_us(ctx, ncol, pool_bytes=600e6):
+    """Average Schur-apply launch time over (v, Sv) buffer pairs rotated so that
+    the pool exceeds the 256 MB Infinity Cache: every launch streams from HBM."""
     import torch
-    v = torch.randn(1, ctx.k, dtype=torch.float64, device="cuda")
-    sv = torch.empty_like(v)
-    sch_us = graph_time_us(lambda: ctx.schur_apply_into(v, sv), 100)
-    op_bytes = ctx.stats()["schur_operator_bytes"]
-    alg_bytes = 2 * ctx.k * 8 + op_bytes
-    achieved = alg_bytes / (sch_us * 1e-6) / 1e9
+    nbuf = max(2, int(np.ceil(pool_bytes / (2 * ncol * ctx.k * 8))))
+    ins = [torch.randn(ncol, ctx.k, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+    outs = [torch.empty(ncol, ctx.k, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+    it = {"i": 0}
+
+    def one():
+        i = it["i"] % nbuf
+        ctx.schur_apply_into(ins[i], outs[i])
+        it["i"] += 1
+
+    us = graph_time_us(one, nbuf, replays=max(4, 200 // nbuf))
+    return us, nbuf
+
+
+def c5_context(smpm, w5):
+    """The large stretched grid's context with the metric kernel's launch shape fixed
+    (plain matrix-core kernel, 4 columns per workgroup: the fastest shape for 8
+    columns in the autotuner's timings), so every run times the same kernel."""
+    saved = {k: os.environ.get(k) for k in ("SMPM_SCHUR_NC", "SMPM_SCHUR_PERSIST")}
+    os.environ["SMPM_SCHUR_NC"], os.environ["SMPM_SCHUR_PERSIST"] = "4", "-1"
+    try:
+        return smpm.Context.from_workload(w5)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def schur_roofline(ctx5, ncol=8):
+    """The metric kernel: the FP64 Schur apply t = S y on the large stretched grid
+    (128 x 128 elements, n = 16) for its 8 right-hand sides, launched as
+    k_schur_mfma<false,16,4,double>.  Algorithmic bytes per launch: each column's y
+    read and t written once (2 k 8 B per column) plus every distinct element operator
+    once."""
+    us, nbuf = rotated_schur_us(ctx5, ncol)
+    alg_bytes = 2 * ncol * ctx5.k * 8 + ctx5.stats()["schur_operator_bytes"]
+    achieved = alg_bytes / (us * 1e-6) / 1e9
     traffic = None
     if SCHUR_TRAFFIC and SCHUR_TRAFFIC.get("kernels_sha256") == kernels_sha256():
         traffic = 1024 * (2.0 * SCHUR_TRAFFIC["fetch_kib"] + 1.0 * SCHUR_TRAFFIC["write_kib"])
-    return {"kernel": "k_schur_mfma<false,16,1,double> (Schur apply, c2 grid, 1 column)",
+    return {"kernel": "k_schur_mfma<false,16,4,double> (Schur apply, 128x128 n=16 stretched grid, %d columns, %d rotated buffer "
+                              "pairs)" % (ncol, nbuf),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "alg_bytes_per_launch": alg_bytes, "avg_launch_us": sch_us}
+            "alg_bytes_per_launch": alg_bytes, "avg_launch_us": us}
 
 
 def main():
@@ -127,8 +163,10 @@ def main():
     params = wl.random_fourier_params(wl.SEED_BASE + 2, 20, 8)
     f_host = wl.eval_fourier(params, x, y, w.Lx, w.Ly)
     f = torch.tensor(f_host, device="cuda").reshape(1, -1)
+    w5 = wl.workload("c5")
+    ctx5 = None if args.no_large and not args.roofline_only else c5_context(smpm, w5)
     if args.roofline_only:
-        print(json.dumps({"roofline": schur_roofline(ctx)}), flush=True)
+        print(json.dumps({"roofline": schur_roofline(ctx5)}), flush=True)
         return
 
     def solve_fp64(rhs):
@@ -204,8 +242,15 @@ def main():
                                            "true_rel_residual_max": infobmx.rel_residual},
             "autotuned": tuned,
         },
-        "roofline": schur_roofline(ctx),
     }
+    # the Schur apply on the c2 grid itself (one column, warm): latency-bound
+    v = torch.randn(1, ctx.k, dtype=torch.float64, device="cuda")
+    sv = torch.empty_like(v)
+    c2_us = graph_time_us(lambda: ctx.schur_apply_into(v, sv), 100)
+    c2_bytes = 2 * ctx.k * 8 + ctx.stats()["schur_operator_bytes"]
+    out["schur_c2"] = {"columns": 1, "avg_launch_us": c2_us, "alg_bytes_per_launch": c2_bytes,
+                       "GB_s": c2_bytes / (c2_us * 1e-6) / 1e9,
+                       "note": "385 KB per launch: bound by launch and wave latency, not HBM"}
 
     if not args.no_c3:
         # batched workload: 64x64 elements, n = 12, 32 advected sources; plain FP64 one
@@ -239,31 +284,70 @@ def main():
         del c3, F3
 
     if not args.no_large:
-        # Schur-apply bandwidth on a large grid with rotated cold buffers (> 256 MB MALL)
-        big = smpm.Context(128, 128, 16, wl.uniform_breaks(128), wl.uniform_breaks(128))
-        kb = big.k
-        op_big = big.stats()["schur_operator_bytes"]
+        out["roofline"] = schur_roofline(ctx5)
+        us1, _ = rotated_schur_us(ctx5, 1)
+        b1 = 2 * ctx5.k * 8 + ctx5.stats()["schur_operator_bytes"]
+        out["schur_c5_1col"] = {"avg_launch_us": us1, "GB_s": b1 / (us1 * 1e-6) / 1e9,
+                                "frac_of_8TBs": b1 / (us1 * 1e-6) / 1e9 / HBM_PEAK_GBS}
+        # the large uneven workload: 8 right-hand sides with nonzero Neumann data
+        x5, y5 = ctx5.node_coords()
+        F5, G5 = wl.c5_sources("c5", x5, y5, ctx5.boundary_arc(), w5.Lx, w5.Ly)
+        F5, G5 = torch.tensor(F5, device="cuda"), torch.tensor(G5, device="cuda")
+        tuned5 = {"1": ctx5.autotune(1), "8": ctx5.autotune(8)}
 
-        def large(nrhs):
-            nbuf = max(2, int(np.ceil(600e6 / (2 * nrhs * kb * 8))))
-            ins = [torch.randn(nrhs, kb, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
-            outs = [torch.empty(nrhs, kb, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
-            it = {"i": 0}
+        def s5(rhs, g, prec):
+            return ctx5.solve(rhs, g, tol=1e-10, maxit=600, precision=prec, inner_tol=1e-5, max_refine=30)
 
-            def one():
-                i = it["i"] % nbuf
-                big.schur_apply_into(ins[i], outs[i])
-                it["i"] += 1
+        t51, i51, _ = timed(lambda r: s5(r, G5[:1].contiguous(), smpm.FP64), F5[:1].contiguous(), 2, 1)
+        t5b, i5b, u5b = timed(lambda r: s5(r, G5, smpm.FP64), F5, 2, 1)
+        t5m, i5m, u5m = timed(lambda r: s5(r, G5, smpm.MIXED_FP32), F5, 2, 1)
+        out["c5"] = {
+            "workload": "c5: 128x128 elements, n=16, x-stretched (ratio 1.05, aspect <= 8) on [0,1]x[0,%.4f], "
+                        "r=%d, k=%d, d=%d (substructured coarse solve), 8 random-Fourier sources + nonzero "
+                        "Neumann data, tol 1e-10" % (w5.Ly, ctx5.r, ctx5.k, ctx5.d),
+            "fp64_single_solves_per_s": 1.0 / t51, "fp64_single_iterations": i51.iterations,
+            "fp64_batched8_solves_per_s": 8 / t5b, "fp64_batched8_iterations_max": i5b.iterations,
+            "fp64_batched8_true_rel_residual_max": i5b.rel_residual,
+            "mixed_fp32_batched8_solves_per_s": 8 / t5m, "mixed_batched8_iterations": i5m.iterations,
+            "mixed_batched8_refinements": i5m.refinements,
+            "mixed_batched8_final_schur_precision": ["fp64", "fp32", "bf16"][i5m.schur_precision],
+            "mixed_batched8_true_rel_residual_max": i5m.rel_residual,
+            "mixed_vs_fp64_rel_l2_max": float(max(torch.linalg.norm(u5m[c] - u5b[c]) / torch.linalg.norm(u5b[c])
+                                                  for c in range(8))),
+            "mixed_batched_vs_fp64_single": (8 / t5m) * t51,
+            "autotuned": tuned5,
+        }
+        del ctx5, F5, G5, u5b, u5m
+        # the three side grids, 8 right-hand sides each, as one concurrent group
+        side = []
+        for name in wl.C5_SIDE_GRIDS:
+            ws = wl.workload(name)
+            cs = smpm.Context.from_workload(ws)
+            xs, ys = cs.node_coords()
+            Fs, Gs = wl.c5_sources(name, xs, ys, cs.boundary_arc(), ws.Lx, ws.Ly)
+            cs.autotune(8)
+            side.append((cs, torch.tensor(Fs, device="cuda"), torch.tensor(Gs, device="cuda")))
+        gkw = dict(tol=1e-10, maxit=600, precision=smpm.MIXED_FP32, inner_tol=1e-5, max_refine=30)
 
-            us = graph_time_us(one, nbuf, replays=max(4, 200 // nbuf))
-            bbytes = 2 * nrhs * kb * 8 + op_big
-            return {"grid": "128x128 elements, n=16, [0,1]^2, k=%d" % kb, "columns": nrhs,
-                    "buffers_rotated": nbuf, "avg_launch_us": us, "alg_bytes_per_launch": bbytes,
-                    "GB_s": bbytes / (us * 1e-6) / 1e9, "frac_of_8TBs": bbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+        def group(_):
+            res = smpm.solve_group([c for c, _, _ in side], [f for _, f, _ in side], [g for _, _, g in side], **gkw)
+            return res[0][0], res[0][1]
 
-        out["schur_large"] = large(1)
-        out["schur_large_batched8"] = large(8)
-        del big
+        def sequential(_):
+            for c, f, g in side:
+                u, info = c.solve(f, g, **gkw)
+            return u, info
+
+        tg, _, _ = timed(group, None, 3, 1)
+        ts, _, _ = timed(sequential, None, 3, 1)
+        res = smpm.solve_group([c for c, _, _ in side], [f for _, f, _ in side], [g for _, _, g in side], **gkw)
+        out["c5_side_grids_group"] = {
+            "grids": "16x16 n=8, 32x32 n=12, 48x48 n=10 on [0,1]^2, 8 right-hand sides each, mixed FP32, tol 1e-10",
+            "group_solves_per_s": 24 / tg, "sequential_solves_per_s": 24 / ts,
+            "iterations": [i.iterations for _, i in res], "refinements": [i.refinements for _, i in res],
+            "true_rel_residual_max": max(i.rel_residual for _, i in res),
+        }
+        del side, res
 
     if not args.no_cpu_baseline:
         from oracle import smpm_oracle as O

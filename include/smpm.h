@@ -122,6 +122,12 @@ typedef struct smpm_solve_info {
   double rel_residual;      /* max over columns of the FP64 ||b_hat - S x|| / ||b_hat||          */
   double removed_component; /* column 0: u_L^T (f + T g), the projected-out incompatibility;
                                adjoint: (1^T c)/(w^T 1), the removed multiple of w            */
+  int schur_precision;      /* smpm_precision of the Schur operator in the last inner solve:
+                               a mixed solve raises it (BF16 -> FP32 -> FP64) when a
+                               refinement cycle contracts the residual too little         */
+  double cycle_residual[16];  /* mixed precision: max over columns of the FP64 true residual
+                                 at the start of refinement cycle i (i < 16; then the final
+                                 one); FP64: [0] = the final residual                      */
 } smpm_solve_info;
 
 typedef struct smpm_plan_stats {
@@ -243,6 +249,18 @@ int smpm_solve(smpm_ctx *ctx, const double *f, const double *g, double *u, int n
  * on P'S^T M^{-T} with P' = Q^T, Q' = P^T and G^T, then mu = A^{-T}(c~ - B^T xi).
  * Then dLoss/df = mu and dLoss/dg = T^T mu (smpm_boundary_transpose).  The
  * stopping rule and the precision options are those of the forward solve. */
+
+/* Solves several independent problems concurrently: problem i is smpm_solve(ctxs[i],
+ * f[i], g ? g[i] : NULL, u[i], nrhs[i], opts, infos ? &infos[i] : NULL) (same options
+ * for all; g[i] may be NULL).  The problems run on streams of their own, each driven by
+ * a host thread, ordered after the work already on `stream`, so the kernels of small
+ * grids overlap on the device.  The contexts must be distinct and on one device.
+ * Workspaces and null vectors are prepared first, in order (this synchronizes the
+ * device).  Returns the first hard error (message prefixed with the problem index),
+ * else SMPM_ENOCONV if a problem missed the tolerance, else SMPM_OK.  Synchronous. */
+int smpm_solve_group(smpm_ctx *const *ctxs, int nproblems, const double *const *f, const double *const *g,
+                     double *const *u, const int *nrhs, const smpm_solve_opts *opts,
+                     smpm_solve_info *infos, void *stream);
 
 /* Autotuner: times, on `stream`, the candidate launch shapes of the Schur apply
  * (1, 2 or 4 right-hand-side columns per workgroup of the plain matrix-core kernel,

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/smpm.h"
@@ -44,6 +45,7 @@ struct Workspace {
   // device-resident GMRES state
   double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr, *sides = nullptr;
   double *xacc = nullptr, *rho = nullptr;  // iterative refinement: solution and residual
+  double* xprev = nullptr;                  // iterate before the last correction
   double* cws = nullptr;                    // substructured coarse solve scratch
   double* tolv = nullptr;                   // device GMRES: tolerance and step counter
   int* jdev = nullptr;
@@ -81,6 +83,7 @@ struct smpm_ctx {
   };
   std::vector<GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;          // capture-only stream (default priority)
+  hipStream_t group_stream = nullptr;        // this problem's stream in smpm_solve_group
   int prereduce_choice[4] = {-1, -1, -1, -1};  // per column-count class: -1 built-in rule, 0/1 tuned
   void drop_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -90,6 +93,7 @@ struct smpm_ctx {
     if (device) {
       drop_graphs();
       if (cap_stream) (void)hipStreamDestroy(cap_stream);
+      if (group_stream) (void)hipStreamDestroy(group_stream);
       for (void* p : ws.mem) (void)hipFree(p);
       if (ws.pinned) (void)hipHostFree(ws.pinned);
       for (hipEvent_t e : ws.ev)
@@ -195,6 +199,7 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.part3, (size_t)w.nch * R);
   rc |= dalloc(w.mem, &w.sides, (size_t)P.nsides * R);
   rc |= dalloc(w.mem, &w.xacc, k * R);
+  rc |= dalloc(w.mem, &w.xprev, k * R);
   rc |= dalloc(w.mem, &w.rho, k * R);
   rc |= dalloc(w.mem, &w.beta_cur, R);
   rc |= dalloc(w.mem, &w.beta0, R);
@@ -1040,6 +1045,73 @@ int smpm_schur_apply_prec(smpm_ctx* c, const double* v, double* Sv, int nrhs, in
   return SMPM_OK;
 }
 
+int smpm_solve_group(smpm_ctx* const* ctxs, int nprob, const double* const* f, const double* const* g,
+                     double* const* u, const int* nrhs, const smpm_solve_opts* opts, smpm_solve_info* infos,
+                     void* stream) {
+  if (!ctxs || nprob < 1 || !f || !u || !nrhs) return fail(SMPM_EINVAL, "bad group arguments");
+  smpm_solve_opts o;
+  smpm_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.maxit < 1 || o.maxit > kMaxIt) return fail(SMPM_EINVAL, "bad solve options (1 <= maxit <= 1000)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < nprob; ++i) {
+    int rc = check_device(ctxs[i]);
+    if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + g_err);
+    if (ctxs[i]->dev_id != ctxs[0]->dev_id) return fail(SMPM_EINVAL, "group problems must share one device");
+    if (nrhs[i] < 1 || !f[i] || !u[i]) return fail(SMPM_EINVAL, "problem " + std::to_string(i) + ": bad vectors");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(SMPM_EINVAL, "a context appears twice in the group");
+  }
+  // Everything that allocates or synchronizes the device happens here, in order,
+  // before the problems run concurrently: null vectors, workspaces, streams.
+  for (int i = 0; i < nprob; ++i) {
+    smpm_ctx* c = ctxs[i];
+    int rc = compute_null_vectors(c, s);
+    if (!rc) rc = ensure_ws(c, nrhs[i], o.maxit);
+    if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + g_err);
+    if (!c->group_stream) HIPCHK(hipStreamCreateWithFlags(&c->group_stream, hipStreamNonBlocking));
+  }
+  hipEvent_t start;
+  HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  hipError_t he = hipEventRecord(start, s);
+  for (int i = 0; i < nprob && he == hipSuccess; ++i) he = hipStreamWaitEvent(ctxs[i]->group_stream, start, 0);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(start);
+    return fail(SMPM_EHIP, std::string("group stream ordering: ") + hipGetErrorString(he));
+  }
+  // one host thread per problem drives its solve on its own stream; the kernels of
+  // the problems overlap on the device
+  std::vector<int> rcs(nprob, SMPM_OK);
+  std::vector<std::string> msgs(nprob);
+  auto run = [&](int i) {
+    smpm_ctx* c = ctxs[i];
+    if (hipSetDevice(c->dev_id) != hipSuccess) {
+      rcs[i] = SMPM_EHIP;
+      msgs[i] = "hipSetDevice failed";
+      return;
+    }
+    rcs[i] = smpm_solve(c, f[i], g ? g[i] : nullptr, u[i], nrhs[i], &o, infos ? &infos[i] : nullptr,
+                        c->group_stream);
+    if (rcs[i] != SMPM_OK) msgs[i] = g_err;
+    if (hipStreamSynchronize(c->group_stream) != hipSuccess && rcs[i] == SMPM_OK) {
+      rcs[i] = SMPM_EHIP;
+      msgs[i] = "stream synchronize failed";
+    }
+  };
+  std::vector<std::thread> workers;
+  workers.reserve(nprob - 1);
+  for (int i = 1; i < nprob; ++i) workers.emplace_back(run, i);
+  run(0);
+  for (auto& t : workers) t.join();
+  (void)hipEventDestroy(start);
+  // a hard error wins over non-convergence
+  int worst = -1;
+  for (int i = 0; i < nprob; ++i)
+    if (rcs[i] != SMPM_OK && (worst < 0 || (rcs[worst] == SMPM_ENOCONV && rcs[i] != SMPM_ENOCONV))) worst = i;
+  if (worst >= 0) return fail(rcs[worst], "problem " + std::to_string(worst) + ": " + msgs[worst]);
+  return SMPM_OK;
+}
+
 int smpm_autotune(smpm_ctx* c, int nrhs, void* stream, smpm_tune_result* out) {
   int rc = check_device(c);
   if (rc) return rc;
@@ -1277,6 +1349,8 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   const int kind = o.variant == 3 ? OP_PSM : o.variant == 2 ? OP_SM : OP_S;
   std::vector<double> tres;
   int cycles = 1;
+  int sprec_final = PREC_F64;  // Schur precision of the last inner solve
+  double hist[16] = {0};
   bool conv = true;
   double* xsol = W.bS;
   if (o.precision == SMPM_FP64) {
@@ -1289,11 +1363,18 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       if (iters[i] >= o.maxit) conv = false;
   } else {
     // Iterative refinement: rho = b_hat - S x in FP64; delta from the deflated GMRES with
-    // FP32 (or BF16) Schur and block-Jacobi operators to inner_tol; x += delta.
-    // MIXED_BF16 starts with BF16 Schur and block-Jacobi operators; a refinement cycle
-    // that contracts the FP64 residual by less than 2x switches the Schur operator to
-    // FP32 for the remaining cycles (the preconditioner precision only affects the
-    // convergence rate, not the attainable accuracy)
+    // FP32 (or BF16) Schur and block-Jacobi operators; x += delta.
+    //  * Inner tolerance: inner_tol, loosened to 0.3 tol / rho_max once the residual is
+    //    near the target, so a cycle never solves further than the outer stop needs.
+    //  * Null space: rho is projected off the left null vector before every inner solve
+    //    (see there).
+    //  * Precision: the attainable accuracy of a cycle is set by the Schur operator's
+    //    rounding times the conditioning of S (the preconditioner's precision only changes
+    //    the convergence rate: GMRES minimizes the residual of S M^{-1} with the same
+    //    M^{-1} that forms delta).  So a cycle that contracts the FP64 residual too little
+    //    raises the Schur precision for the remaining cycles (BF16 -> FP32 below 20x,
+    //    FP32 -> FP64 below 2x), and a cycle that makes it grow is undone (x returns to
+    //    the previous iterate) before the precision is raised.
     int sprec = o.precision == SMPM_MIXED_FP32 ? PREC_F32 : PREC_BF16;
     const int mprec = sprec;
     xsol = W.xacc;
@@ -1301,6 +1382,8 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     HIPCHK(hipMemcpyAsync(W.rho, W.bhat, sizeof(double) * Pl.k * nrhs, hipMemcpyDeviceToDevice, s));
     iters.assign(nrhs, 0);
     std::vector<double> prev(nrhs, 2.0);
+    double cprev = HUGE_VAL;  // largest column residual at the iterate in xprev
+    bool reverted = false;
     int stall = 0;
     tres.assign(nrhs, 1.0);
     conv = false;
@@ -1316,31 +1399,66 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       HIPCHK(hipStreamSynchronize(s));
       const double* a = W.hout;
       const double* bb = W.hout + nrhs;
-      bool all = true, weak = false, slow = false;
+      bool all = true;
+      double cmax = 0;
       for (int i = 0; i < nrhs; ++i) {
         tres[i] = bb[i] > 0 ? std::sqrt(a[i] / bb[i]) : std::sqrt(a[i]);
-        if (tres[i] <= o.tol) {
-          // converged column: zero residual so the inner solve leaves it alone
-          HIPCHK(hipMemsetAsync(W.rho + (size_t)i * Pl.k, 0, sizeof(double) * Pl.k, s));
-        } else {
-          all = false;
-          if (cycles >= 1 && tres[i] > 0.05 * prev[i]) weak = true;
-          if (cycles >= 1 && tres[i] > 0.5 * prev[i]) slow = true;
-        }
-        prev[i] = tres[i];
+        cmax = std::max(cmax, tres[i]);
+        if (tres[i] > o.tol) all = false;
       }
+      if (cycles < 16) hist[cycles] = cmax;
       if (all) {
         conv = true;
         break;
       }
-      // a BF16 Schur operator that contracts the residual by less than 20x per cycle
-      // is replaced by the FP32 one; two cycles without a 2x contraction end the loop
-      if (weak && sprec == PREC_BF16) sprec = PREC_F32;
+      if (cycles > 0 && !reverted && cmax > cprev) {
+        // the last correction made the residual grow: undo it, raise the precision
+        HIPCHK(hipMemcpyAsync(W.xacc, W.xprev, sizeof(double) * Pl.k * nrhs, hipMemcpyDeviceToDevice, s));
+        if (sprec == PREC_F64) break;
+        sprec = sprec == PREC_BF16 ? PREC_F32 : PREC_F64;
+        reverted = true;
+        continue;  // the next pass recomputes the residual of the restored iterate
+      }
+      bool weak = false, slow = false;
+      for (int i = 0; i < nrhs; ++i) {
+        if (tres[i] <= o.tol) {
+          // converged column: zero residual so the inner solve leaves it alone
+          HIPCHK(hipMemsetAsync(W.rho + (size_t)i * Pl.k, 0, sizeof(double) * Pl.k, s));
+        } else if (cycles >= 1 && !reverted) {
+          if (tres[i] > 0.05 * prev[i]) weak = true;
+          if (tres[i] > 0.5 * prev[i]) slow = true;
+        }
+        prev[i] = tres[i];
+      }
+      reverted = false;
+      // raise the Schur precision after a weak cycle; two cycles without a 2x
+      // contraction at FP64 end the loop
+      if (weak && sprec == PREC_BF16) {
+        sprec = PREC_F32;
+        slow = false;
+      } else if (slow && sprec == PREC_F32) {
+        sprec = PREC_F64;
+        slow = false;
+      }
       stall = slow ? stall + 1 : 0;
       if (stall >= 2 || cycles == o.max_refine) break;
+      cprev = cmax;
+      HIPCHK(hipMemcpyAsync(W.xprev, W.xacc, sizeof(double) * Pl.k * nrhs, hipMemcpyDeviceToDevice, s));
+      // rho lies in the range of S (of S^T for the adjoint) only up to the rounding of
+      // b_hat - S x, a component along the left null vector of about eps |b_hat| that
+      // no correction can remove; once |rho| is small it is a sizeable part of rho and
+      // the inner GMRES, fitting it, grows a large correction along the right null
+      // direction, which the rounding of the low-precision operators turns into residual
+      {
+        const double* nl = tr ? c->v0hat : c->uS;
+        launch_mdot(nl, 0, 0, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
+        launch_axpy_shared(W.rho, Pl.k, nl, W.scal, 1.0, W.rho, Pl.k, nrhs, s);
+      }
+      const double itol = std::min(0.5, std::max(o.inner_tol, 0.3 * o.tol / cmax));
       std::vector<int> it;
-      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, o.inner_tol, o.maxit, it, s, sprec, mprec, o.graph != 0);
+      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, itol, o.maxit, it, s, sprec, mprec, o.graph != 0);
       if (rc < 0) return rc;
+      sprec_final = sprec;
       for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
       launch_add(W.xacc, W.bS, 1.0, W.xacc, Pl.k, nrhs, s);
     }
@@ -1369,6 +1487,9 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   if (info) {
     info->iterations = itmax;
     info->refinements = o.precision == SMPM_FP64 ? 1 : cycles;
+    info->schur_precision = sprec_final;
+    for (int q = 0; q < 16; ++q) info->cycle_residual[q] = hist[q];
+    if (o.precision == SMPM_FP64) info->cycle_residual[0] = resmax;
     info->rel_residual = resmax;
     // published before the synchronization above; the adjoint removes a multiple of w
     info->removed_component = W.hout[2 * nrhs] / (tr ? c->wsum : 1.0);

@@ -8,6 +8,8 @@
 // every FP64 result is deterministic from run to run.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "smpm_kernels.h"
 
 namespace smpm {
@@ -1081,14 +1083,15 @@ static bool pers_launch(const DevPlan& P, const double* y, double* t, int nrhs, 
   const size_t lds = (size_t)2 * NC * 4 * KT * kTileLd * sizeof(typename AccOf<T>::type);
   const int ncg = (nrhs + NC - 1) / NC;
   const int64_t nitems = (int64_t)P.ntile * ncg;
-  static int occ[2] = {0, 0};  // resident workgroups per CU, per direction
-  int& oc = occ[transpose ? 1 : 0];
+  static std::atomic<int> occ[2] = {0, 0};  // resident workgroups per CU, per direction
+  int oc = occ[transpose ? 1 : 0].load(std::memory_order_relaxed);
   if (oc == 0) {
     int v = 0;
     const hipError_t e = transpose
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_schur_mfma_pers<true, KT, NC, T>, 16 * KT, lds)
         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_schur_mfma_pers<false, KT, NC, T>, 16 * KT, lds);
     oc = (e == hipSuccess && v > 0) ? v : 1;
+    occ[transpose ? 1 : 0].store(oc, std::memory_order_relaxed);
   }
   const int64_t resident = (int64_t)P.num_cu * oc;
   if (P.schur_pers[schur_nc_class(nrhs)] == 0 && nitems < 2 * resident) return false;

@@ -30,7 +30,7 @@ ABI_SYMBOLS = (
     "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_stats", "smpm_slot_map",
     "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
     "smpm_schur_apply", "smpm_schur_apply_prec", "smpm_precond_apply", "smpm_project", "smpm_solve",
-    "smpm_boundary_transpose", "smpm_autotune",
+    "smpm_boundary_transpose", "smpm_autotune", "smpm_solve_group",
     "smpm_last_error",
 )
 
@@ -42,7 +42,8 @@ class SolveOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("refinements", C.c_int), ("rel_residual", C.c_double),
-                ("removed_component", C.c_double)]
+                ("removed_component", C.c_double), ("schur_precision", C.c_int),
+                ("cycle_residual", C.c_double * 16)]
 
 
 class TuneResult(C.Structure):
@@ -96,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     lib.smpm_solve.argtypes = [vp, vp, vp, vp, C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     lib.smpm_boundary_transpose.argtypes = [vp, vp, vp, C.c_int, vp]
     lib.smpm_autotune.argtypes = [vp, C.c_int, vp, C.POINTER(TuneResult)]
+    lib.smpm_solve_group.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                     C.POINTER(C.c_int), C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     for name in ABI_SYMBOLS:
         if name not in ("smpm_destroy", "smpm_default_opts", "smpm_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -129,6 +132,16 @@ class Info:
     rel_residual: float
     removed_component: float
     status: int
+    schur_precision: int = FP64  # Schur operator precision of the last inner solve
+    cycle_residuals: tuple = ()  # FP64 true residual at the start of each refinement cycle
+
+
+def _info(si, rc):
+    hist = list(si.cycle_residual)
+    while len(hist) > 1 and hist[-1] == 0.0:
+        hist.pop()
+    return Info(si.iterations, si.refinements, si.rel_residual, si.removed_component, rc, si.schur_precision,
+                tuple(hist))
 
 
 class Context:
@@ -313,7 +326,7 @@ class Context:
                                   C.byref(opts), C.byref(info), _stream(torch, stream))
         if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
             _check(rc)
-        return u, Info(info.iterations, info.refinements, info.rel_residual, info.removed_component, rc)
+        return u, _info(info, rc)
 
     def autotune(self, nrhs, stream=None):
         """Time the launch-shape candidates for `nrhs` columns and keep the fastest
@@ -332,6 +345,42 @@ class Context:
         _check(self._lib.smpm_boundary_transpose(self._h, C.c_void_p(mu.data_ptr()), C.c_void_p(out.data_ptr()),
                                                  mu.shape[0], _stream(torch, stream)))
         return out
+
+
+def solve_group(contexts, fs, gs=None, tol=1e-10, maxit=400, variant=3, precision=FP64, inner_tol=1e-5,
+                max_refine=20, stream=None, raise_on_noconv=True, graph=True):
+    """Solve independent problems concurrently (smpm_solve_group): problem i is
+    contexts[i].solve(fs[i], gs[i] if gs else None, ...) with shared options.
+    Returns [(u_i, Info_i)]."""
+    import torch
+    n = len(contexts)
+    if len(fs) != n or (gs is not None and len(gs) != n):
+        raise ValueError("one f (and g) per context")
+    lib = contexts[0]._lib
+    fs = [c._as_cols(f, c.r) for c, f in zip(contexts, fs)]
+    gl = None
+    if gs is not None:
+        gl = []
+        for c, f, g in zip(contexts, fs, gs):
+            if g is not None:
+                g = c._as_cols(g, c.nbdry)
+                if g.shape[0] != f.shape[0]:
+                    raise ValueError("g must have as many columns as f")
+            gl.append(g)
+    us = [torch.empty_like(f) for f in fs]
+    vp = C.c_void_p
+    arr = lambda xs: (vp * n)(*[vp(x) if isinstance(x, int) else x for x in xs])
+    hs = arr([c._h for c in contexts])
+    fp = arr([f.data_ptr() for f in fs])
+    up = arr([u.data_ptr() for u in us])
+    gp = None if gl is None else arr([None if g is None else g.data_ptr() for g in gl])
+    nr = (C.c_int * n)(*[f.shape[0] for f in fs])
+    opts = SolveOpts(tol, maxit, precision, 0, variant, inner_tol, max_refine, int(graph))
+    infos = (SolveInfo * n)()
+    rc = lib.smpm_solve_group(hs, n, fp, gp, up, nr, C.byref(opts), infos, _stream(torch, stream))
+    if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
+        _check(rc)
+    return [(u, _info(i, rc)) for u, i in zip(us, infos)]
 
 
 _SchurSolve = None

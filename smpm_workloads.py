@@ -221,6 +221,25 @@ def advected_sources(seed: int, x, y, count: int = 32, dt: float = 1e-3,
     return out
 
 
+C5_SIDE_GRIDS = ("c5a", "c5b", "c5c")
+
+
+def c5_sources(name: str, x, y, arc, Lx: float, Ly: float, count: int = 8):
+    """Right-hand sides of the large stretched grid ("c5": seeds B+50+i for f_i and
+    B+60+i for g_i) and of its side grids ("c5a"/"c5b"/"c5c" = G 0/1/2: seeds
+    B+70+10G+i for f_i and B+100+10G+i for g_i): random-Fourier sources (20 modes,
+    k <= 8) and nonzero cosine-series Neumann data on every edge.
+    Returns (F (count, len(x)), G (count, len(arc concatenated)))."""
+    if name == "c5":
+        sf, sg = SEED_BASE + 50, SEED_BASE + 60
+    else:
+        G = C5_SIDE_GRIDS.index(name)
+        sf, sg = SEED_BASE + 70 + 10 * G, SEED_BASE + 100 + 10 * G
+    F = np.stack([eval_fourier(random_fourier_params(sf + i, 20, 8), x, y, Lx, Ly) for i in range(count)])
+    Gd = np.stack([eval_edge(random_edge_params(sg + i), *arc, Lx, Ly) for i in range(count)])
+    return F, Gd
+
+
 def random_directions(seed: int, count: int, size: int) -> np.ndarray:
     """`count` N(0,1) directions of length `size`, each scaled to unit 2-norm."""
     rng = np.random.default_rng(seed)

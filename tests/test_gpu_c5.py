@@ -1,0 +1,145 @@
+"""The large uneven workload: the 128 x 128, n = 16 grid with element widths
+stretched geometrically toward x = 0 (ratio 1.05, aspect ratio up to 8), 8
+right-hand sides with nonzero Neumann data, mixed FP32 with FP64 refinement; and
+the concurrent solve of several problems (smpm_solve_group).
+
+Full-size checks use properties that hold at any size: the FP64 true Schur
+residual, agreement of the mixed and FP64 solutions, and the componentwise
+backward error of the un-reduced system L u = f~ at sampled elements, evaluated
+row by row with the oracle's element rows.  The group solve is compared bit for
+bit with solves of the same problems one at a time, and on small grids with the
+oracle's direct solve."""
+import numpy as np
+import pytest
+
+import smpm_workloads as wl
+from oracle import smpm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+smpm = pytest.importorskip("paper_1601_03432_amd.smpm")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+SMALL = {
+    "c1": (8, wl.uniform_breaks(4), wl.uniform_breaks(4)),
+    "stretched_4x3": (7, np.array([0.0, 0.1, 0.25, 0.5, 1.0]), np.array([0.0, 0.3, 0.6, 1.0])),
+    "ragged_9x7": (5, wl.uniform_breaks(9), wl.uniform_breaks(7)),
+}
+
+
+def _small_problem(name, seed, ncol):
+    n, xb, yb = SMALL[name]
+    ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, O.DEFAULT_ALPHA, device=True)
+    x, y = ctx.node_coords()
+    Lx, Ly = xb[-1] - xb[0], yb[-1] - yb[0]
+    F = np.stack([wl.eval_fourier(wl.random_fourier_params(seed + i, 20, 4), x, y, Lx, Ly) for i in range(ncol)])
+    G = np.stack([wl.eval_edge(wl.random_edge_params(seed + 50 + i), *ctx.boundary_arc(), Lx, Ly)
+                  for i in range(ncol)])
+    return ctx, O.Split(O.Grid(n, xb, yb)), F, G
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_group_small_grids_match_oracle_and_single_solves(precision):
+    prec = smpm.FP64 if precision == "fp64" else smpm.MIXED_FP32
+    probs = [_small_problem(name, 500 + 10 * i, 2 + i) for i, name in enumerate(sorted(SMALL))]
+    kw = dict(tol=1e-12, maxit=600, precision=prec)
+    print(f"[gpu-c5] small group {precision}", flush=True)
+    out = smpm.solve_group([p[0] for p in probs], [dev(p[2]) for p in probs], [dev(p[3]) for p in probs], **kw)
+    for (ctx, split, F, G), (u, info) in zip(probs, out):
+        single, _ = ctx.solve(dev(F), dev(G), **kw)
+        assert torch.equal(u, single)
+        assert info.rel_residual <= 1e-11
+        uh = u.cpu().numpy()
+        for c in range(F.shape[0]):
+            want = O.solve_unreduced(split, F[c], G[c])[0]
+            assert rel(uh[c], want) <= (1e-10 if precision == "fp64" else 1e-6)
+
+
+def test_group_rejects_duplicate_contexts():
+    ctx, _, F, G = _small_problem("c1", 520, 1)
+    with pytest.raises(smpm.SmpmError):
+        smpm.solve_group([ctx, ctx], [dev(F), dev(F)])
+
+
+def test_group_side_grids_mixed():
+    """The three side grids (16x16 n=8, 32x32 n=12, 48x48 n=10), 8 right-hand sides
+    each with nonzero Neumann data, mixed FP32 + FP64 refinement to 1e-10, solved as
+    one group: bit-identical to the separate solves, FP64 true residual <= 1e-10."""
+    ctxs, Fs, Gs = [], [], []
+    for name in wl.C5_SIDE_GRIDS:
+        w = wl.workload(name)
+        ctx = smpm.Context.from_workload(w)
+        x, y = ctx.node_coords()
+        F, G = wl.c5_sources(name, x, y, ctx.boundary_arc(), w.Lx, w.Ly)
+        ctxs.append(ctx)
+        Fs.append(dev(F))
+        Gs.append(dev(G))
+    kw = dict(tol=1e-10, maxit=600, precision=smpm.MIXED_FP32)
+    out = smpm.solve_group(ctxs, Fs, Gs, **kw)
+    for name, ctx, F, G, (u, info) in zip(wl.C5_SIDE_GRIDS, ctxs, Fs, Gs, out):
+        print(f"[gpu-c5] {name}: {info.iterations} iterations, {info.refinements} refinements, "
+              f"residual {info.rel_residual:.2e}", flush=True)
+        assert info.rel_residual <= 1e-10
+        single, _ = ctx.solve(F, G, **kw)
+        assert torch.equal(u, single), name
+
+
+def _backward_error_at(grid, u, ft, elems):
+    """max over the rows of the sampled elements of |L u - f~| / (|L| |u| + |f~|)."""
+    n2 = grid.n2
+    worst = 0.0
+    for iy, ix in elems:
+        e = grid.eid(iy, ix)
+        res = -ft[e * n2:(e + 1) * n2].copy()
+        scale = np.abs(ft[e * n2:(e + 1) * n2]).copy()
+        for (jy, jx), blk in O.element_rows(grid, iy, ix).items():
+            uj = u[grid.eid(jy, jx) * n2:(grid.eid(jy, jx) + 1) * n2]
+            res += blk @ uj
+            scale += np.abs(blk) @ np.abs(uj)
+        worst = max(worst, float(np.max(np.abs(res) / scale)))
+    return worst
+
+
+def test_c5_full_size_mixed_8rhs():
+    w = wl.workload("c5")
+    print("[gpu-c5] setup 128x128 n=16 stretched", flush=True)
+    ctx = smpm.Context.from_workload(w)
+    x, y = ctx.node_coords()
+    F, G = wl.c5_sources("c5", x, y, ctx.boundary_arc(), w.Lx, w.Ly)
+    Fd, Gd = dev(F), dev(G)
+    um, im = ctx.solve(Fd, Gd, tol=1e-10, maxit=600, precision=smpm.MIXED_FP32)
+    print(f"[gpu-c5] mixed: {im.iterations} iterations, {im.refinements} refinements, "
+          f"residual {im.rel_residual:.2e}, final Schur precision {im.schur_precision}", flush=True)
+    u64, i64 = ctx.solve(Fd, Gd, tol=1e-10, maxit=600)
+    print(f"[gpu-c5] fp64: {i64.iterations} iterations, residual {i64.rel_residual:.2e}", flush=True)
+    assert im.rel_residual <= 1e-10 and i64.rel_residual <= 1e-10
+    um, u64 = um.cpu().numpy(), u64.cpu().numpy()
+    for c in range(8):
+        assert rel(um[c], u64[c]) <= 1e-6
+    # the un-reduced equations at sampled elements: corners, walls, the narrowest
+    # (most stretched) column and the interior
+    grid = O.Grid(w.n, w.x_breaks, w.y_breaks)
+    T = O.boundary_operator(grid)
+    uL, _ = ctx.null_vectors()
+    elems = [(0, 0), (0, 127), (127, 0), (127, 127), (64, 0), (0, 64), (64, 1), (31, 97), (100, 12)]
+    for c in (0, 5):
+        rhs = F[c] + T @ G[c]
+        ft = rhs - uL * (uL @ rhs)
+        be = _backward_error_at(grid, u64[c], ft, elems)
+        print(f"[gpu-c5] column {c}: sampled componentwise backward error {be:.2e}", flush=True)
+        assert be <= 1e-8
