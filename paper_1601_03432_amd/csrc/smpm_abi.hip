@@ -43,14 +43,15 @@ struct Workspace {
   double* part = nullptr;
   int *active = nullptr, *jcount = nullptr;
   // device-resident GMRES state
-  double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr, *sides = nullptr;
+  double *part1 = nullptr, *part2 = nullptr, *sides = nullptr;
+  double *Hu = nullptr, *dw = nullptr;  // device GMRES: unrotated Hessenberg, reduced dots
   double *xacc = nullptr, *rho = nullptr;  // iterative refinement: solution and residual
   double* xprev = nullptr;                  // iterate before the last correction
   double* cws = nullptr;                    // substructured coarse solve scratch
   double* tolv = nullptr;                   // device GMRES: tolerance and step counter
   int* jdev = nullptr;
-  double *beta_cur = nullptr, *beta0 = nullptr, *tolb = nullptr;
-  int *iters = nullptr, *counter = nullptr;
+  double *tolb = nullptr;
+  int* iters = nullptr;
   int* pinned = nullptr;  // pinned host block: flags (2 x nrhs ints), then hres / hout
   double* hres = nullptr;  // 2 x nrhs residual-estimate ratios (per chunk slot)
   double* hout = nullptr;  // 4 x nrhs small results
@@ -196,16 +197,14 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   w.nch = (int)((P.k + w.rows - 1) / w.rows);
   rc |= dalloc(w.mem, &w.part1, (size_t)w.nch * ldh * R);
   rc |= dalloc(w.mem, &w.part2, (size_t)w.nch * ldh * R);
-  rc |= dalloc(w.mem, &w.part3, (size_t)w.nch * R);
+  rc |= dalloc(w.mem, &w.Hu, ldh * maxit * R);
+  rc |= dalloc(w.mem, &w.dw, ldh * R);
   rc |= dalloc(w.mem, &w.sides, (size_t)P.nsides * R);
   rc |= dalloc(w.mem, &w.xacc, k * R);
   rc |= dalloc(w.mem, &w.xprev, k * R);
   rc |= dalloc(w.mem, &w.rho, k * R);
-  rc |= dalloc(w.mem, &w.beta_cur, R);
-  rc |= dalloc(w.mem, &w.beta0, R);
   rc |= dalloc(w.mem, &w.tolb, R);
   rc |= ialloc(w.mem, &w.iters, R);
-  rc |= ialloc(w.mem, &w.counter, 4 * R);
   // scratch of the substructured coarse solve: [patch parts | separator rhs | lambda]
   int64_t cstride = 0;
   if (P.coarse_mode == 2)
@@ -229,7 +228,6 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   for (int i = 0; i < 2; ++i)
     if (hipEventCreateWithFlags(&w.ev[i], hipEventDisableTiming) != hipSuccess)
       return fail(SMPM_EHIP, "hipEventCreate failed");
-  if (hipMemset(w.counter, 0, 4 * R * sizeof(int)) != hipSuccess) return fail(SMPM_EHIP, "hipMemset failed");
   if (hipDeviceSynchronize() != hipSuccess) return fail(SMPM_EHIP, "hipDeviceSynchronize failed");
   w.nrhs = nrhs;
   w.maxit = maxit;
@@ -374,21 +372,19 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.c2 = W.c2;
   S.part1 = W.part1;
   S.part2 = W.part2;
-  S.part3 = W.part3;
   S.h1 = W.h1;
   S.h2 = W.h2;
+  S.dw = W.dw;
+  S.Hu = W.Hu;
   S.H = W.H;
   S.cs = W.cs;
   S.sn = W.sn;
   S.g = W.g;
   S.y = W.y;
-  S.beta_cur = W.beta_cur;
-  S.beta0 = W.beta0;
   S.tolb = W.tolb;
   S.res = W.res;
   S.active = W.active;
   S.iters = W.iters;
-  S.counter = W.counter;
   S.ldv = W.maxit + 1;
   S.maxit = maxit;
   S.nch = W.nch;
@@ -466,7 +462,8 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
   // convergence rate says the queued chunk will finish the solve: then it waits for
   // that chunk instead of queueing steps that would find every column retired.  Steps
   // past maxit (the last chunk's tail) do nothing.
-  const int nchunks = (maxit + kChunkIters - 1) / kChunkIters;
+  // step j finishes Hessenberg column j - 2, so maxit columns take maxit + 2 steps
+  const int nchunks = (maxit + 2 + kChunkIters - 1) / kChunkIters;
   auto launch_chunk = [&](int ch) -> int {
     if (exec) {
       HIPCHK(hipGraphLaunch(exec, s));

@@ -1,28 +1,37 @@
 // Device-resident GMRES iteration for the deflated Schur complement system.
 //
-// One Arnoldi step j of right-preconditioned GMRES on P S M^{-1} (Algorithm 3,
-// step 4) is five kernels that read j from a device counter and keep every scalar
-// on the device, so the host never waits inside the loop and a captured chunk of
-// steps (hipGraph) replays for any j.  The counter is double-buffered: step q of a
-// chunk reads slot q % 2 and its last kernel writes j + 1 into the other slot, so
-// no kernel reads a value another block of it may be changing:
-//   gm_precond  h2 and beta_j from the previous step's partials; block 0 applies
-//               the Givens rotations to Hessenberg column j-1 and retires the
-//               column once its residual estimate reaches tol * |b|;
-//               v_j = (w - V h2) / beta_j (into V), z = M^{-1} v_j
+// Arnoldi with classical Gram-Schmidt and delayed reorthogonalization (DCGS2, after
+// Swirydowicz, Bielich, Langou, Thomas et al.): the operator is applied to the
+// candidate vector u_j before it is reorthogonalized and normalized, and a single
+// pass over the basis yields both the projections of w_j = A u_j and the
+// reorthogonalization coefficients of u_j.  With Q_m = [q_0 .. q_{m-1}] the final
+// basis and the candidate u_m stored in V_m:
+//   dots   (d_i, c_i) = (q_i^T w_m, q_i^T u_m) for i < m, alpha = u_m^T w_m, nu = u_m^T u_m
+//   rho    = sqrt(nu - |c|^2)                    (Pythagoras)
+//   q_m    = (u_m - Q_m c) / rho                 Hessenberg column m-1 = h'_{m-1} + c, rho below
+//   e      = q_m^T w_m = (alpha - c.d) / rho
+//   u_{m+1}= (w_m - Q_m d - e q_m) / rho         (= A q_m projected once off Q_{m+1})
+//   h'_m   = ([d; e] - H c) / rho                (= Q_{m+1}^T A q_m; H = the unrotated
+//                                                 Hessenberg columns 0..m-1)
+// so each step reads the basis twice (one dot pass, one update pass) instead of four
+// times.  One step j is four kernels (five when the sums are pre-reduced) that read j
+// from a device counter and keep every scalar on the device, so the host never waits
+// inside the loop and a captured chunk of steps (hipGraph) replays for any j.  The
+// counter is double-buffered: step q of a chunk reads slot q % 2 and its last kernel
+// writes j + 1 into the other slot, so no kernel reads a value another block of it
+// may be changing:
+//   gm_update   (m = j - 1) rho, e from the previous dot pass; block 0 applies the
+//               Givens rotations to Hessenberg column m-1 and retires the column
+//               once its residual estimate reaches tol * |b|, and forms h'_m;
+//               q_m into V_m, u_{m+1} into V_{m+1}, z = M^{-1} u_{m+1}
+//               (step 0: z = M^{-1} u_0)
 //   Schur       t = S z, with the per-side sums of t for Z^T t
 //   coarse      c2 = G Z^T t
-//   gm_orth1    w = t - Z c2 - S Z c2 (deflation), partial dots V^T w
-//   gm_orth2    h1 = sum of partials; w -= V h1; partial dots V^T w and |w|^2;
-//               next j
-// Classical Gram-Schmidt is applied twice, the second pass delayed into the next
-// step's gm_precond: h2 = V^T w from gm_orth2's partials, beta^2 = |w|^2 - |h2|^2
-// (Pythagoras), v = (w - V h2) / beta per slot.  One reduction fewer per step, as
-// in the low-synchronization CGS2 variants of Swirydowicz, Bielich, Langou,
-// Thomas et al.
-// Each block handles a chunk of rows.  Every block that needs a reduced value
-// sums the previous kernel's per-chunk partials itself, in one fixed order, so
-// results are deterministic and no inter-block fence is needed.
+//   gm_dots     w = t - Z c2 - S Z c2 (deflation); partial dots of V_0..V_j with w
+//               and with u_j = V_j; next j
+// Each block handles a chunk of rows.  Every block that needs a reduced value sums
+// the previous kernel's per-chunk partials itself, in one fixed order, so results
+// are deterministic and no inter-block fence is needed.
 #include <hip/hip_runtime.h>
 
 #include "smpm_gmres.h"
@@ -69,33 +78,42 @@ __device__ void reduce_partials(const double* __restrict__ part, int nvec, int n
   }
 }
 
-// Partial dots of the chunk held in LDS (wv, `rows` rows) with V_0..V_{nvec-1}:
-// wave q handles groups of kDotUnroll vectors whose loads are all issued before
-// the shuffle reductions; lanes run over rows.
-__device__ void chunk_dots(const double* __restrict__ V, int64_t vvs, int64_t x0, int rows, const double* wv,
-                           int nvec, double* part, int nch, int chunk) {
+// Partial dots of the chunk held in LDS (wv and uv, `rows` rows) with
+// V_0..V_{nvec-1}: one pass over the basis for both vectors.  Wave q handles groups
+// of kDotUnroll basis vectors whose loads are all issued before the shuffle
+// reductions; lanes run over rows.
+__device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x0, int rows, const double* wv,
+                            const double* uv, int nvec, double* partw, double* partu, int nch, int chunk) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i0 = wave * kDotUnroll; i0 < nvec; i0 += kWaves * kDotUnroll) {
-    double acc[kDotUnroll];
+    double aw[kDotUnroll], au[kDotUnroll];
 #pragma unroll
-    for (int u = 0; u < kDotUnroll; ++u) acc[u] = 0.0;
+    for (int u = 0; u < kDotUnroll; ++u) aw[u] = au[u] = 0.0;
     for (int x = lane; x < rows; x += 64) {
-      const double wx = wv[x];
+      const double wx = wv[x], ux = uv[x];
 #pragma unroll
       for (int u = 0; u < kDotUnroll; ++u)
-        if (i0 + u < nvec) acc[u] = fma(V[(int64_t)(i0 + u) * vvs + x0 + x], wx, acc[u]);
+        if (i0 + u < nvec) {
+          const double v = V[(int64_t)(i0 + u) * vvs + x0 + x];
+          aw[u] = fma(v, wx, aw[u]);
+          au[u] = fma(v, ux, au[u]);
+        }
     }
 #pragma unroll
     for (int u = 0; u < kDotUnroll; ++u) {
-      const double v = wave_sum(acc[u]);
-      if (lane == 0 && i0 + u < nvec) part[(int64_t)(i0 + u) * nch + chunk] = v;
+      const double sw = wave_sum(aw[u]);
+      const double su = wave_sum(au[u]);
+      if (lane == 0 && i0 + u < nvec) {
+        partw[(int64_t)(i0 + u) * nch + chunk] = sw;
+        partu[(int64_t)(i0 + u) * nch + chunk] = su;
+      }
     }
   }
 }
 
 // Givens step for Hessenberg column jc = j-1 of one right-hand side, run by
-// block 0 of gm_precond: H(:, jc) = h1 + h2 with beta below the diagonal,
-// rotated by the previous rotations; a new rotation zeroes beta.
+// block 0 of gm_update: H(:, jc) = h1 + h2 with beta below the diagonal (stored
+// unrotated in Hu), rotated by the previous rotations; a new rotation zeroes beta.
 __device__ void givens_column(const GmState& S, int col, int j, double beta, const double* h2) {
   __shared__ double hc[kMaxIt + 2];
   __shared__ double csl[kMaxIt + 1], snl[kMaxIt + 1];
@@ -104,7 +122,12 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
   const double* h1 = S.h1 + (int64_t)col * S.ldv;
   double* csg = S.cs + (int64_t)col * S.ldv;
   double* sng = S.sn + (int64_t)col * S.ldv;
-  for (int i = tid; i <= jc; i += kThreads) hc[i] = h1[i] + h2[i];
+  double* Hu = S.Hu + (int64_t)col * S.ldv * S.maxit + (int64_t)jc * S.ldv;
+  for (int i = tid; i <= jc; i += kThreads) {
+    hc[i] = h1[i] + h2[i];
+    Hu[i] = hc[i];  // the unrotated column, for the corrections of later steps
+  }
+  if (tid == 0) Hu[jc + 1] = beta;
   for (int i = tid; i < jc; i += kThreads) {
     csl[i] = csg[i];
     snl[i] = sng[i];
@@ -144,87 +167,124 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
 
 // ------------------------------------------------------------------ kernels
 
-// beta_j, Givens for column j-1 (block 0), v_j = w / beta_j into V_j and
-// z = M^{-1} v_j (or z = v_j).  givens_only: stop after the Givens step.
+// Step j's first kernel (see the file header; m = j - 1).  Step 0: z = M^{-1} u_0.
+// givens_only: stop after the Givens step (the last step of a solve).
 template <typename OpT>
-__global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int par, int use_precond, int transpose,
-                                                    int givens_only) {
+__global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par, int use_precond, int transpose,
+                                                   int givens_only) {
   using Acc = typename AccOf<OpT>::type;
   __shared__ Acc xs[8 * kMaxN];
-  __shared__ double red[kWaves];
-  __shared__ double h2s[kMaxIt + 1];
+  __shared__ double red[2 * kWaves];
+  __shared__ double ds[kMaxIt + 1];  // d_0..d_{m-1}, then alpha
+  __shared__ double cs2[kMaxIt + 1]; // c_0..c_{m-1}, then nu
+  __shared__ double hsum[kWaves][64];
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
   const int j = S.jdev[par];
-  if (j > S.maxit) return;
-  // second Gram-Schmidt pass of the previous step: h2 and beta (see the file header)
-  const int nh = j;  // h2 has j entries (none before the first step)
-  double beta;
-  if (S.prereduce && nh > 0) {
-    for (int i = tid; i < nh; i += kThreads) h2s[i] = S.h2[(int64_t)col * S.ldv + i];
-    __syncthreads();
-    beta = S.beta_cur[col];
-  } else {
-    if (nh > 0) reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, nh, S.nch, h2s);
-    __syncthreads();
-    if (tid < 64) {
-      double acc = 0.0, hh = 0.0;
-      for (int c = tid; c < S.nch; c += 64) acc += S.part3[(int64_t)col * S.nch + c];
-      for (int i = tid; i < nh; i += 64) hh = fma(h2s[i], h2s[i], hh);
-      acc = wave_sum(acc);
-      hh = wave_sum(hh);
-      if (tid == 0) red[0] = sqrt(fmax(acc - hh, 0.0));
-    }
-    __syncthreads();
-    beta = red[0];
-  }
-  if (blockIdx.x == 0) {
-    if (j == 0) {
-      if (tid == 0) {
-        S.tolb[col] = S.tolv[0] * (S.bref2 ? sqrt(S.bref2[col]) : beta);
-        S.g[(int64_t)col * S.ldv] = beta;
-        S.res[col] = beta;
-        if (!(beta > 0.0)) {
-          S.active[col] = 0;
-          S.iters[col] = 0;
-        }
+  const int64_t k = P.k;
+  double* zc = S.z + (int64_t)col * k;
+  const double* Vc = S.V + (int64_t)col * k;
+  int m = -1;
+  double inv = 0.0, e = 0.0;
+  if (j > 0) {
+    m = j - 1;
+    if (m > S.maxit) return;
+    if (S.prereduce) {
+      for (int i = tid; i <= m; i += kThreads) {
+        ds[i] = S.dw[(int64_t)col * S.ldv + i];
+        cs2[i] = S.h2[(int64_t)col * S.ldv + i];
       }
     } else {
-      givens_column(S, col, j, beta, h2s);
+      reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, m + 1, S.nch, ds);
+      reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, m + 1, S.nch, cs2);
     }
-  }
-  if (givens_only) return;
-  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-  const int64_t k = P.k;
-  const double* wc = S.w + (int64_t)col * k;
-  const double* Vc = S.V + (int64_t)col * k;
-  double* vj = S.V + (int64_t)j * S.vvs + (int64_t)col * k;
-  double* zc = S.z + (int64_t)col * k;
-  // v_j = (w - V h2) / beta at one slot
-  auto vnew = [&](int64_t x) {
-    double acc = wc[x];
+    __syncthreads();
+    if (tid < 64) {
+      double cc = 0.0, cd = 0.0;
+      for (int i = tid; i < m; i += 64) {
+        cc = fma(cs2[i], cs2[i], cc);
+        cd = fma(cs2[i], ds[i], cd);
+      }
+      cc = wave_sum(cc);
+      cd = wave_sum(cd);
+      if (tid == 0) {
+        red[0] = sqrt(fmax(cs2[m] - cc, 0.0));  // rho
+        red[1] = ds[m] - cd;                     // rho * e
+      }
+    }
+    __syncthreads();
+    const double rho = red[0];
+    inv = rho > 0.0 ? 1.0 / rho : 0.0;
+    e = red[1] * inv;
+    if (blockIdx.x == 0) {
+      if (m == 0) {
+        if (tid == 0) {
+          S.tolb[col] = S.tolv[0] * (S.bref2 ? sqrt(S.bref2[col]) : rho);
+          S.g[(int64_t)col * S.ldv] = rho;
+          S.res[col] = rho;
+          if (!(rho > 0.0)) {
+            S.active[col] = 0;
+            S.iters[col] = 0;
+          }
+        }
+      } else {
+        givens_column(S, col, m, rho, cs2);
+      }
+      // h'_m = ([d; e] - H c) / rho with the unrotated columns 0..m-1 (after the
+      // Givens step has read h'_{m-1}): lanes take rows l, the waves split the
+      // columns i, and the four partial sums are added in a fixed order
+      __syncthreads();
+      const double* Hu = S.Hu + (int64_t)col * S.ldv * S.maxit;
+      double* hp = S.h1 + (int64_t)col * S.ldv;
+      const int wave = tid >> 6, lane = tid & 63;
+      for (int l0 = 0; l0 <= m; l0 += 64) {
+        const int l = l0 + lane;
+        double hc = 0.0;
+        if (l <= m) {
 #pragma unroll 8
-    for (int i = 0; i < nh; ++i) acc = fma(-h2s[i], Vc[(int64_t)i * S.vvs + x], acc);
-    return acc * inv;
+          for (int i = max(l - 1, 0) + ((wave - max(l - 1, 0)) & 3); i < m; i += kWaves)
+            hc = fma(Hu[(int64_t)i * S.ldv + l], cs2[i], hc);
+        }
+        hsum[wave][lane] = hc;
+        __syncthreads();
+        if (wave == 0 && l <= m)
+          hp[l] = ((l < m ? ds[l] : e) - ((hsum[0][lane] + hsum[1][lane]) + (hsum[2][lane] + hsum[3][lane]))) * inv;
+        __syncthreads();
+      }
+    }
+    if (givens_only || m >= S.maxit) return;
+  } else if (givens_only) {
+    return;
+  }
+  // q_m into V_m and u_{m+1} into V_{m+1} at one slot; returns u_{m+1} (step 0: u_0)
+  const double* wc = S.w + (int64_t)col * k;
+  double* vm = S.V + (int64_t)max(m, 0) * S.vvs + (int64_t)col * k;
+  double* vn = S.V + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
+  auto update = [&](int64_t x) {
+    if (m < 0) return vn[x];
+    double sc = vm[x], sw = wc[x];
+#pragma unroll 8
+    for (int i = 0; i < m; ++i) {
+      const double v = Vc[(int64_t)i * S.vvs + x];
+      sc = fma(-cs2[i], v, sc);
+      sw = fma(-ds[i], v, sw);
+    }
+    const double q = sc * inv;
+    const double un = fma(-e, q, sw) * inv;
+    vm[x] = q;
+    vn[x] = un;
+    return un;
   };
   if (!use_precond) {
-    for (int64_t x = (int64_t)blockIdx.x * kThreads + tid; x < k; x += (int64_t)gridDim.x * kThreads) {
-      const double v = vnew(x);
-      vj[x] = v;
-      zc[x] = v;
-    }
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + tid; x < k; x += (int64_t)gridDim.x * kThreads)
+      zc[x] = update(x);
     return;
   }
   for (int b = blockIdx.x; b < P.nblk; b += gridDim.x) {
     const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
     const int bc = P.blk_cls[b];
     __syncthreads();
-    for (int i = tid; i < sb; i += kThreads) {
-      const int slot = P.blk_slots[o + i];
-      const double v = vnew(slot);
-      xs[i] = (Acc)v;
-      vj[slot] = v;
-    }
+    for (int i = tid; i < sb; i += kThreads) xs[i] = (Acc)update(P.blk_slots[o + i]);
     __syncthreads();
     const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
     for (int r = tid; r < sb; r += kThreads) {
@@ -236,17 +296,24 @@ __global__ __launch_bounds__(256) void k_gm_precond(DevPlan P, GmState S, int pa
   }
 }
 
-// w = t - (Z c2 + {S Z c2 | S^T Z c2}) on this block's rows (or w = t), then
-// partial dots with V_0..V_j.
-__global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int par, int defl, int transpose) {
+// Step j's last kernel: w = t - (Z c2 + {S Z c2 | S^T Z c2}) on this block's rows (or
+// w = t), then the partial dots of V_0..V_j with w and with u_j = V_j; the next
+// step's index.
+__global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, int defl, int transpose) {
   __shared__ double wv[kRowsMax];
+  __shared__ double uv[kRowsMax];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
-  if (!S.active[col]) return;
   const int j = S.jdev[par];
+  // the step's last kernel sets the next step's index in the other slot (whatever the
+  // columns' activity, so steps keep counting)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) S.jdev[par ^ 1] = j + 1;
+  if (!S.active[col] || j > S.maxit) return;
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const double* tc = S.t + (int64_t)col * k;
   double* wc = S.w + (int64_t)col * k;
+  const double* Vc = S.V + (int64_t)col * k;
+  const double* uj = Vc + (int64_t)j * S.vvs;
   const double* cc = S.c2 + (int64_t)col * P.d;
   const int n = P.n;
   for (int q = tid; q < rows; q += kThreads) {
@@ -275,100 +342,38 @@ __global__ __launch_bounds__(256) void k_gm_orth1(DevPlan P, GmState S, int par,
     }
     wc[slot] = v;
     wv[q] = v;
+    uv[q] = uj[slot];
   }
   __syncthreads();
-  chunk_dots(S.V + (int64_t)col * k, S.vvs, x0, rows, wv, j + 1, S.part1 + (int64_t)col * S.ldv * S.nch, S.nch,
-             chunk);
+  chunk_dots2(Vc, S.vvs, x0, rows, wv, uv, j + 1, S.part1 + (int64_t)col * S.ldv * S.nch,
+              S.part2 + (int64_t)col * S.ldv * S.nch, S.nch, chunk);
 }
 
-// h1 = sum of part1 (block 0 stores it for the Givens step); w -= V h1; partial dots
-// V^T w into part2 and partial |w|^2 into part3; the next step's index.
-__global__ __launch_bounds__(256) void k_gm_orth2(DevPlan P, GmState S, int par) {
-  __shared__ double wv[kRowsMax];
-  __shared__ double hs[kMaxIt + 1];
-  __shared__ double red[kWaves];
-  const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
-  const int j = S.jdev[par];
-  // the step's last kernel sets the next step's index in the other slot (whatever the
-  // columns' activity, so steps keep counting)
-  if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) S.jdev[par ^ 1] = j + 1;
-  if (!S.active[col]) return;
-  const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
-  const int rows = (int)min((int64_t)S.rows, k - x0);
-  const int nvec = j + 1;
-  if (S.prereduce) {
-    for (int i = tid; i < nvec; i += kThreads) hs[i] = S.h1[(int64_t)col * S.ldv + i];
-    __syncthreads();
-  } else {
-    reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, nvec, S.nch, hs);
-    __syncthreads();
-    if (chunk == 0) {
-      double* hdst = S.h1 + (int64_t)col * S.ldv;
-      for (int i = tid; i < nvec; i += kThreads) hdst[i] = hs[i];
-    }
-  }
-  double* wc = S.w + (int64_t)col * k;
-  const double* Vc = S.V + (int64_t)col * k;
-  double nrm = 0.0;
-  for (int q = tid; q < rows; q += kThreads) {
-    const int64_t x = x0 + q;
-    double acc = 0.0;
-#pragma unroll 16
-    for (int i = 0; i < nvec; ++i) acc = fma(hs[i], Vc[(int64_t)i * S.vvs + x], acc);
-    const double v = wc[x] - acc;
-    wc[x] = v;
-    wv[q] = v;
-    nrm = fma(v, v, nrm);
-  }
-  __syncthreads();
-  chunk_dots(Vc, S.vvs, x0, rows, wv, nvec, S.part2 + (int64_t)col * S.ldv * S.nch, S.nch, chunk);
-  const double bs = block_sum(nrm, red);
-  if (tid == 0) S.part3[(int64_t)col * S.nch + chunk] = bs;
-}
-
-// Pre-reduction (one block per column): h1 from gm_orth1's partials.
-__global__ __launch_bounds__(256) void k_gm_reduce_h1(GmState S, int par) {
+// Pre-reduction after gm_dots (one block per column): the dots with w into dw and
+// with u_j into h2, summed exactly as gm_update sums them itself.
+__global__ __launch_bounds__(256) void k_gm_reduce(GmState S, int par) {
   __shared__ double hs[kMaxIt + 1];
   const int col = blockIdx.y;
-  if (!S.active[col]) return;
-  const int nvec = S.jdev[par] + 1;
-  reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, nvec, S.nch, hs);
+  const int j = S.jdev[par];
+  if (!S.active[col] || j > S.maxit) return;
+  reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, j + 1, S.nch, hs);
   __syncthreads();
-  for (int i = threadIdx.x; i < nvec; i += kThreads) S.h1[(int64_t)col * S.ldv + i] = hs[i];
+  for (int i = threadIdx.x; i <= j; i += kThreads) S.dw[(int64_t)col * S.ldv + i] = hs[i];
+  __syncthreads();
+  reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, j + 1, S.nch, hs);
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += kThreads) S.h2[(int64_t)col * S.ldv + i] = hs[i];
 }
 
-// Pre-reduction after gm_orth2: h2 and beta for the next step, summed exactly as
-// gm_precond sums them itself.
-__global__ __launch_bounds__(256) void k_gm_reduce_beta(GmState S, int par) {
-  __shared__ double hs[kMaxIt + 1];
-  const int col = blockIdx.y, tid = threadIdx.x;
-  if (!S.active[col]) return;
-  const int nh = S.jdev[par] + 1;
-  reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, nh, S.nch, hs);
-  __syncthreads();
-  for (int i = tid; i < nh; i += kThreads) S.h2[(int64_t)col * S.ldv + i] = hs[i];
-  if (tid < 64) {
-    double acc = 0.0, hh = 0.0;
-    for (int c = tid; c < S.nch; c += 64) acc += S.part3[(int64_t)col * S.nch + c];
-    for (int i = tid; i < nh; i += 64) hh = fma(hs[i], hs[i], hh);
-    acc = wave_sum(acc);
-    hh = wave_sum(hh);
-    if (tid == 0) S.beta_cur[col] = sqrt(fmax(acc - hh, 0.0));
-  }
-}
-
-// Start of a solve: partial |w|^2 of the initial residual; all columns active;
+// Start of a solve: u_0 = w (the initial residual) into V_0; all columns active;
 // j = 0 and the tolerance.
 __global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S, double tol) {
-  __shared__ double red[kWaves];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const double* wc = S.w + (int64_t)col * k;
-  double nrm = 0.0;
-  for (int q = tid; q < rows; q += kThreads) nrm = fma(wc[x0 + q], wc[x0 + q], nrm);
-  const double bs = block_sum(nrm, red);
-  if (tid == 0) S.part3[(int64_t)col * S.nch + chunk] = bs;
+  double* v0 = S.V + (int64_t)col * k;
+  for (int q = tid; q < rows; q += kThreads) v0[x0 + q] = wc[x0 + q];
   if (chunk == 0 && tid == 0) {
     S.active[col] = 1;
     S.iters[col] = 0;
@@ -430,11 +435,11 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
   const dim3 pg(precond_grid(P, S, kind), nrhs);
   const int up = kind == 1 ? 0 : 1, trn = tr ? 1 : 0;
   if (mprec == PREC_F32)
-    hipLaunchKernelGGL(k_gm_precond<float>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_update<float>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
   else if (mprec == PREC_BF16)
-    hipLaunchKernelGGL(k_gm_precond<bf16s>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_update<bf16s>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
   else
-    hipLaunchKernelGGL(k_gm_precond<double>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
+    hipLaunchKernelGGL(k_gm_update<double>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
   const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P) && P.coarse_mode == 1;
   launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s, sprec);
   if (kind == 3) {
@@ -445,15 +450,13 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
       launch_coarse(P, S.c, S.c2, nrhs, tr, S.active, s);
     }
   }
-  hipLaunchKernelGGL(k_gm_orth1, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
+  hipLaunchKernelGGL(k_gm_dots, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
                      tr ? 1 : 0);
-  if (S.prereduce) hipLaunchKernelGGL(k_gm_reduce_h1, dim3(1, nrhs), dim3(kThreads), 0, s, S, par);
-  hipLaunchKernelGGL(k_gm_orth2, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par);
-  if (S.prereduce) hipLaunchKernelGGL(k_gm_reduce_beta, dim3(1, nrhs), dim3(kThreads), 0, s, S, par);
+  if (S.prereduce) hipLaunchKernelGGL(k_gm_reduce, dim3(1, nrhs), dim3(kThreads), 0, s, S, par);
 }
 
 void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_precond<double>, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 1 ? 0 : 1,
+  hipLaunchKernelGGL(k_gm_update<double>, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 1 ? 0 : 1,
                      tr ? 1 : 0, 1);
 }
 
