@@ -178,6 +178,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   __shared__ double ds[kMaxIt + 1];  // d_0..d_{m-1}, then alpha
   __shared__ double cs2[kMaxIt + 1]; // c_0..c_{m-1}, then nu
   __shared__ double hsum[kWaves][64];
+  __shared__ Acc bpart[256];
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
   const int j = S.jdev[par];
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   auto update = [&](int64_t x) {
     if (m < 0) return vn[x];
     double sc = vm[x], sw = wc[x];
-#pragma unroll 8
+#pragma unroll 16
     for (int i = 0; i < m; ++i) {
       const double v = Vc[(int64_t)i * S.vvs + x];
       sc = fma(-cs2[i], v, sc);
@@ -287,12 +288,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     for (int i = tid; i < sb; i += kThreads) xs[i] = (Acc)update(P.blk_slots[o + i]);
     __syncthreads();
     const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
-    for (int r = tid; r < sb; r += kThreads) {
-      Acc acc = 0;
-#pragma unroll 8
-      for (int c = 0; c < sb; ++c) acc = fma(to_acc(Mp[c * sb + r]), xs[c], acc);
-      zc[P.blk_slots[o + r]] = (double)acc;
-    }
+    block_jacobi_apply(Mp, xs, sb, bpart, [&](int r, Acc v) { zc[P.blk_slots[o + r]] = (double)v; });
   }
 }
 

@@ -655,6 +655,7 @@ __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __rest
                                                  int transpose, const int* __restrict__ active) {
   using Acc = typename AccOf<OpT>::type;
   __shared__ Acc xs[8 * kMaxN];
+  __shared__ Acc part[256];
   const int b = blockIdx.x, col = blockIdx.y, tid = threadIdx.x;
   if (active && !active[col]) return;
   const double* xc = x + (int64_t)col * P.k;
@@ -664,12 +665,7 @@ __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __rest
   for (int i = tid; i < sb; i += 256) xs[i] = (Acc)xc[P.blk_slots[o + i]];
   __syncthreads();
   const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
-  for (int r = tid; r < sb; r += 256) {
-    Acc acc = 0;
-#pragma unroll 8
-    for (int c = 0; c < sb; ++c) acc = fma(to_acc(Mp[c * sb + r]), xs[c], acc);
-    yc[P.blk_slots[o + r]] = (double)acc;
-  }
+  block_jacobi_apply(Mp, xs, sb, part, [&](int r, Acc v) { yc[P.blk_slots[o + r]] = (double)v; });
 }
 
 // ------------------------------------------------------------------ deflation
