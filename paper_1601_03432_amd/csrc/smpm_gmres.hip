@@ -288,7 +288,142 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     for (int i = tid; i < sb; i += kThreads) xs[i] = (Acc)update(P.blk_slots[o + i]);
     __syncthreads();
     const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
-    block_jacobi_apply(Mp, xs, sb, bpart, [&](int r, Acc v) { zc[P.blk_slots[o + r]] = (double)v; });
+    block_jacobi_apply<1>(Mp, xs, 0, sb, bpart, [&](int, int r, Acc v) { zc[P.blk_slots[o + r]] = (double)v; });
+  }
+}
+
+// Step j's first kernel for NC columns at once, with pre-reduced dot sums (large
+// grids, several columns): as k_gm_update, but every block-Jacobi inverse is read
+// once for the NC columns.  Same arithmetic per column, so the same bits.
+template <typename OpT, int NC>
+__global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int par, int use_precond, int transpose) {
+  using Acc = typename AccOf<OpT>::type;
+  __shared__ Acc xs[NC][8 * kMaxN];
+  __shared__ Acc bpart[NC * 256];
+  __shared__ double scal[NC][2];  // rho, e
+  __shared__ double hsum[kWaves][64];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t k = P.k;
+  const int nrhs = (int)(S.vvs / k);
+  const int c0 = blockIdx.y * NC;
+  bool on[NC];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    on[c] = c0 + c < nrhs && S.active[c0 + c];
+    any = any || on[c];
+  }
+  if (!any) return;
+  const int j = S.jdev[par];
+  const int m = j - 1;
+  if (m > S.maxit) return;
+  if (j > 0) {
+    // rho and e per column from the pre-reduced sums: wave w takes columns w, w+4, ...
+    for (int c = wave; c < NC; c += kWaves) {
+      if (!on[c]) continue;
+      const double* cu = S.h2 + (int64_t)(c0 + c) * S.ldv;
+      const double* dw = S.dw + (int64_t)(c0 + c) * S.ldv;
+      double cc = 0.0, cd = 0.0;
+      for (int i = lane; i < m; i += 64) {
+        cc = fma(cu[i], cu[i], cc);
+        cd = fma(cu[i], dw[i], cd);
+      }
+      cc = wave_sum(cc);
+      cd = wave_sum(cd);
+      if (lane == 0) {
+        const double rho = sqrt(fmax(cu[m] - cc, 0.0));
+        scal[c][0] = rho;
+        scal[c][1] = (dw[m] - cd) * (rho > 0.0 ? 1.0 / rho : 0.0);
+      }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) {
+      for (int c = 0; c < NC; ++c) {
+        if (!on[c]) continue;
+        const int col = c0 + c;
+        const double rho = scal[c][0], e = scal[c][1];
+        const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
+        const double* cu = S.h2 + (int64_t)col * S.ldv;
+        const double* dw = S.dw + (int64_t)col * S.ldv;
+        if (m == 0) {
+          if (tid == 0) {
+            S.tolb[col] = S.tolv[0] * (S.bref2 ? sqrt(S.bref2[col]) : rho);
+            S.g[(int64_t)col * S.ldv] = rho;
+            S.res[col] = rho;
+            if (!(rho > 0.0)) {
+              S.active[col] = 0;
+              S.iters[col] = 0;
+            }
+          }
+        } else {
+          givens_column(S, col, m, rho, cu);
+        }
+        __syncthreads();
+        const double* Hu = S.Hu + (int64_t)col * S.ldv * S.maxit;
+        double* hp = S.h1 + (int64_t)col * S.ldv;
+        for (int l0 = 0; l0 <= m; l0 += 64) {
+          const int l = l0 + lane;
+          double hc = 0.0;
+          if (l <= m) {
+#pragma unroll 8
+            for (int i = max(l - 1, 0) + ((wave - max(l - 1, 0)) & 3); i < m; i += kWaves)
+              hc = fma(Hu[(int64_t)i * S.ldv + l], cu[i], hc);
+          }
+          hsum[wave][lane] = hc;
+          __syncthreads();
+          if (wave == 0 && l <= m)
+            hp[l] = ((l < m ? dw[l] : e) - ((hsum[0][lane] + hsum[1][lane]) + (hsum[2][lane] + hsum[3][lane]))) * inv;
+          __syncthreads();
+        }
+      }
+    }
+    if (m >= S.maxit) return;
+  }
+  // q_m and u_{m+1} of column c at one slot (step 0: u_0)
+  auto update = [&](int c, int64_t x) {
+    const int col = c0 + c;
+    const double* Vc = S.V + (int64_t)col * k;
+    double* vn = S.V + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
+    if (m < 0) return vn[x];
+    double* vm = S.V + (int64_t)m * S.vvs + (int64_t)col * k;
+    const double* cu = S.h2 + (int64_t)col * S.ldv;
+    const double* dw = S.dw + (int64_t)col * S.ldv;
+    const double rho = scal[c][0], e = scal[c][1];
+    const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
+    double sc = vm[x], sw = S.w[(int64_t)col * k + x];
+#pragma unroll 16
+    for (int i = 0; i < m; ++i) {
+      const double v = Vc[(int64_t)i * S.vvs + x];
+      sc = fma(-cu[i], v, sc);
+      sw = fma(-dw[i], v, sw);
+    }
+    const double q = sc * inv;
+    const double un = fma(-e, q, sw) * inv;
+    vm[x] = q;
+    vn[x] = un;
+    return un;
+  };
+  if (!use_precond) {
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + tid; x < k; x += (int64_t)gridDim.x * kThreads)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (on[c]) S.z[(int64_t)(c0 + c) * k + x] = update(c, x);
+    return;
+  }
+  for (int b = blockIdx.x; b < P.nblk; b += gridDim.x) {
+    const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
+    const int bc = P.blk_cls[b];
+    __syncthreads();
+    for (int i = tid; i < sb; i += kThreads) {
+      const int slot = P.blk_slots[o + i];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xs[c][i] = on[c] ? (Acc)update(c, slot) : Acc(0);
+    }
+    __syncthreads();
+    const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
+    block_jacobi_apply<NC>(Mp, &xs[0][0], 8 * kMaxN, sb, bpart, [&](int c, int r, Acc v) {
+      if (on[c]) S.z[(int64_t)(c0 + c) * k + P.blk_slots[o + r]] = (double)v;
+    });
   }
 }
 
@@ -430,12 +565,30 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
              int mprec) {
   const dim3 pg(precond_grid(P, S, kind), nrhs);
   const int up = kind == 1 ? 0 : 1, trn = tr ? 1 : 0;
-  if (mprec == PREC_F32)
+  if (S.prereduce && nrhs >= 2 && up) {
+    // several columns per workgroup: each block-Jacobi inverse is read once for them
+    const int nc = nrhs >= 4 ? 4 : 2;
+    const dim3 pn(pg.x, (nrhs + nc - 1) / nc);
+#define SMPM_UPDATE_N(T)                                                                            \
+  if (nc == 4)                                                                                      \
+    hipLaunchKernelGGL((k_gm_update_n<T, 4>), pn, dim3(kThreads), 0, s, P, S, par, up, trn);         \
+  else                                                                                              \
+    hipLaunchKernelGGL((k_gm_update_n<T, 2>), pn, dim3(kThreads), 0, s, P, S, par, up, trn);
+    if (mprec == PREC_F32) {
+      SMPM_UPDATE_N(float)
+    } else if (mprec == PREC_BF16) {
+      SMPM_UPDATE_N(bf16s)
+    } else {
+      SMPM_UPDATE_N(double)
+    }
+#undef SMPM_UPDATE_N
+  } else if (mprec == PREC_F32) {
     hipLaunchKernelGGL(k_gm_update<float>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
-  else if (mprec == PREC_BF16)
+  } else if (mprec == PREC_BF16) {
     hipLaunchKernelGGL(k_gm_update<bf16s>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
-  else
+  } else {
     hipLaunchKernelGGL(k_gm_update<double>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
+  }
   const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P) && P.coarse_mode == 1;
   launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s, sprec);
   if (kind == 3) {

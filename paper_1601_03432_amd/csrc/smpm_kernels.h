@@ -141,28 +141,40 @@ template <>
 __device__ __forceinline__ const bf16s* mma_op<bf16s>(const DevPlan& P, bool adj) {
   return reinterpret_cast<const bf16s*>(adj ? P.AadjB : P.AfwdB);
 }
-// One block-Jacobi block applied by a 256-thread workgroup: y_r = sum_c M[c*sb + r] x_c
-// (sb <= 8 kMaxN = 256).  The columns of each row are split into 256/sb contiguous
-// parts summed by separate threads and then added in a fixed order, so every caller
-// gets the same bits.  Contains a barrier: call from all threads.  part: LDS, 256 Acc.
-template <typename OpT, typename Acc, typename Store>
-__device__ __forceinline__ void block_jacobi_apply(const OpT* __restrict__ Mp, const Acc* xs, int sb, Acc* part,
-                                                   Store store) {
+// One block-Jacobi block applied by a 256-thread workgroup to NV vectors x_v (LDS,
+// x_v[c] = xs[v * xstride + c]): y_{v,r} = sum_c M[c*sb + r] x_{v,c} (sb <= 8 kMaxN =
+// 256), each entry of M read once for all NV vectors.  The columns of each row are
+// split into 256/sb contiguous parts summed by separate threads and then added in a
+// fixed order, so every caller (and every NV) gets the same bits per vector.
+// Contains a barrier: call from all threads.  part: LDS, NV * 256 Acc.
+template <int NV, typename OpT, typename Acc, typename Store>
+__device__ __forceinline__ void block_jacobi_apply(const OpT* __restrict__ Mp, const Acc* xs, int xstride, int sb,
+                                                   Acc* part, Store store) {
   const int tid = threadIdx.x;
   const int np = max(1, 256 / sb), len = (sb + np - 1) / np;
   if (tid < np * sb) {
     const int r = tid % sb, p = tid / sb;
     const int c0 = p * len, c1 = min(sb, c0 + len);
-    Acc acc = 0;
+    Acc acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0;
 #pragma unroll 8
-    for (int c = c0; c < c1; ++c) acc = fma(to_acc(Mp[c * sb + r]), xs[c], acc);
-    part[p * sb + r] = acc;
+    for (int c = c0; c < c1; ++c) {
+      const Acc mv = to_acc(Mp[c * sb + r]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = fma(mv, xs[v * xstride + c], acc[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) part[v * 256 + p * sb + r] = acc[v];
   }
   __syncthreads();
   if (tid < sb) {
-    Acc sum = part[tid];
-    for (int p = 1; p < np; ++p) sum += part[p * sb + tid];
-    store(tid, sum);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      Acc sum = part[v * 256 + tid];
+      for (int p = 1; p < np; ++p) sum += part[v * 256 + p * sb + tid];
+      store(v, tid, sum);
+    }
   }
 }
 

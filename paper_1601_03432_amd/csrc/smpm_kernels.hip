@@ -665,7 +665,7 @@ __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __rest
   for (int i = tid; i < sb; i += 256) xs[i] = (Acc)xc[P.blk_slots[o + i]];
   __syncthreads();
   const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
-  block_jacobi_apply(Mp, xs, sb, part, [&](int r, Acc v) { yc[P.blk_slots[o + r]] = (double)v; });
+  block_jacobi_apply<1>(Mp, xs, 0, sb, part, [&](int, int r, Acc v) { yc[P.blk_slots[o + r]] = (double)v; });
 }
 
 // ------------------------------------------------------------------ deflation
