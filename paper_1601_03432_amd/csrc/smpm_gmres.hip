@@ -20,11 +20,11 @@
 // counter is double-buffered: step q of a chunk reads slot q % 2 and its last kernel
 // writes j + 1 into the other slot, so no kernel reads a value another block of it
 // may be changing:
-//   gm_update   (m = j - 1) rho, e from the previous dot pass; block 0 applies the
-//               Givens rotations to Hessenberg column m-1 and retires the column
-//               once its residual estimate reaches tol * |b|, and forms h'_m;
-//               q_m into V_m, u_{m+1} into V_{m+1}, z = M^{-1} u_{m+1}
-//               (step 0: z = M^{-1} u_0)
+//   gm_update   (m = j - 1) rho, e from the previous dot pass; block 0 (alone)
+//               applies the Givens rotations to Hessenberg column m-1, retires the
+//               column once its residual estimate reaches tol * |b|, and forms h'_m;
+//               the other blocks write q_m into V_m and u_{m+1} into V_{m+1} and
+//               apply z = M^{-1} u_{m+1} (step 0: z = M^{-1} u_0)
 //   Schur       t = S z, with the per-side sums of t for Z^T t
 //   coarse      c2 = G Z^T t
 //   gm_dots     w = t - Z c2 - S Z c2 (deflation); partial dots of V_0..V_j with w
@@ -58,22 +58,32 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// out[i] = sum_c part[i*nch + c], i < nvec, into LDS.  Wave q owns groups of
-// eight vectors; lanes take chunks lane, lane+64, ... and a fixed shuffle tree
-// combines them, so every block obtains bit-identical sums.
-__device__ void reduce_partials(const double* __restrict__ part, int nvec, int nch, double* out) {
+// outA[i] = sum_c partA[i*nch + c] and outB likewise, i < nvec, into LDS, with the
+// loads of both arrays in flight together.  Wave q owns groups of eight vectors;
+// lanes take chunks lane, lane+64, ... and a fixed shuffle tree combines them, so
+// every block obtains bit-identical sums.
+__device__ void reduce_partials2(const double* __restrict__ pa, const double* __restrict__ pb, int nvec, int nch,
+                                 double* oa, double* ob) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i0 = wave * 8; i0 < nvec; i0 += kWaves * 8) {
-    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double aa[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double ab[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int c = lane; c < nch; c += 64) {
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (i0 + u < nvec) acc[u] += part[(int64_t)(i0 + u) * nch + c];
+        if (i0 + u < nvec) {
+          aa[u] += pa[(int64_t)(i0 + u) * nch + c];
+          ab[u] += pb[(int64_t)(i0 + u) * nch + c];
+        }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const double v = wave_sum(acc[u]);
-      if (lane == 0 && i0 + u < nvec) out[i0 + u] = v;
+      const double va = wave_sum(aa[u]);
+      const double vb = wave_sum(ab[u]);
+      if (lane == 0 && i0 + u < nvec) {
+        oa[i0 + u] = va;
+        ob[i0 + u] = vb;
+      }
     }
   }
 }
@@ -196,8 +206,8 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
         cs2[i] = S.h2[(int64_t)col * S.ldv + i];
       }
     } else {
-      reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, m + 1, S.nch, ds);
-      reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, m + 1, S.nch, cs2);
+      reduce_partials2(S.part1 + (int64_t)col * S.ldv * S.nch, S.part2 + (int64_t)col * S.ldv * S.nch, m + 1,
+                       S.nch, ds, cs2);
     }
     __syncthreads();
     if (tid < 64) {
@@ -276,12 +286,14 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     vn[x] = un;
     return un;
   };
+  // block 0 takes the Givens step alone; blocks 1.. share the slots
+  if (blockIdx.x == 0 && gridDim.x > 1) return;
+  const int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0, nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
   if (!use_precond) {
-    for (int64_t x = (int64_t)blockIdx.x * kThreads + tid; x < k; x += (int64_t)gridDim.x * kThreads)
-      zc[x] = update(x);
+    for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads) zc[x] = update(x);
     return;
   }
-  for (int b = blockIdx.x; b < P.nblk; b += gridDim.x) {
+  for (int b = wb; b < P.nblk; b += nwb) {
     const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
     const int bc = P.blk_cls[b];
     __syncthreads();
@@ -403,14 +415,17 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     vn[x] = un;
     return un;
   };
+  // block 0 takes the Givens steps alone; blocks 1.. share the slots
+  if (blockIdx.x == 0 && gridDim.x > 1) return;
+  const int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0, nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
   if (!use_precond) {
-    for (int64_t x = (int64_t)blockIdx.x * kThreads + tid; x < k; x += (int64_t)gridDim.x * kThreads)
+    for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads)
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (on[c]) S.z[(int64_t)(c0 + c) * k + x] = update(c, x);
     return;
   }
-  for (int b = blockIdx.x; b < P.nblk; b += gridDim.x) {
+  for (int b = wb; b < P.nblk; b += nwb) {
     const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
     const int bc = P.blk_cls[b];
     __syncthreads();
@@ -483,17 +498,17 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
 // Pre-reduction after gm_dots (one block per column): the dots with w into dw and
 // with u_j into h2, summed exactly as gm_update sums them itself.
 __global__ __launch_bounds__(256) void k_gm_reduce(GmState S, int par) {
-  __shared__ double hs[kMaxIt + 1];
+  __shared__ double ha[kMaxIt + 1], hb[kMaxIt + 1];
   const int col = blockIdx.y;
   const int j = S.jdev[par];
   if (!S.active[col] || j > S.maxit) return;
-  reduce_partials(S.part1 + (int64_t)col * S.ldv * S.nch, j + 1, S.nch, hs);
+  reduce_partials2(S.part1 + (int64_t)col * S.ldv * S.nch, S.part2 + (int64_t)col * S.ldv * S.nch, j + 1, S.nch,
+                   ha, hb);
   __syncthreads();
-  for (int i = threadIdx.x; i <= j; i += kThreads) S.dw[(int64_t)col * S.ldv + i] = hs[i];
-  __syncthreads();
-  reduce_partials(S.part2 + (int64_t)col * S.ldv * S.nch, j + 1, S.nch, hs);
-  __syncthreads();
-  for (int i = threadIdx.x; i <= j; i += kThreads) S.h2[(int64_t)col * S.ldv + i] = hs[i];
+  for (int i = threadIdx.x; i <= j; i += kThreads) {
+    S.dw[(int64_t)col * S.ldv + i] = ha[i];
+    S.h2[(int64_t)col * S.ldv + i] = hb[i];
+  }
 }
 
 // Start of a solve: u_0 = w (the initial residual) into V_0; all columns active;
@@ -557,8 +572,9 @@ void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStrea
   hipLaunchKernelGGL(k_gm_start, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, tol);
 }
 
+// block 0 of gm_update takes the Givens step; the others share the slots
 static int precond_grid(const DevPlan& P, const GmState& S, int kind) {
-  return kind == 1 ? S.nch : std::max(1, std::min(P.nblk, 1024));
+  return 1 + (kind == 1 ? S.nch : std::max(1, std::min(P.nblk, 1024)));
 }
 
 void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s, int sprec,
