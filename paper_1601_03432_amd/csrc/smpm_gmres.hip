@@ -69,12 +69,20 @@ __device__ void reduce_partials2(const double* __restrict__ pa, const double* __
     double aa[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double ab[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int c = lane; c < nch; c += 64) {
+      // loads of rows past nvec repeat the last row (in bounds, never used), so all
+      // sixteen loads are issued before the first add
+      double la[8], lb[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (i0 + u < nvec) {
-          aa[u] += pa[(int64_t)(i0 + u) * nch + c];
-          ab[u] += pb[(int64_t)(i0 + u) * nch + c];
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int64_t at = (int64_t)min(i0 + u, nvec - 1) * nch + c;
+        la[u] = pa[at];
+        lb[u] = pb[at];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        aa[u] += la[u];
+        ab[u] += lb[u];
+      }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -101,13 +109,16 @@ __device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x
     for (int u = 0; u < kDotUnroll; ++u) aw[u] = au[u] = 0.0;
     for (int x = lane; x < rows; x += 64) {
       const double wx = wv[x], ux = uv[x];
+      // vectors past nvec repeat the last one (in bounds, results never stored), so
+      // every load is issued before the first product
+      double vv[kDotUnroll];
 #pragma unroll
-      for (int u = 0; u < kDotUnroll; ++u)
-        if (i0 + u < nvec) {
-          const double v = V[(int64_t)(i0 + u) * vvs + x0 + x];
-          aw[u] = fma(v, wx, aw[u]);
-          au[u] = fma(v, ux, au[u]);
-        }
+      for (int u = 0; u < kDotUnroll; ++u) vv[u] = V[(int64_t)min(i0 + u, nvec - 1) * vvs + x0 + x];
+#pragma unroll
+      for (int u = 0; u < kDotUnroll; ++u) {
+        aw[u] = fma(vv[u], wx, aw[u]);
+        au[u] = fma(vv[u], ux, au[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < kDotUnroll; ++u) {
