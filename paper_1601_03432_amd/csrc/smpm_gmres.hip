@@ -324,6 +324,8 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
   __shared__ Acc xs[NC][8 * kMaxN];
   __shared__ Acc bpart[NC * 256];
   __shared__ double scal[NC][2];  // rho, e
+  constexpr int kStage = 128;
+  __shared__ double cst[NC][2][kStage];  // c and d of the columns (m <= kStage)
   __shared__ double hsum[kWaves][64];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t k = P.k;
@@ -403,22 +405,44 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     if (m >= S.maxit) return;
   }
   // q_m and u_{m+1} of column c at one slot (step 0: u_0)
+  // the columns' coefficients in LDS when they fit (the common case), else read
+  // from memory in the loop; the same products in the same order either way
+  const bool staged = m >= 0 && m <= kStage;
+  if (staged) {
+    for (int t = tid; t < NC * m; t += kThreads) {
+      const int c = t / max(m, 1), i = t - c * m;
+      if (on[c]) {
+        cst[c][0][i] = S.h2[(int64_t)(c0 + c) * S.ldv + i];
+        cst[c][1][i] = S.dw[(int64_t)(c0 + c) * S.ldv + i];
+      }
+    }
+    __syncthreads();
+  }
   auto update = [&](int c, int64_t x) {
     const int col = c0 + c;
     const double* Vc = S.V + (int64_t)col * k;
     double* vn = S.V + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
     if (m < 0) return vn[x];
     double* vm = S.V + (int64_t)m * S.vvs + (int64_t)col * k;
-    const double* cu = S.h2 + (int64_t)col * S.ldv;
-    const double* dw = S.dw + (int64_t)col * S.ldv;
     const double rho = scal[c][0], e = scal[c][1];
     const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
     double sc = vm[x], sw = S.w[(int64_t)col * k + x];
+    if (staged) {
 #pragma unroll 16
-    for (int i = 0; i < m; ++i) {
-      const double v = Vc[(int64_t)i * S.vvs + x];
-      sc = fma(-cu[i], v, sc);
-      sw = fma(-dw[i], v, sw);
+      for (int i = 0; i < m; ++i) {
+        const double v = Vc[(int64_t)i * S.vvs + x];
+        sc = fma(-cst[c][0][i], v, sc);
+        sw = fma(-cst[c][1][i], v, sw);
+      }
+    } else {
+      const double* cu = S.h2 + (int64_t)col * S.ldv;
+      const double* dw = S.dw + (int64_t)col * S.ldv;
+#pragma unroll 16
+      for (int i = 0; i < m; ++i) {
+        const double v = Vc[(int64_t)i * S.vvs + x];
+        sc = fma(-cu[i], v, sc);
+        sw = fma(-dw[i], v, sw);
+      }
     }
     const double q = sc * inv;
     const double un = fma(-e, q, sw) * inv;
