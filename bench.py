@@ -40,15 +40,20 @@ HBM_PEAK_GBS = 8000.0
 # averaged over the timed launches), each scaled by the counter's reading for a
 # plain kernel of known size (FETCH_SIZE reads half of a 64 MiB elementwise read,
 # so x2.0; WRITE_SIZE matches a 64 MiB fill, x1.0).  Valid only for the kernel
-# source it was measured on (sha256 below); otherwise null.
+# source it was measured on (sha256 of the Schur section below); otherwise null.
 SCHUR_TRAFFIC = {"fetch_kib": 39084.8, "write_kib": 65024.0,
-                 "kernels_sha256": "021b746138935e2bf6568528208e18867649de2e6c3910d166c9973566d741e7"}
+                 "kernels_sha256": "86adfef4933869c2b79bd4bf97e5dad6c0d6a1ff147b993a57738523742e4224"}
 
 
 def kernels_sha256():
+    """sha256 of the metric kernel's source: the matrix-core Schur apply section of
+    csrc/smpm_kernels.hip (its helpers and k_schur_mfma)."""
     import hashlib
     path = os.path.join(ROOT, "paper_1601_03432_amd", "csrc", "smpm_kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    txt = open(path).read()
+    a = txt.index("// ------------------------------------------------------------------ Schur apply on matrix cores")
+    b = txt.index("// Persistent, software-pipelined variant")
+    return hashlib.sha256(txt[a:b].encode()).hexdigest()
 
 
 def graph_time_us(launch, launches, replays=20):

@@ -766,30 +766,49 @@ __global__ __launch_bounds__(256) void k_sub_rhs(DevPlan P, const double* __rest
 }
 
 // x_B = S_B^{-1} r (transpose: S_B^{-T} r): wave per row, r staged in LDS.
-__global__ __launch_bounds__(256) void k_sub_sep(DevPlan P, double* __restrict__ c2, int transpose,
+template <int NC>
+__global__ __launch_bounds__(256) void k_sub_sep(DevPlan P, double* __restrict__ c2, int transpose, int nrhs,
                                                  const int* __restrict__ active) {
-  extern __shared__ double rl[];
-  const int col = blockIdx.y;
-  if (active && !active[col]) return;
+  // x_B = S_B^{-1} r for NC columns at once: each row of S_B^{-1} is read once for
+  // all of them; r comes through the caches (per column, the same sums in the same
+  // order as for one column)
+  const int c0 = blockIdx.y * NC;
+  bool on[NC];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    on[c] = c0 + c < nrhs && (!active || active[c0 + c]);
+    any = any || on[c];
+  }
+  if (!any) return;
   const int nS = P.sub_nsep + P.sub_border;
-  double* ws = P.cws + (int64_t)col * P.cws_stride;
-  const double* r = ws + sub_part_len(P);
-  for (int j = threadIdx.x; j < nS; j += blockDim.x) rl[j] = r[j];
-  __syncthreads();
+  const double* r[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) r[c] = P.cws + (int64_t)(on[c] ? c0 + c : c0) * P.cws_stride + sub_part_len(P);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double* Si = transpose ? P.sub_SiT : P.sub_Si;
   for (int q = 0; q < 4; ++q) {
     const int a = (blockIdx.x * 4 + wave) * 4 + q;
     if (a >= nS) break;
     const double* row = Si + (int64_t)a * nS;
-    double acc = 0.0;
-    for (int j = lane; j < nS; j += 64) acc = fma(row[j], rl[j], acc);
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) {
-      if (a < P.sub_nsep)
-        c2[(int64_t)col * P.d + P.sub_sep_iface[a]] = acc;
-      else
-        ws[sub_part_len(P) + nS] = acc;  // lambda
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int j = lane; j < nS; j += 64) {
+      const double m = row[j];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = fma(m, r[c][j], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double v = acc[c];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0 && on[c]) {
+        if (a < P.sub_nsep)
+          c2[(int64_t)(c0 + c) * P.d + P.sub_sep_iface[a]] = v;
+        else
+          P.cws[(int64_t)(c0 + c) * P.cws_stride + sub_part_len(P) + nS] = v;  // lambda
+      }
     }
   }
 }
@@ -1252,8 +1271,11 @@ void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool
                        active);
     if (nS > 0) {
       hipLaunchKernelGGL(k_sub_rhs, dim3((nS + 255) / 256, nrhs), dim3(256), 0, s, P, c, active);
-      hipLaunchKernelGGL(k_sub_sep, dim3((nS + 15) / 16, nrhs), dim3(256), (size_t)nS * sizeof(double), s, P, c2,
-                         tr, active);
+      if (nrhs >= 4)
+        hipLaunchKernelGGL(k_sub_sep<4>, dim3((nS + 15) / 16, (nrhs + 3) / 4), dim3(256), 0, s, P, c2, tr, nrhs,
+                           active);
+      else
+        hipLaunchKernelGGL(k_sub_sep<1>, dim3((nS + 15) / 16, nrhs), dim3(256), 0, s, P, c2, tr, nrhs, active);
       hipLaunchKernelGGL(k_sub_patch2, dim3(P.sub_npatch, nrhs), dim3(256), sub_patch_lds(P), s, P, c2, tr,
                          active);
     }
