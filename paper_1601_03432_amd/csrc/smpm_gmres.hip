@@ -299,12 +299,16 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   };
   // block 0 takes the Givens step alone; blocks 1.. share the slots
   if (blockIdx.x == 0 && gridDim.x > 1) return;
-  const int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0, nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
+  int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
+  const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
   if (!use_precond) {
     for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads) zc[x] = update(x);
     return;
   }
-  for (int b = wb; b < P.nblk; b += nwb) {
+  // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD adjacent
+  if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
+  const int per = (P.nblk + nwb - 1) / nwb;
+  for (int b = wb * per; b < min(P.nblk, (wb + 1) * per); ++b) {
     const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
     const int bc = P.blk_cls[b];
     __syncthreads();
@@ -452,7 +456,8 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
   };
   // block 0 takes the Givens steps alone; blocks 1.. share the slots
   if (blockIdx.x == 0 && gridDim.x > 1) return;
-  const int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0, nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
+  int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
+  const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
   if (!use_precond) {
     for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads)
 #pragma unroll
@@ -460,7 +465,10 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
         if (on[c]) S.z[(int64_t)(c0 + c) * k + x] = update(c, x);
     return;
   }
-  for (int b = wb; b < P.nblk; b += nwb) {
+  // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD adjacent
+  if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
+  const int per = (P.nblk + nwb - 1) / nwb;
+  for (int b = wb * per; b < min(P.nblk, (wb + 1) * per); ++b) {
     const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
     const int bc = P.blk_cls[b];
     __syncthreads();

@@ -101,6 +101,11 @@ struct DevPlan {
 constexpr int kGroup = 8;
 constexpr int kTile = 16;
 
+// Workgroup b of nb (nb a multiple of 8) mapped so that each of the 8 XCDs (which
+// receive workgroup ids round-robin) works on one contiguous range: neighbouring
+// work items then share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
+
 // operator precision of the Schur / block-Jacobi applies
 enum OpPrec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 

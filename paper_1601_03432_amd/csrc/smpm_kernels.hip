@@ -22,10 +22,6 @@ __device__ __forceinline__ int side_node(int n, int s, int t) {
 
 // ------------------------------------------------------------------ Schur apply
 
-// Blocks are mapped so that each of the 8 XCDs (which receive block ids
-// round-robin) works on one contiguous range of groups: neighbouring elements
-// then share an L2.
-__device__ __forceinline__ int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
 constexpr int kPrefetch = 8;  // independent operator loads in flight per lane
 
@@ -656,7 +652,8 @@ __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __rest
   using Acc = typename AccOf<OpT>::type;
   __shared__ Acc xs[8 * kMaxN];
   __shared__ Acc part[256];
-  const int b = blockIdx.x, col = blockIdx.y, tid = threadIdx.x;
+  const int b = gridDim.x % 8 == 0 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int col = blockIdx.y, tid = threadIdx.x;
   if (active && !active[col]) return;
   const double* xc = x + (int64_t)col * P.k;
   double* yc = y + (int64_t)col * P.k;
@@ -787,23 +784,38 @@ __global__ __launch_bounds__(256) void k_sub_sep(DevPlan P, double* __restrict__
   for (int c = 0; c < NC; ++c) r[c] = P.cws + (int64_t)(on[c] ? c0 + c : c0) * P.cws_stride + sub_part_len(P);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double* Si = transpose ? P.sub_SiT : P.sub_Si;
+  // the wave's four rows advance together (rows past nS repeat the last row, in
+  // bounds, results not stored), so their loads are in flight at once
+  const int a0 = (blockIdx.x * 4 + wave) * 4;
+  if (a0 >= nS) return;
+  const double* row[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) row[q] = Si + (int64_t)min(a0 + q, nS - 1) * nS;
+  double acc[4][NC];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[q][c] = 0.0;
+#pragma unroll 2
+  for (int j = lane; j < nS; j += 64) {
+    double m[4], rv[NC];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = row[q][j];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rv[c] = r[c][j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[q][c] = fma(m[q], rv[c], acc[q][c]);
+  }
+#pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int a = (blockIdx.x * 4 + wave) * 4 + q;
-    if (a >= nS) break;
-    const double* row = Si + (int64_t)a * nS;
-    double acc[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int j = lane; j < nS; j += 64) {
-      const double m = row[j];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] = fma(m, r[c][j], acc[c]);
-    }
+    const int a = a0 + q;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      double v = acc[c];
+      double v = acc[q][c];
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if (lane == 0 && on[c]) {
+      if (lane == 0 && on[c] && a < nS) {
         if (a < P.sub_nsep)
           c2[(int64_t)(c0 + c) * P.d + P.sub_sep_iface[a]] = v;
         else

@@ -592,6 +592,24 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
     p.blk_cls.push_back(it->second);
   }
   p.nblk = (int)p.blk_red.size();
+  {
+    // order the blocks by class, so that a run of blocks given to one workgroup (and
+    // the runs of one XCD) mostly share one block inverse in cache
+    std::vector<int> ord(p.nblk);
+    for (int b = 0; b < p.nblk; ++b) ord[b] = b;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return p.blk_cls[a] < p.blk_cls[b]; });
+    std::vector<int> red, off{0}, slots, cls;
+    for (int b : ord) {
+      red.push_back(p.blk_red[b]);
+      cls.push_back(p.blk_cls[b]);
+      slots.insert(slots.end(), p.blk_slots.begin() + p.blk_off[b], p.blk_slots.begin() + p.blk_off[b + 1]);
+      off.push_back((int)slots.size());
+    }
+    p.blk_red.swap(red);
+    p.blk_off.swap(off);
+    p.blk_slots.swap(slots);
+    p.blk_cls.swap(cls);
+  }
   int64_t mtot = 0;
   for (size_t b = 0; b < bmats.size(); ++b) {
     p.bcls_off.push_back(mtot);
