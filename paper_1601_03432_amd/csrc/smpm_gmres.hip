@@ -135,9 +135,12 @@ __device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x
 // Givens step for Hessenberg column jc = j-1 of one right-hand side, run by
 // block 0 of gm_update: H(:, jc) = h1 + h2 with beta below the diagonal (stored
 // unrotated in Hu), rotated by the previous rotations; a new rotation zeroes beta.
-__device__ void givens_column(const GmState& S, int col, int j, double beta, const double* h2) {
-  __shared__ double hc[kMaxIt + 2];
-  __shared__ double csl[kMaxIt + 1], snl[kMaxIt + 1];
+// lds: the caller's LDS, kGivensLds doubles.
+constexpr int kGivensLds = 3 * (kMaxIt + 2);
+__device__ void givens_column(const GmState& S, int col, int j, double beta, const double* h2, double* lds) {
+  double* hc = lds;
+  double* csl = lds + (kMaxIt + 2);
+  double* snl = lds + 2 * (kMaxIt + 2);
   const int tid = threadIdx.x;
   const int jc = j - 1;
   const double* h1 = S.h1 + (int64_t)col * S.ldv;
@@ -190,16 +193,24 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
 
 // Step j's first kernel (see the file header; m = j - 1).  Step 0: z = M^{-1} u_0.
 // givens_only: stop after the Givens step (the last step of a solve).
-template <typename OpT>
+template <typename OpT, bool PRE>
 __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par, int use_precond, int transpose,
                                                    int givens_only) {
   using Acc = typename AccOf<OpT>::type;
-  __shared__ Acc xs[8 * kMaxN];
+  // block-Jacobi staging: up to kGroup blocks of one class, kStageSlots slots
+  constexpr int kGroup = 4, kStageSlots = 512;
+  static_assert(kStageSlots >= 8 * kMaxN, "one block must fit the staging area");
+  static_assert((kStageSlots + kGroup * 256) * sizeof(Acc) <= kGivensLds * sizeof(double), "LDS union");
+  // block 0 uses wsp for the Givens step and then for the h' sums; the other blocks
+  // (which never take the Givens step when the grid has more than one block) stage
+  // their slots in it
+  __shared__ double wsp[kGivensLds];
   __shared__ double red[2 * kWaves];
   __shared__ double ds[kMaxIt + 1];  // d_0..d_{m-1}, then alpha
   __shared__ double cs2[kMaxIt + 1]; // c_0..c_{m-1}, then nu
-  __shared__ double hsum[kWaves][64];
-  __shared__ Acc bpart[256];
+  double (*hsum)[64] = reinterpret_cast<double (*)[64]>(wsp);
+  Acc* xs = reinterpret_cast<Acc*>(wsp);
+  Acc* bpart = xs + kStageSlots;
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
   const int j = S.jdev[par];
@@ -211,7 +222,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   if (j > 0) {
     m = j - 1;
     if (m > S.maxit) return;
-    if (S.prereduce) {
+    if (PRE) {  // sums reduced once per column by k_gm_reduce
       for (int i = tid; i <= m; i += kThreads) {
         ds[i] = S.dw[(int64_t)col * S.ldv + i];
         cs2[i] = S.h2[(int64_t)col * S.ldv + i];
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
           }
         }
       } else {
-        givens_column(S, col, m, rho, cs2);
+        givens_column(S, col, m, rho, cs2, wsp);
       }
       // h'_m = ([d; e] - H c) / rho with the unrotated columns 0..m-1 (after the
       // Givens step has read h'_{m-1}): lanes take rows l, the waves split the
@@ -297,6 +308,34 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     vn[x] = un;
     return un;
   };
+  // the same at two slots, the loads of both in flight together (x1 is stored only
+  // if st1; otherwise it must still be a valid slot)
+  auto update2 = [&](int64_t x0, int64_t x1, bool st1, double& r0, double& r1) {
+    if (m < 0) {
+      r0 = vn[x0];
+      r1 = vn[x1];
+      return;
+    }
+    double sc0 = vm[x0], sw0 = wc[x0], sc1 = vm[x1], sw1 = wc[x1];
+#pragma unroll 8
+    for (int i = 0; i < m; ++i) {
+      const double v0 = Vc[(int64_t)i * S.vvs + x0];
+      const double v1 = Vc[(int64_t)i * S.vvs + x1];
+      sc0 = fma(-cs2[i], v0, sc0);
+      sw0 = fma(-ds[i], v0, sw0);
+      sc1 = fma(-cs2[i], v1, sc1);
+      sw1 = fma(-ds[i], v1, sw1);
+    }
+    const double q0 = sc0 * inv, q1 = sc1 * inv;
+    r0 = fma(-e, q0, sw0) * inv;
+    r1 = fma(-e, q1, sw1) * inv;
+    vm[x0] = q0;
+    vn[x0] = r0;
+    if (st1) {
+      vm[x1] = q1;
+      vn[x1] = r1;
+    }
+  };
   // block 0 takes the Givens step alone; blocks 1.. share the slots
   if (blockIdx.x == 0 && gridDim.x > 1) return;
   int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
@@ -305,17 +344,38 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads) zc[x] = update(x);
     return;
   }
-  // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD adjacent
+  // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD
+  // adjacent; consecutive blocks of one class are staged together and share every
+  // read of their inverse (the apply gives each block the same bits as alone)
   if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
   const int per = (P.nblk + nwb - 1) / nwb;
-  for (int b = wb * per; b < min(P.nblk, (wb + 1) * per); ++b) {
-    const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
+  const int bend = min(P.nblk, (wb + 1) * per);
+  for (int b = wb * per; b < bend;) {
+    const int o0 = P.blk_off[b], sb = P.blk_off[b + 1] - o0;
     const int bc = P.blk_cls[b];
-    __syncthreads();
-    for (int i = tid; i < sb; i += kThreads) xs[i] = (Acc)update(P.blk_slots[o + i]);
+    int nb = 1;  // blocks of one class have one size and adjacent slot lists
+    while (nb < kGroup && b + nb < bend && P.blk_cls[b + nb] == bc && (nb + 1) * sb <= kStageSlots) ++nb;
+    const int tot = nb * sb;
+    __syncthreads();  // the previous group's apply has read xs (block 0: wsp is free)
+    if (tot > kThreads) {
+      const int i1 = tid + kThreads;
+      const bool in1 = i1 < tot;
+      double r0, r1;
+      update2(P.blk_slots[o0 + tid], P.blk_slots[o0 + (in1 ? i1 : tot - 1)], in1, r0, r1);
+      xs[tid] = (Acc)r0;
+      if (in1) xs[i1] = (Acc)r1;
+    } else if (tid < tot) {
+      xs[tid] = (Acc)update(P.blk_slots[o0 + tid]);
+    }
     __syncthreads();
     const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
-    block_jacobi_apply<1>(Mp, xs, 0, sb, bpart, [&](int, int r, Acc v) { zc[P.blk_slots[o + r]] = (double)v; });
+    if (nb == 1)
+      block_jacobi_apply<1>(Mp, xs, sb, sb, bpart, [&](int, int r, Acc val) { zc[P.blk_slots[o0 + r]] = (double)val; });
+    else
+      block_jacobi_apply<kGroup>(Mp, xs, sb, sb, bpart, [&](int v, int r, Acc val) {
+        if (v < nb) zc[P.blk_slots[o0 + v * sb + r]] = (double)val;
+      });
+    b += nb;
   }
 }
 
@@ -331,6 +391,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
   constexpr int kStage = 128;
   __shared__ double cst[NC][2][kStage];  // c and d of the columns (m <= kStage)
   __shared__ double hsum[kWaves][64];
+  __shared__ double gwork[kGivensLds];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t k = P.k;
   const int nrhs = (int)(S.vvs / k);
@@ -385,7 +446,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
             }
           }
         } else {
-          givens_column(S, col, m, rho, cu);
+          givens_column(S, col, m, rho, cu, gwork);
         }
         __syncthreads();
         const double* Hu = S.Hu + (int64_t)col * S.ldv * S.maxit;
@@ -454,6 +515,50 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     vn[x] = un;
     return un;
   };
+  // the same for column ca at slot xa and column cb at slot xb, the loads of both in
+  // flight together (both columns active, m >= 0)
+  auto update2 = [&](int ca, int64_t xa, int cb, int64_t xb, double& ra, double& rb) {
+    const double* Va = S.V + (int64_t)(c0 + ca) * k;
+    const double* Vb = S.V + (int64_t)(c0 + cb) * k;
+    double* vma = S.V + (int64_t)m * S.vvs + (int64_t)(c0 + ca) * k;
+    double* vmb = S.V + (int64_t)m * S.vvs + (int64_t)(c0 + cb) * k;
+    double sca = vma[xa], swa = S.w[(int64_t)(c0 + ca) * k + xa];
+    double scb = vmb[xb], swb = S.w[(int64_t)(c0 + cb) * k + xb];
+    if (staged) {
+#pragma unroll 8
+      for (int i = 0; i < m; ++i) {
+        const double va = Va[(int64_t)i * S.vvs + xa];
+        const double vb = Vb[(int64_t)i * S.vvs + xb];
+        sca = fma(-cst[ca][0][i], va, sca);
+        swa = fma(-cst[ca][1][i], va, swa);
+        scb = fma(-cst[cb][0][i], vb, scb);
+        swb = fma(-cst[cb][1][i], vb, swb);
+      }
+    } else {
+      const double* cua = S.h2 + (int64_t)(c0 + ca) * S.ldv;
+      const double* dwa = S.dw + (int64_t)(c0 + ca) * S.ldv;
+      const double* cub = S.h2 + (int64_t)(c0 + cb) * S.ldv;
+      const double* dwb = S.dw + (int64_t)(c0 + cb) * S.ldv;
+#pragma unroll 8
+      for (int i = 0; i < m; ++i) {
+        const double va = Va[(int64_t)i * S.vvs + xa];
+        const double vb = Vb[(int64_t)i * S.vvs + xb];
+        sca = fma(-cua[i], va, sca);
+        swa = fma(-dwa[i], va, swa);
+        scb = fma(-cub[i], vb, scb);
+        swb = fma(-dwb[i], vb, swb);
+      }
+    }
+    const double inva = scal[ca][0] > 0.0 ? 1.0 / scal[ca][0] : 0.0;
+    const double invb = scal[cb][0] > 0.0 ? 1.0 / scal[cb][0] : 0.0;
+    const double qa = sca * inva, qb = scb * invb;
+    ra = fma(-scal[ca][1], qa, swa) * inva;
+    rb = fma(-scal[cb][1], qb, swb) * invb;
+    vma[xa] = qa;
+    S.V[(int64_t)(m + 1) * S.vvs + (int64_t)(c0 + ca) * k + xa] = ra;
+    vmb[xb] = qb;
+    S.V[(int64_t)(m + 1) * S.vvs + (int64_t)(c0 + cb) * k + xb] = rb;
+  };
   // block 0 takes the Givens steps alone; blocks 1.. share the slots
   if (blockIdx.x == 0 && gridDim.x > 1) return;
   int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
@@ -472,10 +577,23 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
     const int bc = P.blk_cls[b];
     __syncthreads();
-    for (int i = tid; i < sb; i += kThreads) {
-      const int slot = P.blk_slots[o + i];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) xs[c][i] = on[c] ? (Acc)update(c, slot) : Acc(0);
+    // the NC * sb (column, slot) items, two per thread
+    const int tot = NC * sb;
+    for (int u = tid; u < tot; u += 2 * kThreads) {
+      const int ca = u / sb, ia = u - ca * sb;
+      const int u1 = u + kThreads;
+      const bool in1 = u1 < tot;
+      const int cb = in1 ? u1 / sb : ca, ib = in1 ? u1 - cb * sb : ia;
+      const bool pa = on[ca], pb = in1 && on[cb];
+      if (pa && pb && m >= 0) {
+        double ra, rb;
+        update2(ca, P.blk_slots[o + ia], cb, P.blk_slots[o + ib], ra, rb);
+        xs[ca][ia] = (Acc)ra;
+        xs[cb][ib] = (Acc)rb;
+      } else {
+        xs[ca][ia] = pa ? (Acc)update(ca, P.blk_slots[o + ia]) : Acc(0);
+        if (in1) xs[cb][ib] = pb ? (Acc)update(cb, P.blk_slots[o + ib]) : Acc(0);
+      }
     }
     __syncthreads();
     const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
@@ -641,12 +759,20 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
       SMPM_UPDATE_N(double)
     }
 #undef SMPM_UPDATE_N
-  } else if (mprec == PREC_F32) {
-    hipLaunchKernelGGL(k_gm_update<float>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
-  } else if (mprec == PREC_BF16) {
-    hipLaunchKernelGGL(k_gm_update<bf16s>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
   } else {
-    hipLaunchKernelGGL(k_gm_update<double>, pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
+#define SMPM_UPDATE_1(T)                                                                                   \
+  if (S.prereduce)                                                                                          \
+    hipLaunchKernelGGL((k_gm_update<T, true>), pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);            \
+  else                                                                                                      \
+    hipLaunchKernelGGL((k_gm_update<T, false>), pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
+    if (mprec == PREC_F32) {
+      SMPM_UPDATE_1(float)
+    } else if (mprec == PREC_BF16) {
+      SMPM_UPDATE_1(bf16s)
+    } else {
+      SMPM_UPDATE_1(double)
+    }
+#undef SMPM_UPDATE_1
   }
   const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P) && P.coarse_mode == 1;
   launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s, sprec);
@@ -664,8 +790,12 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
 }
 
 void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_update<double>, dim3(1, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 1 ? 0 : 1,
-                     tr ? 1 : 0, 1);
+  if (S.prereduce)
+    hipLaunchKernelGGL((k_gm_update<double, true>), dim3(1, nrhs), dim3(kThreads), 0, s, P, S, par,
+                       kind == 1 ? 0 : 1, tr ? 1 : 0, 1);
+  else
+    hipLaunchKernelGGL((k_gm_update<double, false>), dim3(1, nrhs), dim3(kThreads), 0, s, P, S, par,
+                       kind == 1 ? 0 : 1, tr ? 1 : 0, 1);
 }
 
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s) {
