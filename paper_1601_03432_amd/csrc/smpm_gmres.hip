@@ -58,41 +58,69 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// outA[i] = sum_c partA[i*nch + c] and outB likewise, i < nvec, into LDS, with the
-// loads of both arrays in flight together.  Wave q owns groups of eight vectors;
-// lanes take chunks lane, lane+64, ... and a fixed shuffle tree combines them, so
-// every block obtains bit-identical sums.
+// oa[v] = sum_c pa[c*ld + v] and ob likewise, v < nvec (the dots' partials, one row of
+// ld entries per chunk), with the loads of both arrays in flight together.  The
+// order of the additions is fixed whatever the block shape: chunk c belongs to class
+// c mod 16, a class sums its chunks in increasing c, and the class sums s_q are
+// combined as (t_0 + t_1) + (t_2 + t_3) with t_r = (s_r + s_{r+4}) + (s_{r+8} +
+// s_{r+12}); every block, of 4 or of 16 waves, obtains the same bits.  Lanes run
+// over vectors (coalesced rows), the NW waves share the classes.  Vector groups
+// g0, g0 + gstep, ... of 64.  lds: 2 * NW * 64 doubles.  Contains barriers: call from
+// all threads of the block.
+template <int NW>
 __device__ void reduce_partials2(const double* __restrict__ pa, const double* __restrict__ pb, int nvec, int nch,
-                                 double* oa, double* ob) {
+                                 int ld, double* oa, double* ob, double* lds, int g0 = 0, int gstep = 1) {
+  static_assert(NW == 4 || NW == 16, "four or sixteen waves");
+  constexpr int CPW = 16 / NW;  // classes of this wave: q = wave + NW * t
+  constexpr int R = 16 / CPW;   // 16-chunk strides per batch: 2 * CPW * R = 32 loads in flight
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i0 = wave * 8; i0 < nvec; i0 += kWaves * 8) {
-    double aa[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double ab[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int c = lane; c < nch; c += 64) {
-      // loads of rows past nvec repeat the last row (in bounds, never used), so all
-      // sixteen loads are issued before the first add
-      double la[8], lb[8];
+  for (int g = g0; g * 64 < nvec; g += gstep) {
+    const int v = min(g * 64 + lane, nvec - 1);
+    double sa[CPW], sb[CPW];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int64_t at = (int64_t)min(i0 + u, nvec - 1) * nch + c;
-        la[u] = pa[at];
-        lb[u] = pb[at];
+    for (int t = 0; t < CPW; ++t) sa[t] = sb[t] = 0.0;
+    for (int c0 = 0; c0 < nch; c0 += 16 * R) {
+      // chunks past nch repeat the last one (in bounds) and are not added
+      double la[R][CPW], lb[R][CPW];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < CPW; ++t) {
+          const int64_t at = (int64_t)min(c0 + 16 * r + wave + NW * t, nch - 1) * ld + v;
+          la[r][t] = pa[at];
+          lb[r][t] = pb[at];
+        }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < CPW; ++t) {
+          const bool ok = c0 + 16 * r + wave + NW * t < nch;
+          sa[t] = ok ? sa[t] + la[r][t] : sa[t];
+          sb[t] = ok ? sb[t] + lb[r][t] : sb[t];
+        }
+    }
+    const int out = g * 64 + lane;
+    if (NW == 4) {  // this wave holds s_w, s_{w+4}, s_{w+8}, s_{w+12}: t_w
+      lds[wave * 64 + lane] = (sa[0] + sa[CPW > 1 ? 1 : 0]) + (sa[CPW > 2 ? 2 : 0] + sa[CPW > 3 ? 3 : 0]);
+      lds[256 + wave * 64 + lane] = (sb[0] + sb[CPW > 1 ? 1 : 0]) + (sb[CPW > 2 ? 2 : 0] + sb[CPW > 3 ? 3 : 0]);
+      __syncthreads();
+      if (wave == 0 && out < nvec) {
+        oa[out] = (lds[lane] + lds[64 + lane]) + (lds[128 + lane] + lds[192 + lane]);
+        ob[out] = (lds[256 + lane] + lds[320 + lane]) + (lds[384 + lane] + lds[448 + lane]);
       }
+    } else {  // this wave holds s_w
+      lds[wave * 64 + lane] = sa[0];
+      lds[1024 + wave * 64 + lane] = sb[0];
+      __syncthreads();
+      if (wave < 2 && out < nvec) {
+        const double* q = lds + wave * 1024 + lane;
+        double tr[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        aa[u] += la[u];
-        ab[u] += lb[u];
+        for (int r = 0; r < 4; ++r) tr[r] = (q[r * 64] + q[(r + 4) * 64]) + (q[(r + 8) * 64] + q[(r + 12) * 64]);
+        (wave == 0 ? oa : ob)[out] = (tr[0] + tr[1]) + (tr[2] + tr[3]);
       }
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const double va = wave_sum(aa[u]);
-      const double vb = wave_sum(ab[u]);
-      if (lane == 0 && i0 + u < nvec) {
-        oa[i0 + u] = va;
-        ob[i0 + u] = vb;
-      }
-    }
+    __syncthreads();
   }
 }
 
@@ -101,7 +129,7 @@ __device__ void reduce_partials2(const double* __restrict__ pa, const double* __
 // of kDotUnroll basis vectors whose loads are all issued before the shuffle
 // reductions; lanes run over rows.
 __device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x0, int rows, const double* wv,
-                            const double* uv, int nvec, double* partw, double* partu, int nch, int chunk) {
+                            const double* uv, int nvec, double* partw, double* partu, int ld, int chunk) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i0 = wave * kDotUnroll; i0 < nvec; i0 += kWaves * kDotUnroll) {
     double aw[kDotUnroll], au[kDotUnroll];
@@ -125,8 +153,8 @@ __device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x
       const double sw = wave_sum(aw[u]);
       const double su = wave_sum(au[u]);
       if (lane == 0 && i0 + u < nvec) {
-        partw[(int64_t)(i0 + u) * nch + chunk] = sw;
-        partu[(int64_t)(i0 + u) * nch + chunk] = su;
+        partw[(int64_t)chunk * ld + i0 + u] = sw;
+        partu[(int64_t)chunk * ld + i0 + u] = su;
       }
     }
   }
@@ -228,8 +256,8 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
         cs2[i] = S.h2[(int64_t)col * S.ldv + i];
       }
     } else {
-      reduce_partials2(S.part1 + (int64_t)col * S.ldv * S.nch, S.part2 + (int64_t)col * S.ldv * S.nch, m + 1,
-                       S.nch, ds, cs2);
+      reduce_partials2<kWaves>(S.part1 + (int64_t)col * S.ldv * S.nch, S.part2 + (int64_t)col * S.ldv * S.nch,
+                               m + 1, S.nch, S.ldv, ds, cs2, wsp);
     }
     __syncthreads();
     if (tid < 64) {
@@ -653,23 +681,22 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
   }
   __syncthreads();
   chunk_dots2(Vc, S.vvs, x0, rows, wv, uv, j + 1, S.part1 + (int64_t)col * S.ldv * S.nch,
-              S.part2 + (int64_t)col * S.ldv * S.nch, S.nch, chunk);
+              S.part2 + (int64_t)col * S.ldv * S.nch, S.ldv, chunk);
 }
 
-// Pre-reduction after gm_dots (one block per column): the dots with w into dw and
-// with u_j into h2, summed exactly as gm_update sums them itself.
-__global__ __launch_bounds__(256) void k_gm_reduce(GmState S, int par) {
-  __shared__ double ha[kMaxIt + 1], hb[kMaxIt + 1];
+// Pre-reduction after gm_dots (up to four 1024-thread blocks per column, splitting
+// the vectors in groups of 64): the dots with w into dw and with u_j into h2, summed
+// exactly as gm_update sums them itself.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_gm_reduce(GmState S, int par) {
+  __shared__ double lds[2 * 16 * 64];
   const int col = blockIdx.y;
   const int j = S.jdev[par];
   if (!S.active[col] || j > S.maxit) return;
-  reduce_partials2(S.part1 + (int64_t)col * S.ldv * S.nch, S.part2 + (int64_t)col * S.ldv * S.nch, j + 1, S.nch,
-                   ha, hb);
-  __syncthreads();
-  for (int i = threadIdx.x; i <= j; i += kThreads) {
-    S.dw[(int64_t)col * S.ldv + i] = ha[i];
-    S.h2[(int64_t)col * S.ldv + i] = hb[i];
-  }
+  reduce_partials2<kReduceThreads / 64>(S.part1 + (int64_t)col * S.ldv * S.nch,
+                                        S.part2 + (int64_t)col * S.ldv * S.nch, j + 1, S.nch, S.ldv,
+                                        S.dw + (int64_t)col * S.ldv, S.h2 + (int64_t)col * S.ldv, lds, blockIdx.x,
+                                        gridDim.x);
 }
 
 // Start of a solve: u_0 = w (the initial residual) into V_0; all columns active;
@@ -786,7 +813,9 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
   }
   hipLaunchKernelGGL(k_gm_dots, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
                      tr ? 1 : 0);
-  if (S.prereduce) hipLaunchKernelGGL(k_gm_reduce, dim3(1, nrhs), dim3(kThreads), 0, s, S, par);
+  if (S.prereduce)
+    hipLaunchKernelGGL(k_gm_reduce, dim3((S.maxit + 64) / 64 < 4 ? (S.maxit + 64) / 64 : 4, nrhs), dim3(kReduceThreads), 0, s, S,
+                       par);
 }
 
 void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s) {
