@@ -135,6 +135,7 @@ __device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x
     double aw[kDotUnroll], au[kDotUnroll];
 #pragma unroll
     for (int u = 0; u < kDotUnroll; ++u) aw[u] = au[u] = 0.0;
+#pragma unroll 2
     for (int x = lane; x < rows; x += 64) {
       const double wx = wv[x], ux = uv[x];
       // vectors past nvec repeat the last one (in bounds, results never stored), so
@@ -165,6 +166,7 @@ __device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x
 // unrotated in Hu), rotated by the previous rotations; a new rotation zeroes beta.
 // lds: the caller's LDS, kGivensLds doubles.
 constexpr int kGivensLds = 3 * (kMaxIt + 2);
+template <int B>
 __device__ void givens_column(const GmState& S, int col, int j, double beta, const double* h2, double* lds) {
   double* hc = lds;
   double* csl = lds + (kMaxIt + 2);
@@ -187,12 +189,27 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
   __syncthreads();
   if (tid == 0) {
     hc[jc + 1] = beta;
-    for (int i = 0; i < jc; ++i) {
-      const double a = hc[i], b = hc[i + 1];
-      hc[i] = csl[i] * a + snl[i] * b;
-      hc[i + 1] = -snl[i] * a + csl[i] * b;
+    // the entry carried from rotation i to i + 1 stays in a register; the operands
+    // of B rotations are loaded before they are applied (rotation i reads hc[i + 1],
+    // which only rotation i + 1 writes).  The same operations whatever B.
+    double a = hc[0];
+    for (int i0 = 0; i0 < jc; i0 += B) {
+      double bb[B], ci[B], si[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int i = min(i0 + u, jc - 1);
+        bb[u] = hc[i + 1];
+        ci[u] = csl[i];
+        si[u] = snl[i];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (i0 + u < jc) {
+          hc[i0 + u] = ci[u] * a + si[u] * bb[u];
+          a = -si[u] * a + ci[u] * bb[u];
+        }
     }
-    const double a = hc[jc], b = hc[jc + 1];
+    const double b = beta;
     const double rr = hypot(a, b);
     const double c = rr > 0.0 ? a / rr : 1.0;
     const double s = rr > 0.0 ? b / rr : 0.0;
@@ -289,7 +306,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
           }
         }
       } else {
-        givens_column(S, col, m, rho, cs2, wsp);
+        givens_column<4>(S, col, m, rho, cs2, wsp);
       }
       // h'_m = ([d; e] - H c) / rho with the unrotated columns 0..m-1 (after the
       // Givens step has read h'_{m-1}): lanes take rows l, the waves split the
@@ -302,9 +319,16 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
         const int l = l0 + lane;
         double hc = 0.0;
         if (l <= m) {
-#pragma unroll 8
-          for (int i = max(l - 1, 0) + ((wave - max(l - 1, 0)) & 3); i < m; i += kWaves)
-            hc = fma(Hu[(int64_t)i * S.ldv + l], cs2[i], hc);
+          // this wave's columns i = ib, ib + 4, ...: clamped loads issued eight at a time
+          const int ib = max(l - 1, 0) + ((wave - max(l - 1, 0)) & 3);
+          for (int i0 = ib; i0 < m; i0 += 8 * kWaves) {
+            double hv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) hv[u] = Hu[(int64_t)min(i0 + u * kWaves, m - 1) * S.ldv + l];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (i0 + u * kWaves < m) hc = fma(hv[u], cs2[i0 + u * kWaves], hc);
+          }
         }
         hsum[wave][lane] = hc;
         __syncthreads();
@@ -324,11 +348,39 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   auto update = [&](int64_t x) {
     if (m < 0) return vn[x];
     double sc = vm[x], sw = wc[x];
-#pragma unroll 16
-    for (int i = 0; i < m; ++i) {
-      const double v = Vc[(int64_t)i * S.vvs + x];
-      sc = fma(-cs2[i], v, sc);
-      sw = fma(-ds[i], v, sw);
+    // batches of 32: every load of a batch is issued before its products, which run in
+    // order (same bits as a plain loop); the last, partial batch clamps and masks
+    for (int i0 = 0; i0 < m; i0 += 32) {
+      double v_[32];
+      if (i0 + 32 <= m) {
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          const int i = i0 + u;
+          v_[u] = Vc[(int64_t)i * S.vvs + x];
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          const int i = i0 + u;
+          const double v = v_[u];
+          sc = fma(-cs2[i], v, sc);
+          sw = fma(-ds[i], v, sw);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          const int i = min(i0 + u, m - 1);
+          v_[u] = Vc[(int64_t)i * S.vvs + x];
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          const int i = i0 + u;
+          if (i < m) {
+            const double v = v_[u];
+            sc = fma(-cs2[i], v, sc);
+            sw = fma(-ds[i], v, sw);
+          }
+        }
+      }
     }
     const double q = sc * inv;
     const double un = fma(-e, q, sw) * inv;
@@ -345,14 +397,48 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
       return;
     }
     double sc0 = vm[x0], sw0 = wc[x0], sc1 = vm[x1], sw1 = wc[x1];
-#pragma unroll 8
-    for (int i = 0; i < m; ++i) {
-      const double v0 = Vc[(int64_t)i * S.vvs + x0];
-      const double v1 = Vc[(int64_t)i * S.vvs + x1];
-      sc0 = fma(-cs2[i], v0, sc0);
-      sw0 = fma(-ds[i], v0, sw0);
-      sc1 = fma(-cs2[i], v1, sc1);
-      sw1 = fma(-ds[i], v1, sw1);
+    // batches of 8: every load of a batch is issued before its products, which run in
+    // order (same bits as a plain loop); the last, partial batch clamps and masks
+    for (int i0 = 0; i0 < m; i0 += 8) {
+      double v0_[8];
+      double v1_[8];
+      if (i0 + 8 <= m) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          v0_[u] = Vc[(int64_t)i * S.vvs + x0];
+          v1_[u] = Vc[(int64_t)i * S.vvs + x1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          const double v0 = v0_[u];
+          const double v1 = v1_[u];
+          sc0 = fma(-cs2[i], v0, sc0);
+          sw0 = fma(-ds[i], v0, sw0);
+          sc1 = fma(-cs2[i], v1, sc1);
+          sw1 = fma(-ds[i], v1, sw1);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = min(i0 + u, m - 1);
+          v0_[u] = Vc[(int64_t)i * S.vvs + x0];
+          v1_[u] = Vc[(int64_t)i * S.vvs + x1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          if (i < m) {
+            const double v0 = v0_[u];
+            const double v1 = v1_[u];
+            sc0 = fma(-cs2[i], v0, sc0);
+            sw0 = fma(-ds[i], v0, sw0);
+            sc1 = fma(-cs2[i], v1, sc1);
+            sw1 = fma(-ds[i], v1, sw1);
+          }
+        }
+      }
     }
     const double q0 = sc0 * inv, q1 = sc1 * inv;
     r0 = fma(-e, q0, sw0) * inv;
@@ -413,13 +499,19 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
 template <typename OpT, int NC>
 __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int par, int use_precond, int transpose) {
   using Acc = typename AccOf<OpT>::type;
-  __shared__ Acc xs[NC][8 * kMaxN];
-  __shared__ Acc bpart[NC * 256];
-  __shared__ double scal[NC][2];  // rho, e
   constexpr int kStage = 128;
-  __shared__ double cst[NC][2][kStage];  // c and d of the columns (m <= kStage)
+  // block 0's Givens steps use the front of `area`; after them (behind barriers) it
+  // holds the columns' coefficients cst (c and d, m <= kStage) and the staged
+  // block-Jacobi inputs xs with their partial sums bpart
+  constexpr int kXs = NC * 8 * kMaxN;
+  constexpr int kStaged = (2 * kXs * (int)sizeof(Acc) + 7) / 8 + NC * 2 * kStage;
+  __shared__ double area[kStaged > kGivensLds ? kStaged : kGivensLds];
+  double* gwork = area;
+  Acc (*xs)[8 * kMaxN] = reinterpret_cast<Acc (*)[8 * kMaxN]>(area);
+  Acc* bpart = reinterpret_cast<Acc*>(area) + kXs;
+  double (*cst)[2][kStage] = reinterpret_cast<double (*)[2][kStage]>(area + (2 * kXs * (int)sizeof(Acc) + 7) / 8);
+  __shared__ double scal[NC][2];  // rho, e
   __shared__ double hsum[kWaves][64];
-  __shared__ double gwork[kGivensLds];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t k = P.k;
   const int nrhs = (int)(S.vvs / k);
@@ -474,7 +566,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
             }
           }
         } else {
-          givens_column(S, col, m, rho, cu, gwork);
+          givens_column<1>(S, col, m, rho, cu, gwork);
         }
         __syncthreads();
         const double* Hu = S.Hu + (int64_t)col * S.ldv * S.maxit;
@@ -483,9 +575,16 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
           const int l = l0 + lane;
           double hc = 0.0;
           if (l <= m) {
-#pragma unroll 8
-            for (int i = max(l - 1, 0) + ((wave - max(l - 1, 0)) & 3); i < m; i += kWaves)
-              hc = fma(Hu[(int64_t)i * S.ldv + l], cu[i], hc);
+            // this wave's columns i = ib, ib + 4, ...: clamped loads issued eight at a time
+            const int ib = max(l - 1, 0) + ((wave - max(l - 1, 0)) & 3);
+            for (int i0 = ib; i0 < m; i0 += 8 * kWaves) {
+              double hv[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) hv[u] = Hu[(int64_t)min(i0 + u * kWaves, m - 1) * S.ldv + l];
+#pragma unroll
+              for (int u = 0; u < 8; ++u)
+                if (i0 + u * kWaves < m) hc = fma(hv[u], cu[i0 + u * kWaves], hc);
+            }
           }
           hsum[wave][lane] = hc;
           __syncthreads();
@@ -521,20 +620,44 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
     double sc = vm[x], sw = S.w[(int64_t)col * k + x];
     if (staged) {
-#pragma unroll 16
-      for (int i = 0; i < m; ++i) {
-        const double v = Vc[(int64_t)i * S.vvs + x];
-        sc = fma(-cst[c][0][i], v, sc);
-        sw = fma(-cst[c][1][i], v, sw);
+      // clamped loads issued together, then the products in order (same bits as a plain loop)
+      for (int i0 = 0; i0 < m; i0 += 16) {
+        double v_[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int i = min(i0 + u, m - 1);
+          v_[u] = Vc[(int64_t)i * S.vvs + x];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int i = i0 + u;
+          if (i < m) {
+            const double v = v_[u];
+            sc = fma(-cst[c][0][i], v, sc);
+            sw = fma(-cst[c][1][i], v, sw);
+          }
+        }
       }
     } else {
       const double* cu = S.h2 + (int64_t)col * S.ldv;
       const double* dw = S.dw + (int64_t)col * S.ldv;
-#pragma unroll 16
-      for (int i = 0; i < m; ++i) {
-        const double v = Vc[(int64_t)i * S.vvs + x];
-        sc = fma(-cu[i], v, sc);
-        sw = fma(-dw[i], v, sw);
+      // clamped loads issued together, then the products in order (same bits as a plain loop)
+      for (int i0 = 0; i0 < m; i0 += 16) {
+        double v_[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int i = min(i0 + u, m - 1);
+          v_[u] = Vc[(int64_t)i * S.vvs + x];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int i = i0 + u;
+          if (i < m) {
+            const double v = v_[u];
+            sc = fma(-cu[i], v, sc);
+            sw = fma(-dw[i], v, sw);
+          }
+        }
       }
     }
     const double q = sc * inv;
@@ -553,28 +676,56 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     double sca = vma[xa], swa = S.w[(int64_t)(c0 + ca) * k + xa];
     double scb = vmb[xb], swb = S.w[(int64_t)(c0 + cb) * k + xb];
     if (staged) {
-#pragma unroll 8
-      for (int i = 0; i < m; ++i) {
-        const double va = Va[(int64_t)i * S.vvs + xa];
-        const double vb = Vb[(int64_t)i * S.vvs + xb];
-        sca = fma(-cst[ca][0][i], va, sca);
-        swa = fma(-cst[ca][1][i], va, swa);
-        scb = fma(-cst[cb][0][i], vb, scb);
-        swb = fma(-cst[cb][1][i], vb, swb);
+      // clamped loads issued together, then the products in order (same bits as a plain loop)
+      for (int i0 = 0; i0 < m; i0 += 8) {
+        double va_[8];
+        double vb_[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = min(i0 + u, m - 1);
+          va_[u] = Va[(int64_t)i * S.vvs + xa];
+          vb_[u] = Vb[(int64_t)i * S.vvs + xb];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          if (i < m) {
+            const double va = va_[u];
+            const double vb = vb_[u];
+            sca = fma(-cst[ca][0][i], va, sca);
+            swa = fma(-cst[ca][1][i], va, swa);
+            scb = fma(-cst[cb][0][i], vb, scb);
+            swb = fma(-cst[cb][1][i], vb, swb);
+          }
+        }
       }
     } else {
       const double* cua = S.h2 + (int64_t)(c0 + ca) * S.ldv;
       const double* dwa = S.dw + (int64_t)(c0 + ca) * S.ldv;
       const double* cub = S.h2 + (int64_t)(c0 + cb) * S.ldv;
       const double* dwb = S.dw + (int64_t)(c0 + cb) * S.ldv;
-#pragma unroll 8
-      for (int i = 0; i < m; ++i) {
-        const double va = Va[(int64_t)i * S.vvs + xa];
-        const double vb = Vb[(int64_t)i * S.vvs + xb];
-        sca = fma(-cua[i], va, sca);
-        swa = fma(-dwa[i], va, swa);
-        scb = fma(-cub[i], vb, scb);
-        swb = fma(-dwb[i], vb, swb);
+      // clamped loads issued together, then the products in order (same bits as a plain loop)
+      for (int i0 = 0; i0 < m; i0 += 8) {
+        double va_[8];
+        double vb_[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = min(i0 + u, m - 1);
+          va_[u] = Va[(int64_t)i * S.vvs + xa];
+          vb_[u] = Vb[(int64_t)i * S.vvs + xb];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          if (i < m) {
+            const double va = va_[u];
+            const double vb = vb_[u];
+            sca = fma(-cua[i], va, sca);
+            swa = fma(-dwa[i], va, swa);
+            scb = fma(-cub[i], vb, scb);
+            swb = fma(-dwb[i], vb, swb);
+          }
+        }
       }
     }
     const double inva = scal[ca][0] > 0.0 ? 1.0 / scal[ca][0] : 0.0;
@@ -748,8 +899,14 @@ __global__ __launch_bounds__(256) void k_gm_combine(DevPlan P, GmState S, double
   const double* Vc = S.V + (int64_t)col * k;
   for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < k; q += (int64_t)gridDim.x * kThreads) {
     double acc = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < J; ++i) acc = fma(yc[i], Vc[(int64_t)i * S.vvs + q], acc);
+    for (int i0 = 0; i0 < J; i0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = Vc[(int64_t)min(i0 + u, J - 1) * S.vvs + q];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < J) acc = fma(yc[i0 + u], v[u], acc);
+    }
     x[(int64_t)col * k + q] = acc;
   }
 }
