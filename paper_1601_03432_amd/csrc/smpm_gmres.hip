@@ -236,14 +236,36 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
 
 // ------------------------------------------------------------------ kernels
 
+// Block-Jacobi staging of the Arnoldi update: up to kGroupBlocks consecutive blocks of
+// one class (one size, adjacent slot lists), kStageSlots slots at most.
+constexpr int kGroupBlocks = 4, kStageSlots = 512;
+struct BlockGroup {
+  int o0, sb, bc, nb;  // first slot-list entry, block size, class, blocks
+};
+// The group starting at block b of a run ending before bend; the class entries of
+// the following blocks are loaded together.
+__device__ __forceinline__ BlockGroup block_group(const DevPlan& P, int b, int bend) {
+  BlockGroup g;
+  g.o0 = P.blk_off[b];
+  g.sb = P.blk_off[b + 1] - g.o0;
+  g.bc = P.blk_cls[b];
+  int cl[kGroupBlocks];
+#pragma unroll
+  for (int u = 1; u < kGroupBlocks; ++u) cl[u] = P.blk_cls[min(b + u, bend - 1)];
+  g.nb = 1;
+#pragma unroll
+  for (int u = 1; u < kGroupBlocks; ++u)
+    if (g.nb == u && b + u < bend && cl[u] == g.bc && (u + 1) * g.sb <= kStageSlots) g.nb = u + 1;
+  return g;
+}
+
 // Step j's first kernel (see the file header; m = j - 1).  Step 0: z = M^{-1} u_0.
 // givens_only: stop after the Givens step (the last step of a solve).
 template <typename OpT, bool PRE>
 __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par, int use_precond, int transpose,
                                                    int givens_only) {
   using Acc = typename AccOf<OpT>::type;
-  // block-Jacobi staging: up to kGroup blocks of one class, kStageSlots slots
-  constexpr int kGroup = 4, kStageSlots = 512;
+  constexpr int kGroup = kGroupBlocks;
   static_assert(kStageSlots >= 8 * kMaxN, "one block must fit the staging area");
   static_assert((kStageSlots + kGroup * 256) * sizeof(Acc) <= kGivensLds * sizeof(double), "LDS union");
   // block 0 uses wsp for the Givens step and then for the h' sums; the other blocks
@@ -345,12 +367,11 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   const double* wc = S.w + (int64_t)col * k;
   double* vm = S.V + (int64_t)max(m, 0) * S.vvs + (int64_t)col * k;
   double* vn = S.V + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
-  auto update = [&](int64_t x) {
-    if (m < 0) return vn[x];
-    double sc = vm[x], sw = wc[x];
+  // the products from basis vector i_begin on, then q_m and u_{m+1} at slot x
+  auto finish = [&](int64_t x, int i_begin, double sc, double sw) {
     // batches of 32: every load of a batch is issued before its products, which run in
     // order (same bits as a plain loop); the last, partial batch clamps and masks
-    for (int i0 = 0; i0 < m; i0 += 32) {
+    for (int i0 = i_begin; i0 < m; i0 += 32) {
       double v_[32];
       if (i0 + 32 <= m) {
 #pragma unroll
@@ -388,6 +409,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     vn[x] = un;
     return un;
   };
+  auto update = [&](int64_t x) { return m < 0 ? vn[x] : finish(x, 0, vm[x], wc[x]); };
   // the same at two slots, the loads of both in flight together (x1 is stored only
   // if st1; otherwise it must still be a valid slot)
   auto update2 = [&](int64_t x0, int64_t x1, bool st1, double& r0, double& r1) {
@@ -465,10 +487,8 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   const int per = (P.nblk + nwb - 1) / nwb;
   const int bend = min(P.nblk, (wb + 1) * per);
   for (int b = wb * per; b < bend;) {
-    const int o0 = P.blk_off[b], sb = P.blk_off[b + 1] - o0;
-    const int bc = P.blk_cls[b];
-    int nb = 1;  // blocks of one class have one size and adjacent slot lists
-    while (nb < kGroup && b + nb < bend && P.blk_cls[b + nb] == bc && (nb + 1) * sb <= kStageSlots) ++nb;
+    const BlockGroup g = block_group(P, b, bend);
+    const int o0 = g.o0, sb = g.sb, bc = g.bc, nb = g.nb;
     const int tot = nb * sb;
     __syncthreads();  // the previous group's apply has read xs (block 0: wsp is free)
     if (tot > kThreads) {
