@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--no-paper-study", action="store_true", help="skip the paper's iteration-count study")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline form (e.g. for kernel traces of the solve)")
+    ap.add_argument("--large-single-only", action="store_true",
+                    help="time only the large stretched grid's one-column FP64 solve (e.g. for kernel traces)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the metric kernel (no solves), e.g. for hardware-counter runs")
     args = ap.parse_args()
@@ -173,7 +175,8 @@ def main():
     f_host = wl.eval_fourier(params, x, y, w.Lx, w.Ly)
     f = torch.tensor(f_host, device="cuda").reshape(1, -1)
     w5 = wl.workload("c5")
-    ctx5 = None if (args.no_large or args.headline_only) and not args.roofline_only else c5_context(smpm, w5)
+    ctx5 = None if (args.no_large or args.headline_only) and not (args.roofline_only or args.large_single_only) \
+        else c5_context(smpm, w5)
     if args.roofline_only:
         print(json.dumps({"roofline": schur_roofline(ctx5)}), flush=True)
         return
@@ -196,6 +199,16 @@ def main():
         t1 = time.perf_counter()
         return (t1 - t0) / steps, info, u
 
+    if args.large_single_only:
+        x5, y5 = ctx5.node_coords()
+        F5, G5 = wl.c5_sources("c5", x5, y5, ctx5.boundary_arc(), w5.Lx, w5.Ly)
+        f5, g5 = torch.tensor(F5[:1], device="cuda"), torch.tensor(G5[:1], device="cuda")
+        ctx5.autotune(1)
+        sec, info, _ = timed(lambda r: ctx5.solve(r, g5, tol=1e-10, maxit=600), f5, args.steps, args.warmup)
+        print(json.dumps({"form": "fp64, large stretched grid, one column", "solves_per_s": 1.0 / sec,
+                          "ms_per_step": sec * 1e3, "iterations": info.iterations,
+                          "true_rel_residual": info.rel_residual}), flush=True)
+        return
     if args.headline_only:
         fn = solve_fp64 if args.precision == "fp64" else solve_mixed
         sec, info, _ = timed(fn, f, args.steps, args.warmup)
