@@ -36,11 +36,32 @@
 
 #include "smpm_gmres.h"
 
+#include <type_traits>
+
 namespace smpm {
 
 namespace {
 
 constexpr int kThreads = 256;
+
+// Basis entries are read once per pass.  Once the part of the basis a pass reads is
+// larger than the last-level cache can keep (kStreamBytes; the 256 MB Infinity Cache
+// also holds the other operands), caching it only evicts what is reused (block-Jacobi
+// inverses, coefficients, partial sums): those loads are then non-temporal.  The
+// choice is uniform over a launch.
+constexpr int64_t kStreamBytes = 192ll << 20;
+__device__ __forceinline__ bool stream_basis(int64_t nvec, int64_t vvs) { return nvec * vvs * 8 > kStreamBytes; }
+template <bool NT>
+__device__ __forceinline__ double ld_basis(const double* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+// kernels branch once on the choice and run a copy of their basis loops compiled for
+// it (the tag is std::true_type or std::false_type)
+template <typename Tag>
+constexpr bool kNT = Tag::value;
 constexpr int kWaves = kThreads / 64;
 constexpr int kDotUnroll = 8;
 
@@ -128,6 +149,7 @@ __device__ void reduce_partials2(const double* __restrict__ pa, const double* __
 // V_0..V_{nvec-1}: one pass over the basis for both vectors.  Wave q handles groups
 // of kDotUnroll basis vectors whose loads are all issued before the shuffle
 // reductions; lanes run over rows.
+template <bool NT>
 __device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x0, int rows, const double* wv,
                             const double* uv, int nvec, double* partw, double* partu, int ld, int chunk) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -142,7 +164,7 @@ __device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x
       // every load is issued before the first product
       double vv[kDotUnroll];
 #pragma unroll
-      for (int u = 0; u < kDotUnroll; ++u) vv[u] = V[(int64_t)min(i0 + u, nvec - 1) * vvs + x0 + x];
+      for (int u = 0; u < kDotUnroll; ++u) vv[u] = ld_basis<NT>(&V[(int64_t)min(i0 + u, nvec - 1) * vvs + x0 + x]);
 #pragma unroll
       for (int u = 0; u < kDotUnroll; ++u) {
         aw[u] = fma(vv[u], wx, aw[u]);
@@ -238,7 +260,10 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
 
 // Block-Jacobi staging of the Arnoldi update: up to kGroupBlocks consecutive blocks of
 // one class (one size, adjacent slot lists), kStageSlots slots at most.
-constexpr int kGroupBlocks = 4, kStageSlots = 512;
+constexpr int kGroupBlocks = 8, kStageSlots = 1024;
+// LDS of the single-column update: block 0's Givens step, or the other blocks'
+// staged slots and the apply's partial sums
+constexpr int kUpdLds = kStageSlots + kGroupBlocks * 256 > kGivensLds ? kStageSlots + kGroupBlocks * 256 : kGivensLds;
 struct BlockGroup {
   int o0, sb, bc, nb;  // first slot-list entry, block size, class, blocks
 };
@@ -267,11 +292,11 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   using Acc = typename AccOf<OpT>::type;
   constexpr int kGroup = kGroupBlocks;
   static_assert(kStageSlots >= 8 * kMaxN, "one block must fit the staging area");
-  static_assert((kStageSlots + kGroup * 256) * sizeof(Acc) <= kGivensLds * sizeof(double), "LDS union");
+  static_assert((kStageSlots + kGroup * 256) * sizeof(Acc) <= kUpdLds * sizeof(double), "LDS union");
   // block 0 uses wsp for the Givens step and then for the h' sums; the other blocks
   // (which never take the Givens step when the grid has more than one block) stage
   // their slots in it
-  __shared__ double wsp[kGivensLds];
+  __shared__ double wsp[kUpdLds];
   __shared__ double red[2 * kWaves];
   __shared__ double ds[kMaxIt + 1];  // d_0..d_{m-1}, then alpha
   __shared__ double cs2[kMaxIt + 1]; // c_0..c_{m-1}, then nu
@@ -281,6 +306,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
   const int j = S.jdev[par];
+  const bool nt = stream_basis(j > 1 ? j : 1, S.vvs);
   const int64_t k = P.k;
   double* zc = S.z + (int64_t)col * k;
   const double* Vc = S.V + (int64_t)col * k;
@@ -368,7 +394,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   double* vm = S.V + (int64_t)max(m, 0) * S.vvs + (int64_t)col * k;
   double* vn = S.V + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
   // the products from basis vector i_begin on, then q_m and u_{m+1} at slot x
-  auto finish = [&](int64_t x, int i_begin, double sc, double sw) {
+  auto finish = [&](auto nt_, int64_t x, int i_begin, double sc, double sw) {
     // batches of 32: every load of a batch is issued before its products, which run in
     // order (same bits as a plain loop); the last, partial batch clamps and masks
     for (int i0 = i_begin; i0 < m; i0 += 32) {
@@ -377,7 +403,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
           const int i = i0 + u;
-          v_[u] = Vc[(int64_t)i * S.vvs + x];
+          v_[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)i * S.vvs + x]);
         }
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
@@ -390,7 +416,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
           const int i = min(i0 + u, m - 1);
-          v_[u] = Vc[(int64_t)i * S.vvs + x];
+          v_[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)i * S.vvs + x]);
         }
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
@@ -409,10 +435,10 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     vn[x] = un;
     return un;
   };
-  auto update = [&](int64_t x) { return m < 0 ? vn[x] : finish(x, 0, vm[x], wc[x]); };
+  auto update = [&](auto nt_, int64_t x) { return m < 0 ? vn[x] : finish(nt_, x, 0, vm[x], wc[x]); };
   // the same at two slots, the loads of both in flight together (x1 is stored only
   // if st1; otherwise it must still be a valid slot)
-  auto update2 = [&](int64_t x0, int64_t x1, bool st1, double& r0, double& r1) {
+  auto update2 = [&](auto nt_, int64_t x0, int64_t x1, bool st1, double& r0, double& r1) {
     if (m < 0) {
       r0 = vn[x0];
       r1 = vn[x1];
@@ -428,8 +454,8 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int i = i0 + u;
-          v0_[u] = Vc[(int64_t)i * S.vvs + x0];
-          v1_[u] = Vc[(int64_t)i * S.vvs + x1];
+          v0_[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)i * S.vvs + x0]);
+          v1_[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)i * S.vvs + x1]);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -445,8 +471,8 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int i = min(i0 + u, m - 1);
-          v0_[u] = Vc[(int64_t)i * S.vvs + x0];
-          v1_[u] = Vc[(int64_t)i * S.vvs + x1];
+          v0_[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)i * S.vvs + x0]);
+          v1_[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)i * S.vvs + x1]);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -474,43 +500,55 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   };
   // block 0 takes the Givens step alone; blocks 1.. share the slots
   if (blockIdx.x == 0 && gridDim.x > 1) return;
-  int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
-  const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
-  if (!use_precond) {
-    for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads) zc[x] = update(x);
-    return;
-  }
-  // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD
-  // adjacent; consecutive blocks of one class are staged together and share every
-  // read of their inverse (the apply gives each block the same bits as alone)
-  if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
-  const int per = (P.nblk + nwb - 1) / nwb;
-  const int bend = min(P.nblk, (wb + 1) * per);
-  for (int b = wb * per; b < bend;) {
-    const BlockGroup g = block_group(P, b, bend);
-    const int o0 = g.o0, sb = g.sb, bc = g.bc, nb = g.nb;
-    const int tot = nb * sb;
-    __syncthreads();  // the previous group's apply has read xs (block 0: wsp is free)
-    if (tot > kThreads) {
-      const int i1 = tid + kThreads;
-      const bool in1 = i1 < tot;
-      double r0, r1;
-      update2(P.blk_slots[o0 + tid], P.blk_slots[o0 + (in1 ? i1 : tot - 1)], in1, r0, r1);
-      xs[tid] = (Acc)r0;
-      if (in1) xs[i1] = (Acc)r1;
-    } else if (tid < tot) {
-      xs[tid] = (Acc)update(P.blk_slots[o0 + tid]);
+  // the rest once per launch, with the basis loads compiled for the streaming choice
+  auto tail = [&](auto nt_) {
+    int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
+    const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
+    if (!use_precond) {
+      for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads) zc[x] = update(nt_, x);
+      return;
     }
-    __syncthreads();
-    const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
-    if (nb == 1)
-      block_jacobi_apply<1>(Mp, xs, sb, sb, bpart, [&](int, int r, Acc val) { zc[P.blk_slots[o0 + r]] = (double)val; });
-    else
-      block_jacobi_apply<kGroup>(Mp, xs, sb, sb, bpart, [&](int v, int r, Acc val) {
+    // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD
+    // adjacent; consecutive blocks of one class are staged together and share every
+    // read of their inverse (the apply gives each block the same bits as alone)
+    if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
+    const int per = (P.nblk + nwb - 1) / nwb;
+    const int bend = min(P.nblk, (wb + 1) * per);
+    for (int b = wb * per; b < bend;) {
+      const BlockGroup g = block_group(P, b, bend);
+      const int o0 = g.o0, sb = g.sb, bc = g.bc, nb = g.nb;
+      const int tot = nb * sb;
+      __syncthreads();  // the previous group's apply has read xs (block 0: wsp is free)
+      // two slots per thread while there are two, then one
+      for (int i0 = tid; i0 < tot; i0 += 2 * kThreads) {
+        const int i1 = i0 + kThreads;
+        if (i1 < tot) {
+          double r0, r1;
+          update2(nt_, P.blk_slots[o0 + i0], P.blk_slots[o0 + i1], true, r0, r1);
+          xs[i0] = (Acc)r0;
+          xs[i1] = (Acc)r1;
+        } else {
+          xs[i0] = (Acc)update(nt_, P.blk_slots[o0 + i0]);
+        }
+      }
+      __syncthreads();
+      const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
+      auto put = [&](int v, int r, Acc val) {
         if (v < nb) zc[P.blk_slots[o0 + v * sb + r]] = (double)val;
-      });
-    b += nb;
-  }
+      };
+      if (nb == 1)
+        block_jacobi_apply<1>(Mp, xs, sb, sb, bpart, put);
+      else if (nb <= 4)
+        block_jacobi_apply<4>(Mp, xs, sb, sb, bpart, put);
+      else
+        block_jacobi_apply<kGroup>(Mp, xs, sb, sb, bpart, put);
+      b += nb;
+    }
+  };
+  if (nt)
+    tail(std::true_type{});
+  else
+    tail(std::false_type{});
 }
 
 // Step j's first kernel for NC columns at once, with pre-reduced dot sums (large
@@ -545,6 +583,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
   }
   if (!any) return;
   const int j = S.jdev[par];
+  const bool nt = stream_basis(j > 1 ? j : 1, S.vvs);
   const int m = j - 1;
   if (m > S.maxit) return;
   if (j > 0) {
@@ -630,7 +669,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     }
     __syncthreads();
   }
-  auto update = [&](int c, int64_t x) {
+  auto update = [&](auto nt_, int c, int64_t x) {
     const int col = c0 + c;
     const double* Vc = S.V + (int64_t)col * k;
     double* vn = S.V + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
@@ -646,7 +685,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int i = min(i0 + u, m - 1);
-          v_[u] = Vc[(int64_t)i * S.vvs + x];
+          v_[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)i * S.vvs + x]);
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -667,7 +706,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int i = min(i0 + u, m - 1);
-          v_[u] = Vc[(int64_t)i * S.vvs + x];
+          v_[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)i * S.vvs + x]);
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -688,7 +727,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
   };
   // the same for column ca at slot xa and column cb at slot xb, the loads of both in
   // flight together (both columns active, m >= 0)
-  auto update2 = [&](int ca, int64_t xa, int cb, int64_t xb, double& ra, double& rb) {
+  auto update2 = [&](auto nt_, int ca, int64_t xa, int cb, int64_t xb, double& ra, double& rb) {
     const double* Va = S.V + (int64_t)(c0 + ca) * k;
     const double* Vb = S.V + (int64_t)(c0 + cb) * k;
     double* vma = S.V + (int64_t)m * S.vvs + (int64_t)(c0 + ca) * k;
@@ -703,8 +742,8 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int i = min(i0 + u, m - 1);
-          va_[u] = Va[(int64_t)i * S.vvs + xa];
-          vb_[u] = Vb[(int64_t)i * S.vvs + xb];
+          va_[u] = ld_basis<kNT<decltype(nt_)>>(&Va[(int64_t)i * S.vvs + xa]);
+          vb_[u] = ld_basis<kNT<decltype(nt_)>>(&Vb[(int64_t)i * S.vvs + xb]);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -731,8 +770,8 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int i = min(i0 + u, m - 1);
-          va_[u] = Va[(int64_t)i * S.vvs + xa];
-          vb_[u] = Vb[(int64_t)i * S.vvs + xb];
+          va_[u] = ld_basis<kNT<decltype(nt_)>>(&Va[(int64_t)i * S.vvs + xa]);
+          vb_[u] = ld_basis<kNT<decltype(nt_)>>(&Vb[(int64_t)i * S.vvs + xb]);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -760,46 +799,53 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
   };
   // block 0 takes the Givens steps alone; blocks 1.. share the slots
   if (blockIdx.x == 0 && gridDim.x > 1) return;
-  int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
-  const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
-  if (!use_precond) {
-    for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads)
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (on[c]) S.z[(int64_t)(c0 + c) * k + x] = update(c, x);
-    return;
-  }
-  // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD adjacent
-  if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
-  const int per = (P.nblk + nwb - 1) / nwb;
-  for (int b = wb * per; b < min(P.nblk, (wb + 1) * per); ++b) {
-    const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
-    const int bc = P.blk_cls[b];
-    __syncthreads();
-    // the NC * sb (column, slot) items, two per thread
-    const int tot = NC * sb;
-    for (int u = tid; u < tot; u += 2 * kThreads) {
-      const int ca = u / sb, ia = u - ca * sb;
-      const int u1 = u + kThreads;
-      const bool in1 = u1 < tot;
-      const int cb = in1 ? u1 / sb : ca, ib = in1 ? u1 - cb * sb : ia;
-      const bool pa = on[ca], pb = in1 && on[cb];
-      if (pa && pb && m >= 0) {
-        double ra, rb;
-        update2(ca, P.blk_slots[o + ia], cb, P.blk_slots[o + ib], ra, rb);
-        xs[ca][ia] = (Acc)ra;
-        xs[cb][ib] = (Acc)rb;
-      } else {
-        xs[ca][ia] = pa ? (Acc)update(ca, P.blk_slots[o + ia]) : Acc(0);
-        if (in1) xs[cb][ib] = pb ? (Acc)update(cb, P.blk_slots[o + ib]) : Acc(0);
-      }
+  // the rest once per launch, with the basis loads compiled for the streaming choice
+  auto tail = [&](auto nt_) {
+    int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
+    const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
+    if (!use_precond) {
+      for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads)
+  #pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (on[c]) S.z[(int64_t)(c0 + c) * k + x] = update(nt_, c, x);
+      return;
     }
-    __syncthreads();
-    const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
-    block_jacobi_apply<NC>(Mp, &xs[0][0], 8 * kMaxN, sb, bpart, [&](int c, int r, Acc v) {
-      if (on[c]) S.z[(int64_t)(c0 + c) * k + P.blk_slots[o + r]] = (double)v;
-    });
-  }
+    // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD adjacent
+    if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
+    const int per = (P.nblk + nwb - 1) / nwb;
+    for (int b = wb * per; b < min(P.nblk, (wb + 1) * per); ++b) {
+      const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
+      const int bc = P.blk_cls[b];
+      __syncthreads();
+      // the NC * sb (column, slot) items, two per thread
+      const int tot = NC * sb;
+      for (int u = tid; u < tot; u += 2 * kThreads) {
+        const int ca = u / sb, ia = u - ca * sb;
+        const int u1 = u + kThreads;
+        const bool in1 = u1 < tot;
+        const int cb = in1 ? u1 / sb : ca, ib = in1 ? u1 - cb * sb : ia;
+        const bool pa = on[ca], pb = in1 && on[cb];
+        if (pa && pb && m >= 0) {
+          double ra, rb;
+          update2(nt_, ca, P.blk_slots[o + ia], cb, P.blk_slots[o + ib], ra, rb);
+          xs[ca][ia] = (Acc)ra;
+          xs[cb][ib] = (Acc)rb;
+        } else {
+          xs[ca][ia] = pa ? (Acc)update(nt_, ca, P.blk_slots[o + ia]) : Acc(0);
+          if (in1) xs[cb][ib] = pb ? (Acc)update(nt_, cb, P.blk_slots[o + ib]) : Acc(0);
+        }
+      }
+      __syncthreads();
+      const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
+      block_jacobi_apply<NC>(Mp, &xs[0][0], 8 * kMaxN, sb, bpart, [&](int c, int r, Acc v) {
+        if (on[c]) S.z[(int64_t)(c0 + c) * k + P.blk_slots[o + r]] = (double)v;
+      });
+    }
+  };
+  if (nt)
+    tail(std::true_type{});
+  else
+    tail(std::false_type{});
 }
 
 // Step j's last kernel: w = t - (Z c2 + {S Z c2 | S^T Z c2}) on this block's rows (or
@@ -851,8 +897,12 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
     uv[q] = uj[slot];
   }
   __syncthreads();
-  chunk_dots2(Vc, S.vvs, x0, rows, wv, uv, j + 1, S.part1 + (int64_t)col * S.ldv * S.nch,
-              S.part2 + (int64_t)col * S.ldv * S.nch, S.ldv, chunk);
+  double* p1 = S.part1 + (int64_t)col * S.ldv * S.nch;
+  double* p2 = S.part2 + (int64_t)col * S.ldv * S.nch;
+  if (stream_basis(j + 1, S.vvs))
+    chunk_dots2<true>(Vc, S.vvs, x0, rows, wv, uv, j + 1, p1, p2, S.ldv, chunk);
+  else
+    chunk_dots2<false>(Vc, S.vvs, x0, rows, wv, uv, j + 1, p1, p2, S.ldv, chunk);
 }
 
 // Pre-reduction after gm_dots (up to four 1024-thread blocks per column, splitting
