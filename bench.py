@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # plain kernel of known size (FETCH_SIZE reads half of a 64 MiB elementwise read,
 # so x2.0; WRITE_SIZE matches a 64 MiB fill, x1.0).  Valid only for the kernel
 # source it was measured on (sha256 of the Schur section below); otherwise null.
-SCHUR_TRAFFIC = {"fetch_kib": 39084.8, "write_kib": 65024.0,
-                 "kernels_sha256": "86adfef4933869c2b79bd4bf97e5dad6c0d6a1ff147b993a57738523742e4224"}
+SCHUR_TRAFFIC = {"fetch_kib": 38203.7, "write_kib": 65024.0,
+                 "kernels_sha256": "32e089a2710ebfc6c13617adc8b743ee4dac2ad6adc3438b17be1b5caf30630d"}
 
 
 def kernels_sha256():
@@ -121,7 +121,8 @@ def c5_context(smpm, w5):
 def schur_roofline(ctx5, ncol=8):
     """The metric kernel: the FP64 Schur apply t = S y on the large stretched grid
     (128 x 128 elements, n = 16) for its 8 right-hand sides, launched as
-    k_schur_mfma<false,16,4,double>.  Algorithmic bytes per launch: each column's y
+    k_schur_mfma<false,16,4,double,true> (the standalone apply, output written with
+    non-temporal stores).  Algorithmic bytes per launch: each column's y
     read and t written once (2 k 8 B per column) plus every distinct element operator
     once."""
     us, nbuf = rotated_schur_us(ctx5, ncol)
@@ -130,7 +131,7 @@ def schur_roofline(ctx5, ncol=8):
     traffic = None
     if SCHUR_TRAFFIC and SCHUR_TRAFFIC.get("kernels_sha256") == kernels_sha256():
         traffic = 1024 * (2.0 * SCHUR_TRAFFIC["fetch_kib"] + 1.0 * SCHUR_TRAFFIC["write_kib"])
-    return {"kernel": "k_schur_mfma<false,16,4,double> (Schur apply, 128x128 n=16 stretched grid, %d columns, %d rotated buffer "
+    return {"kernel": "k_schur_mfma<false,16,4,double,true> (Schur apply, 128x128 n=16 stretched grid, %d columns, %d rotated buffer "
                               "pairs)" % (ncol, nbuf),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -1023,7 +1023,9 @@ int smpm_schur_apply(smpm_ctx* c, const double* v, double* Sv, int nrhs, int tra
   if (!v || !Sv || nrhs < 1) return fail(SMPM_EINVAL, "bad vector arguments");
   const size_t bytes = sizeof(double) * c->plan.k * nrhs;
   if (aliases(v, bytes, Sv, bytes)) return fail(SMPM_EINVAL, "input and output alias");
-  launch_schur(c->dp, v, Sv, nrhs, transpose != 0, nullptr, static_cast<hipStream_t>(stream));
+  // the result goes back to the caller: written past the caches
+  launch_schur_ex(c->dp, v, Sv, nrhs, transpose != 0, nullptr, nullptr, static_cast<hipStream_t>(stream), PREC_F64,
+                  true);
   HIPCHK(hipGetLastError());
   return SMPM_OK;
 }

@@ -202,9 +202,12 @@ __device__ __forceinline__ const bf16s* minv_op<bf16s>(const DevPlan& P, bool tr
 void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
                   const int* active, hipStream_t s);
 // as launch_schur; if side_sums != nullptr (forward, n <= 16 only) it also writes the
-// sum of t over every inter-element side (nsides per column)
+// sum of t over every inter-element side (nsides per column).  stream_out: t is not
+// read again soon (it goes back to the caller), so the FP64 matrix-core kernel writes
+// it with non-temporal stores.
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
-                     const int* active, double* side_sums, hipStream_t s, int prec = PREC_F64);
+                     const int* active, double* side_sums, hipStream_t s, int prec = PREC_F64,
+                     bool stream_out = false);
 bool schur_has_side_sums(const DevPlan& P);
 int schur_nc_class(int nrhs);  // index into DevPlan::schur_nc
 // persistent, pipelined Schur apply (no side sums); false if the plain launch is used

@@ -226,7 +226,7 @@ constexpr int kTileLd = kTile + 1;  // LDS row stride of the staged Y tile
 // loads are issued before the first wait.  The 16x16 results go back through LDS
 // so that 16 lanes write 16 consecutive rows (one receiving side, or the element's
 // own slots) with one coalesced store.
-template <bool ADJ, int KT, int NC, typename OpT>
+template <bool ADJ, int KT, int NC, typename OpT, bool NTS = false>
 __global__ __launch_bounds__(256) void k_schur_mfma(DevPlan P, const double* __restrict__ y,
                                                     double* __restrict__ t, int nrhs,
                                                     const int* __restrict__ active,
@@ -344,7 +344,12 @@ __global__ __launch_bounds__(256) void k_schur_mfma(DevPlan P, const double* __r
     for (int v = 0; v < 4; ++v) {
       const int uu = (lane >> 4) + 4 * v;
       const double tv = yv[c][v] + (double)ys[((c * kWaves + wave) * kTile + uu) * kTileLd + row];
-      if (slot[v] >= 0) tc[slot[v]] = tv;
+      if (slot[v] >= 0) {
+        if constexpr (NTS)  // an output that goes back to the caller: streamed past the caches
+          __builtin_nontemporal_store(tv, &tc[slot[v]]);
+        else
+          tc[slot[v]] = tv;
+      }
       if (!ADJ && side_sums) {
         // sums over the rows of each receiving side: 16-lane butterflies, fixed order
         double* pp = part + (c * kTile + uu) * 4 * kWaves;
@@ -1165,7 +1170,7 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
 }
 
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
-                     double* side_sums, hipStream_t s, int prec) {
+                     double* side_sums, hipStream_t s, int prec, bool stream_out) {
   if (transpose || !schur_has_side_sums(P)) side_sums = nullptr;
   if (P.mma_mt > 0 && !side_sums && P.schur_pers[schur_nc_class(nrhs)] >= 0 && launch_schur_pers(P, y, t, nrhs, transpose, active, s, prec))
     return;
@@ -1182,26 +1187,28 @@ void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, boo
                        (side_sums ? (size_t)nc * kTile * 4 * (kt / 4) * sizeof(double) : 0);
     const dim3 g((P.ntile + 7) / 8 * 8, (nrhs + nc - 1) / nc);
     const dim3 b(16 * kt);
-#define SMPM_MFMA_LAUNCH(KT, NC, T)                                                                       \
-  if (transpose)                                                                                          \
-    hipLaunchKernelGGL((k_schur_mfma<true, KT, NC, T>), g, b, lds, s, P, y, t, nrhs, active, nullptr);    \
-  else                                                                                                    \
-    hipLaunchKernelGGL((k_schur_mfma<false, KT, NC, T>), g, b, lds, s, P, y, t, nrhs, active, side_sums);
-#define SMPM_MFMA_NC(KT, T)                 \
+#define SMPM_MFMA_LAUNCH(KT, NC, T, NTS)                                                                       \
+  if (transpose)                                                                                               \
+    hipLaunchKernelGGL((k_schur_mfma<true, KT, NC, T, NTS>), g, b, lds, s, P, y, t, nrhs, active, nullptr);    \
+  else                                                                                                         \
+    hipLaunchKernelGGL((k_schur_mfma<false, KT, NC, T, NTS>), g, b, lds, s, P, y, t, nrhs, active, side_sums);
+#define SMPM_MFMA_NC(KT, T, NTS)            \
   if (nc == 4) {                            \
-    SMPM_MFMA_LAUNCH(KT, 4, T)              \
+    SMPM_MFMA_LAUNCH(KT, 4, T, NTS)         \
   } else if (nc == 2) {                     \
-    SMPM_MFMA_LAUNCH(KT, 2, T)              \
+    SMPM_MFMA_LAUNCH(KT, 2, T, NTS)         \
   } else {                                  \
-    SMPM_MFMA_LAUNCH(KT, 1, T)              \
+    SMPM_MFMA_LAUNCH(KT, 1, T, NTS)         \
   }
-#define SMPM_MFMA_PREC(KT)           \
-  if (prec == PREC_F32) {            \
-    SMPM_MFMA_NC(KT, float)          \
-  } else if (prec == PREC_BF16) {    \
-    SMPM_MFMA_NC(KT, bf16s)          \
-  } else {                           \
-    SMPM_MFMA_NC(KT, double)         \
+#define SMPM_MFMA_PREC(KT)              \
+  if (prec == PREC_F32) {               \
+    SMPM_MFMA_NC(KT, float, false)      \
+  } else if (prec == PREC_BF16) {       \
+    SMPM_MFMA_NC(KT, bf16s, false)      \
+  } else if (stream_out) {              \
+    SMPM_MFMA_NC(KT, double, true)      \
+  } else {                              \
+    SMPM_MFMA_NC(KT, double, false)     \
   }
     switch (kt) {
       case 4: SMPM_MFMA_PREC(4) break;
