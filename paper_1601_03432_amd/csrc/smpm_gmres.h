@@ -21,7 +21,7 @@ struct GmState {
   double* c;        // Z^T t
   double* sides;    // per-side sums of t (nsides per column), for Z^T t
   double* c2;       // G c
-  double* part1;    // partial dots with w, col*ldv*nch + i*nch + chunk
+  double* part1;    // partial dots with w, col*ldv*nch + chunk*ldv + i (chunk-major)
   double* part2;    // partial dots with u_j
   double* h1;       // h' = Q^T A q of the last finished vector, col*ldv
   double* h2;       // pre-reduced dots with u_j

@@ -30,8 +30,10 @@
 //   gm_dots     w = t - Z c2 - S Z c2 (deflation); partial dots of V_0..V_j with w
 //               and with u_j = V_j; next j
 // Each block handles a chunk of rows.  Every block that needs a reduced value sums
-// the previous kernel's per-chunk partials itself, in one fixed order, so results
-// are deterministic and no inter-block fence is needed.
+// the previous kernel's per-chunk partials itself (or k_gm_reduce does it once per
+// column), in one fixed order whatever the block shape, so results are
+// deterministic and no inter-block fence is needed.  Basis loads become
+// non-temporal once the part of the basis a pass reads outgrows the last-level cache.
 #include <hip/hip_runtime.h>
 
 #include "smpm_gmres.h"
