@@ -160,8 +160,8 @@ def main():
                     help="time only the metric kernel (no solves), e.g. for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
-                                   "note, not part of this build", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; sharding over several GPUs is "
+                                   "not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

@@ -609,7 +609,7 @@ class Deflation:
         self.Z = deflation_matrix(sys.grid, sys.split.sides)
         self.d = self.Z.shape[1]
         self.C = (self.Z.T @ (sys.S @ self.Z)).toarray() if self.d else np.zeros((0, 0))
-        # scale of C: ||Z||^2 ||S||, so that a d = 1 coarse matrix can be judged singular
+        # scale of C: ||Z||^2 ||S||, so that a d = 1 coarse matrix can be recognised as singular
         self.scale = 2 * sys.grid.n * spla.norm(sys.S, 1)
         if self.d:
             U, sv, Vt = np.linalg.svd(self.C)
