@@ -208,7 +208,9 @@ int smpm_export(const smpm_ctx *ctx, int what, int64_t *count, int64_t *rows, in
 int smpm_null_vectors(smpm_ctx *ctx, double *uL, double *uS);
 
 /* Sv = S v (transpose = 0) or S^T v (transpose = 1) for nrhs k-vectors
- * (Eq. schur_complement_system).  Device pointers, column-blocked. */
+ * (Eq. schur_complement_system).  Device pointers, column-blocked.  Sv is
+ * written with non-temporal stores (it is the caller's result, not reread by
+ * the library). */
 int smpm_schur_apply(smpm_ctx *ctx, const double *v, double *Sv, int nrhs, int transpose,
                      void *stream);
 
