@@ -943,8 +943,10 @@ __global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S, double t
 
 // y = R^{-1} g for the first iters[col] columns (R = rotated Hessenberg), one
 // block per column, column-oriented back substitution.
+constexpr int kLsqStage = 64;  // Krylov dimensions whose triangle is staged in LDS
 __global__ __launch_bounds__(256) void k_gm_lsq(GmState S) {
   __shared__ double gs[kMaxIt + 1];
+  __shared__ double rs[kLsqStage * kLsqStage];
   const int col = blockIdx.x, tid = threadIdx.x;
   const int J = S.iters[col];
   const double* gc = S.g + (int64_t)col * S.ldv;
@@ -952,6 +954,23 @@ __global__ __launch_bounds__(256) void k_gm_lsq(GmState S) {
   double* yc = S.y + (int64_t)col * S.ldv;
   for (int i = tid; i < J; i += kThreads) gs[i] = gc[i];
   for (int i = J + tid; i < S.ldv; i += kThreads) yc[i] = 0.0;
+  if (J <= kLsqStage) {
+    // the triangle staged in LDS with every load in flight, then the same steps
+    // from LDS (one memory round trip instead of two per column)
+    for (int t = tid; t < J * J; t += kThreads) {
+      const int i = t / J, m = t - i * J;
+      if (m <= i) rs[i * kLsqStage + m] = Hc[(int64_t)i * S.ldv + m];
+    }
+    __syncthreads();
+    for (int i = J - 1; i >= 0; --i) {
+      const double yi = gs[i] / rs[i * kLsqStage + i];
+      __syncthreads();
+      for (int m = tid; m < i; m += kThreads) gs[m] -= rs[i * kLsqStage + m] * yi;
+      if (tid == 0) yc[i] = yi;
+      __syncthreads();
+    }
+    return;
+  }
   __syncthreads();
   for (int i = J - 1; i >= 0; --i) {
     const double yi = gs[i] / Hc[(int64_t)i * S.ldv + i];
