@@ -58,7 +58,9 @@ def kernels_sha256():
 
 def graph_time_us(launch, launches, replays=20):
     """Average duration of one launch: `launches` calls of `launch` captured in a HIP
-    graph, replayed `replays` times between HIP events on the replaying stream."""
+    graph, replayed `replays` times between HIP events on the replaying stream, after
+    replays // 2 untimed replays (the GPU clock settles; the first replays after setup
+    run a few percent slower)."""
     import torch
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -71,7 +73,8 @@ def graph_time_us(launch, launches, replays=20):
     with torch.cuda.graph(g):
         for _ in range(launches):
             launch()
-    g.replay()
+    for _ in range(max(1, replays // 2)):
+        g.replay()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
