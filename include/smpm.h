@@ -160,7 +160,7 @@ void smpm_default_opts(smpm_solve_opts *opts);
  * x_breaks (m_x+1) and y_breaks (m_y+1) are host arrays of strictly increasing
  * element breakpoints.  Requires m_x*m_y >= 2, 3 <= n <= 32, penalty finite and
  * nonzero.  The coarse solve with C = Z^T S Z is a dense G = C^+ for up to
- * 4096 interfaces (environment SMPM_DENSE_COARSE_MAX overrides the limit);
+ * 4096 interfaces (environment SMPM_DENSE_COARSE_MAX may lower the limit);
  * larger grids solve with C exactly by one level of substructuring: patches of
  * 8 x 8 elements (SMPM_COARSE_PATCH overrides; doubled while the separator
  * system would exceed 8192 unknowns), dense inverses of the patch-interior

@@ -45,7 +45,7 @@ std::vector<double> to_colmajor(const double* a, int m, int n) {
 
 }  // namespace
 
-int dense_coarse_limit() { return env_int("SMPM_DENSE_COARSE_MAX", 4096); }
+int dense_coarse_limit() { return std::min(env_int("SMPM_DENSE_COARSE_MAX", kDenseCoarseMax), kDenseCoarseMax); }
 
 // Sparse C = Z^T S Z, rows sorted by column.  Row i: 2n on the diagonal (Z^T Z) plus,
 // for each side of interface i, the row sums over that side of the outgoing fluxes

@@ -11,6 +11,7 @@
 #include <atomic>
 
 #include "smpm_kernels.h"
+#include "smpm_plan.h"  // kDenseCoarseMax
 
 namespace smpm {
 
@@ -856,16 +857,46 @@ __global__ __launch_bounds__(256) void k_sub_patch2(DevPlan P, double* __restric
 __global__ __launch_bounds__(256) void k_coarse_sides(DevPlan P, const double* __restrict__ ss,
                                                       double* __restrict__ c2, int transpose,
                                                       const int* __restrict__ active) {
+  __shared__ double cs[kDenseCoarseMax];
   const int col = blockIdx.y;
   if (active && !active[col]) return;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int d = P.d;
+  const double* sc = ss + (int64_t)col * P.nsides;
+  // the interface sums c_j = s(side a) + s(side b) into LDS, four per thread and
+  // round: the index loads, then the gathers, are issued together
+  for (int j0 = threadIdx.x; j0 < d; j0 += 4 * 256) {
+    int sa[4], sb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = min(j0 + u * 256, d - 1);
+      sa[u] = P.iface_side[2 * j];
+      sb[u] = P.iface_side[2 * j + 1];
+    }
+    double va[4], vb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      va[u] = sc[sa[u]];
+      vb[u] = sc[sb[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + u * 256 < d) cs[j0 + u * 256] = va[u] + vb[u];
+  }
+  __syncthreads();
   if (i >= d) return;
   const double* Gp = (transpose ? P.GT : P.G) + (int64_t)i * d;
-  const double* sc = ss + (int64_t)col * P.nsides;
+  // the row's products in lane order (j = lane, lane + 64, ...), its loads eight at a time
   double acc = 0.0;
-  for (int j = lane; j < d; j += 64) acc = fma(Gp[j], sc[P.iface_side[2 * j]] + sc[P.iface_side[2 * j + 1]], acc);
+  for (int j0 = lane; j0 < d; j0 += 8 * 64) {
+    double g[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g[u] = Gp[min(j0 + u * 64, d - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u * 64 < d) acc = fma(g[u], cs[j0 + u * 64], acc);
+  }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) c2[(int64_t)col * d + i] = acc;
 }
@@ -1305,6 +1336,7 @@ void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool
 
 void launch_coarse_sides(const DevPlan& P, const double* side_sums, double* c2, int nrhs, bool transpose,
                          const int* active, hipStream_t s) {
+  // dense mode only: d <= dense_coarse_limit() <= kDenseCoarseMax, the kernel's LDS
   if (P.d == 0 || !P.has_coarse || P.coarse_mode != 1) return;
   hipLaunchKernelGGL(k_coarse_sides, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, side_sums, c2, transpose ? 1 : 0,
                      active);

@@ -128,8 +128,10 @@ void export_precond_inv_coo(const Plan& p, std::vector<int64_t>& ri, std::vector
                             std::vector<double>& v);
 
 // Coarse solve helpers (smpm_coarse.cpp).  Grids with more interfaces than
-// dense_coarse_limit() (default 4096, environment SMPM_DENSE_COARSE_MAX) use the
-// substructured solve with patches of SMPM_COARSE_PATCH (default 8) elements a side.
+// dense_coarse_limit() (kDenseCoarseMax = 4096, the most the dense coarse kernel
+// stages; the environment SMPM_DENSE_COARSE_MAX may lower it) use the substructured
+// solve with patches of SMPM_COARSE_PATCH (default 8) elements a side.
+constexpr int kDenseCoarseMax = 4096;
 int dense_coarse_limit();
 void build_coarse_rows(const Plan& p, std::vector<int64_t>& row_off, std::vector<int>& cols,
                        std::vector<double>& vals);
