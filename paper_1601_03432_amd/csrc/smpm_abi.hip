@@ -690,7 +690,26 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
         btau.push_back(p.alpha / (omega0 * hp));  // tau sigma = (2 alpha/(omega0 h_e^2)) (h_e/2)
       }
   }
+  // per inter-element side, the interfaces and coefficient offsets that the deflation
+  // w = t - Z c2 - {S, S^T} Z c2 reads for the side's slots (two 16-byte loads a side)
+  std::vector<int> side_fwd((size_t)p.nsides * 8, -1), side_adj((size_t)p.nsides * 8, -1);
+  for (int64_t si = 0; si < p.nsides; ++si) {
+    const int e = p.side_elem[si], sd = p.side_dir[si];
+    const int J = p.nbr[(size_t)e * 4 + sd];
+    int* f = &side_fwd[(size_t)si * 8];
+    int* a = &side_adj[(size_t)si * 8];
+    f[0] = a[0] = p.iface[(size_t)e * 4 + sd];
+    for (int s2 = 0; s2 < 4; ++s2) {
+      f[1 + s2] = J >= 0 ? p.iface[(size_t)J * 4 + s2] : -1;
+      a[1 + s2] = p.iface[(size_t)e * 4 + s2];
+    }
+    f[5] = J >= 0 ? (p.cls[J] * 4 + (sd ^ 1)) * n * 4 : 0;
+    a[5] = p.cls[e] * 4 * 4 * n;
+    a[6] = p.slot_off[e];
+  }
   int rc = SMPM_OK;
+  rc |= upload(c, side_fwd, &d.side_fwd, s);
+  rc |= upload(c, side_adj, &d.side_adj, s);
   rc |= upload(c, p.nbr, &d.nbr, s);
   rc |= upload(c, p.cls, &d.cls, s);
   rc |= upload(c, p.slot_off, &d.slot_off, s);

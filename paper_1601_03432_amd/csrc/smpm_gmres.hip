@@ -869,31 +869,10 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
   const double* Vc = S.V + (int64_t)col * k;
   const double* uj = Vc + (int64_t)j * S.vvs;
   const double* cc = S.c2 + (int64_t)col * P.d;
-  const int n = P.n;
   for (int q = tid; q < rows; q += kThreads) {
     const int64_t slot = x0 + q;
     double v = tc[slot];
-    if (defl) {
-      const int si = (int)(slot / n), tt = (int)(slot - (int64_t)si * n);
-      const int e = P.side_elem[si], s = P.side_dir[si];
-      double acc = cc[P.iface[e * 4 + s]];
-      if (!transpose) {
-        const int J = P.nbr[e * 4 + s], cJ = P.cls[J], so = s ^ 1;
-        const double* wz = P.WZ + (((int64_t)cJ * 4 + so) * n + tt) * 4;
-        for (int s2 = 0; s2 < 4; ++s2) {
-          const int j2 = P.iface[J * 4 + s2];
-          if (j2 >= 0) acc = fma(wz[s2], cc[j2], acc);
-        }
-      } else {
-        const int ce = P.cls[e];
-        const int cidx = (int)(slot - P.slot_off[e]);
-        for (int s2 = 0; s2 < 4; ++s2) {
-          const int j2 = P.iface[e * 4 + s2];
-          if (j2 >= 0) acc = fma(P.WZc[((int64_t)ce * 4 + s2) * 4 * n + cidx], cc[j2], acc);
-        }
-      }
-      v -= acc;
-    }
+    if (defl) v -= deflation(P, cc, slot, transpose != 0);
     wc[slot] = v;
     wv[q] = v;
     uv[q] = uj[slot];

@@ -21,6 +21,11 @@ struct DevPlan {
   const int* iface;        // nel*4
   const int* side_elem;    // nsides
   const int* side_dir;     // nsides
+  // per side, 8 ints: the deflation's interfaces and coefficient offsets
+  //   side_fwd: own interface, the neighbour's 4 interfaces, WZ offset of (neighbour class, facing side)
+  //   side_adj: own interface, the element's 4 interfaces, WZc offset of the element class, first slot
+  const int* side_fwd;
+  const int* side_adj;
   const int* iface_side;   // d*2
   const int* cls_nslots;   // ncls
   const int* cls_sidecol;  // ncls*4
@@ -181,6 +186,31 @@ __device__ __forceinline__ void block_jacobi_apply(const OpT* __restrict__ Mp, c
       store(v, tid, sum);
     }
   }
+}
+
+// (Z c2 + S Z c2)[slot] (forward) or (Z c2 + S^T Z c2)[slot] (transpose): the coarse
+// value of the slot's interface plus the coupling of the interfaces the side's
+// flux reaches, from the side's table entry (two 16-byte loads), then the values.
+__device__ __forceinline__ double deflation(const DevPlan& P, const double* __restrict__ cc, int64_t slot,
+                                            bool transpose) {
+  const int n = P.n;
+  const int si = (int)(slot / n), tt = (int)(slot - (int64_t)si * n);
+  const int4* tb = reinterpret_cast<const int4*>((transpose ? P.side_adj : P.side_fwd) + (int64_t)si * 8);
+  const int4 a = tb[0], b = tb[1];
+  const int js[4] = {a.y, a.z, a.w, b.x};
+  double acc = cc[a.x];
+  if (!transpose) {
+    const double* wz = P.WZ + b.y + tt * 4;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+      if (js[s2] >= 0) acc = fma(wz[s2], cc[js[s2]], acc);
+  } else {
+    const int cidx = (int)(slot - b.z);
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+      if (js[s2] >= 0) acc = fma(P.WZc[(int64_t)b.y + s2 * 4 * n + cidx], cc[js[s2]], acc);
+  }
+  return acc;
 }
 
 template <typename T>

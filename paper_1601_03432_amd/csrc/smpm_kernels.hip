@@ -908,25 +908,13 @@ __global__ void k_prolong(DevPlan P, const double* __restrict__ t, const double*
   if (active && !active[col]) return;
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= P.k) return;
-  const int n = P.n;
-  const int si = (int)(slot / n), tt = (int)(slot - (int64_t)si * n);
-  const int e = P.side_elem[si], s = P.side_dir[si];
   const double* cc = c2 + (int64_t)col * P.d;
-  double acc = cc[P.iface[e * 4 + s]];
-  if (sz == 1) {
-    const int J = P.nbr[e * 4 + s], cJ = P.cls[J], so = s ^ 1;
-    const double* wz = P.WZ + (((int64_t)cJ * 4 + so) * n + tt) * 4;
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int j2 = P.iface[J * 4 + s2];
-      if (j2 >= 0) acc = fma(wz[s2], cc[j2], acc);
-    }
-  } else if (sz == 2) {
-    const int ce = P.cls[e];
-    const int cidx = (int)(slot - P.slot_off[e]);
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int j2 = P.iface[e * 4 + s2];
-      if (j2 >= 0) acc = fma(P.WZc[((int64_t)ce * 4 + s2) * 4 * n + cidx], cc[j2], acc);
-    }
+  double acc;
+  if (sz == 1 || sz == 2) {
+    acc = deflation(P, cc, slot, sz == 2);
+  } else {
+    const int si = (int)(slot / P.n);
+    acc = cc[P.iface[P.side_elem[si] * 4 + P.side_dir[si]]];
   }
   const int64_t o = (int64_t)col * P.k + slot;
   w[o] = t[o] + sign * acc;
