@@ -732,15 +732,24 @@ __global__ __launch_bounds__(256) void k_sub_patch1(DevPlan P, const double* __r
   const double* M = (transpose ? P.sub_Fr : P.sub_Rc) + P.sub_FR_off[pp];
   double* part = P.cws + (int64_t)col * P.cws_stride + P.sub_B_off[pp] + (int64_t)pp * P.sub_border;
   for (int row = threadIdx.x; row < ni + nbb; row += blockDim.x) {
+    // row of K_pp^{-1} (interior) or of R_p (separator part): its entries loaded
+    // sixteen at a time (clamped in the last batch), the products in order
+    const bool interior = row < ni;
+    const double* src = interior ? K + row : M + (row - ni);
+    const int64_t ld = interior ? ni : nbb;
     double acc = 0.0;
-    if (row < ni) {
-      for (int j = 0; j < ni; ++j) acc = fma(K[(int64_t)j * ni + row], cl[j], acc);
-      c2[(int64_t)col * P.d + P.sub_I[i0 + row]] = acc;
-    } else {
-      const int l = row - ni;
-      for (int j = 0; j < ni; ++j) acc = fma(M[(int64_t)j * nbb + l], cl[j], acc);
-      part[l] = acc;
+    for (int j0 = 0; j0 < ni; j0 += 16) {
+      double kv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) kv[u] = src[(int64_t)min(j0 + u, ni - 1) * ld];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (j0 + u < ni) acc = fma(kv[u], cl[j0 + u], acc);
     }
+    if (interior)
+      c2[(int64_t)col * P.d + P.sub_I[i0 + row]] = acc;
+    else
+      part[row - ni] = acc;
   }
 }
 
