@@ -770,9 +770,20 @@ __global__ __launch_bounds__(256) void k_sub_rhs(DevPlan P, const double* __rest
     const double qb = ws[P.sub_B_off[pl[2]] + (int64_t)pl[2] * P.sub_border + pl[3]];
     r[b] = c[(int64_t)col * P.d + P.sub_sep_iface[b]] - qa - qb;
   } else {
+    // lambda part = last of each patch; sixteen patches' loads at a time, sums in order
+    const int np = P.sub_npatch;
     double acc = 0.0;
-    for (int pp = 0; pp < P.sub_npatch; ++pp)
-      acc += ws[P.sub_B_off[pp + 1] + (int64_t)pp * P.sub_border];  // lambda part = last of the patch
+    for (int p0 = 0; p0 < np; p0 += 16) {
+      int off[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) off[u] = P.sub_B_off[min(p0 + u, np - 1) + 1];
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = ws[off[u] + (int64_t)min(p0 + u, np - 1) * P.sub_border];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (p0 + u < np) acc += v[u];
+    }
     r[b] = -acc;
   }
 }
@@ -857,7 +868,15 @@ __global__ __launch_bounds__(256) void k_sub_patch2(DevPlan P, double* __restric
   const double* M = (transpose ? P.sub_Rr : P.sub_Fc) + P.sub_FR_off[pp];
   for (int row = threadIdx.x; row < ni; row += blockDim.x) {
     double acc = cc[P.sub_I[i0 + row]];
-    for (int l = 0; l < nbb; ++l) acc = fma(-M[(int64_t)l * ni + row], xl[l], acc);
+    // the row's entries sixteen at a time (clamped in the last batch), products in order
+    for (int l0 = 0; l0 < nbb; l0 += 16) {
+      double mv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) mv[u] = M[(int64_t)min(l0 + u, nbb - 1) * ni + row];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (l0 + u < nbb) acc = fma(-mv[u], xl[l0 + u], acc);
+    }
     cc[P.sub_I[i0 + row]] = acc;
   }
 }
