@@ -886,19 +886,54 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
     chunk_dots2<false>(Vc, S.vvs, x0, rows, wv, uv, j + 1, p1, p2, S.ldv, chunk);
 }
 
-// Pre-reduction after gm_dots (up to four 1024-thread blocks per column, splitting
-// the vectors in groups of 64): the dots with w into dw and with u_j into h2, summed
-// exactly as gm_update sums them itself.
-constexpr int kReduceThreads = 1024;
-__global__ __launch_bounds__(kReduceThreads) void k_gm_reduce(GmState S, int par) {
-  __shared__ double lds[2 * 16 * 64];
+// Pre-reduction after gm_dots: the dots with w into dw and with u_j into h2, summed
+// exactly as gm_update sums them itself (chunk class c mod 16, each class in
+// increasing c, then the same tree).  A block takes 16 vectors: its lanes are
+// 16 vectors x 4 classes and its 4 waves the class quarters, so every wave load reads
+// four 128-byte rows and the blocks of a column share the work.
+constexpr int kReduceVecs = 16;
+__global__ __launch_bounds__(256) void k_gm_reduce(GmState S, int par) {
+  __shared__ double cs[2][16][kReduceVecs];
   const int col = blockIdx.y;
   const int j = S.jdev[par];
   if (!S.active[col] || j > S.maxit) return;
-  reduce_partials2<kReduceThreads / 64>(S.part1 + (int64_t)col * S.ldv * S.nch,
-                                        S.part2 + (int64_t)col * S.ldv * S.nch, j + 1, S.nch, S.ldv,
-                                        S.dw + (int64_t)col * S.ldv, S.h2 + (int64_t)col * S.ldv, lds, blockIdx.x,
-                                        gridDim.x);
+  const int nvec = j + 1, v0 = blockIdx.x * kReduceVecs;
+  if (v0 >= nvec) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int vl = lane & 15, q = wave * 4 + (lane >> 4);  // vector v0 + vl, class q
+  const int v = min(v0 + vl, nvec - 1);
+  const int nch = S.nch, ld = S.ldv;
+  const double* pa = S.part1 + (int64_t)col * ld * nch;
+  const double* pb = S.part2 + (int64_t)col * ld * nch;
+  double sa = 0.0, sb = 0.0;
+  for (int c0 = q; c0 < nch; c0 += 16 * 16) {
+    // sixteen chunks of the class per batch (past nch: the last chunk, not added)
+    double la[16], lb[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t at = (int64_t)min(c0 + 16 * u, nch - 1) * ld + v;
+      la[u] = pa[at];
+      lb[u] = pb[at];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (c0 + 16 * u < nch) {
+        sa += la[u];
+        sb += lb[u];
+      }
+  }
+  cs[0][q][vl] = sa;
+  cs[1][q][vl] = sb;
+  __syncthreads();
+  if (threadIdx.x < 2 * kReduceVecs) {
+    const int a = threadIdx.x / kReduceVecs, vv = threadIdx.x - a * kReduceVecs;
+    if (v0 + vv < nvec) {
+      double tr[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tr[r] = (cs[a][r][vv] + cs[a][r + 4][vv]) + (cs[a][r + 8][vv] + cs[a][r + 12][vv]);
+      (a == 0 ? S.dw : S.h2)[(int64_t)col * ld + v0 + vv] = (tr[0] + tr[1]) + (tr[2] + tr[3]);
+    }
+  }
 }
 
 // Start of a solve: u_0 = w (the initial residual) into V_0; all columns active;
@@ -1041,8 +1076,7 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
   hipLaunchKernelGGL(k_gm_dots, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
                      tr ? 1 : 0);
   if (S.prereduce)
-    hipLaunchKernelGGL(k_gm_reduce, dim3((S.maxit + 64) / 64 < 4 ? (S.maxit + 64) / 64 : 4, nrhs), dim3(kReduceThreads), 0, s, S,
-                       par);
+    hipLaunchKernelGGL(k_gm_reduce, dim3((S.maxit + kReduceVecs) / kReduceVecs, nrhs), dim3(256), 0, s, S, par);
 }
 
 void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s) {
