@@ -86,7 +86,8 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // order of the additions is fixed whatever the block shape: chunk c belongs to class
 // c mod 16, a class sums its chunks in increasing c, and the class sums s_q are
 // combined as (t_0 + t_1) + (t_2 + t_3) with t_r = (s_r + s_{r+4}) + (s_{r+8} +
-// s_{r+12}); every block, of 4 or of 16 waves, obtains the same bits.  Lanes run
+// s_{r+12}); every block, of 4 or of 16 waves, obtains the same bits, and so does
+// k_gm_reduce, which follows the same order with another lane mapping.  Lanes run
 // over vectors (coalesced rows), the NW waves share the classes.  Vector groups
 // g0, g0 + gstep, ... of 64.  lds: 2 * NW * 64 doubles.  Contains barriers: call from
 // all threads of the block.
