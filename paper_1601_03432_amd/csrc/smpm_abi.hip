@@ -753,6 +753,16 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   rc |= upload(c, p.sub.Rr, &d.sub_Rr, s);
   rc |= upload(c, p.sub.sep_iface, &d.sub_sep_iface, s);
   rc |= upload(c, p.sub.sep_pl, &d.sub_sep_pl, s);
+  // the substructured kernels' two-step index lookups, composed once here
+  std::vector<int> sub_B_iface(p.sub.B.size()), sub_sep_woff(p.sub.sep_pl.size() / 2);
+  for (size_t i = 0; i < p.sub.B.size(); ++i) sub_B_iface[i] = p.sub.sep_iface[p.sub.B[i]];
+  for (size_t b = 0; b * 4 < p.sub.sep_pl.size(); ++b)
+    for (int h = 0; h < 2; ++h) {
+      const int pp = p.sub.sep_pl[b * 4 + 2 * h], loc = p.sub.sep_pl[b * 4 + 2 * h + 1];
+      sub_sep_woff[b * 2 + h] = p.sub.B_off[pp] + pp * p.sub.border + loc;
+    }
+  rc |= upload(c, sub_B_iface, &d.sub_B_iface, s);
+  rc |= upload(c, sub_sep_woff, &d.sub_sep_woff, s);
   rc |= upload(c, p.sub.Si, &d.sub_Si, s);
   rc |= upload(c, p.sub.SiT, &d.sub_SiT, s);
   rc |= upload(c, to_f32(p.Wc), &d.WcF, s);

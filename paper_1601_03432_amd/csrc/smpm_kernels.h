@@ -64,6 +64,8 @@ struct DevPlan {
   const double* sub_Rr;
   const int* sub_sep_iface;  // nsep
   const int* sub_sep_pl;     // nsep*4: (patch, local) of both patches
+  const int* sub_B_iface;    // per entry of sub_B: the separator's interface
+  const int* sub_sep_woff;   // nsep*2: where the two patches' parts of a separator sit in cws
   const double* sub_Si;    // separator system inverse, row-major, and its transpose
   const double* sub_SiT;
   int sub_lds_max;         // max over patches of max(ni, nbb): LDS doubles of the patch kernels

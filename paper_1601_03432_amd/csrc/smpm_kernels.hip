@@ -765,9 +765,9 @@ __global__ __launch_bounds__(256) void k_sub_rhs(DevPlan P, const double* __rest
   const double* ws = P.cws + (int64_t)col * P.cws_stride;
   double* r = P.cws + (int64_t)col * P.cws_stride + sub_part_len(P);
   if (b < P.sub_nsep) {
-    const int* pl = P.sub_sep_pl + (int64_t)b * 4;
-    const double qa = ws[P.sub_B_off[pl[0]] + (int64_t)pl[0] * P.sub_border + pl[1]];
-    const double qb = ws[P.sub_B_off[pl[2]] + (int64_t)pl[2] * P.sub_border + pl[3]];
+    const int* wo = P.sub_sep_woff + (int64_t)b * 2;
+    const double qa = ws[wo[0]];
+    const double qb = ws[wo[1]];
     r[b] = c[(int64_t)col * P.d + P.sub_sep_iface[b]] - qa - qb;
   } else {
     // lambda part = last of each patch; sixteen patches' loads at a time, sums in order
@@ -862,8 +862,7 @@ __global__ __launch_bounds__(256) void k_sub_patch2(DevPlan P, double* __restric
   double* cc = c2 + (int64_t)col * P.d;
   const double* ws = P.cws + (int64_t)col * P.cws_stride;
   for (int l = threadIdx.x; l < nbb; l += blockDim.x)
-    xl[l] = l < nb ? cc[P.sub_sep_iface[P.sub_B[b0 + l]]]
-                   : ws[sub_part_len(P) + P.sub_nsep + P.sub_border];
+    xl[l] = l < nb ? cc[P.sub_B_iface[b0 + l]] : ws[sub_part_len(P) + P.sub_nsep + P.sub_border];
   __syncthreads();
   const double* M = (transpose ? P.sub_Rr : P.sub_Fc) + P.sub_FR_off[pp];
   for (int row = threadIdx.x; row < ni; row += blockDim.x) {
