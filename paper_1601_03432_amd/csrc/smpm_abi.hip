@@ -79,7 +79,7 @@ struct smpm_ctx {
   // captured chunks of Arnoldi steps, keyed by the solve's shape; they hold workspace
   // pointers, so a workspace reallocation drops them
   struct GraphEntry {
-    int nrhs, kind, tr, sprec, mprec, maxit, prereduce;
+    int nrhs, kind, tr, sprec, mprec, maxit, prereduce, stream;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
@@ -396,6 +396,8 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.prereduce = (int64_t)S.nch * nrhs > 1024 ? 1 : 0;
   if (c->prereduce_choice[schur_nc_class(nrhs)] >= 0) S.prereduce = c->prereduce_choice[schur_nc_class(nrhs)];
   if (const char* e = std::getenv("SMPM_PREREDUCE")) S.prereduce = e[0] == '1' ? 1 : e[0] == '0' ? 0 : S.prereduce;
+  S.stream = -1;  // test hook: SMPM_STREAM_BASIS=1 / 0 forces one kind of basis load
+  if (const char* e = std::getenv("SMPM_STREAM_BASIS")) S.stream = e[0] == '1' ? 1 : e[0] == '0' ? 0 : -1;
   S.bref2 = W.scal2 + 2 * nrhs;
   return S;
 }
@@ -407,7 +409,7 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
                 hipGraphExec_t* out) {
   for (const auto& g : c->graphs)
     if (g.nrhs == nrhs && g.kind == kind && g.tr == (int)tr && g.sprec == sprec && g.mprec == mprec &&
-        g.maxit == S.maxit && g.prereduce == S.prereduce) {
+        g.maxit == S.maxit && g.prereduce == S.prereduce && g.stream == S.stream) {
       *out = g.exec;
       return SMPM_OK;
     }
@@ -425,7 +427,7 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
     (void)hipGraphExecDestroy(c->graphs.front().exec);
     c->graphs.erase(c->graphs.begin());
   }
-  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, S.prereduce, exec});
+  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, S.prereduce, S.stream, exec});
   *out = exec;
   return SMPM_OK;
 }

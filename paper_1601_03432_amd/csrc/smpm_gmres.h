@@ -46,6 +46,8 @@ struct GmState {
                     // (large grids x many columns); 0: every consumer block reduces
                     // the partials itself (fewer launches).  Same summation order.
   const double* bref2;  // squared reference norm per column (|b|^2): stop when |g| <= tol |b|
+  int stream;       // basis loads: -1 non-temporal once a pass reads more than the
+                    // last-level cache keeps, 0 always ordinary, 1 always non-temporal
 };
 
 // u_0 = w into V_0, all columns active, j = 0 and the tolerance on the device

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   const int col = blockIdx.y, tid = threadIdx.x;
   if (!S.active[col]) return;
   const int j = S.jdev[par];
-  const bool nt = stream_basis(j > 1 ? j : 1, S.vvs);
+  const bool nt = S.stream > 0 || (S.stream < 0 && stream_basis(j > 1 ? j : 1, S.vvs));
   const int64_t k = P.k;
   double* zc = S.z + (int64_t)col * k;
   const double* Vc = S.V + (int64_t)col * k;
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
   }
   if (!any) return;
   const int j = S.jdev[par];
-  const bool nt = stream_basis(j > 1 ? j : 1, S.vvs);
+  const bool nt = S.stream > 0 || (S.stream < 0 && stream_basis(j > 1 ? j : 1, S.vvs));
   const int m = j - 1;
   if (m > S.maxit) return;
   if (j > 0) {
@@ -881,7 +881,7 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
   __syncthreads();
   double* p1 = S.part1 + (int64_t)col * S.ldv * S.nch;
   double* p2 = S.part2 + (int64_t)col * S.ldv * S.nch;
-  if (stream_basis(j + 1, S.vvs))
+  if (S.stream > 0 || (S.stream < 0 && stream_basis(j + 1, S.vvs)))
     chunk_dots2<true>(Vc, S.vvs, x0, rows, wv, uv, j + 1, p1, p2, S.ldv, chunk);
   else
     chunk_dots2<false>(Vc, S.vvs, x0, rows, wv, uv, j + 1, p1, p2, S.ldv, chunk);

@@ -1,6 +1,9 @@
 """Edge cases and error paths of the device solve, through the C ABI: a column that
 exhausts maxit, a zero right-hand side inside a batch, invalid options, the maxit
-limit, non-convergence reported by a group solve, and run-to-run determinism."""
+limit, non-convergence reported by a group solve, run-to-run determinism, and the
+cache policy of the basis loads leaving the bits unchanged."""
+import os
+
 import numpy as np
 import pytest
 
@@ -100,3 +103,32 @@ def test_repeated_solves_are_bit_identical(precision):
     for _ in range(3):
         u, _ = ctx.solve(F, **kw)
         assert torch.equal(u, ref)
+
+
+def _with_env(env, fn):
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("ncol,prereduce", [(1, "0"), (4, "1")])
+def test_streaming_basis_loads_keep_the_bits(ncol, prereduce):
+    """Non-temporal basis loads (forced on a small grid, where the library would use
+    ordinary ones) change only the cache policy: the solution and the iteration count
+    are bit-identical (one column through the single-column update; four columns
+    through the multi-column update with pre-reduced sums)."""
+    print(f"[gpu-edges] streaming basis loads, {ncol} columns", flush=True)
+    ctx = ctx_c1()
+    F = source(ctx, 940, ncol)
+    kw = dict(tol=1e-12, maxit=600)
+    ref, info = _with_env({"SMPM_STREAM_BASIS": "0", "SMPM_PREREDUCE": prereduce}, lambda: ctx.solve(F, **kw))
+    u, info_s = _with_env({"SMPM_STREAM_BASIS": "1", "SMPM_PREREDUCE": prereduce}, lambda: ctx.solve(F, **kw))
+    assert torch.equal(u, ref)
+    assert info_s.iterations == info.iterations
