@@ -112,7 +112,8 @@ typedef struct smpm_solve_opts {
   int graph;          /* 1: the Arnoldi steps run as replays of a captured hipGraph of 8 steps
                          (captured once per solve shape and context); 0: launched one by one.
                          (Environment SMPM_PREREDUCE=0/1 forces how the orthogonalization
-                         sums are reduced: once per column or in every block.)
+                         sums are reduced: once per column or in every block;
+                         SMPM_STREAM_BASIS=0/1 forces ordinary or non-temporal basis loads.)
                          Results are identical (default 1)                                        */
 } smpm_solve_opts;
 
