@@ -679,18 +679,22 @@ __global__ __launch_bounds__(256) void k_iface_sum(DevPlan P, const double* __re
                                                    const int* __restrict__ active) {
   const int col = blockIdx.y;
   if (active && !active[col]) return;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (j >= P.d) return;
-  const double* tc = t + (int64_t)col * P.k;
   const int n = P.n;
+  // with 2n <= 32 a wavefront takes two interfaces, one per half (the halves' trees
+  // are the 64-lane tree without its first step, which only added zeros)
+  const bool pack = 2 * n <= 32;
+  const int lane = threadIdx.x & 63;
+  const int j = pack ? blockIdx.x * 8 + (threadIdx.x >> 6) * 2 + (lane >> 5) : blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = pack ? lane & 31 : lane;
+  if (j >= P.d) return;  // a whole wave, or a whole half whose partners are in it
+  const double* tc = t + (int64_t)col * P.k;
   double acc = 0.0;
-  for (int q = lane; q < 2 * n; q += 64) {
+  for (int q = l; q < 2 * n; q += 64) {
     const int h = q / n, i = q - h * n;
     acc += tc[(int64_t)P.iface_side[2 * j + h] * n + i];
   }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) c[(int64_t)col * P.d + j] = acc;
+  for (int off = pack ? 16 : 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (l == 0) c[(int64_t)col * P.d + j] = acc;
 }
 
 // c2 = G c (or G^T c): one wavefront per row, lanes over the row, fixed shuffle tree.
@@ -1323,7 +1327,7 @@ void launch_precond(const DevPlan& P, const double* x, double* y, int nrhs, bool
 
 void launch_iface_sum(const DevPlan& P, const double* t, double* c, int nrhs, const int* active, hipStream_t s) {
   if (P.d == 0 || !P.has_coarse) return;
-  hipLaunchKernelGGL(k_iface_sum, grid1(P.d, 4, nrhs), dim3(256), 0, s, P, t, c, active);
+  hipLaunchKernelGGL(k_iface_sum, grid1(P.d, 2 * P.n <= 32 ? 8 : 4, nrhs), dim3(256), 0, s, P, t, c, active);
 }
 
 void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool transpose, const int* active,
