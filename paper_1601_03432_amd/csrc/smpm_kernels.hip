@@ -737,17 +737,17 @@ __global__ __launch_bounds__(256) void k_sub_patch1(DevPlan P, const double* __r
   double* part = P.cws + (int64_t)col * P.cws_stride + P.sub_B_off[pp] + (int64_t)pp * P.sub_border;
   for (int row = threadIdx.x; row < ni + nbb; row += blockDim.x) {
     // row of K_pp^{-1} (interior) or of R_p (separator part): its entries loaded
-    // sixteen at a time (clamped in the last batch), the products in order
+    // 32 at a time (clamped in the last batch), the products in order
     const bool interior = row < ni;
     const double* src = interior ? K + row : M + (row - ni);
     const int64_t ld = interior ? ni : nbb;
     double acc = 0.0;
-    for (int j0 = 0; j0 < ni; j0 += 16) {
-      double kv[16];
+    for (int j0 = 0; j0 < ni; j0 += 32) {
+      double kv[32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) kv[u] = src[(int64_t)min(j0 + u, ni - 1) * ld];
+      for (int u = 0; u < 32; ++u) kv[u] = src[(int64_t)min(j0 + u, ni - 1) * ld];
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
+      for (int u = 0; u < 32; ++u)
         if (j0 + u < ni) acc = fma(kv[u], cl[j0 + u], acc);
     }
     if (interior)
