@@ -124,3 +124,18 @@ def test_substructured_coarse_matches_oracle(name, patch, monkeypatch):
     Gl = ctx.export(smpm.EXPORT_COARSE_PINV)
     assert np.abs(Cl - m.defl.C).max() <= 1e-11 * max(1.0, np.abs(m.defl.C).max())
     assert np.abs(Gl - m.defl.G).max() <= 1e-9 * max(1e-300, np.abs(m.defl.G).max()) + 1e-14
+
+
+def test_dense_coarse_limit_is_capped(monkeypatch):
+    """A dense-coarse limit above what the dense coarse kernel stages (4096
+    interfaces) is capped: a grid with more interfaces still takes the substructured
+    solve."""
+    _lib()
+    monkeypatch.setenv("SMPM_DENSE_COARSE_MAX", "1000000")
+    m = 48
+    xb = yb = np.linspace(0.0, 1.0, m + 1)
+    ctx = smpm.Context(m, m, 4, xb, yb, O.DEFAULT_ALPHA, device=False)
+    assert ctx.d == 2 * m * (m - 1) > 4096
+    st = ctx.stats()
+    assert st["has_coarse"] == 1
+    assert 0 < st["coarse_bytes"] < ctx.d * ctx.d * 8
