@@ -871,13 +871,13 @@ __global__ __launch_bounds__(256) void k_sub_patch2(DevPlan P, double* __restric
   const double* M = (transpose ? P.sub_Rr : P.sub_Fc) + P.sub_FR_off[pp];
   for (int row = threadIdx.x; row < ni; row += blockDim.x) {
     double acc = cc[P.sub_I[i0 + row]];
-    // the row's entries sixteen at a time (clamped in the last batch), products in order
-    for (int l0 = 0; l0 < nbb; l0 += 16) {
-      double mv[16];
+    // the row's entries 32 at a time (clamped in the last batch), products in order
+    for (int l0 = 0; l0 < nbb; l0 += 32) {
+      double mv[32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) mv[u] = M[(int64_t)min(l0 + u, nbb - 1) * ni + row];
+      for (int u = 0; u < 32; ++u) mv[u] = M[(int64_t)min(l0 + u, nbb - 1) * ni + row];
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
+      for (int u = 0; u < 32; ++u)
         if (l0 + u < nbb) acc = fma(-mv[u], xl[l0 + u], acc);
     }
     cc[P.sub_I[i0 + row]] = acc;
