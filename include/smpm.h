@@ -34,12 +34,21 @@
  * Discretization (Sec. 1.2, Eq. smpm_poisson).  At the nodes of an element side
  * the row of L adds tau (R u_i - R u_j) across an inter-element side and
  * tau sigma n.grad u_i on a physical side (right-hand side tau sigma g), with
- * the Robin operator R = I + sigma n_i.grad, sigma = h_e/2, tau = 2*penalty/
- * (omega_0*h_e^2), omega_0 = 2/(N(N+1)) the GLL end weight and h_e the smaller
- * extent of the element whose row it is (its values serve u_i and u_j alike;
- * on a square element sigma n.grad is the normal derivative in the reference
- * coordinates [-1,1]^2).  Sec. 1.2 leaves tau to a heuristic; recommended
- * penalty: 8 (any finite nonzero value is accepted).
+ * the Robin operator R = I + sigma n_i.grad; the values of the element whose row
+ * it is serve u_i and u_j alike.  Sec. 1.2 prints R = I + n.grad (sigma = 1) and
+ * leaves tau to a heuristic; smpm_robin selects the reading of sigma and tau
+ * (omega_0 = 2/(N(N+1)) the GLL end weight, h_perp the element's extent normal to
+ * the side, h_e its smaller extent):
+ *   SMPM_ROBIN_LITERAL    sigma = 1,          tau = 2 penalty / (omega_0 h_perp)
+ *   SMPM_ROBIN_REFERENCE  sigma = h_perp / 2, tau = 2 penalty / (omega_0 h_perp^2)
+ *                         (sigma n.grad = the normal derivative in the element's
+ *                         reference coordinates [-1,1]^2)
+ *   SMPM_ROBIN_MIN        sigma = h_e / 2,    tau = 2 penalty / (omega_0 h_e^2)
+ *                         (default; equals REFERENCE on square elements and keeps
+ *                         GMRES convergent on elements of aspect ratio up to 8,
+ *                         where it is neither the physical nor the reference-
+ *                         coordinate derivative)
+ * Recommended penalty: 8 (any finite nonzero value is accepted).
  *
  * Ownership and streams.  A context owns its setup data and device workspace;
  * smpm_destroy releases them.  The caller owns every vector argument.  Device
@@ -79,6 +88,12 @@ enum smpm_precision {
   SMPM_FP64 = 0,         /* everything in FP64 */
   SMPM_MIXED_FP32 = 1,   /* FP32 Schur/preconditioner applies inside FP64 refinement */
   SMPM_MIXED_BF16 = 2    /* BF16 operators, FP32 accumulation, FP64 refinement */
+};
+
+enum smpm_robin {
+  SMPM_ROBIN_MIN = 0,        /* sigma = h_e/2 (default)                              */
+  SMPM_ROBIN_LITERAL = 1,    /* sigma = 1: R = I + n.grad as printed in Sec. 1.2      */
+  SMPM_ROBIN_REFERENCE = 2   /* sigma = h_perp/2: reference-coordinate derivative     */
 };
 
 enum smpm_projection {
@@ -172,12 +187,22 @@ void smpm_default_opts(smpm_solve_opts *opts);
 int smpm_plan(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
               double penalty, smpm_ctx **out);
 
+/* smpm_plan with a chosen reading of the Robin operator (smpm_robin; smpm_plan uses
+ * SMPM_ROBIN_MIN).  SMPM_EINVAL for an unknown mode. */
+int smpm_plan_robin(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
+                    double penalty, int robin, smpm_ctx **out);
+
 /* smpm_plan + upload to the current device.  Synchronous.  The null vectors
  * u_S (left null vector of S) and u_L (left null vector of L, Sec. 1.4) are
  * computed on first use (smpm_solve, smpm_project L/S, smpm_null_vectors) by a
  * GMRES solve with the transposed Schur complement. */
 int smpm_setup(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
                double penalty, void *stream, smpm_ctx **out);
+
+/* smpm_setup with a chosen reading of the Robin operator (smpm_robin; smpm_setup
+ * uses SMPM_ROBIN_MIN). */
+int smpm_setup_robin(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
+                     double penalty, int robin, void *stream, smpm_ctx **out);
 
 /* Releases everything the context owns (NULL is ignored). */
 void smpm_destroy(smpm_ctx *ctx);

@@ -30,13 +30,20 @@ Readings where the paper is silent or at odds with itself:
   slot to its node (so E^T E = I holds except between the two slots of such a
   corner node).
 * Robin operator and penalty.  Sec. 1.2 writes R_ij = I + n_i.grad and leaves
-  tau to a heuristic.  R = I + sigma n_i.grad with sigma = h_e/2 and
-  tau_e = 2 alpha / (omega_0 h_e^2), h_e the smaller extent of element i (the
-  element whose row it is; its sigma and tau serve u_i and u_j alike) and
-  omega_0 = 2/(N(N+1)) the GLL end weight.  On a square element sigma n.grad is
-  the normal derivative in the reference coordinates.  A physical side carries
-  tau sigma n.grad u and tau sigma g.  alpha = 8 on all sides by default (the
-  oracle accepts any alpha_int / alpha_phys).
+  tau to a heuristic.  The oracle takes R = I + sigma n_i.grad with one of three
+  readings of the length sigma and the matching penalty tau (omega_0 = 2/(N(N+1))
+  the GLL end weight, h_perp the element's extent normal to the side, h_e its
+  smaller extent; the values of the element whose row it is serve u_i and u_j
+  alike):
+    "literal"    sigma = 1 (R exactly as printed, physical coordinates),
+                 tau = 2 alpha / (omega_0 h_perp);
+    "reference"  sigma = h_perp/2 (the normal derivative in the element's
+                 reference coordinates [-1,1]^2), tau = 2 alpha / (omega_0 h_perp^2);
+    "min"        sigma = h_e/2, tau = 2 alpha / (omega_0 h_e^2) (default; equal
+                 to "reference" on square elements).
+  A physical side carries tau sigma n.grad u and tau sigma g (for "literal" the
+  tau_i n.grad u_i and tau_i g_i of Eq. smpm_poisson).  alpha = 8 on all sides by
+  default (the oracle accepts any alpha_int / alpha_phys).
 * Element-corner nodes receive the penalty terms of both sides containing them.
 * Block-Jacobi blocks follow the checkerboard: the block of a "red" element
   ((ix+iy) even) holds that element's slots and the slots of its neighbours'
@@ -59,6 +66,7 @@ W, E, S, N = 0, 1, 2, 3
 SIDES = (W, E, S, N)
 OPPOSITE = {W: E, E: W, S: N, N: S}
 DEFAULT_ALPHA = 8.0
+ROBIN_MODES = ("min", "literal", "reference")
 
 
 # ---------------------------------------------------------------------------
@@ -111,7 +119,10 @@ class Grid:
     (p runs along x).  Element (iy, ix) covers [x_ix, x_ix+1] x [y_iy, y_iy+1].
     """
 
-    def __init__(self, n, x_breaks, y_breaks, alpha_int=DEFAULT_ALPHA, alpha_phys=None):
+    def __init__(self, n, x_breaks, y_breaks, alpha_int=DEFAULT_ALPHA, alpha_phys=None, robin="min"):
+        if robin not in ROBIN_MODES:
+            raise ValueError(f"robin must be one of {ROBIN_MODES}")
+        self.robin = robin
         self.n = int(n)
         self.Np = self.n - 1
         self.xb = np.asarray(x_breaks, np.float64)
@@ -152,17 +163,28 @@ class Grid:
         """h_e: the smaller extent of element (iy, ix)."""
         return min(self.width(ix), self.height(iy))
 
+    def normal_len(self, iy, ix, side):
+        """h_perp: the extent of element (iy, ix) normal to one of its sides."""
+        return self.width(ix) if side in (W, E) else self.height(iy)
+
     def tau(self, iy, ix, side):
-        """Penalty of one side of one element: 2 alpha / (omega_0 h_e^2) (reading
-        stated in the module header)."""
+        """Penalty of one side of one element (readings stated in the module header):
+        2 alpha / (omega_0 h_perp) for "literal", 2 alpha / (omega_0 l^2) otherwise
+        with l = h_perp ("reference") or h_e ("min")."""
         omega0 = 2.0 / (self.Np * (self.Np + 1))
         alpha = self.alpha_int if self.neighbor(iy, ix, side) is not None else self.alpha_phys
-        return 2.0 * alpha / (omega0 * self.elem_len(iy, ix) ** 2)
+        if self.robin == "literal":
+            return 2.0 * alpha / (omega0 * self.normal_len(iy, ix, side))
+        ell = self.normal_len(iy, ix, side) if self.robin == "reference" else self.elem_len(iy, ix)
+        return 2.0 * alpha / (omega0 * ell ** 2)
 
     def sigma(self, iy, ix, side):
         """Length scale of the Robin operator R = I + sigma n.grad on one side of
-        element (iy, ix): h_e / 2 (on a square element sigma n.grad is the normal
-        derivative in the element's reference coordinates)."""
+        element (iy, ix): 1 ("literal"), h_perp/2 ("reference") or h_e/2 ("min")."""
+        if self.robin == "literal":
+            return 1.0
+        if self.robin == "reference":
+            return 0.5 * self.normal_len(iy, ix, side)
         return 0.5 * self.elem_len(iy, ix)
 
     def side_nodes(self, side):

@@ -675,7 +675,6 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   // boundary data map: south, north, west, east
   std::vector<int> bnode;
   std::vector<double> btau;
-  const double omega0 = p.omega[0];
   for (int edge = 0; edge < 4; ++edge) {
     const int cnt = edge < 2 ? p.mx : p.my;
     for (int q = 0; q < cnt; ++q)
@@ -685,11 +684,10 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
         else if (edge == 1) { e = (p.my - 1) * p.mx + q; s2 = SN; }
         else if (edge == 2) { e = q * p.mx; s2 = SW; }
         else { e = q * p.mx + p.mx - 1; s2 = SE; }
-        const int ix = e % p.mx, iy = e / p.mx;
-        const double hp = std::min(p.wx[ix], p.hy[iy]);  // the element's smaller extent
         int l = s2 == SW ? t * n : s2 == SE ? t * n + n - 1 : s2 == SS ? t : (n - 1) * n + t;
         bnode.push_back(e * n * n + l);
-        btau.push_back(p.alpha / (omega0 * hp));  // tau sigma = (2 alpha/(omega0 h_e^2)) (h_e/2)
+        // coefficient of g: the physical side's tau sigma
+        btau.push_back(p.side_tau[(size_t)e * 4 + s2] * p.side_sig[(size_t)e * 4 + s2]);
       }
   }
   // per inter-element side, the interfaces and coefficient offsets that the deflation
@@ -871,14 +869,15 @@ void smpm_default_opts(smpm_solve_opts* o) {
 
 const char* smpm_last_error(void) { return g_err.c_str(); }
 
-int smpm_plan(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, smpm_ctx** out) {
+int smpm_plan_robin(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, int robin,
+                    smpm_ctx** out) {
   g_err.clear();
   if (!out) return fail(SMPM_EINVAL, "null output pointer");
   smpm_ctx* c = new (std::nothrow) smpm_ctx();
   if (!c) return fail(SMPM_ENOMEM, "host allocation failed");
   std::string msg;
   try {
-    msg = build_plan(c->plan, m_y, m_x, n, xb, yb, penalty);
+    msg = build_plan(c->plan, m_y, m_x, n, xb, yb, penalty, robin);
   } catch (const std::bad_alloc&) {
     delete c;
     return fail(SMPM_ENOMEM, "host allocation failed in setup");
@@ -892,12 +891,16 @@ int smpm_plan(int m_y, int m_x, int n, const double* xb, const double* yb, doubl
   return SMPM_OK;
 }
 
-int smpm_setup(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, void* stream,
-               smpm_ctx** out) {
+int smpm_plan(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, smpm_ctx** out) {
+  return smpm_plan_robin(m_y, m_x, n, xb, yb, penalty, SMPM_ROBIN_MIN, out);
+}
+
+int smpm_setup_robin(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, int robin,
+                     void* stream, smpm_ctx** out) {
   g_err.clear();
   if (!out) return fail(SMPM_EINVAL, "null output pointer");
   smpm_ctx* c = nullptr;
-  int rc = smpm_plan(m_y, m_x, n, xb, yb, penalty, &c);
+  int rc = smpm_plan_robin(m_y, m_x, n, xb, yb, penalty, robin, &c);
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&c->dev_id) != hipSuccess) {
@@ -914,6 +917,11 @@ int smpm_setup(int m_y, int m_x, int n, const double* xb, const double* yb, doub
   }
   *out = c;
   return SMPM_OK;
+}
+
+int smpm_setup(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, void* stream,
+               smpm_ctx** out) {
+  return smpm_setup_robin(m_y, m_x, n, xb, yb, penalty, SMPM_ROBIN_MIN, stream, out);
 }
 
 void smpm_destroy(smpm_ctx* c) { delete c; }

@@ -3,8 +3,12 @@
 // Discretization (Sec. 1.2, Eq. smpm_poisson): on each element the collocated
 // Laplacian plus, at the nodes of each side, tau (u + sigma n.grad u) - tau (u_j +
 // sigma n.grad u_j) across an inter-element side, or tau sigma n.grad u on a
-// physical side; sigma = h_e/2 and tau = 2 alpha / (omega_0 h_e^2) with h_e the
-// element's smaller extent (receiving element's values for both u_i and u_j).
+// physical side (receiving element's values for both u_i and u_j).  Three readings
+// of the Robin length sigma and the penalty tau (h_perp = the element's extent
+// normal to the side, h_e = its smaller extent, omega_0 the GLL end weight):
+//   literal    sigma = 1,          tau = 2 alpha / (omega_0 h_perp)   (R = I + n.grad)
+//   reference  sigma = h_perp / 2, tau = 2 alpha / (omega_0 h_perp^2)
+//   min        sigma = h_e / 2,    tau = 2 alpha / (omega_0 h_e^2)    (default)
 // Split (Sec. 1.3): A = the element-local part, B = the neighbour flux of each
 // side slot, E = slot -> node inclusion, S = I + B A^{-1} E.  Each distinct
 // element class stores A^{-1} and the outgoing side fluxes W = R A^{-1} E
@@ -252,11 +256,12 @@ static std::vector<double> local_matrix(const Plan& p, const ElementClass& c) {
 // ---------------------------------------------------------------- plan
 
 std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const double* yb,
-                       double alpha) {
+                       double alpha, int robin) {
   if (m_x < 1 || m_y < 1 || (int64_t)m_x * m_y < 2) return "need at least two elements";
   if (n < 3 || n > 32) return "n must be in [3, 32]";
   if (!xb || !yb) return "null breakpoints";
   if (!std::isfinite(alpha) || alpha == 0.0) return "penalty must be finite and nonzero";
+  if (robin != kRobinMin && robin != kRobinLiteral && robin != kRobinReference) return "unknown Robin mode";
   for (int i = 0; i < m_x; ++i)
     if (!(xb[i + 1] > xb[i]) || !std::isfinite(xb[i]) || !std::isfinite(xb[i + 1]))
       return "x breakpoints must be finite and strictly increasing";
@@ -270,6 +275,7 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
   p.nel = m_x * m_y;
   p.r = (int64_t)n * n * p.nel;
   p.alpha = alpha;
+  p.robin = robin;
   p.xb.assign(xb, xb + m_x + 1);
   p.yb.assign(yb, yb + m_y + 1);
   gll(n, p.xi, p.omega, p.D);
@@ -346,19 +352,30 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
     }
   p.d = d;
 
-  // penalty of an element's sides, tau = 2 alpha / (omega_0 h_e^2), and the length
-  // scale of its Robin operator R = I + sigma n.grad, sigma = h_e / 2, with h_e the
-  // element's smaller extent (on a square element sigma n.grad is the normal
-  // derivative in reference coordinates)
+  // penalty tau and Robin length sigma (R = I + sigma n.grad) of side s of element e
+  auto normal_len = [&](int e, int s) { return s == SW || s == SE ? p.wx[e % m_x] : p.hy[e / m_x]; };
   auto elem_len = [&](int e) { return std::min(p.wx[e % m_x], p.hy[e / m_x]); };
-  auto tau_of = [&](int e, int) {
-    const double he = elem_len(e);
-    return 2.0 * alpha / (omega0 * he * he);
+  auto tau_of = [&](int e, int s) {
+    if (robin == kRobinLiteral) return 2.0 * alpha / (omega0 * normal_len(e, s));
+    const double l = robin == kRobinReference ? normal_len(e, s) : elem_len(e);
+    return 2.0 * alpha / (omega0 * l * l);
   };
-  auto sig_of = [&](int e, int) { return 0.5 * elem_len(e); };
+  auto sig_of = [&](int e, int s) {
+    if (robin == kRobinLiteral) return 1.0;
+    return 0.5 * (robin == kRobinReference ? normal_len(e, s) : elem_len(e));
+  };
+  p.side_tau.assign((size_t)p.nel * 4, 0.0);
+  p.side_sig.assign((size_t)p.nel * 4, 0.0);
+  for (int e = 0; e < p.nel; ++e)
+    for (int s = 0; s < 4; ++s) {
+      p.side_tau[(size_t)e * 4 + s] = tau_of(e, s);
+      p.side_sig[(size_t)e * 4 + s] = sig_of(e, s);
+    }
 
   // element classes
-  std::map<std::tuple<double, double, int, double, double, double, double>, int> key2cls;
+  std::map<std::tuple<double, double, int, double, double, double, double, std::tuple<double, double, double, double>>,
+           int>
+      key2cls;
   p.cls.assign(p.nel, -1);
   for (int e = 0; e < p.nel; ++e) {
     const int ix = e % m_x, iy = e / m_x;
@@ -373,8 +390,8 @@ std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* xb, const
       c.tau_recv[s] = j >= 0 ? tau_of(j, opposite(s)) : 0.0;
       c.sig_recv[s] = j >= 0 ? sig_of(j, opposite(s)) : 0.0;
     }
-    auto key = std::make_tuple(c.w, c.h, c.mask, c.tau_recv[0], c.tau_recv[1], c.tau_recv[2],
-                               c.tau_recv[3]);
+    auto key = std::make_tuple(c.w, c.h, c.mask, c.tau_recv[0], c.tau_recv[1], c.tau_recv[2], c.tau_recv[3],
+                               std::make_tuple(c.sig_recv[0], c.sig_recv[1], c.sig_recv[2], c.sig_recv[3]));
     auto it = key2cls.find(key);
     if (it == key2cls.end()) {
       int col = 0;

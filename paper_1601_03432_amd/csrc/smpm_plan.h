@@ -17,6 +17,8 @@
 namespace smpm {
 
 enum Side { SW = 0, SE = 1, SS = 2, SN = 3 };
+// readings of the Robin length sigma (values of smpm_robin in smpm.h)
+constexpr int kRobinMin = 0, kRobinLiteral = 1, kRobinReference = 2;
 inline int opposite(int s) { return s ^ 1; }
 
 struct ElementClass {
@@ -24,7 +26,7 @@ struct ElementClass {
   int mask = 0;            // bit s set: side s is an inter-element side
   double tau_own[4] = {0, 0, 0, 0};   // penalty of this element's sides
   double tau_recv[4] = {0, 0, 0, 0};  // penalty of the neighbour side facing side s
-  double sig_own[4] = {0, 0, 0, 0};   // Robin length scale h_e/2 of this element's sides
+  double sig_own[4] = {0, 0, 0, 0};   // Robin length scale sigma of this element's sides
   double sig_recv[4] = {0, 0, 0, 0};  // ... of the neighbour side facing side s
   int nslots = 0;          // slots owned by an element of this class
   int side_col[4] = {-1, -1, -1, -1};  // first slot column of side s within the element
@@ -52,6 +54,8 @@ struct Plan {
   int n = 0, mx = 0, my = 0, nel = 0;
   int64_t r = 0, k = 0, d = 0, nsides = 0;
   double alpha = 0;
+  int robin = kRobinMin;
+  std::vector<double> side_tau, side_sig;  // nel*4: tau and sigma of every side (physical ones too)
   std::vector<double> xb, yb;
   std::vector<double> wx, hy;  // element widths / heights (equal within 1e-12 relative -> identical)
   // GLL
@@ -117,7 +121,7 @@ struct Plan {
 
 // Builds the plan.  Returns an empty string on success, else the error text.
 std::string build_plan(Plan& p, int m_y, int m_x, int n, const double* x_breaks,
-                       const double* y_breaks, double alpha);
+                       const double* y_breaks, double alpha, int robin = kRobinMin);
 
 // Host export helpers used by the CPU tests of the setup.
 void export_schur_coo(const Plan& p, std::vector<int64_t>& ri, std::vector<int64_t>& ci,

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsmpm.so")
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESINGULAR, ENODEVICE = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 PROJ_L, PROJ_S, PROJ_P, PROJ_Q, PROJ_MEAN = 0, 1, 2, 3, 4
+ROBIN = {"min": 0, "literal": 1, "reference": 2}  # smpm_robin
 EXPORT_SCHUR, EXPORT_FLUX_SOLVE, EXPORT_PRECOND_INV, EXPORT_COARSE, EXPORT_COARSE_PINV = 0, 1, 2, 3, 4
 
 # every symbol include/smpm.h declares
@@ -27,7 +28,7 @@ EXPORT_SCHUR, EXPORT_FLUX_SOLVE, EXPORT_PRECOND_INV, EXPORT_COARSE, EXPORT_COARS
 DEFAULT_PENALTY = 8.0
 
 ABI_SYMBOLS = (
-    "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_destroy", "smpm_sizes", "smpm_stats", "smpm_slot_map",
+    "smpm_default_opts", "smpm_plan", "smpm_setup", "smpm_plan_robin", "smpm_setup_robin", "smpm_destroy", "smpm_sizes", "smpm_stats", "smpm_slot_map",
     "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
     "smpm_schur_apply", "smpm_schur_apply_prec", "smpm_precond_apply", "smpm_project", "smpm_solve",
     "smpm_boundary_transpose", "smpm_autotune", "smpm_solve_group",
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     lib.smpm_default_opts.restype = None
     lib.smpm_plan.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, C.POINTER(vp)]
     lib.smpm_setup.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, vp, C.POINTER(vp)]
+    lib.smpm_plan_robin.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, C.c_int, C.POINTER(vp)]
+    lib.smpm_setup_robin.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, C.c_int, vp, C.POINTER(vp)]
     lib.smpm_destroy.argtypes = [vp]
     lib.smpm_destroy.restype = None
     lib.smpm_sizes.argtypes = [vp, i64p, i64p, i64p]
@@ -145,29 +148,33 @@ def _info(si, rc):
 
 
 class Context:
-    """One grid: m_y x m_x elements with breakpoints, n GLL points, penalty alpha.
+    """One grid: m_y x m_x elements with breakpoints, n GLL points, penalty alpha and
+    the reading of the Robin operator ("min", "literal" or "reference", smpm_robin).
 
-    device=False builds the host plan only (smpm_plan); device=True also uploads
-    it and computes the null vectors on the current GPU (smpm_setup).
+    device=False builds the host plan only (smpm_plan_robin); device=True also
+    uploads it to the current GPU (smpm_setup_robin).
     """
 
-    def __init__(self, m_y, m_x, n, x_breaks, y_breaks, penalty=DEFAULT_PENALTY, device=True, stream=None):
+    def __init__(self, m_y, m_x, n, x_breaks, y_breaks, penalty=DEFAULT_PENALTY, device=True, stream=None,
+                 robin="min"):
         lib = load_library()
         xb = np.ascontiguousarray(x_breaks, np.float64)
         yb = np.ascontiguousarray(y_breaks, np.float64)
         if xb.size != m_x + 1 or yb.size != m_y + 1:
             raise ValueError("breakpoint arrays must have m_x+1 and m_y+1 entries")
+        mode = ROBIN[robin] if isinstance(robin, str) else int(robin)
         h = C.c_void_p()
         if device:
             import torch
-            rc = lib.smpm_setup(m_y, m_x, n, _dptr(xb), _dptr(yb), float(penalty), _stream(torch, stream),
-                                C.byref(h))
+            rc = lib.smpm_setup_robin(m_y, m_x, n, _dptr(xb), _dptr(yb), float(penalty), mode,
+                                      _stream(torch, stream), C.byref(h))
         else:
-            rc = lib.smpm_plan(m_y, m_x, n, _dptr(xb), _dptr(yb), float(penalty), C.byref(h))
+            rc = lib.smpm_plan_robin(m_y, m_x, n, _dptr(xb), _dptr(yb), float(penalty), mode, C.byref(h))
         _check(rc)
         self._h = h
         self._lib = lib
         self.device = device
+        self.robin = robin
         self.m_x, self.m_y, self.n = m_x, m_y, n
         r, k, d = C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib.smpm_sizes(h, C.byref(r), C.byref(k), C.byref(d)))
@@ -175,8 +182,8 @@ class Context:
         self.nbdry = 2 * n * (m_x + m_y)
 
     @classmethod
-    def from_workload(cls, w, penalty=DEFAULT_PENALTY, device=True):
-        return cls(w.m_y, w.m_x, w.n, w.x_breaks, w.y_breaks, penalty, device)
+    def from_workload(cls, w, penalty=DEFAULT_PENALTY, device=True, robin="min"):
+        return cls(w.m_y, w.m_x, w.n, w.x_breaks, w.y_breaks, penalty, device, robin=robin)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

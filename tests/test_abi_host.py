@@ -65,13 +65,21 @@ GRIDS = {
 }
 
 
+def test_plan_rejects_unknown_robin_mode():
+    _lib()
+    with pytest.raises(smpm.SmpmError) as ei:
+        smpm.Context(2, 2, 5, [0, .5, 1], [0, .5, 1], 8.0, device=False, robin=7)
+    assert ei.value.code == smpm.EINVAL
+
+
+@pytest.mark.parametrize("robin", O.ROBIN_MODES)
 @pytest.mark.parametrize("name", sorted(GRIDS))
-def test_setup_operators_match_oracle(name):
+def test_setup_operators_match_oracle(name, robin):
     _lib()
     n, xb, yb = GRIDS[name]()
     xb, yb = np.asarray(xb, float), np.asarray(yb, float)
-    ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, O.DEFAULT_ALPHA, device=False)
-    g = O.Grid(n, xb, yb)
+    ctx = smpm.Context(len(yb) - 1, len(xb) - 1, n, xb, yb, O.DEFAULT_ALPHA, device=False, robin=robin)
+    g = O.Grid(n, xb, yb, robin=robin)
     m = O.Method(g)
     assert (ctx.r, ctx.k, ctx.d) == (g.r, m.split.k, m.defl.d)
     assert np.array_equal(ctx.slot_map(), m.split.slot_node)

@@ -19,12 +19,13 @@ def grid(m_x, m_y, n, Lx=1.0, Ly=1.0, **kw):
 
 # ---------------------------------------------------------------- operator L
 
+@pytest.mark.parametrize("robin", O.ROBIN_MODES)
 @pytest.mark.parametrize("alpha", [8.0, -8.0, -1.0, 3.0])
-def test_polynomial_exactness(alpha):
+def test_polynomial_exactness(alpha, robin):
     """For a global polynomial of degree <= N per variable the interface jumps vanish,
     so L p = lap p at every node not on the physical boundary, and
-    lap p + tau sigma dp/dn there (Eq. smpm_poisson)."""
-    g = O.Grid(6, [0.0, 0.3, 1.0, 1.2], [0.0, 0.5, 1.1], alpha_int=alpha, alpha_phys=alpha)
+    lap p + tau sigma dp/dn there (Eq. smpm_poisson), for every reading of sigma."""
+    g = O.Grid(6, [0.0, 0.3, 1.0, 1.2], [0.0, 0.5, 1.1], alpha_int=alpha, alpha_phys=alpha, robin=robin)
     L, _ = O.assemble(g)
     x, y = g.node_coords()
     a, b = 4, 3
@@ -81,6 +82,64 @@ def test_conservation_at_special_penalty():
     oint = qx @ gb[:g.m_x * g.n] + qx @ gb[g.m_x * g.n:2 * g.m_x * g.n] \
         + qy @ gb[2 * g.m_x * g.n:2 * g.m_x * g.n + g.m_y * g.n] + qy @ gb[2 * g.m_x * g.n + g.m_y * g.n:]
     assert abs(w @ (T @ gb) + oint) <= 1e-12 * np.abs(gb).sum()
+
+
+def _weighted_column_sums(g):
+    L, _ = O.assemble(g)
+    Ld = L.toarray()
+    return np.abs(g.quad_weights() @ Ld).max() / np.abs(Ld).max()
+
+
+def test_conservation_literal_robin_nonuniform():
+    """R = I + n.grad as printed (sigma = 1) with tau = 2 alpha/(omega_0 h_perp): GLL
+    summation by parts turns w^T L u into side quadratures of
+    (1 + alpha_i + alpha_j)(jump of the normal derivative) + (alpha_i - alpha_j)(value
+    jump) on interfaces and (1 + alpha_phys) dn u on the boundary, so alpha = -1/2 on
+    interfaces and -1 on physical sides give w^T L = 0 on any Cartesian grid,
+    non-uniform and non-square elements included.  Pins tau ~ 1/h_perp, sigma = 1
+    and the corner sums of the literal reading."""
+    g = O.Grid(6, [0.0, 0.3, 1.0, 1.2], [0.0, 0.5, 1.1, 1.25], alpha_int=-0.5, alpha_phys=-1.0,
+               robin="literal")
+    assert _weighted_column_sums(g) <= 1e-12
+    # the same penalty under the other readings is not conservative on this grid
+    for robin in ("min", "reference"):
+        g2 = O.Grid(6, [0.0, 0.3, 1.0, 1.2], [0.0, 0.5, 1.1, 1.25], alpha_int=-0.5, alpha_phys=-1.0,
+                    robin=robin)
+        assert _weighted_column_sums(g2) > 1e-6
+
+
+def test_conservation_reference_robin_uniform_nonsquare():
+    """sigma = h_perp/2, tau = 2 alpha/(omega_0 h_perp^2): the side terms weigh
+    (alpha/h_perp)(value jump) + (alpha/2)(derivative jump), so alpha = -1 on
+    interfaces and -2 on physical sides conserve whenever h_perp agrees across each
+    interface (uniform widths and heights), also on non-square elements.  The
+    min(w, h) reading is not conservative there."""
+    xb, yb = wl.uniform_breaks(3, 1.5), wl.uniform_breaks(4, 0.8)   # w = 0.5, h = 0.2
+    g = O.Grid(7, xb, yb, alpha_int=-1.0, alpha_phys=-2.0, robin="reference")
+    assert _weighted_column_sums(g) <= 1e-12
+    g2 = O.Grid(7, xb, yb, alpha_int=-1.0, alpha_phys=-2.0, robin="min")
+    assert _weighted_column_sums(g2) > 1e-6
+
+
+@pytest.mark.parametrize("robin", O.ROBIN_MODES)
+def test_manufactured_non_square_elements(robin):
+    """Spectral convergence in n on 4 x 3 elements of aspect 1.5 ([0,2] x [0,1]) and on
+    a stretched grid (aspect up to 4) at the default penalty, for every reading of
+    the Robin operator (the discretization is consistent for any sigma: a smooth
+    solution has zero jumps of u + sigma n.grad u)."""
+    for xb, yb in ((wl.uniform_breaks(4, 2.0), wl.uniform_breaks(3, 1.0)),
+                   (np.array([0.0, 0.1, 0.25, 0.5, 1.0]), np.array([0.0, 0.3, 0.6, 1.0]))):
+        Lx, Ly = xb[-1], yb[-1]
+        errs = []
+        for n in (5, 7, 9, 11):
+            g = O.Grid(n, xb, yb, robin=robin)
+            x, y = g.node_coords()
+            u, f = wl.manufactured_cos(x, y, 1, Lx, Ly)
+            uh, mu, _, _ = O.solve_unreduced(O.Split(g), f)
+            errs.append(np.abs(uh - O.mean_zero(g, u)).max())
+        for a, b in zip(errs, errs[1:]):
+            assert b < a / 50.0, (robin, errs)
+        assert errs[-1] < 1e-9, (robin, errs)
 
 
 def test_left_null_vector_matches_svd():
