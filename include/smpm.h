@@ -155,6 +155,12 @@ typedef struct smpm_plan_stats {
   int64_t coarse_bytes;           /* FP64 bytes of the dense coarse pseudo-inverse (0 if none)   */
   int32_t coarse_singular;        /* 1 if C is singular (pseudo-inverse), 0 otherwise            */
   int32_t has_coarse;             /* 1 if the deflated solve is available                        */
+  double null_residual;           /* ||S^T u_S||_2 / ||S|| of the computed left null vector u_S
+                                     (||S|| taken as the bound below); -1 before the null
+                                     vectors are computed.  Setup accepts <= 1e-12.            */
+  int32_t null_iterations;        /* GMRES iterations (over restarts) of the null-vector solve  */
+  int32_t pad_;
+  double schur_norm_bound;        /* sqrt(||S||_1 ||S||_inf) >= ||S||_2                          */
 } smpm_plan_stats;
 
 typedef struct smpm_tune_result {
@@ -195,7 +201,9 @@ int smpm_plan_robin(int m_y, int m_x, int n, const double *x_breaks, const doubl
 /* smpm_plan + upload to the current device.  Synchronous.  The null vectors
  * u_S (left null vector of S) and u_L (left null vector of L, Sec. 1.4) are
  * computed on first use (smpm_solve, smpm_project L/S, smpm_null_vectors) by a
- * GMRES solve with the transposed Schur complement. */
+ * restarted GMRES solve with the transposed Schur complement; that first call
+ * returns SMPM_ESINGULAR if ||S^T u_S|| / ||S|| stays above 1e-12 (smpm_stats
+ * reports the value). */
 int smpm_setup(int m_y, int m_x, int n, const double *x_breaks, const double *y_breaks,
                double penalty, void *stream, smpm_ctx **out);
 

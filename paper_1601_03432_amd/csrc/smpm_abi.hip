@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -56,6 +57,8 @@ struct Workspace {
   double* hres = nullptr;  // 2 x nrhs residual-estimate ratios (per chunk slot)
   double* hout = nullptr;  // 4 x nrhs small results
   int* hiters = nullptr;   // nrhs iteration counts
+  int* nonfinite = nullptr;   // device flag: f or g held a non-finite entry
+  int* hnonfinite = nullptr;  // its pinned host copy
   hipEvent_t ev[2] = {nullptr, nullptr};
   int nch = 0, rows = 0;
   std::vector<void*> mem;
@@ -74,6 +77,8 @@ struct smpm_ctx {
   double wsum = 0;
   bool precond_regular = true;               // false when the single block is all of S
   bool have_null = false;                    // u_L, u_S computed (on first use)
+  double null_residual = -1.0;               // ||S^T u_S|| / ||S|| bound (-1: not computed)
+  int null_iterations = 0;                   // GMRES iterations the null-vector solve took
   std::vector<double> h_uL, h_uS;
   Workspace ws;
   // captured chunks of Arnoldi steps, keyed by the solve's shape; they hold workspace
@@ -212,16 +217,18 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.cws, (size_t)std::max<int64_t>(cstride, 1) * R);
   rc |= dalloc(w.mem, &w.tolv, 1);
   rc |= ialloc(w.mem, &w.jdev, 2);
+  rc |= ialloc(w.mem, &w.nonfinite, 1);
   if (rc != SMPM_OK) return SMPM_ENOMEM;
   c->dp.cws = w.cws;
   c->dp.cws_stride = cstride;
   {
-    // [flags 2R ints | iters R ints | pad] [hres 2R doubles] [hout 4R doubles]
-    const size_t ibytes = ((3 * R * sizeof(int) + 63) / 64) * 64;
+    // [flags 2R ints | iters R ints | non-finite flag | pad] [hres 2R doubles] [hout 4R doubles]
+    const size_t ibytes = (((3 * R + 1) * sizeof(int) + 63) / 64) * 64;
     const size_t bytes = ibytes + 6 * R * sizeof(double);
     if (hipHostMalloc((void**)&w.pinned, bytes, hipHostMallocCoherent) != hipSuccess)
       return fail(SMPM_ENOMEM, "hipHostMalloc failed");
     w.hiters = w.pinned + 2 * R;
+    w.hnonfinite = w.pinned + 3 * R;
     w.hres = reinterpret_cast<double*>(reinterpret_cast<char*>(w.pinned) + ibytes);
     w.hout = w.hres + 2 * R;
   }
@@ -566,27 +573,91 @@ int true_residual(smpm_ctx* c, bool tr, const double* b, const double* x, int nr
   return SMPM_OK;
 }
 
+// Upper bound of ||S||_2: sqrt(||S||_1 ||S||_inf), from the class operators (S = I +
+// the side fluxes W; row sums over the neighbour's slots, column sums over the four
+// receiving sides).
+double schur_norm_bound(const Plan& p) {
+  const int n = p.n;
+  double rmax = 0.0, cmax = 0.0;
+  for (size_t J = 0; J < p.classes.size(); ++J) {
+    const int ns = p.classes[J].nslots;
+    std::vector<double> col(ns, 0.0);
+    for (int so = 0; so < 4; ++so) {
+      const int64_t wo = p.W_off[J * 4 + so];
+      if (wo < 0) continue;
+      for (int t = 0; t < n; ++t) {
+        double rs = 0.0;
+        for (int cc = 0; cc < ns; ++cc) {
+          const double a = std::fabs(p.Wr[wo + (size_t)t * ns + cc]);
+          rs += a;
+          col[cc] += a;
+        }
+        rmax = std::max(rmax, rs);
+      }
+    }
+    for (double v : col) cmax = std::max(cmax, v);
+  }
+  return std::sqrt((1.0 + rmax) * (1.0 + cmax));
+}
+
 // u_S: (S + v0hat v0hat^T) is nonsingular and its transpose maps u_S to a multiple of
 // v0hat, so u_S = normalize((S + v0hat v0hat^T)^{-T} v0hat).  u_L = normalize(A^{-T} B^T u_S)
 // up to sign, since u_L^T L = 0 and E^T u_L is parallel to u_S (Sec. 1.4).
+// The solve restarts from its residual (y += GMRES(v0hat - (S^T + v0hat v0hat^T) y))
+// until ||S^T u_S|| <= kNullTol ||S|| (the norm bound above); SMPM_ESINGULAR otherwise.
+constexpr double kNullTol = 1e-12;
+constexpr int kNullCycles = 8, kNullMaxit = 600;
 int compute_null_vectors(smpm_ctx* c, hipStream_t s) {
   if (c->have_null) return SMPM_OK;
   const Plan& Pl = c->plan;
   const DevPlan& P = c->dp;
-  int rc = ensure_ws(c, 1, 600);
+  int rc = ensure_ws(c, 1, kNullMaxit);
   if (rc) return rc;
   Workspace& W = c->ws;
+  const int64_t k = Pl.k;
+  const double snorm = schur_norm_bound(Pl);
+  double* y = W.xacc;   // accumulated solution
+  double* rv = W.rho;   // right-hand side of the current cycle
   std::vector<int> it;
-  double* y = W.bS;
-  // GMRES on (S^T + v0hat v0hat^T) M^{-T}, then y <- M^{-T} y
-  int j = gmres(c, OP_RANK1, true, c->v0hat, W.x, 1, 1e-14, 600, it, s);
-  if (j < 0) return j;
-  if (c->precond_regular)
-    launch_precond(P, W.x, y, 1, true, nullptr, s);
-  else
-    HIPCHK(hipMemcpyAsync(y, W.x, sizeof(double) * Pl.k, hipMemcpyDeviceToDevice, s));
-  std::vector<double> hy(Pl.k);
-  HIPCHK(hipMemcpyAsync(hy.data(), y, Pl.k * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemsetAsync(y, 0, sizeof(double) * k, s));
+  HIPCHK(hipMemcpyAsync(rv, c->v0hat, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+  double null_res = HUGE_VAL;
+  int total = 0;
+  std::vector<double> hy(k);
+  for (int cyc = 0; cyc < kNullCycles; ++cyc) {
+    // GMRES on (S^T + v0hat v0hat^T) M^{-T}, then delta = M^{-T} x; y += delta
+    int j = gmres(c, OP_RANK1, true, rv, W.x, 1, 1e-14, kNullMaxit, it, s);
+    if (j < 0) return j;
+    total += j;
+    if (c->precond_regular)
+      launch_precond(P, W.x, W.t, 1, true, nullptr, s);
+    else
+      HIPCHK(hipMemcpyAsync(W.t, W.x, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+    launch_add(y, W.t, 1.0, y, k, 1, s);
+    // rv = v0hat - S^T y - v0hat (v0hat^T y);  ||S^T y|| and ||y|| for the check
+    launch_schur(P, y, W.t, 1, true, nullptr, s);
+    launch_mdot(c->v0hat, 0, 0, 1, y, k, nullptr, k, 1, W.part, W.scal2, nullptr, s);
+    launch_mdot(W.t, 0, k, 1, W.t, k, nullptr, k, 1, W.part, W.scal2 + 1, nullptr, s);
+    launch_mdot(y, 0, k, 1, y, k, nullptr, k, 1, W.part, W.scal2 + 2, nullptr, s);
+    launch_add(c->v0hat, W.t, -1.0, rv, k, 1, s);
+    launch_axpy_shared(rv, k, c->v0hat, W.scal2, 1.0, rv, k, 1, s);
+    launch_publish(W.scal2, 3, W.hout, s);
+    HIPCHK(hipStreamSynchronize(s));
+    const double sty = std::sqrt(W.hout[1]), yn = std::sqrt(W.hout[2]);
+    null_res = yn > 0 ? sty / (yn * snorm) : HUGE_VAL;
+    if (!std::isfinite(null_res)) break;
+    if (null_res <= kNullTol) break;
+  }
+  c->null_residual = null_res;
+  c->null_iterations = total;
+  if (!(null_res <= kNullTol)) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf,
+                  "left null vector of S not resolved: ||S^T u_S|| / ||S|| = %.3g after %d GMRES iterations", null_res,
+                  total);
+    return fail(SMPM_ESINGULAR, buf);
+  }
+  HIPCHK(hipMemcpyAsync(hy.data(), y, k * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   double nn = 0, sum = 0;
   for (double v : hy) {
@@ -949,6 +1020,9 @@ int smpm_stats(const smpm_ctx* c, smpm_plan_stats* o) {
                         : (int64_t)(p.G.size() * sizeof(double));
   o->coarse_singular = p.coarse_singular ? 1 : 0;
   o->has_coarse = p.has_coarse ? 1 : 0;
+  o->null_residual = c->null_residual;
+  o->null_iterations = c->null_iterations;
+  o->schur_norm_bound = schur_norm_bound(p);
   return SMPM_OK;
 }
 
@@ -1363,9 +1437,12 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   rc = ensure_ws(c, nrhs, o.maxit);
   if (rc) return rc;
   Workspace& W = c->ws;
+  // non-finite f or g: flagged by the kernels that first read them, reported as
+  // SMPM_EINVAL once the solve has run (a NaN estimate retires its column at once)
+  HIPCHK(hipMemsetAsync(W.nonfinite, 0, sizeof(int), s));
   if (!tr) {
     // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
-    launch_rhs(P, f, g, W.rhs, nrhs, s);
+    launch_rhs(P, f, g, W.rhs, nrhs, W.nonfinite, s);
     launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
     launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, s);  // read after the final synchronization
     launch_axpy_shared(W.rhs, Pl.r, c->uL, W.scal, 1.0, W.ft, Pl.r, nrhs, s);
@@ -1375,6 +1452,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   } else {
     // adjoint of the solution map: c~ = c - w (1^T c)/(w^T 1); S^T xi = E^T A^{-T} c~
     // (consistent: v0^T E^T A^{-T} c~ = -1^T c~ = 0), projected off v0 against rounding
+    launch_check_finite(f, Pl.r * nrhs, W.nonfinite, s);
     launch_mdot(c->ones, 0, 0, 1, f, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
     launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, s);  // read after the final synchronization
     launch_axpy_shared(f, Pl.r, c->wq, W.scal, 1.0 / c->wsum, W.ft, Pl.r, nrhs, s);
@@ -1397,8 +1475,37 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     if (rc < 0) return rc;
     rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
     if (rc) return rc;
+    // The least-squares estimate met tol, but the FP64 true residual decides.  Where it
+    // misses tol by rounding (finite, iterations left), FP64 correction cycles
+    // x += GMRES(b_hat - S x) bring it down (at most two).
+    for (int extra = 0; extra < 2; ++extra) {
+      double worst = 0.0;
+      bool fixable = true, any = false;
+      for (int i = 0; i < nrhs; ++i) {
+        if (tres[i] <= o.tol) continue;
+        any = true;
+        if (!std::isfinite(tres[i]) || iters[i] >= o.maxit) fixable = false;
+        worst = std::max(worst, tres[i]);
+      }
+      if (!any || !fixable) break;
+      HIPCHK(hipMemcpyAsync(W.xacc, W.bS, sizeof(double) * Pl.k * nrhs, hipMemcpyDeviceToDevice, s));
+      launch_schur(P, W.xacc, W.t, nrhs, tr, nullptr, s);
+      launch_add(W.bhat, W.t, -1.0, W.rho, Pl.k, nrhs, s);
+      const double* nl = tr ? c->v0hat : c->uS;
+      launch_mdot(nl, 0, 0, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
+      launch_axpy_shared(W.rho, Pl.k, nl, W.scal, 1.0, W.rho, Pl.k, nrhs, s);
+      std::vector<int> it;
+      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, std::min(0.5, 0.3 * o.tol / worst), o.maxit, it, s,
+                       PREC_F64, PREC_F64, o.graph != 0);
+      if (rc < 0) return rc;
+      for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
+      launch_add(W.xacc, W.bS, 1.0, W.bS, Pl.k, nrhs, s);
+      ++cycles;
+      rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
+      if (rc) return rc;
+    }
     for (int i = 0; i < nrhs; ++i)
-      if (iters[i] >= o.maxit) conv = false;
+      if (!(tres[i] <= o.tol)) conv = false;  // NaN counts as not converged
   } else {
     // Iterative refinement: rho = b_hat - S x in FP64; delta from the deflated GMRES with
     // FP32 (or BF16) Schur and block-Jacobi operators; x += delta.
@@ -1437,18 +1544,20 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       HIPCHK(hipStreamSynchronize(s));
       const double* a = W.hout;
       const double* bb = W.hout + nrhs;
-      bool all = true;
+      bool all = true, finite = true;
       double cmax = 0;
       for (int i = 0; i < nrhs; ++i) {
         tres[i] = bb[i] > 0 ? std::sqrt(a[i] / bb[i]) : std::sqrt(a[i]);
+        if (!std::isfinite(tres[i])) finite = false;
         cmax = std::max(cmax, tres[i]);
-        if (tres[i] > o.tol) all = false;
+        if (!(tres[i] <= o.tol)) all = false;
       }
-      if (cycles < 16) hist[cycles] = cmax;
+      if (cycles < 16) hist[cycles] = finite ? cmax : NAN;
       if (all) {
         conv = true;
         break;
       }
+      if (!finite) break;  // a non-finite residual cannot be refined
       if (cycles > 0 && !reverted && cmax > cprev) {
         // the last correction made the residual grow: undo it, raise the precision
         HIPCHK(hipMemcpyAsync(W.xacc, W.xprev, sizeof(double) * Pl.k * nrhs, hipMemcpyDeviceToDevice, s));
@@ -1514,17 +1623,18 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     launch_mdot(c->uL, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
     launch_axpy_shared(u, Pl.r, c->uL, W.scal, 1.0, u, Pl.r, nrhs, s);
   }
+  launch_publish_i(W.nonfinite, 1, W.hnonfinite, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   int itmax = 0;
   double resmax = 0;
   for (int i = 0; i < nrhs; ++i) {
     itmax = std::max(itmax, iters[i]);
-    resmax = std::max(resmax, tres[i]);
+    resmax = std::isnan(tres[i]) || std::isnan(resmax) ? NAN : std::max(resmax, tres[i]);
   }
   if (info) {
     info->iterations = itmax;
-    info->refinements = o.precision == SMPM_FP64 ? 1 : cycles;
+    info->refinements = cycles;
     info->schur_precision = sprec_final;
     for (int q = 0; q < 16; ++q) info->cycle_residual[q] = hist[q];
     if (o.precision == SMPM_FP64) info->cycle_residual[0] = resmax;
@@ -1532,9 +1642,12 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     // published before the synchronization above; the adjoint removes a multiple of w
     info->removed_component = W.hout[2 * nrhs] / (tr ? c->wsum : 1.0);
   }
+  if (*W.hnonfinite)
+    return fail(SMPM_EINVAL, tr ? "the cotangent holds a non-finite entry" : "f or g holds a non-finite entry");
   if (!conv)
-    return fail(SMPM_ENOCONV, o.precision == SMPM_FP64 ? "GMRES reached maxit before the tolerance"
-                                                        : "iterative refinement did not reach the tolerance");
+    return fail(SMPM_ENOCONV, o.precision == SMPM_FP64
+                                  ? "the FP64 true residual missed the tolerance (GMRES reached maxit or stalled)"
+                                  : "iterative refinement did not reach the tolerance");
   return SMPM_OK;
 }
 

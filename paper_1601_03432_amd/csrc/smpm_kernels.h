@@ -264,7 +264,11 @@ void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool
 // w = t + sign * (Z c2 + SZ c2) with sz = 0: no S term, 1: S Z, 2: S^T Z
 void launch_prolong(const DevPlan& P, const double* t, const double* c2, double* w, int nrhs, int sz,
                     double sign, const int* active, hipStream_t s);
-void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, hipStream_t s);
+// rhs = f + T g (g may be NULL); *flag is set to 1 if f or g holds a non-finite entry
+void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, int* flag,
+                hipStream_t s);
+// *flag = 1 if a[0..len) holds a non-finite entry (flag cleared by the caller)
+void launch_check_finite(const double* a, int64_t len, int* flag, hipStream_t s);
 void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, hipStream_t s);  // dg = T^T mu
 
 void launch_fill_pattern(double* b, int64_t len, hipStream_t s);  // values in (-1, 1) for timing runs

@@ -969,12 +969,31 @@ __global__ void k_fill_pattern(double* __restrict__ b, int64_t len) {
   b[i] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-// rhs[node] += tau g over boundary entries [b0, b1) (a range whose nodes are distinct)
-__global__ void k_bdry_add(DevPlan P, const double* __restrict__ g, double* __restrict__ rhs, int64_t b0, int64_t b1) {
+// b = a, and *flag = 1 if an entry of a is not finite (threads that see one store 1;
+// the flag is cleared by the caller)
+__global__ void k_copy_check(const double* __restrict__ a, double* __restrict__ b, int64_t len, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const double v = a[i];
+  b[i] = v;
+  if (!isfinite(v)) *flag = 1;
+}
+
+__global__ void k_check_finite(const double* __restrict__ a, int64_t len, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len && !isfinite(a[i])) *flag = 1;
+}
+
+// rhs[node] += tau g over boundary entries [b0, b1) (a range whose nodes are distinct);
+// *flag = 1 for a non-finite g entry
+__global__ void k_bdry_add(DevPlan P, const double* __restrict__ g, double* __restrict__ rhs, int64_t b0, int64_t b1,
+                           int* flag) {
   const int col = blockIdx.y;
   const int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1) return;
-  rhs[(int64_t)col * P.r + P.bdry_node[b]] += P.bdry_tau[b] * g[(int64_t)col * P.nbdry + b];
+  const double gv = g[(int64_t)col * P.nbdry + b];
+  if (!isfinite(gv)) *flag = 1;
+  rhs[(int64_t)col * P.r + P.bdry_node[b]] += P.bdry_tau[b] * gv;
 }
 
 __global__ void k_bdry_adj(DevPlan P, const double* __restrict__ mu, double* __restrict__ dg) {
@@ -1366,15 +1385,20 @@ void launch_prolong(const DevPlan& P, const double* t, const double* c2, double*
   hipLaunchKernelGGL(k_prolong, grid1(P.k, 256, nrhs), dim3(256), 0, s, P, t, c2, w, sz, sign, active);
 }
 
-void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, hipStream_t s) {
+void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, int* flag,
+                hipStream_t s) {
   const int64_t len = P.r * nrhs;
-  hipLaunchKernelGGL(k_copy, grid1(len, 256), dim3(256), 0, s, f, rhs, len);
+  hipLaunchKernelGGL(k_copy_check, grid1(len, 256), dim3(256), 0, s, f, rhs, len, flag);
   if (!g) return;
   // south + north edges first (distinct nodes), then west + east edges (distinct nodes);
   // a domain-corner node receives one term from each launch
   const int64_t sn = 2 * (int64_t)P.mx * P.n;
-  hipLaunchKernelGGL(k_bdry_add, grid1(sn, 256, nrhs), dim3(256), 0, s, P, g, rhs, (int64_t)0, sn);
-  hipLaunchKernelGGL(k_bdry_add, grid1(P.nbdry - sn, 256, nrhs), dim3(256), 0, s, P, g, rhs, sn, P.nbdry);
+  hipLaunchKernelGGL(k_bdry_add, grid1(sn, 256, nrhs), dim3(256), 0, s, P, g, rhs, (int64_t)0, sn, flag);
+  hipLaunchKernelGGL(k_bdry_add, grid1(P.nbdry - sn, 256, nrhs), dim3(256), 0, s, P, g, rhs, sn, P.nbdry, flag);
+}
+
+void launch_check_finite(const double* a, int64_t len, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_finite, grid1(len, 256), dim3(256), 0, s, a, len, flag);
 }
 
 void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, hipStream_t s) {

@@ -56,7 +56,9 @@ class PlanStats(C.Structure):
     _fields_ = [("element_classes", C.c_int64), ("block_classes", C.c_int64),
                 ("schur_operator_bytes", C.c_int64), ("precond_operator_bytes", C.c_int64),
                 ("flux_operator_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
-                ("coarse_singular", C.c_int32), ("has_coarse", C.c_int32)]
+                ("coarse_singular", C.c_int32), ("has_coarse", C.c_int32),
+                ("null_residual", C.c_double), ("null_iterations", C.c_int32), ("pad_", C.c_int32),
+                ("schur_norm_bound", C.c_double)]
 
 
 class SmpmError(RuntimeError):

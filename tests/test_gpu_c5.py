@@ -115,6 +115,26 @@ def _backward_error_at(grid, u, ft, elems):
     return worst
 
 
+def _left_null_error_at(grid, uL, elems):
+    """max over the columns of the sampled elements of |(L^T u_L)_j| / (|L|^T |u_L|)_j."""
+    n2 = grid.n2
+    worst = 0.0
+    for jy, jx in elems:
+        j = grid.eid(jy, jx)
+        acc = np.zeros(n2)
+        scale = np.zeros(n2)
+        rows_of = [(jy, jx)] + [nb for nb in (grid.neighbor(jy, jx, s) for s in O.SIDES) if nb is not None]
+        for iy, ix in rows_of:
+            blk = O.element_rows(grid, iy, ix).get((jy, jx))
+            if blk is None:
+                continue
+            ui = uL[grid.eid(iy, ix) * n2:(grid.eid(iy, ix) + 1) * n2]
+            acc += blk.T @ ui
+            scale += np.abs(blk).T @ np.abs(ui)
+        worst = max(worst, float(np.max(np.abs(acc) / scale)))
+    return worst
+
+
 def test_c5_full_size_mixed_8rhs():
     w = wl.workload("c5")
     print("[gpu-c5] setup 128x128 n=16 stretched", flush=True)
@@ -135,8 +155,17 @@ def test_c5_full_size_mixed_8rhs():
     # (most stretched) column and the interior
     grid = O.Grid(w.n, w.x_breaks, w.y_breaks)
     T = O.boundary_operator(grid)
-    uL, _ = ctx.null_vectors()
+    uL, uS = ctx.null_vectors()
     elems = [(0, 0), (0, 127), (127, 0), (127, 127), (64, 0), (0, 64), (64, 1), (31, 97), (100, 12)]
+    # the null vectors: the restarted null-vector solve's reported residual, the
+    # transposed Schur apply of u_S, and u_L^T L = 0 on the columns of the sampled
+    # elements, summed from the oracle's element rows of the element and its neighbours
+    st = ctx.stats()
+    print(f"[gpu-c5] null residual {st['null_residual']:.2e} after {st['null_iterations']} iterations", flush=True)
+    assert 0 <= st["null_residual"] <= 1e-12
+    sty = ctx.schur_apply(dev(uS), transpose=True).cpu().numpy()[0]
+    assert np.linalg.norm(sty) <= 1e-12 * st["schur_norm_bound"]
+    assert _left_null_error_at(grid, uL, elems) <= 1e-9
     for c in (0, 5):
         rhs = F[c] + T @ G[c]
         ft = rhs - uL * (uL @ rhs)
