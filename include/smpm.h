@@ -268,6 +268,22 @@ int smpm_precond_apply(smpm_ctx *ctx, const double *x, double *y, int nrhs, int 
 int smpm_project(smpm_ctx *ctx, int which, const double *in, double *out, int nrhs,
                  int transpose, void *stream);
 
+/* smpm_project without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels in the same order as smpm_project (identical results),
+ * with their scratch (the Schur product, interface sums, coarse solution and
+ * substructured-solve scratch, dot partials) in a static device array of 32 MiB per
+ * GPU instead of the context's workspace.  Calls no hipMalloc/hipFree.
+ * Limits: SMPM_EINVAL if the call needs more than 32 MiB of scratch (about
+ * (k + 2 d) nrhs doubles plus small terms; e.g. up to 3 columns on a 128 x 128,
+ * n = 16 grid), and for SMPM_PROJ_L / SMPM_PROJ_S (not transposed) before the null
+ * vectors exist (smpm_null_vectors or smpm_solve computes them; that allocates).
+ * All contexts on one GPU share the array: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be ordered by the caller.  in == out is
+ * allowed. */
+int smpm_project_noalloc(smpm_ctx *ctx, int which, const double *in, double *out, int nrhs,
+                         int transpose, void *stream);
+
 /* Solves L u = f~ for nrhs right-hand sides by Algorithm 3 (Sec. 2):
  * f~ = (I - u_L u_L^T)(f + T g), b_S = B A^{-1} f~ projected out of u_S, GMRES
  * on P S M^{-1}, x = Q M^{-1} x_1 + Z G Z^T b_hat, u = A^{-1}(f~ - E x), and the

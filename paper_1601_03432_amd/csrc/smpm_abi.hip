@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -914,6 +915,105 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   return SMPM_OK;
 }
 
+// ---------------------------------------------------------------- static scratch
+
+// Device scratch of smpm_project_noalloc: a file-scope array, one copy per GPU, held
+// until the process ends.  Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol): its device address is looked up
+// once per device with hipGetSymbolAddress (at context setup, with the device
+// current) and that pointer is used for every launch.
+constexpr size_t kNoAllocScratchDoubles = (size_t)4 << 20;  // 32 MiB
+__device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Resolves (once per device) and returns the device address of `scratch` on device
+// `dev`, which must be the current device.
+int noalloc_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SMPM_EINVAL, "device id out of range for the static scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SMPM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return SMPM_OK;
+}
+
+// Scratch of a projection: the Schur product t (k x nrhs), the interface sums c and
+// the coarse solution c2 (d x nrhs each), the dot partials and the dots.
+struct ProjScratch {
+  double *t, *c, *c2, *part, *scal;
+};
+
+int project_impl(smpm_ctx* c, const DevPlan& P, const ProjScratch& sc, int which, const double* in, double* out,
+                 int nrhs, bool tr, hipStream_t s) {
+  if ((which == SMPM_PROJ_P || which == SMPM_PROJ_Q) && !c->plan.has_coarse)
+    return fail(SMPM_EINVAL, "no coarse space on this grid");
+  switch (which) {
+    case SMPM_PROJ_L: {
+      const double* u = tr ? c->rhat : c->uL;
+      launch_mdot(u, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, sc.part, sc.scal, nullptr, s);
+      launch_axpy_shared(in, P.r, u, sc.scal, 1.0, out, P.r, nrhs, s);
+      break;
+    }
+    case SMPM_PROJ_S: {
+      const double* u = tr ? c->v0hat : c->uS;
+      launch_mdot(u, 0, 0, 1, in, P.k, nullptr, P.k, nrhs, sc.part, sc.scal, nullptr, s);
+      launch_axpy_shared(in, P.k, u, sc.scal, 1.0, out, P.k, nrhs, s);
+      break;
+    }
+    case SMPM_PROJ_MEAN: {
+      // x - 1 (w^T x)/(w^T 1); transposed: x - w (1^T x)/(w^T 1)
+      if (!tr) {
+        launch_mdot(c->wq, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, sc.part, sc.scal, nullptr, s);
+        launch_axpy_shared(in, P.r, c->ones, sc.scal, 1.0 / c->wsum, out, P.r, nrhs, s);
+      } else {
+        launch_mdot(c->ones, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, sc.part, sc.scal, nullptr, s);
+        launch_axpy_shared(in, P.r, c->wq, sc.scal, 1.0 / c->wsum, out, P.r, nrhs, s);
+      }
+      break;
+    }
+    case SMPM_PROJ_P: {
+      // P x = x - S Z G Z^T x;  P^T x = x - Z G^T Z^T S^T x
+      if (!tr) {
+        launch_iface_sum(P, in, sc.c, nrhs, nullptr, s);
+        launch_coarse(P, sc.c, sc.c2, nrhs, false, nullptr, s);
+        launch_prolong(P, in, sc.c2, out, nrhs, 1, -1.0, nullptr, s);
+      } else {
+        launch_schur(P, in, sc.t, nrhs, true, nullptr, s);
+        launch_iface_sum(P, sc.t, sc.c, nrhs, nullptr, s);
+        launch_coarse(P, sc.c, sc.c2, nrhs, true, nullptr, s);
+        launch_prolong(P, in, sc.c2, out, nrhs, 0, -1.0, nullptr, s);
+      }
+      break;
+    }
+    case SMPM_PROJ_Q: {
+      // Q x = x - Z G Z^T S x;  Q^T x = x - S^T Z G^T Z^T x
+      if (!tr) {
+        launch_schur(P, in, sc.t, nrhs, false, nullptr, s);
+        launch_iface_sum(P, sc.t, sc.c, nrhs, nullptr, s);
+        launch_coarse(P, sc.c, sc.c2, nrhs, false, nullptr, s);
+        launch_prolong(P, in, sc.c2, out, nrhs, 0, -1.0, nullptr, s);
+      } else {
+        launch_iface_sum(P, in, sc.c, nrhs, nullptr, s);
+        launch_coarse(P, sc.c, sc.c2, nrhs, true, nullptr, s);
+        launch_prolong(P, in, sc.c2, out, nrhs, 2, -1.0, nullptr, s);
+      }
+      break;
+    }
+    default:
+      return fail(SMPM_EINVAL, "unknown projection");
+  }
+  HIPCHK(hipGetLastError());
+  return SMPM_OK;
+}
+
+
 bool aliases(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
@@ -979,7 +1079,9 @@ int smpm_setup_robin(int m_y, int m_x, int n, const double* xb, const double* yb
     return fail(SMPM_EHIP, "no HIP device");
   }
   c->device = true;
-  rc = do_upload(c, s);
+  double* scr = nullptr;
+  rc = noalloc_scratch(c->dev_id, &scr);  // the static scratch's address on this device
+  if (!rc) rc = do_upload(c, s);
   if (rc) {
     std::string keep = g_err;
     delete c;
@@ -1343,71 +1445,54 @@ int smpm_project(smpm_ctx* c, int which, const double* in, double* out, int nrhs
   rc = ensure_ws(c, nrhs, 1);
   if (rc) return rc;
   Workspace& W = c->ws;
-  const DevPlan& P = c->dp;
   const bool tr = transpose != 0;
   if ((which == SMPM_PROJ_L || which == SMPM_PROJ_S) && !tr) {
     rc = compute_null_vectors(c, s);
     if (rc) return rc;
   }
-  if ((which == SMPM_PROJ_P || which == SMPM_PROJ_Q) && !c->plan.has_coarse)
-    return fail(SMPM_EINVAL, "no coarse space on this grid");
-  switch (which) {
-    case SMPM_PROJ_L: {
-      const double* u = tr ? c->rhat : c->uL;
-      launch_mdot(u, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, W.part, W.scal, nullptr, s);
-      launch_axpy_shared(in, P.r, u, W.scal, 1.0, out, P.r, nrhs, s);
-      break;
-    }
-    case SMPM_PROJ_S: {
-      const double* u = tr ? c->v0hat : c->uS;
-      launch_mdot(u, 0, 0, 1, in, P.k, nullptr, P.k, nrhs, W.part, W.scal, nullptr, s);
-      launch_axpy_shared(in, P.k, u, W.scal, 1.0, out, P.k, nrhs, s);
-      break;
-    }
-    case SMPM_PROJ_MEAN: {
-      // x - 1 (w^T x)/(w^T 1); transposed: x - w (1^T x)/(w^T 1)
-      if (!tr) {
-        launch_mdot(c->wq, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, W.part, W.scal, nullptr, s);
-        launch_axpy_shared(in, P.r, c->ones, W.scal, 1.0 / c->wsum, out, P.r, nrhs, s);
-      } else {
-        launch_mdot(c->ones, 0, 0, 1, in, P.r, nullptr, P.r, nrhs, W.part, W.scal, nullptr, s);
-        launch_axpy_shared(in, P.r, c->wq, W.scal, 1.0 / c->wsum, out, P.r, nrhs, s);
-      }
-      break;
-    }
-    case SMPM_PROJ_P: {
-      // P x = x - S Z G Z^T x;  P^T x = x - Z G^T Z^T S^T x
-      if (!tr) {
-        launch_iface_sum(P, in, W.c, nrhs, nullptr, s);
-        launch_coarse(P, W.c, W.c2, nrhs, false, nullptr, s);
-        launch_prolong(P, in, W.c2, out, nrhs, 1, -1.0, nullptr, s);
-      } else {
-        launch_schur(P, in, W.t, nrhs, true, nullptr, s);
-        launch_iface_sum(P, W.t, W.c, nrhs, nullptr, s);
-        launch_coarse(P, W.c, W.c2, nrhs, true, nullptr, s);
-        launch_prolong(P, in, W.c2, out, nrhs, 0, -1.0, nullptr, s);
-      }
-      break;
-    }
-    case SMPM_PROJ_Q: {
-      // Q x = x - Z G Z^T S x;  Q^T x = x - S^T Z G^T Z^T x
-      if (!tr) {
-        launch_schur(P, in, W.t, nrhs, false, nullptr, s);
-        launch_iface_sum(P, W.t, W.c, nrhs, nullptr, s);
-        launch_coarse(P, W.c, W.c2, nrhs, false, nullptr, s);
-        launch_prolong(P, in, W.c2, out, nrhs, 0, -1.0, nullptr, s);
-      } else {
-        launch_iface_sum(P, in, W.c, nrhs, nullptr, s);
-        launch_coarse(P, W.c, W.c2, nrhs, true, nullptr, s);
-        launch_prolong(P, in, W.c2, out, nrhs, 2, -1.0, nullptr, s);
-      }
-      break;
-    }
-    default:
-      return fail(SMPM_EINVAL, "unknown projection");
+  ProjScratch sc{W.t, W.c, W.c2, W.part, W.scal};
+  return project_impl(c, c->dp, sc, which, in, out, nrhs, tr, s);
+}
+
+int smpm_project_noalloc(smpm_ctx* c, int which, const double* in, double* out, int nrhs, int transpose,
+                         void* stream) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!in || !out || nrhs < 1) return fail(SMPM_EINVAL, "bad vector arguments");
+  if (which < SMPM_PROJ_L || which > SMPM_PROJ_MEAN) return fail(SMPM_EINVAL, "unknown projection");
+  const bool tr = transpose != 0;
+  if ((which == SMPM_PROJ_L || which == SMPM_PROJ_S) && !tr && !c->have_null)
+    return fail(SMPM_EINVAL,
+                "the null vectors are not computed yet (computing them allocates): call smpm_null_vectors or "
+                "smpm_solve on this context first");
+  const Plan& Pl = c->plan;
+  // scratch layout per call: [t: k x nrhs][c: d x nrhs][c2: d x nrhs][coarse: cstride x nrhs]
+  // [partials: chunks x nrhs][dots: nrhs], each part 32-double aligned
+  auto up = [](int64_t v) { return (v + 31) / 32 * 32; };
+  const int64_t R = nrhs, d = std::max<int64_t>(Pl.d, 1);
+  int64_t cstride = 0;
+  if (Pl.coarse_mode == 2)
+    cstride = (int64_t)Pl.sub.B.size() + (int64_t)Pl.sub.npatch * Pl.sub.border + Pl.sub.nsep + Pl.sub.border + 1;
+  const int64_t nch = reduce_chunks(std::max<int64_t>(Pl.r, Pl.k));
+  const int64_t o_t = 0, o_c = o_t + up(Pl.k * R), o_c2 = o_c + up(d * R), o_cws = o_c2 + up(d * R),
+                o_part = o_cws + up(std::max<int64_t>(cstride, 1) * R), o_scal = o_part + up(nch * R),
+                need = o_scal + up(R);
+  if (need > (int64_t)kNoAllocScratchDoubles) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "smpm_project_noalloc: %lld doubles of scratch needed, the static maximum is %lld (%d MiB); "
+                  "use fewer columns per call or smpm_project",
+                  (long long)need, (long long)kNoAllocScratchDoubles, (int)(kNoAllocScratchDoubles * 8 >> 20));
+    return fail(SMPM_EINVAL, buf);
   }
-  HIPCHK(hipGetLastError());
-  return SMPM_OK;
+  double* base = nullptr;
+  rc = noalloc_scratch(c->dev_id, &base);
+  if (rc) return rc;
+  DevPlan P = c->dp;  // the substructured coarse solve reads its scratch through the plan view
+  P.cws = base + o_cws;
+  P.cws_stride = cstride;
+  ProjScratch sc{base + o_t, base + o_c, base + o_c2, base + o_part, base + o_scal};
+  return project_impl(c, P, sc, which, in, out, nrhs, tr, static_cast<hipStream_t>(stream));
 }
 
 int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrhs, const smpm_solve_opts* opts_in,

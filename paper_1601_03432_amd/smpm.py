@@ -32,7 +32,7 @@ ABI_SYMBOLS = (
     "smpm_node_coords", "smpm_quadrature_weights", "smpm_export", "smpm_null_vectors",
     "smpm_schur_apply", "smpm_schur_apply_prec", "smpm_precond_apply", "smpm_project", "smpm_solve",
     "smpm_boundary_transpose", "smpm_autotune", "smpm_solve_group",
-    "smpm_last_error",
+    "smpm_project_noalloc", "smpm_last_error",
 )
 
 
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     lib.smpm_schur_apply_prec.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]
     lib.smpm_precond_apply.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp]
     lib.smpm_project.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
+    lib.smpm_project_noalloc.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
     lib.smpm_solve.argtypes = [vp, vp, vp, vp, C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     lib.smpm_boundary_transpose.argtypes = [vp, vp, vp, C.c_int, vp]
     lib.smpm_autotune.argtypes = [vp, C.c_int, vp, C.POINTER(TuneResult)]
@@ -313,6 +314,22 @@ class Context:
         out = torch.empty_like(x)
         _check(self._lib.smpm_project(self._h, which, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
                                       x.shape[0], int(transpose), _stream(torch, stream)))
+        return out
+
+    def project_noalloc(self, which, x, out, transpose=False, stream=None):
+        """smpm_project_noalloc: the projection into a preallocated `out` (same shape as
+        x, contiguous (columns, length) CUDA float64; may be x itself) with the library's
+        static scratch instead of its workspace (no device allocation)."""
+        import torch
+        length = self.r if which in (PROJ_L, PROJ_MEAN) else self.k
+        for t in (x, out):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                    and t.dim() == 2 and t.shape[1] == length and t.is_contiguous()):
+                raise ValueError(f"expected contiguous CUDA float64 tensors of shape (columns, {length})")
+        if out.shape != x.shape:
+            raise ValueError("out must match x in shape")
+        _check(self._lib.smpm_project_noalloc(self._h, which, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                              x.shape[0], int(transpose), _stream(torch, stream)))
         return out
 
     def solve(self, f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64, transpose=False,
