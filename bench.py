@@ -41,19 +41,21 @@ HBM_PEAK_GBS = 8000.0
 # plain kernel of known size (FETCH_SIZE reads half of a 64 MiB elementwise read,
 # so x2.0; WRITE_SIZE matches a 64 MiB fill, x1.0).  Valid only for the kernel
 # source it was measured on (sha256 of the Schur section below); otherwise null.
-SCHUR_TRAFFIC = {"fetch_kib": 38203.7, "write_kib": 65024.0,
-                 "kernels_sha256": "32e089a2710ebfc6c13617adc8b743ee4dac2ad6adc3438b17be1b5caf30630d"}
+SCHUR_TRAFFIC = {"fetch_kib": 36565.6, "write_kib": 65024.0,
+                 "kernels_sha256": "53deb40964168ebb0fcbe34120be1a09179a4ce398415059bf339da90bab6ff4"}
 
 
 def kernels_sha256():
-    """sha256 of the metric kernel's source: the matrix-core Schur apply section of
-    csrc/smpm_kernels.hip (its helpers and k_schur_mfma)."""
+    """sha256 of the metric kernel's source: the matrix-core helpers of the Schur
+    apply section of csrc/smpm_kernels.hip and the column-pipelined kernel."""
     import hashlib
     path = os.path.join(ROOT, "paper_1601_03432_amd", "csrc", "smpm_kernels.hip")
     txt = open(path).read()
     a = txt.index("// ------------------------------------------------------------------ Schur apply on matrix cores")
-    b = txt.index("// Persistent, software-pipelined variant")
-    return hashlib.sha256(txt[a:b].encode()).hexdigest()
+    b = txt.index("// KT = 4-deep steps (4*KT >= 4n")
+    c = txt.index("// Column-pipelined variant (no side sums)")
+    d = txt.index("// Warp-specialized persistent variant (no side sums)")
+    return hashlib.sha256((txt[a:b] + txt[c:d]).encode()).hexdigest()
 
 
 def graph_time_us(launch, launches, replays=20):
@@ -87,9 +89,11 @@ def graph_time_us(launch, launches, replays=20):
     return start.elapsed_time(end) * 1e3 / (replays * launches)
 
 
-def rotated_schur_us(ctx, ncol, pool_bytes=600e6):
+def rotated_schur_us(ctx, ncol, pool_bytes=600e6, precision=None):
     """Average Schur-apply launch time over (v, Sv) buffer pairs rotated so that
-    the pool exceeds the 256 MB Infinity Cache: every launch streams from HBM."""
+    the pool exceeds the 256 MB Infinity Cache: every launch streams from HBM.
+    precision: None for smpm_schur_apply (FP64), else the operator precision of
+    smpm_schur_apply_prec."""
     import torch
     nbuf = max(2, int(np.ceil(pool_bytes / (2 * ncol * ctx.k * 8))))
     ins = [torch.randn(ncol, ctx.k, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
@@ -98,7 +102,10 @@ def rotated_schur_us(ctx, ncol, pool_bytes=600e6):
 
     def one():
         i = it["i"] % nbuf
-        ctx.schur_apply_into(ins[i], outs[i])
+        if precision is None:
+            ctx.schur_apply_into(ins[i], outs[i])
+        else:
+            ctx.schur_apply_prec(ins[i], outs[i], precision)
         it["i"] += 1
 
     us = graph_time_us(one, nbuf, replays=max(4, 200 // nbuf))
@@ -107,10 +114,13 @@ def rotated_schur_us(ctx, ncol, pool_bytes=600e6):
 
 def c5_context(smpm, w5):
     """The large stretched grid's context with the metric kernel's launch shape fixed
-    (plain matrix-core kernel, 4 columns per workgroup: the fastest shape for 8
-    columns in the autotuner's timings), so every run times the same kernel."""
-    saved = {k: os.environ.get(k) for k in ("SMPM_SCHUR_NC", "SMPM_SCHUR_PERSIST")}
-    os.environ["SMPM_SCHUR_NC"], os.environ["SMPM_SCHUR_PERSIST"] = "4", "-1"
+    (the column-pipelined matrix-core kernel, one tile and 8 columns per workgroup:
+    the fastest shape for 8 columns in the autotuner's timings), so every run times
+    the same kernel."""
+    keys = ("SMPM_SCHUR_NC", "SMPM_SCHUR_PERSIST", "SMPM_SCHUR_CPW")
+    saved = {k: os.environ.get(k) for k in keys}
+    os.environ.pop("SMPM_SCHUR_NC", None)
+    os.environ["SMPM_SCHUR_PERSIST"], os.environ["SMPM_SCHUR_CPW"] = "3", "8"
     try:
         return smpm.Context.from_workload(w5)
     finally:
@@ -121,21 +131,31 @@ def c5_context(smpm, w5):
                 os.environ[k] = v
 
 
-def schur_roofline(ctx5, ncol=8):
+def schur_roofline(ctx5, ncol=8, precision=None):
     """The metric kernel: the FP64 Schur apply t = S y on the large stretched grid
     (128 x 128 elements, n = 16) for its 8 right-hand sides, launched as
-    k_schur_mfma<false,16,4,double,true> (the standalone apply, output written with
-    non-temporal stores).  Algorithmic bytes per launch: each column's y
-    read and t written once (2 k 8 B per column) plus every distinct element operator
-    once."""
-    us, nbuf = rotated_schur_us(ctx5, ncol)
-    alg_bytes = 2 * ncol * ctx5.k * 8 + ctx5.stats()["schur_operator_bytes"]
+    k_schur_cols<false,16,8,double,true> (the standalone apply, output written with
+    non-temporal stores).  Algorithmic bytes per launch: each column's y read and t
+    written once (2 k 8 B per column) plus every distinct element operator once.
+    precision = MIXED_FP32 times the same kernel with the FP32 operator copies (FP32
+    matrix cores and accumulation, FP64 vectors), the mixed-precision solves' apply."""
+    from paper_1601_03432_amd import smpm
+    if precision is None or precision == smpm.FP64:
+        us, nbuf = rotated_schur_us(ctx5, ncol)
+        op_bytes = ctx5.stats()["schur_operator_bytes"]
+        kname = "k_schur_cols<false,16,8,double,true>"
+    else:
+        us, nbuf = rotated_schur_us(ctx5, ncol, precision=precision)
+        op_bytes = ctx5.stats()["schur_operator_bytes"] // 2
+        kname = "k_schur_cols<false,16,8,float,false>"
+    alg_bytes = 2 * ncol * ctx5.k * 8 + op_bytes
     achieved = alg_bytes / (us * 1e-6) / 1e9
     traffic = None
-    if SCHUR_TRAFFIC and SCHUR_TRAFFIC.get("kernels_sha256") == kernels_sha256():
+    if (precision is None or precision == smpm.FP64) and SCHUR_TRAFFIC \
+            and SCHUR_TRAFFIC.get("kernels_sha256") == kernels_sha256():
         traffic = 1024 * (2.0 * SCHUR_TRAFFIC["fetch_kib"] + 1.0 * SCHUR_TRAFFIC["write_kib"])
-    return {"kernel": "k_schur_mfma<false,16,4,double,true> (Schur apply, 128x128 n=16 stretched grid, %d columns, %d rotated buffer "
-                              "pairs)" % (ncol, nbuf),
+    return {"kernel": "%s (Schur apply, 128x128 n=16 stretched grid, %d columns, %d rotated buffer pairs)"
+                      % (kname, ncol, nbuf),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes, "avg_launch_us": us}
@@ -182,7 +202,8 @@ def main():
     ctx5 = None if (args.no_large or args.headline_only) and not (args.roofline_only or args.large_single_only) \
         else c5_context(smpm, w5)
     if args.roofline_only:
-        print(json.dumps({"roofline": schur_roofline(ctx5)}), flush=True)
+        print(json.dumps({"roofline": schur_roofline(ctx5),
+                          "roofline_fp32_operators": schur_roofline(ctx5, precision=smpm.MIXED_FP32)}), flush=True)
         return
 
     def solve_fp64(rhs):
@@ -317,6 +338,7 @@ def main():
 
     if not args.no_large:
         out["roofline"] = schur_roofline(ctx5)
+        out["roofline_fp32_operators"] = schur_roofline(ctx5, precision=smpm.MIXED_FP32)
         us1, _ = rotated_schur_us(ctx5, 1)
         b1 = 2 * ctx5.k * 8 + ctx5.stats()["schur_operator_bytes"]
         out["schur_c5_1col"] = {"avg_launch_us": us1, "GB_s": b1 / (us1 * 1e-6) / 1e9,

@@ -167,7 +167,9 @@ typedef struct smpm_tune_result {
   int nrhs;                          /* column count the choice was made for (its class:
                                         1, 2-3, 4-7 or >= 8 columns)                         */
   int schur_columns_per_workgroup;   /* right-hand-side columns one Schur workgroup takes     */
-  int schur_persistent;              /* 1: persistent pipelined Schur kernel                  */
+  int schur_persistent;              /* Schur kernel: 0 plain matrix-core kernel, 1 persistent
+                                        pipelined, 2 warp-specialized persistent, 3 column-
+                                        pipelined (one tile, its columns one after another)  */
   int prereduce;                     /* 1: Gram-Schmidt sums reduced once per column; 0: in
                                         every consumer block; -1: not tuned (no coarse space) */
   double schur_us;                   /* measured Schur apply time of the choice               */
@@ -316,7 +318,9 @@ int smpm_solve_group(smpm_ctx *const *ctxs, int nproblems, const double *const *
 
 /* Autotuner: times, on `stream`, the candidate launch shapes of the Schur apply
  * (1, 2 or 4 right-hand-side columns per workgroup of the plain matrix-core kernel,
- * or the persistent pipelined kernel) and the two ways of reducing the Gram-Schmidt
+ * the persistent pipelined kernel, the warp-specialized persistent kernel, or the
+ * column-pipelined kernel with 2, 4 or 8 columns per workgroup) and the two ways of
+ * reducing the Gram-Schmidt
  * sums (24 deflated Arnoldi steps each) for `nrhs` columns on this context's grid,
  * and keeps the fastest for every later call with a column count of the same class.
  * Every candidate computes each column with the same arithmetic in the same order,

@@ -859,7 +859,13 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   for (int q = 0; q < 4; ++q) d.schur_nc[q] = 0;
   for (int q = 0; q < 4; ++q) d.schur_pers[q] = 0;
   if (const char* e = std::getenv("SMPM_SCHUR_PERSIST"))  // sweep hook
-    for (int q = 0; q < 4; ++q) d.schur_pers[q] = std::atoi(e) > 0 ? 1 : std::atoi(e) < 0 ? -1 : 0;
+    for (int q = 0; q < 4; ++q) {
+      const int v = std::atoi(e);
+      d.schur_pers[q] = v >= 3 ? 3 : v == 2 ? 2 : v > 0 ? 1 : v < 0 ? -1 : 0;
+    }
+  for (int q = 0; q < 4; ++q) d.schur_cpw[q] = 0;
+  if (const char* e = std::getenv("SMPM_SCHUR_CPW"))  // sweep hook: columns per workgroup (column-pipelined)
+    for (int q = 0; q < 4; ++q) d.schur_cpw[q] = std::max(0, std::min(64, std::atoi(e)));
   {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->dev_id) != hipSuccess || ncu <= 0)
@@ -1357,18 +1363,23 @@ int smpm_autotune(smpm_ctx* c, int nrhs, void* stream, smpm_tune_result* out) {
   };
   // 1. Schur launch shape, timed as the deflated Arnoldi step launches it (with the
   //    fused per-side sums where the dense coarse solve consumes them): the plain
-  //    kernel with 1, 2 or 4 columns per workgroup, or the persistent kernel
+  //    kernel with 1, 2 or 4 columns per workgroup, the persistent kernel, the
+  //    warp-specialized persistent kernel (1 or 2 columns per item) or the
+  //    column-pipelined kernel (2, 4 or 8 columns per workgroup); the last three have
+  //    no side sums
   const bool fused = schur_has_side_sums(P) && P.coarse_mode == 1;
-  struct Cand { int pers, nc; };
-  const Cand cands[] = {{-1, 1}, {-1, 2}, {-1, 4}, {1, 0}};
+  struct Cand { int pers, nc, cpw; };
+  const Cand cands[] = {{-1, 1, 0}, {-1, 2, 0}, {-1, 4, 0}, {1, 0, 0}, {2, 1, 0},
+                        {2, 2, 0},  {3, 0, 2},  {3, 0, 4},  {3, 0, 8}};
   float best = 1e30f;
-  Cand pick{P.schur_pers[cls], P.schur_nc[cls]};
+  Cand pick{P.schur_pers[cls], P.schur_nc[cls], P.schur_cpw[cls]};
   if (P.mma_mt > 0) {
     for (const Cand& cd : cands) {
-      if (cd.nc > nrhs) continue;
-      if (cd.pers > 0 && fused) continue;  // the persistent kernel has no side sums
+      if (cd.nc > nrhs || (cd.cpw > 1 && cd.cpw / 2 >= nrhs)) continue;
+      if (cd.pers > 0 && fused) continue;
       P.schur_pers[cls] = cd.pers;
       P.schur_nc[cls] = cd.nc;
+      P.schur_cpw[cls] = cd.cpw;
       const float us =
           time_us([&] { launch_schur_ex(P, W.xacc, W.t, nrhs, false, nullptr, fused ? W.sides : nullptr, s); }, 20);
       if (us < best) {
@@ -1378,6 +1389,7 @@ int smpm_autotune(smpm_ctx* c, int nrhs, void* stream, smpm_tune_result* out) {
     }
     P.schur_pers[cls] = pick.pers;
     P.schur_nc[cls] = pick.nc;
+    P.schur_cpw[cls] = pick.cpw;
   }
   c->drop_graphs();  // captured steps hold the launch shapes they were recorded with
   rc = hipGetLastError() == hipSuccess ? SMPM_OK : fail(SMPM_EHIP, "Schur timing launch failed");
@@ -1406,8 +1418,10 @@ int smpm_autotune(smpm_ctx* c, int nrhs, void* stream, smpm_tune_result* out) {
   if (rc != SMPM_OK) return rc;
   if (out) {
     out->nrhs = nrhs;
-    out->schur_columns_per_workgroup = pick.pers > 0 ? (nrhs >= 2 ? 2 : 1) : (pick.nc > 0 ? pick.nc : 1);
-    out->schur_persistent = pick.pers > 0 ? 1 : 0;
+    out->schur_columns_per_workgroup = pick.pers == 3   ? std::min(pick.cpw, nrhs)
+                                       : pick.pers == 1 ? (nrhs >= 2 ? 2 : 1)
+                                                        : (pick.nc > 0 ? pick.nc : 1);
+    out->schur_persistent = pick.pers > 0 ? pick.pers : 0;
     out->prereduce = pre_pick;
     out->schur_us = best < 1e29f ? best : 0.0;
     out->step_us = best_step < 1e29f ? best_step : 0.0;

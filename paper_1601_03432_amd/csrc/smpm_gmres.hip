@@ -216,7 +216,9 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
     hc[jc + 1] = beta;
     // the entry carried from rotation i to i + 1 stays in a register; the operands
     // of B rotations are loaded before they are applied (rotation i reads hc[i + 1],
-    // which only rotation i + 1 writes).  The same operations whatever B.
+    // which only rotation i + 1 writes).  The same operations whatever B: the fused
+    // multiply-adds are written out, so no instantiation is left to contract
+    // c a + s b differently.
     double a = hc[0];
     for (int i0 = 0; i0 < jc; i0 += B) {
       double bb[B], ci[B], si[B];
@@ -230,8 +232,9 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
 #pragma unroll
       for (int u = 0; u < B; ++u)
         if (i0 + u < jc) {
-          hc[i0 + u] = ci[u] * a + si[u] * bb[u];
-          a = -si[u] * a + ci[u] * bb[u];
+          const double sb = si[u] * bb[u], sa = si[u] * a;
+          hc[i0 + u] = fma(ci[u], a, sb);
+          a = fma(ci[u], bb[u], -sa);
         }
     }
     const double b = beta;
@@ -247,7 +250,10 @@ __device__ void givens_column(const GmState& S, int col, int j, double beta, con
     gc[jc] = c * gj;
     const double res = fabs(gc[jc + 1]);
     S.res[col] = res;
-    if (!(res > S.tolb[col]) || j >= S.maxit || !(beta > 0.0)) {
+    // a column retires once its estimate meets the threshold, at maxit, on a breakdown,
+    // or when the estimate is not finite (iterating on NaN is useless; the host's FP64
+    // true residual then reports the column as not converged)
+    if (res <= S.tolb[col] || !isfinite(res) || j >= S.maxit || !(beta > 0.0)) {
       S.active[col] = 0;
       S.iters[col] = j;
     }

@@ -95,7 +95,9 @@ struct DevPlan {
   int schur_nc[4];         // right-hand-side columns per Schur workgroup for 1, 2-3, 4-7 and
                            // >= 8 columns (0: built-in choice); set by the autotuner
   int schur_pers[4];       // persistent Schur apply per column-count class: -1 never, 0 when
-                           // items >= 2x resident workgroups, 1 always (no side sums)
+                           // items >= 2x resident workgroups, 1 always, 2 the warp-specialized
+                           // persistent kernel, 3 the column-pipelined kernel (no side sums)
+  int schur_cpw[4];        // columns per workgroup of the column-pipelined kernel (0: 8)
   int num_cu;              // compute units of the device
   const double* Afwd;      // [cls][w][q][lane] fragments of W (forward) and W^T (transpose)
   const double* Aadj;

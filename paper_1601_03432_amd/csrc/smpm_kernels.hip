@@ -539,6 +539,289 @@ __global__ __launch_bounds__(256) void k_schur_mfma_pers(DevPlan P, const double
   }
 }
 
+// Column-pipelined variant (no side sums): one workgroup per tile and group of up to
+// cpw columns, taken one column per pass.  The operator fragments and the tile's index
+// tables are loaded once; the gathers of column c+1 are issued before the products of
+// column c (the pass loop is unrolled, so the two register sets are indexed
+// statically), so each workgroup keeps loads in flight while its matrix cores run.  Y
+// tiles are double-buffered in LDS, the result tile has its own buffer; two barriers
+// per pass, the same count for every thread.  Every column gets the arithmetic of
+// k_schur_mfma.
+template <bool ADJ, int KT, int CPW, typename OpT, bool NTS>
+__global__ __launch_bounds__(256) void k_schur_cols(DevPlan P, const double* __restrict__ y,
+                                                    double* __restrict__ t, int nrhs,
+                                                    const int* __restrict__ active) {
+  using Acc = typename AccOf<OpT>::type;
+  using M = Mma<Acc>;
+  constexpr int kRows = 4 * KT;
+  constexpr int kPer = kTile * kRows / (16 * KT);  // staged values per thread (= 4)
+  constexpr int kBuf = kRows * kTileLd;
+  extern __shared__ double lds[];
+  Acc* ybuf = reinterpret_cast<Acc*>(lds);         // [2][kRows][kTileLd]
+  Acc* rbuf = ybuf + 2 * kBuf;                     // [kWaves][kTile][kTileLd]
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= P.ntile) return;
+  const int c0 = blockIdx.y * CPW;
+  const int passes = min(CPW, nrhs - c0);
+  if (passes <= 0) return;
+  const int n = P.n, no = 4 * n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int J = P.tile_cls[tile];
+  const int ns = P.cls_nslots[J];
+  const int kdim = ADJ ? no : ns;
+  const int* src = P.tile_src + tile * kTile;
+  const int* dst = P.tile_dst + tile * kTile * 4;
+  const OpT* Af = mma_op<OpT>(P, ADJ) + ((int64_t)(J * P.mma_mt + wave) * KT) * 64 + lane;
+  Acc a[KT];
+#pragma unroll
+  for (int q = 0; q < KT; ++q) a[q] = to_acc(Af[q * 64]);
+  const int row = lane & 15, mr = wave * 16 + row;
+  const int srow = min(mr / n, 3);
+  int tb[4], sb[kPer];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int uu = (lane >> 4) + 4 * v;
+    tb[v] = ADJ ? src[uu] : dst[uu * 4 + srow];
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int q = tid + j * 16 * KT;
+    const int uu = q / kRows, kk = q - uu * kRows;
+    sb[j] = ADJ ? dst[uu * 4 + min(kk / n, 3)] : src[uu];
+  }
+  const bool row_ok = ADJ ? mr < ns : mr < no;
+  int slot[4], gi[kPer];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) slot[v] = row_ok && tb[v] >= 0 ? tb[v] + (ADJ ? mr : mr - srow * n) : -1;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int q = tid + j * 16 * KT;
+    const int uu = q / kRows, kk = q - uu * kRows;
+    const int sd = kk / n;
+    const bool ok = sb[j] >= 0 && kk < kdim;
+    gi[j] = ok ? sb[j] + (ADJ ? kk - sd * n : kk) : -1;
+  }
+  // column loads into register set b (statically indexed after unrolling)
+  double st[2][kPer], yv[2][4];
+  auto load = [&](int c, int b) {
+    const double* yc = y + (int64_t)c * P.k;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) st[b][j] = yc[max(gi[j], 0)];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) yv[b][v] = yc[max(slot[v], 0)];
+  };
+  load(c0, 0);
+#pragma unroll
+  for (int p = 0; p < CPW; ++p) {
+    if (p >= passes) break;  // uniform over the workgroup
+    const int c = c0 + p, b = p & 1;
+    Acc* yb = ybuf + b * kBuf;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int q = tid + j * 16 * KT;
+      const int uu = q / kRows, kk = q - uu * kRows;
+      yb[kk * kTileLd + uu] = gi[j] >= 0 ? (Acc)st[b][j] : Acc(0);
+    }
+    // the next column's gathers fly during this column's products and stores
+    if (p + 1 < passes) load(c + 1, b ^ 1);
+    __syncthreads();
+    typename M::V acc = typename M::V{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < KT; ++q) acc = M::mma(a[q], yb[(4 * q + (lane >> 4)) * kTileLd + (lane & 15)], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rbuf[(wave * kTile + (lane & 15)) * kTileLd + M::row(lane, v)] = acc[v];
+    __syncthreads();
+    if (!active || active[c]) {
+      double* tc = t + (int64_t)c * P.k;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int uu = (lane >> 4) + 4 * v;
+        const double tv = yv[b][v] + (double)rbuf[(wave * kTile + uu) * kTileLd + row];
+        if (slot[v] >= 0) {
+          if constexpr (NTS)
+            __builtin_nontemporal_store(tv, &tc[slot[v]]);
+          else
+            tc[slot[v]] = tv;
+        }
+      }
+    }
+  }
+}
+
+// Warp-specialized persistent variant (no side sums): a workgroup of 2 x kWaves
+// wavefronts walks its (tile, column group) items as the persistent kernel does.
+// The first kWaves ("compute") run the matrix-core products of item s from one LDS
+// Y buffer into one LDS result buffer; meanwhile the other kWaves ("memory") store
+// the results of item s-1 (plus its identity term, loaded one step earlier), load
+// the identity-term values of item s and gather the Y tile of item s+1 into the
+// other Y buffer.  One barrier per step, count + 1 steps for count items, taken by
+// every wavefront.  The products and the loads and stores of neighbouring items so
+// overlap inside one workgroup; every column gets the arithmetic of k_schur_mfma.
+template <bool ADJ, int KT, int NC, typename OpT, bool NTS>
+__global__ __launch_bounds__(32 * KT) void k_schur_ws(DevPlan P, const double* __restrict__ y,
+                                                      double* __restrict__ t, int nrhs,
+                                                      const int* __restrict__ active, int ncg) {
+  using Acc = typename AccOf<OpT>::type;
+  using M = Mma<Acc>;
+  constexpr int kThr = 16 * KT;                    // threads of one role
+  constexpr int kRows = 4 * KT;
+  constexpr int kPer = kTile * kRows / kThr;       // staged values per thread and column (= 4)
+  constexpr int kWaves = KT / 4;
+  constexpr int kBuf = NC * kRows * kTileLd;       // one Y tile set (or result tile set)
+  extern __shared__ double lds[];
+  Acc* ybuf = reinterpret_cast<Acc*>(lds);         // [2][kBuf]
+  Acc* rbuf = ybuf + 2 * kBuf;                     // [2][kBuf]: [NC][kWaves][kTile][kTileLd]
+  const int n = P.n, no = 4 * n;
+  const bool mem = threadIdx.x >= kThr;
+  const int tid = (int)threadIdx.x - (mem ? kThr : 0), wave = tid >> 6, lane = tid & 63;
+  const int row = lane & 15, mr = wave * 16 + row;
+  const int srow = min(mr / n, 3);
+  const int64_t nitems = (int64_t)P.ntile * ncg;
+  const int xcd = blockIdx.x & 7, nbx = gridDim.x >> 3;
+  const int64_t hi = nitems * (xcd + 1) / 8;
+  const int64_t first = nitems * xcd / 8 + (blockIdx.x >> 3);
+  const int count = first < hi ? (int)((hi - first + nbx - 1) / nbx) : 0;
+  if (count == 0) return;  // uniform over the workgroup
+
+  // tables of item it (memory role): columns, output slots, gather indices
+  auto tables = [&](int64_t it, int& c0, bool (&on)[NC], int (&slot)[4], int (&gi)[kPer]) {
+    const int tile = (int)(it / ncg);
+    c0 = (int)(it - (int64_t)tile * ncg) * NC;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) on[c] = c0 + c < nrhs && (!active || active[c0 + c]);
+    const int J = P.tile_cls[tile];
+    const int ns = P.cls_nslots[J];
+    const int kdim = ADJ ? no : ns;
+    const int* src = P.tile_src + tile * kTile;
+    const int* dst = P.tile_dst + tile * kTile * 4;
+    int tb[4], sb[kPer];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int uu = (lane >> 4) + 4 * v;
+      tb[v] = ADJ ? src[uu] : dst[uu * 4 + srow];
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int q = tid + j * kThr;
+      const int uu = q / kRows, kk = q - uu * kRows;
+      sb[j] = ADJ ? dst[uu * 4 + min(kk / n, 3)] : src[uu];
+    }
+    const bool row_ok = ADJ ? mr < ns : mr < no;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) slot[v] = row_ok && tb[v] >= 0 ? tb[v] + (ADJ ? mr : mr - srow * n) : -1;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int q = tid + j * kThr;
+      const int uu = q / kRows, kk = q - uu * kRows;
+      const int s = kk / n;
+      const bool ok = sb[j] >= 0 && kk < kdim;
+      gi[j] = ok ? sb[j] + (ADJ ? kk - s * n : kk) : -1;
+    }
+  };
+  // gather the Y tile of an item into an LDS buffer as [c][kk][u]
+  auto gather = [&](int c0, const bool (&on)[NC], const int (&gi)[kPer], Acc* yb) {
+    double st[NC][kPer];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double* yc = y + (int64_t)(on[c] ? c0 + c : 0) * P.k;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) st[c][j] = yc[max(gi[j], 0)];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int q = tid + j * kThr;
+        const int uu = q / kRows, kk = q - uu * kRows;
+        yb[(c * kRows + kk) * kTileLd + uu] = gi[j] >= 0 ? (Acc)st[c][j] : Acc(0);
+      }
+  };
+
+  if (mem) {
+    // memory role: prologue gathers item 0; step s stores item s-1, loads the identity
+    // term of item s and gathers item s+1
+    int c0p = 0, c0c = 0;
+    bool onp[NC], onc[NC];
+    int slotp[4], slotc[4], gic[kPer];
+    double yv[NC][4];
+    tables(first, c0c, onc, slotc, gic);
+    gather(c0c, onc, gic, ybuf);
+    __syncthreads();
+    for (int s = 0; s <= count; ++s) {
+      if (s >= 1) {
+        const Acc* rb = rbuf + ((s - 1) & 1) * kBuf;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (!onp[c]) continue;
+          double* tc = t + (int64_t)(c0p + c) * P.k;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int uu = (lane >> 4) + 4 * v;
+            const double tv = yv[c][v] + (double)rb[((c * kWaves + wave) * kTile + uu) * kTileLd + row];
+            if (slotp[v] >= 0) {
+              if constexpr (NTS)
+                __builtin_nontemporal_store(tv, &tc[slotp[v]]);
+              else
+                tc[slotp[v]] = tv;
+            }
+          }
+        }
+      }
+      if (s < count) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double* yc = y + (int64_t)(onc[c] ? c0c + c : 0) * P.k;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) yv[c][v] = yc[max(slotc[v], 0)];
+        }
+        c0p = c0c;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) onp[c] = onc[c];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) slotp[v] = slotc[v];
+        if (s + 1 < count) {
+          tables(first + (int64_t)(s + 1) * nbx, c0c, onc, slotc, gic);
+          gather(c0c, onc, gic, ybuf + ((s + 1) & 1) * kBuf);
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    // compute role: products of item s from Y buffer s % 2 into result buffer s % 2
+    int Ja = -1;
+    Acc a[KT];
+    __syncthreads();
+    for (int s = 0; s <= count; ++s) {
+      if (s < count) {
+        const int tile = (int)((first + (int64_t)s * nbx) / ncg);
+        const int J = P.tile_cls[tile];
+        if (J != Ja) {  // uniform over the workgroup
+          const OpT* Af = mma_op<OpT>(P, ADJ) + ((int64_t)(J * P.mma_mt + wave) * KT) * 64 + lane;
+#pragma unroll
+          for (int q = 0; q < KT; ++q) a[q] = to_acc(Af[q * 64]);
+          Ja = J;
+        }
+        const Acc* yb = ybuf + (s & 1) * kBuf;
+        Acc* rb = rbuf + (s & 1) * kBuf;
+        typename M::V acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          acc[c] = typename M::V{0, 0, 0, 0};
+#pragma unroll
+          for (int q = 0; q < KT; ++q)
+            acc[c] = M::mma(a[q], yb[(c * kRows + 4 * q + (lane >> 4)) * kTileLd + (lane & 15)], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            rb[((c * kWaves + wave) * kTile + (lane & 15)) * kTileLd + M::row(lane, v)] = acc[c][v];
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------------------------ B A^{-1} and its transpose
 
 __global__ __launch_bounds__(64) void k_flux(DevPlan P, const double* __restrict__ f, double* __restrict__ b) {
@@ -1221,6 +1504,119 @@ static bool pers_prec(const DevPlan& P, const double* y, double* t, int nrhs, bo
   return pers_nc<KT, double>(P, y, t, nrhs, tr, active, s);
 }
 
+// Column-pipelined Schur apply (no side sums): one workgroup per (tile, group of cpw
+// columns, cpw = 1, 2, 4 or 8); cpw from the tuned value of the column-count class, else 8.
+template <int KT, typename T, bool NTS>
+static void cols_launch(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
+                        hipStream_t s, int cpw) {
+  const size_t lds = (size_t)3 * 4 * KT * kTileLd * sizeof(typename AccOf<T>::type);
+  const int c = cpw >= 8 ? 8 : cpw >= 4 ? 4 : cpw >= 2 ? 2 : 1;
+  const dim3 g((P.ntile + 7) / 8 * 8, (nrhs + c - 1) / c), b(16 * KT);
+#define SMPM_COLS_LAUNCH(C)                                                                                    \
+  if (transpose)                                                                                               \
+    hipLaunchKernelGGL((k_schur_cols<true, KT, C, T, NTS>), g, b, lds, s, P, y, t, nrhs, active);              \
+  else                                                                                                         \
+    hipLaunchKernelGGL((k_schur_cols<false, KT, C, T, NTS>), g, b, lds, s, P, y, t, nrhs, active);
+  if (c == 8) {
+    SMPM_COLS_LAUNCH(8)
+  } else if (c == 4) {
+    SMPM_COLS_LAUNCH(4)
+  } else if (c == 2) {
+    SMPM_COLS_LAUNCH(2)
+  } else {
+    SMPM_COLS_LAUNCH(1)
+  }
+#undef SMPM_COLS_LAUNCH
+}
+
+template <int KT>
+static void cols_prec(const DevPlan& P, const double* y, double* t, int nrhs, bool tr, const int* active,
+                      hipStream_t s, int prec, int cpw, bool nts) {
+  if (prec == PREC_F32)
+    cols_launch<KT, float, false>(P, y, t, nrhs, tr, active, s, cpw);
+  else if (prec == PREC_BF16)
+    cols_launch<KT, bf16s, false>(P, y, t, nrhs, tr, active, s, cpw);
+  else if (nts)
+    cols_launch<KT, double, true>(P, y, t, nrhs, tr, active, s, cpw);
+  else
+    cols_launch<KT, double, false>(P, y, t, nrhs, tr, active, s, cpw);
+}
+
+static void launch_schur_cols(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
+                              const int* active, hipStream_t s, int prec, bool nts) {
+  const int tuned = P.schur_cpw[schur_nc_class(nrhs)];
+  const int cpw = tuned > 0 ? tuned : 8;
+  switch (4 * P.mma_mt) {
+    case 4: cols_prec<4>(P, y, t, nrhs, transpose, active, s, prec, cpw, nts); break;
+    case 8: cols_prec<8>(P, y, t, nrhs, transpose, active, s, prec, cpw, nts); break;
+    case 12: cols_prec<12>(P, y, t, nrhs, transpose, active, s, prec, cpw, nts); break;
+    default: cols_prec<16>(P, y, t, nrhs, transpose, active, s, prec, cpw, nts); break;
+  }
+}
+
+// Warp-specialized persistent Schur apply (no side sums): one workgroup per resident
+// slot of the device, items (tile, column group) split over the XCDs.
+template <int KT, int NC, typename T, bool NTS>
+static void ws_launch(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
+                      hipStream_t s) {
+  const size_t lds = (size_t)4 * NC * 4 * KT * kTileLd * sizeof(typename AccOf<T>::type);
+  const int ncg = (nrhs + NC - 1) / NC;
+  const int64_t nitems = (int64_t)P.ntile * ncg;
+  static std::atomic<int> occ[2] = {0, 0};  // resident workgroups per CU, per direction
+  int oc = occ[transpose ? 1 : 0].load(std::memory_order_relaxed);
+  if (oc == 0) {
+    int v = 0;
+    const hipError_t e = transpose
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_schur_ws<true, KT, NC, T, NTS>, 32 * KT, lds)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_schur_ws<false, KT, NC, T, NTS>, 32 * KT, lds);
+    oc = (e == hipSuccess && v > 0) ? v : 1;
+    occ[transpose ? 1 : 0].store(oc, std::memory_order_relaxed);
+  }
+  int64_t blocks = std::min<int64_t>((int64_t)P.num_cu * oc, nitems);
+  blocks = (blocks + 7) / 8 * 8;
+  const dim3 g((unsigned)blocks), b(32 * KT);
+  if (transpose)
+    hipLaunchKernelGGL((k_schur_ws<true, KT, NC, T, NTS>), g, b, lds, s, P, y, t, nrhs, active, ncg);
+  else
+    hipLaunchKernelGGL((k_schur_ws<false, KT, NC, T, NTS>), g, b, lds, s, P, y, t, nrhs, active, ncg);
+}
+
+template <int KT, typename T, bool NTS>
+static void ws_nc(const DevPlan& P, const double* y, double* t, int nrhs, bool tr, const int* active,
+                  hipStream_t s, int nc) {
+  if (nc >= 4 && nrhs >= 4)
+    ws_launch<KT, 4, T, NTS>(P, y, t, nrhs, tr, active, s);
+  else if (nc >= 2 && nrhs >= 2)
+    ws_launch<KT, 2, T, NTS>(P, y, t, nrhs, tr, active, s);
+  else
+    ws_launch<KT, 1, T, NTS>(P, y, t, nrhs, tr, active, s);
+}
+
+template <int KT>
+static void ws_prec(const DevPlan& P, const double* y, double* t, int nrhs, bool tr, const int* active,
+                    hipStream_t s, int prec, int nc, bool nts) {
+  if (prec == PREC_F32)
+    ws_nc<KT, float, false>(P, y, t, nrhs, tr, active, s, nc);
+  else if (prec == PREC_BF16)
+    ws_nc<KT, bf16s, false>(P, y, t, nrhs, tr, active, s, nc);
+  else if (nts)
+    ws_nc<KT, double, true>(P, y, t, nrhs, tr, active, s, nc);
+  else
+    ws_nc<KT, double, false>(P, y, t, nrhs, tr, active, s, nc);
+}
+
+static void launch_schur_ws(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose,
+                            const int* active, hipStream_t s, int prec, bool nts) {
+  const int tuned = P.schur_nc[schur_nc_class(nrhs)];
+  const int nc = tuned > 0 ? tuned : 2;
+  switch (4 * P.mma_mt) {
+    case 4: ws_prec<4>(P, y, t, nrhs, transpose, active, s, prec, nc, nts); break;
+    case 8: ws_prec<8>(P, y, t, nrhs, transpose, active, s, prec, nc, nts); break;
+    case 12: ws_prec<12>(P, y, t, nrhs, transpose, active, s, prec, nc, nts); break;
+    default: ws_prec<16>(P, y, t, nrhs, transpose, active, s, prec, nc, nts); break;
+  }
+}
+
 bool launch_schur_pers(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
                        hipStream_t s, int prec) {
   switch (4 * P.mma_mt) {
@@ -1241,6 +1637,14 @@ void launch_schur(const DevPlan& P, const double* y, double* t, int nrhs, bool t
 void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, bool transpose, const int* active,
                      double* side_sums, hipStream_t s, int prec, bool stream_out) {
   if (transpose || !schur_has_side_sums(P)) side_sums = nullptr;
+  if (P.mma_mt > 0 && !side_sums && P.schur_pers[schur_nc_class(nrhs)] == 2) {
+    launch_schur_ws(P, y, t, nrhs, transpose, active, s, prec, stream_out);
+    return;
+  }
+  if (P.mma_mt > 0 && !side_sums && P.schur_pers[schur_nc_class(nrhs)] == 3) {
+    launch_schur_cols(P, y, t, nrhs, transpose, active, s, prec, stream_out);
+    return;
+  }
   if (P.mma_mt > 0 && !side_sums && P.schur_pers[schur_nc_class(nrhs)] >= 0 && launch_schur_pers(P, y, t, nrhs, transpose, active, s, prec))
     return;
   if (P.mma_mt > 0) {

@@ -77,3 +77,29 @@ def test_autotune_rejects_bad_column_count():
     ctx = _context(4, 6, False)
     with pytest.raises(smpm.SmpmError):
         ctx.autotune(0)
+
+
+@pytest.mark.parametrize("shape", [
+    (("SMPM_SCHUR_PERSIST", "1"),),
+    (("SMPM_SCHUR_PERSIST", "2"), ("SMPM_SCHUR_NC", "1")),
+    (("SMPM_SCHUR_PERSIST", "2"), ("SMPM_SCHUR_NC", "2")),
+    (("SMPM_SCHUR_PERSIST", "3"), ("SMPM_SCHUR_CPW", "4")),
+    (("SMPM_SCHUR_PERSIST", "3"), ("SMPM_SCHUR_CPW", "8")),
+    (("SMPM_PREREDUCE", "1"),),
+    (("SMPM_PREREDUCE", "0"),),
+], ids=["persistent", "ws_nc1", "ws_nc2", "cols_cpw4", "cols_cpw8", "prereduce1", "prereduce0"])
+def test_launch_shapes_give_identical_solves(shape, monkeypatch):
+    """Every Schur launch shape and either reduction of the Gram-Schmidt sums gives the
+    solutions of the default choice bit for bit (8 columns, substructured coarse
+    solve, the shape the autotuner may pick)."""
+    base = _context(16, 8, True)
+    F = _rhs(base, 700, 8)
+    kw = dict(tol=1e-11, maxit=600)
+    ref, info = base.solve(F, **kw)
+    for name, val in shape:
+        monkeypatch.setenv(name, val)
+    ctx = _context(16, 8, True)
+    u, info2 = ctx.solve(F, **kw)
+    diff = (u - ref).abs().max().item()
+    print(f"[gpu-autotune] {shape}: max |diff| {diff:.3e}, iterations {info2.iterations} vs {info.iterations}")
+    assert torch.equal(u, ref), (shape, diff)

@@ -8,8 +8,8 @@ grid); orders 17..32 take the vector kernels.  Each order is checked on a ragged
 5 x 3 element grid (tiles of one element class hold 1 to 3 elements) and on a
 stretched 4 x 3 grid (aspect up to 4, nonsingular coarse matrix): the Schur apply
 forward and transposed in FP64, FP32 and BF16, with 1, 2 and 4 columns per
-workgroup and the persistent kernel, the block-Jacobi preconditioner (blocks of up
-to 8n slots), the null vectors, the projections and full solves.
+workgroup, the persistent kernel, the warp-specialized persistent kernel and the
+column-pipelined kernel, the block-Jacobi preconditioner (blocks of up to 8n slots), the null vectors, the projections and full solves.
 
 Bars: single FP64 operator applies 1e-12 (two independent FP64 setups, measured
 ~1e-13); FP32 / BF16 operators 1e-5 / 2e-2 (operand rounding 2^-24 / 2^-8 over at
@@ -76,6 +76,11 @@ SHAPES = {
     "nc2": (("SMPM_SCHUR_NC", "2"), ("SMPM_SCHUR_PERSIST", "-1")),
     "nc4": (("SMPM_SCHUR_NC", "4"), ("SMPM_SCHUR_PERSIST", "-1")),
     "persistent": (("SMPM_SCHUR_PERSIST", "1"),),
+    "ws_nc1": (("SMPM_SCHUR_NC", "1"), ("SMPM_SCHUR_PERSIST", "2")),
+    "ws_nc2": (("SMPM_SCHUR_NC", "2"), ("SMPM_SCHUR_PERSIST", "2")),
+    "ws_nc4": (("SMPM_SCHUR_NC", "4"), ("SMPM_SCHUR_PERSIST", "2")),
+    "cols_cpw2": (("SMPM_SCHUR_CPW", "2"), ("SMPM_SCHUR_PERSIST", "3")),
+    "cols_cpw8": (("SMPM_SCHUR_CPW", "8"), ("SMPM_SCHUR_PERSIST", "3")),
 }
 
 
@@ -98,7 +103,7 @@ def test_schur_apply_fp64(n, geom, shape, transpose, monkeypatch):
 
 @pytest.mark.parametrize("n", ORDERS)
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-@pytest.mark.parametrize("shape", ["nc1", "nc4", "persistent"])
+@pytest.mark.parametrize("shape", ["nc1", "nc4", "persistent", "ws_nc2", "cols_cpw2"])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_schur_apply_low_precision(n, precision, shape, transpose, monkeypatch):
     if n > 16 and shape != "nc1":
