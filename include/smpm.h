@@ -130,6 +130,13 @@ typedef struct smpm_solve_opts {
                          sums are reduced: once per column or in every block;
                          SMPM_STREAM_BASIS=0/1 forces ordinary or non-temporal basis loads.)
                          Results are identical (default 1)                                        */
+  int stop_rule;      /* reference of the GMRES stopping test: 0 (default) |b_hat|, the norm the
+                         FP64 true residual is accepted against; 1 the initial GMRES residual
+                         |P b_hat| (|b_hat| for Algorithms 1 and 2), the rule of Sec. 3.2.  The
+                         returned solution is still accepted on its FP64 true residual          */
+  int profile;        /* 1: time the solve's phases with HIP events (smpm_solve_info.phase_ms;
+                         synchronizes between phases); 0 (default): no timing.  The environment
+                         SMPM_PROFILE=1 turns it on as well                                     */
 } smpm_solve_opts;
 
 typedef struct smpm_solve_info {
@@ -144,6 +151,17 @@ typedef struct smpm_solve_info {
   double cycle_residual[16];  /* mixed precision: max over columns of the FP64 true residual
                                  at the start of refinement cycle i (i < 16; then the final
                                  one); FP64: [0] = the final residual                      */
+  int cycle_iterations[16];   /* GMRES iterations of each cycle (max over columns): FP64, the
+                                 solve then its correction cycles; mixed, the refinement
+                                 cycles (the first 16)                                      */
+  int history_len;            /* entries of history (GMRES iterations of the last cycle of
+                                 column 0, plus one)                                       */
+  double history[1001];       /* column 0, last GMRES cycle: the least-squares residual
+                                 estimate |g_j| after j iterations relative to the stopping
+                                 reference (history[0] = initial residual / reference)     */
+  double phase_ms[4];         /* with opts.profile: right-hand side and projections (steps
+                                 1-3), GMRES and refinement (steps 4-8), back-substitution
+                                 and normalization (step 9), whole call; else zeros        */
 } smpm_solve_info;
 
 typedef struct smpm_plan_stats {

@@ -60,6 +60,11 @@ struct Workspace {
   int* hiters = nullptr;   // nrhs iteration counts
   int* nonfinite = nullptr;   // device flag: f or g held a non-finite entry
   int* hnonfinite = nullptr;  // its pinned host copy
+  double* hhist = nullptr;    // pinned: column 0's rotated right-hand side g (maxit + 1) and tol |ref|
+  double* hhist_cs = nullptr;
+  double* hhist_tolb = nullptr;
+  int hist_len = 0;           // entries of the last GMRES run's history (iterations + 1)
+  double hist_tol = 1.0;      // that run's relative tolerance (threshold = tol * reference)
   hipEvent_t ev[2] = {nullptr, nullptr};
   int nch = 0, rows = 0;
   std::vector<void*> mem;
@@ -85,7 +90,7 @@ struct smpm_ctx {
   // captured chunks of Arnoldi steps, keyed by the solve's shape; they hold workspace
   // pointers, so a workspace reallocation drops them
   struct GraphEntry {
-    int nrhs, kind, tr, sprec, mprec, maxit, prereduce, stream;
+    int nrhs, kind, tr, sprec, mprec, maxit, prereduce, stream, rule;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
@@ -224,14 +229,18 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   c->dp.cws_stride = cstride;
   {
     // [flags 2R ints | iters R ints | non-finite flag | pad] [hres 2R doubles] [hout 4R doubles]
+    // [rotated rhs g: ldh doubles | Givens cosines: ldh doubles | threshold]
     const size_t ibytes = (((3 * R + 1) * sizeof(int) + 63) / 64) * 64;
-    const size_t bytes = ibytes + 6 * R * sizeof(double);
+    const size_t bytes = ibytes + (6 * R + 2 * ldh + 1) * sizeof(double);
     if (hipHostMalloc((void**)&w.pinned, bytes, hipHostMallocCoherent) != hipSuccess)
       return fail(SMPM_ENOMEM, "hipHostMalloc failed");
     w.hiters = w.pinned + 2 * R;
     w.hnonfinite = w.pinned + 3 * R;
     w.hres = reinterpret_cast<double*>(reinterpret_cast<char*>(w.pinned) + ibytes);
     w.hout = w.hres + 2 * R;
+    w.hhist = w.hout + 4 * R;
+    w.hhist_cs = w.hhist + ldh;
+    w.hhist_tolb = w.hhist_cs + ldh;
   }
   for (int i = 0; i < 2; ++i)
     if (hipEventCreateWithFlags(&w.ev[i], hipEventDisableTiming) != hipSuccess)
@@ -415,9 +424,10 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
 constexpr int kChunkIters = 8;
 int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int sprec, int mprec,
                 hipGraphExec_t* out) {
+  const int rule = S.bref2 ? 0 : 1;
   for (const auto& g : c->graphs)
     if (g.nrhs == nrhs && g.kind == kind && g.tr == (int)tr && g.sprec == sprec && g.mprec == mprec &&
-        g.maxit == S.maxit && g.prereduce == S.prereduce && g.stream == S.stream) {
+        g.maxit == S.maxit && g.prereduce == S.prereduce && g.stream == S.stream && g.rule == rule) {
       *out = g.exec;
       return SMPM_OK;
     }
@@ -435,7 +445,7 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
     (void)hipGraphExecDestroy(c->graphs.front().exec);
     c->graphs.erase(c->graphs.begin());
   }
-  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, S.prereduce, S.stream, exec});
+  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, S.prereduce, S.stream, rule, exec});
   *out = exec;
   return SMPM_OK;
 }
@@ -445,14 +455,15 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
 // one chunk behind, so the device never waits for the host.
 int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, double tol, int maxit,
               std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64,
-              bool use_graph = true) {
+              bool use_graph = true, int rule = 0) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   GmState S = gm_state(c, nrhs, maxit);
-  // the stopping rule is relative to |b| (the Schur right-hand side), the quantity
-  // the FP64 true residual is accepted against; S is complete before any capture
+  // stopping reference: |b| (the Schur right-hand side, the quantity the FP64 true
+  // residual is accepted against), or with rule 1 the initial GMRES residual (the
+  // step-0 kernel takes it when bref2 is null); S is complete before any capture
   launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
-  S.bref2 = W.scal2 + 2 * nrhs;
+  S.bref2 = rule == 1 ? nullptr : W.scal2 + 2 * nrhs;
   hipGraphExec_t exec = nullptr;
   if (use_graph) {
     const int rc = chunk_graph(c, S, nrhs, kind, tr, sprec, mprec, &exec);
@@ -522,8 +533,15 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
   gm_finish(P, S, nrhs, x, s);
   iters.assign(nrhs, 0);
   launch_publish_i(W.iters, nrhs, W.hiters, s);
+  // column 0's rotated right-hand side (|g_j| = the residual estimate after j steps)
+  // and its stopping threshold, for smpm_solve_info.history
+  launch_publish(W.g, maxit + 1, W.hhist, s);
+  launch_publish(W.cs, maxit + 1, W.hhist_cs, s);
+  launch_publish(W.tolb, 1, W.hhist_tolb, s);
   HIPCHK(hipStreamSynchronize(s));
   std::copy(W.hiters, W.hiters + nrhs, iters.begin());
+  W.hist_len = std::min(iters[0], maxit) + 1;
+  W.hist_tol = tol;
   int jmax = 0;
   for (int v : iters) jmax = std::max(jmax, v);
   return jmax;
@@ -531,11 +549,11 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
 
 int solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, int nrhs, double tol, int maxit,
                 std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64,
-                bool use_graph = true) {
+                bool use_graph = true, int rule = 0) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   double* x1 = W.x;  // note: x may not alias W.x
-  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s, sprec, mprec, use_graph);
+  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s, sprec, mprec, use_graph, rule);
   if (rc < 0) return rc;
   // the post-processing uses the operators (and precisions) of the GMRES operator, so
   // that x = M^{-1} x1 reproduces the preconditioned iterate exactly
@@ -1042,6 +1060,8 @@ void smpm_default_opts(smpm_solve_opts* o) {
   o->inner_tol = 1e-5;
   o->max_refine = 20;
   o->graph = 1;
+  o->stop_rule = 0;
+  o->profile = 0;
 }
 
 const char* smpm_last_error(void) { return g_err.c_str(); }
@@ -1530,12 +1550,26 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   const DevPlan& P = c->dp;
   const size_t rb = sizeof(double) * Pl.r * nrhs;
   if (aliases(f, rb, u, rb)) return fail(SMPM_EINVAL, "f and u alias");
+  if (o.stop_rule != 0 && o.stop_rule != 1) return fail(SMPM_EINVAL, "stop_rule must be 0 or 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   rc = compute_null_vectors(c, s);
   if (rc) return rc;
   rc = ensure_ws(c, nrhs, o.maxit);
   if (rc) return rc;
   Workspace& W = c->ws;
+  W.hist_len = 0;
+  // per-phase timing (opts.profile or SMPM_PROFILE=1): events on the solve's stream
+  bool profile = o.profile != 0;
+  if (const char* e = std::getenv("SMPM_PROFILE")) profile = profile || e[0] == '1';
+  hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (profile) {
+    for (auto& e : pev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(pev[0], s));
+  }
+  auto mark = [&](int i) {
+    if (profile) (void)hipEventRecord(pev[i], s);
+  };
+  const int rule = o.stop_rule;
   // non-finite f or g: flagged by the kernels that first read them, reported as
   // SMPM_EINVAL once the solve has run (a NaN estimate retires its column at once)
   HIPCHK(hipMemsetAsync(W.nonfinite, 0, sizeof(int), s));
@@ -1559,6 +1593,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     launch_mdot(c->v0hat, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
     launch_axpy_shared(W.bS, Pl.k, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, s);
   }
+  mark(1);
   // steps 4-8
   std::vector<int> iters;
   const int kind = o.variant == 3 ? OP_PSM : o.variant == 2 ? OP_SM : OP_S;
@@ -1566,12 +1601,22 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   int cycles = 1;
   int sprec_final = PREC_F64;  // Schur precision of the last inner solve
   double hist[16] = {0};
+  int cyc_it[16] = {0};
+  int ncyc = 0;
+  auto note_cycle = [&](const std::vector<int>& it) {
+    int mx = 0;
+    for (int v : it) mx = std::max(mx, v);
+    if (ncyc < 16) cyc_it[ncyc] = mx;
+    ++ncyc;
+  };
   bool conv = true;
   double* xsol = W.bS;
   if (o.precision == SMPM_FP64) {
     // x lands in W.bS (free after b_hat is formed)
-    rc = solve_schur(c, kind, tr, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s, PREC_F64, PREC_F64, o.graph != 0);
+    rc = solve_schur(c, kind, tr, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s, PREC_F64, PREC_F64, o.graph != 0,
+                     rule);
     if (rc < 0) return rc;
+    note_cycle(iters);
     rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
     if (rc) return rc;
     // The least-squares estimate met tol, but the FP64 true residual decides.  Where it
@@ -1595,8 +1640,9 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       launch_axpy_shared(W.rho, Pl.k, nl, W.scal, 1.0, W.rho, Pl.k, nrhs, s);
       std::vector<int> it;
       rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, std::min(0.5, 0.3 * o.tol / worst), o.maxit, it, s,
-                       PREC_F64, PREC_F64, o.graph != 0);
+                       PREC_F64, PREC_F64, o.graph != 0, rule);
       if (rc < 0) return rc;
+      note_cycle(it);
       for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
       launch_add(W.xacc, W.bS, 1.0, W.bS, Pl.k, nrhs, s);
       ++cycles;
@@ -1702,13 +1748,15 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       }
       const double itol = std::min(0.5, std::max(o.inner_tol, 0.3 * o.tol / cmax));
       std::vector<int> it;
-      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, itol, o.maxit, it, s, sprec, mprec, o.graph != 0);
+      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, itol, o.maxit, it, s, sprec, mprec, o.graph != 0, rule);
       if (rc < 0) return rc;
+      note_cycle(it);
       sprec_final = sprec;
       for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
       launch_add(W.xacc, W.bS, 1.0, W.xacc, Pl.k, nrhs, s);
     }
   }
+  mark(2);
   if (!tr) {
     // step 9 and the constant: u = A^{-1}(f~ - E x); u -= (w^T u / w^T 1)
     launch_backsub(P, W.ft, xsol, u, nrhs, s);
@@ -1723,8 +1771,14 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     launch_axpy_shared(u, Pl.r, c->uL, W.scal, 1.0, u, Pl.r, nrhs, s);
   }
   launch_publish_i(W.nonfinite, 1, W.hnonfinite, s);
+  mark(3);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
+  float pms[3] = {0, 0, 0};
+  if (profile) {
+    for (int i = 0; i < 3; ++i) (void)hipEventElapsedTime(&pms[i], pev[i], pev[i + 1]);
+    for (auto& e : pev) (void)hipEventDestroy(e);
+  }
   int itmax = 0;
   double resmax = 0;
   for (int i = 0; i < nrhs; ++i) {
@@ -1740,6 +1794,22 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     info->rel_residual = resmax;
     // published before the synchronization above; the adjoint removes a multiple of w
     info->removed_component = W.hout[2 * nrhs] / (tr ? c->wsum : 1.0);
+    const double ref = *W.hhist_tolb / W.hist_tol;
+    // the estimate after i steps was g_i when step i set it; the rotation of step i + 1
+    // has since multiplied it by that rotation's cosine (the last entry is unrotated)
+    info->history_len = W.hist_len;
+    for (int i = 0; i < 1001; ++i) {
+      double v = 0.0;
+      if (i < W.hist_len && ref > 0) {
+        v = std::fabs(W.hhist[i]);
+        if (i + 1 < W.hist_len && W.hhist_cs[i] != 0.0) v /= std::fabs(W.hhist_cs[i]);
+        v /= ref;
+      }
+      info->history[i] = v;
+    }
+    for (int i = 0; i < 16; ++i) info->cycle_iterations[i] = cyc_it[i];
+    for (int i = 0; i < 3; ++i) info->phase_ms[i] = pms[i];
+    info->phase_ms[3] = pms[0] + pms[1] + pms[2];
   }
   if (*W.hnonfinite)
     return fail(SMPM_EINVAL, tr ? "the cotangent holds a non-finite entry" : "f or g holds a non-finite entry");

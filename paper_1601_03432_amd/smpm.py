@@ -38,13 +38,16 @@ ABI_SYMBOLS = (
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("transpose", C.c_int),
-                ("variant", C.c_int), ("inner_tol", C.c_double), ("max_refine", C.c_int), ("graph", C.c_int)]
+                ("variant", C.c_int), ("inner_tol", C.c_double), ("max_refine", C.c_int), ("graph", C.c_int),
+                ("stop_rule", C.c_int), ("profile", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("refinements", C.c_int), ("rel_residual", C.c_double),
                 ("removed_component", C.c_double), ("schur_precision", C.c_int),
-                ("cycle_residual", C.c_double * 16)]
+                ("cycle_residual", C.c_double * 16), ("cycle_iterations", C.c_int * 16),
+                ("history_len", C.c_int), ("history", C.c_double * 1001),
+                ("phase_ms", C.c_double * 4)]
 
 
 class TuneResult(C.Structure):
@@ -140,14 +143,19 @@ class Info:
     status: int
     schur_precision: int = FP64  # Schur operator precision of the last inner solve
     cycle_residuals: tuple = ()  # FP64 true residual at the start of each refinement cycle
+    history: tuple = ()          # column 0, last GMRES cycle: residual estimates / stopping reference
+    phase_ms: tuple = ()         # with profile=True: steps 1-3, 4-8, 9, total (ms)
+    cycle_iterations: tuple = ()  # GMRES iterations of each solve / refinement cycle
 
 
 def _info(si, rc):
     hist = list(si.cycle_residual)
     while len(hist) > 1 and hist[-1] == 0.0:
         hist.pop()
+    ncyc = min(16, max(1, si.refinements))
     return Info(si.iterations, si.refinements, si.rel_residual, si.removed_component, rc, si.schur_precision,
-                tuple(hist))
+                tuple(hist), tuple(si.history[:si.history_len]), tuple(si.phase_ms),
+                tuple(si.cycle_iterations[:ncyc]))
 
 
 class Context:
@@ -333,7 +341,8 @@ class Context:
         return out
 
     def solve(self, f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64, transpose=False,
-              inner_tol=1e-5, max_refine=20, stream=None, raise_on_noconv=True, graph=True):
+              inner_tol=1e-5, max_refine=20, stream=None, raise_on_noconv=True, graph=True, stop_rule=0,
+              profile=False):
         import torch
         f = self._as_cols(f, self.r)
         nrhs = f.shape[0]
@@ -346,7 +355,8 @@ class Context:
                 raise ValueError("g must have as many columns as f")
             gp = C.c_void_p(g.data_ptr())
         u = torch.empty_like(f)
-        opts = SolveOpts(tol, maxit, precision, int(transpose), variant, inner_tol, max_refine, int(graph))
+        opts = SolveOpts(tol, maxit, precision, int(transpose), variant, inner_tol, max_refine, int(graph),
+                         int(stop_rule), int(profile))
         info = SolveInfo()
         rc = self._lib.smpm_solve(self._h, C.c_void_p(f.data_ptr()), gp, C.c_void_p(u.data_ptr()), nrhs,
                                   C.byref(opts), C.byref(info), _stream(torch, stream))
@@ -401,7 +411,7 @@ def solve_group(contexts, fs, gs=None, tol=1e-10, maxit=400, variant=3, precisio
     up = arr([u.data_ptr() for u in us])
     gp = None if gl is None else arr([None if g is None else g.data_ptr() for g in gl])
     nr = (C.c_int * n)(*[f.shape[0] for f in fs])
-    opts = SolveOpts(tol, maxit, precision, 0, variant, inner_tol, max_refine, int(graph))
+    opts = SolveOpts(tol, maxit, precision, 0, variant, inner_tol, max_refine, int(graph), 0, 0)
     infos = (SolveInfo * n)()
     rc = lib.smpm_solve_group(hs, n, fp, gp, up, nr, C.byref(opts), infos, _stream(torch, stream))
     if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
