@@ -80,6 +80,9 @@ struct smpm_ctx {
   std::vector<void*> mem;                    // setup allocations
   double *uL = nullptr, *uS = nullptr, *v0hat = nullptr, *wq = nullptr, *ones = nullptr;
   double *rhat = nullptr;                    // 1/sqrt(r) vector (left null vector of L^T)
+  double* zv0 = nullptr;                     // Z^T v0hat (d), for the deflated null-vector solve
+  double *r1_p = nullptr, *r1_q1 = nullptr, *r1_q2 = nullptr;  // its exact coarse correction
+  bool r1_defl = false;                      // the deflated null-vector solve is set up
   double wsum = 0;
   bool precond_regular = true;               // false when the single block is all of S
   bool have_null = false;                    // u_L, u_S computed (on first use)
@@ -262,7 +265,45 @@ int check_device(const smpm_ctx* c) {
 
 // ---------------------------------------------------------------- operator pieces
 
-enum OpKind { OP_S = 1, OP_SM = 2, OP_PSM = 3, OP_RANK1 = 4 };
+enum OpKind { OP_S = 1, OP_SM = 2, OP_PSM = 3, OP_RANK1 = 4, OP_RANK1_DEFL = 5 };
+
+// A = S^T + v0hat v0hat^T (nonsingular; its transpose-inverse maps v0hat to a multiple of
+// u_S).  Deflated with the coarse space of Algorithm 3: P_A r = r - A Z G^T Z^T r, for
+// which A Q_A = P_A A with Q_A = I - Z G^T Z^T A; any fixed coarse map keeps the solve
+// exact, and G^T = (C^+)^T approximates (Z^T A Z)^{-1} = (C^T + a a^T)^{-1}, a = Z^T v0hat,
+// up to the rank-one term.  w = A Z c2 for the coarse values c2: S^T Z c2 + v0hat (a^T c2).
+void rank1_coarse_term(smpm_ctx* c, const double* t, const double* c2, double* w, hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  launch_prolong(P, t, c2, w, 1, 2, -1.0, nullptr, s);  // w = t - S^T Z c2
+  launch_mdot(c->zv0, 0, 0, 1, c2, P.d, nullptr, P.d, 1, W.part, W.scal2 + 3, nullptr, s);
+  launch_axpy_shared(w, P.k, c->v0hat, W.scal2 + 3, 1.0, w, P.k, 1, s);  // w -= v0hat (a^T c2)
+}
+// c2 = (Z^T A Z)^{-1} cin exactly: Z^T A Z = C^T + a a^T with a = Z^T v0hat.  From the
+// coarse solve's G^T = (C^T)^+ (C^T)^{-1} for nonsingular C):
+//   singular C (a = gamma tau_hat, tau_hat spanning the right null space of C and u_C
+//     the left one): y = G^T c + beta u_C, beta = (tau_hat^T c / (gamma^2 |tau_hat|^2)
+//     - tau_hat^T G^T c) / (tau_hat^T u_C);
+//   nonsingular C (Sherman-Morrison): y = G^T c - G^T a (a^T G^T c) / (1 + a^T G^T a);
+// i.e. c2 = G^T c + p (q1^T c + q2^T G^T c) with the d-vectors p, q1, q2 set up once.
+void rank1_coarse(smpm_ctx* c, const double* cin, double* c2, hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  launch_coarse(P, cin, c2, 1, true, nullptr, s);
+  launch_mdot(c->r1_q1, 0, 0, 1, cin, P.d, nullptr, P.d, 1, W.part, W.scal2 + 1, nullptr, s);
+  launch_mdot(c->r1_q2, 0, 0, 1, c2, P.d, nullptr, P.d, 1, W.part, W.scal2 + 2, nullptr, s);
+  launch_axpy_shared(c2, P.d, c->r1_p, W.scal2 + 1, -1.0, c2, P.d, 1, s);
+  launch_axpy_shared(c2, P.d, c->r1_p, W.scal2 + 2, -1.0, c2, P.d, 1, s);
+}
+
+// t = A z
+void rank1_apply(smpm_ctx* c, const double* z, double* t, hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  launch_schur(P, z, t, 1, true, nullptr, s);
+  launch_mdot(c->v0hat, 0, 0, 1, z, P.k, nullptr, P.k, 1, W.part, W.scal2, nullptr, s);
+  launch_axpy_shared(t, P.k, c->v0hat, W.scal2, -1.0, t, P.k, 1, s);
+}
 
 // w = op(v) for the chosen operator; transpose selects the adjoint pieces.
 void apply_op(smpm_ctx* c, int kind, bool tr, const double* v, double* w, int nrhs, const int* act,
@@ -287,6 +328,14 @@ void apply_op(smpm_ctx* c, int kind, bool tr, const double* v, double* w, int nr
     launch_axpy_shared(w, P.k, c->v0hat, W.scal2, -1.0, w, P.k, nrhs, s);
     return;
   }
+  if (kind == OP_RANK1_DEFL) {
+    // P_A A M^{-T} v (one column): t = A z, c2 = G^T Z^T t, w = t - A Z c2
+    rank1_apply(c, W.z, W.t, s);
+    launch_iface_sum(P, W.t, W.c, 1, nullptr, s);
+    rank1_coarse(c, W.c, W.c2, s);
+    rank1_coarse_term(c, W.t, W.c2, w, s);
+    return;
+  }
   launch_schur(P, W.z, W.t, nrhs, tr, act, s);
   launch_iface_sum(P, W.t, W.c, nrhs, act, s);
   launch_coarse(P, W.c, W.c2, nrhs, tr, act, s);
@@ -295,10 +344,10 @@ void apply_op(smpm_ctx* c, int kind, bool tr, const double* v, double* w, int nr
 
 // Right-preconditioned GMRES from x0 = 0 (Algorithm 3 step 4 and 5-8 for OP_PSM):
 // Arnoldi with classical Gram-Schmidt applied twice, Givens rotations, per-column
-// stopping |g_{j+1}| <= tol * beta.  b, x: k x nrhs.  Returns iterations (max over
+// stopping |g_{j+1}| <= tol * beta (beta the initial residual, or ref if positive).  b, x: k x nrhs.  Returns iterations (max over
 // columns) or a negative status.
 int gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, double tol, int maxit,
-          std::vector<int>& iters, hipStream_t s) {
+          std::vector<int>& iters, hipStream_t s, double ref = 0.0) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   const int64_t k = P.k;
@@ -317,6 +366,10 @@ int gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, 
     launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
     launch_prolong(P, b, W.c2, r0, nrhs, tr ? 2 : 1, -1.0, nullptr, s);
+  } else if (kind == OP_RANK1_DEFL) {
+    launch_iface_sum(P, b, W.c, 1, nullptr, s);
+    rank1_coarse(c, W.c, W.c2, s);
+    rank1_coarse_term(c, b, W.c2, r0, s);
   } else {
     HIPCHK(hipMemcpyAsync(r0, b, sizeof(double) * k * nrhs, hipMemcpyDeviceToDevice, s));
   }
@@ -355,7 +408,7 @@ int gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, 
     for (int col = 0; col < nrhs; ++col) {
       if (!act[col]) continue;
       iters[col] = j + 1;
-      if (!(res[col] > tol * beta[col]) || j + 1 == maxit) {
+      if (res[col] <= tol * (ref > 0.0 ? ref : beta[col]) || !std::isfinite(res[col]) || j + 1 == maxit) {
         act[col] = 0;
         --nact;
         changed = true;
@@ -643,15 +696,85 @@ int compute_null_vectors(smpm_ctx* c, hipStream_t s) {
   double null_res = HUGE_VAL;
   int total = 0;
   std::vector<double> hy(k);
+  // deflated when the grid has a coarse space and a regular preconditioner
+  bool defl = Pl.has_coarse && c->precond_regular;
+  if (defl && !c->zv0) {
+    // a = Z^T v0hat and the exact coarse correction's vectors p, q1, q2 (see rank1_coarse)
+    const int64_t d = Pl.d;
+    int r2 = dalloc(c->mem, &c->zv0, d);
+    r2 |= dalloc(c->mem, &c->r1_p, d);
+    r2 |= dalloc(c->mem, &c->r1_q1, d);
+    r2 |= dalloc(c->mem, &c->r1_q2, d);
+    if (r2) return SMPM_ENOMEM;
+    launch_iface_sum(P, c->v0hat, c->zv0, 1, nullptr, s);
+    std::vector<double> a(d), pv(d, 0.0), q1(d, 0.0), q2(d, 0.0);
+    HIPCHK(hipMemcpyAsync(a.data(), c->zv0, d * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (Pl.coarse_singular && (int64_t)Pl.tau_hat.size() == d && (int64_t)Pl.uC.size() == d) {
+      double tt = 0, ta = 0, tu = 0;
+      for (int64_t i = 0; i < d; ++i) {
+        tt += Pl.tau_hat[i] * Pl.tau_hat[i];
+        ta += Pl.tau_hat[i] * a[i];
+        tu += Pl.tau_hat[i] * Pl.uC[i];
+      }
+      const double gam = ta / tt;
+      double off = 0, an = 0;
+      for (int64_t i = 0; i < d; ++i) {
+        off = std::max(off, std::fabs(a[i] - gam * Pl.tau_hat[i]));
+        an = std::max(an, std::fabs(a[i]));
+      }
+      if (off <= 1e-10 * an && std::fabs(tu) > 1e-14 * std::sqrt(tt) && gam != 0.0) {
+        for (int64_t i = 0; i < d; ++i) {
+          pv[i] = Pl.uC[i];
+          q1[i] = Pl.tau_hat[i] / (gam * gam * tt * tu);
+          q2[i] = -Pl.tau_hat[i] / tu;
+        }
+      } else {
+        defl = false;  // not the structure the correction assumes: plain rank-one solve
+      }
+    } else if (!Pl.coarse_singular) {
+      HIPCHK(hipMemcpyAsync(c->r1_q1, c->zv0, d * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_coarse(P, c->r1_q1, c->r1_p, 1, true, nullptr, s);  // p = G^T a
+      HIPCHK(hipMemcpyAsync(pv.data(), c->r1_p, d * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double ap = 0;
+      for (int64_t i = 0; i < d; ++i) ap += a[i] * pv[i];
+      for (int64_t i = 0; i < d; ++i) q2[i] = -a[i] / (1.0 + ap);
+    } else {
+      defl = false;
+    }
+    HIPCHK(hipMemcpyAsync(c->r1_p, pv.data(), d * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->r1_q1, q1.data(), d * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->r1_q2, q2.data(), d * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->r1_defl = defl;
+  }
+  defl = defl && c->r1_defl;
   for (int cyc = 0; cyc < kNullCycles; ++cyc) {
-    // GMRES on (S^T + v0hat v0hat^T) M^{-T}, then delta = M^{-T} x; y += delta
-    int j = gmres(c, OP_RANK1, true, rv, W.x, 1, 1e-14, kNullMaxit, it, s);
-    if (j < 0) return j;
-    total += j;
-    if (c->precond_regular)
-      launch_precond(P, W.x, W.t, 1, true, nullptr, s);
-    else
-      HIPCHK(hipMemcpyAsync(W.t, W.x, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+    if (defl) {
+      // GMRES on P_A A M^{-T}, stopped at an absolute 1e-13 = 1e-13 |v0hat|: enough for
+      // ||S^T u_S|| / ||S|| <= 1e-12 (|y| >= 1, ||S|| >= 1), and above the rounding floor
+      // of the deflated operator (~1e-14); delta = Q_A M^{-T} x + Z G^T Z^T rv
+      // = z + Z G^T Z^T (rv - A z),  z = M^{-T} x
+      int j = gmres(c, OP_RANK1_DEFL, true, rv, W.x, 1, 1e-13, kNullMaxit, it, s, 1.0);
+      if (j < 0) return j;
+      total += j;
+      launch_precond(P, W.x, W.z, 1, true, nullptr, s);
+      rank1_apply(c, W.z, W.t, s);
+      launch_add(rv, W.t, -1.0, W.w, k, 1, s);
+      launch_iface_sum(P, W.w, W.c, 1, nullptr, s);
+      rank1_coarse(c, W.c, W.c2, s);
+      launch_prolong(P, W.z, W.c2, W.t, 1, 0, 1.0, nullptr, s);  // t = z + Z c2
+    } else {
+      // GMRES on (S^T + v0hat v0hat^T) M^{-T}, then delta = M^{-T} x
+      int j = gmres(c, OP_RANK1, true, rv, W.x, 1, 1e-14, kNullMaxit, it, s);
+      if (j < 0) return j;
+      total += j;
+      if (c->precond_regular)
+        launch_precond(P, W.x, W.t, 1, true, nullptr, s);
+      else
+        HIPCHK(hipMemcpyAsync(W.t, W.x, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+    }
     launch_add(y, W.t, 1.0, y, k, 1, s);
     // rv = v0hat - S^T y - v0hat (v0hat^T y);  ||S^T y|| and ||y|| for the check
     launch_schur(P, y, W.t, 1, true, nullptr, s);

@@ -116,11 +116,12 @@ def _backward_error_at(grid, u, ft, elems):
 
 
 def _left_null_error_at(grid, uL, elems):
-    """max over the columns of the sampled elements of |(L^T u_L)_j| / (|L|^T |u_L|)_j."""
+    """Normwise left-null residual at the columns of the sampled elements:
+    max_j |(L^T u_L)_j| / max_j (|L|^T |u_L|)_j (u_L spans many magnitudes on this grid,
+    so a componentwise ratio would measure rounding where u_L is tiny)."""
     n2 = grid.n2
-    worst = 0.0
+    num, den = 0.0, 0.0
     for jy, jx in elems:
-        j = grid.eid(jy, jx)
         acc = np.zeros(n2)
         scale = np.zeros(n2)
         rows_of = [(jy, jx)] + [nb for nb in (grid.neighbor(jy, jx, s) for s in O.SIDES) if nb is not None]
@@ -131,8 +132,8 @@ def _left_null_error_at(grid, uL, elems):
             ui = uL[grid.eid(iy, ix) * n2:(grid.eid(iy, ix) + 1) * n2]
             acc += blk.T @ ui
             scale += np.abs(blk).T @ np.abs(ui)
-        worst = max(worst, float(np.max(np.abs(acc) / scale)))
-    return worst
+        num, den = max(num, float(np.abs(acc).max())), max(den, float(scale.max()))
+    return num / den
 
 
 def test_c5_full_size_mixed_8rhs():
@@ -165,7 +166,9 @@ def test_c5_full_size_mixed_8rhs():
     assert 0 <= st["null_residual"] <= 1e-12
     sty = ctx.schur_apply(dev(uS), transpose=True).cpu().numpy()[0]
     assert np.linalg.norm(sty) <= 1e-12 * st["schur_norm_bound"]
-    assert _left_null_error_at(grid, uL, elems) <= 1e-9
+    lerr = _left_null_error_at(grid, uL, elems)
+    print(f"[gpu-c5] sampled normwise |L^T u_L| / (|L|^T |u_L|): {lerr:.2e}", flush=True)
+    assert lerr <= 1e-11
     for c in (0, 5):
         rhs = F[c] + T @ G[c]
         ft = rhs - uL * (uL @ rhs)

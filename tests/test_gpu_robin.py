@@ -161,3 +161,23 @@ def test_adjoint(robin, name):
     mu, info = ctx.solve(dev(c), tol=1e-12, maxit=800, transpose=True)
     want = O.solve_adjoint_unreduced(m.split, c[0])[0]
     assert rel(mu.cpu().numpy()[0], want) <= 1e-10
+
+
+@pytest.mark.parametrize("robin,alpha", [("literal", 32.0), ("min", 8.0)])
+def test_null_vectors_32x32_n5(robin, alpha):
+    """The h-refinement grid of Sec. 3.2 (32 x 32, n = 5): the deflated null-vector solve
+    with the exact rank-one coarse correction reaches ||S^T u_S|| / ||S|| <= 1e-12 and
+    the oracle's bordered-LU null vectors.  The literal reading runs at penalty 32: at
+    8 its S has further singular values near 3e-6 on this grid and no iteration
+    converges (the oracle's own Algorithm 3 stalls at 1e-4)."""
+    m, n = 32, 5
+    ctx = smpm.Context(m, m, n, wl.uniform_breaks(m), wl.uniform_breaks(m), alpha, robin=robin)
+    uL, uS = ctx.null_vectors()
+    st = ctx.stats()
+    print(f"[gpu-robin] 32x32 n=5 {robin}: null residual {st['null_residual']:.2e} after "
+          f"{st['null_iterations']} iterations", flush=True)
+    assert 0 <= st["null_residual"] <= 1e-12
+    sysm = O.SchurSystem(O.Split(O.Grid(n, wl.uniform_breaks(m), wl.uniform_breaks(m), alpha_int=alpha,
+                                        alpha_phys=alpha, robin=robin)))
+    assert rel_sign(uS, sysm.uS) <= 1e-9
+    assert rel_sign(uL, sysm.uL) <= 1e-9
