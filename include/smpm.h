@@ -124,8 +124,11 @@ typedef struct smpm_solve_opts {
   double inner_tol;   /* mixed precision: inner GMRES tolerance per refinement cycle (1e-5: two
                          cycles reach 1e-10 with about the FP64 iteration count)               */
   int max_refine;     /* mixed precision: maximum refinement cycles (default 20)                 */
-  int graph;          /* 1: the Arnoldi steps run as replays of a captured hipGraph of 8 steps
-                         (captured once per solve shape and context); 0: launched one by one.
+  int graph;          /* 1: the Arnoldi steps run as replays of a captured hipGraph of 8 steps,
+                         and the launch sequences before and after them (right-hand side,
+                         projections and GMRES start; least squares, recovery of x, FP64 true
+                         residual and back-substitution) as replays of two more (each captured
+                         once per solve shape and context); 0: launched one by one.
                          (Environment SMPM_PREREDUCE=0/1 forces how the orthogonalization
                          sums are reduced: once per column or in every block;
                          SMPM_STREAM_BASIS=0/1 forces ordinary or non-temporal basis loads.)
@@ -134,8 +137,8 @@ typedef struct smpm_solve_opts {
                          FP64 true residual is accepted against; 1 the initial GMRES residual
                          |P b_hat| (|b_hat| for Algorithms 1 and 2), the rule of Sec. 3.2.  The
                          returned solution is still accepted on its FP64 true residual          */
-  int profile;        /* 1: time the solve's phases with HIP events (smpm_solve_info.phase_ms;
-                         synchronizes between phases); 0 (default): no timing.  The environment
+  int profile;        /* 1: time the solve's phases with HIP events recorded on its stream
+                         (smpm_solve_info.phase_ms); 0 (default): no timing.  The environment
                          SMPM_PROFILE=1 turns it on as well                                     */
 } smpm_solve_opts;
 
@@ -159,9 +162,12 @@ typedef struct smpm_solve_info {
   double history[1001];       /* column 0, last GMRES cycle: the least-squares residual
                                  estimate |g_j| after j iterations relative to the stopping
                                  reference (history[0] = initial residual / reference)     */
-  double phase_ms[4];         /* with opts.profile: right-hand side and projections (steps
-                                 1-3), GMRES and refinement (steps 4-8), back-substitution
-                                 and normalization (step 9), whole call; else zeros        */
+  double phase_ms[4];         /* with opts.profile: [0] right-hand side and projections
+                                 (steps 1-3) and, in FP64, the GMRES start; [1] the Arnoldi
+                                 iterations (mixed: all refinement cycles); [2] FP64: least
+                                 squares, recovery of x (steps 5-8), true residual, step 9
+                                 and any correction cycles; mixed: step 9; [3] whole call;
+                                 else zeros                                                  */
 } smpm_solve_info;
 
 typedef struct smpm_plan_stats {

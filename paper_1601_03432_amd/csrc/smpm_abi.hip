@@ -50,6 +50,7 @@ struct Workspace {
   double *xacc = nullptr, *rho = nullptr;  // iterative refinement: solution and residual
   double* xprev = nullptr;                  // iterate before the last correction
   double* cws = nullptr;                    // substructured coarse solve scratch
+  double* ubuf = nullptr;                   // r x nrhs: back-substituted solution before the mean
   double* tolv = nullptr;                   // device GMRES: tolerance and step counter
   int* jdev = nullptr;
   double *tolb = nullptr;
@@ -94,6 +95,8 @@ struct smpm_ctx {
   // pointers, so a workspace reallocation drops them
   struct GraphEntry {
     int nrhs, kind, tr, sprec, mprec, maxit, prereduce, stream, rule;
+    int phase;           // 0: a chunk of Arnoldi steps, 1: a solve's pre-phase, 2: its post-phase
+    uint64_t tolbits;    // the tolerance the phase bakes in (pre-phase)
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
@@ -215,6 +218,7 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.dw, ldh * R);
   rc |= dalloc(w.mem, &w.sides, (size_t)P.nsides * R);
   rc |= dalloc(w.mem, &w.xacc, k * R);
+  rc |= dalloc(w.mem, &w.ubuf, r * R);
   rc |= dalloc(w.mem, &w.xprev, k * R);
   rc |= dalloc(w.mem, &w.rho, k * R);
   rc |= dalloc(w.mem, &w.tolb, R);
@@ -472,15 +476,24 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   return S;
 }
 
-// The executable graph of kChunkIters Arnoldi steps for this solve shape (captured on
-// first use on the context's capture stream; nothing runs during the capture).
+// The executable graph of kChunkIters Arnoldi steps and the publication of the
+// columns' activity flags and residual ratios (pinned slot chunk % 2) for this solve
+// shape (captured on first use on the context's capture stream; nothing runs during
+// the capture).
 constexpr int kChunkIters = 8;
+constexpr size_t kMaxGraphs = 32;  // executable graphs kept per context (oldest dropped)
+void publish_chunk(smpm_ctx* c, const GmState& S, int nrhs, hipStream_t s) {
+  Workspace& W = c->ws;
+  launch_publish_chunk(W.active, W.res, W.tolb, nrhs, S.jdev, kChunkIters, W.pinned, W.hres, W.nrhs, s);
+}
+
 int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int sprec, int mprec,
                 hipGraphExec_t* out) {
   const int rule = S.bref2 ? 0 : 1;
   for (const auto& g : c->graphs)
-    if (g.nrhs == nrhs && g.kind == kind && g.tr == (int)tr && g.sprec == sprec && g.mprec == mprec &&
-        g.maxit == S.maxit && g.prereduce == S.prereduce && g.stream == S.stream && g.rule == rule) {
+    if (g.phase == 0 && g.nrhs == nrhs && g.kind == kind && g.tr == (int)tr && g.sprec == sprec &&
+        g.mprec == mprec && g.maxit == S.maxit && g.prereduce == S.prereduce && g.stream == S.stream &&
+        g.rule == rule) {
       *out = g.exec;
       return SMPM_OK;
     }
@@ -488,54 +501,120 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   for (int q = 0; q < kChunkIters; ++q) gm_step(c->dp, S, nrhs, q & 1, kind, tr, c->cap_stream, sprec, mprec);
+  publish_chunk(c, S, nrhs, c->cap_stream);
   const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &graph);
   if (e1 != hipSuccess || !graph) return fail(SMPM_EHIP, "hipStreamEndCapture failed");
   hipGraphExec_t exec = nullptr;
   const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e2 != hipSuccess) return fail(SMPM_EHIP, "hipGraphInstantiate failed");
-  if (c->graphs.size() >= 16) {
+  if (c->graphs.size() >= kMaxGraphs) {
     (void)hipGraphExecDestroy(c->graphs.front().exec);
     c->graphs.erase(c->graphs.begin());
   }
-  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, S.prereduce, S.stream, rule, exec});
+  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, S.prereduce, S.stream, rule, 0, 0, exec});
   *out = exec;
   return SMPM_OK;
 }
 
-// Device-resident GMRES from x0 = 0 on S (kind 1), S M^{-1} (2) or P S M^{-1} (3).
-// The host enqueues Arnoldi steps in chunks and polls per-column activity flags
-// one chunk behind, so the device never waits for the host.
-int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, double tol, int maxit,
-              std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64,
-              bool use_graph = true, int rule = 0) {
+// A solve phase (a sequence of kernel launches with no host work in between, on fixed
+// workspace pointers) replayed from a graph captured on first use for its key, or run
+// directly when graphs are off or the capture fails.
+template <typename Body>
+int run_phase(smpm_ctx* c, bool use_graph, int phase, const GmState& S, int nrhs, int kind, bool tr, int sprec,
+              int mprec, double tol, hipStream_t s, Body&& body) {
+  if (!use_graph) {
+    body(s);
+    HIPCHK(hipGetLastError());
+    return SMPM_OK;
+  }
+  uint64_t tb = 0;
+  std::memcpy(&tb, &tol, sizeof tb);
+  const int rule = S.bref2 ? 0 : 1;
+  for (const auto& g : c->graphs)
+    if (g.phase == phase && g.nrhs == nrhs && g.kind == kind && g.tr == (int)tr && g.sprec == sprec &&
+        g.mprec == mprec && g.maxit == S.maxit && g.prereduce == S.prereduce && g.stream == S.stream &&
+        g.rule == rule && g.tolbits == tb) {
+      HIPCHK(hipGraphLaunch(g.exec, s));
+      return SMPM_OK;
+    }
+  if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  body(c->cap_stream);
+  const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &graph);
+  if (e1 != hipSuccess || !graph) return fail(SMPM_EHIP, "hipStreamEndCapture failed (solve phase)");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(SMPM_EHIP, "hipGraphInstantiate failed (solve phase)");
+  if (c->graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({nrhs, kind, (int)tr, sprec, mprec, S.maxit, S.prereduce, S.stream, rule, phase, tb, exec});
+  HIPCHK(hipGraphLaunch(exec, s));
+  return SMPM_OK;
+}
+
+// GMRES prologue for right-hand side b: the stopping reference |b|^2, the initial
+// residual r0 = P b (kind 3) or b into W.w, and gm_start (V_0, flags, tolerance).
+void gm_prologue(smpm_ctx* c, const GmState& S, int kind, bool tr, const double* b, int nrhs, double tol,
+                 hipStream_t s) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
-  GmState S = gm_state(c, nrhs, maxit);
-  // stopping reference: |b| (the Schur right-hand side, the quantity the FP64 true
-  // residual is accepted against), or with rule 1 the initial GMRES residual (the
-  // step-0 kernel takes it when bref2 is null); S is complete before any capture
   launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
-  S.bref2 = rule == 1 ? nullptr : W.scal2 + 2 * nrhs;
-  hipGraphExec_t exec = nullptr;
-  if (use_graph) {
-    const int rc = chunk_graph(c, S, nrhs, kind, tr, sprec, mprec, &exec);
-    if (rc) return rc;
-  }
   if (kind == 3) {
     launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
     launch_prolong(P, b, W.c2, W.w, nrhs, tr ? 2 : 1, -1.0, nullptr, s);
   } else {
-    HIPCHK(hipMemcpyAsync(W.w, b, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
+    launch_copy(b, W.w, P.k * nrhs, s);
   }
   gm_start(P, S, nrhs, tol, s);
-  // Chunks of kChunkIters steps; after each, a kernel publishes the activity flags and
-  // residual ratios (estimate / threshold) into pinned slot chunk % 2.  The host keeps
-  // one chunk queued ahead of the one it waits for, except when the observed
-  // convergence rate says the queued chunk will finish the solve: then it waits for
-  // that chunk instead of queueing steps that would find every column retired.  Steps
-  // past maxit (the last chunk's tail) do nothing.
+}
+
+// GMRES epilogue: the closing Givens step, the least-squares solution and x1 = V y, and
+// the counts and column 0's history (rotated right-hand side, cosines, threshold) into
+// pinned memory, read after the caller's synchronization.
+void gm_epilogue(smpm_ctx* c, const GmState& S, int kind, bool tr, double* x1, int nrhs, hipStream_t s) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  gm_close(P, S, nrhs, 0, kind, tr, s);  // chunks hold an even number of steps
+  gm_finish(P, S, nrhs, x1, s);
+  launch_publish_i(W.iters, nrhs, W.hiters, s);
+  launch_publish(W.g, S.maxit + 1, W.hhist, s);
+  launch_publish(W.cs, S.maxit + 1, W.hhist_cs, s);
+  launch_publish(W.tolb, 1, W.hhist_tolb, s);
+}
+
+// Reads what gm_epilogue published (after a synchronization).
+int gm_collect(smpm_ctx* c, int nrhs, int maxit, double tol, std::vector<int>& iters) {
+  Workspace& W = c->ws;
+  iters.assign(W.hiters, W.hiters + nrhs);
+  W.hist_len = std::min(iters[0], maxit) + 1;
+  W.hist_tol = tol;
+  int jmax = 0;
+  for (int v : iters) jmax = std::max(jmax, v);
+  return jmax;
+}
+
+// The Arnoldi iterations after gm_prologue: chunks of kChunkIters steps; after each, a
+// kernel publishes the activity flags and residual ratios (estimate / threshold) into
+// pinned slot chunk % 2.  The host keeps one chunk queued ahead of the one it waits
+// for, except when the observed convergence rate says the queued chunk will finish
+// the solve: then it waits for that chunk instead of queueing steps that would find
+// every column retired.  Steps past maxit (the last chunk's tail) do nothing.  Returns
+// once every column has retired (no synchronization after the last chunk's event).
+int gm_loop(smpm_ctx* c, const GmState& S, int kind, bool tr, int nrhs, int maxit, hipStream_t s, int sprec,
+            int mprec, bool use_graph) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    const int rc = chunk_graph(c, S, nrhs, kind, tr, sprec, mprec, &exec);
+    if (rc) return rc;
+  }
   // step j finishes Hessenberg column j - 2, so maxit columns take maxit + 2 steps
   const int nchunks = (maxit + 2 + kChunkIters - 1) / kChunkIters;
   auto launch_chunk = [&](int ch) -> int {
@@ -543,9 +622,8 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
       HIPCHK(hipGraphLaunch(exec, s));
     } else {
       for (int q = 0; q < kChunkIters; ++q) gm_step(P, S, nrhs, q & 1, kind, tr, s, sprec, mprec);
+      publish_chunk(c, S, nrhs, s);
     }
-    launch_publish_flags(W.active, W.res, W.tolb, nrhs, W.pinned + (ch & 1) * W.nrhs, W.hres + (ch & 1) * W.nrhs,
-                         s);
     HIPCHK(hipEventRecord(W.ev[ch & 1], s));
     return SMPM_OK;
   };
@@ -554,14 +632,14 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
   bool finishing = false;  // the chunk in flight is predicted to complete every column
   int rc0 = launch_chunk(launched++);
   if (rc0) return rc0;
-  for (int c = 0; c < nchunks; ++c) {
-    if (!finishing && launched == c + 1 && launched < nchunks) {
+  for (int ci = 0; ci < nchunks; ++ci) {
+    if (!finishing && launched == ci + 1 && launched < nchunks) {
       rc0 = launch_chunk(launched++);
       if (rc0) return rc0;
     }
-    HIPCHK(hipEventSynchronize(W.ev[c & 1]));
-    const int* fl = W.pinned + (c & 1) * W.nrhs;
-    const double* ra = W.hres + (c & 1) * W.nrhs;
+    HIPCHK(hipEventSynchronize(W.ev[ci & 1]));
+    const int* fl = W.pinned + (ci & 1) * W.nrhs;
+    const double* ra = W.hres + (ci & 1) * W.nrhs;
     bool any = false;
     double steps_left = 0.0;
     for (int i = 0; i < nrhs; ++i) {
@@ -574,48 +652,50 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
       steps_left = std::max(steps_left, left);
       prev_ratio[i] = r;
     }
-    if (!any || c + 1 >= nchunks) break;
-    // the chunk queued after c covers the next kChunkIters steps
+    if (!any || ci + 1 >= nchunks) break;
+    // the chunk queued after ci covers the next kChunkIters steps
     finishing = steps_left <= kChunkIters;
-    if (launched == c + 1) {
+    if (launched == ci + 1) {
       rc0 = launch_chunk(launched++);
       if (rc0) return rc0;
     }
   }
-  gm_close(P, S, nrhs, 0, kind, tr, s);  // chunks hold an even number of steps
-  gm_finish(P, S, nrhs, x, s);
-  iters.assign(nrhs, 0);
-  launch_publish_i(W.iters, nrhs, W.hiters, s);
-  // column 0's rotated right-hand side (|g_j| = the residual estimate after j steps)
-  // and its stopping threshold, for smpm_solve_info.history
-  launch_publish(W.g, maxit + 1, W.hhist, s);
-  launch_publish(W.cs, maxit + 1, W.hhist_cs, s);
-  launch_publish(W.tolb, 1, W.hhist_tolb, s);
-  HIPCHK(hipStreamSynchronize(s));
-  std::copy(W.hiters, W.hiters + nrhs, iters.begin());
-  W.hist_len = std::min(iters[0], maxit) + 1;
-  W.hist_tol = tol;
-  int jmax = 0;
-  for (int v : iters) jmax = std::max(jmax, v);
-  return jmax;
+  return SMPM_OK;
 }
 
-int solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, int nrhs, double tol, int maxit,
-                std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64,
-                bool use_graph = true, int rule = 0) {
+// Device-resident GMRES from x0 = 0 on S (kind 1), S M^{-1} (2) or P S M^{-1} (3):
+// prologue, iterations and epilogue, then a synchronization.  Returns the largest
+// iteration count over the columns.
+int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, double tol, int maxit,
+              std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64,
+              bool use_graph = true, int rule = 0) {
+  Workspace& W = c->ws;
+  GmState S = gm_state(c, nrhs, maxit);
+  // stopping reference: |b| (the Schur right-hand side, the quantity the FP64 true
+  // residual is accepted against), or with rule 1 the initial GMRES residual (the
+  // step-0 kernel takes it when bref2 is null)
+  S.bref2 = rule == 1 ? nullptr : W.scal2 + 2 * nrhs;
+  gm_prologue(c, S, kind, tr, b, nrhs, tol, s);
+  int rc = gm_loop(c, S, kind, tr, nrhs, maxit, s, sprec, mprec, use_graph);
+  if (rc) return rc;
+  gm_epilogue(c, S, kind, tr, x, nrhs, s);
+  HIPCHK(hipStreamSynchronize(s));
+  return gm_collect(c, nrhs, maxit, tol, iters);
+}
+
+// x from the GMRES solution x1 of the preconditioned (and deflated) system, with the
+// operators (and precisions) of the GMRES operator, so that x = M^{-1} x1 reproduces
+// the preconditioned iterate exactly (Algorithm 3 steps 5-8).
+void recover_x(smpm_ctx* c, int kind, bool tr, const double* bhat, const double* x1, double* x, int nrhs, int sprec,
+               int mprec, hipStream_t s) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
-  double* x1 = W.x;  // note: x may not alias W.x
-  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s, sprec, mprec, use_graph, rule);
-  if (rc < 0) return rc;
-  // the post-processing uses the operators (and precisions) of the GMRES operator, so
-  // that x = M^{-1} x1 reproduces the preconditioned iterate exactly
   if (kind == OP_S) {
-    HIPCHK(hipMemcpyAsync(x, x1, sizeof(double) * P.k * nrhs, hipMemcpyDeviceToDevice, s));
+    launch_copy(x1, x, P.k * nrhs, s);
   } else if (kind == OP_SM) {
     launch_precond(P, x1, x, nrhs, tr, nullptr, s, mprec);
   } else {
-    // x = z + Z G Z^T (b_hat - S z), z = M^{-1} x1   (Algorithm 3 steps 5-8)
+    // x = z + Z G Z^T (b_hat - S z), z = M^{-1} x1
     launch_precond(P, x1, W.z, nrhs, tr, nullptr, s, mprec);
     launch_schur_ex(P, W.z, W.t, nrhs, tr, nullptr, nullptr, s, sprec);
     launch_add(bhat, W.t, -1.0, W.w, P.k, nrhs, s);
@@ -623,12 +703,10 @@ int solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, i
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
     launch_prolong(P, W.z, W.c2, x, nrhs, 0, 1.0, nullptr, s);
   }
-  return rc;
 }
 
-// ||b - S x|| / ||b|| per column (FP64), returned on the host.
-int true_residual(smpm_ctx* c, bool tr, const double* b, const double* x, int nrhs, std::vector<double>& out,
-                  hipStream_t s) {
+// |b - S x|^2 and |b|^2 per column into pinned hout[0..nrhs) and hout[nrhs..2 nrhs)
+void true_residual_enqueue(smpm_ctx* c, bool tr, const double* b, const double* x, int nrhs, hipStream_t s) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   launch_schur(P, x, W.t, nrhs, tr, nullptr, s);
@@ -637,11 +715,33 @@ int true_residual(smpm_ctx* c, bool tr, const double* b, const double* x, int nr
   launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2, nullptr, s);
   launch_publish(W.scal, nrhs, W.hout, s);
   launch_publish(W.scal2, nrhs, W.hout + nrhs, s);
-  HIPCHK(hipStreamSynchronize(s));
+}
+
+void true_residual_read(smpm_ctx* c, int nrhs, std::vector<double>& out) {
+  Workspace& W = c->ws;
   const double* a = W.hout;
   const double* bb = W.hout + nrhs;
   out.resize(nrhs);
   for (int i = 0; i < nrhs; ++i) out[i] = bb[i] > 0 ? std::sqrt(a[i] / bb[i]) : std::sqrt(a[i]);
+}
+
+int solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, int nrhs, double tol, int maxit,
+                std::vector<int>& iters, hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64,
+                bool use_graph = true, int rule = 0) {
+  Workspace& W = c->ws;
+  double* x1 = W.x;  // note: x may not alias W.x
+  int rc = gmres_dev(c, kind, tr, bhat, x1, nrhs, tol, maxit, iters, s, sprec, mprec, use_graph, rule);
+  if (rc < 0) return rc;
+  recover_x(c, kind, tr, bhat, x1, x, nrhs, sprec, mprec, s);
+  return rc;
+}
+
+// ||b - S x|| / ||b|| per column (FP64), returned on the host.
+int true_residual(smpm_ctx* c, bool tr, const double* b, const double* x, int nrhs, std::vector<double>& out,
+                  hipStream_t s) {
+  true_residual_enqueue(c, tr, b, x, nrhs, s);
+  HIPCHK(hipStreamSynchronize(s));
+  true_residual_read(c, nrhs, out);
   return SMPM_OK;
 }
 
@@ -1693,30 +1793,54 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     if (profile) (void)hipEventRecord(pev[i], s);
   };
   const int rule = o.stop_rule;
-  // non-finite f or g: flagged by the kernels that first read them, reported as
-  // SMPM_EINVAL once the solve has run (a NaN estimate retires its column at once)
+  const bool use_graph = o.graph != 0;
+  // non-finite f or g: flagged by the kernel that first reads them, reported as
+  // SMPM_EINVAL once the solve has run (a NaN estimate retires its column at once).
+  // That kernel copies the user's data into W.rhs (adding T g); every later step works
+  // on workspace buffers, so the phases below can be replayed from captured graphs.
   HIPCHK(hipMemsetAsync(W.nonfinite, 0, sizeof(int), s));
-  if (!tr) {
-    // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
-    launch_rhs(P, f, g, W.rhs, nrhs, W.nonfinite, s);
-    launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
-    launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, s);  // read after the final synchronization
-    launch_axpy_shared(W.rhs, Pl.r, c->uL, W.scal, 1.0, W.ft, Pl.r, nrhs, s);
-    launch_flux(P, W.ft, W.bS, nrhs, s);
-    launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
-    launch_axpy_shared(W.bS, Pl.k, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, s);
-  } else {
-    // adjoint of the solution map: c~ = c - w (1^T c)/(w^T 1); S^T xi = E^T A^{-T} c~
-    // (consistent: v0^T E^T A^{-T} c~ = -1^T c~ = 0), projected off v0 against rounding
-    launch_check_finite(f, Pl.r * nrhs, W.nonfinite, s);
-    launch_mdot(c->ones, 0, 0, 1, f, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
-    launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, s);  // read after the final synchronization
-    launch_axpy_shared(f, Pl.r, c->wq, W.scal, 1.0 / c->wsum, W.ft, Pl.r, nrhs, s);
-    launch_local_adj(P, W.ft, W.bS, nrhs, true, s);
-    launch_mdot(c->v0hat, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
-    launch_axpy_shared(W.bS, Pl.k, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, s);
-  }
-  mark(1);
+  launch_rhs(P, f, tr ? nullptr : g, W.rhs, nrhs, W.nonfinite, s);
+  auto pre_body = [&](hipStream_t q) {
+    if (!tr) {
+      // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
+      launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, q);
+      launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, q);  // read after the final synchronization
+      launch_axpy_shared(W.rhs, Pl.r, c->uL, W.scal, 1.0, W.ft, Pl.r, nrhs, q);
+      launch_flux(P, W.ft, W.bS, nrhs, q);
+      launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
+      launch_axpy_shared(W.bS, Pl.k, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, q);
+    } else {
+      // adjoint of the solution map: c~ = c - w (1^T c)/(w^T 1); S^T xi = E^T A^{-T} c~
+      // (consistent: v0^T E^T A^{-T} c~ = -1^T c~ = 0), projected off v0 against rounding
+      launch_mdot(c->ones, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, q);
+      launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, q);  // read after the final synchronization
+      launch_axpy_shared(W.rhs, Pl.r, c->wq, W.scal, 1.0 / c->wsum, W.ft, Pl.r, nrhs, q);
+      launch_local_adj(P, W.ft, W.bS, nrhs, true, q);
+      launch_mdot(c->v0hat, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
+      launch_axpy_shared(W.bS, Pl.k, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, q);
+    }
+  };
+  // step 9 up to the last store: forward u = A^{-1}(f~ - E x) into W.ubuf and w^T u
+  // into W.scal; adjoint mu = A^{-T}(c~ - B^T xi) into W.ubuf and u_L^T mu into W.scal
+  auto post_body = [&](const double* xs, hipStream_t q) {
+    if (!tr) {
+      launch_backsub(P, W.ft, xs, W.ubuf, nrhs, q);
+      launch_mdot(c->wq, 0, 0, 1, W.ubuf, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, q);
+    } else {
+      launch_local_adj(P, W.ft, W.ubuf, nrhs, false, q);
+      launch_flux_adj(P, xs, W.rhs, nrhs, q);
+      launch_add(W.ubuf, W.rhs, -1.0, W.ubuf, Pl.r, nrhs, q);
+      launch_mdot(c->uL, 0, 0, 1, W.ubuf, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, q);
+    }
+  };
+  // the last store into the user's u: the constant (forward: u -= (w^T u / w^T 1) 1) or
+  // the u_L component (adjoint, the null space of L^T) removed
+  auto store_u = [&](hipStream_t q) {
+    if (!tr)
+      launch_axpy_shared(W.ubuf, Pl.r, c->ones, W.scal, 1.0 / c->wsum, u, Pl.r, nrhs, q);
+    else
+      launch_axpy_shared(W.ubuf, Pl.r, c->uL, W.scal, 1.0, u, Pl.r, nrhs, q);
+  };
   // steps 4-8
   std::vector<int> iters;
   const int kind = o.variant == 3 ? OP_PSM : o.variant == 2 ? OP_SM : OP_S;
@@ -1733,18 +1857,43 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     ++ncyc;
   };
   bool conv = true;
-  double* xsol = W.bS;
   if (o.precision == SMPM_FP64) {
-    // x lands in W.bS (free after b_hat is formed)
-    rc = solve_schur(c, kind, tr, W.bhat, W.bS, nrhs, o.tol, o.maxit, iters, s, PREC_F64, PREC_F64, o.graph != 0,
-                     rule);
-    if (rc < 0) return rc;
-    note_cycle(iters);
-    rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
+    // One pass with a single synchronization: [steps 1-3, GMRES start] as one phase;
+    // the Arnoldi chunks; [closing rotation, least squares, recovery of x into W.bS
+    // (steps 5-8), the FP64 true residual, step 9 into W.ubuf] as another; the store
+    // into u.  Each phase is a fixed launch sequence on workspace buffers, replayed
+    // from a graph captured on first use for its shape.
+    GmState S = gm_state(c, nrhs, o.maxit);
+    // stopping reference: |b_hat| (the quantity the FP64 true residual is accepted
+    // against), or with rule 1 the initial GMRES residual (the step-0 kernel takes it
+    // when bref2 is null)
+    S.bref2 = rule == 1 ? nullptr : W.scal2 + 2 * nrhs;
+    rc = run_phase(c, use_graph, 1, S, nrhs, kind, tr, PREC_F64, PREC_F64, o.tol, s, [&](hipStream_t q) {
+      pre_body(q);
+      gm_prologue(c, S, kind, tr, W.bhat, nrhs, o.tol, q);
+    });
     if (rc) return rc;
+    mark(1);
+    rc = gm_loop(c, S, kind, tr, nrhs, o.maxit, s, PREC_F64, PREC_F64, use_graph);
+    if (rc) return rc;
+    mark(2);
+    rc = run_phase(c, use_graph, 2, S, nrhs, kind, tr, PREC_F64, PREC_F64, o.tol, s, [&](hipStream_t q) {
+      gm_epilogue(c, S, kind, tr, W.x, nrhs, q);
+      recover_x(c, kind, tr, W.bhat, W.x, W.bS, nrhs, PREC_F64, PREC_F64, q);
+      true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q);
+      post_body(W.bS, q);
+      launch_publish_i(W.nonfinite, 1, W.hnonfinite, q);
+    });
+    if (rc) return rc;
+    store_u(s);
+    HIPCHK(hipStreamSynchronize(s));
+    gm_collect(c, nrhs, o.maxit, o.tol, iters);
+    note_cycle(iters);
+    true_residual_read(c, nrhs, tres);
     // The least-squares estimate met tol, but the FP64 true residual decides.  Where it
     // misses tol by rounding (finite, iterations left), FP64 correction cycles
-    // x += GMRES(b_hat - S x) bring it down (at most two).
+    // x += GMRES(b_hat - S x) bring it down (at most two); u is then formed again.
+    bool corrected = false;
     for (int extra = 0; extra < 2; ++extra) {
       double worst = 0.0;
       bool fixable = true, any = false;
@@ -1755,7 +1904,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
         worst = std::max(worst, tres[i]);
       }
       if (!any || !fixable) break;
-      HIPCHK(hipMemcpyAsync(W.xacc, W.bS, sizeof(double) * Pl.k * nrhs, hipMemcpyDeviceToDevice, s));
+      launch_copy(W.bS, W.xacc, Pl.k * nrhs, s);
       launch_schur(P, W.xacc, W.t, nrhs, tr, nullptr, s);
       launch_add(W.bhat, W.t, -1.0, W.rho, Pl.k, nrhs, s);
       const double* nl = tr ? c->v0hat : c->uS;
@@ -1763,18 +1912,27 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       launch_axpy_shared(W.rho, Pl.k, nl, W.scal, 1.0, W.rho, Pl.k, nrhs, s);
       std::vector<int> it;
       rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, std::min(0.5, 0.3 * o.tol / worst), o.maxit, it, s,
-                       PREC_F64, PREC_F64, o.graph != 0, rule);
+                       PREC_F64, PREC_F64, use_graph, rule);
       if (rc < 0) return rc;
       note_cycle(it);
       for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
       launch_add(W.xacc, W.bS, 1.0, W.bS, Pl.k, nrhs, s);
       ++cycles;
+      corrected = true;
       rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
       if (rc) return rc;
     }
     for (int i = 0; i < nrhs; ++i)
       if (!(tres[i] <= o.tol)) conv = false;  // NaN counts as not converged
+    if (corrected) {
+      post_body(W.bS, s);
+      store_u(s);
+    }
   } else {
+    rc = run_phase(c, use_graph, 1, gm_state(c, nrhs, o.maxit), nrhs, 0, tr, PREC_F64, PREC_F64, 0.0, s,
+                   [&](hipStream_t q) { pre_body(q); });
+    if (rc) return rc;
+    mark(1);
     // Iterative refinement: rho = b_hat - S x in FP64; delta from the deflated GMRES with
     // FP32 (or BF16) Schur and block-Jacobi operators; x += delta.
     //  * Inner tolerance: inner_tol, loosened to 0.3 tol / rho_max once the residual is
@@ -1790,7 +1948,6 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     //    the previous iterate) before the precision is raised.
     int sprec = o.precision == SMPM_MIXED_FP32 ? PREC_F32 : PREC_BF16;
     const int mprec = sprec;
-    xsol = W.xacc;
     HIPCHK(hipMemsetAsync(W.xacc, 0, sizeof(double) * Pl.k * nrhs, s));
     HIPCHK(hipMemcpyAsync(W.rho, W.bhat, sizeof(double) * Pl.k * nrhs, hipMemcpyDeviceToDevice, s));
     iters.assign(nrhs, 0);
@@ -1878,22 +2035,11 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       for (int i = 0; i < nrhs; ++i) iters[i] += it[i];
       launch_add(W.xacc, W.bS, 1.0, W.xacc, Pl.k, nrhs, s);
     }
+    mark(2);
+    post_body(W.xacc, s);
+    store_u(s);
+    launch_publish_i(W.nonfinite, 1, W.hnonfinite, s);
   }
-  mark(2);
-  if (!tr) {
-    // step 9 and the constant: u = A^{-1}(f~ - E x); u -= (w^T u / w^T 1)
-    launch_backsub(P, W.ft, xsol, u, nrhs, s);
-    launch_mdot(c->wq, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
-    launch_axpy_shared(u, Pl.r, c->ones, W.scal, 1.0 / c->wsum, u, Pl.r, nrhs, s);
-  } else {
-    // mu = A^{-T}(c~ - B^T xi), then the u_L component (null space of L^T) removed
-    launch_local_adj(P, W.ft, u, nrhs, false, s);
-    launch_flux_adj(P, xsol, W.rhs, nrhs, s);
-    launch_add(u, W.rhs, -1.0, u, Pl.r, nrhs, s);
-    launch_mdot(c->uL, 0, 0, 1, u, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, s);
-    launch_axpy_shared(u, Pl.r, c->uL, W.scal, 1.0, u, Pl.r, nrhs, s);
-  }
-  launch_publish_i(W.nonfinite, 1, W.hnonfinite, s);
   mark(3);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

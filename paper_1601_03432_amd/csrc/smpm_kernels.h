@@ -269,6 +269,8 @@ void launch_prolong(const DevPlan& P, const double* t, const double* c2, double*
 // rhs = f + T g (g may be NULL); *flag is set to 1 if f or g holds a non-finite entry
 void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs, int nrhs, int* flag,
                 hipStream_t s);
+// b = a over len doubles (a kernel, so it can be captured into a graph)
+void launch_copy(const double* a, double* b, int64_t len, hipStream_t s);
 // *flag = 1 if a[0..len) holds a non-finite entry (flag cleared by the caller)
 void launch_check_finite(const double* a, int64_t len, int* flag, hipStream_t s);
 void launch_bdry_adj(const DevPlan& P, const double* mu, double* dg, int nrhs, hipStream_t s);  // dg = T^T mu
@@ -281,6 +283,10 @@ void launch_publish_i(const int* src, int n, int* host_dst, hipStream_t s);
 // hflag[i] = active[i], hratio[i] = res[i] / tolb[i]
 void launch_publish_flags(const int* active, const double* res, const double* tolb, int n, int* hflag,
                           double* hratio, hipStream_t s);
+// as launch_publish_flags after a chunk of steps Arnoldi steps, into slot
+// (jdev[0] / steps - 1) % 2 of hflag / hratio (stride entries per slot)
+void launch_publish_chunk(const int* active, const double* res, const double* tolb, int n, const int* jdev, int steps,
+                          int* hflag, double* hratio, int stride, hipStream_t s);
 
 // ---- vector kernels over nrhs columns of length len (column stride ld)
 int reduce_chunks(int64_t len);

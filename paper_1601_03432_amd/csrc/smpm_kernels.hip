@@ -1307,6 +1307,19 @@ __global__ void k_publish_flags(const int* __restrict__ active, const double* __
   hratio[i] = tolb[i] > 0.0 ? res[i] / tolb[i] : 0.0;
 }
 
+// the same after a chunk of steps steps, into pinned slot (chunk index) % 2 of stride
+// entries; the chunk index comes from the step counter (jdev = steps done so far), so
+// one captured launch serves every chunk
+__global__ void k_publish_chunk(const int* __restrict__ active, const double* __restrict__ res,
+                                const double* __restrict__ tolb, int n, const int* __restrict__ jdev, int steps,
+                                int* hflag, double* hratio, int stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int slot = ((jdev[0] / steps) - 1) & 1;
+  hflag[slot * stride + i] = active[i];
+  hratio[slot * stride + i] = tolb[i] > 0.0 ? res[i] / tolb[i] : 0.0;
+}
+
 // ------------------------------------------------------------------ vector kernels
 
 constexpr int kChunk = 2048;   // elements per reduction chunk (256 threads x 8)
@@ -1801,6 +1814,10 @@ void launch_rhs(const DevPlan& P, const double* f, const double* g, double* rhs,
   hipLaunchKernelGGL(k_bdry_add, grid1(P.nbdry - sn, 256, nrhs), dim3(256), 0, s, P, g, rhs, sn, P.nbdry, flag);
 }
 
+void launch_copy(const double* a, double* b, int64_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, grid1(len, 256), dim3(256), 0, s, a, b, len);
+}
+
 void launch_check_finite(const double* a, int64_t len, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_check_finite, grid1(len, 256), dim3(256), 0, s, a, len, flag);
 }
@@ -1824,6 +1841,12 @@ void launch_publish_i(const int* src, int n, int* host_dst, hipStream_t s) {
 void launch_publish_flags(const int* active, const double* res, const double* tolb, int n, int* hflag,
                           double* hratio, hipStream_t s) {
   hipLaunchKernelGGL(k_publish_flags, dim3((n + 255) / 256), dim3(256), 0, s, active, res, tolb, n, hflag, hratio);
+}
+
+void launch_publish_chunk(const int* active, const double* res, const double* tolb, int n, const int* jdev, int steps,
+                          int* hflag, double* hratio, int stride, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish_chunk, dim3((n + 255) / 256), dim3(256), 0, s, active, res, tolb, n, jdev, steps,
+                     hflag, hratio, stride);
 }
 
 void launch_mdot(const double* A, int64_t a_vs, int64_t a_cs, int nvec, const double* b, int64_t b_cs,
