@@ -313,12 +313,51 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   Acc* xs = reinterpret_cast<Acc*>(wsp);
   Acc* bpart = xs + kStageSlots;
   const int col = blockIdx.y, tid = threadIdx.x;
+  // The slot blocks' run of block-Jacobi blocks and its first group: their table loads
+  // depend on nothing, so they are issued before anything waits (the column's
+  // activity, the step index); the tail reuses them.
+  const bool slot_block = use_precond && !givens_only && (gridDim.x == 1 || blockIdx.x > 0);
+  int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
+  const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
+  if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
+  const int per = (P.nblk + nwb - 1) / nwb;
+  const int b0 = wb * per, bend = min(P.nblk, (wb + 1) * per);
+  BlockGroup g0 = {0, 0, 0, 0};
+  if (slot_block && b0 < bend) g0 = block_group(P, b0, bend);
   if (!S.active[col]) return;
   const int j = S.jdev[par];
   const bool nt = S.stream > 0 || (S.stream < 0 && stream_basis(j > 1 ? j : 1, S.vvs));
   const int64_t k = P.k;
   double* zc = S.z + (int64_t)col * k;
   const double* Vc = S.V + (int64_t)col * k;
+  // The first group's inverse, and, when the group holds at most one slot per thread
+  // and 1 <= m <= kPre, the thread's slot with its basis entries V_0..V_{m-1}, u_m and
+  // w: loaded before the Gram-Schmidt sums are reduced (none of them needs a sum), so
+  // the round trips overlap.
+  constexpr int kPre = 32;
+  double pv[kPre];
+  double pvm = 0.0, pwc = 0.0;
+  int64_t px = -1;
+  const int mp = j - 1;
+  int64_t mb0 = 0;
+  if (slot_block && b0 < bend) mb0 = P.bcls_off[g0.bc];
+  // uniform over the block
+  const bool pre = slot_block && gridDim.x > 1 && b0 < bend && g0.nb * g0.sb <= kThreads && mp >= 1 &&
+                   mp <= kPre && mp <= S.maxit;
+  if (pre && tid < g0.nb * g0.sb) {
+    px = P.blk_slots[g0.o0 + tid];
+    auto load = [&](auto nt_) {
+#pragma unroll
+      for (int u = 0; u < kPre; ++u)
+        pv[u] = ld_basis<kNT<decltype(nt_)>>(&Vc[(int64_t)min(u, mp - 1) * S.vvs + px]);
+    };
+    if (nt)
+      load(std::true_type{});
+    else
+      load(std::false_type{});
+    pvm = Vc[(int64_t)mp * S.vvs + px];
+    pwc = S.w[(int64_t)col * k + px];
+  }
   int m = -1;
   double inv = 0.0, e = 0.0;
   if (j > 0) {
@@ -445,6 +484,22 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     return un;
   };
   auto update = [&](auto nt_, int64_t x) { return m < 0 ? vn[x] : finish(nt_, x, 0, vm[x], wc[x]); };
+  // the same from the prefetched entries (this thread's slot px, 1 <= m <= kPre): the
+  // products in order, then q_m and u_{m+1} as finish() forms them
+  auto update_pre = [&]() {
+    double sc = pvm, sw = pwc;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u)
+      if (u < m) {
+        sc = fma(-cs2[u], pv[u], sc);
+        sw = fma(-ds[u], pv[u], sw);
+      }
+    const double q = sc * inv;
+    const double un = fma(-e, q, sw) * inv;
+    vm[px] = q;
+    vn[px] = un;
+    return un;
+  };
   // the same at two slots, the loads of both in flight together (x1 is stored only
   // if st1; otherwise it must still be a valid slot)
   auto update2 = [&](auto nt_, int64_t x0, int64_t x1, bool st1, double& r0, double& r1) {
@@ -511,23 +566,22 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   if (blockIdx.x == 0 && gridDim.x > 1) return;
   // the rest once per launch, with the basis loads compiled for the streaming choice
   auto tail = [&](auto nt_) {
-    int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
-    const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
     if (!use_precond) {
-      for (int64_t x = (int64_t)wb * kThreads + tid; x < k; x += (int64_t)nwb * kThreads) zc[x] = update(nt_, x);
+      const int wr = gridDim.x > 1 ? blockIdx.x - 1 : 0;  // row blocks in launch order
+      for (int64_t x = (int64_t)wr * kThreads + tid; x < k; x += (int64_t)nwb * kThreads) zc[x] = update(nt_, x);
       return;
     }
     // a contiguous run of the (class-ordered) blocks per workgroup, runs of one XCD
     // adjacent; consecutive blocks of one class are staged together and share every
     // read of their inverse (the apply gives each block the same bits as alone)
-    if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
-    const int per = (P.nblk + nwb - 1) / nwb;
-    const int bend = min(P.nblk, (wb + 1) * per);
-    for (int b = wb * per; b < bend;) {
-      const BlockGroup g = block_group(P, b, bend);
+    for (int b = b0; b < bend;) {
+      const BlockGroup g = b == b0 ? g0 : block_group(P, b, bend);
       const int o0 = g.o0, sb = g.sb, bc = g.bc, nb = g.nb;
       const int tot = nb * sb;
       __syncthreads();  // the previous group's apply has read xs (block 0: wsp is free)
+      if (pre && b == b0) {
+        if (tid < tot) xs[tid] = (Acc)update_pre();
+      } else
       // two slots per thread while there are two, then one
       for (int i0 = tid; i0 < tot; i0 += 2 * kThreads) {
         const int i1 = i0 + kThreads;
@@ -541,7 +595,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
         }
       }
       __syncthreads();
-      const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
+      const OpT* Mp = minv_op<OpT>(P, transpose != 0) + (b == b0 ? mb0 : P.bcls_off[bc]);
       auto put = [&](int v, int r, Acc val) {
         if (v < nb) zc[P.blk_slots[o0 + v * sb + r]] = (double)val;
       };
@@ -876,6 +930,67 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
   const double* Vc = S.V + (int64_t)col * k;
   const double* uj = Vc + (int64_t)j * S.vvs;
   const double* cc = S.c2 + (int64_t)col * P.d;
+  const bool nt = S.stream > 0 || (S.stream < 0 && stream_basis(j + 1, S.vvs));
+  double* p1 = S.part1 + (int64_t)col * S.ldv * S.nch;
+  double* p2 = S.part2 + (int64_t)col * S.ldv * S.nch;
+  // At most 32 basis vectors and 256 rows (one group of kDotUnroll vectors per wave,
+  // four rows per lane): the wave's basis entries are loaded before w is formed (they
+  // need no w), so their round trip overlaps the deflation's; the products then run
+  // in chunk_dots2's order.
+  const int nvec = j + 1, wave = tid >> 6, lane = tid & 63;
+  if (nvec <= kDotUnroll * kWaves && rows <= 4 * 64) {
+    const int i0 = wave * kDotUnroll;
+    double vv[4][kDotUnroll];
+    if (i0 < nvec) {
+      auto load = [&](auto nt_) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int u = 0; u < kDotUnroll; ++u)
+            vv[r][u] = ld_basis<kNT<decltype(nt_)>>(
+                &Vc[(int64_t)min(i0 + u, nvec - 1) * S.vvs + x0 + min(lane + 64 * r, rows - 1)]);
+      };
+      if (nt)
+        load(std::true_type{});
+      else
+        load(std::false_type{});
+    }
+    for (int q = tid; q < rows; q += kThreads) {
+      const int64_t slot = x0 + q;
+      double v = tc[slot];
+      if (defl) v -= deflation(P, cc, slot, transpose != 0);
+      wc[slot] = v;
+      wv[q] = v;
+      uv[q] = uj[slot];
+    }
+    __syncthreads();
+    if (i0 >= nvec) return;
+    double aw[kDotUnroll], au[kDotUnroll];
+#pragma unroll
+    for (int u = 0; u < kDotUnroll; ++u) aw[u] = au[u] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x = lane + 64 * r;
+      if (x < rows) {
+        const double wx = wv[x], ux = uv[x];
+#pragma unroll
+        for (int u = 0; u < kDotUnroll; ++u) {
+          aw[u] = fma(vv[r][u], wx, aw[u]);
+          au[u] = fma(vv[r][u], ux, au[u]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kDotUnroll; ++u) {
+      const double sw = wave_sum(aw[u]);
+      const double su = wave_sum(au[u]);
+      if (lane == 0 && i0 + u < nvec) {
+        p1[(int64_t)chunk * S.ldv + i0 + u] = sw;
+        p2[(int64_t)chunk * S.ldv + i0 + u] = su;
+      }
+    }
+    return;
+  }
   for (int q = tid; q < rows; q += kThreads) {
     const int64_t slot = x0 + q;
     double v = tc[slot];
@@ -885,12 +1000,10 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
     uv[q] = uj[slot];
   }
   __syncthreads();
-  double* p1 = S.part1 + (int64_t)col * S.ldv * S.nch;
-  double* p2 = S.part2 + (int64_t)col * S.ldv * S.nch;
-  if (S.stream > 0 || (S.stream < 0 && stream_basis(j + 1, S.vvs)))
-    chunk_dots2<true>(Vc, S.vvs, x0, rows, wv, uv, j + 1, p1, p2, S.ldv, chunk);
+  if (nt)
+    chunk_dots2<true>(Vc, S.vvs, x0, rows, wv, uv, nvec, p1, p2, S.ldv, chunk);
   else
-    chunk_dots2<false>(Vc, S.vvs, x0, rows, wv, uv, j + 1, p1, p2, S.ldv, chunk);
+    chunk_dots2<false>(Vc, S.vvs, x0, rows, wv, uv, nvec, p1, p2, S.ldv, chunk);
 }
 
 // Pre-reduction after gm_dots: the dots with w into dw and with u_j into h2, summed

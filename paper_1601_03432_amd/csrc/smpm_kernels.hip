@@ -239,21 +239,14 @@ __global__ __launch_bounds__(256) void k_schur_mfma(DevPlan P, const double* __r
   constexpr int kWaves = KT / 4;
   extern __shared__ double lds[];
   const int c0 = blockIdx.y * NC;
-  bool on[NC];
-  bool any = false;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    on[c] = c0 + c < nrhs && (!active || active[c0 + c]);
-    any = any || on[c];
-  }
-  if (!any) return;
   const int tile = xcd_block(blockIdx.x, gridDim.x);
   if (tile >= P.ntile) return;
+  // Nothing below waits for the columns' activity or the class's slot count until
+  // the staged values are written: the table loads, the operator fragments and the
+  // y gathers (in-bounds, masked afterwards) are all in flight first.
   const int n = P.n, no = 4 * n;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int J = P.tile_cls[tile];
-  const int ns = P.cls_nslots[J];
-  const int kdim = ADJ ? no : ns;
   // ys: the staged Y tiles [NC][kRows][kTileLd]; after the products the same space
   // holds the result tiles [NC][kWaves][kTile][kTileLd] (as many entries)
   Acc* ys = reinterpret_cast<Acc*>(lds);
@@ -285,37 +278,53 @@ __global__ __launch_bounds__(256) void k_schur_mfma(DevPlan P, const double* __r
     const int uu = q / kRows, kk = q - uu * kRows;
     sb[j] = ADJ ? dst[uu * 4 + min(kk / n, 3)] : src[uu];
   }
-  const bool row_ok = ADJ ? mr < ns : mr < no;
-  int slot[4];
+  // the output slots (row mr of the tile's elements; the transpose's rows end at the
+  // class's slot count, known later), clamped into the vector for the gathers of y
+  int slotg[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) slot[v] = row_ok && tb[v] >= 0 ? tb[v] + (ADJ ? mr : mr - srow * n) : -1;
+  for (int v = 0; v < 4; ++v)
+    slotg[v] = tb[v] >= 0 ? (int)min((int64_t)tb[v] + (ADJ ? mr : mr - srow * n), P.k - 1) : -1;
   // the Y tile as [kk][u]: forward gathers the element's own slots, transpose the
-  // neighbours' slots facing it
+  // neighbours' slots facing it (the gather index is clamped into the vector; entries
+  // past the contraction length kdim are masked once it is known)
   int gi[kPer];
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     const int q = tid + j * 16 * KT;
     const int uu = q / kRows, kk = q - uu * kRows;
     const int s = kk / n;
-    const bool ok = sb[j] >= 0 && kk < kdim;
-    gi[j] = ok ? sb[j] + (ADJ ? kk - s * n : kk) : -1;
+    gi[j] = sb[j] >= 0 ? (int)min((int64_t)sb[j] + (ADJ ? kk - s * n : kk), P.k - 1) : -1;
   }
   double yv[NC][4], st[NC][kPer];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const double* yc = y + (int64_t)(on[c] ? c0 + c : 0) * P.k;
+    const double* yc = y + (int64_t)(c0 + c < nrhs ? c0 + c : 0) * P.k;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) st[c][j] = yc[max(gi[j], 0)];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) yv[c][v] = yc[max(slot[v], 0)];
+    for (int v = 0; v < 4; ++v) yv[c][v] = yc[max(slotg[v], 0)];
   }
+  bool on[NC];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    on[c] = c0 + c < nrhs && (!active || active[c0 + c]);
+    any = any || on[c];
+  }
+  if (!any) return;
+  const int ns = P.cls_nslots[J];
+  const int kdim = ADJ ? no : ns;
+  const bool row_ok = ADJ ? mr < ns : mr < no;
+  int slot[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) slot[v] = row_ok && tb[v] >= 0 ? tb[v] + (ADJ ? mr : mr - srow * n) : -1;
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int q = tid + j * 16 * KT;
       const int uu = q / kRows, kk = q - uu * kRows;
-      ys[(c * kRows + kk) * kTileLd + uu] = gi[j] >= 0 ? (Acc)st[c][j] : Acc(0);
+      ys[(c * kRows + kk) * kTileLd + uu] = gi[j] >= 0 && kk < kdim ? (Acc)st[c][j] : Acc(0);
     }
   __syncthreads();
 
@@ -1173,10 +1182,16 @@ __global__ __launch_bounds__(256) void k_coarse_sides(DevPlan P, const double* _
                                                       const int* __restrict__ active) {
   __shared__ double cs[kDenseCoarseMax];
   const int col = blockIdx.y;
-  if (active && !active[col]) return;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int d = P.d;
+  // the first 512 entries of this wave's row of G (or G^T): they need nothing else,
+  // so their loads are issued before the column's activity and the sums are read
+  const double* Gp = (transpose ? P.GT : P.G) + (int64_t)min(i, d - 1) * d;
+  double g0[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) g0[u] = Gp[min(lane + u * 64, d - 1)];
+  if (active && !active[col]) return;
   const double* sc = ss + (int64_t)col * P.nsides;
   // the interface sums c_j = s(side a) + s(side b) into LDS, four per thread and
   // round: the index loads, then the gathers, are issued together
@@ -1200,10 +1215,12 @@ __global__ __launch_bounds__(256) void k_coarse_sides(DevPlan P, const double* _
   }
   __syncthreads();
   if (i >= d) return;
-  const double* Gp = (transpose ? P.GT : P.G) + (int64_t)i * d;
   // the row's products in lane order (j = lane, lane + 64, ...), its loads eight at a time
   double acc = 0.0;
-  for (int j0 = lane; j0 < d; j0 += 8 * 64) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (lane + u * 64 < d) acc = fma(g0[u], cs[lane + u * 64], acc);
+  for (int j0 = lane + 8 * 64; j0 < d; j0 += 8 * 64) {
     double g[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) g[u] = Gp[min(j0 + u * 64, d - 1)];
