@@ -582,10 +582,20 @@ void gm_epilogue(smpm_ctx* c, const GmState& S, int kind, bool tr, double* x1, i
   Workspace& W = c->ws;
   gm_close(P, S, nrhs, 0, kind, tr, s);  // chunks hold an even number of steps
   gm_finish(P, S, nrhs, x1, s);
-  launch_publish_i(W.iters, nrhs, W.hiters, s);
-  launch_publish(W.g, S.maxit + 1, W.hhist, s);
-  launch_publish(W.cs, S.maxit + 1, W.hhist_cs, s);
-  launch_publish(W.tolb, 1, W.hhist_tolb, s);
+  PublishSet ps = {};
+  ps.src[0] = W.g;
+  ps.dst[0] = W.hhist;
+  ps.n[0] = S.maxit + 1;
+  ps.src[1] = W.cs;
+  ps.dst[1] = W.hhist_cs;
+  ps.n[1] = S.maxit + 1;
+  ps.src[2] = W.tolb;
+  ps.dst[2] = W.hhist_tolb;
+  ps.n[2] = 1;
+  ps.isrc = W.iters;
+  ps.idst = W.hiters;
+  ps.in = nrhs;
+  launch_publish_set(ps, s);
 }
 
 // Reads what gm_epilogue published (after a synchronization).
@@ -705,16 +715,27 @@ void recover_x(smpm_ctx* c, int kind, bool tr, const double* bhat, const double*
   }
 }
 
-// |b - S x|^2 and |b|^2 per column into pinned hout[0..nrhs) and hout[nrhs..2 nrhs)
-void true_residual_enqueue(smpm_ctx* c, bool tr, const double* b, const double* x, int nrhs, hipStream_t s) {
+// |b - S x|^2 and |b|^2 per column into pinned hout[0..nrhs) and hout[nrhs..2 nrhs);
+// b2, if given, already holds |b|^2 (the same reduction of the same b)
+void true_residual_enqueue(smpm_ctx* c, bool tr, const double* b, const double* x, int nrhs, hipStream_t s,
+                           const double* b2 = nullptr) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   launch_schur(P, x, W.t, nrhs, tr, nullptr, s);
   launch_add(b, W.t, -1.0, W.w, P.k, nrhs, s);
   launch_mdot(W.w, 0, P.k, 1, W.w, P.k, nullptr, P.k, nrhs, W.part, W.scal, nullptr, s);
-  launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2, nullptr, s);
-  launch_publish(W.scal, nrhs, W.hout, s);
-  launch_publish(W.scal2, nrhs, W.hout + nrhs, s);
+  if (!b2) {
+    launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2, nullptr, s);
+    b2 = W.scal2;
+  }
+  PublishSet ps = {};
+  ps.src[0] = W.scal;
+  ps.dst[0] = W.hout;
+  ps.n[0] = nrhs;
+  ps.src[1] = b2;
+  ps.dst[1] = W.hout + nrhs;
+  ps.n[1] = nrhs;
+  launch_publish_set(ps, s);
 }
 
 void true_residual_read(smpm_ctx* c, int nrhs, std::vector<double>& out) {
@@ -1880,7 +1901,8 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     rc = run_phase(c, use_graph, 2, S, nrhs, kind, tr, PREC_F64, PREC_F64, o.tol, s, [&](hipStream_t q) {
       gm_epilogue(c, S, kind, tr, W.x, nrhs, q);
       recover_x(c, kind, tr, W.bhat, W.x, W.bS, nrhs, PREC_F64, PREC_F64, q);
-      true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q);
+      // |b_hat|^2 is the prologue's stopping reference (the same reduction of b_hat)
+      true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q, W.scal2 + 2 * nrhs);
       post_body(W.bS, q);
       launch_publish_i(W.nonfinite, 1, W.hnonfinite, q);
     });

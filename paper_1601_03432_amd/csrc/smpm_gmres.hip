@@ -1096,12 +1096,13 @@ __global__ __launch_bounds__(256) void k_gm_lsq(GmState S) {
       if (m <= i) rs[i * kLsqStage + m] = Hc[(int64_t)i * S.ldv + m];
     }
     __syncthreads();
+    // one wave: lane m keeps g_m in a register; the steps need no barrier
+    if (tid >= 64) return;
+    double g = tid < J ? gs[tid] : 0.0;
     for (int i = J - 1; i >= 0; --i) {
-      const double yi = gs[i] / rs[i * kLsqStage + i];
-      __syncthreads();
-      for (int m = tid; m < i; m += kThreads) gs[m] -= rs[i * kLsqStage + m] * yi;
+      const double yi = __shfl(g, i) / rs[i * kLsqStage + i];
+      if (tid < i) g = fma(-rs[i * kLsqStage + tid], yi, g);
       if (tid == 0) yc[i] = yi;
-      __syncthreads();
     }
     return;
   }
@@ -1109,7 +1110,7 @@ __global__ __launch_bounds__(256) void k_gm_lsq(GmState S) {
   for (int i = J - 1; i >= 0; --i) {
     const double yi = gs[i] / Hc[(int64_t)i * S.ldv + i];
     __syncthreads();
-    for (int m = tid; m < i; m += kThreads) gs[m] -= Hc[(int64_t)i * S.ldv + m] * yi;
+    for (int m = tid; m < i; m += kThreads) gs[m] = fma(-Hc[(int64_t)i * S.ldv + m], yi, gs[m]);
     if (tid == 0) yc[i] = yi;
     __syncthreads();
   }

@@ -280,6 +280,16 @@ void launch_fill_pattern(double* b, int64_t len, hipStream_t s);  // values in (
 // ---- small results into pinned (mapped, coherent) host memory by a kernel
 void launch_publish(const double* src, int n, double* host_dst, hipStream_t s);
 void launch_publish_i(const int* src, int n, int* host_dst, hipStream_t s);
+// up to four double ranges and one int range in one launch (unused entries: n = 0)
+struct PublishSet {
+  const double* src[4];
+  double* dst[4];
+  int n[4];
+  const int* isrc;
+  int* idst;
+  int in;
+};
+void launch_publish_set(const PublishSet& p, hipStream_t s);
 // hflag[i] = active[i], hratio[i] = res[i] / tolb[i]
 void launch_publish_flags(const int* active, const double* res, const double* tolb, int n, int* hflag,
                           double* hratio, hipStream_t s);

@@ -851,8 +851,15 @@ __global__ __launch_bounds__(64) void k_flux(DevPlan P, const double* __restrict
     if (j < 0) continue;
     const double* Hp = P.Hc + P.H_off[P.cls[j] * 4 + (s ^ 1)];
     double acc = 0.0;
-#pragma unroll 8
-    for (int l = 0; l < n2; ++l) acc = fma(Hp[l * n + i], fs[s * n2 + l], acc);
+    // 32 operator loads in flight per batch (in bounds), the products in order
+    for (int l0 = 0; l0 < n2; l0 += 32) {
+      double h[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) h[u] = Hp[min(l0 + u, n2 - 1) * n + i];
+#pragma unroll
+      for (int u = 0; u < 32; ++u)
+        if (l0 + u < n2) acc = fma(h[u], fs[s * n2 + l0 + u], acc);
+    }
     bc[P.side_slot[e * 4 + s] + i] = acc;
   }
 }
@@ -906,8 +913,15 @@ __global__ __launch_bounds__(256) void k_backsub(DevPlan P, const double* __rest
   const double* Ap = P.AinvT + (int64_t)P.cls[e] * n2 * n2;
   for (int l = tid; l < n2; l += 256) {
     double acc = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < n2; ++m) acc = fma(Ap[(int64_t)m * n2 + l], zs[m], acc);
+    // 32 operator loads in flight per batch (in bounds), the products in order
+    for (int m0 = 0; m0 < n2; m0 += 32) {
+      double a[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) a[u] = Ap[(int64_t)min(m0 + u, n2 - 1) * n2 + l];
+#pragma unroll
+      for (int u = 0; u < 32; ++u)
+        if (m0 + u < n2) acc = fma(a[u], zs[m0 + u], acc);
+    }
     uc[(int64_t)e * n2 + l] = acc;
   }
 }
@@ -926,8 +940,14 @@ __global__ __launch_bounds__(256) void k_local_adj(DevPlan P, const double* __re
   const double* Ap = P.Ainv + (int64_t)P.cls[e] * n2 * n2;
   for (int l = tid; l < n2; l += 256) {
     double acc = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < n2; ++m) acc = fma(Ap[(int64_t)m * n2 + l], cs[m], acc);
+    for (int m0 = 0; m0 < n2; m0 += 32) {
+      double a[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) a[u] = Ap[(int64_t)min(m0 + u, n2 - 1) * n2 + l];
+#pragma unroll
+      for (int u = 0; u < 32; ++u)
+        if (m0 + u < n2) acc = fma(a[u], cs[m0 + u], acc);
+    }
     if (to_slots)
       ws[l] = acc;
     else
@@ -1314,6 +1334,11 @@ __global__ void k_publish(const double* __restrict__ src, int n, double* dst) {
 __global__ void k_publish_i(const int* __restrict__ src, int n, int* dst) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
+}
+__global__ __launch_bounds__(256) void k_publish_set(PublishSet p) {
+  for (int q = 0; q < 4; ++q)
+    for (int i = threadIdx.x; i < p.n[q]; i += 256) p.dst[q][i] = p.src[q][i];
+  for (int i = threadIdx.x; i < p.in; i += 256) p.idst[i] = p.isrc[i];
 }
 // per column: activity flag and residual estimate / threshold
 __global__ void k_publish_flags(const int* __restrict__ active, const double* __restrict__ res,
@@ -1854,6 +1879,9 @@ void launch_publish(const double* src, int n, double* host_dst, hipStream_t s) {
 }
 void launch_publish_i(const int* src, int n, int* host_dst, hipStream_t s) {
   hipLaunchKernelGGL(k_publish_i, dim3((n + 255) / 256), dim3(256), 0, s, src, n, host_dst);
+}
+void launch_publish_set(const PublishSet& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish_set, dim3(1), dim3(256), 0, s, p);
 }
 void launch_publish_flags(const int* active, const double* res, const double* tolb, int n, int* hflag,
                           double* hratio, hipStream_t s) {
