@@ -12,6 +12,7 @@
 #include <string>
 #include <mutex>
 #include <thread>
+#include <functional>
 #include <vector>
 
 #include "../../include/smpm.h"
@@ -51,6 +52,8 @@ struct Workspace {
   double* xprev = nullptr;                  // iterate before the last correction
   double* cws = nullptr;                    // substructured coarse solve scratch
   double* ubuf = nullptr;                   // r x nrhs: back-substituted solution before the mean
+  double* w2 = nullptr;                     // k x nrhs: residual scratch of the post-processing (never
+                                            // the Arnoldi state, so it may run speculatively)
   double* tolv = nullptr;                   // device GMRES: tolerance and step counter
   int* jdev = nullptr;
   double *tolb = nullptr;
@@ -59,8 +62,10 @@ struct Workspace {
   double* hres = nullptr;  // 2 x nrhs residual-estimate ratios (per chunk slot)
   double* hout = nullptr;  // 4 x nrhs small results
   int* hiters = nullptr;   // nrhs iteration counts
-  int* nonfinite = nullptr;   // device flag: f or g held a non-finite entry
-  int* hnonfinite = nullptr;  // its pinned host copy
+  // f or g held a non-finite entry: a flag in the pinned (coherent) area, set by the
+  // kernels that first read f and g, cleared and read by the host around a solve
+  int* nonfinite = nullptr;
+  int* hnonfinite = nullptr;  // the same flag (host view)
   double* hhist = nullptr;    // pinned: column 0's rotated right-hand side g (maxit + 1) and tol |ref|
   double* hhist_cs = nullptr;
   double* hhist_tolb = nullptr;
@@ -219,6 +224,7 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.sides, (size_t)P.nsides * R);
   rc |= dalloc(w.mem, &w.xacc, k * R);
   rc |= dalloc(w.mem, &w.ubuf, r * R);
+  rc |= dalloc(w.mem, &w.w2, k * R);
   rc |= dalloc(w.mem, &w.xprev, k * R);
   rc |= dalloc(w.mem, &w.rho, k * R);
   rc |= dalloc(w.mem, &w.tolb, R);
@@ -230,7 +236,6 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.cws, (size_t)std::max<int64_t>(cstride, 1) * R);
   rc |= dalloc(w.mem, &w.tolv, 1);
   rc |= ialloc(w.mem, &w.jdev, 2);
-  rc |= ialloc(w.mem, &w.nonfinite, 1);
   if (rc != SMPM_OK) return SMPM_ENOMEM;
   c->dp.cws = w.cws;
   c->dp.cws_stride = cstride;
@@ -243,6 +248,7 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
       return fail(SMPM_ENOMEM, "hipHostMalloc failed");
     w.hiters = w.pinned + 2 * R;
     w.hnonfinite = w.pinned + 3 * R;
+    w.nonfinite = w.hnonfinite;
     w.hres = reinterpret_cast<double*>(reinterpret_cast<char*>(w.pinned) + ibytes);
     w.hout = w.hres + 2 * R;
     w.hhist = w.hout + 4 * R;
@@ -580,7 +586,8 @@ void gm_prologue(smpm_ctx* c, const GmState& S, int kind, bool tr, const double*
 void gm_epilogue(smpm_ctx* c, const GmState& S, int kind, bool tr, double* x1, int nrhs, hipStream_t s) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
-  gm_close(P, S, nrhs, 0, kind, tr, s);  // chunks hold an even number of steps
+  // every column has retired in a Givens step by the time the iterations end (the
+  // retirement test includes j >= maxit), so the Hessenberg columns are complete
   gm_finish(P, S, nrhs, x1, s);
   PublishSet ps = {};
   ps.src[0] = W.g;
@@ -614,12 +621,20 @@ int gm_collect(smpm_ctx* c, int nrhs, int maxit, double tol, std::vector<int>& i
 // pinned slot chunk % 2.  The host keeps one chunk queued ahead of the one it waits
 // for, except when the observed convergence rate says the queued chunk will finish
 // the solve: then it waits for that chunk instead of queueing steps that would find
-// every column retired.  Steps past maxit (the last chunk's tail) do nothing.  Returns
-// once every column has retired (no synchronization after the last chunk's event).
+// every column retired.  Steps past maxit (the last chunk's tail) do nothing.
+//
+// With post != nullptr the caller's post-processing (which must leave the Arnoldi
+// state alone) is queued right behind the chunk predicted to finish, so it runs
+// without waiting for the host; *post_done says whether the queued copy followed the
+// chunk that did finish.  If the prediction fails, the next chunk is queued after it
+// and the caller runs the post-processing again once the loop ends (the early copy
+// only wrote outputs the later one rewrites).  Returns once every column has retired
+// (no synchronization after the last chunk's event).
 int gm_loop(smpm_ctx* c, const GmState& S, int kind, bool tr, int nrhs, int maxit, hipStream_t s, int sprec,
-            int mprec, bool use_graph) {
+            int mprec, bool use_graph, const std::function<int()>* post = nullptr, bool* post_done = nullptr) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
+  if (post_done) *post_done = false;
   hipGraphExec_t exec = nullptr;
   if (use_graph) {
     const int rc = chunk_graph(c, S, nrhs, kind, tr, sprec, mprec, &exec);
@@ -627,7 +642,10 @@ int gm_loop(smpm_ctx* c, const GmState& S, int kind, bool tr, int nrhs, int maxi
   }
   // step j finishes Hessenberg column j - 2, so maxit columns take maxit + 2 steps
   const int nchunks = (maxit + 2 + kChunkIters - 1) / kChunkIters;
+  bool spec_live = false;  // a speculative post-processing is queued behind the last chunk
+  int spec_count = 0;
   auto launch_chunk = [&](int ch) -> int {
+    spec_live = false;  // steps queued behind it: it ran too early
     if (exec) {
       HIPCHK(hipGraphLaunch(exec, s));
     } else {
@@ -662,12 +680,22 @@ int gm_loop(smpm_ctx* c, const GmState& S, int kind, bool tr, int nrhs, int maxi
       steps_left = std::max(steps_left, left);
       prev_ratio[i] = r;
     }
-    if (!any || ci + 1 >= nchunks) break;
+    if (!any || ci + 1 >= nchunks) {
+      // the queued copy is valid if nothing was queued after this chunk but it
+      if (post_done) *post_done = spec_live && launched == ci + 1;
+      break;
+    }
     // the chunk queued after ci covers the next kChunkIters steps
     finishing = steps_left <= kChunkIters;
     if (launched == ci + 1) {
       rc0 = launch_chunk(launched++);
       if (rc0) return rc0;
+    }
+    if (post && finishing && !spec_live && spec_count < 2 && launched == ci + 2) {
+      rc0 = (*post)();
+      if (rc0) return rc0;
+      spec_live = true;
+      ++spec_count;
     }
   }
   return SMPM_OK;
@@ -708,8 +736,8 @@ void recover_x(smpm_ctx* c, int kind, bool tr, const double* bhat, const double*
     // x = z + Z G Z^T (b_hat - S z), z = M^{-1} x1
     launch_precond(P, x1, W.z, nrhs, tr, nullptr, s, mprec);
     launch_schur_ex(P, W.z, W.t, nrhs, tr, nullptr, nullptr, s, sprec);
-    launch_add(bhat, W.t, -1.0, W.w, P.k, nrhs, s);
-    launch_iface_sum(P, W.w, W.c, nrhs, nullptr, s);
+    launch_add(bhat, W.t, -1.0, W.w2, P.k, nrhs, s);
+    launch_iface_sum(P, W.w2, W.c, nrhs, nullptr, s);
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
     launch_prolong(P, W.z, W.c2, x, nrhs, 0, 1.0, nullptr, s);
   }
@@ -722,8 +750,8 @@ void true_residual_enqueue(smpm_ctx* c, bool tr, const double* b, const double* 
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   launch_schur(P, x, W.t, nrhs, tr, nullptr, s);
-  launch_add(b, W.t, -1.0, W.w, P.k, nrhs, s);
-  launch_mdot(W.w, 0, P.k, 1, W.w, P.k, nullptr, P.k, nrhs, W.part, W.scal, nullptr, s);
+  launch_add(b, W.t, -1.0, W.w2, P.k, nrhs, s);
+  launch_mdot(W.w2, 0, P.k, 1, W.w2, P.k, nullptr, P.k, nrhs, W.part, W.scal, nullptr, s);
   if (!b2) {
     launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2, nullptr, s);
     b2 = W.scal2;
@@ -1819,7 +1847,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   // SMPM_EINVAL once the solve has run (a NaN estimate retires its column at once).
   // That kernel copies the user's data into W.rhs (adding T g); every later step works
   // on workspace buffers, so the phases below can be replayed from captured graphs.
-  HIPCHK(hipMemsetAsync(W.nonfinite, 0, sizeof(int), s));
+  *W.hnonfinite = 0;  // nothing of an earlier solve is in flight (each ends synchronized)
   launch_rhs(P, f, tr ? nullptr : g, W.rhs, nrhs, W.nonfinite, s);
   auto pre_body = [&](hipStream_t q) {
     if (!tr) {
@@ -1895,19 +1923,28 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     });
     if (rc) return rc;
     mark(1);
-    rc = gm_loop(c, S, kind, tr, nrhs, o.maxit, s, PREC_F64, PREC_F64, use_graph);
+    // the post-processing touches no Arnoldi state (its residual scratch is W.w2), so
+    // the loop may queue it behind the chunk it predicts to be the last
+    const std::function<int()> post = [&]() -> int {
+      mark(2);
+      const int r = run_phase(c, use_graph, 2, S, nrhs, kind, tr, PREC_F64, PREC_F64, o.tol, s, [&](hipStream_t q) {
+        gm_epilogue(c, S, kind, tr, W.x, nrhs, q);
+        recover_x(c, kind, tr, W.bhat, W.x, W.bS, nrhs, PREC_F64, PREC_F64, q);
+        // |b_hat|^2 is the prologue's stopping reference (the same reduction of b_hat)
+        true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q, W.scal2 + 2 * nrhs);
+        post_body(W.bS, q);
+      });
+      if (r) return r;
+      store_u(s);
+      return SMPM_OK;
+    };
+    bool post_done = false;
+    rc = gm_loop(c, S, kind, tr, nrhs, o.maxit, s, PREC_F64, PREC_F64, use_graph, &post, &post_done);
     if (rc) return rc;
-    mark(2);
-    rc = run_phase(c, use_graph, 2, S, nrhs, kind, tr, PREC_F64, PREC_F64, o.tol, s, [&](hipStream_t q) {
-      gm_epilogue(c, S, kind, tr, W.x, nrhs, q);
-      recover_x(c, kind, tr, W.bhat, W.x, W.bS, nrhs, PREC_F64, PREC_F64, q);
-      // |b_hat|^2 is the prologue's stopping reference (the same reduction of b_hat)
-      true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q, W.scal2 + 2 * nrhs);
-      post_body(W.bS, q);
-      launch_publish_i(W.nonfinite, 1, W.hnonfinite, q);
-    });
-    if (rc) return rc;
-    store_u(s);
+    if (!post_done) {
+      rc = post();
+      if (rc) return rc;
+    }
     HIPCHK(hipStreamSynchronize(s));
     gm_collect(c, nrhs, o.maxit, o.tol, iters);
     note_cycle(iters);
@@ -2060,7 +2097,6 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     mark(2);
     post_body(W.xacc, s);
     store_u(s);
-    launch_publish_i(W.nonfinite, 1, W.hnonfinite, s);
   }
   mark(3);
   HIPCHK(hipGetLastError());

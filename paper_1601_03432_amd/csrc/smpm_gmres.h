@@ -61,7 +61,6 @@ void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStrea
 void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s,
              int sprec = PREC_F64, int mprec = PREC_F64);
 // Givens step for the column the next step would finish (par = steps % 2)
-void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s);
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s);
 int gm_rows_per_chunk(int64_t k);
 

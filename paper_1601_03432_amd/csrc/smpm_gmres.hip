@@ -294,10 +294,8 @@ __device__ __forceinline__ BlockGroup block_group(const DevPlan& P, int b, int b
 }
 
 // Step j's first kernel (see the file header; m = j - 1).  Step 0: z = M^{-1} u_0.
-// givens_only: stop after the Givens step (the last step of a solve).
 template <typename OpT, bool PRE>
-__global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par, int use_precond, int transpose,
-                                                   int givens_only) {
+__global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par, int use_precond, int transpose) {
   using Acc = typename AccOf<OpT>::type;
   constexpr int kGroup = kGroupBlocks;
   static_assert(kStageSlots >= 8 * kMaxN, "one block must fit the staging area");
@@ -316,7 +314,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   // The slot blocks' run of block-Jacobi blocks and its first group: their table loads
   // depend on nothing, so they are issued before anything waits (the column's
   // activity, the step index); the tail reuses them.
-  const bool slot_block = use_precond && !givens_only && (gridDim.x == 1 || blockIdx.x > 0);
+  const bool slot_block = use_precond && (gridDim.x == 1 || blockIdx.x > 0);
   int wb = gridDim.x > 1 ? blockIdx.x - 1 : 0;
   const int nwb = gridDim.x > 1 ? gridDim.x - 1 : 1;
   if (nwb % 8 == 0) wb = xcd_block(wb, nwb);
@@ -433,9 +431,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
         __syncthreads();
       }
     }
-    if (givens_only || m >= S.maxit) return;
-  } else if (givens_only) {
-    return;
+    if (m >= S.maxit) return;
   }
   // q_m into V_m and u_{m+1} into V_{m+1} at one slot; returns u_{m+1} (step 0: u_0)
   const double* wc = S.w + (int64_t)col * k;
@@ -918,13 +914,19 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
   __shared__ double wv[kRowsMax];
   __shared__ double uv[kRowsMax];
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
+  const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
+  const int rows = (int)min((int64_t)S.rows, k - x0);
+  // with one row per thread, the row's t and its deflation table entry need nothing
+  // of this step's counters: their loads go out first
+  const int64_t xt = x0 + min(tid, rows - 1);
+  const double tv0 = S.t[(int64_t)col * k + xt];
+  int4 ta = {0, 0, 0, 0}, tb = {0, 0, 0, 0};
+  if (defl && rows <= kThreads) deflation_table(P, xt, transpose != 0, ta, tb);
   const int j = S.jdev[par];
   // the step's last kernel sets the next step's index in the other slot (whatever the
   // columns' activity, so steps keep counting)
   if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) S.jdev[par ^ 1] = j + 1;
   if (!S.active[col] || j > S.maxit) return;
-  const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
-  const int rows = (int)min((int64_t)S.rows, k - x0);
   const double* tc = S.t + (int64_t)col * k;
   double* wc = S.w + (int64_t)col * k;
   const double* Vc = S.V + (int64_t)col * k;
@@ -955,13 +957,12 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
       else
         load(std::false_type{});
     }
-    for (int q = tid; q < rows; q += kThreads) {
-      const int64_t slot = x0 + q;
-      double v = tc[slot];
-      if (defl) v -= deflation(P, cc, slot, transpose != 0);
-      wc[slot] = v;
-      wv[q] = v;
-      uv[q] = uj[slot];
+    if (tid < rows) {
+      double v = tv0;
+      if (defl) v -= deflation_tb(P, cc, xt, transpose != 0, ta, tb);
+      wc[xt] = v;
+      wv[tid] = v;
+      uv[tid] = uj[xt];
     }
     __syncthreads();
     if (i0 >= nvec) return;
@@ -1172,9 +1173,9 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
   } else {
 #define SMPM_UPDATE_1(T)                                                                                   \
   if (S.prereduce)                                                                                          \
-    hipLaunchKernelGGL((k_gm_update<T, true>), pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);            \
+    hipLaunchKernelGGL((k_gm_update<T, true>), pg, dim3(kThreads), 0, s, P, S, par, up, trn);               \
   else                                                                                                      \
-    hipLaunchKernelGGL((k_gm_update<T, false>), pg, dim3(kThreads), 0, s, P, S, par, up, trn, 0);
+    hipLaunchKernelGGL((k_gm_update<T, false>), pg, dim3(kThreads), 0, s, P, S, par, up, trn);
     if (mprec == PREC_F32) {
       SMPM_UPDATE_1(float)
     } else if (mprec == PREC_BF16) {
@@ -1198,15 +1199,6 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
                      tr ? 1 : 0);
   if (S.prereduce)
     hipLaunchKernelGGL(k_gm_reduce, dim3((S.maxit + kReduceVecs) / kReduceVecs, nrhs), dim3(256), 0, s, S, par);
-}
-
-void gm_close(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s) {
-  if (S.prereduce)
-    hipLaunchKernelGGL((k_gm_update<double, true>), dim3(1, nrhs), dim3(kThreads), 0, s, P, S, par,
-                       kind == 1 ? 0 : 1, tr ? 1 : 0, 1);
-  else
-    hipLaunchKernelGGL((k_gm_update<double, false>), dim3(1, nrhs), dim3(kThreads), 0, s, P, S, par,
-                       kind == 1 ? 0 : 1, tr ? 1 : 0, 1);
 }
 
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s) {

@@ -195,6 +195,32 @@ __device__ __forceinline__ void block_jacobi_apply(const OpT* __restrict__ Mp, c
 // (Z c2 + S Z c2)[slot] (forward) or (Z c2 + S^T Z c2)[slot] (transpose): the coarse
 // value of the slot's interface plus the coupling of the interfaces the side's
 // flux reaches, from the side's table entry (two 16-byte loads), then the values.
+// The side's table entry (two int4) of a slot, for deflation_tb.
+__device__ __forceinline__ void deflation_table(const DevPlan& P, int64_t slot, bool transpose, int4& a, int4& b) {
+  const int4* tb = reinterpret_cast<const int4*>((transpose ? P.side_adj : P.side_fwd) + (slot / P.n) * 8);
+  a = tb[0];
+  b = tb[1];
+}
+// deflation() from the slot's table entry, loaded beforehand
+__device__ __forceinline__ double deflation_tb(const DevPlan& P, const double* __restrict__ cc, int64_t slot,
+                                               bool transpose, int4 a, int4 b) {
+  const int n = P.n;
+  const int tt = (int)(slot % n);
+  const int js[4] = {a.y, a.z, a.w, b.x};
+  double acc = cc[a.x];
+  if (!transpose) {
+    const double* wz = P.WZ + b.y + tt * 4;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+      if (js[s2] >= 0) acc = fma(wz[s2], cc[js[s2]], acc);
+  } else {
+    const int cidx = (int)(slot - b.z);
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+      if (js[s2] >= 0) acc = fma(P.WZc[(int64_t)b.y + s2 * 4 * n + cidx], cc[js[s2]], acc);
+  }
+  return acc;
+}
 __device__ __forceinline__ double deflation(const DevPlan& P, const double* __restrict__ cc, int64_t slot,
                                             bool transpose) {
   const int n = P.n;

@@ -1211,6 +1211,14 @@ __global__ __launch_bounds__(256) void k_coarse_sides(DevPlan P, const double* _
   double g0[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) g0[u] = Gp[min(lane + u * 64, d - 1)];
+  // the first round's interface side indices, also before the activity check
+  int sa0[4], sb0[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = min((int)threadIdx.x + u * 256, d - 1);
+    sa0[u] = P.iface_side[2 * j];
+    sb0[u] = P.iface_side[2 * j + 1];
+  }
   if (active && !active[col]) return;
   const double* sc = ss + (int64_t)col * P.nsides;
   // the interface sums c_j = s(side a) + s(side b) into LDS, four per thread and
@@ -1220,8 +1228,8 @@ __global__ __launch_bounds__(256) void k_coarse_sides(DevPlan P, const double* _
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = min(j0 + u * 256, d - 1);
-      sa[u] = P.iface_side[2 * j];
-      sb[u] = P.iface_side[2 * j + 1];
+      sa[u] = j0 == (int)threadIdx.x ? sa0[u] : P.iface_side[2 * j];
+      sb[u] = j0 == (int)threadIdx.x ? sb0[u] : P.iface_side[2 * j + 1];
     }
     double va[4], vb[4];
 #pragma unroll
