@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -71,7 +72,7 @@ struct Workspace {
   double* hhist_tolb = nullptr;
   int hist_len = 0;           // entries of the last GMRES run's history (iterations + 1)
   double hist_tol = 1.0;      // that run's relative tolerance (threshold = tol * reference)
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  int* hseq = nullptr;  // pinned: chunks of Arnoldi steps reported by the device (GmState)
   int nch = 0, rows = 0;
   std::vector<void*> mem;
 };
@@ -119,8 +120,6 @@ struct smpm_ctx {
       if (group_stream) (void)hipStreamDestroy(group_stream);
       for (void* p : ws.mem) (void)hipFree(p);
       if (ws.pinned) (void)hipHostFree(ws.pinned);
-      for (hipEvent_t e : ws.ev)
-        if (e) (void)hipEventDestroy(e);
       for (void* p : mem) (void)hipFree(p);
     }
   }
@@ -184,8 +183,6 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   maxit = std::max(maxit, w.maxit);
   for (void* p : w.mem) (void)hipFree(p);
   if (w.pinned) (void)hipHostFree(w.pinned);
-  for (hipEvent_t e : w.ev)
-    if (e) (void)hipEventDestroy(e);
   w = Workspace();
   const Plan& P = c->plan;
   const size_t r = P.r, k = P.k, d = std::max<int64_t>(P.d, 1), R = nrhs, ldh = maxit + 1;
@@ -240,24 +237,22 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   c->dp.cws = w.cws;
   c->dp.cws_stride = cstride;
   {
-    // [flags 2R ints | iters R ints | non-finite flag | pad] [hres 2R doubles] [hout 4R doubles]
-    // [rotated rhs g: ldh doubles | Givens cosines: ldh doubles | threshold]
-    const size_t ibytes = (((3 * R + 1) * sizeof(int) + 63) / 64) * 64;
+    // [flags 2R ints | iters R ints | non-finite flag | chunk count | pad] [hres 2R doubles]
+    // [hout 4R doubles] [rotated rhs g: ldh doubles | Givens cosines: ldh doubles | threshold]
+    const size_t ibytes = (((3 * R + 2) * sizeof(int) + 63) / 64) * 64;
     const size_t bytes = ibytes + (6 * R + 2 * ldh + 1) * sizeof(double);
     if (hipHostMalloc((void**)&w.pinned, bytes, hipHostMallocCoherent) != hipSuccess)
       return fail(SMPM_ENOMEM, "hipHostMalloc failed");
     w.hiters = w.pinned + 2 * R;
     w.hnonfinite = w.pinned + 3 * R;
     w.nonfinite = w.hnonfinite;
+    w.hseq = w.pinned + 3 * R + 1;
     w.hres = reinterpret_cast<double*>(reinterpret_cast<char*>(w.pinned) + ibytes);
     w.hout = w.hres + 2 * R;
     w.hhist = w.hout + 4 * R;
     w.hhist_cs = w.hhist + ldh;
     w.hhist_tolb = w.hhist_cs + ldh;
   }
-  for (int i = 0; i < 2; ++i)
-    if (hipEventCreateWithFlags(&w.ev[i], hipEventDisableTiming) != hipSuccess)
-      return fail(SMPM_EHIP, "hipEventCreate failed");
   if (hipDeviceSynchronize() != hipSuccess) return fail(SMPM_EHIP, "hipDeviceSynchronize failed");
   w.nrhs = nrhs;
   w.maxit = maxit;
@@ -439,6 +434,9 @@ int gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nrhs, 
   return jmax;
 }
 
+// Arnoldi steps per replayed chunk (and per progress report to the host)
+constexpr int kChunkIters = 8;
+
 GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   Workspace& W = c->ws;
   GmState S;
@@ -479,19 +477,18 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.stream = -1;  // test hook: SMPM_STREAM_BASIS=1 / 0 forces one kind of basis load
   if (const char* e = std::getenv("SMPM_STREAM_BASIS")) S.stream = e[0] == '1' ? 1 : e[0] == '0' ? 0 : -1;
   S.bref2 = W.scal2 + 2 * nrhs;
+  S.hflag = W.pinned;
+  S.hratio = W.hres;
+  S.hseq = W.hseq;
+  S.pub_stride = W.nrhs;
+  S.pub_every = kChunkIters;
   return S;
 }
 
-// The executable graph of kChunkIters Arnoldi steps and the publication of the
-// columns' activity flags and residual ratios (pinned slot chunk % 2) for this solve
-// shape (captured on first use on the context's capture stream; nothing runs during
-// the capture).
-constexpr int kChunkIters = 8;
 constexpr size_t kMaxGraphs = 32;  // executable graphs kept per context (oldest dropped)
-void publish_chunk(smpm_ctx* c, const GmState& S, int nrhs, hipStream_t s) {
-  Workspace& W = c->ws;
-  launch_publish_chunk(W.active, W.res, W.tolb, nrhs, S.jdev, kChunkIters, W.pinned, W.hres, W.nrhs, s);
-}
+// The executable graph of kChunkIters Arnoldi steps for this solve shape (its last
+// step reports the columns' progress to the host; captured on first use on the
+// context's capture stream; nothing runs during the capture).
 
 int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int sprec, int mprec,
                 hipGraphExec_t* out) {
@@ -507,7 +504,6 @@ int chunk_graph(smpm_ctx* c, const GmState& S, int nrhs, int kind, bool tr, int 
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   for (int q = 0; q < kChunkIters; ++q) gm_step(c->dp, S, nrhs, q & 1, kind, tr, c->cap_stream, sprec, mprec);
-  publish_chunk(c, S, nrhs, c->cap_stream);
   const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &graph);
   if (e1 != hipSuccess || !graph) return fail(SMPM_EHIP, "hipStreamEndCapture failed");
   hipGraphExec_t exec = nullptr;
@@ -616,12 +612,13 @@ int gm_collect(smpm_ctx* c, int nrhs, int maxit, double tol, std::vector<int>& i
   return jmax;
 }
 
-// The Arnoldi iterations after gm_prologue: chunks of kChunkIters steps; after each, a
-// kernel publishes the activity flags and residual ratios (estimate / threshold) into
-// pinned slot chunk % 2.  The host keeps one chunk queued ahead of the one it waits
-// for, except when the observed convergence rate says the queued chunk will finish
-// the solve: then it waits for that chunk instead of queueing steps that would find
-// every column retired.  Steps past maxit (the last chunk's tail) do nothing.
+// The Arnoldi iterations after gm_prologue: chunks of kChunkIters steps; the last step
+// of each reports the activity flags and residual ratios (estimate / threshold) into
+// pinned slot chunk % 2, then the chunk count, which the host polls.  The host keeps
+// one chunk queued ahead of the one it waits for (so a slot is never rewritten while
+// it is read), except when the observed convergence rate says the queued chunk will
+// finish the solve: then it waits for that chunk instead of queueing steps that would
+// find every column retired.  Steps past maxit (the last chunk's tail) do nothing.
 //
 // With post != nullptr the caller's post-processing (which must leave the Arnoldi
 // state alone) is queued right behind the chunk predicted to finish, so it runs
@@ -629,7 +626,7 @@ int gm_collect(smpm_ctx* c, int nrhs, int maxit, double tol, std::vector<int>& i
 // chunk that did finish.  If the prediction fails, the next chunk is queued after it
 // and the caller runs the post-processing again once the loop ends (the early copy
 // only wrote outputs the later one rewrites).  Returns once every column has retired
-// (no synchronization after the last chunk's event).
+// (queued work may still be running).
 int gm_loop(smpm_ctx* c, const GmState& S, int kind, bool tr, int nrhs, int maxit, hipStream_t s, int sprec,
             int mprec, bool use_graph, const std::function<int()>* post = nullptr, bool* post_done = nullptr) {
   const DevPlan& P = c->dp;
@@ -646,15 +643,30 @@ int gm_loop(smpm_ctx* c, const GmState& S, int kind, bool tr, int nrhs, int maxi
   int spec_count = 0;
   auto launch_chunk = [&](int ch) -> int {
     spec_live = false;  // steps queued behind it: it ran too early
+    (void)ch;
     if (exec) {
       HIPCHK(hipGraphLaunch(exec, s));
     } else {
       for (int q = 0; q < kChunkIters; ++q) gm_step(P, S, nrhs, q & 1, kind, tr, s, sprec, mprec);
-      publish_chunk(c, S, nrhs, s);
     }
-    HIPCHK(hipEventRecord(W.ev[ch & 1], s));
     return SMPM_OK;
   };
+  // the device's report of chunk ci (its count in pinned memory, written after the
+  // flags with a system-scope fence); the stream is polled now and then so that an
+  // error, or work that ended without the report, returns instead of waiting forever
+  auto wait_chunk = [&](int ci) -> int {
+    volatile int* seq = W.hseq;
+    for (long spins = 1; *seq < ci + 1; ++spins) {
+      if (spins % 2048 == 0) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipSuccess && *seq < ci + 1) return fail(SMPM_EHIP, "a chunk of Arnoldi steps ended unreported");
+        if (e != hipSuccess && e != hipErrorNotReady) return fail(SMPM_EHIP, hipGetErrorString(e));
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return SMPM_OK;
+  };
+  *W.hseq = 0;  // the stream is idle: every caller synchronizes before and after a loop
   std::vector<double> prev_ratio(nrhs, -1.0);
   int launched = 0;
   bool finishing = false;  // the chunk in flight is predicted to complete every column
@@ -665,7 +677,8 @@ int gm_loop(smpm_ctx* c, const GmState& S, int kind, bool tr, int nrhs, int maxi
       rc0 = launch_chunk(launched++);
       if (rc0) return rc0;
     }
-    HIPCHK(hipEventSynchronize(W.ev[ci & 1]));
+    rc0 = wait_chunk(ci);
+    if (rc0) return rc0;
     const int* fl = W.pinned + (ci & 1) * W.nrhs;
     const double* ra = W.hres + (ci & 1) * W.nrhs;
     bool any = false;
@@ -744,9 +757,10 @@ void recover_x(smpm_ctx* c, int kind, bool tr, const double* bhat, const double*
 }
 
 // |b - S x|^2 and |b|^2 per column into pinned hout[0..nrhs) and hout[nrhs..2 nrhs);
-// b2, if given, already holds |b|^2 (the same reduction of the same b)
+// b2, if given, already holds |b|^2 (the same reduction of the same b); extra, if
+// given, nrhs more values published into hout[2 nrhs..3 nrhs)
 void true_residual_enqueue(smpm_ctx* c, bool tr, const double* b, const double* x, int nrhs, hipStream_t s,
-                           const double* b2 = nullptr) {
+                           const double* b2 = nullptr, const double* extra = nullptr) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   launch_schur(P, x, W.t, nrhs, tr, nullptr, s);
@@ -763,6 +777,11 @@ void true_residual_enqueue(smpm_ctx* c, bool tr, const double* b, const double* 
   ps.src[1] = b2;
   ps.dst[1] = W.hout + nrhs;
   ps.n[1] = nrhs;
+  if (extra) {
+    ps.src[2] = extra;
+    ps.dst[2] = W.hout + 2 * nrhs;
+    ps.n[2] = nrhs;
+  }
   launch_publish_set(ps, s);
 }
 
@@ -1849,21 +1868,21 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   // on workspace buffers, so the phases below can be replayed from captured graphs.
   *W.hnonfinite = 0;  // nothing of an earlier solve is in flight (each ends synchronized)
   launch_rhs(P, f, tr ? nullptr : g, W.rhs, nrhs, W.nonfinite, s);
+  // u_L^T (f + T g) (adjoint: 1^T c) per column, published with the post-processing
+  double* removed = W.scal2 + 3 * nrhs;
   auto pre_body = [&](hipStream_t q) {
     if (!tr) {
       // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
-      launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, q);
-      launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, q);  // read after the final synchronization
-      launch_axpy_shared(W.rhs, Pl.r, c->uL, W.scal, 1.0, W.ft, Pl.r, nrhs, q);
+      launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, removed, nullptr, q);
+      launch_axpy_shared(W.rhs, Pl.r, c->uL, removed, 1.0, W.ft, Pl.r, nrhs, q);
       launch_flux(P, W.ft, W.bS, nrhs, q);
       launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
       launch_axpy_shared(W.bS, Pl.k, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, q);
     } else {
       // adjoint of the solution map: c~ = c - w (1^T c)/(w^T 1); S^T xi = E^T A^{-T} c~
       // (consistent: v0^T E^T A^{-T} c~ = -1^T c~ = 0), projected off v0 against rounding
-      launch_mdot(c->ones, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, q);
-      launch_publish(W.scal, nrhs, W.hout + 2 * nrhs, q);  // read after the final synchronization
-      launch_axpy_shared(W.rhs, Pl.r, c->wq, W.scal, 1.0 / c->wsum, W.ft, Pl.r, nrhs, q);
+      launch_mdot(c->ones, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, removed, nullptr, q);
+      launch_axpy_shared(W.rhs, Pl.r, c->wq, removed, 1.0 / c->wsum, W.ft, Pl.r, nrhs, q);
       launch_local_adj(P, W.ft, W.bS, nrhs, true, q);
       launch_mdot(c->v0hat, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
       launch_axpy_shared(W.bS, Pl.k, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, q);
@@ -1931,7 +1950,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
         gm_epilogue(c, S, kind, tr, W.x, nrhs, q);
         recover_x(c, kind, tr, W.bhat, W.x, W.bS, nrhs, PREC_F64, PREC_F64, q);
         // |b_hat|^2 is the prologue's stopping reference (the same reduction of b_hat)
-        true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q, W.scal2 + 2 * nrhs);
+        true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q, W.scal2 + 2 * nrhs, removed);
         post_body(W.bS, q);
       });
       if (r) return r;
@@ -2097,6 +2116,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     mark(2);
     post_body(W.xacc, s);
     store_u(s);
+    launch_publish(removed, nrhs, W.hout + 2 * nrhs, s);
   }
   mark(3);
   HIPCHK(hipGetLastError());

@@ -48,6 +48,15 @@ struct GmState {
   const double* bref2;  // squared reference norm per column (|b|^2): stop when |g| <= tol |b|
   int stream;       // basis loads: -1 non-temporal once a pass reads more than the
                     // last-level cache keeps, 0 always ordinary, 1 always non-temporal
+  // progress for the host (pinned, coherent memory): the step that completes every
+  // pub_every-th step (0: none) writes each column's activity flag and residual
+  // estimate / threshold into slot (chunk % 2) of hflag / hratio (pub_stride entries
+  // a slot), then, after a system-scope fence, the number of such chunks into *hseq
+  int* hflag;
+  double* hratio;
+  int* hseq;
+  int pub_stride;
+  int pub_every;
 };
 
 // u_0 = w into V_0, all columns active, j = 0 and the tolerance on the device
@@ -60,7 +69,7 @@ void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStrea
 // sprec / mprec: OpPrec of the Schur and block-Jacobi operators
 void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bool tr, hipStream_t s,
              int sprec = PREC_F64, int mprec = PREC_F64);
-// Givens step for the column the next step would finish (par = steps % 2)
+// y = R^{-1} g over each column's iterations, then x = V y
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s);
 int gm_rows_per_chunk(int64_t k);
 

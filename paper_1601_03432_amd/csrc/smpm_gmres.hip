@@ -926,6 +926,18 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
   // the step's last kernel sets the next step's index in the other slot (whatever the
   // columns' activity, so steps keep counting)
   if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) S.jdev[par ^ 1] = j + 1;
+  // the step that completes a chunk reports the columns' progress to the host (the
+  // flags were set by this step's first kernel)
+  if (S.pub_every > 0 && blockIdx.x == 0 && blockIdx.y == 0 && (j + 1) % S.pub_every == 0) {
+    const int done = (j + 1) / S.pub_every, slot = (done - 1) & 1;
+    for (int i = tid; i < (int)gridDim.y; i += kThreads) {
+      S.hflag[slot * S.pub_stride + i] = S.active[i];
+      S.hratio[slot * S.pub_stride + i] = S.tolb[i] > 0.0 ? S.res[i] / S.tolb[i] : 0.0;
+    }
+    __threadfence_system();
+    __syncthreads();
+    if (tid == 0) S.hseq[0] = done;
+  }
   if (!S.active[col] || j > S.maxit) return;
   const double* tc = S.t + (int64_t)col * k;
   double* wc = S.w + (int64_t)col * k;

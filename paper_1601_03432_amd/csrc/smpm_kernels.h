@@ -316,13 +316,6 @@ struct PublishSet {
   int in;
 };
 void launch_publish_set(const PublishSet& p, hipStream_t s);
-// hflag[i] = active[i], hratio[i] = res[i] / tolb[i]
-void launch_publish_flags(const int* active, const double* res, const double* tolb, int n, int* hflag,
-                          double* hratio, hipStream_t s);
-// as launch_publish_flags after a chunk of steps Arnoldi steps, into slot
-// (jdev[0] / steps - 1) % 2 of hflag / hratio (stride entries per slot)
-void launch_publish_chunk(const int* active, const double* res, const double* tolb, int n, const int* jdev, int steps,
-                          int* hflag, double* hratio, int stride, hipStream_t s);
 
 // ---- vector kernels over nrhs columns of length len (column stride ld)
 int reduce_chunks(int64_t len);

@@ -926,6 +926,141 @@ __global__ __launch_bounds__(256) void k_backsub(DevPlan P, const double* __rest
   }
 }
 
+// ---- element applies on the matrix cores (n <= 16): one block takes a tile of up to
+// 16 elements of one class, stages their vectors in LDS ([contraction][element]) and
+// multiplies by the class operator with FP64 16x16x4 MFMAs, so the operator is read
+// once per tile instead of once per element.  Lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; register v of lane l holds C[(l >> 4) + 4v][l % 16].  Results
+// go back through LDS so that consecutive lanes store consecutive rows.
+constexpr int kMmaN2 = 256;  // largest n^2 of these kernels (n <= 16)
+constexpr int kMmaBatch = 32;  // operator loads in flight per lane
+
+// A operand row `row` (clamped in) of a row-major source, loaded for k-steps
+// m0 + 4q + kk, q < kMmaBatch; entries past `len` or of invalid rows are zero
+template <typename Ld>
+__device__ __forceinline__ void mma_load_a(double (&a)[kMmaBatch], int m0, int kk, int len, bool rok, Ld ld) {
+#pragma unroll
+  for (int q = 0; q < kMmaBatch; ++q) a[q] = ld(min(m0 + 4 * q + kk, len - 1));
+#pragma unroll
+  for (int q = 0; q < kMmaBatch; ++q)
+    if (!rok || m0 + 4 * q + kk >= len) a[q] = 0.0;
+}
+
+// b_S = B A^{-1} f on element tiles: rows (side s, node i) of the class's side
+// operators H_{J,s} (4n x n^2, stored [l][i] per side) times the tile's f; row
+// (s, i) of element u lands on the neighbour's slot facing side s (tile_dst).
+__global__ __launch_bounds__(256) void k_flux_mfma(DevPlan P, const double* __restrict__ f, double* __restrict__ b) {
+  __shared__ double fs[kMmaN2 * kTileLd];
+  __shared__ double os[4][kTile * kTileLd];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= P.ntile) return;
+  const int col = blockIdx.y;
+  const int n = P.n, n2 = P.n2, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int J = P.tile_cls[tile];
+  const int* el = P.tile_elem + tile * kTile;
+  const int* dst = P.tile_dst + tile * kTile * 4;
+  const double* fc = f + (int64_t)col * P.r;
+  const int kr = (n2 + 3) & ~3;
+  for (int q = tid; q < kr * kTile; q += 256) {
+    const int u = q / kr, l = q - u * kr;
+    const int e = el[u];
+    fs[l * kTileLd + u] = e >= 0 && l < n2 ? fc[(int64_t)e * n2 + l] : 0.0;
+  }
+  __syncthreads();
+  // 4n <= 64 rows: row tile `wave` (waves past the row count only join the barrier)
+  const int r = lane & 15, kk = lane >> 4;
+  const int rt = wave;
+  const bool act = rt * 16 < 4 * n;
+  if (act) {
+    const int row = rt * 16 + r;
+    const int s = min(row / n, 3), i = min(row - s * n, n - 1);
+    const int64_t ho = P.H_off[J * 4 + s];
+    const bool rok = row < 4 * n && ho >= 0;
+    const double* Hp = P.Hc + (ho >= 0 ? ho : 0);
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < kr; m0 += 4 * kMmaBatch) {
+      double a[kMmaBatch];
+      mma_load_a(a, m0, kk, n2, rok, [&](int m) { return Hp[(int64_t)m * n + i]; });
+#pragma unroll
+      for (int q = 0; q < kMmaBatch; ++q)
+        if (m0 + 4 * q < kr) acc = Mma<double>::mma(a[q], fs[(m0 + 4 * q + kk) * kTileLd + r], acc);
+    }
+    // the 16 x 16 result as [element][row] in this wave's LDS
+#pragma unroll
+    for (int v = 0; v < 4; ++v) os[wave][r * kTileLd + Mma<double>::row(lane, v)] = acc[v];
+  }
+  __syncthreads();
+  if (!act) return;
+  // row-contiguous stores: row (s, i) of element u to the neighbour's slot facing s
+  double* bc = b + (int64_t)col * P.k;
+  for (int q = lane; q < kTile * 16; q += 64) {
+    const int u = q >> 4, rr = q & 15;
+    const int orow = rt * 16 + rr;
+    if (orow >= 4 * n || el[u] < 0) continue;
+    const int os_ = orow / n, oi = orow - os_ * n;
+    const int base = dst[u * 4 + os_];
+    if (base >= 0) bc[base + oi] = os[wave][u * kTileLd + rr];
+  }
+}
+
+// u_e = A_e^{-1} (f_e - E_e x) on element tiles: the tile's right-hand sides are
+// staged (the slot values subtracted as k_backsub does, W/E sides then S/N), then
+// rows [64 g, 64 g + 64) of the class's A^{-1} (stored transposed, [m][l]) multiply
+// them, one 16-row tile per wave.
+__global__ __launch_bounds__(256) void k_backsub_mfma(DevPlan P, const double* __restrict__ f,
+                                                      const double* __restrict__ x, double* __restrict__ u) {
+  __shared__ double zs[kMmaN2 * kTileLd];
+  __shared__ double os[4][kTile * kTileLd];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= P.ntile) return;
+  const int col = blockIdx.z;
+  const int n = P.n, n2 = P.n2, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int J = P.tile_cls[tile];
+  const int* el = P.tile_elem + tile * kTile;
+  const double* fc = f + (int64_t)col * P.r;
+  const double* xc = x + (int64_t)col * P.k;
+  const int kr = (n2 + 3) & ~3;
+  for (int q = tid; q < kr * kTile; q += 256) {
+    const int uu = q / kr, l = q - uu * kr;
+    const int e = el[uu];
+    zs[l * kTileLd + uu] = e >= 0 && l < n2 ? fc[(int64_t)e * n2 + l] : 0.0;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {  // W/E sides touch disjoint nodes, then S/N
+    for (int q = tid; q < kTile * 2 * n; q += 256) {
+      const int uu = q / (2 * n), qq = q - uu * 2 * n;
+      const int s = 2 * pass + qq / n, tt = qq % n;
+      const int e = el[uu];
+      if (e < 0) continue;
+      const int base = P.side_slot[e * 4 + s];
+      if (base >= 0) zs[side_node(n, s, tt) * kTileLd + uu] -= xc[base + tt];
+    }
+    __syncthreads();
+  }
+  const int r = lane & 15, kk = lane >> 4;
+  const int row = blockIdx.y * 64 + wave * 16 + r;
+  const bool rok = row < n2;
+  const double* Ap = P.AinvT + (int64_t)J * n2 * n2 + min(row, n2 - 1);
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int m0 = 0; m0 < kr; m0 += 4 * kMmaBatch) {
+    double a[kMmaBatch];
+    mma_load_a(a, m0, kk, n2, rok, [&](int m) { return Ap[(int64_t)m * n2]; });
+#pragma unroll
+    for (int q = 0; q < kMmaBatch; ++q)
+      if (m0 + 4 * q < kr) acc = Mma<double>::mma(a[q], zs[(m0 + 4 * q + kk) * kTileLd + r], acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) os[wave][r * kTileLd + Mma<double>::row(lane, v)] = acc[v];
+  __syncthreads();
+  double* uc = u + (int64_t)col * P.r;
+  const int row0 = blockIdx.y * 64 + wave * 16;
+  for (int q = lane; q < kTile * 16; q += 64) {
+    const int uu = q >> 4, rr = q & 15;
+    const int e = el[uu];
+    if (e >= 0 && row0 + rr < n2) uc[(int64_t)e * n2 + row0 + rr] = os[wave][uu * kTileLd + rr];
+  }
+}
+
 // out = A^{-T} c  (to_slots = 0, r-vector) or E^T A^{-T} c (to_slots = 1, k-vector).
 __global__ __launch_bounds__(256) void k_local_adj(DevPlan P, const double* __restrict__ c, double* __restrict__ out,
                                                    int to_slots) {
@@ -1348,28 +1483,6 @@ __global__ __launch_bounds__(256) void k_publish_set(PublishSet p) {
     for (int i = threadIdx.x; i < p.n[q]; i += 256) p.dst[q][i] = p.src[q][i];
   for (int i = threadIdx.x; i < p.in; i += 256) p.idst[i] = p.isrc[i];
 }
-// per column: activity flag and residual estimate / threshold
-__global__ void k_publish_flags(const int* __restrict__ active, const double* __restrict__ res,
-                                const double* __restrict__ tolb, int n, int* hflag, double* hratio) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  hflag[i] = active[i];
-  hratio[i] = tolb[i] > 0.0 ? res[i] / tolb[i] : 0.0;
-}
-
-// the same after a chunk of steps steps, into pinned slot (chunk index) % 2 of stride
-// entries; the chunk index comes from the step counter (jdev = steps done so far), so
-// one captured launch serves every chunk
-__global__ void k_publish_chunk(const int* __restrict__ active, const double* __restrict__ res,
-                                const double* __restrict__ tolb, int n, const int* __restrict__ jdev, int steps,
-                                int* hflag, double* hratio, int stride) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int slot = ((jdev[0] / steps) - 1) & 1;
-  hflag[slot * stride + i] = active[i];
-  hratio[slot * stride + i] = tolb[i] > 0.0 ? res[i] / tolb[i] : 0.0;
-}
-
 // ------------------------------------------------------------------ vector kernels
 
 constexpr int kChunk = 2048;   // elements per reduction chunk (256 threads x 8)
@@ -1784,6 +1897,11 @@ void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, boo
 }
 
 void launch_flux(const DevPlan& P, const double* f, double* b, int nrhs, hipStream_t s) {
+  if (P.mma_mt > 0 && P.n2 <= kMmaN2) {
+    // a multiple of 8 workgroups, so that the XCD-aware order is a permutation of the tiles
+    hipLaunchKernelGGL(k_flux_mfma, dim3((P.ntile + 7) / 8 * 8, nrhs), dim3(256), 0, s, P, f, b);
+    return;
+  }
   hipLaunchKernelGGL(k_flux, dim3(P.nel, nrhs), dim3(64), 4 * P.n2 * sizeof(double), s, P, f, b);
 }
 
@@ -1792,6 +1910,11 @@ void launch_flux_adj(const DevPlan& P, const double* x, double* y, int nrhs, hip
 }
 
 void launch_backsub(const DevPlan& P, const double* f, const double* x, double* u, int nrhs, hipStream_t s) {
+  if (P.mma_mt > 0 && P.n2 <= kMmaN2) {
+    hipLaunchKernelGGL(k_backsub_mfma, dim3((P.ntile + 7) / 8 * 8, (P.n2 + 63) / 64, nrhs), dim3(256), 0, s, P, f,
+                       x, u);
+    return;
+  }
   hipLaunchKernelGGL(k_backsub, dim3(P.nel, nrhs), dim3(256), P.n2 * sizeof(double), s, P, f, x, u);
 }
 
@@ -1891,17 +2014,6 @@ void launch_publish_i(const int* src, int n, int* host_dst, hipStream_t s) {
 void launch_publish_set(const PublishSet& p, hipStream_t s) {
   hipLaunchKernelGGL(k_publish_set, dim3(1), dim3(256), 0, s, p);
 }
-void launch_publish_flags(const int* active, const double* res, const double* tolb, int n, int* hflag,
-                          double* hratio, hipStream_t s) {
-  hipLaunchKernelGGL(k_publish_flags, dim3((n + 255) / 256), dim3(256), 0, s, active, res, tolb, n, hflag, hratio);
-}
-
-void launch_publish_chunk(const int* active, const double* res, const double* tolb, int n, const int* jdev, int steps,
-                          int* hflag, double* hratio, int stride, hipStream_t s) {
-  hipLaunchKernelGGL(k_publish_chunk, dim3((n + 255) / 256), dim3(256), 0, s, active, res, tolb, n, jdev, steps,
-                     hflag, hratio, stride);
-}
-
 void launch_mdot(const double* A, int64_t a_vs, int64_t a_cs, int nvec, const double* b, int64_t b_cs,
                  const double* wt, int64_t len, int nrhs, double* part, double* out, const int* active,
                  hipStream_t s) {

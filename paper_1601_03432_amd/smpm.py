@@ -130,6 +130,11 @@ def _i64ptr(a: np.ndarray):
 
 def _stream(torch, stream):
     if stream is None:
+        # the current stream's handle without building a Stream object (when this
+        # torch build exposes it)
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return C.c_void_p(raw(torch.cuda.current_device()))
         stream = torch.cuda.current_stream()
     return C.c_void_p(stream.cuda_stream)
 
@@ -184,6 +189,7 @@ class Context:
         _check(rc)
         self._h = h
         self._lib = lib
+        self._opts_cache = {}  # SolveOpts by argument tuple (the library copies them)
         self.device = device
         self.robin = robin
         self.m_x, self.m_y, self.n = m_x, m_y, n
@@ -355,8 +361,13 @@ class Context:
                 raise ValueError("g must have as many columns as f")
             gp = C.c_void_p(g.data_ptr())
         u = torch.empty_like(f)
-        opts = SolveOpts(tol, maxit, precision, int(transpose), variant, inner_tol, max_refine, int(graph),
-                         int(stop_rule), int(profile))
+        key = (tol, maxit, precision, transpose, variant, inner_tol, max_refine, graph, stop_rule, profile)
+        opts = self._opts_cache.get(key)
+        if opts is None:
+            opts = SolveOpts(tol, maxit, precision, int(transpose), variant, inner_tol, max_refine, int(graph),
+                             int(stop_rule), int(profile))
+            if len(self._opts_cache) < 64:
+                self._opts_cache[key] = opts
         info = SolveInfo()
         rc = self._lib.smpm_solve(self._h, C.c_void_p(f.data_ptr()), gp, C.c_void_p(u.data_ptr()), nrhs,
                                   C.byref(opts), C.byref(info), _stream(torch, stream))
