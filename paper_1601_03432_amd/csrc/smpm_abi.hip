@@ -53,8 +53,6 @@ struct Workspace {
   double* xprev = nullptr;                  // iterate before the last correction
   double* cws = nullptr;                    // substructured coarse solve scratch
   double* ubuf = nullptr;                   // r x nrhs: back-substituted solution before the mean
-  double* w2 = nullptr;                     // k x nrhs: residual scratch of the post-processing (never
-                                            // the Arnoldi state, so it may run speculatively)
   double* tolv = nullptr;                   // device GMRES: tolerance and step counter
   int* jdev = nullptr;
   double *tolb = nullptr;
@@ -221,7 +219,6 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.sides, (size_t)P.nsides * R);
   rc |= dalloc(w.mem, &w.xacc, k * R);
   rc |= dalloc(w.mem, &w.ubuf, r * R);
-  rc |= dalloc(w.mem, &w.w2, k * R);
   rc |= dalloc(w.mem, &w.xprev, k * R);
   rc |= dalloc(w.mem, &w.rho, k * R);
   rc |= dalloc(w.mem, &w.tolb, R);
@@ -561,25 +558,28 @@ int run_phase(smpm_ctx* c, bool use_graph, int phase, const GmState& S, int nrhs
 
 // GMRES prologue for right-hand side b: the stopping reference |b|^2, the initial
 // residual r0 = P b (kind 3) or b into W.w, and gm_start (V_0, flags, tolerance).
+// (norm_done: the caller already formed |b|^2 there, by the same reduction.)
 void gm_prologue(smpm_ctx* c, const GmState& S, int kind, bool tr, const double* b, int nrhs, double tol,
-                 hipStream_t s) {
+                 hipStream_t s, bool norm_done = false) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
-  launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
+  if (!norm_done) launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
   if (kind == 3) {
     launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
-    launch_prolong(P, b, W.c2, W.w, nrhs, tr ? 2 : 1, -1.0, nullptr, s);
+    gm_start_deflated(P, S, nrhs, b, W.c2, tr, tol, s);  // r0 = P b into w and V_0
   } else {
     launch_copy(b, W.w, P.k * nrhs, s);
+    gm_start(P, S, nrhs, tol, s);
   }
-  gm_start(P, S, nrhs, tol, s);
 }
 
-// GMRES epilogue: the closing Givens step, the least-squares solution and x1 = V y, and
-// the counts and column 0's history (rotated right-hand side, cosines, threshold) into
-// pinned memory, read after the caller's synchronization.
-void gm_epilogue(smpm_ctx* c, const GmState& S, int kind, bool tr, double* x1, int nrhs, hipStream_t s) {
+// GMRES epilogue: the least-squares solution and x1 = V y, and the counts and column 0's
+// history (rotated right-hand side, cosines, threshold) into pinned memory, read after
+// the caller's synchronization (with defer, the publication is added to *defer for the
+// caller to launch with its own).
+void gm_epilogue(smpm_ctx* c, const GmState& S, int kind, bool tr, double* x1, int nrhs, hipStream_t s,
+                 PublishSet* defer = nullptr) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   // every column has retired in a Givens step by the time the iterations end (the
@@ -598,7 +598,10 @@ void gm_epilogue(smpm_ctx* c, const GmState& S, int kind, bool tr, double* x1, i
   ps.isrc = W.iters;
   ps.idst = W.hiters;
   ps.in = nrhs;
-  launch_publish_set(ps, s);
+  if (defer)
+    *defer = ps;
+  else
+    launch_publish_set(ps, s);
 }
 
 // Reads what gm_epilogue published (after a synchronization).
@@ -749,8 +752,7 @@ void recover_x(smpm_ctx* c, int kind, bool tr, const double* bhat, const double*
     // x = z + Z G Z^T (b_hat - S z), z = M^{-1} x1
     launch_precond(P, x1, W.z, nrhs, tr, nullptr, s, mprec);
     launch_schur_ex(P, W.z, W.t, nrhs, tr, nullptr, nullptr, s, sprec);
-    launch_add(bhat, W.t, -1.0, W.w2, P.k, nrhs, s);
-    launch_iface_sum(P, W.w2, W.c, nrhs, nullptr, s);
+    launch_iface_sum_diff(P, bhat, W.t, -1.0, W.c, nrhs, s);  // Z^T (b_hat - S z)
     launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
     launch_prolong(P, W.z, W.c2, x, nrhs, 0, 1.0, nullptr, s);
   }
@@ -758,19 +760,31 @@ void recover_x(smpm_ctx* c, int kind, bool tr, const double* bhat, const double*
 
 // |b - S x|^2 and |b|^2 per column into pinned hout[0..nrhs) and hout[nrhs..2 nrhs);
 // b2, if given, already holds |b|^2 (the same reduction of the same b); extra, if
-// given, nrhs more values published into hout[2 nrhs..3 nrhs)
+// given, nrhs more values published into hout[2 nrhs..3 nrhs); more, if given, the
+// caller's other publications, launched together with these.
 void true_residual_enqueue(smpm_ctx* c, bool tr, const double* b, const double* x, int nrhs, hipStream_t s,
-                           const double* b2 = nullptr, const double* extra = nullptr) {
+                           const double* b2 = nullptr, const double* extra = nullptr,
+                           const PublishSet* more = nullptr) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   launch_schur(P, x, W.t, nrhs, tr, nullptr, s);
-  launch_add(b, W.t, -1.0, W.w2, P.k, nrhs, s);
-  launch_mdot(W.w2, 0, P.k, 1, W.w2, P.k, nullptr, P.k, nrhs, W.part, W.scal, nullptr, s);
+  launch_norm2_diff(b, W.t, -1.0, P.k, nrhs, W.part, W.scal, s);  // |b - S x|^2
   if (!b2) {
     launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2, nullptr, s);
     b2 = W.scal2;
   }
   PublishSet ps = {};
+  if (more) {
+    // the caller's entries go after these three
+    for (int q = 0; q < 3; ++q) {
+      ps.src[4 + q] = more->src[q];
+      ps.dst[4 + q] = more->dst[q];
+      ps.n[4 + q] = more->n[q];
+    }
+    ps.isrc = more->isrc;
+    ps.idst = more->idst;
+    ps.in = more->in;
+  }
   ps.src[0] = W.scal;
   ps.dst[0] = W.hout;
   ps.n[0] = nrhs;
@@ -1874,10 +1888,13 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     if (!tr) {
       // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
       launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, removed, nullptr, q);
-      launch_axpy_shared(W.rhs, Pl.r, c->uL, removed, 1.0, W.ft, Pl.r, nrhs, q);
-      launch_flux(P, W.ft, W.bS, nrhs, q);
+      if (!launch_flux_projected(P, W.rhs, c->uL, removed, 1.0, W.ft, W.bS, nrhs, q)) {
+        launch_axpy_shared(W.rhs, Pl.r, c->uL, removed, 1.0, W.ft, Pl.r, nrhs, q);
+        launch_flux(P, W.ft, W.bS, nrhs, q);
+      }
       launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
-      launch_axpy_shared(W.bS, Pl.k, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, q);
+      // b_hat, and |b_hat|^2 (the GMRES stopping reference) in the same launch
+      launch_axpy_norm2(W.bS, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, W.part, W.scal2 + 2 * nrhs, q);
     } else {
       // adjoint of the solution map: c~ = c - w (1^T c)/(w^T 1); S^T xi = E^T A^{-T} c~
       // (consistent: v0^T E^T A^{-T} c~ = -1^T c~ = 0), projected off v0 against rounding
@@ -1885,7 +1902,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       launch_axpy_shared(W.rhs, Pl.r, c->wq, removed, 1.0 / c->wsum, W.ft, Pl.r, nrhs, q);
       launch_local_adj(P, W.ft, W.bS, nrhs, true, q);
       launch_mdot(c->v0hat, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
-      launch_axpy_shared(W.bS, Pl.k, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, q);
+      launch_axpy_norm2(W.bS, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, W.part, W.scal2 + 2 * nrhs, q);
     }
   };
   // step 9 up to the last store: forward u = A^{-1}(f~ - E x) into W.ubuf and w^T u
@@ -1938,19 +1955,21 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     S.bref2 = rule == 1 ? nullptr : W.scal2 + 2 * nrhs;
     rc = run_phase(c, use_graph, 1, S, nrhs, kind, tr, PREC_F64, PREC_F64, o.tol, s, [&](hipStream_t q) {
       pre_body(q);
-      gm_prologue(c, S, kind, tr, W.bhat, nrhs, o.tol, q);
+      gm_prologue(c, S, kind, tr, W.bhat, nrhs, o.tol, q, true);  // |b_hat|^2 formed with b_hat
     });
     if (rc) return rc;
     mark(1);
-    // the post-processing touches no Arnoldi state (its residual scratch is W.w2), so
-    // the loop may queue it behind the chunk it predicts to be the last
+    // the post-processing touches no Arnoldi state (it forms its residual terms without
+    // a scratch vector), so the loop may queue it behind the chunk it predicts to be
+    // the last
     const std::function<int()> post = [&]() -> int {
       mark(2);
       const int r = run_phase(c, use_graph, 2, S, nrhs, kind, tr, PREC_F64, PREC_F64, o.tol, s, [&](hipStream_t q) {
-        gm_epilogue(c, S, kind, tr, W.x, nrhs, q);
+        PublishSet hist = {};
+        gm_epilogue(c, S, kind, tr, W.x, nrhs, q, &hist);
         recover_x(c, kind, tr, W.bhat, W.x, W.bS, nrhs, PREC_F64, PREC_F64, q);
         // |b_hat|^2 is the prologue's stopping reference (the same reduction of b_hat)
-        true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q, W.scal2 + 2 * nrhs, removed);
+        true_residual_enqueue(c, tr, W.bhat, W.bS, nrhs, q, W.scal2 + 2 * nrhs, removed, &hist);
         post_body(W.bS, q);
       });
       if (r) return r;

@@ -61,6 +61,9 @@ struct GmState {
 
 // u_0 = w into V_0, all columns active, j = 0 and the tolerance on the device
 void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStream_t s);
+// the same from b with u_0 = w = b - (Z c2 + {S, S^T} Z c2) (c2 = G Z^T b already formed)
+void gm_start_deflated(const DevPlan& P, const GmState& S, int nrhs, const double* b, const double* c2, bool tr,
+                       double tol, hipStream_t s);
 // One Arnoldi step with j read from slot `par` of the device counter (its last kernel
 // writes j + 1 into slot par ^ 1; the q-th step after gm_start uses par = q % 2), so
 // a captured sequence of steps replays for any j.  Step j finishes Hessenberg column

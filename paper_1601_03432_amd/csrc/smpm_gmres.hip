@@ -1088,6 +1088,29 @@ __global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S, double t
   }
 }
 
+// Start of a deflated solve from b: r_0 = b - (Z c2 + {S, S^T} Z c2) into w and V_0,
+// all columns active, j = 0 and the tolerance (the values of k_prolong followed by
+// k_gm_start, in one launch).
+__global__ __launch_bounds__(256) void k_gm_start_defl(DevPlan P, GmState S, const double* __restrict__ b,
+                                                       const double* __restrict__ c2, int transpose, double tol) {
+  const int col = blockIdx.y, tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) {
+    S.active[col] = 1;
+    S.iters[col] = 0;
+    if (col == 0) {
+      S.jdev[0] = 0;
+      S.tolv[0] = tol;
+    }
+  }
+  const int64_t slot = (int64_t)blockIdx.x * kThreads + tid;
+  if (slot >= P.k) return;
+  const double acc = deflation(P, c2 + (int64_t)col * P.d, slot, transpose != 0);
+  const int64_t o = (int64_t)col * P.k + slot;
+  const double v = b[o] + -1.0 * acc;
+  S.w[o] = v;
+  S.V[o] = v;
+}
+
 // y = R^{-1} g for the first iters[col] columns (R = rotated Hessenberg), one
 // block per column, column-oriented back substitution.
 constexpr int kLsqStage = 64;  // Krylov dimensions whose triangle is staged in LDS
@@ -1151,6 +1174,12 @@ __global__ __launch_bounds__(256) void k_gm_combine(DevPlan P, GmState S, double
 }
 
 // ------------------------------------------------------------------ launchers
+
+void gm_start_deflated(const DevPlan& P, const GmState& S, int nrhs, const double* b, const double* c2, bool tr,
+                       double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_start_defl, dim3((unsigned)((P.k + kThreads - 1) / kThreads), nrhs), dim3(kThreads), 0, s,
+                     P, S, b, c2, tr ? 1 : 0, tol);
+}
 
 void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStream_t s) {
   hipLaunchKernelGGL(k_gm_start, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, tol);

@@ -306,11 +306,11 @@ void launch_fill_pattern(double* b, int64_t len, hipStream_t s);  // values in (
 // ---- small results into pinned (mapped, coherent) host memory by a kernel
 void launch_publish(const double* src, int n, double* host_dst, hipStream_t s);
 void launch_publish_i(const int* src, int n, int* host_dst, hipStream_t s);
-// up to four double ranges and one int range in one launch (unused entries: n = 0)
+// up to eight double ranges and one int range in one launch (unused entries: n = 0)
 struct PublishSet {
-  const double* src[4];
-  double* dst[4];
-  int n[4];
+  const double* src[8];
+  double* dst[8];
+  int n[8];
   const int* isrc;
   int* idst;
   int in;
@@ -334,6 +334,20 @@ void launch_axpy_shared(const double* x, int64_t x_cs, const double* u, const do
 void launch_scale_inv(const double* x, int64_t x_cs, const double* nrm, bool sq, double* y, int64_t y_cs,
                       int64_t len, int nrhs, const int* active, hipStream_t s);
 void launch_add(const double* a, const double* b, double sb, double* y, int64_t len, int nrhs, hipStream_t s);
+// Fused pairs (each gives the bits of the two launches it replaces):
+//  out[col] = sum_x (a + sb b)[x]^2                         (launch_add, then launch_mdot of the result with itself)
+void launch_norm2_diff(const double* a, const double* b, double sb, int64_t len, int nrhs, double* part, double* out,
+                       hipStream_t s);
+//  y = x - dot[col] * scale * u, out[col] = |y|^2            (launch_axpy_shared, then launch_mdot(y, y))
+void launch_axpy_norm2(const double* x, const double* u, const double* dot, double scale, double* y, int64_t len,
+                       int nrhs, double* part, double* out, hipStream_t s);
+//  c = Z^T (a + sb t)                                       (launch_add, then launch_iface_sum)
+void launch_iface_sum_diff(const DevPlan& P, const double* a, const double* t, double sb, double* c, int nrhs,
+                           hipStream_t s);
+//  ft = f - dot[col] * scale * u (r-vector), then b = B A^{-1} ft; false (nothing launched) when the
+//  element applies do not run on the matrix cores (n > 16)
+bool launch_flux_projected(const DevPlan& P, const double* f, const double* u, const double* dot, double scale,
+                           double* ft, double* b, int nrhs, hipStream_t s);
 
 // ---- GMRES small dense work (one thread per column)
 // H(col) (ldh x maxit col-major: H[j*ldh + i]), cs, sn, g of length ldh; hnew: j+1 coefficients,

@@ -949,7 +949,11 @@ __device__ __forceinline__ void mma_load_a(double (&a)[kMmaBatch], int m0, int k
 // b_S = B A^{-1} f on element tiles: rows (side s, node i) of the class's side
 // operators H_{J,s} (4n x n^2, stored [l][i] per side) times the tile's f; row
 // (s, i) of element u lands on the neighbour's slot facing side s (tile_dst).
-__global__ __launch_bounds__(256) void k_flux_mfma(DevPlan P, const double* __restrict__ f, double* __restrict__ b) {
+// With pu != nullptr the staged values are ft = f - pdot[col] * pscale * pu (written
+// to ft as well): the projection that precedes B A^{-1} in the solve.
+__global__ __launch_bounds__(256) void k_flux_mfma(DevPlan P, const double* __restrict__ f, double* __restrict__ b,
+                                                   const double* __restrict__ pu, const double* __restrict__ pdot,
+                                                   double pscale, double* __restrict__ ft) {
   __shared__ double fs[kMmaN2 * kTileLd];
   __shared__ double os[4][kTile * kTileLd];
   const int tile = xcd_block(blockIdx.x, gridDim.x);
@@ -964,7 +968,16 @@ __global__ __launch_bounds__(256) void k_flux_mfma(DevPlan P, const double* __re
   for (int q = tid; q < kr * kTile; q += 256) {
     const int u = q / kr, l = q - u * kr;
     const int e = el[u];
-    fs[l * kTileLd + u] = e >= 0 && l < n2 ? fc[(int64_t)e * n2 + l] : 0.0;
+    double v = 0.0;
+    if (e >= 0 && l < n2) {
+      const int64_t x = (int64_t)e * n2 + l;
+      v = fc[x];
+      if (pu) {
+        v = v - pdot[col] * pscale * pu[x];
+        ft[(int64_t)col * P.r + x] = v;
+      }
+    }
+    fs[l * kTileLd + u] = v;
   }
   __syncthreads();
   // 4n <= 64 rows: row tile `wave` (waves past the row count only join the barrier)
@@ -1123,7 +1136,8 @@ __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __rest
 // c_j = sum of t over the 2n slots of interface j: one wavefront per interface,
 // lanes over slots, fixed shuffle tree.
 __global__ __launch_bounds__(256) void k_iface_sum(DevPlan P, const double* __restrict__ t, double* __restrict__ c,
-                                                   const int* __restrict__ active) {
+                                                   const int* __restrict__ active, const double* __restrict__ a,
+                                                   double sb) {
   const int col = blockIdx.y;
   if (active && !active[col]) return;
   const int n = P.n;
@@ -1135,10 +1149,12 @@ __global__ __launch_bounds__(256) void k_iface_sum(DevPlan P, const double* __re
   const int l = pack ? lane & 31 : lane;
   if (j >= P.d) return;  // a whole wave, or a whole half whose partners are in it
   const double* tc = t + (int64_t)col * P.k;
+  const double* ac = a ? a + (int64_t)col * P.k : nullptr;  // sums of a + sb t instead of t
   double acc = 0.0;
   for (int q = l; q < 2 * n; q += 64) {
     const int h = q / n, i = q - h * n;
-    acc += tc[(int64_t)P.iface_side[2 * j + h] * n + i];
+    const int64_t x = (int64_t)P.iface_side[2 * j + h] * n + i;
+    acc += ac ? ac[x] + sb * tc[x] : tc[x];
   }
   for (int off = pack ? 16 : 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (l == 0) c[(int64_t)col * P.d + j] = acc;
@@ -1479,7 +1495,7 @@ __global__ void k_publish_i(const int* __restrict__ src, int n, int* dst) {
   if (i < n) dst[i] = src[i];
 }
 __global__ __launch_bounds__(256) void k_publish_set(PublishSet p) {
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 8; ++q)
     for (int i = threadIdx.x; i < p.n[q]; i += 256) p.dst[q][i] = p.src[q][i];
   for (int i = threadIdx.x; i < p.in; i += 256) p.idst[i] = p.isrc[i];
 }
@@ -1538,6 +1554,54 @@ __global__ void k_mdot_final(const double* __restrict__ part, int nvec, int nchu
   double acc = 0.0;
   for (int c = 0; c < nchunks; ++c) acc += p[c];
   out[idx] = acc;
+}
+
+// Partial sums of |a + sb b|^2 over the chunk of k_mdot_part (same element order and
+// tree as k_mdot_part of that vector with itself).
+__global__ __launch_bounds__(256) void k_norm2_diff_part(const double* __restrict__ a, const double* __restrict__ b,
+                                                         double sb, int64_t len, int nchunks,
+                                                         double* __restrict__ part) {
+  __shared__ double red[4];
+  const int chunk = blockIdx.x, col = blockIdx.y;
+  const int64_t x0 = (int64_t)chunk * kChunk;
+  double dv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t x = x0 + q * 256 + threadIdx.x;
+    dv[q] = x < len ? a[(int64_t)col * len + x] + sb * b[(int64_t)col * len + x] : 0.0;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (x0 + q * 256 + threadIdx.x < len) acc = fma(dv[q], dv[q], acc);
+  const double sum = block_sum_256(acc, red);
+  if (threadIdx.x == 0) part[(int64_t)col * nchunks + chunk] = sum;
+}
+
+// y = x - dot[col] * scale * u written, with the partial sums of |y|^2 as above
+__global__ __launch_bounds__(256) void k_axpy_norm2_part(const double* __restrict__ xv, const double* __restrict__ u,
+                                                         const double* __restrict__ dot, double scale,
+                                                         double* __restrict__ y, int64_t len, int nchunks,
+                                                         double* __restrict__ part) {
+  __shared__ double red[4];
+  const int chunk = blockIdx.x, col = blockIdx.y;
+  const int64_t x0 = (int64_t)chunk * kChunk;
+  double yv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t x = x0 + q * 256 + threadIdx.x;
+    yv[q] = 0.0;
+    if (x < len) {
+      yv[q] = xv[(int64_t)col * len + x] - dot[col] * scale * u[x];
+      y[(int64_t)col * len + x] = yv[q];
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (x0 + q * 256 + threadIdx.x < len) acc = fma(yv[q], yv[q], acc);
+  const double sum = block_sum_256(acc, red);
+  if (threadIdx.x == 0) part[(int64_t)col * nchunks + chunk] = sum;
 }
 
 __global__ __launch_bounds__(256) void k_mupdate(double* __restrict__ w, int64_t w_cs, const double* __restrict__ A,
@@ -1899,10 +1963,18 @@ void launch_schur_ex(const DevPlan& P, const double* y, double* t, int nrhs, boo
 void launch_flux(const DevPlan& P, const double* f, double* b, int nrhs, hipStream_t s) {
   if (P.mma_mt > 0 && P.n2 <= kMmaN2) {
     // a multiple of 8 workgroups, so that the XCD-aware order is a permutation of the tiles
-    hipLaunchKernelGGL(k_flux_mfma, dim3((P.ntile + 7) / 8 * 8, nrhs), dim3(256), 0, s, P, f, b);
+    hipLaunchKernelGGL(k_flux_mfma, dim3((P.ntile + 7) / 8 * 8, nrhs), dim3(256), 0, s, P, f, b,
+                       (const double*)nullptr, (const double*)nullptr, 0.0, (double*)nullptr);
     return;
   }
   hipLaunchKernelGGL(k_flux, dim3(P.nel, nrhs), dim3(64), 4 * P.n2 * sizeof(double), s, P, f, b);
+}
+
+bool launch_flux_projected(const DevPlan& P, const double* f, const double* u, const double* dot, double scale,
+                           double* ft, double* b, int nrhs, hipStream_t s) {
+  if (!(P.mma_mt > 0 && P.n2 <= kMmaN2)) return false;
+  hipLaunchKernelGGL(k_flux_mfma, dim3((P.ntile + 7) / 8 * 8, nrhs), dim3(256), 0, s, P, f, b, u, dot, scale, ft);
+  return true;
 }
 
 void launch_flux_adj(const DevPlan& P, const double* x, double* y, int nrhs, hipStream_t s) {
@@ -1936,7 +2008,15 @@ void launch_precond(const DevPlan& P, const double* x, double* y, int nrhs, bool
 
 void launch_iface_sum(const DevPlan& P, const double* t, double* c, int nrhs, const int* active, hipStream_t s) {
   if (P.d == 0 || !P.has_coarse) return;
-  hipLaunchKernelGGL(k_iface_sum, grid1(P.d, 2 * P.n <= 32 ? 8 : 4, nrhs), dim3(256), 0, s, P, t, c, active);
+  hipLaunchKernelGGL(k_iface_sum, grid1(P.d, 2 * P.n <= 32 ? 8 : 4, nrhs), dim3(256), 0, s, P, t, c, active,
+                     (const double*)nullptr, 0.0);
+}
+
+void launch_iface_sum_diff(const DevPlan& P, const double* a, const double* t, double sb, double* c, int nrhs,
+                           hipStream_t s) {
+  if (P.d == 0 || !P.has_coarse) return;
+  hipLaunchKernelGGL(k_iface_sum, grid1(P.d, 2 * P.n <= 32 ? 8 : 4, nrhs), dim3(256), 0, s, P, t, c,
+                     (const int*)nullptr, a, sb);
 }
 
 void launch_coarse(const DevPlan& P, const double* c, double* c2, int nrhs, bool transpose, const int* active,
@@ -2022,6 +2102,22 @@ void launch_mdot(const double* A, int64_t a_vs, int64_t a_cs, int nvec, const do
   hipLaunchKernelGGL(k_mdot_part, g, dim3(256), 0, s, A, a_vs, a_cs, nvec, b, b_cs, wt, len, nch, part, active);
   hipLaunchKernelGGL(k_mdot_final, grid1((int64_t)nvec * nrhs, 128), dim3(128), 0, s, part, nvec, nch, nrhs, out,
                      active);
+}
+
+void launch_norm2_diff(const double* a, const double* b, double sb, int64_t len, int nrhs, double* part, double* out,
+                       hipStream_t s) {
+  const int nch = reduce_chunks(len);
+  hipLaunchKernelGGL(k_norm2_diff_part, dim3(nch, nrhs), dim3(256), 0, s, a, b, sb, len, nch, part);
+  hipLaunchKernelGGL(k_mdot_final, grid1((int64_t)nrhs, 128), dim3(128), 0, s, part, 1, nch, nrhs, out,
+                     (const int*)nullptr);
+}
+
+void launch_axpy_norm2(const double* x, const double* u, const double* dot, double scale, double* y, int64_t len,
+                       int nrhs, double* part, double* out, hipStream_t s) {
+  const int nch = reduce_chunks(len);
+  hipLaunchKernelGGL(k_axpy_norm2_part, dim3(nch, nrhs), dim3(256), 0, s, x, u, dot, scale, y, len, nch, part);
+  hipLaunchKernelGGL(k_mdot_final, grid1((int64_t)nrhs, 128), dim3(128), 0, s, part, 1, nch, nrhs, out,
+                     (const int*)nullptr);
 }
 
 void launch_mupdate(double* w, int64_t w_cs, const double* A, int64_t a_vs, int64_t a_cs, int nvec,
