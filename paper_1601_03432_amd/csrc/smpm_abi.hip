@@ -207,7 +207,9 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.res, R);
   rc |= dalloc(w.mem, &w.y, ldh * R);
   const size_t nch = reduce_chunks(std::max<int64_t>(P.r, P.k));
-  rc |= dalloc(w.mem, &w.part, nch * ldh * R);
+  // reduction partials: the multi-dots' chunks, or one per back-substitution block
+  const size_t nbk = (size_t)((P.ntile + 7) / 8 * 8) * (size_t)((P.n * P.n + 63) / 64);
+  rc |= dalloc(w.mem, &w.part, std::max(nch * ldh, nbk) * R);
   rc |= ialloc(w.mem, &w.active, R);
   rc |= ialloc(w.mem, &w.jcount, R);
   w.rows = gm_rows_per_chunk(P.k);
@@ -1909,8 +1911,10 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   // into W.scal; adjoint mu = A^{-T}(c~ - B^T xi) into W.ubuf and u_L^T mu into W.scal
   auto post_body = [&](const double* xs, hipStream_t q) {
     if (!tr) {
-      launch_backsub(P, W.ft, xs, W.ubuf, nrhs, q);
-      launch_mdot(c->wq, 0, 0, 1, W.ubuf, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, q);
+      if (!launch_backsub_dot(P, W.ft, xs, W.ubuf, c->wq, nrhs, W.part, W.scal, q)) {
+        launch_backsub(P, W.ft, xs, W.ubuf, nrhs, q);
+        launch_mdot(c->wq, 0, 0, 1, W.ubuf, Pl.r, nullptr, Pl.r, nrhs, W.part, W.scal, nullptr, q);
+      }
     } else {
       launch_local_adj(P, W.ft, W.ubuf, nrhs, false, q);
       launch_flux_adj(P, xs, W.rhs, nrhs, q);

@@ -346,6 +346,11 @@ void launch_iface_sum_diff(const DevPlan& P, const double* a, const double* t, d
                            hipStream_t s);
 //  ft = f - dot[col] * scale * u (r-vector), then b = B A^{-1} ft; false (nothing launched) when the
 //  element applies do not run on the matrix cores (n > 16)
+//  u = A^{-1}(f - E x) and out[col] = wq . u (partials in part, at least 4 * ntile + 32
+//  per column); false (nothing launched) when the element applies do not run on the
+//  matrix cores (n > 16)
+bool launch_backsub_dot(const DevPlan& P, const double* f, const double* x, double* u, const double* wq, int nrhs,
+                        double* part, double* out, hipStream_t s);
 bool launch_flux_projected(const DevPlan& P, const double* f, const double* u, const double* dot, double scale,
                            double* ft, double* b, int nrhs, hipStream_t s);
 

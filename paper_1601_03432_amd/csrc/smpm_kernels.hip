@@ -1020,13 +1020,21 @@ __global__ __launch_bounds__(256) void k_flux_mfma(DevPlan P, const double* __re
 // staged (the slot values subtracted as k_backsub does, W/E sides then S/N), then
 // rows [64 g, 64 g + 64) of the class's A^{-1} (stored transposed, [m][l]) multiply
 // them, one 16-row tile per wave.
+// With wq != nullptr each block also writes the partial sum of wq . u over its outputs
+// to part[col][block] (blocks in launch order), for the mean of u.
 __global__ __launch_bounds__(256) void k_backsub_mfma(DevPlan P, const double* __restrict__ f,
-                                                      const double* __restrict__ x, double* __restrict__ u) {
+                                                      const double* __restrict__ x, double* __restrict__ u,
+                                                      const double* __restrict__ wq, double* __restrict__ part) {
   __shared__ double zs[kMmaN2 * kTileLd];
   __shared__ double os[4][kTile * kTileLd];
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
-  if (tile >= P.ntile) return;
+  __shared__ double red[4];
   const int col = blockIdx.z;
+  const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= P.ntile) {
+    if (wq && threadIdx.x == 0) part[(int64_t)col * nblk + blk] = 0.0;
+    return;
+  }
   const int n = P.n, n2 = P.n2, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int J = P.tile_cls[tile];
   const int* el = P.tile_elem + tile * kTile;
@@ -1067,11 +1075,22 @@ __global__ __launch_bounds__(256) void k_backsub_mfma(DevPlan P, const double* _
   __syncthreads();
   double* uc = u + (int64_t)col * P.r;
   const int row0 = blockIdx.y * 64 + wave * 16;
+  double wsum = 0.0;
   for (int q = lane; q < kTile * 16; q += 64) {
     const int uu = q >> 4, rr = q & 15;
     const int e = el[uu];
-    if (e >= 0 && row0 + rr < n2) uc[(int64_t)e * n2 + row0 + rr] = os[wave][uu * kTileLd + rr];
+    if (e >= 0 && row0 + rr < n2) {
+      const int64_t o = (int64_t)e * n2 + row0 + rr;
+      const double v = os[wave][uu * kTileLd + rr];
+      uc[o] = v;
+      if (wq) wsum = fma(wq[o], v, wsum);
+    }
   }
+  if (!wq) return;
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
+  if (lane == 0) red[wave] = wsum;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)col * nblk + blk] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // out = A^{-T} c  (to_slots = 0, r-vector) or E^T A^{-T} c (to_slots = 1, k-vector).
@@ -1970,6 +1989,17 @@ void launch_flux(const DevPlan& P, const double* f, double* b, int nrhs, hipStre
   hipLaunchKernelGGL(k_flux, dim3(P.nel, nrhs), dim3(64), 4 * P.n2 * sizeof(double), s, P, f, b);
 }
 
+bool launch_backsub_dot(const DevPlan& P, const double* f, const double* x, double* u, const double* wq, int nrhs,
+                        double* part, double* out, hipStream_t s) {
+  if (!(P.mma_mt > 0 && P.n2 <= kMmaN2)) return false;
+  const dim3 g((P.ntile + 7) / 8 * 8, (P.n2 + 63) / 64, nrhs);
+  hipLaunchKernelGGL(k_backsub_mfma, g, dim3(256), 0, s, P, f, x, u, wq, part);
+  const int nblk = (int)(g.x * g.y);
+  hipLaunchKernelGGL(k_mdot_final, grid1((int64_t)nrhs, 128), dim3(128), 0, s, part, 1, nblk, nrhs, out,
+                     (const int*)nullptr);
+  return true;
+}
+
 bool launch_flux_projected(const DevPlan& P, const double* f, const double* u, const double* dot, double scale,
                            double* ft, double* b, int nrhs, hipStream_t s) {
   if (!(P.mma_mt > 0 && P.n2 <= kMmaN2)) return false;
@@ -1984,7 +2014,7 @@ void launch_flux_adj(const DevPlan& P, const double* x, double* y, int nrhs, hip
 void launch_backsub(const DevPlan& P, const double* f, const double* x, double* u, int nrhs, hipStream_t s) {
   if (P.mma_mt > 0 && P.n2 <= kMmaN2) {
     hipLaunchKernelGGL(k_backsub_mfma, dim3((P.ntile + 7) / 8 * 8, (P.n2 + 63) / 64, nrhs), dim3(256), 0, s, P, f,
-                       x, u);
+                       x, u, (const double*)nullptr, (double*)nullptr);
     return;
   }
   hipLaunchKernelGGL(k_backsub, dim3(P.nel, nrhs), dim3(256), P.n2 * sizeof(double), s, P, f, x, u);
