@@ -107,6 +107,9 @@ struct smpm_ctx {
   hipStream_t cap_stream = nullptr;          // capture-only stream (default priority)
   hipStream_t group_stream = nullptr;        // this problem's stream in smpm_solve_group
   int prereduce_choice[4] = {-1, -1, -1, -1};  // per column-count class: -1 built-in rule, 0/1 tuned
+  // inner solves with FP32 / BF16 operators keep their Krylov basis in FP32 (read at
+  // setup; the environment SMPM_MIXED_BASIS=64 keeps it FP64, for comparisons)
+  int mixed_basis32 = 1;
   void drop_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     graphs.clear();
@@ -481,6 +484,7 @@ GmState gm_state(smpm_ctx* c, int nrhs, int maxit) {
   S.hseq = W.hseq;
   S.pub_stride = W.nrhs;
   S.pub_every = kChunkIters;
+  S.basis32 = 0;
   return S;
 }
 
@@ -731,6 +735,9 @@ int gmres_dev(smpm_ctx* c, int kind, bool tr, const double* b, double* x, int nr
   // residual is accepted against), or with rule 1 the initial GMRES residual (the
   // step-0 kernel takes it when bref2 is null)
   S.bref2 = rule == 1 ? nullptr : W.scal2 + 2 * nrhs;
+  // an inner solve with low-precision operators only has to reach its loose inner
+  // tolerance: its basis is stored in FP32 (half the basis traffic), arithmetic FP64
+  S.basis32 = sprec != PREC_F64 && c->mixed_basis32 ? 1 : 0;
   gm_prologue(c, S, kind, tr, b, nrhs, tol, s);
   int rc = gm_loop(c, S, kind, tr, nrhs, maxit, s, sprec, mprec, use_graph);
   if (rc) return rc;
@@ -1183,6 +1190,7 @@ int do_upload(smpm_ctx* c, hipStream_t s) {
   d.mma_mt = p.mma_mt;
   for (int q = 0; q < 4; ++q) d.schur_nc[q] = 0;
   for (int q = 0; q < 4; ++q) d.schur_pers[q] = 0;
+  if (const char* e = std::getenv("SMPM_MIXED_BASIS")) c->mixed_basis32 = std::atoi(e) == 64 ? 0 : 1;
   if (const char* e = std::getenv("SMPM_SCHUR_PERSIST"))  // sweep hook
     for (int q = 0; q < 4; ++q) {
       const int v = std::atoi(e);
@@ -2036,8 +2044,10 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     mark(1);
     // Iterative refinement: rho = b_hat - S x in FP64; delta from the deflated GMRES with
     // FP32 (or BF16) Schur and block-Jacobi operators; x += delta.
-    //  * Inner tolerance: inner_tol, loosened to 0.3 tol / rho_max once the residual is
-    //    near the target, so a cycle never solves further than the outer stop needs.
+    //  * Inner tolerance: the reduction that finishes the solve when one cycle can
+    //    attain it (see there), else inner_tol; never further than the outer stop needs.
+    //  * Basis: with FP32 / BF16 operators the inner solve stores its Krylov basis in
+    //    FP32 (its arithmetic stays FP64): half the basis traffic of a step.
     //  * Null space: rho is projected off the left null vector before every inner solve
     //    (see there).
     //  * Precision: the attainable accuracy of a cycle is set by the Schur operator's
@@ -2127,7 +2137,14 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
         launch_mdot(nl, 0, 0, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
         launch_axpy_shared(W.rho, Pl.k, nl, W.scal, 1.0, W.rho, Pl.k, nrhs, s);
       }
-      const double itol = std::min(0.5, std::max(o.inner_tol, 0.3 * o.tol / cmax));
+      // inner tolerance: the reduction that finishes the solve (0.3 tol / rho_max) when
+      // one cycle at this precision can attain it (at least 1e-7 with FP32 operators,
+      // 1e-3 with BF16; looser than inner_tol near the target, tighter one cycle before
+      // it), else inner_tol.  A cycle with FP32 operators reaches about 3e-6 of its
+      // starting residual at best, so aiming lower only lengthens it.
+      const double need = 0.3 * o.tol / cmax;
+      const double reach = sprec == PREC_BF16 ? 1e-3 : sprec == PREC_F32 ? 1e-7 : 1e-12;
+      const double itol = std::min(0.5, need >= reach ? need : std::max(o.inner_tol, need));
       std::vector<int> it;
       rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, itol, o.maxit, it, s, sprec, mprec, o.graph != 0, rule);
       if (rc < 0) return rc;

@@ -13,7 +13,8 @@ constexpr int kMaxIt = 1000;     // largest Krylov dimension per solve
 constexpr int kRowsMax = 2048;   // rows of a k-vector handled by one block
 
 struct GmState {
-  double* V;        // basis: V + i*vvs + col*k (V_j holds the candidate u_j until it is final)
+  double* V;        // basis: V + i*vvs + col*k (V_j holds the candidate u_j until it is final);
+                    // with basis32 the same buffer holds FP32 entries at the same indices
   int64_t vvs;      // stride between basis vectors (= k * nrhs)
   double* w;        // operator output of the current step, col*k
   double* z;        // M^{-1} u_j
@@ -57,6 +58,7 @@ struct GmState {
   int* hseq;
   int pub_stride;
   int pub_every;
+  int basis32;      // 1: the basis is stored in FP32 (a float view of V; low-precision inner solves)
 };
 
 // u_0 = w into V_0, all columns active, j = 0 and the tolerance on the device

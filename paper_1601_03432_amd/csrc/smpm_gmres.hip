@@ -53,12 +53,18 @@ constexpr int kThreads = 256;
 // choice is uniform over a launch.
 constexpr int64_t kStreamBytes = 192ll << 20;
 __device__ __forceinline__ bool stream_basis(int64_t nvec, int64_t vvs) { return nvec * vvs * 8 > kStreamBytes; }
-template <bool NT>
-__device__ __forceinline__ double ld_basis(const double* p) {
+template <bool NT, typename VT>
+__device__ __forceinline__ double ld_basis(const VT* p) {
   if constexpr (NT)
-    return __builtin_nontemporal_load(p);
+    return (double)__builtin_nontemporal_load(p);
   else
-    return *p;
+    return (double)*p;
+}
+// The Krylov basis is stored in FP64, or in FP32 (a float view of the same buffer,
+// same element strides) for the inner solves of mixed precision; all arithmetic is FP64.
+template <typename VT>
+__device__ __forceinline__ VT* basis(const GmState& S) {
+  return reinterpret_cast<VT*>(S.V);
 }
 // kernels branch once on the choice and run a copy of their basis loops compiled for
 // it (the tag is std::true_type or std::false_type)
@@ -152,8 +158,8 @@ __device__ void reduce_partials2(const double* __restrict__ pa, const double* __
 // V_0..V_{nvec-1}: one pass over the basis for both vectors.  Wave q handles groups
 // of kDotUnroll basis vectors whose loads are all issued before the shuffle
 // reductions; lanes run over rows.
-template <bool NT>
-__device__ void chunk_dots2(const double* __restrict__ V, int64_t vvs, int64_t x0, int rows, const double* wv,
+template <bool NT, typename VT>
+__device__ void chunk_dots2(const VT* __restrict__ V, int64_t vvs, int64_t x0, int rows, const double* wv,
                             const double* uv, int nvec, double* partw, double* partu, int ld, int chunk) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i0 = wave * kDotUnroll; i0 < nvec; i0 += kWaves * kDotUnroll) {
@@ -294,7 +300,7 @@ __device__ __forceinline__ BlockGroup block_group(const DevPlan& P, int b, int b
 }
 
 // Step j's first kernel (see the file header; m = j - 1).  Step 0: z = M^{-1} u_0.
-template <typename OpT, bool PRE>
+template <typename OpT, bool PRE, typename VT>
 __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par, int use_precond, int transpose) {
   using Acc = typename AccOf<OpT>::type;
   constexpr int kGroup = kGroupBlocks;
@@ -327,7 +333,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   const bool nt = S.stream > 0 || (S.stream < 0 && stream_basis(j > 1 ? j : 1, S.vvs));
   const int64_t k = P.k;
   double* zc = S.z + (int64_t)col * k;
-  const double* Vc = S.V + (int64_t)col * k;
+  const VT* Vc = basis<VT>(S) + (int64_t)col * k;
   // The first group's inverse, and, when the group holds at most one slot per thread
   // and 1 <= m <= kPre, the thread's slot with its basis entries V_0..V_{m-1}, u_m and
   // w: loaded before the Gram-Schmidt sums are reduced (none of them needs a sum), so
@@ -435,8 +441,8 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
   }
   // q_m into V_m and u_{m+1} into V_{m+1} at one slot; returns u_{m+1} (step 0: u_0)
   const double* wc = S.w + (int64_t)col * k;
-  double* vm = S.V + (int64_t)max(m, 0) * S.vvs + (int64_t)col * k;
-  double* vn = S.V + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
+  VT* vm = basis<VT>(S) + (int64_t)max(m, 0) * S.vvs + (int64_t)col * k;
+  VT* vn = basis<VT>(S) + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
   // the products from basis vector i_begin on, then q_m and u_{m+1} at slot x
   auto finish = [&](auto nt_, int64_t x, int i_begin, double sc, double sw) {
     // batches of 32: every load of a batch is issued before its products, which run in
@@ -475,11 +481,13 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     }
     const double q = sc * inv;
     const double un = fma(-e, q, sw) * inv;
-    vm[x] = q;
-    vn[x] = un;
+    vm[x] = (VT)q;
+    vn[x] = (VT)un;
     return un;
   };
-  auto update = [&](auto nt_, int64_t x) { return m < 0 ? vn[x] : finish(nt_, x, 0, vm[x], wc[x]); };
+  auto update = [&](auto nt_, int64_t x) -> double {
+    return m < 0 ? (double)vn[x] : finish(nt_, x, 0, (double)vm[x], wc[x]);
+  };
   // the same from the prefetched entries (this thread's slot px, 1 <= m <= kPre): the
   // products in order, then q_m and u_{m+1} as finish() forms them
   auto update_pre = [&]() {
@@ -492,8 +500,8 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
       }
     const double q = sc * inv;
     const double un = fma(-e, q, sw) * inv;
-    vm[px] = q;
-    vn[px] = un;
+    vm[px] = (VT)q;
+    vn[px] = (VT)un;
     return un;
   };
   // the same at two slots, the loads of both in flight together (x1 is stored only
@@ -551,11 +559,11 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
     const double q0 = sc0 * inv, q1 = sc1 * inv;
     r0 = fma(-e, q0, sw0) * inv;
     r1 = fma(-e, q1, sw1) * inv;
-    vm[x0] = q0;
-    vn[x0] = r0;
+    vm[x0] = (VT)q0;
+    vn[x0] = (VT)r0;
     if (st1) {
-      vm[x1] = q1;
-      vn[x1] = r1;
+      vm[x1] = (VT)q1;
+      vn[x1] = (VT)r1;
     }
   };
   // block 0 takes the Givens step alone; blocks 1.. share the slots
@@ -613,7 +621,7 @@ __global__ __launch_bounds__(256) void k_gm_update(DevPlan P, GmState S, int par
 // Step j's first kernel for NC columns at once, with pre-reduced dot sums (large
 // grids, several columns): as k_gm_update, but every block-Jacobi inverse is read
 // once for the NC columns.  Same arithmetic per column, so the same bits.
-template <typename OpT, int NC>
+template <typename OpT, int NC, typename VT>
 __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int par, int use_precond, int transpose) {
   using Acc = typename AccOf<OpT>::type;
   constexpr int kStage = 128;
@@ -730,10 +738,10 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
   }
   auto update = [&](auto nt_, int c, int64_t x) {
     const int col = c0 + c;
-    const double* Vc = S.V + (int64_t)col * k;
-    double* vn = S.V + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
-    if (m < 0) return vn[x];
-    double* vm = S.V + (int64_t)m * S.vvs + (int64_t)col * k;
+    const VT* Vc = basis<VT>(S) + (int64_t)col * k;
+    VT* vn = basis<VT>(S) + (int64_t)(m + 1) * S.vvs + (int64_t)col * k;
+    if (m < 0) return (double)vn[x];
+    VT* vm = basis<VT>(S) + (int64_t)m * S.vvs + (int64_t)col * k;
     const double rho = scal[c][0], e = scal[c][1];
     const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
     double sc = vm[x], sw = S.w[(int64_t)col * k + x];
@@ -780,17 +788,17 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     }
     const double q = sc * inv;
     const double un = fma(-e, q, sw) * inv;
-    vm[x] = q;
-    vn[x] = un;
+    vm[x] = (VT)q;
+    vn[x] = (VT)un;
     return un;
   };
   // the same for column ca at slot xa and column cb at slot xb, the loads of both in
   // flight together (both columns active, m >= 0)
   auto update2 = [&](auto nt_, int ca, int64_t xa, int cb, int64_t xb, double& ra, double& rb) {
-    const double* Va = S.V + (int64_t)(c0 + ca) * k;
-    const double* Vb = S.V + (int64_t)(c0 + cb) * k;
-    double* vma = S.V + (int64_t)m * S.vvs + (int64_t)(c0 + ca) * k;
-    double* vmb = S.V + (int64_t)m * S.vvs + (int64_t)(c0 + cb) * k;
+    const VT* Va = basis<VT>(S) + (int64_t)(c0 + ca) * k;
+    const VT* Vb = basis<VT>(S) + (int64_t)(c0 + cb) * k;
+    VT* vma = basis<VT>(S) + (int64_t)m * S.vvs + (int64_t)(c0 + ca) * k;
+    VT* vmb = basis<VT>(S) + (int64_t)m * S.vvs + (int64_t)(c0 + cb) * k;
     double sca = vma[xa], swa = S.w[(int64_t)(c0 + ca) * k + xa];
     double scb = vmb[xb], swb = S.w[(int64_t)(c0 + cb) * k + xb];
     if (staged) {
@@ -851,10 +859,10 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
     const double qa = sca * inva, qb = scb * invb;
     ra = fma(-scal[ca][1], qa, swa) * inva;
     rb = fma(-scal[cb][1], qb, swb) * invb;
-    vma[xa] = qa;
-    S.V[(int64_t)(m + 1) * S.vvs + (int64_t)(c0 + ca) * k + xa] = ra;
-    vmb[xb] = qb;
-    S.V[(int64_t)(m + 1) * S.vvs + (int64_t)(c0 + cb) * k + xb] = rb;
+    vma[xa] = (VT)qa;
+    basis<VT>(S)[(int64_t)(m + 1) * S.vvs + (int64_t)(c0 + ca) * k + xa] = (VT)ra;
+    vmb[xb] = (VT)qb;
+    basis<VT>(S)[(int64_t)(m + 1) * S.vvs + (int64_t)(c0 + cb) * k + xb] = (VT)rb;
   };
   // block 0 takes the Givens steps alone; blocks 1.. share the slots
   if (blockIdx.x == 0 && gridDim.x > 1) return;
@@ -910,6 +918,7 @@ __global__ __launch_bounds__(256) void k_gm_update_n(DevPlan P, GmState S, int p
 // Step j's last kernel: w = t - (Z c2 + {S Z c2 | S^T Z c2}) on this block's rows (or
 // w = t), then the partial dots of V_0..V_j with w and with u_j = V_j; the next
 // step's index.
+template <typename VT>
 __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, int defl, int transpose) {
   __shared__ double wv[kRowsMax];
   __shared__ double uv[kRowsMax];
@@ -941,8 +950,8 @@ __global__ __launch_bounds__(256) void k_gm_dots(DevPlan P, GmState S, int par, 
   if (!S.active[col] || j > S.maxit) return;
   const double* tc = S.t + (int64_t)col * k;
   double* wc = S.w + (int64_t)col * k;
-  const double* Vc = S.V + (int64_t)col * k;
-  const double* uj = Vc + (int64_t)j * S.vvs;
+  const VT* Vc = basis<VT>(S) + (int64_t)col * k;
+  const VT* uj = Vc + (int64_t)j * S.vvs;
   const double* cc = S.c2 + (int64_t)col * P.d;
   const bool nt = S.stream > 0 || (S.stream < 0 && stream_basis(j + 1, S.vvs));
   double* p1 = S.part1 + (int64_t)col * S.ldv * S.nch;
@@ -1071,13 +1080,14 @@ __global__ __launch_bounds__(256) void k_gm_reduce(GmState S, int par) {
 
 // Start of a solve: u_0 = w (the initial residual) into V_0; all columns active;
 // j = 0 and the tolerance.
+template <typename VT>
 __global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S, double tol) {
   const int col = blockIdx.y, chunk = blockIdx.x, tid = threadIdx.x;
   const int64_t k = P.k, x0 = (int64_t)chunk * S.rows;
   const int rows = (int)min((int64_t)S.rows, k - x0);
   const double* wc = S.w + (int64_t)col * k;
-  double* v0 = S.V + (int64_t)col * k;
-  for (int q = tid; q < rows; q += kThreads) v0[x0 + q] = wc[x0 + q];
+  VT* v0 = basis<VT>(S) + (int64_t)col * k;
+  for (int q = tid; q < rows; q += kThreads) v0[x0 + q] = (VT)wc[x0 + q];
   if (chunk == 0 && tid == 0) {
     S.active[col] = 1;
     S.iters[col] = 0;
@@ -1091,6 +1101,7 @@ __global__ __launch_bounds__(256) void k_gm_start(DevPlan P, GmState S, double t
 // Start of a deflated solve from b: r_0 = b - (Z c2 + {S, S^T} Z c2) into w and V_0,
 // all columns active, j = 0 and the tolerance (the values of k_prolong followed by
 // k_gm_start, in one launch).
+template <typename VT>
 __global__ __launch_bounds__(256) void k_gm_start_defl(DevPlan P, GmState S, const double* __restrict__ b,
                                                        const double* __restrict__ c2, int transpose, double tol) {
   const int col = blockIdx.y, tid = threadIdx.x;
@@ -1108,7 +1119,7 @@ __global__ __launch_bounds__(256) void k_gm_start_defl(DevPlan P, GmState S, con
   const int64_t o = (int64_t)col * P.k + slot;
   const double v = b[o] + -1.0 * acc;
   S.w[o] = v;
-  S.V[o] = v;
+  basis<VT>(S)[o] = (VT)v;
 }
 
 // y = R^{-1} g for the first iters[col] columns (R = rotated Hessenberg), one
@@ -1153,12 +1164,13 @@ __global__ __launch_bounds__(256) void k_gm_lsq(GmState S) {
 }
 
 // x = sum_{i < iters[col]} y_i V_i
+template <typename VT>
 __global__ __launch_bounds__(256) void k_gm_combine(DevPlan P, GmState S, double* __restrict__ x) {
   const int col = blockIdx.y;
   const int64_t k = P.k;
   const int J = S.iters[col];
   const double* yc = S.y + (int64_t)col * S.ldv;
-  const double* Vc = S.V + (int64_t)col * k;
+  const VT* Vc = basis<VT>(S) + (int64_t)col * k;
   for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < k; q += (int64_t)gridDim.x * kThreads) {
     double acc = 0.0;
     for (int i0 = 0; i0 < J; i0 += 8) {
@@ -1177,12 +1189,18 @@ __global__ __launch_bounds__(256) void k_gm_combine(DevPlan P, GmState S, double
 
 void gm_start_deflated(const DevPlan& P, const GmState& S, int nrhs, const double* b, const double* c2, bool tr,
                        double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_start_defl, dim3((unsigned)((P.k + kThreads - 1) / kThreads), nrhs), dim3(kThreads), 0, s,
-                     P, S, b, c2, tr ? 1 : 0, tol);
+  const dim3 g((unsigned)((P.k + kThreads - 1) / kThreads), nrhs);
+  if (S.basis32)
+    hipLaunchKernelGGL(k_gm_start_defl<float>, g, dim3(kThreads), 0, s, P, S, b, c2, tr ? 1 : 0, tol);
+  else
+    hipLaunchKernelGGL(k_gm_start_defl<double>, g, dim3(kThreads), 0, s, P, S, b, c2, tr ? 1 : 0, tol);
 }
 
 void gm_start(const DevPlan& P, const GmState& S, int nrhs, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_start, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, tol);
+  if (S.basis32)
+    hipLaunchKernelGGL(k_gm_start<float>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, tol);
+  else
+    hipLaunchKernelGGL(k_gm_start<double>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, tol);
 }
 
 // block 0 of gm_update takes the Givens step; the others share the slots
@@ -1198,11 +1216,17 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
     // several columns per workgroup: each block-Jacobi inverse is read once for them
     const int nc = nrhs >= 4 ? 4 : 2;
     const dim3 pn(pg.x, (nrhs + nc - 1) / nc);
-#define SMPM_UPDATE_N(T)                                                                            \
-  if (nc == 4)                                                                                      \
-    hipLaunchKernelGGL((k_gm_update_n<T, 4>), pn, dim3(kThreads), 0, s, P, S, par, up, trn);         \
-  else                                                                                              \
-    hipLaunchKernelGGL((k_gm_update_n<T, 2>), pn, dim3(kThreads), 0, s, P, S, par, up, trn);
+#define SMPM_UPDATE_NV(T, VT)                                                                        \
+  if (nc == 4)                                                                                       \
+    hipLaunchKernelGGL((k_gm_update_n<T, 4, VT>), pn, dim3(kThreads), 0, s, P, S, par, up, trn);      \
+  else                                                                                               \
+    hipLaunchKernelGGL((k_gm_update_n<T, 2, VT>), pn, dim3(kThreads), 0, s, P, S, par, up, trn);
+#define SMPM_UPDATE_N(T)      \
+  if (S.basis32) {            \
+    SMPM_UPDATE_NV(T, float)  \
+  } else {                    \
+    SMPM_UPDATE_NV(T, double) \
+  }
     if (mprec == PREC_F32) {
       SMPM_UPDATE_N(float)
     } else if (mprec == PREC_BF16) {
@@ -1211,12 +1235,19 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
       SMPM_UPDATE_N(double)
     }
 #undef SMPM_UPDATE_N
+#undef SMPM_UPDATE_NV
   } else {
-#define SMPM_UPDATE_1(T)                                                                                   \
+#define SMPM_UPDATE_1V(T, VT)                                                                               \
   if (S.prereduce)                                                                                          \
-    hipLaunchKernelGGL((k_gm_update<T, true>), pg, dim3(kThreads), 0, s, P, S, par, up, trn);               \
+    hipLaunchKernelGGL((k_gm_update<T, true, VT>), pg, dim3(kThreads), 0, s, P, S, par, up, trn);           \
   else                                                                                                      \
-    hipLaunchKernelGGL((k_gm_update<T, false>), pg, dim3(kThreads), 0, s, P, S, par, up, trn);
+    hipLaunchKernelGGL((k_gm_update<T, false, VT>), pg, dim3(kThreads), 0, s, P, S, par, up, trn);
+#define SMPM_UPDATE_1(T)      \
+  if (S.basis32) {            \
+    SMPM_UPDATE_1V(T, float)  \
+  } else {                    \
+    SMPM_UPDATE_1V(T, double) \
+  }
     if (mprec == PREC_F32) {
       SMPM_UPDATE_1(float)
     } else if (mprec == PREC_BF16) {
@@ -1225,6 +1256,7 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
       SMPM_UPDATE_1(double)
     }
 #undef SMPM_UPDATE_1
+#undef SMPM_UPDATE_1V
   }
   const bool fused_sums = kind == 3 && !tr && schur_has_side_sums(P) && P.coarse_mode == 1;
   launch_schur_ex(P, S.z, S.t, nrhs, tr, S.active, fused_sums ? S.sides : nullptr, s, sprec);
@@ -1236,8 +1268,12 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
       launch_coarse(P, S.c, S.c2, nrhs, tr, S.active, s);
     }
   }
-  hipLaunchKernelGGL(k_gm_dots, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
-                     tr ? 1 : 0);
+  if (S.basis32)
+    hipLaunchKernelGGL(k_gm_dots<float>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
+                       tr ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_gm_dots<double>, dim3(S.nch, nrhs), dim3(kThreads), 0, s, P, S, par, kind == 3 ? 1 : 0,
+                       tr ? 1 : 0);
   if (S.prereduce)
     hipLaunchKernelGGL(k_gm_reduce, dim3((S.maxit + kReduceVecs) / kReduceVecs, nrhs), dim3(256), 0, s, S, par);
 }
@@ -1245,7 +1281,10 @@ void gm_step(const DevPlan& P, const GmState& S, int nrhs, int par, int kind, bo
 void gm_finish(const DevPlan& P, const GmState& S, int nrhs, double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_gm_lsq, dim3(nrhs), dim3(kThreads), 0, s, S);
   const int64_t blocks = std::min<int64_t>((P.k + kThreads - 1) / kThreads, 2048);
-  hipLaunchKernelGGL(k_gm_combine, dim3((unsigned)blocks, nrhs), dim3(kThreads), 0, s, P, S, x);
+  if (S.basis32)
+    hipLaunchKernelGGL(k_gm_combine<float>, dim3((unsigned)blocks, nrhs), dim3(kThreads), 0, s, P, S, x);
+  else
+    hipLaunchKernelGGL(k_gm_combine<double>, dim3((unsigned)blocks, nrhs), dim3(kThreads), 0, s, P, S, x);
 }
 
 int gm_rows_per_chunk(int64_t k) {
