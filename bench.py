@@ -364,13 +364,14 @@ def main():
         def s3_fp64(rhs):
             return c3.solve(rhs, tol=1e-10, maxit=600)
 
-        def s3_mixed(rhs):
-            return c3.solve(rhs, tol=1e-10, maxit=600, precision=smpm.MIXED_FP32, inner_tol=1e-5, max_refine=30)
+        def s3_mixed(rhs, prec=smpm.MIXED_FP32):
+            return c3.solve(rhs, tol=1e-10, maxit=600, precision=prec, inner_tol=1e-5, max_refine=30)
 
         tuned3 = {"1": c3.autotune(1), str(w3.nrhs): c3.autotune(w3.nrhs)}
         t1, i1, _ = timed(s3_fp64, F3[:1].contiguous(), 5, 1)
         tb, ib, _ = timed(s3_fp64, F3, 3, 1)
         tm, im, _ = timed(s3_mixed, F3, 3, 1)
+        tbf, ibf, _ = timed(lambda r: s3_mixed(r, smpm.MIXED_BF16), F3, 3, 1)
         out["batched_c3"] = {
             "workload": "c3: 64x64 elements, n=12, [0,1]^2, r=589824, k=193536, d=8064 (substructured coarse "
                         "solve), 32 advected random-Fourier sources + noise (std 1e-3), tol 1e-10",
@@ -380,6 +381,10 @@ def main():
             "mixed_fp32_batched32_solves_per_s": w3.nrhs / tm, "mixed_batched32_iterations": im.iterations,
             "mixed_batched32_refinements": im.refinements, "mixed_batched32_true_rel_residual_max": im.rel_residual,
             "mixed_batched_vs_fp64_single": (w3.nrhs / tm) * t1,
+            "mixed_bf16_batched32_solves_per_s": w3.nrhs / tbf, "mixed_bf16_batched32_iterations": ibf.iterations,
+            "mixed_bf16_batched32_refinements": ibf.refinements,
+            "mixed_bf16_batched32_final_schur_precision": ["fp64", "fp32", "bf16"][ibf.schur_precision],
+            "mixed_bf16_batched32_true_rel_residual_max": ibf.rel_residual,
             "autotuned": tuned3,
         }
         del c3, F3
@@ -403,6 +408,7 @@ def main():
         t51, i51, _ = timed(lambda r: s5(r, G5[:1].contiguous(), smpm.FP64), F5[:1].contiguous(), 2, 1)
         t5b, i5b, u5b = timed(lambda r: s5(r, G5, smpm.FP64), F5, 2, 1)
         t5m, i5m, u5m = timed(lambda r: s5(r, G5, smpm.MIXED_FP32), F5, 2, 1)
+        t5h, i5h, _ = timed(lambda r: s5(r, G5, smpm.MIXED_BF16), F5, 1, 1)
         out["c5"] = {
             "workload": "c5: 128x128 elements, n=16, x-stretched (ratio 1.05, aspect <= 8) on [0,1]x[0,%.4f], "
                         "r=%d, k=%d, d=%d (substructured coarse solve), 8 random-Fourier sources + nonzero "
@@ -417,6 +423,9 @@ def main():
             "mixed_vs_fp64_rel_l2_max": float(max(torch.linalg.norm(u5m[c] - u5b[c]) / torch.linalg.norm(u5b[c])
                                                   for c in range(8))),
             "mixed_batched_vs_fp64_single": (8 / t5m) * t51,
+            "mixed_bf16_batched8_solves_per_s": 8 / t5h, "mixed_bf16_batched8_iterations": i5h.iterations,
+            "mixed_bf16_batched8_refinements": i5h.refinements,
+            "mixed_bf16_batched8_true_rel_residual_max": i5h.rel_residual,
             "autotuned": tuned5,
         }
         del ctx5, F5, G5, u5b, u5m
@@ -460,15 +469,31 @@ def main():
         m = O.Method(g)
         xo, yo = g.node_coords()
         fo = wl.eval_fourier(params, xo, yo, w.Lx, w.Ly)
+        import threadpoolctl
         t0 = time.perf_counter()
         for _ in range(args.cpu_solves):
             m.solve(fo, variant=3, tol=1e-10, maxit=600)
         t1 = time.perf_counter()
-        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        # the threads the oracle's numeric libraries actually had (their pools' sizes)
+        pools = threadpoolctl.threadpool_info()
+        cores = max([p.get("num_threads", 1) for p in pools] + [1])
+        with threadpoolctl.threadpool_limits(limits=1):
+            s0 = time.perf_counter()
+            m.solve(fo, variant=3, tol=1e-10, maxit=600)
+            s1 = time.perf_counter()
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": args.cpu_solves / (t1 - t0), "unit": "solves/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"{args.cpu_solves} oracle Algorithm-3 solves of the same c2 problem "
-                                         f"(numpy/scipy FP64, setup excluded)"}
+                                         f"(numpy/scipy FP64, setup excluded)",
+                               "one_core": {"value": 1.0 / (s1 - s0), "cores": 1,
+                                            "sample": "1 solve of the same problem, numeric libraries on one thread"},
+                               "cpu_model": model}
     print(json.dumps(out))
 
 
