@@ -211,7 +211,8 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   rc |= dalloc(w.mem, &w.y, ldh * R);
   const size_t nch = reduce_chunks(std::max<int64_t>(P.r, P.k));
   // reduction partials: the multi-dots' chunks, or one per back-substitution block
-  const size_t nbk = (size_t)((P.ntile + 7) / 8 * 8) * (size_t)((P.n * P.n + 63) / 64);
+  const size_t ntp = (size_t)((P.ntile + 7) / 8 * 8);  // tile-blocks of the element applies
+  const size_t nbk = std::max(ntp * (size_t)((P.n * P.n + 63) / 64), 4 * ntp);
   rc |= dalloc(w.mem, &w.part, std::max(nch * ldh, nbk) * R);
   rc |= ialloc(w.mem, &w.active, R);
   rc |= ialloc(w.mem, &w.jcount, R);
@@ -564,15 +565,20 @@ int run_phase(smpm_ctx* c, bool use_graph, int phase, const GmState& S, int nrhs
 
 // GMRES prologue for right-hand side b: the stopping reference |b|^2, the initial
 // residual r0 = P b (kind 3) or b into W.w, and gm_start (V_0, flags, tolerance).
-// (norm_done: the caller already formed |b|^2 there, by the same reduction.)
+// (norm_done: the caller already formed |b|^2 there, by the same reduction; sides_done:
+// and the per-side sums of b in W.sides, for the dense coarse solve.)
 void gm_prologue(smpm_ctx* c, const GmState& S, int kind, bool tr, const double* b, int nrhs, double tol,
-                 hipStream_t s, bool norm_done = false) {
+                 hipStream_t s, bool norm_done = false, bool sides_done = false) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   if (!norm_done) launch_mdot(b, 0, P.k, 1, b, P.k, nullptr, P.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
   if (kind == 3) {
-    launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
-    launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
+    if (sides_done) {
+      launch_coarse_sides(P, W.sides, W.c2, nrhs, tr, nullptr, s);  // Z^T b = the interfaces' side sums
+    } else {
+      launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
+      launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
+    }
     gm_start_deflated(P, S, nrhs, b, W.c2, tr, tol, s);  // r0 = P b into w and V_0
   } else {
     launch_copy(b, W.w, P.k * nrhs, s);
@@ -1894,17 +1900,23 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   launch_rhs(P, f, tr ? nullptr : g, W.rhs, nrhs, W.nonfinite, s);
   // u_L^T (f + T g) (adjoint: 1^T c) per column, published with the post-processing
   double* removed = W.scal2 + 3 * nrhs;
+  // b_hat's side sums feed the dense coarse solve of the GMRES start (sides of n
+  // consecutive slots, summed by n-lane butterflies: n a power of two)
+  const bool sides_ok = o.variant == 3 && Pl.has_coarse && P.coarse_mode == 1 && P.d > 0 && Pl.n <= 64 &&
+                        (Pl.n & (Pl.n - 1)) == 0;
   auto pre_body = [&](hipStream_t q) {
     if (!tr) {
       // steps 1-3: f~ = (I - u_L u_L^T)(f + T g); b_S = B A^{-1} f~; b_hat = (I - u_S u_S^T) b_S
       launch_mdot(c->uL, 0, 0, 1, W.rhs, Pl.r, nullptr, Pl.r, nrhs, W.part, removed, nullptr, q);
-      if (!launch_flux_projected(P, W.rhs, c->uL, removed, 1.0, W.ft, W.bS, nrhs, q)) {
+      // f~ while B A^{-1} stages it, with u_S^T b_S from the stored slots
+      if (!launch_flux_projected(P, W.rhs, c->uL, removed, 1.0, W.ft, W.bS, nrhs, q, c->uS, W.part, W.scal)) {
         launch_axpy_shared(W.rhs, Pl.r, c->uL, removed, 1.0, W.ft, Pl.r, nrhs, q);
         launch_flux(P, W.ft, W.bS, nrhs, q);
+        launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
       }
-      launch_mdot(c->uS, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
-      // b_hat, and |b_hat|^2 (the GMRES stopping reference) in the same launch
-      launch_axpy_norm2(W.bS, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, W.part, W.scal2 + 2 * nrhs, q);
+      // b_hat, and |b_hat|^2 (the GMRES stopping reference) and its side sums in the same launch
+      launch_axpy_norm2(W.bS, c->uS, W.scal, 1.0, W.bhat, Pl.k, nrhs, W.part, W.scal2 + 2 * nrhs, q,
+                        sides_ok ? W.sides : nullptr, P.n);
     } else {
       // adjoint of the solution map: c~ = c - w (1^T c)/(w^T 1); S^T xi = E^T A^{-T} c~
       // (consistent: v0^T E^T A^{-T} c~ = -1^T c~ = 0), projected off v0 against rounding
@@ -1912,7 +1924,8 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       launch_axpy_shared(W.rhs, Pl.r, c->wq, removed, 1.0 / c->wsum, W.ft, Pl.r, nrhs, q);
       launch_local_adj(P, W.ft, W.bS, nrhs, true, q);
       launch_mdot(c->v0hat, 0, 0, 1, W.bS, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, q);
-      launch_axpy_norm2(W.bS, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, W.part, W.scal2 + 2 * nrhs, q);
+      launch_axpy_norm2(W.bS, c->v0hat, W.scal, 1.0, W.bhat, Pl.k, nrhs, W.part, W.scal2 + 2 * nrhs, q,
+                        sides_ok ? W.sides : nullptr, P.n);
     }
   };
   // step 9 up to the last store: forward u = A^{-1}(f~ - E x) into W.ubuf and w^T u
@@ -1967,7 +1980,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     S.bref2 = rule == 1 ? nullptr : W.scal2 + 2 * nrhs;
     rc = run_phase(c, use_graph, 1, S, nrhs, kind, tr, PREC_F64, PREC_F64, o.tol, s, [&](hipStream_t q) {
       pre_body(q);
-      gm_prologue(c, S, kind, tr, W.bhat, nrhs, o.tol, q, true);  // |b_hat|^2 formed with b_hat
+      gm_prologue(c, S, kind, tr, W.bhat, nrhs, o.tol, q, true, sides_ok);  // |b_hat|^2 (and sides) with b_hat
     });
     if (rc) return rc;
     mark(1);

@@ -334,25 +334,29 @@ void launch_axpy_shared(const double* x, int64_t x_cs, const double* u, const do
 void launch_scale_inv(const double* x, int64_t x_cs, const double* nrm, bool sq, double* y, int64_t y_cs,
                       int64_t len, int nrhs, const int* active, hipStream_t s);
 void launch_add(const double* a, const double* b, double sb, double* y, int64_t len, int nrhs, hipStream_t s);
-// Fused pairs (each gives the bits of the two launches it replaces):
+// Fused pairs (the first three give the bits of the two launches they replace):
 //  out[col] = sum_x (a + sb b)[x]^2                         (launch_add, then launch_mdot of the result with itself)
 void launch_norm2_diff(const double* a, const double* b, double sb, int64_t len, int nrhs, double* part, double* out,
                        hipStream_t s);
-//  y = x - dot[col] * scale * u, out[col] = |y|^2            (launch_axpy_shared, then launch_mdot(y, y))
+//  y = x - dot[col] * scale * u, out[col] = |y|^2            (launch_axpy_shared, then launch_mdot(y, y));
+//  with sides != nullptr also the sums of y over runs of n entries into sides (len / n per column; n a
+//  power of two <= 64: the per-side sums of a slot vector)
 void launch_axpy_norm2(const double* x, const double* u, const double* dot, double scale, double* y, int64_t len,
-                       int nrhs, double* part, double* out, hipStream_t s);
+                       int nrhs, double* part, double* out, hipStream_t s, double* sides = nullptr, int n = 0);
 //  c = Z^T (a + sb t)                                       (launch_add, then launch_iface_sum)
 void launch_iface_sum_diff(const DevPlan& P, const double* a, const double* t, double sb, double* c, int nrhs,
                            hipStream_t s);
-//  ft = f - dot[col] * scale * u (r-vector), then b = B A^{-1} ft; false (nothing launched) when the
-//  element applies do not run on the matrix cores (n > 16)
-//  u = A^{-1}(f - E x) and out[col] = wq . u (partials in part, at least 4 * ntile + 32
-//  per column); false (nothing launched) when the element applies do not run on the
-//  matrix cores (n > 16)
+//  u = A^{-1}(f - E x) and out[col] = wq . u (partials in part, one per tile-block and row
+//  group); false (nothing launched) when the element applies do not run on the matrix
+//  cores (n > 16)
 bool launch_backsub_dot(const DevPlan& P, const double* f, const double* x, double* u, const double* wq, int nrhs,
                         double* part, double* out, hipStream_t s);
+//  ft = f - dot[col] * scale * u (r-vector), then b = B A^{-1} ft, and with du != nullptr
+//  dout[col] = du . b (partials in part, 4 per tile-block); false (nothing launched) when the
+//  element applies do not run on the matrix cores (n > 16)
 bool launch_flux_projected(const DevPlan& P, const double* f, const double* u, const double* dot, double scale,
-                           double* ft, double* b, int nrhs, hipStream_t s);
+                           double* ft, double* b, int nrhs, hipStream_t s, const double* du = nullptr,
+                           double* part = nullptr, double* dout = nullptr);
 
 // ---- GMRES small dense work (one thread per column)
 // H(col) (ldh x maxit col-major: H[j*ldh + i]), cs, sn, g of length ldh; hnew: j+1 coefficients,

@@ -951,14 +951,21 @@ __device__ __forceinline__ void mma_load_a(double (&a)[kMmaBatch], int m0, int k
 // (s, i) of element u lands on the neighbour's slot facing side s (tile_dst).
 // With pu != nullptr the staged values are ft = f - pdot[col] * pscale * pu (written
 // to ft as well): the projection that precedes B A^{-1} in the solve.
+// With du != nullptr each wave also writes the partial sum of du . b over the slots it
+// stores to part[col][block][wave] (zeros for idle waves and padding blocks).
 __global__ __launch_bounds__(256) void k_flux_mfma(DevPlan P, const double* __restrict__ f, double* __restrict__ b,
                                                    const double* __restrict__ pu, const double* __restrict__ pdot,
-                                                   double pscale, double* __restrict__ ft) {
+                                                   double pscale, double* __restrict__ ft,
+                                                   const double* __restrict__ du, double* __restrict__ part) {
   __shared__ double fs[kMmaN2 * kTileLd];
   __shared__ double os[4][kTile * kTileLd];
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
-  if (tile >= P.ntile) return;
   const int col = blockIdx.y;
+  double* pw = du ? part + ((int64_t)col * gridDim.x + blockIdx.x) * 4 + (threadIdx.x >> 6) : nullptr;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= P.ntile) {
+    if (pw && (threadIdx.x & 63) == 0) *pw = 0.0;
+    return;
+  }
   const int n = P.n, n2 = P.n2, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int J = P.tile_cls[tile];
   const int* el = P.tile_elem + tile * kTile;
@@ -1003,17 +1010,28 @@ __global__ __launch_bounds__(256) void k_flux_mfma(DevPlan P, const double* __re
     for (int v = 0; v < 4; ++v) os[wave][r * kTileLd + Mma<double>::row(lane, v)] = acc[v];
   }
   __syncthreads();
-  if (!act) return;
+  if (!act) {
+    if (pw && lane == 0) *pw = 0.0;
+    return;
+  }
   // row-contiguous stores: row (s, i) of element u to the neighbour's slot facing s
   double* bc = b + (int64_t)col * P.k;
+  double dsum = 0.0;
   for (int q = lane; q < kTile * 16; q += 64) {
     const int u = q >> 4, rr = q & 15;
     const int orow = rt * 16 + rr;
     if (orow >= 4 * n || el[u] < 0) continue;
     const int os_ = orow / n, oi = orow - os_ * n;
     const int base = dst[u * 4 + os_];
-    if (base >= 0) bc[base + oi] = os[wave][u * kTileLd + rr];
+    if (base >= 0) {
+      const double v = os[wave][u * kTileLd + rr];
+      bc[base + oi] = v;
+      if (du) dsum = fma(du[base + oi], v, dsum);
+    }
   }
+  if (!pw) return;
+  for (int off = 32; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off);
+  if (lane == 0) *pw = dsum;
 }
 
 // u_e = A_e^{-1} (f_e - E_e x) on element tiles: the tile's right-hand sides are
@@ -1598,10 +1616,13 @@ __global__ __launch_bounds__(256) void k_norm2_diff_part(const double* __restric
 }
 
 // y = x - dot[col] * scale * u written, with the partial sums of |y|^2 as above
+// (with sides != nullptr, also the sums of y over each run of n consecutive entries,
+// n a power of two <= 64: the per-side sums of a slot vector)
 __global__ __launch_bounds__(256) void k_axpy_norm2_part(const double* __restrict__ xv, const double* __restrict__ u,
                                                          const double* __restrict__ dot, double scale,
                                                          double* __restrict__ y, int64_t len, int nchunks,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part, double* __restrict__ sides,
+                                                         int n) {
   __shared__ double red[4];
   const int chunk = blockIdx.x, col = blockIdx.y;
   const int64_t x0 = (int64_t)chunk * kChunk;
@@ -1619,6 +1640,17 @@ __global__ __launch_bounds__(256) void k_axpy_norm2_part(const double* __restric
 #pragma unroll
   for (int q = 0; q < 8; ++q)
     if (x0 + q * 256 + threadIdx.x < len) acc = fma(yv[q], yv[q], acc);
+  if (sides) {
+    // n consecutive lanes hold one side's entries for each q: a butterfly over them
+    const int64_t nsides = len / n;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double v = yv[q];
+      for (int off = n >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      const int64_t x = x0 + q * 256 + threadIdx.x;
+      if ((threadIdx.x & (n - 1)) == 0 && x / n < nsides) sides[(int64_t)col * nsides + x / n] = v;
+    }
+  }
   const double sum = block_sum_256(acc, red);
   if (threadIdx.x == 0) part[(int64_t)col * nchunks + chunk] = sum;
 }
@@ -1983,7 +2015,8 @@ void launch_flux(const DevPlan& P, const double* f, double* b, int nrhs, hipStre
   if (P.mma_mt > 0 && P.n2 <= kMmaN2) {
     // a multiple of 8 workgroups, so that the XCD-aware order is a permutation of the tiles
     hipLaunchKernelGGL(k_flux_mfma, dim3((P.ntile + 7) / 8 * 8, nrhs), dim3(256), 0, s, P, f, b,
-                       (const double*)nullptr, (const double*)nullptr, 0.0, (double*)nullptr);
+                       (const double*)nullptr, (const double*)nullptr, 0.0, (double*)nullptr, (const double*)nullptr,
+                       (double*)nullptr);
     return;
   }
   hipLaunchKernelGGL(k_flux, dim3(P.nel, nrhs), dim3(64), 4 * P.n2 * sizeof(double), s, P, f, b);
@@ -2001,9 +2034,14 @@ bool launch_backsub_dot(const DevPlan& P, const double* f, const double* x, doub
 }
 
 bool launch_flux_projected(const DevPlan& P, const double* f, const double* u, const double* dot, double scale,
-                           double* ft, double* b, int nrhs, hipStream_t s) {
+                           double* ft, double* b, int nrhs, hipStream_t s, const double* du, double* part,
+                           double* dout) {
   if (!(P.mma_mt > 0 && P.n2 <= kMmaN2)) return false;
-  hipLaunchKernelGGL(k_flux_mfma, dim3((P.ntile + 7) / 8 * 8, nrhs), dim3(256), 0, s, P, f, b, u, dot, scale, ft);
+  const int nb = (P.ntile + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_flux_mfma, dim3(nb, nrhs), dim3(256), 0, s, P, f, b, u, dot, scale, ft, du, part);
+  if (du)
+    hipLaunchKernelGGL(k_mdot_final, grid1((int64_t)nrhs, 128), dim3(128), 0, s, part, 1, 4 * nb, nrhs, dout,
+                       (const int*)nullptr);
   return true;
 }
 
@@ -2143,9 +2181,10 @@ void launch_norm2_diff(const double* a, const double* b, double sb, int64_t len,
 }
 
 void launch_axpy_norm2(const double* x, const double* u, const double* dot, double scale, double* y, int64_t len,
-                       int nrhs, double* part, double* out, hipStream_t s) {
+                       int nrhs, double* part, double* out, hipStream_t s, double* sides, int n) {
   const int nch = reduce_chunks(len);
-  hipLaunchKernelGGL(k_axpy_norm2_part, dim3(nch, nrhs), dim3(256), 0, s, x, u, dot, scale, y, len, nch, part);
+  hipLaunchKernelGGL(k_axpy_norm2_part, dim3(nch, nrhs), dim3(256), 0, s, x, u, dot, scale, y, len, nch, part,
+                     sides, n);
   hipLaunchKernelGGL(k_mdot_final, grid1((int64_t)nrhs, 128), dim3(128), 0, s, part, 1, nch, nrhs, out,
                      (const int*)nullptr);
 }
