@@ -706,6 +706,86 @@ def gmres(apply_op, b, tol=1e-10, maxit=400):
     return V[:, :len(y)] @ y, j + 1, hist
 
 
+def block_orthonormalize(W, drop):
+    """Q (k x r), R (r x s) with W = Q R: the columns of W taken in order, each made
+    orthogonal to the kept ones by Gram-Schmidt applied twice; a column whose
+    remaining part is <= drop times its own norm adds no vector (rank deflation) and
+    keeps only its coefficients on the earlier vectors."""
+    k, s = W.shape
+    Q = []
+    R = np.zeros((s, s))
+    for i in range(s):
+        w = W[:, i].copy()
+        nrm0 = np.linalg.norm(w)
+        for _ in range(2):
+            for c, q in enumerate(Q):
+                h = q @ w
+                R[c, i] += h
+                w = w - h * q
+        nrm = np.linalg.norm(w)
+        if nrm0 > 0.0 and nrm > drop * nrm0:
+            R[len(Q), i] = nrm
+            Q.append(w / nrm)
+    r = len(Q)
+    return (np.column_stack(Q) if r else np.zeros((k, 0))), R[:r, :]
+
+
+def block_gmres(apply_op, B, tol=1e-10, maxit=400, ref=None, drop=1e-6):
+    """Block GMRES from X0 = 0 for op(X) = B with s columns (not in the paper: its
+    step 4 solved for all right-hand sides in one block Krylov space).  The iterate
+    after j block steps minimizes every column's residual over the block Krylov space
+    span{B, op B, ..., op^{j-1} B}.  Block Arnoldi: the new block op(V_j) is made
+    orthogonal to every basis vector by block classical Gram-Schmidt applied twice,
+    then orthonormalized within itself by block_orthonormalize (whose dropped columns
+    shrink the next block); the least-squares problem min ||E_1 R_0 - H Y|| is
+    re-solved by lstsq at every step.  Stops when every column's least-squares
+    residual is <= tol * ref[c] (ref: the columns' norms of B by default), when no
+    vector is added, or after maxit block steps.  Returns (X, steps, history), history
+    the per-column residuals after each step (the first entry those of B)."""
+    k, s = B.shape
+    ref = np.linalg.norm(B, axis=0) if ref is None else np.asarray(ref, float)
+    V0, R0 = block_orthonormalize(B, drop)
+    hist = [np.linalg.norm(B, axis=0)]
+    if V0.shape[1] == 0:
+        return np.zeros_like(B), 0, hist
+    V = V0
+    blocks = [V0.shape[1]]      # sizes of the blocks V_0, V_1, ...
+    Hcols = []                  # block columns of H, each (rows so far) x r_j
+    Y = np.zeros((0, s))
+    X = np.zeros_like(B)
+    steps = 0
+    for j in range(maxit):
+        n_old = V.shape[1]
+        lo = n_old - blocks[-1]
+        Vj = V[:, lo:]
+        Wb = apply_op(Vj)
+        h = V.T @ Wb
+        Wb = Wb - V @ h
+        h2 = V.T @ Wb
+        Wb = Wb - V @ h2
+        h = h + h2
+        Vn, Rn = block_orthonormalize(Wb, drop)
+        Hcols.append(np.vstack([h, Rn]))
+        rows = n_old + Vn.shape[1]
+        H = np.zeros((rows, n_old))
+        c0 = 0
+        for hc in Hcols:
+            H[:hc.shape[0], c0:c0 + hc.shape[1]] = hc
+            c0 += hc.shape[1]
+        E = np.zeros((rows, s))
+        E[:R0.shape[0], :] = R0
+        Y, *_ = np.linalg.lstsq(H, E, rcond=None)
+        res = np.linalg.norm(E - H @ Y, axis=0)
+        hist.append(res)
+        steps = j + 1
+        X = V @ Y
+        if np.all(res <= tol * ref) or Vn.shape[1] == 0:
+            break
+        V = np.hstack([V, Vn])
+        blocks.append(Vn.shape[1])
+    return X, steps, hist
+
+
 class Method:
     """Algorithms 1, 2 and 3 of the paper on one grid."""
 
@@ -735,6 +815,32 @@ class Method:
         u = sys.back_substitute(ft, x)                      # step 9 (+ constant fixed)
         true_res = np.linalg.norm(bhat - S @ x) / max(np.linalg.norm(bhat), 1e-300)
         return u, {"iters": it, "history": hist, "x": x, "bhat": bhat, "true_rel_res": true_res}
+
+    def solve_block(self, F, variant=3, tol=1e-10, maxit=400, drop=1e-6):
+        """Algorithm 3 (or 1, 2) for the columns of F (r x s) with step 4 solved by
+        block_gmres over all columns at once, stopping at tol * |b_hat| per column.
+        Returns (U, info)."""
+        sys = self.sys
+        S = sys.S
+        cols = [sys.schur_rhs(F[:, c]) for c in range(F.shape[1])]
+        Bh = np.column_stack([c[2] for c in cols])
+        ref = np.linalg.norm(Bh, axis=0)
+        Minv = lambda Z: np.column_stack([self.M.solve(Z[:, c]) for c in range(Z.shape[1])])
+        if variant == 1:
+            X, it, hist = block_gmres(lambda Z: S @ Z, Bh, tol, maxit, ref, drop)
+        elif variant == 2:
+            Xp, it, hist = block_gmres(lambda Z: S @ Minv(Z), Bh, tol, maxit, ref, drop)
+            X = Minv(Xp)
+        else:
+            P = self.defl.P
+            Pc = lambda Z: np.column_stack([P(Z[:, c]) for c in range(Z.shape[1])])
+            X1, it, hist = block_gmres(lambda Z: Pc(S @ Minv(Z)), Pc(Bh), tol, maxit, ref, drop)
+            X1 = Minv(X1)
+            X = np.column_stack([self.defl.Q(X1[:, c]) + self.defl.coarse_part(Bh[:, c])
+                                 for c in range(Bh.shape[1])])
+        U = np.column_stack([sys.back_substitute(cols[c][0], X[:, c]) for c in range(Bh.shape[1])])
+        true_res = np.linalg.norm(Bh - S @ X, axis=0) / np.maximum(ref, 1e-300)
+        return U, {"iters": it, "history": hist, "X": X, "Bhat": Bh, "true_rel_res": true_res}
 
 
 # ---------------------------------------------------------------------------
