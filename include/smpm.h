@@ -143,6 +143,15 @@ typedef struct smpm_solve_opts {
   int profile;        /* 1: time the solve's phases with HIP events recorded on its stream
                          (smpm_solve_info.phase_ms); 0 (default): no timing.  The environment
                          SMPM_PROFILE=1 turns it on as well                                     */
+  int block;          /* 1: step 4 as block GMRES (FP64 only, at most 32 columns): all columns
+                         share one block Krylov space span{R0, op R0, ...}, R0 the deflated
+                         right-hand sides, each column's residual minimized over all of it;
+                         the basis is extended by block classical Gram-Schmidt applied twice
+                         and Cholesky QR applied twice, and a block column whose part
+                         orthogonal to the block's earlier columns is at most 1e-6 of its norm
+                         adds no vector (rank deflation).  Iterations count block steps;
+                         maxit caps them.  0 (default): each column its own GMRES, batched.
+                         opts.graph is not used by the block path                             */
 } smpm_solve_opts;
 
 typedef struct smpm_solve_info {

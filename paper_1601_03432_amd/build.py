@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsmpm.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HIP_SOURCES = ["smpm_kernels.hip", "smpm_gmres.hip", "smpm_abi.hip"]
+HIP_SOURCES = ["smpm_kernels.hip", "smpm_gmres.hip", "smpm_block.hip", "smpm_abi.hip"]
 CXX_SOURCES = ["smpm_plan.cpp", "smpm_coarse.cpp"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]

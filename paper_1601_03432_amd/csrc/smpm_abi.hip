@@ -18,6 +18,7 @@
 
 #include "../../include/smpm.h"
 #include "smpm_gmres.h"
+#include "smpm_block.h"
 #include "smpm_kernels.h"
 #include "smpm_plan.h"
 
@@ -75,6 +76,21 @@ struct Workspace {
   std::vector<void*> mem;
 };
 
+// Block GMRES workspace for (s columns, maxit block steps); grown on demand.  The
+// basis lives in Workspace::V (s (maxit + 1) vectors fit there).
+struct BlockWs {
+  int s = 0, maxit = 0, cap = 0, ldH = 0;
+  double *H = nullptr, *refl = nullptr, *rbeta = nullptr, *G = nullptr, *res = nullptr;
+  double *h = nullptr, *h2 = nullptr, *gram = nullptr, *T1 = nullptr, *T2 = nullptr, *R1 = nullptr, *R2 = nullptr;
+  double *Y = nullptr, *part = nullptr;
+  int* cnt = nullptr;        // device: kept counts of the two Cholesky QR passes
+  int* hcnt = nullptr;       // pinned: the same, published after each step
+  double* hres = nullptr;    // pinned: least-squares residual per column
+  double* href = nullptr;    // pinned: squared stopping reference per column
+  std::vector<void*> mem;
+  void* pinned = nullptr;
+};
+
 }  // namespace
 
 struct smpm_ctx {
@@ -95,6 +111,7 @@ struct smpm_ctx {
   int null_iterations = 0;                   // GMRES iterations the null-vector solve took
   std::vector<double> h_uL, h_uS;
   Workspace ws;
+  BlockWs bws;
   // captured chunks of Arnoldi steps, keyed by the solve's shape; they hold workspace
   // pointers, so a workspace reallocation drops them
   struct GraphEntry {
@@ -121,6 +138,8 @@ struct smpm_ctx {
       if (group_stream) (void)hipStreamDestroy(group_stream);
       for (void* p : ws.mem) (void)hipFree(p);
       if (ws.pinned) (void)hipHostFree(ws.pinned);
+      for (void* p : bws.mem) (void)hipFree(p);
+      if (bws.pinned) (void)hipHostFree(bws.pinned);
       for (void* p : mem) (void)hipFree(p);
     }
   }
@@ -259,6 +278,44 @@ int ensure_ws(smpm_ctx* c, int nrhs, int maxit) {
   if (hipDeviceSynchronize() != hipSuccess) return fail(SMPM_EHIP, "hipDeviceSynchronize failed");
   w.nrhs = nrhs;
   w.maxit = maxit;
+  return SMPM_OK;
+}
+
+int ensure_bws(smpm_ctx* c, int s, int maxit) {
+  BlockWs& b = c->bws;
+  if (b.s >= s && b.maxit >= maxit) return SMPM_OK;
+  s = std::max(s, b.s);
+  maxit = std::max(maxit, b.maxit);
+  for (void* p : b.mem) (void)hipFree(p);
+  if (b.pinned) (void)hipHostFree(b.pinned);
+  b = BlockWs();
+  const size_t cap = (size_t)s * (maxit + 1), ldH = cap + kBgMaxCols, S = s, sq = kBgMaxCols * kBgMaxCols;
+  int rc = SMPM_OK;
+  rc |= dalloc(b.mem, &b.H, ldH * cap);
+  rc |= dalloc(b.mem, &b.refl, cap * 64);
+  rc |= dalloc(b.mem, &b.rbeta, cap);
+  rc |= dalloc(b.mem, &b.G, ldH * S);
+  rc |= dalloc(b.mem, &b.res, S);
+  rc |= dalloc(b.mem, &b.h, ldH * S);
+  rc |= dalloc(b.mem, &b.h2, ldH * S);
+  rc |= dalloc(b.mem, &b.gram, sq);
+  rc |= dalloc(b.mem, &b.T1, sq);
+  rc |= dalloc(b.mem, &b.T2, sq);
+  rc |= dalloc(b.mem, &b.R1, sq);
+  rc |= dalloc(b.mem, &b.R2, sq);
+  rc |= dalloc(b.mem, &b.Y, cap * S);
+  rc |= dalloc(b.mem, &b.part, (size_t)bg_dot_part_size());
+  rc |= ialloc(b.mem, &b.cnt, 2);
+  if (rc != SMPM_OK) return SMPM_ENOMEM;
+  if (hipHostMalloc(&b.pinned, 64 + 2 * S * sizeof(double), hipHostMallocCoherent) != hipSuccess)
+    return fail(SMPM_ENOMEM, "hipHostMalloc failed");
+  b.hcnt = static_cast<int*>(b.pinned);
+  b.hres = reinterpret_cast<double*>(static_cast<char*>(b.pinned) + 64);
+  b.href = b.hres + S;
+  b.s = s;
+  b.maxit = maxit;
+  b.cap = (int)cap;
+  b.ldH = (int)ldH;
   return SMPM_OK;
 }
 
@@ -842,6 +899,114 @@ int true_residual(smpm_ctx* c, bool tr, const double* b, const double* x, int nr
   return SMPM_OK;
 }
 
+// Rank-deflation threshold of block GMRES: a block column whose part orthogonal to
+// the block's earlier columns is at most this fraction of its norm adds no vector
+// (the Gram matrix resolves relative parts down to about 1e-7 in FP64).
+constexpr double kBlockDrop = 1e-6;
+
+// Cholesky QR applied twice to the m columns at wb (m <= kBgMaxCols), with rank
+// deflation in the first pass: the kept vectors go to dst (columns past the kept
+// count are zero), the count to B.cnt[1] (B.cnt[0]: the first pass), and R (kept x m,
+// ld kBgMaxCols, wb = dst R) to B.R2.  tmp: scratch of m vectors.
+void block_cholqr(smpm_ctx* c, const double* wb, int m, double* dst, double* tmp, hipStream_t s) {
+  BlockWs& B = c->bws;
+  const int64_t k = c->dp.k;
+  launch_bg_dot(wb, m, wb, m, k, B.part, B.gram, m, 0.0, s);
+  launch_bg_chol(B.gram, m, kBlockDrop, nullptr, nullptr, B.cnt, B.T1, B.R1, s);
+  launch_bg_update(wb, m, B.T1, m, 1.0, nullptr, 0.0, tmp, m, k, s);
+  launch_bg_dot(tmp, m, tmp, m, k, B.part, B.gram, m, 0.0, s);
+  launch_bg_chol(B.gram, m, 0.0, B.cnt, B.R1, B.cnt + 1, B.T2, B.R2, s);
+  launch_bg_update(tmp, m, B.T2, m, 1.0, nullptr, 0.0, dst, m, k, s);
+}
+
+// Block GMRES (FP64) from x1 = 0 for op(x1) = b, all nrhs <= kBgMaxCols columns in one
+// block Krylov space, op by kind as in gmres (OP_S, OP_SM, OP_PSM; P b is the start
+// for OP_PSM).  Each block step: W = op(V_j); block classical Gram-Schmidt against the
+// whole basis, applied twice (the sums and updates on matrix cores); Cholesky QR of
+// W twice, with rank deflation, gives V_{j+1} and the block's subdiagonal part; the
+// least-squares problem is updated by Householder reflections.  x1 = V Y at the end.
+// Stops when every column's least-squares residual is <= tol times its reference
+// (ref2: squared references on the device; null: the start block's column norms),
+// when a block adds no vector, or after maxit block steps.  res0 (host, optional)
+// receives column 0's residual / reference after each step (the start first).
+// Returns the block steps taken, or a negative status.
+int block_gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x1, int nrhs, double tol, int maxit,
+                const double* ref2, hipStream_t s, std::vector<double>* res0 = nullptr) {
+  const DevPlan& P = c->dp;
+  Workspace& W = c->ws;
+  BlockWs& B = c->bws;
+  const int64_t k = P.k;
+  double* r0 = W.w;
+  if (kind == OP_PSM) {
+    launch_iface_sum(P, b, W.c, nrhs, nullptr, s);
+    launch_coarse(P, W.c, W.c2, nrhs, tr, nullptr, s);
+    launch_prolong(P, b, W.c2, r0, nrhs, tr ? 2 : 1, -1.0, nullptr, s);
+  } else {
+    launch_copy(b, r0, k * nrhs, s);
+  }
+  if (!ref2) {
+    launch_mdot(r0, 0, k, 1, r0, k, nullptr, k, nrhs, W.part, W.scal, nullptr, s);
+    ref2 = W.scal;
+  }
+  HIPCHK(hipMemcpyAsync(B.href, ref2, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  BgLsq L{B.H, B.ldH, B.refl, B.rbeta, B.G, nrhs, B.res};
+  block_cholqr(c, r0, nrhs, W.V, W.t, s);
+  launch_bg_lsq_start(L, B.R2, B.cnt + 1, s);
+  // |R_0| per column = the start block's column norms (the reflections keep them)
+  launch_bg_dot(r0, nrhs, r0, nrhs, k, B.part, B.gram, nrhs, 0.0, s);
+  HIPCHK(hipMemcpyAsync(B.hcnt, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  std::vector<double> g0(nrhs * nrhs);
+  HIPCHK(hipMemcpyAsync(g0.data(), B.gram, g0.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> ref(nrhs);
+  for (int i = 0; i < nrhs; ++i) ref[i] = std::sqrt(std::max(B.href[i], 0.0));
+  if (res0) res0->assign(1, ref[0] > 0 ? std::sqrt(std::max(g0[0], 0.0)) / ref[0] : 0.0);
+  int nv = B.hcnt[1];
+  if (B.hcnt[1] != B.hcnt[0]) return fail(SMPM_EHIP, "block orthonormalization lost a vector in its second pass");
+  int n0 = 0, steps = 0;
+  const int ldh = B.ldH;
+  for (int j = 0; j < maxit && nv > n0; ++j) {
+    const int r = nv - n0;
+    apply_op(c, kind, tr, W.V + (int64_t)n0 * k, W.w, r, nullptr, s);
+    launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h, ldh, 0.0, s);
+    launch_bg_update(W.V, nv, B.h, ldh, -1.0, W.w, 1.0, W.w, r, k, s);
+    launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h2, ldh, 0.0, s);
+    launch_bg_update(W.V, nv, B.h2, ldh, -1.0, W.w, 1.0, W.w, r, k, s);
+    launch_add(B.h, B.h2, 1.0, B.h, (int64_t)ldh * r, 1, s);
+    block_cholqr(c, W.w, r, W.V + (int64_t)nv * k, W.t, s);
+    launch_bg_lsq(L, n0, r, nv, B.h, ldh, B.R2, B.cnt + 1, B.hres, B.hcnt, s);
+    HIPCHK(hipMemcpyAsync(B.hcnt, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (B.hcnt[1] != B.hcnt[0]) return fail(SMPM_EHIP, "block orthonormalization lost a vector in its second pass");
+    steps = j + 1;
+    n0 = nv;
+    nv += B.hcnt[1];
+    bool done = true, finite = true;
+    for (int i = 0; i < nrhs; ++i) {
+      if (!std::isfinite(B.hres[i])) finite = false;
+      if (!(B.hres[i] <= tol * ref[i])) done = false;
+    }
+    if (res0) res0->push_back(ref[0] > 0 ? B.hres[0] / ref[0] : 0.0);
+    if (done || !finite) break;
+  }
+  launch_bg_backsolve(L, n0, B.Y, B.cap, s);
+  if (n0 > 0)
+    launch_bg_update(W.V, n0, B.Y, B.cap, 1.0, nullptr, 0.0, x1, nrhs, k, s);
+  else
+    HIPCHK(hipMemsetAsync(x1, 0, sizeof(double) * k * nrhs, s));
+  return steps;
+}
+
+// block_gmres, then x from its solution (Algorithm 3 steps 5-8 for OP_PSM).
+int block_solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, int nrhs, double tol,
+                      int maxit, const double* ref2, hipStream_t s, std::vector<double>* res0) {
+  Workspace& W = c->ws;
+  const int rc = block_gmres(c, kind, tr, bhat, W.x, nrhs, tol, maxit, ref2, s, res0);
+  if (rc < 0) return rc;
+  recover_x(c, kind, tr, bhat, W.x, x, nrhs, PREC_F64, PREC_F64, s);
+  return rc;
+}
+
 // Upper bound of ||S||_2: sqrt(||S||_1 ||S||_inf), from the class operators (S = I +
 // the side fluxes W; row sums over the neighbour's slots, column sums over the four
 // receiving sides).
@@ -1383,6 +1548,7 @@ void smpm_default_opts(smpm_solve_opts* o) {
   o->graph = 1;
   o->stop_rule = 0;
   o->profile = 0;
+  o->block = 0;
 }
 
 const char* smpm_last_error(void) { return g_err.c_str(); }
@@ -1872,6 +2038,8 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   const size_t rb = sizeof(double) * Pl.r * nrhs;
   if (aliases(f, rb, u, rb)) return fail(SMPM_EINVAL, "f and u alias");
   if (o.stop_rule != 0 && o.stop_rule != 1) return fail(SMPM_EINVAL, "stop_rule must be 0 or 1");
+  if (o.block != 0 && o.precision != SMPM_FP64) return fail(SMPM_EINVAL, "block GMRES runs in FP64 only");
+  if (o.block != 0 && nrhs > kBgMaxCols) return fail(SMPM_EINVAL, "block GMRES takes at most 32 columns");
   hipStream_t s = static_cast<hipStream_t>(stream);
   rc = compute_null_vectors(c, s);
   if (rc) return rc;
@@ -1967,7 +2135,64 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     ++ncyc;
   };
   bool conv = true;
-  if (o.precision == SMPM_FP64) {
+  if (o.block) {
+    // Steps 1-3, then step 4 as block GMRES over all columns (FP64, launched as it
+    // goes: a block step waits for its kept count), steps 5-9; FP64 correction cycles
+    // as below when the true residual misses tol.
+    rc = ensure_bws(c, nrhs, o.maxit);
+    if (rc) return rc;
+    pre_body(s);
+    mark(1);
+    std::vector<double> res0;
+    const int st0 = block_solve_schur(c, kind, tr, W.bhat, W.bS, nrhs, o.tol, o.maxit,
+                                      rule == 1 ? nullptr : W.scal2 + 2 * nrhs, s, &res0);
+    if (st0 < 0) return st0;
+    iters.assign(nrhs, st0);
+    note_cycle(iters);
+    rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
+    if (rc) return rc;
+    for (int extra = 0; extra < 2; ++extra) {
+      double worst = 0.0;
+      bool fixable = true, any = false;
+      for (int i = 0; i < nrhs; ++i) {
+        if (tres[i] <= o.tol) continue;
+        any = true;
+        if (!std::isfinite(tres[i]) || iters[i] >= o.maxit) fixable = false;
+        worst = std::max(worst, tres[i]);
+      }
+      if (!any || !fixable) break;
+      launch_copy(W.bS, W.xacc, Pl.k * nrhs, s);
+      launch_schur(P, W.xacc, W.t, nrhs, tr, nullptr, s);
+      launch_add(W.bhat, W.t, -1.0, W.rho, Pl.k, nrhs, s);
+      const double* nl = tr ? c->v0hat : c->uS;
+      launch_mdot(nl, 0, 0, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
+      launch_axpy_shared(W.rho, Pl.k, nl, W.scal, 1.0, W.rho, Pl.k, nrhs, s);
+      const int st = block_solve_schur(c, kind, tr, W.rho, W.bS, nrhs, std::min(0.5, 0.3 * o.tol / worst), o.maxit,
+                                       nullptr, s, &res0);
+      if (st < 0) return st;
+      std::vector<int> it(nrhs, st);
+      note_cycle(it);
+      for (int i = 0; i < nrhs; ++i) iters[i] += st;
+      launch_add(W.xacc, W.bS, 1.0, W.bS, Pl.k, nrhs, s);
+      ++cycles;
+      rc = true_residual(c, tr, W.bhat, W.bS, nrhs, tres, s);
+      if (rc) return rc;
+    }
+    for (int i = 0; i < nrhs; ++i)
+      if (!(tres[i] <= o.tol)) conv = false;
+    mark(2);
+    post_body(W.bS, s);
+    store_u(s);
+    launch_publish(removed, nrhs, W.hout + 2 * nrhs, s);
+    // history: column 0's least-squares residual / reference after each block step
+    W.hist_len = (int)std::min<size_t>(res0.size(), (size_t)W.maxit + 1);
+    for (int i = 0; i < W.hist_len; ++i) {
+      W.hhist[i] = res0[i];
+      W.hhist_cs[i] = 0.0;
+    }
+    *W.hhist_tolb = 1.0;
+    W.hist_tol = 1.0;
+  } else if (o.precision == SMPM_FP64) {
     // One pass with a single synchronization: [steps 1-3, GMRES start] as one phase;
     // the Arnoldi chunks; [closing rotation, least squares, recovery of x into W.bS
     // (steps 5-8), the FP64 true residual, step 9 into W.ubuf] as another; the store

@@ -1,0 +1,406 @@
+// Block GMRES kernels (see smpm_block.h).  The block Krylov method is not in the
+// paper; it solves Algorithm 3's step 4 for all right-hand sides in one space.
+#include "smpm_block.h"
+
+#include <algorithm>
+
+namespace smpm {
+
+namespace {
+
+typedef double bg_v4d __attribute__((ext_vector_type(4)));
+
+// 16x16x4 FP64 matrix-core step.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and holds C[(l / 16) + 4 v][l % 16] in register v.
+__device__ __forceinline__ bg_v4d bg_mma(double a, double b, bg_v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+constexpr int kTargetBlocks = 2048;  // workgroups a dot launch aims for
+constexpr int kMinChunk = 256;       // shortest x chunk of a dot workgroup
+
+void dot_chunks(int64_t len, int na, int* nch, int64_t* per) {
+  const int64_t ablk = (na + 63) / 64;
+  int64_t want = std::max<int64_t>(1, kTargetBlocks / ablk);
+  want = std::min<int64_t>(want, std::max<int64_t>(1, (len + kMinChunk - 1) / kMinChunk));
+  int64_t p = (len + want - 1) / want;
+  p = (p + 15) / 16 * 16;
+  *per = p;
+  *nch = (int)((len + p - 1) / p);
+}
+
+// Partial sums of A^T B over one x chunk: workgroup (chunk, 64 rows of A), wavefront
+// w owns A rows 16w..16w+15 against all (<= 32) columns of B.  Step q of an unrolled
+// group of four takes x = xb + 4q + l/16 for both operands, so each lane reads its
+// own A row and B row at the same x.
+__global__ __launch_bounds__(256) void k_bg_dot(const double* __restrict__ A, int na, const double* __restrict__ B,
+                                                int nb, int64_t len, int64_t per, double* __restrict__ part) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int a0 = blockIdx.y * 64 + wave * 16;
+  if (a0 >= na) return;  // no barrier below
+  const int64_t x0 = (int64_t)blockIdx.x * per;
+  const int64_t x1 = min(len, x0 + per);
+  const int ar = a0 + (lane & 15);
+  const bool aok = ar < na;
+  const double* ap = A + (int64_t)(aok ? ar : 0) * len;
+  const int b0 = lane & 15, b1 = 16 + (lane & 15);
+  const bool two = nb > 16;
+  const bool b0ok = b0 < nb, b1ok = b1 < nb;
+  const double* bp0 = B + (int64_t)(b0ok ? b0 : 0) * len;
+  const double* bp1 = B + (int64_t)(b1ok ? b1 : 0) * len;
+  const int kq = lane >> 4;
+  bg_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t xb = x0; xb < x1; xb += 16) {
+    double av[4], bv0[4], bv1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t x = xb + 4 * q + kq;
+      const int64_t xc = x < x1 ? x : x0;  // in bounds; masked below
+      av[q] = ap[xc];
+      bv0[q] = bp0[xc];
+      bv1[q] = two ? bp1[xc] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = aok && xb + 4 * q + kq < x1;
+      const double a = ok ? av[q] : 0.0;
+      acc0 = bg_mma(a, b0ok ? bv0[q] : 0.0, acc0);
+      if (two) acc1 = bg_mma(a, b1ok ? bv1[q] : 0.0, acc1);
+    }
+  }
+  const int bc = lane & 15;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = a0 + (lane >> 4) + 4 * v;
+    if (a >= na) continue;
+    if (bc < nb) part[((int64_t)blockIdx.x * nb + bc) * na + a] = acc0[v];
+    if (two && 16 + bc < nb) part[((int64_t)blockIdx.x * nb + 16 + bc) * na + a] = acc1[v];
+  }
+}
+
+__global__ void k_bg_dot_final(const double* __restrict__ part, int na, int nb, int nch, double* __restrict__ out,
+                               int ldo, double beta) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= na * nb) return;
+  const int a = idx % na, b = idx / na;
+  double acc = 0.0;
+  for (int c = 0; c < nch; ++c) acc += part[((int64_t)c * nb + b) * na + a];
+  double* o = out + (int64_t)b * ldo + a;
+  *o = beta != 0.0 ? beta * *o + acc : acc;
+}
+
+// out = beta win + alpha A H: workgroup of four wavefronts, each 16 consecutive x
+// against all (<= 32) columns; the contraction runs over the na vectors of A in
+// groups of 16 (four matrix-core steps, a = ab + 4q + l/16).
+__global__ __launch_bounds__(256) void k_bg_update(const double* __restrict__ A, int na, const double* __restrict__ H,
+                                                   int ldh, double alpha, const double* win, double beta, double* out,
+                                                   int nb, int64_t len) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (x0 >= len) return;
+  const int64_t xr = x0 + (lane & 15);
+  const int64_t xc = xr < len ? xr : x0;
+  const int kq = lane >> 4, bc = lane & 15;
+  const bool two = nb > 16;
+  const bool b0ok = bc < nb, b1ok = 16 + bc < nb;
+  const double* h0 = H + (int64_t)(b0ok ? bc : 0) * ldh;
+  const double* h1 = H + (int64_t)(b1ok ? 16 + bc : 0) * ldh;
+  bg_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int ab = 0; ab < na; ab += 16) {
+    double av[4], hv0[4], hv1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = ab + 4 * q + kq;
+      const int ac = a < na ? a : 0;
+      av[q] = A[(int64_t)ac * len + xc];
+      hv0[q] = h0[ac];
+      hv1[q] = two ? h1[ac] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = ab + 4 * q + kq < na;
+      const double a = ok ? av[q] : 0.0;
+      acc0 = bg_mma(a, b0ok ? hv0[q] : 0.0, acc0);
+      if (two) acc1 = bg_mma(a, b1ok ? hv1[q] : 0.0, acc1);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t x = x0 + (lane >> 4) + 4 * v;
+    if (x >= len) continue;
+    if (b0ok) {
+      const int64_t o = (int64_t)bc * len + x;
+      out[o] = beta != 0.0 ? beta * win[o] + alpha * acc0[v] : alpha * acc0[v];
+    }
+    if (two && b1ok) {
+      const int64_t o = (int64_t)(16 + bc) * len + x;
+      out[o] = beta != 0.0 ? beta * win[o] + alpha * acc1[v] : alpha * acc1[v];
+    }
+  }
+}
+
+// Cholesky QR pass (one wavefront; see launch_bg_chol).  Gs[i + 32 j] = G_ij,
+// Rs[c + 32 i] = R_ci, Ts[i + 32 c] = T_ic.
+__global__ __launch_bounds__(64) void k_bg_chol(const double* __restrict__ G, int m, double drop,
+                                                const int* __restrict__ cnt_in, const double* __restrict__ rprev,
+                                                int* __restrict__ cnt, double* __restrict__ T, double* __restrict__ R) {
+  __shared__ double Gs[kBgMaxCols * kBgMaxCols], Rs[kBgMaxCols * kBgMaxCols], Ts[kBgMaxCols * kBgMaxCols];
+  const int l = threadIdx.x;
+  const int mm = cnt_in ? min(*cnt_in, m) : m;
+  for (int q = l; q < kBgMaxCols * kBgMaxCols; q += 64) {
+    Gs[q] = 0.0;
+    Rs[q] = 0.0;
+    Ts[q] = 0.0;
+  }
+  __syncthreads();
+  for (int q = l; q < m * m; q += 64) Gs[(q % m) + kBgMaxCols * (q / m)] = G[q];
+  __syncthreads();
+  int kept = 0;
+  for (int i = 0; i < mm; ++i) {
+    const double ri = l < kept ? Rs[l + kBgMaxCols * i] : 0.0;
+    const double p = wave_sum(ri * ri);
+    const double gii = Gs[i + kBgMaxCols * i];
+    const double d = gii - p;
+    // NaN fails every comparison: such a column is dropped
+    const bool keep = gii > 0.0 && d > 0.0 && d > drop * drop * gii;
+    if (keep) {
+      const double rho = sqrt(d);
+      double rl = 0.0, tl = 0.0;
+      if (l > i && l < mm) {
+        rl = Gs[i + kBgMaxCols * l];
+        for (int c = 0; c < kept; ++c) rl -= Rs[c + kBgMaxCols * i] * Rs[c + kBgMaxCols * l];
+        rl /= rho;
+      }
+      if (l < m) {
+        tl = l == i ? 1.0 : 0.0;
+        for (int c = 0; c < kept; ++c) tl -= Rs[c + kBgMaxCols * i] * Ts[l + kBgMaxCols * c];
+        tl /= rho;
+      }
+      __syncthreads();
+      if (l > i && l < mm) Rs[kept + kBgMaxCols * l] = rl;
+      if (l < m) Ts[l + kBgMaxCols * kept] = tl;
+      if (l == 0) Rs[kept + kBgMaxCols * i] = rho;
+      ++kept;
+    }
+    __syncthreads();
+  }
+  if (l == 0) *cnt = kept;
+  for (int q = l; q < m * m; q += 64) T[q] = Ts[(q % m) + kBgMaxCols * (q / m)];
+  for (int q = l; q < kBgMaxCols * kBgMaxCols; q += 64) {
+    const int c = q % kBgMaxCols, i = q / kBgMaxCols;
+    double v = 0.0;
+    if (c < kept && i < m) {
+      if (rprev) {
+        for (int cp = 0; cp < mm; ++cp) v += Rs[c + kBgMaxCols * cp] * rprev[cp + kBgMaxCols * i];
+      } else {
+        v = Rs[c + kBgMaxCols * i];
+      }
+    }
+    R[q] = v;
+  }
+}
+
+constexpr int kLsqWaves = 16;  // wavefronts of the least-squares kernel
+
+// Block step of the Householder least-squares update (one workgroup, 16 wavefronts).
+// Work slots: the r new columns of Hbar, then the s columns of G; wavefront w owns
+// slots w, w + 16, w + 32, w + 48.  A slot keeps a 64-row window of its column in
+// registers, row rho in lane rho % 64, so a reflection of rows p .. p+63 is one
+// multiply-add and one wavefront sum per lane; when p advances, the row leaving the
+// window is stored and the row entering it loaded.  Reflections are at most 64 rows
+// long (a column's rows below its diagonal are the r + cnt of its block step).
+__global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int r, int nv,
+                                                          const double* __restrict__ h, int ldh,
+                                                          const double* __restrict__ R, const int* __restrict__ cntp,
+                                                          double* host_res, int* host_cnt) {
+  __shared__ double vsh[64];
+  __shared__ double bsh;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int cnt = *cntp;
+  const int rows = nv + cnt;
+  const int s = L.s;
+  const int64_t ld = L.ldH;
+  // the new columns of Hbar
+  for (int q = tid; q < r * rows; q += 64 * kLsqWaves) {
+    const int c = q / rows, row = q % rows;
+    L.H[(int64_t)(n0 + c) * ld + row] = row < nv ? h[(int64_t)c * ldh + row] : R[(row - nv) + kBgMaxCols * c];
+  }
+  __syncthreads();
+  const int nslot = r + s;
+  double* col[4];
+  double reg[4];
+  bool own[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = wave + kLsqWaves * u;
+    own[u] = q < nslot;
+    col[u] = q < r ? L.H + (int64_t)(n0 + q) * ld : L.G + (int64_t)(own[u] ? q - r : 0) * ld;
+    // H slots start their window at row 0, G slots at row n0 (earlier reflections
+    // were applied to G in earlier steps)
+    const int base = q < r ? 0 : n0;
+    const int row = base + ((lane - base) & 63);
+    reg[u] = own[u] && row < rows ? col[u][row] : 0.0;
+  }
+  // advance the window of slot u past row p
+  auto advance = [&](int u, int p) {
+    if (lane == (p & 63)) {
+      col[u][p] = reg[u];
+      reg[u] = p + 64 < rows ? col[u][p + 64] : 0.0;
+    }
+  };
+  // earlier reflections on the new columns
+  for (int p = 0; p < n0; ++p) {
+    const int t = (lane - p) & 63;
+    const double v = L.refl[(int64_t)p * 64 + t];
+    const double be = L.rbeta[p];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = wave + kLsqWaves * u;
+      if (!own[u] || q >= r) continue;
+      if (be != 0.0) {
+        const double dt = wave_sum(v * reg[u]);
+        reg[u] -= be * dt * v;
+      }
+      advance(u, p);
+    }
+  }
+  // the new columns' own reflections, applied to the later new columns and to G
+  for (int c = 0; c < r; ++c) {
+    const int p = n0 + c;
+    const int t = (lane - p) & 63;
+    const int len = rows - p;
+    if (wave == c % kLsqWaves) {
+      const int u = c / kLsqWaves;
+      const double x = t < len ? reg[u] : 0.0;
+      const double sig = wave_sum(t >= 1 ? x * x : 0.0);
+      const double x0 = __shfl(x, p & 63);
+      double v = 0.0, be = 0.0, alpha = x0;
+      if (sig > 0.0) {
+        const double nrm = sqrt(x0 * x0 + sig);
+        alpha = x0 >= 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        v = t == 0 ? v0 : x;
+        be = 2.0 / (v0 * v0 + sig);
+      }
+      vsh[t] = v;
+      if (lane == 0) bsh = be;
+      L.refl[(int64_t)p * 64 + t] = v;
+      if (lane == 0) L.rbeta[p] = be;
+      if (lane == (p & 63)) col[u][p] = alpha;
+    }
+    __syncthreads();
+    const double v = vsh[t];
+    const double be = bsh;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = wave + kLsqWaves * u;
+      if (!own[u] || q <= c) continue;
+      if (be != 0.0) {
+        const double dt = wave_sum(v * reg[u]);
+        reg[u] -= be * dt * v;
+      }
+      advance(u, p);
+    }
+    __syncthreads();  // vsh is rewritten by the next column
+  }
+  // G: store the window (rows nv .. rows-1 hold the residual block) and the residuals
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = wave + kLsqWaves * u;
+    if (!own[u] || q < r) continue;
+    const int row = nv + ((lane - nv) & 63);
+    if (row < rows) col[u][row] = reg[u];
+    const double rs = sqrt(wave_sum(row < rows ? reg[u] * reg[u] : 0.0));
+    if (lane == 0) {
+      L.res[q - r] = rs;
+      host_res[q - r] = rs;
+    }
+  }
+  if (tid == 0) {
+    host_cnt[0] = cnt;
+  }
+}
+
+// Y = triangle(H)^{-1} G[0 .. ncol): Y starts as G, then column-oriented back
+// substitution (one workgroup).
+__global__ __launch_bounds__(1024) void k_bg_backsolve(BgLsq L, int ncol, double* __restrict__ Y, int ldy) {
+  const int tid = threadIdx.x;
+  const int s = L.s;
+  for (int q = tid; q < ncol * s; q += 1024) {
+    const int row = q % ncol, g = q / ncol;
+    Y[(int64_t)g * ldy + row] = L.G[(int64_t)g * L.ldH + row];
+  }
+  __syncthreads();
+  for (int i = ncol - 1; i >= 0; --i) {
+    const double* hc = L.H + (int64_t)i * L.ldH;
+    if (tid < s) {
+      const double d = hc[i];
+      Y[(int64_t)tid * ldy + i] = d != 0.0 ? Y[(int64_t)tid * ldy + i] / d : 0.0;
+    }
+    __syncthreads();
+    for (int q = tid; q < i * s; q += 1024) {
+      const int row = q % i, g = q / i;
+      Y[(int64_t)g * ldy + row] -= hc[row] * Y[(int64_t)g * ldy + i];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_bg_lsq_start(BgLsq L, const double* __restrict__ R0, const int* __restrict__ m) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= L.ldH * L.s) return;
+  const int row = (int)(idx % L.ldH), g = (int)(idx / L.ldH);
+  L.G[idx] = row < *m ? R0[row + kBgMaxCols * g] : 0.0;
+}
+
+}  // namespace
+
+int64_t bg_dot_part_size() { return (int64_t)(kTargetBlocks + 64) * 64 * kBgMaxCols; }
+
+void launch_bg_dot(const double* A, int na, const double* B, int nb, int64_t len, double* part, double* out,
+                   int ldo, double beta, hipStream_t s) {
+  if (na <= 0 || nb <= 0) return;
+  int nch;
+  int64_t per;
+  dot_chunks(len, na, &nch, &per);
+  hipLaunchKernelGGL(k_bg_dot, dim3(nch, (na + 63) / 64), dim3(256), 0, s, A, na, B, nb, len, per, part);
+  const int tot = na * nb;
+  hipLaunchKernelGGL(k_bg_dot_final, dim3((tot + 255) / 256), dim3(256), 0, s, part, na, nb, nch, out, ldo, beta);
+}
+
+void launch_bg_update(const double* A, int na, const double* H, int ldh, double alpha, const double* win,
+                      double beta, double* out, int nb, int64_t len, hipStream_t s) {
+  if (nb <= 0) return;
+  const int64_t blocks = (len + 63) / 64;
+  hipLaunchKernelGGL(k_bg_update, dim3((unsigned)blocks), dim3(256), 0, s, A, na, H, ldh, alpha, win, beta, out, nb,
+                     len);
+}
+
+void launch_bg_chol(const double* G, int m, double drop, const int* cnt_in, const double* rprev, int* cnt, double* T,
+                    double* R, hipStream_t s) {
+  hipLaunchKernelGGL(k_bg_chol, dim3(1), dim3(64), 0, s, G, m, drop, cnt_in, rprev, cnt, T, R);
+}
+
+void launch_bg_lsq(const BgLsq& L, int n0, int r, int nv, const double* h, int ldh, const double* R, const int* cnt,
+                   double* host_res, int* host_cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_bg_lsq, dim3(1), dim3(64 * kLsqWaves), 0, s, L, n0, r, nv, h, ldh, R, cnt, host_res,
+                     host_cnt);
+}
+
+void launch_bg_backsolve(const BgLsq& L, int ncol, double* Y, int ldy, hipStream_t s) {
+  if (ncol <= 0) return;
+  hipLaunchKernelGGL(k_bg_backsolve, dim3(1), dim3(1024), 0, s, L, ncol, Y, ldy);
+}
+
+void launch_bg_lsq_start(const BgLsq& L, const double* R0, const int* m, hipStream_t s) {
+  const int64_t tot = (int64_t)L.ldH * L.s;
+  hipLaunchKernelGGL(k_bg_lsq_start, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L, R0, m);
+}
+
+}  // namespace smpm

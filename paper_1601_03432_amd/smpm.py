@@ -39,7 +39,7 @@ ABI_SYMBOLS = (
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("transpose", C.c_int),
                 ("variant", C.c_int), ("inner_tol", C.c_double), ("max_refine", C.c_int), ("graph", C.c_int),
-                ("stop_rule", C.c_int), ("profile", C.c_int)]
+                ("stop_rule", C.c_int), ("profile", C.c_int), ("block", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -348,7 +348,7 @@ class Context:
 
     def solve(self, f, g=None, tol=1e-10, maxit=400, variant=3, precision=FP64, transpose=False,
               inner_tol=1e-5, max_refine=20, stream=None, raise_on_noconv=True, graph=True, stop_rule=0,
-              profile=False):
+              profile=False, block=False):
         import torch
         f = self._as_cols(f, self.r)
         nrhs = f.shape[0]
@@ -361,11 +361,11 @@ class Context:
                 raise ValueError("g must have as many columns as f")
             gp = C.c_void_p(g.data_ptr())
         u = torch.empty_like(f)
-        key = (tol, maxit, precision, transpose, variant, inner_tol, max_refine, graph, stop_rule, profile)
+        key = (tol, maxit, precision, transpose, variant, inner_tol, max_refine, graph, stop_rule, profile, block)
         opts = self._opts_cache.get(key)
         if opts is None:
             opts = SolveOpts(tol, maxit, precision, int(transpose), variant, inner_tol, max_refine, int(graph),
-                             int(stop_rule), int(profile))
+                             int(stop_rule), int(profile), int(block))
             if len(self._opts_cache) < 64:
                 self._opts_cache[key] = opts
         info = SolveInfo()
