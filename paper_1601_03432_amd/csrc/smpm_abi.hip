@@ -82,7 +82,7 @@ struct BlockWs {
   int s = 0, maxit = 0, cap = 0, ldH = 0;
   double *H = nullptr, *refl = nullptr, *rbeta = nullptr, *G = nullptr, *res = nullptr;
   double *h = nullptr, *h2 = nullptr, *gram = nullptr, *T1 = nullptr, *T2 = nullptr, *R1 = nullptr, *R2 = nullptr;
-  double *Y = nullptr, *part = nullptr;
+  double *Y = nullptr, *part = nullptr, *ht = nullptr;
   int* cnt = nullptr;        // device: kept counts of the two Cholesky QR passes
   int* hcnt = nullptr;       // pinned: the same, published after each step
   double* hres = nullptr;    // pinned: least-squares residual per column
@@ -298,6 +298,7 @@ int ensure_bws(smpm_ctx* c, int s, int maxit) {
   rc |= dalloc(b.mem, &b.res, S);
   rc |= dalloc(b.mem, &b.h, ldH * S);
   rc |= dalloc(b.mem, &b.h2, ldH * S);
+  rc |= dalloc(b.mem, &b.ht, ldH * kBgMaxCols);
   rc |= dalloc(b.mem, &b.gram, sq);
   rc |= dalloc(b.mem, &b.T1, sq);
   rc |= dalloc(b.mem, &b.T2, sq);
@@ -913,10 +914,10 @@ void block_cholqr(smpm_ctx* c, const double* wb, int m, double* dst, double* tmp
   const int64_t k = c->dp.k;
   launch_bg_dot(wb, m, wb, m, k, B.part, B.gram, m, 0.0, s);
   launch_bg_chol(B.gram, m, kBlockDrop, nullptr, nullptr, B.cnt, B.T1, B.R1, s);
-  launch_bg_update(wb, m, B.T1, m, 1.0, nullptr, 0.0, tmp, m, k, s);
+  launch_bg_update(wb, m, B.T1, 1, m, 1.0, nullptr, 0.0, tmp, m, k, s);
   launch_bg_dot(tmp, m, tmp, m, k, B.part, B.gram, m, 0.0, s);
   launch_bg_chol(B.gram, m, 0.0, B.cnt, B.R1, B.cnt + 1, B.T2, B.R2, s);
-  launch_bg_update(tmp, m, B.T2, m, 1.0, nullptr, 0.0, dst, m, k, s);
+  launch_bg_update(tmp, m, B.T2, 1, m, 1.0, nullptr, 0.0, dst, m, k, s);
 }
 
 // Block GMRES (FP64) from x1 = 0 for op(x1) = b, all nrhs <= kBgMaxCols columns in one
@@ -968,10 +969,11 @@ int block_gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x1, int
   for (int j = 0; j < maxit && nv > n0; ++j) {
     const int r = nv - n0;
     apply_op(c, kind, tr, W.V + (int64_t)n0 * k, W.w, r, nullptr, s);
-    launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h, ldh, 0.0, s);
-    launch_bg_update(W.V, nv, B.h, ldh, -1.0, W.w, 1.0, W.w, r, k, s);
-    launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h2, ldh, 0.0, s);
-    launch_bg_update(W.V, nv, B.h2, ldh, -1.0, W.w, 1.0, W.w, r, k, s);
+    // the updates read the sums transposed (a row of 32 per basis vector)
+    launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h, ldh, 0.0, s, B.ht);
+    launch_bg_update(W.V, nv, B.ht, kBgMaxCols, 1, -1.0, W.w, 1.0, W.w, r, k, s);
+    launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h2, ldh, 0.0, s, B.ht);
+    launch_bg_update(W.V, nv, B.ht, kBgMaxCols, 1, -1.0, W.w, 1.0, W.w, r, k, s);
     launch_add(B.h, B.h2, 1.0, B.h, (int64_t)ldh * r, 1, s);
     block_cholqr(c, W.w, r, W.V + (int64_t)nv * k, W.t, s);
     launch_bg_lsq(L, n0, r, nv, B.h, ldh, B.R2, B.cnt + 1, B.hres, B.hcnt, s);
@@ -991,7 +993,7 @@ int block_gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x1, int
   }
   launch_bg_backsolve(L, n0, B.Y, B.cap, s);
   if (n0 > 0)
-    launch_bg_update(W.V, n0, B.Y, B.cap, 1.0, nullptr, 0.0, x1, nrhs, k, s);
+    launch_bg_update(W.V, n0, B.Y, 1, B.cap, 1.0, nullptr, 0.0, x1, nrhs, k, s);
   else
     HIPCHK(hipMemsetAsync(x1, 0, sizeof(double) * k * nrhs, s));
   return steps;

@@ -19,16 +19,17 @@ constexpr int kBgMaxCols = 32;  // widest block (columns per block)
 int64_t bg_dot_part_size();
 
 // out[b * ldo + a] = beta * out[b * ldo + a] + sum_x A[a * len + x] B[b * len + x]
-// for a < na, b < nb (nb <= kBgMaxCols); beta = 0 does not read out.  Deterministic:
-// fixed x chunks summed in a fixed order.
+// for a < na, b < nb (nb <= kBgMaxCols); beta = 0 does not read out; outT, if given,
+// receives the same values at outT[a * kBgMaxCols + b].  Deterministic: fixed x chunks
+// summed in a fixed order.
 void launch_bg_dot(const double* A, int na, const double* B, int nb, int64_t len, double* part, double* out,
-                   int ldo, double beta, hipStream_t s);
+                   int ldo, double beta, hipStream_t s, double* outT = nullptr);
 
-// out[b * len + x] = beta * win[b * len + x] + alpha * sum_a A[a * len + x] H[b * ldh + a]
+// out[b * len + x] = beta * win[b * len + x] + alpha * sum_a A[a * len + x] H[a * sa + b * sb]
 // for b < nb (nb <= kBgMaxCols), x < len.  out may equal win, never A; beta = 0 does
 // not read win.
-void launch_bg_update(const double* A, int na, const double* H, int ldh, double alpha, const double* win,
-                      double beta, double* out, int nb, int64_t len, hipStream_t s);
+void launch_bg_update(const double* A, int na, const double* H, int64_t sa, int64_t sb, double alpha,
+                      const double* win, double beta, double* out, int nb, int64_t len, hipStream_t s);
 
 // One pass of Cholesky QR of a block of m columns (Gram matrix G, m x m, ld m):
 // columns taken in order, a column whose part orthogonal to the kept ones is <= drop

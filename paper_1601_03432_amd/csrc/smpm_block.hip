@@ -35,16 +35,24 @@ void dot_chunks(int64_t len, int na, int* nch, int64_t* per) {
   *nch = (int)((len + p - 1) / p);
 }
 
-// Partial sums of A^T B over one x chunk: workgroup (chunk, 64 rows of A), wavefront
-// w owns A rows 16w..16w+15 against all (<= 32) columns of B.  Step q of an unrolled
-// group of four takes x = xb + 4q + l/16 for both operands, so each lane reads its
-// own A row and B row at the same x.
+// Partial sums of A^T B over one x chunk.  Work items (chunk, 64 rows of A) are
+// chunk-major and every XCD takes a contiguous range of them (workgroup w runs on
+// XCD w % 8), so the A row groups of one chunk share that XCD's L2 copy of B's
+// chunk.  Wavefront w of an item owns A rows 16w..16w+15 against all (<= 32) columns
+// of B; step q of an unrolled group of four takes x = xb + 4q + l/16 for both
+// operands.  part[(b * na + a) * nch + chunk].
 __global__ __launch_bounds__(256) void k_bg_dot(const double* __restrict__ A, int na, const double* __restrict__ B,
-                                                int nb, int64_t len, int64_t per, double* __restrict__ part) {
+                                                int nb, int64_t len, int64_t per, int nch, int items,
+                                                double* __restrict__ part) {
+  const int ablk = (na + 63) / 64;
+  const int per_xcd = (int)(gridDim.x / 8);
+  const int item = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (item >= items) return;
+  const int chunk = item / ablk, ab = item - chunk * ablk;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int a0 = blockIdx.y * 64 + wave * 16;
+  const int a0 = ab * 64 + wave * 16;
   if (a0 >= na) return;  // no barrier below
-  const int64_t x0 = (int64_t)blockIdx.x * per;
+  const int64_t x0 = (int64_t)chunk * per;
   const int64_t x1 = min(len, x0 + per);
   const int ar = a0 + (lane & 15);
   const bool aok = ar < na;
@@ -79,28 +87,37 @@ __global__ __launch_bounds__(256) void k_bg_dot(const double* __restrict__ A, in
   for (int v = 0; v < 4; ++v) {
     const int a = a0 + (lane >> 4) + 4 * v;
     if (a >= na) continue;
-    if (bc < nb) part[((int64_t)blockIdx.x * nb + bc) * na + a] = acc0[v];
-    if (two && 16 + bc < nb) part[((int64_t)blockIdx.x * nb + 16 + bc) * na + a] = acc1[v];
+    if (bc < nb) part[((int64_t)bc * na + a) * nch + chunk] = acc0[v];
+    if (two && 16 + bc < nb) part[((int64_t)(16 + bc) * na + a) * nch + chunk] = acc1[v];
   }
 }
 
-__global__ void k_bg_dot_final(const double* __restrict__ part, int na, int nb, int nch, double* __restrict__ out,
-                               int ldo, double beta) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= na * nb) return;
-  const int a = idx % na, b = idx / na;
+// One wavefront per output: lanes take the chunks c = lane, lane + 64, ... in order,
+// then a fixed butterfly.  out[b * ldo + a] (and, with outT, outT[a * kBgMaxCols + b]).
+__global__ __launch_bounds__(256) void k_bg_dot_final(const double* __restrict__ part, int na, int nb, int nch,
+                                                      double* __restrict__ out, int ldo, double beta,
+                                                      double* __restrict__ outT) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (o >= na * nb) return;
+  const int a = o % na, b = o / na;
+  const double* p = part + (int64_t)o * nch;
   double acc = 0.0;
-  for (int c = 0; c < nch; ++c) acc += part[((int64_t)c * nb + b) * na + a];
-  double* o = out + (int64_t)b * ldo + a;
-  *o = beta != 0.0 ? beta * *o + acc : acc;
+  for (int c = lane; c < nch; c += 64) acc += p[c];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    double* d = out + (int64_t)b * ldo + a;
+    const double v = beta != 0.0 ? beta * *d + acc : acc;
+    *d = v;
+    if (outT) outT[(int64_t)a * kBgMaxCols + b] = v;
+  }
 }
 
 // out = beta win + alpha A H: workgroup of four wavefronts, each 16 consecutive x
 // against all (<= 32) columns; the contraction runs over the na vectors of A in
 // groups of 16 (four matrix-core steps, a = ab + 4q + l/16).
 __global__ __launch_bounds__(256) void k_bg_update(const double* __restrict__ A, int na, const double* __restrict__ H,
-                                                   int ldh, double alpha, const double* win, double beta, double* out,
-                                                   int nb, int64_t len) {
+                                                   int64_t sa, int64_t sb, double alpha, const double* win,
+                                                   double beta, double* out, int nb, int64_t len) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
   if (x0 >= len) return;
@@ -109,8 +126,8 @@ __global__ __launch_bounds__(256) void k_bg_update(const double* __restrict__ A,
   const int kq = lane >> 4, bc = lane & 15;
   const bool two = nb > 16;
   const bool b0ok = bc < nb, b1ok = 16 + bc < nb;
-  const double* h0 = H + (int64_t)(b0ok ? bc : 0) * ldh;
-  const double* h1 = H + (int64_t)(b1ok ? 16 + bc : 0) * ldh;
+  const double* h0 = H + (b0ok ? bc : 0) * sb;
+  const double* h1 = H + (b1ok ? 16 + bc : 0) * sb;
   bg_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   for (int ab = 0; ab < na; ab += 16) {
     double av[4], hv0[4], hv1[4];
@@ -119,8 +136,8 @@ __global__ __launch_bounds__(256) void k_bg_update(const double* __restrict__ A,
       const int a = ab + 4 * q + kq;
       const int ac = a < na ? a : 0;
       av[q] = A[(int64_t)ac * len + xc];
-      hv0[q] = h0[ac];
-      hv1[q] = two ? h1[ac] : 0.0;
+      hv0[q] = h0[ac * sa];
+      hv1[q] = two ? h1[ac * sa] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -145,61 +162,62 @@ __global__ __launch_bounds__(256) void k_bg_update(const double* __restrict__ A,
   }
 }
 
-// Cholesky QR pass (one wavefront; see launch_bg_chol).  Gs[i + 32 j] = G_ij,
-// Rs[c + 32 i] = R_ci, Ts[i + 32 c] = T_ic.
-__global__ __launch_bounds__(64) void k_bg_chol(const double* __restrict__ G, int m, double drop,
-                                                const int* __restrict__ cnt_in, const double* __restrict__ rprev,
-                                                int* __restrict__ cnt, double* __restrict__ T, double* __restrict__ R) {
-  __shared__ double Gs[kBgMaxCols * kBgMaxCols], Rs[kBgMaxCols * kBgMaxCols], Ts[kBgMaxCols * kBgMaxCols];
-  const int l = threadIdx.x;
+// Cholesky QR pass (one workgroup; see launch_bg_chol), right-looking: once column i
+// yields a vector, the remaining Gram entries and the remaining columns' coefficient
+// vectors (Es column l = e_l minus its parts on the kept vectors) are updated at once.
+// As[i + 32 j]: Gram matrix being reduced, Gd: its original diagonal, Rs[c + 32 l] =
+// R_cl, Ts[i + 32 c] = T_ic.
+__global__ __launch_bounds__(256) void k_bg_chol(const double* __restrict__ G, int m, double drop,
+                                                 const int* __restrict__ cnt_in, const double* __restrict__ rprev,
+                                                 int* __restrict__ cnt, double* __restrict__ T,
+                                                 double* __restrict__ R) {
+  constexpr int C = kBgMaxCols;
+  __shared__ double As[C * C], Es[C * C], Rs[C * C], Ts[C * C], Gd[C];
+  const int tid = threadIdx.x;
   const int mm = cnt_in ? min(*cnt_in, m) : m;
-  for (int q = l; q < kBgMaxCols * kBgMaxCols; q += 64) {
-    Gs[q] = 0.0;
+  for (int q = tid; q < C * C; q += 256) {
+    const int i = q % C, j = q / C;
+    As[q] = i < m && j < m ? G[i + m * j] : 0.0;
+    Es[q] = i == j ? 1.0 : 0.0;
     Rs[q] = 0.0;
     Ts[q] = 0.0;
   }
-  __syncthreads();
-  for (int q = l; q < m * m; q += 64) Gs[(q % m) + kBgMaxCols * (q / m)] = G[q];
+  if (tid < C) Gd[tid] = tid < m ? G[tid + m * tid] : 0.0;
   __syncthreads();
   int kept = 0;
   for (int i = 0; i < mm; ++i) {
-    const double ri = l < kept ? Rs[l + kBgMaxCols * i] : 0.0;
-    const double p = wave_sum(ri * ri);
-    const double gii = Gs[i + kBgMaxCols * i];
-    const double d = gii - p;
+    const double d = As[i + C * i], gii = Gd[i];
     // NaN fails every comparison: such a column is dropped
     const bool keep = gii > 0.0 && d > 0.0 && d > drop * drop * gii;
-    if (keep) {
-      const double rho = sqrt(d);
-      double rl = 0.0, tl = 0.0;
-      if (l > i && l < mm) {
-        rl = Gs[i + kBgMaxCols * l];
-        for (int c = 0; c < kept; ++c) rl -= Rs[c + kBgMaxCols * i] * Rs[c + kBgMaxCols * l];
-        rl /= rho;
-      }
-      if (l < m) {
-        tl = l == i ? 1.0 : 0.0;
-        for (int c = 0; c < kept; ++c) tl -= Rs[c + kBgMaxCols * i] * Ts[l + kBgMaxCols * c];
-        tl /= rho;
-      }
-      __syncthreads();
-      if (l > i && l < mm) Rs[kept + kBgMaxCols * l] = rl;
-      if (l < m) Ts[l + kBgMaxCols * kept] = tl;
-      if (l == 0) Rs[kept + kBgMaxCols * i] = rho;
-      ++kept;
+    if (!keep) continue;  // uniform over the workgroup
+    const double rho = sqrt(d);
+    if (tid < C) {
+      const int l = tid;
+      if (l > i && l < mm) Rs[kept + C * l] = As[i + C * l] / rho;
+      if (l == i) Rs[kept + C * l] = rho;
+      if (l < m) Ts[l + C * kept] = Es[l + C * i] / rho;
     }
     __syncthreads();
+    for (int q = tid; q < C * C; q += 256) {
+      const int u = q % C, l = q / C;
+      if (l > i && l < mm) {
+        if (u > i && u < mm) As[u + C * l] -= Rs[kept + C * u] * Rs[kept + C * l];
+        if (u < m) Es[u + C * l] -= Rs[kept + C * l] * Ts[u + C * kept];
+      }
+    }
+    ++kept;
+    __syncthreads();
   }
-  if (l == 0) *cnt = kept;
-  for (int q = l; q < m * m; q += 64) T[q] = Ts[(q % m) + kBgMaxCols * (q / m)];
-  for (int q = l; q < kBgMaxCols * kBgMaxCols; q += 64) {
-    const int c = q % kBgMaxCols, i = q / kBgMaxCols;
+  if (tid == 0) *cnt = kept;
+  for (int q = tid; q < m * m; q += 256) T[q] = Ts[(q % m) + C * (q / m)];
+  for (int q = tid; q < C * C; q += 256) {
+    const int c = q % C, i = q / C;
     double v = 0.0;
     if (c < kept && i < m) {
       if (rprev) {
-        for (int cp = 0; cp < mm; ++cp) v += Rs[c + kBgMaxCols * cp] * rprev[cp + kBgMaxCols * i];
+        for (int cp = 0; cp < mm; ++cp) v += Rs[c + C * cp] * rprev[cp + C * i];
       } else {
-        v = Rs[c + kBgMaxCols * i];
+        v = Rs[c + C * i];
       }
     }
     R[q] = v;
@@ -254,11 +272,26 @@ __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int 
       reg[u] = p + 64 < rows ? col[u][p + 64] : 0.0;
     }
   };
-  // earlier reflections on the new columns
+  // earlier reflections on the new columns; the rows entering the windows during
+  // the next 64 reflections are loaded at once (row p0 + 64 + lane), and each
+  // reflection is loaded one ahead
+  double nxt[4] = {0.0, 0.0, 0.0, 0.0};
+  double vn = n0 > 0 ? L.refl[lane] : 0.0;
+  double bn = n0 > 0 ? L.rbeta[0] : 0.0;
   for (int p = 0; p < n0; ++p) {
-    const int t = (lane - p) & 63;
-    const double v = L.refl[(int64_t)p * 64 + t];
-    const double be = L.rbeta[p];
+    if ((p & 63) == 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = wave + kLsqWaves * u;
+        const int row = p + 64 + lane;
+        nxt[u] = own[u] && q < r && row < rows ? col[u][row] : 0.0;
+      }
+    }
+    const double v = vn, be = bn;
+    if (p + 1 < n0) {
+      vn = L.refl[(int64_t)(p + 1) * 64 + ((lane - p - 1) & 63)];
+      bn = L.rbeta[p + 1];
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int q = wave + kLsqWaves * u;
@@ -267,7 +300,10 @@ __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int 
         const double dt = wave_sum(v * reg[u]);
         reg[u] -= be * dt * v;
       }
-      advance(u, p);
+      if (lane == (p & 63)) {
+        col[u][p] = reg[u];
+        reg[u] = nxt[u];
+      }
     }
   }
   // the new columns' own reflections, applied to the later new columns and to G
@@ -327,26 +363,49 @@ __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int 
   }
 }
 
-// Y = triangle(H)^{-1} G[0 .. ncol): Y starts as G, then column-oriented back
-// substitution (one workgroup).
+// Y = triangle(H)^{-1} G[0 .. ncol) by blocks of 32 rows from the bottom (one
+// workgroup): a block's triangle and right-hand sides are solved in LDS, then the
+// rows above it are updated with the block's solution.
 __global__ __launch_bounds__(1024) void k_bg_backsolve(BgLsq L, int ncol, double* __restrict__ Y, int ldy) {
+  constexpr int C = kBgMaxCols;
+  __shared__ double tri[C * (C + 1)], yb[C * (C + 1)];  // tri[r + 33 c] = H[i0 + r][i0 + c], yb[r + 33 g]
   const int tid = threadIdx.x;
   const int s = L.s;
+  const int64_t ld = L.ldH;
   for (int q = tid; q < ncol * s; q += 1024) {
     const int row = q % ncol, g = q / ncol;
-    Y[(int64_t)g * ldy + row] = L.G[(int64_t)g * L.ldH + row];
+    Y[(int64_t)g * ldy + row] = L.G[(int64_t)g * ld + row];
   }
   __syncthreads();
-  for (int i = ncol - 1; i >= 0; --i) {
-    const double* hc = L.H + (int64_t)i * L.ldH;
-    if (tid < s) {
-      const double d = hc[i];
-      Y[(int64_t)tid * ldy + i] = d != 0.0 ? Y[(int64_t)tid * ldy + i] / d : 0.0;
+  for (int i1 = ncol; i1 > 0; i1 -= C) {
+    const int i0 = max(0, i1 - C), nb = i1 - i0;
+    for (int q = tid; q < C * C; q += 1024) {
+      const int r = q % C, c = q / C;
+      tri[r + (C + 1) * c] = r < nb && c < nb && r <= c ? L.H[(int64_t)(i0 + c) * ld + i0 + r] : 0.0;
+      yb[r + (C + 1) * c] = r < nb && c < s ? Y[(int64_t)c * ldy + i0 + r] : 0.0;
     }
     __syncthreads();
-    for (int q = tid; q < i * s; q += 1024) {
-      const int row = q % i, g = q / i;
-      Y[(int64_t)g * ldy + row] -= hc[row] * Y[(int64_t)g * ldy + i];
+    for (int rr = nb - 1; rr >= 0; --rr) {
+      if (tid < s) {
+        const double dg = tri[rr + (C + 1) * rr];
+        yb[rr + (C + 1) * tid] = dg != 0.0 ? yb[rr + (C + 1) * tid] / dg : 0.0;
+      }
+      __syncthreads();
+      if (tid < rr * s) {
+        const int r = tid % rr, g = tid / rr;
+        yb[r + (C + 1) * g] -= tri[r + (C + 1) * rr] * yb[rr + (C + 1) * g];
+      }
+      __syncthreads();
+    }
+    for (int q = tid; q < nb * s; q += 1024) {
+      const int r = q % nb, g = q / nb;
+      Y[(int64_t)g * ldy + i0 + r] = yb[r + (C + 1) * g];
+    }
+    for (int q = tid; q < i0 * s; q += 1024) {
+      const int row = q % i0, g = q / i0;
+      double acc = 0.0;
+      for (int c = 0; c < nb; ++c) acc += L.H[(int64_t)(i0 + c) * ld + row] * yb[c + (C + 1) * g];
+      Y[(int64_t)g * ldy + row] -= acc;
     }
     __syncthreads();
   }
@@ -364,27 +423,29 @@ __global__ void k_bg_lsq_start(BgLsq L, const double* __restrict__ R0, const int
 int64_t bg_dot_part_size() { return (int64_t)(kTargetBlocks + 64) * 64 * kBgMaxCols; }
 
 void launch_bg_dot(const double* A, int na, const double* B, int nb, int64_t len, double* part, double* out,
-                   int ldo, double beta, hipStream_t s) {
+                   int ldo, double beta, hipStream_t s, double* outT) {
   if (na <= 0 || nb <= 0) return;
   int nch;
   int64_t per;
   dot_chunks(len, na, &nch, &per);
-  hipLaunchKernelGGL(k_bg_dot, dim3(nch, (na + 63) / 64), dim3(256), 0, s, A, na, B, nb, len, per, part);
+  const int items = nch * ((na + 63) / 64);
+  const int grid = (items + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_bg_dot, dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
   const int tot = na * nb;
-  hipLaunchKernelGGL(k_bg_dot_final, dim3((tot + 255) / 256), dim3(256), 0, s, part, na, nb, nch, out, ldo, beta);
+  hipLaunchKernelGGL(k_bg_dot_final, dim3((tot + 3) / 4), dim3(256), 0, s, part, na, nb, nch, out, ldo, beta, outT);
 }
 
-void launch_bg_update(const double* A, int na, const double* H, int ldh, double alpha, const double* win,
-                      double beta, double* out, int nb, int64_t len, hipStream_t s) {
+void launch_bg_update(const double* A, int na, const double* H, int64_t sa, int64_t sb, double alpha,
+                      const double* win, double beta, double* out, int nb, int64_t len, hipStream_t s) {
   if (nb <= 0) return;
   const int64_t blocks = (len + 63) / 64;
-  hipLaunchKernelGGL(k_bg_update, dim3((unsigned)blocks), dim3(256), 0, s, A, na, H, ldh, alpha, win, beta, out, nb,
-                     len);
+  hipLaunchKernelGGL(k_bg_update, dim3((unsigned)blocks), dim3(256), 0, s, A, na, H, sa, sb, alpha, win, beta, out,
+                     nb, len);
 }
 
 void launch_bg_chol(const double* G, int m, double drop, const int* cnt_in, const double* rprev, int* cnt, double* T,
                     double* R, hipStream_t s) {
-  hipLaunchKernelGGL(k_bg_chol, dim3(1), dim3(64), 0, s, G, m, drop, cnt_in, rprev, cnt, T, R);
+  hipLaunchKernelGGL(k_bg_chol, dim3(1), dim3(256), 0, s, G, m, drop, cnt_in, rprev, cnt, T, R);
 }
 
 void launch_bg_lsq(const BgLsq& L, int n0, int r, int nv, const double* h, int ldh, const double* R, const int* cnt,
