@@ -227,6 +227,9 @@ def main():
                     help="time only the headline form (e.g. for kernel traces of the solve)")
     ap.add_argument("--large-single-only", action="store_true",
                     help="time only the large stretched grid's one-column FP64 solve (e.g. for kernel traces)")
+    ap.add_argument("--large-batched-only", action="store_true",
+                    help="time only the large stretched grid's 8-column solve in --precision (e.g. for kernel "
+                         "traces)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the metric kernel (no solves), e.g. for hardware-counter runs")
     args = ap.parse_args()
@@ -247,7 +250,8 @@ def main():
     f_host = wl.eval_fourier(params, x, y, w.Lx, w.Ly)
     f = torch.tensor(f_host, device="cuda").reshape(1, -1)
     w5 = wl.workload("c5")
-    ctx5 = None if (args.no_large or args.headline_only) and not (args.roofline_only or args.large_single_only) \
+    ctx5 = None if (args.no_large or args.headline_only) and not (args.roofline_only or args.large_single_only or
+                                                                  args.large_batched_only) \
         else c5_context(smpm, w5)
     if args.roofline_only:
         print(json.dumps({"roofline": schur_roofline(ctx5),
@@ -281,6 +285,18 @@ def main():
         print(json.dumps({"form": "fp64, large stretched grid, one column", "solves_per_s": 1.0 / sec,
                           "ms_per_step": sec * 1e3, "iterations": info.iterations,
                           "true_rel_residual": info.rel_residual}), flush=True)
+        return
+    if args.large_batched_only:
+        x5, y5 = ctx5.node_coords()
+        F5, G5 = wl.c5_sources("c5", x5, y5, ctx5.boundary_arc(), w5.Lx, w5.Ly)
+        F5, G5 = torch.tensor(F5, device="cuda"), torch.tensor(G5, device="cuda")
+        ctx5.autotune(8)
+        prec = smpm.FP64 if args.precision == "fp64" else smpm.MIXED_FP32
+        sec, info, _ = timed(lambda r: ctx5.solve(r, G5, tol=1e-10, maxit=600, precision=prec, inner_tol=1e-5,
+                                                  max_refine=30), F5, args.steps, args.warmup)
+        print(json.dumps({"form": args.precision + ", large stretched grid, 8 columns", "solves_per_s": 8 / sec,
+                          "ms_per_step": sec * 1e3, "iterations": info.iterations,
+                          "refinements": info.refinements, "true_rel_residual": info.rel_residual}), flush=True)
         return
     if args.headline_only:
         fn = solve_fp64 if args.precision == "fp64" else solve_mixed
@@ -369,9 +385,12 @@ def main():
 
         tuned3 = {"1": c3.autotune(1), str(w3.nrhs): c3.autotune(w3.nrhs)}
         t1, i1, _ = timed(s3_fp64, F3[:1].contiguous(), 5, 1)
-        tb, ib, _ = timed(s3_fp64, F3, 3, 1)
+        tb, ib, u3b = timed(s3_fp64, F3, 3, 1)
         tm, im, _ = timed(s3_mixed, F3, 3, 1)
         tbf, ibf, _ = timed(lambda r: s3_mixed(r, smpm.MIXED_BF16), F3, 3, 1)
+        # block GMRES: all 32 columns in one block Krylov space (FP64)
+        tbk, ibk, u3k = timed(lambda r: c3.solve(r, tol=1e-10, maxit=200, block=True), F3, 2, 1)
+        blk_diff = float(max(torch.linalg.norm(u3k[c] - u3b[c]) / torch.linalg.norm(u3b[c]) for c in range(w3.nrhs)))
         out["batched_c3"] = {
             "workload": "c3: 64x64 elements, n=12, [0,1]^2, r=589824, k=193536, d=8064 (substructured coarse "
                         "solve), 32 advected random-Fourier sources + noise (std 1e-3), tol 1e-10",
@@ -385,9 +404,12 @@ def main():
             "mixed_bf16_batched32_refinements": ibf.refinements,
             "mixed_bf16_batched32_final_schur_precision": ["fp64", "fp32", "bf16"][ibf.schur_precision],
             "mixed_bf16_batched32_true_rel_residual_max": ibf.rel_residual,
+            "fp64_block32_solves_per_s": w3.nrhs / tbk, "fp64_block32_block_steps": ibk.iterations,
+            "fp64_block32_refinements": ibk.refinements, "fp64_block32_true_rel_residual_max": ibk.rel_residual,
+            "fp64_block32_vs_batched32_rel_l2_max": blk_diff,
             "autotuned": tuned3,
         }
-        del c3, F3
+        del c3, F3, u3b, u3k
 
     if not args.no_large:
         out["roofline"] = schur_roofline(ctx5)
@@ -409,6 +431,7 @@ def main():
         t5b, i5b, u5b = timed(lambda r: s5(r, G5, smpm.FP64), F5, 2, 1)
         t5m, i5m, u5m = timed(lambda r: s5(r, G5, smpm.MIXED_FP32), F5, 2, 1)
         t5h, i5h, _ = timed(lambda r: s5(r, G5, smpm.MIXED_BF16), F5, 1, 1)
+        t5k, i5k, u5k = timed(lambda r: ctx5.solve(r, G5, tol=1e-10, maxit=200, block=True), F5, 1, 1)
         out["c5"] = {
             "workload": "c5: 128x128 elements, n=16, x-stretched (ratio 1.05, aspect <= 8) on [0,1]x[0,%.4f], "
                         "r=%d, k=%d, d=%d (substructured coarse solve), 8 random-Fourier sources + nonzero "
@@ -426,9 +449,13 @@ def main():
             "mixed_bf16_batched8_solves_per_s": 8 / t5h, "mixed_bf16_batched8_iterations": i5h.iterations,
             "mixed_bf16_batched8_refinements": i5h.refinements,
             "mixed_bf16_batched8_true_rel_residual_max": i5h.rel_residual,
+            "fp64_block8_solves_per_s": 8 / t5k, "fp64_block8_block_steps": i5k.iterations,
+            "fp64_block8_refinements": i5k.refinements, "fp64_block8_true_rel_residual_max": i5k.rel_residual,
+            "fp64_block8_vs_batched8_rel_l2_max": float(max(torch.linalg.norm(u5k[c] - u5b[c]) /
+                                                            torch.linalg.norm(u5b[c]) for c in range(8))),
             "autotuned": tuned5,
         }
-        del ctx5, F5, G5, u5b, u5m
+        del ctx5, F5, G5, u5b, u5m, u5k
         # the three side grids, 8 right-hand sides each, as one concurrent group
         side = []
         for name in wl.C5_SIDE_GRIDS:
