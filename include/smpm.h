@@ -143,7 +143,8 @@ typedef struct smpm_solve_opts {
   int profile;        /* 1: time the solve's phases with HIP events recorded on its stream
                          (smpm_solve_info.phase_ms); 0 (default): no timing.  The environment
                          SMPM_PROFILE=1 turns it on as well                                     */
-  int block;          /* 1: step 4 as block GMRES (FP64 only, at most 32 columns): all columns
+  int block;          /* 1: step 4 as block GMRES (at most 32 columns; with mixed precision the
+                         inner solve of every refinement cycle, its operators FP32 or BF16): all columns
                          share one block Krylov space span{R0, op R0, ...}, R0 the deflated
                          right-hand sides, each column's residual minimized over all of it;
                          the basis is extended by block classical Gram-Schmidt applied twice

@@ -371,18 +371,19 @@ void rank1_apply(smpm_ctx* c, const double* z, double* t, hipStream_t s) {
   launch_axpy_shared(t, P.k, c->v0hat, W.scal2, -1.0, t, P.k, 1, s);
 }
 
-// w = op(v) for the chosen operator; transpose selects the adjoint pieces.
+// w = op(v) for the chosen operator; transpose selects the adjoint pieces.  sprec,
+// mprec: precision of the Schur and block-Jacobi operators of OP_S, OP_SM, OP_PSM.
 void apply_op(smpm_ctx* c, int kind, bool tr, const double* v, double* w, int nrhs, const int* act,
-              hipStream_t s) {
+              hipStream_t s, int sprec = PREC_F64, int mprec = PREC_F64) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   if (kind == OP_S) {
-    launch_schur(P, v, w, nrhs, tr, act, s);
+    launch_schur_ex(P, v, w, nrhs, tr, act, nullptr, s, sprec);
     return;
   }
-  if (kind != OP_RANK1 || c->precond_regular) launch_precond(P, v, W.z, nrhs, tr, act, s);
+  if (kind != OP_RANK1 || c->precond_regular) launch_precond(P, v, W.z, nrhs, tr, act, s, mprec);
   if (kind == OP_SM) {
-    launch_schur(P, W.z, w, nrhs, tr, act, s);
+    launch_schur_ex(P, W.z, w, nrhs, tr, act, nullptr, s, sprec);
     return;
   }
   if (kind == OP_RANK1) {
@@ -402,7 +403,7 @@ void apply_op(smpm_ctx* c, int kind, bool tr, const double* v, double* w, int nr
     rank1_coarse_term(c, W.t, W.c2, w, s);
     return;
   }
-  launch_schur(P, W.z, W.t, nrhs, tr, act, s);
+  launch_schur_ex(P, W.z, W.t, nrhs, tr, act, nullptr, s, sprec);
   launch_iface_sum(P, W.t, W.c, nrhs, act, s);
   launch_coarse(P, W.c, W.c2, nrhs, tr, act, s);
   launch_prolong(P, W.t, W.c2, w, nrhs, tr ? 2 : 1, -1.0, act, s);
@@ -909,15 +910,16 @@ constexpr double kBlockDrop = 1e-6;
 // deflation in the first pass: the kept vectors go to dst (columns past the kept
 // count are zero), the count to B.cnt[1] (B.cnt[0]: the first pass), and R (kept x m,
 // ld kBgMaxCols, wb = dst R) to B.R2.  tmp: scratch of m vectors.
-void block_cholqr(smpm_ctx* c, const double* wb, int m, double* dst, double* tmp, hipStream_t s) {
+template <typename VT>
+void block_cholqr(smpm_ctx* c, const double* wb, int m, VT* dst, double* tmp, hipStream_t s) {
   BlockWs& B = c->bws;
   const int64_t k = c->dp.k;
   launch_bg_dot(wb, m, wb, m, k, B.part, B.gram, m, 0.0, s);
   launch_bg_chol(B.gram, m, kBlockDrop, nullptr, nullptr, B.cnt, B.T1, B.R1, s);
-  launch_bg_update(wb, m, B.T1, 1, m, 1.0, nullptr, 0.0, tmp, m, k, s);
+  launch_bg_update(wb, m, B.T1, 1, m, 1.0, (const double*)nullptr, 0.0, tmp, m, k, s);
   launch_bg_dot(tmp, m, tmp, m, k, B.part, B.gram, m, 0.0, s);
   launch_bg_chol(B.gram, m, 0.0, B.cnt, B.R1, B.cnt + 1, B.T2, B.R2, s);
-  launch_bg_update(tmp, m, B.T2, 1, m, 1.0, nullptr, 0.0, dst, m, k, s);
+  launch_bg_update(tmp, m, B.T2, 1, m, 1.0, (const VT*)nullptr, 0.0, dst, m, k, s);
 }
 
 // Block GMRES (FP64) from x1 = 0 for op(x1) = b, all nrhs <= kBgMaxCols columns in one
@@ -932,7 +934,8 @@ void block_cholqr(smpm_ctx* c, const double* wb, int m, double* dst, double* tmp
 // receives column 0's residual / reference after each step (the start first).
 // Returns the block steps taken, or a negative status.
 int block_gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x1, int nrhs, double tol, int maxit,
-                const double* ref2, hipStream_t s, std::vector<double>* res0 = nullptr) {
+                const double* ref2, hipStream_t s, std::vector<double>* res0 = nullptr, int sprec = PREC_F64,
+                int mprec = PREC_F64) {
   const DevPlan& P = c->dp;
   Workspace& W = c->ws;
   BlockWs& B = c->bws;
@@ -951,7 +954,14 @@ int block_gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x1, int
   }
   HIPCHK(hipMemcpyAsync(B.href, ref2, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
   BgLsq L{B.H, B.ldH, B.refl, B.rbeta, B.G, nrhs, B.res};
-  block_cholqr(c, r0, nrhs, W.V, W.t, s);
+  // an inner solve with low-precision operators stores its basis in FP32 (the
+  // products stay FP64), as the batched inner solves do
+  const bool b32 = sprec != PREC_F64 && c->mixed_basis32;
+  float* V32 = reinterpret_cast<float*>(W.V);
+  if (b32)
+    block_cholqr(c, r0, nrhs, V32, W.t, s);
+  else
+    block_cholqr(c, r0, nrhs, W.V, W.t, s);
   launch_bg_lsq_start(L, B.R2, B.cnt + 1, s);
   // |R_0| per column = the start block's column norms (the reflections keep them)
   launch_bg_dot(r0, nrhs, r0, nrhs, k, B.part, B.gram, nrhs, 0.0, s);
@@ -968,14 +978,27 @@ int block_gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x1, int
   const int ldh = B.ldH;
   for (int j = 0; j < maxit && nv > n0; ++j) {
     const int r = nv - n0;
-    apply_op(c, kind, tr, W.V + (int64_t)n0 * k, W.w, r, nullptr, s);
-    // the updates read the sums transposed (a row of 32 per basis vector)
-    launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h, ldh, 0.0, s, B.ht);
-    launch_bg_update(W.V, nv, B.ht, kBgMaxCols, 1, -1.0, W.w, 1.0, W.w, r, k, s);
-    launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h2, ldh, 0.0, s, B.ht);
-    launch_bg_update(W.V, nv, B.ht, kBgMaxCols, 1, -1.0, W.w, 1.0, W.w, r, k, s);
+    // the updates read the sums transposed (a row of 32 per basis vector); x1's buffer
+    // holds the widened block of an FP32 basis until x1 is formed
+    if (b32) {
+      launch_bg_widen(V32 + (int64_t)n0 * k, x1, (int64_t)r * k, s);
+      apply_op(c, kind, tr, x1, W.w, r, nullptr, s, sprec, mprec);
+      launch_bg_dot(V32, nv, W.w, r, k, B.part, B.h, ldh, 0.0, s, B.ht);
+      launch_bg_update(V32, nv, B.ht, kBgMaxCols, 1, -1.0, W.w, 1.0, W.w, r, k, s);
+      launch_bg_dot(V32, nv, W.w, r, k, B.part, B.h2, ldh, 0.0, s, B.ht);
+      launch_bg_update(V32, nv, B.ht, kBgMaxCols, 1, -1.0, W.w, 1.0, W.w, r, k, s);
+    } else {
+      apply_op(c, kind, tr, W.V + (int64_t)n0 * k, W.w, r, nullptr, s, sprec, mprec);
+      launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h, ldh, 0.0, s, B.ht);
+      launch_bg_update(W.V, nv, B.ht, kBgMaxCols, 1, -1.0, W.w, 1.0, W.w, r, k, s);
+      launch_bg_dot(W.V, nv, W.w, r, k, B.part, B.h2, ldh, 0.0, s, B.ht);
+      launch_bg_update(W.V, nv, B.ht, kBgMaxCols, 1, -1.0, W.w, 1.0, W.w, r, k, s);
+    }
     launch_add(B.h, B.h2, 1.0, B.h, (int64_t)ldh * r, 1, s);
-    block_cholqr(c, W.w, r, W.V + (int64_t)nv * k, W.t, s);
+    if (b32)
+      block_cholqr(c, W.w, r, V32 + (int64_t)nv * k, W.t, s);
+    else
+      block_cholqr(c, W.w, r, W.V + (int64_t)nv * k, W.t, s);
     launch_bg_lsq(L, n0, r, nv, B.h, ldh, B.R2, B.cnt + 1, B.hres, B.hcnt, s);
     HIPCHK(hipMemcpyAsync(B.hcnt, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -992,20 +1015,24 @@ int block_gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x1, int
     if (done || !finite) break;
   }
   launch_bg_backsolve(L, n0, B.Y, B.cap, s);
-  if (n0 > 0)
-    launch_bg_update(W.V, n0, B.Y, 1, B.cap, 1.0, nullptr, 0.0, x1, nrhs, k, s);
+  if (n0 > 0 && b32)
+    launch_bg_update(V32, n0, B.Y, 1, B.cap, 1.0, (const double*)nullptr, 0.0, x1, nrhs, k, s);
+  else if (n0 > 0)
+    launch_bg_update(W.V, n0, B.Y, 1, B.cap, 1.0, (const double*)nullptr, 0.0, x1, nrhs, k, s);
   else
     HIPCHK(hipMemsetAsync(x1, 0, sizeof(double) * k * nrhs, s));
   return steps;
 }
 
-// block_gmres, then x from its solution (Algorithm 3 steps 5-8 for OP_PSM).
+// block_gmres, then x from its solution (Algorithm 3 steps 5-8 for OP_PSM), with the
+// operators in the given precisions (the refinement cycles of mixed precision).
 int block_solve_schur(smpm_ctx* c, int kind, bool tr, const double* bhat, double* x, int nrhs, double tol,
-                      int maxit, const double* ref2, hipStream_t s, std::vector<double>* res0) {
+                      int maxit, const double* ref2, hipStream_t s, std::vector<double>* res0,
+                      int sprec = PREC_F64, int mprec = PREC_F64) {
   Workspace& W = c->ws;
-  const int rc = block_gmres(c, kind, tr, bhat, W.x, nrhs, tol, maxit, ref2, s, res0);
+  const int rc = block_gmres(c, kind, tr, bhat, W.x, nrhs, tol, maxit, ref2, s, res0, sprec, mprec);
   if (rc < 0) return rc;
-  recover_x(c, kind, tr, bhat, W.x, x, nrhs, PREC_F64, PREC_F64, s);
+  recover_x(c, kind, tr, bhat, W.x, x, nrhs, sprec, mprec, s);
   return rc;
 }
 
@@ -2040,7 +2067,6 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
   const size_t rb = sizeof(double) * Pl.r * nrhs;
   if (aliases(f, rb, u, rb)) return fail(SMPM_EINVAL, "f and u alias");
   if (o.stop_rule != 0 && o.stop_rule != 1) return fail(SMPM_EINVAL, "stop_rule must be 0 or 1");
-  if (o.block != 0 && o.precision != SMPM_FP64) return fail(SMPM_EINVAL, "block GMRES runs in FP64 only");
   if (o.block != 0 && nrhs > kBgMaxCols) return fail(SMPM_EINVAL, "block GMRES takes at most 32 columns");
   hipStream_t s = static_cast<hipStream_t>(stream);
   rc = compute_null_vectors(c, s);
@@ -2137,7 +2163,7 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
     ++ncyc;
   };
   bool conv = true;
-  if (o.block) {
+  if (o.block && o.precision == SMPM_FP64) {
     // Steps 1-3, then step 4 as block GMRES over all columns (FP64, launched as it
     // goes: a block step waits for its kept count), steps 5-9; FP64 correction cycles
     // as below when the true residual misses tol.
@@ -2169,8 +2195,10 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       const double* nl = tr ? c->v0hat : c->uS;
       launch_mdot(nl, 0, 0, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal, nullptr, s);
       launch_axpy_shared(W.rho, Pl.k, nl, W.scal, 1.0, W.rho, Pl.k, nrhs, s);
+      if (rule != 1)
+        launch_mdot(W.rho, 0, Pl.k, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
       const int st = block_solve_schur(c, kind, tr, W.rho, W.bS, nrhs, std::min(0.5, 0.3 * o.tol / worst), o.maxit,
-                                       nullptr, s, &res0);
+                                       rule == 1 ? nullptr : W.scal2 + 2 * nrhs, s, &res0);
       if (st < 0) return st;
       std::vector<int> it(nrhs, st);
       note_cycle(it);
@@ -2386,7 +2414,21 @@ int smpm_solve(smpm_ctx* c, const double* f, const double* g, double* u, int nrh
       const double reach = sprec == PREC_BF16 ? 1e-3 : sprec == PREC_F32 ? 1e-7 : 1e-12;
       const double itol = std::min(0.5, need >= reach ? need : std::max(o.inner_tol, need));
       std::vector<int> it;
-      rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, itol, o.maxit, it, s, sprec, mprec, o.graph != 0, rule);
+      if (o.block) {
+        // block GMRES as the inner solve: all columns in one block Krylov space
+        // (stopping reference |rho| per column, as the batched inner solve takes it)
+        rc = ensure_bws(c, nrhs, o.maxit);
+        if (rc) return rc;
+        if (rule != 1)
+          launch_mdot(W.rho, 0, Pl.k, 1, W.rho, Pl.k, nullptr, Pl.k, nrhs, W.part, W.scal2 + 2 * nrhs, nullptr, s);
+        const int st = block_solve_schur(c, kind, tr, W.rho, W.bS, nrhs, itol, o.maxit,
+                                         rule == 1 ? nullptr : W.scal2 + 2 * nrhs, s, nullptr, sprec, mprec);
+        if (st < 0) return st;
+        it.assign(nrhs, st);
+        rc = st;
+      } else {
+        rc = solve_schur(c, kind, tr, W.rho, W.bS, nrhs, itol, o.maxit, it, s, sprec, mprec, o.graph != 0, rule);
+      }
       if (rc < 0) return rc;
       note_cycle(it);
       sprec_final = sprec;

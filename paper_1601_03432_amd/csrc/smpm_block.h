@@ -22,14 +22,21 @@ int64_t bg_dot_part_size();
 // for a < na, b < nb (nb <= kBgMaxCols); beta = 0 does not read out; outT, if given,
 // receives the same values at outT[a * kBgMaxCols + b].  Deterministic: fixed x chunks
 // summed in a fixed order.
-void launch_bg_dot(const double* A, int na, const double* B, int nb, int64_t len, double* part, double* out,
-                   int ldo, double beta, hipStream_t s, double* outT = nullptr);
+// A is FP64, or FP32 (a basis stored in FP32; the products are FP64).
+template <typename AT>
+void launch_bg_dot(const AT* A, int na, const double* B, int nb, int64_t len, double* part, double* out, int ldo,
+                   double beta, hipStream_t s, double* outT = nullptr);
 
 // out[b * len + x] = beta * win[b * len + x] + alpha * sum_a A[a * len + x] H[a * sa + b * sb]
 // for b < nb (nb <= kBgMaxCols), x < len.  out may equal win, never A; beta = 0 does
-// not read win.
-void launch_bg_update(const double* A, int na, const double* H, int64_t sa, int64_t sb, double alpha,
-                      const double* win, double beta, double* out, int nb, int64_t len, hipStream_t s);
+// not read win.  Instantiated for (A, out) = (FP64, FP64), (FP32, FP64) and (FP64,
+// FP32): FP64 arithmetic, an FP32 basis read or written.
+template <typename AT, typename OT>
+void launch_bg_update(const AT* A, int na, const double* H, int64_t sa, int64_t sb, double alpha, const OT* win,
+                      double beta, OT* out, int nb, int64_t len, hipStream_t s);
+
+// b = (double) a, n entries
+void launch_bg_widen(const float* a, double* b, int64_t n, hipStream_t s);
 
 // One pass of Cholesky QR of a block of m columns (Gram matrix G, m x m, ld m):
 // columns taken in order, a column whose part orthogonal to the kept ones is <= drop

@@ -30,59 +30,77 @@ void dot_chunks(int64_t len, int na, int* nch, int64_t* per) {
   int64_t want = std::max<int64_t>(1, kTargetBlocks / ablk);
   want = std::min<int64_t>(want, std::max<int64_t>(1, (len + kMinChunk - 1) / kMinChunk));
   int64_t p = (len + want - 1) / want;
-  p = (p + 15) / 16 * 16;
+  p = (p + 63) / 64 * 64;
   *per = p;
   *nch = (int)((len + p - 1) / p);
 }
 
 // Partial sums of A^T B over one x chunk.  Work items (chunk, 64 rows of A) are
 // chunk-major and every XCD takes a contiguous range of them (workgroup w runs on
-// XCD w % 8), so the A row groups of one chunk share that XCD's L2 copy of B's
-// chunk.  Wavefront w of an item owns A rows 16w..16w+15 against all (<= 32) columns
-// of B; step q of an unrolled group of four takes x = xb + 4q + l/16 for both
-// operands.  part[(b * na + a) * nch + chunk].
-__global__ __launch_bounds__(256) void k_bg_dot(const double* __restrict__ A, int na, const double* __restrict__ B,
+// XCD w % 8), so the row groups of one chunk share that XCD's L2 copy of B's chunk.
+// The chunk is walked 64 entries at a time: the 64 A rows and the (<= 32) B columns
+// of the step go to LDS as whole 512-byte row segments (every load issued before the
+// first store, clamped into the vectors and masked), then wavefront w multiplies
+// its 16 A rows against both 16-column B tiles in 16 matrix-core steps (step q takes
+// entries 4q .. 4q+3).  part[(b * na + a) * nch + chunk].
+constexpr int kDotLd = 68;  // LDS row stride in doubles (rows land 4 banks apart)
+template <typename AT>
+__global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na, const double* __restrict__ B,
                                                 int nb, int64_t len, int64_t per, int nch, int items,
                                                 double* __restrict__ part) {
+  __shared__ double As[64 * kDotLd], Bs[kBgMaxCols * kDotLd];
   const int ablk = (na + 63) / 64;
   const int per_xcd = (int)(gridDim.x / 8);
   const int item = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-  if (item >= items) return;
+  if (item >= items) return;  // uniform over the workgroup
   const int chunk = item / ablk, ab = item - chunk * ablk;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int a0 = ab * 64 + wave * 16;
-  if (a0 >= na) return;  // no barrier below
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t x0 = (int64_t)chunk * per;
   const int64_t x1 = min(len, x0 + per);
-  const int ar = a0 + (lane & 15);
-  const bool aok = ar < na;
-  const double* ap = A + (int64_t)(aok ? ar : 0) * len;
-  const int b0 = lane & 15, b1 = 16 + (lane & 15);
   const bool two = nb > 16;
-  const bool b0ok = b0 < nb, b1ok = b1 < nb;
-  const double* bp0 = B + (int64_t)(b0ok ? b0 : 0) * len;
-  const double* bp1 = B + (int64_t)(b1ok ? b1 : 0) * len;
-  const int kq = lane >> 4;
+  const bool active = ab * 64 + wave * 16 < na;
   bg_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t xb = x0; xb < x1; xb += 16) {
-    double av[4], bv0[4], bv1[4];
+  for (int64_t xb = x0; xb < x1; xb += 64) {
+    const int64_t gx = xb + lane;
+    const bool xok = gx < x1;
+    const int64_t xc = xok ? gx : x0;
+    double av[16], bv[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t x = xb + 4 * q + kq;
-      const int64_t xc = x < x1 ? x : x0;  // in bounds; masked below
-      av[q] = ap[xc];
-      bv0[q] = bp0[xc];
-      bv1[q] = two ? bp1[xc] : 0.0;
+    for (int i = 0; i < 16; ++i) {
+      const int ar = ab * 64 + wave + 4 * i;
+      av[i] = (double)A[(int64_t)(ar < na ? ar : 0) * len + xc];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool ok = aok && xb + 4 * q + kq < x1;
-      const double a = ok ? av[q] : 0.0;
-      acc0 = bg_mma(a, b0ok ? bv0[q] : 0.0, acc0);
-      if (two) acc1 = bg_mma(a, b1ok ? bv1[q] : 0.0, acc1);
+    for (int i = 0; i < 8; ++i) {
+      const int br = wave + 4 * i;
+      bv[i] = B[(int64_t)(br < nb ? br : 0) * len + xc];
     }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = wave + 4 * i;
+      As[row * kDotLd + lane] = xok && ab * 64 + row < na ? av[i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int row = wave + 4 * i;
+      Bs[row * kDotLd + lane] = xok && row < nb ? bv[i] : 0.0;
+    }
+    __syncthreads();
+    if (active) {
+      const double* ar = As + (wave * 16 + (lane & 15)) * kDotLd + (lane >> 4);
+      const double* b0 = Bs + (lane & 15) * kDotLd + (lane >> 4);
+      const double* b1 = Bs + (16 + (lane & 15)) * kDotLd + (lane >> 4);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double a = ar[4 * q];
+        acc0 = bg_mma(a, b0[4 * q], acc0);
+        if (two) acc1 = bg_mma(a, b1[4 * q], acc1);
+      }
+    }
+    __syncthreads();
   }
-  const int bc = lane & 15;
+  if (!active) return;
+  const int a0 = ab * 64 + wave * 16, bc = lane & 15;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int a = a0 + (lane >> 4) + 4 * v;
@@ -115,9 +133,10 @@ __global__ __launch_bounds__(256) void k_bg_dot_final(const double* __restrict__
 // out = beta win + alpha A H: workgroup of four wavefronts, each 16 consecutive x
 // against all (<= 32) columns; the contraction runs over the na vectors of A in
 // groups of 16 (four matrix-core steps, a = ab + 4q + l/16).
-__global__ __launch_bounds__(256) void k_bg_update(const double* __restrict__ A, int na, const double* __restrict__ H,
-                                                   int64_t sa, int64_t sb, double alpha, const double* win,
-                                                   double beta, double* out, int nb, int64_t len) {
+template <typename AT, typename OT>
+__global__ __launch_bounds__(256) void k_bg_update(const AT* __restrict__ A, int na, const double* __restrict__ H,
+                                                   int64_t sa, int64_t sb, double alpha, const OT* win,
+                                                   double beta, OT* out, int nb, int64_t len) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
   if (x0 >= len) return;
@@ -135,7 +154,7 @@ __global__ __launch_bounds__(256) void k_bg_update(const double* __restrict__ A,
     for (int q = 0; q < 4; ++q) {
       const int a = ab + 4 * q + kq;
       const int ac = a < na ? a : 0;
-      av[q] = A[(int64_t)ac * len + xc];
+      av[q] = (double)A[(int64_t)ac * len + xc];
       hv0[q] = h0[ac * sa];
       hv1[q] = two ? h1[ac * sa] : 0.0;
     }
@@ -153,11 +172,11 @@ __global__ __launch_bounds__(256) void k_bg_update(const double* __restrict__ A,
     if (x >= len) continue;
     if (b0ok) {
       const int64_t o = (int64_t)bc * len + x;
-      out[o] = beta != 0.0 ? beta * win[o] + alpha * acc0[v] : alpha * acc0[v];
+      out[o] = (OT)(beta != 0.0 ? beta * (double)win[o] + alpha * acc0[v] : alpha * acc0[v]);
     }
     if (two && b1ok) {
       const int64_t o = (int64_t)(16 + bc) * len + x;
-      out[o] = beta != 0.0 ? beta * win[o] + alpha * acc1[v] : alpha * acc1[v];
+      out[o] = (OT)(beta != 0.0 ? beta * (double)win[o] + alpha * acc1[v] : alpha * acc1[v]);
     }
   }
 }
@@ -411,6 +430,11 @@ __global__ __launch_bounds__(1024) void k_bg_backsolve(BgLsq L, int ncol, double
   }
 }
 
+__global__ void k_bg_widen(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
 __global__ void k_bg_lsq_start(BgLsq L, const double* __restrict__ R0, const int* __restrict__ m) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= L.ldH * L.s) return;
@@ -422,25 +446,42 @@ __global__ void k_bg_lsq_start(BgLsq L, const double* __restrict__ R0, const int
 
 int64_t bg_dot_part_size() { return (int64_t)(kTargetBlocks + 64) * 64 * kBgMaxCols; }
 
-void launch_bg_dot(const double* A, int na, const double* B, int nb, int64_t len, double* part, double* out,
-                   int ldo, double beta, hipStream_t s, double* outT) {
+template <typename AT>
+void launch_bg_dot(const AT* A, int na, const double* B, int nb, int64_t len, double* part, double* out, int ldo,
+                   double beta, hipStream_t s, double* outT) {
   if (na <= 0 || nb <= 0) return;
   int nch;
   int64_t per;
   dot_chunks(len, na, &nch, &per);
   const int items = nch * ((na + 63) / 64);
   const int grid = (items + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_bg_dot, dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
+  hipLaunchKernelGGL(k_bg_dot<AT>, dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
   const int tot = na * nb;
   hipLaunchKernelGGL(k_bg_dot_final, dim3((tot + 3) / 4), dim3(256), 0, s, part, na, nb, nch, out, ldo, beta, outT);
 }
 
-void launch_bg_update(const double* A, int na, const double* H, int64_t sa, int64_t sb, double alpha,
-                      const double* win, double beta, double* out, int nb, int64_t len, hipStream_t s) {
+template <typename AT, typename OT>
+void launch_bg_update(const AT* A, int na, const double* H, int64_t sa, int64_t sb, double alpha, const OT* win,
+                      double beta, OT* out, int nb, int64_t len, hipStream_t s) {
   if (nb <= 0) return;
   const int64_t blocks = (len + 63) / 64;
-  hipLaunchKernelGGL(k_bg_update, dim3((unsigned)blocks), dim3(256), 0, s, A, na, H, sa, sb, alpha, win, beta, out,
-                     nb, len);
+  hipLaunchKernelGGL((k_bg_update<AT, OT>), dim3((unsigned)blocks), dim3(256), 0, s, A, na, H, sa, sb, alpha, win,
+                     beta, out, nb, len);
+}
+
+template void launch_bg_dot<double>(const double*, int, const double*, int, int64_t, double*, double*, int, double,
+                                    hipStream_t, double*);
+template void launch_bg_dot<float>(const float*, int, const double*, int, int64_t, double*, double*, int, double,
+                                   hipStream_t, double*);
+template void launch_bg_update<double, double>(const double*, int, const double*, int64_t, int64_t, double,
+                                               const double*, double, double*, int, int64_t, hipStream_t);
+template void launch_bg_update<float, double>(const float*, int, const double*, int64_t, int64_t, double,
+                                              const double*, double, double*, int, int64_t, hipStream_t);
+template void launch_bg_update<double, float>(const double*, int, const double*, int64_t, int64_t, double,
+                                              const float*, double, float*, int, int64_t, hipStream_t);
+
+void launch_bg_widen(const float* a, double* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_bg_widen, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
 }
 
 void launch_bg_chol(const double* G, int m, double drop, const int* cnt_in, const double* rprev, int* cnt, double* T,

@@ -3,7 +3,8 @@ Krylov space) against the oracle's block GMRES: block step counts, the per-step
 least-squares residuals of column 0, and the solutions, for Algorithms 1-3, at
 order 6 and at order 16 (the full-width matrix-core tiles), with dependent columns
 (rank deflation), one column, 32 advected sources (nearly dependent columns, the
-batched workload's shape at a smaller grid), the adjoint, and the error paths."""
+batched workload's shape at a smaller grid), the adjoint, block GMRES as the inner
+solve of mixed-precision refinement, and the error paths."""
 import numpy as np
 import pytest
 
@@ -118,11 +119,24 @@ def test_adjoint_block_equals_batched():
     assert (Ub - Up).norm().item() <= 1e-9 * Up.norm().item()
 
 
+@pytest.mark.parametrize("precision", ["MIXED_FP32", "MIXED_BF16"])
+def test_mixed_precision_block(precision):
+    """Block GMRES as the inner solve of the refinement cycles (FP32 / BF16 operators):
+    within 1e-6 of the oracle's block solution, FP64 true residual <= 1e-10."""
+    meth, ctx = _pair(16, 8)
+    F = _sources(meth, 8, 140)
+    print(f"[gpu-block] mixed {precision} m=16 n=8 cols=8", flush=True)
+    Uo, io = meth.solve_block(F, tol=1e-11)
+    Ug, ig = _gpu_solve(ctx, F, tol=1e-10, maxit=200, precision=getattr(smpm, precision), inner_tol=1e-5,
+                        max_refine=30)
+    assert ig.rel_residual <= 1e-10
+    for c in range(F.shape[1]):
+        assert np.linalg.norm(Ug[:, c] - Uo[:, c]) <= 1e-6 * np.linalg.norm(Uo[:, c]), c
+
+
 def test_block_error_paths():
     meth, ctx = _pair(4, 6)
     F = torch.tensor(_sources(meth, 2, 130).T.copy(), dtype=torch.float64, device="cuda")
-    with pytest.raises(smpm.SmpmError):
-        ctx.solve(F, block=True, precision=smpm.MIXED_FP32)
     F33 = F[:1].repeat(33, 1).contiguous()
     with pytest.raises(smpm.SmpmError):
         ctx.solve(F33, block=True)
