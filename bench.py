@@ -230,6 +230,11 @@ def main():
     ap.add_argument("--large-batched-only", action="store_true",
                     help="time only the large stretched grid's 8-column solve in --precision (e.g. for kernel "
                          "traces)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a plain 64 MiB device copy, 20 times: the reference kernel that scales the "
+                         "hardware byte counters")
+    ap.add_argument("--block", action="store_true",
+                    help="with --large-batched-only: block GMRES over the 8 columns")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the metric kernel (no solves), e.g. for hardware-counter runs")
     args = ap.parse_args()
@@ -242,6 +247,14 @@ def main():
     from paper_1601_03432_amd import smpm
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.randn(8 << 20, dtype=torch.float64, device="cuda")  # 64 MiB
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": a.numel() * 8}), flush=True)
+        return
     stream = torch.cuda.current_stream()
     w = wl.workload("c2")
     ctx = smpm.Context.from_workload(w)
@@ -292,9 +305,11 @@ def main():
         F5, G5 = torch.tensor(F5, device="cuda"), torch.tensor(G5, device="cuda")
         ctx5.autotune(8)
         prec = smpm.FP64 if args.precision == "fp64" else smpm.MIXED_FP32
-        sec, info, _ = timed(lambda r: ctx5.solve(r, G5, tol=1e-10, maxit=600, precision=prec, inner_tol=1e-5,
-                                                  max_refine=30), F5, args.steps, args.warmup)
-        print(json.dumps({"form": args.precision + ", large stretched grid, 8 columns", "solves_per_s": 8 / sec,
+        sec, info, _ = timed(lambda r: ctx5.solve(r, G5, tol=1e-10, maxit=200 if args.block else 600,
+                                                  precision=prec, inner_tol=1e-5, max_refine=30, block=args.block),
+                             F5, args.steps, args.warmup)
+        form = args.precision + (" block GMRES" if args.block else " batched") + ", large stretched grid, 8 columns"
+        print(json.dumps({"form": form, "solves_per_s": 8 / sec,
                           "ms_per_step": sec * 1e3, "iterations": info.iterations,
                           "refinements": info.refinements, "true_rel_residual": info.rel_residual}), flush=True)
         return
@@ -390,6 +405,8 @@ def main():
         tbf, ibf, _ = timed(lambda r: s3_mixed(r, smpm.MIXED_BF16), F3, 3, 1)
         # block GMRES: all 32 columns in one block Krylov space (FP64)
         tbk, ibk, u3k = timed(lambda r: c3.solve(r, tol=1e-10, maxit=200, block=True), F3, 2, 1)
+        tbm, ibm, _ = timed(lambda r: c3.solve(r, tol=1e-10, maxit=200, block=True, precision=smpm.MIXED_FP32,
+                                               inner_tol=1e-5, max_refine=30), F3, 2, 1)
         blk_diff = float(max(torch.linalg.norm(u3k[c] - u3b[c]) / torch.linalg.norm(u3b[c]) for c in range(w3.nrhs)))
         out["batched_c3"] = {
             "workload": "c3: 64x64 elements, n=12, [0,1]^2, r=589824, k=193536, d=8064 (substructured coarse "
@@ -407,6 +424,8 @@ def main():
             "fp64_block32_solves_per_s": w3.nrhs / tbk, "fp64_block32_block_steps": ibk.iterations,
             "fp64_block32_refinements": ibk.refinements, "fp64_block32_true_rel_residual_max": ibk.rel_residual,
             "fp64_block32_vs_batched32_rel_l2_max": blk_diff,
+            "mixed_fp32_block32_solves_per_s": w3.nrhs / tbm, "mixed_block32_block_steps": ibm.iterations,
+            "mixed_block32_refinements": ibm.refinements, "mixed_block32_true_rel_residual_max": ibm.rel_residual,
             "autotuned": tuned3,
         }
         del c3, F3, u3b, u3k
@@ -432,6 +451,9 @@ def main():
         t5m, i5m, u5m = timed(lambda r: s5(r, G5, smpm.MIXED_FP32), F5, 2, 1)
         t5h, i5h, _ = timed(lambda r: s5(r, G5, smpm.MIXED_BF16), F5, 1, 1)
         t5k, i5k, u5k = timed(lambda r: ctx5.solve(r, G5, tol=1e-10, maxit=200, block=True), F5, 1, 1)
+        t5km, i5km, u5km = timed(lambda r: ctx5.solve(r, G5, tol=1e-10, maxit=200, block=True,
+                                                      precision=smpm.MIXED_FP32, inner_tol=1e-5, max_refine=30),
+                                 F5, 2, 1)
         out["c5"] = {
             "workload": "c5: 128x128 elements, n=16, x-stretched (ratio 1.05, aspect <= 8) on [0,1]x[0,%.4f], "
                         "r=%d, k=%d, d=%d (substructured coarse solve), 8 random-Fourier sources + nonzero "
@@ -453,9 +475,15 @@ def main():
             "fp64_block8_refinements": i5k.refinements, "fp64_block8_true_rel_residual_max": i5k.rel_residual,
             "fp64_block8_vs_batched8_rel_l2_max": float(max(torch.linalg.norm(u5k[c] - u5b[c]) /
                                                             torch.linalg.norm(u5b[c]) for c in range(8))),
+            "mixed_fp32_block8_solves_per_s": 8 / t5km, "mixed_block8_block_steps": i5km.iterations,
+            "mixed_block8_refinements": i5km.refinements,
+            "mixed_block8_true_rel_residual_max": i5km.rel_residual,
+            "mixed_block8_vs_fp64_batched8_rel_l2_max": float(max(torch.linalg.norm(u5km[c] - u5b[c]) /
+                                                                  torch.linalg.norm(u5b[c]) for c in range(8))),
+            "mixed_block_vs_fp64_single": (8 / t5km) * t51,
             "autotuned": tuned5,
         }
-        del ctx5, F5, G5, u5b, u5m, u5k
+        del ctx5, F5, G5, u5b, u5m, u5k, u5km
         # the three side grids, 8 right-hand sides each, as one concurrent group
         side = []
         for name in wl.C5_SIDE_GRIDS:
