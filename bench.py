@@ -221,6 +221,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 64x64, n=12 batched measurement")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 32x32, n=10 differentiation measurement")
     ap.add_argument("--cpu-solves", type=int, default=2)
     ap.add_argument("--no-paper-study", action="store_true", help="skip the paper's iteration-count study")
     ap.add_argument("--headline-only", action="store_true",
@@ -429,6 +430,59 @@ def main():
             "autotuned": tuned3,
         }
         del c3, F3, u3b, u3k
+
+    if not args.no_c4:
+        # differentiation workload: 32x32 elements, n = 10, FP64; loss |u(f, g) - u_t|^2,
+        # gradient by the differentiable solve (forward solve + adjoint solve), checked by
+        # central differences along 50 unit directions (one 100-column batched solve)
+        w4 = wl.workload("c4")
+        c4 = smpm.Context.from_workload(w4)
+        x4, y4 = c4.node_coords()
+        f4 = torch.tensor(wl.eval_fourier(wl.random_fourier_params(wl.SEED_BASE + 40, 20, 8), x4, y4, 1.0, 1.0),
+                          device="cuda")
+        g4 = torch.tensor(wl.eval_edge(wl.random_edge_params(wl.SEED_BASE + 41), *c4.boundary_arc(), 1.0, 1.0),
+                          device="cuda")
+        ut4 = torch.tensor(wl.eval_fourier(wl.random_fourier_params(wl.SEED_BASE + 42, 20, 8), x4, y4, 1.0, 1.0),
+                           device="cuda")
+
+        def grad4(tol):
+            ft, gt = f4.clone().requires_grad_(True), g4.clone().requires_grad_(True)
+            u = smpm.solve_differentiable(c4, ft, gt, tol=tol, maxit=800)
+            ((u - ut4) ** 2).sum().backward()
+            return ft.grad, gt.grad
+
+        for _ in range(2):
+            grad4(1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 10
+        for _ in range(reps):
+            dfg = grad4(1e-10)
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - t0) / reps
+        tf4, i4, _ = timed(lambda r: c4.solve(r, g4.reshape(1, -1), tol=1e-10, maxit=800), f4.reshape(1, -1), 10, 2)
+        ta4, ia4, _ = timed(lambda r: c4.solve(r, tol=1e-10, maxit=800, transpose=True), ut4.reshape(1, -1), 10, 2)
+        gf, gg = grad4(1e-12)
+        nd, h = 50, 1e-6
+        Df = torch.tensor(wl.random_directions(wl.SEED_BASE + 43, nd, c4.r), device="cuda")
+        Dg = torch.tensor(wl.random_directions(wl.SEED_BASE + 44, nd, c4.nbdry), device="cuda")
+        ad = (Df * gf).sum(dim=1) + (Dg * gg).sum(dim=1)
+        Fp = torch.cat([f4 + h * Df, f4 - h * Df]).contiguous()
+        Gp = torch.cat([g4 + h * Dg, g4 - h * Dg]).contiguous()
+        tfd, ifd, U = timed(lambda r: c4.solve(r, Gp, tol=1e-12, maxit=800), Fp, 1, 1)
+        Lp = ((U - ut4) ** 2).sum(dim=1)
+        fd = (Lp[:nd] - Lp[nd:]) / (2 * h)
+        out["differentiation_c4"] = {
+            "workload": "c4: 32x32 elements, n=10, [0,1]^2, r=%d, FP64; loss |u(f,g) - u_t|^2 with random-Fourier "
+                        "f (seed 160103472), edge data g (160103473), target u_t (160103474)" % c4.r,
+            "gradients_per_s": 1.0 / tg, "ms_per_gradient": tg * 1e3,
+            "forward_solves_per_s": 1.0 / tf4, "forward_iterations": i4.iterations,
+            "adjoint_solves_per_s": 1.0 / ta4, "adjoint_iterations": ia4.iterations,
+            "fd_check": {"directions": nd, "h": h, "tol": 1e-12,
+                         "max_abs_fd_minus_ad_over_max_abs_ad": float((fd - ad).abs().max() / ad.abs().max()),
+                         "batched100_solves_per_s": 2 * nd / tfd, "batched100_iterations_max": ifd.iterations},
+        }
+        del c4, U, Fp, Gp
 
     if not args.no_large:
         out["roofline"] = schur_roofline(ctx5)
