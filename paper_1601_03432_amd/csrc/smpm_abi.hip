@@ -999,8 +999,7 @@ int block_gmres(smpm_ctx* c, int kind, bool tr, const double* b, double* x1, int
       block_cholqr(c, W.w, r, V32 + (int64_t)nv * k, W.t, s);
     else
       block_cholqr(c, W.w, r, W.V + (int64_t)nv * k, W.t, s);
-    launch_bg_lsq(L, n0, r, nv, B.h, ldh, B.R2, B.cnt + 1, B.hres, B.hcnt, s);
-    HIPCHK(hipMemcpyAsync(B.hcnt, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    launch_bg_lsq(L, n0, r, nv, B.h, ldh, B.R2, B.cnt, B.hres, B.hcnt, s);
     HIPCHK(hipStreamSynchronize(s));
     if (B.hcnt[1] != B.hcnt[0]) return fail(SMPM_EHIP, "block orthonormalization lost a vector in its second pass");
     steps = j + 1;

@@ -63,11 +63,12 @@ struct BgLsq {
 };
 
 // Block step: columns n0 .. n0+r-1 of Hbar arrive (h: nv x r, ld ldh, the basis
-// coefficients; R: *cnt x r, ld kBgMaxCols, the new block's coefficients, its rows
-// nv .. nv + *cnt - 1).  Applies the earlier reflections, reduces the new columns,
-// rotates G, sets res and publishes res and *cnt to host memory (pinned).
-void launch_bg_lsq(const BgLsq& L, int n0, int r, int nv, const double* h, int ldh, const double* R, const int* cnt,
-                   double* host_res, int* host_cnt, hipStream_t s);
+// coefficients; R: cnts[1] x r, ld kBgMaxCols, the new block's coefficients, its rows
+// nv .. nv + cnts[1] - 1; cnts: the kept counts of the two Cholesky QR passes).
+// Applies the earlier reflections, reduces the new columns, rotates G, sets res and
+// publishes res (s doubles) and both counts (2 ints) to host memory (pinned).
+void launch_bg_lsq(const BgLsq& L, int n0, int r, int nv, const double* h, int ldh, const double* R,
+                   const int* cnts, double* host_res, int* host_cnt, hipStream_t s);
 
 // Y (ncol x s, ld ldy) = triangle(H)^{-1} G[0 .. ncol)
 void launch_bg_backsolve(const BgLsq& L, int ncol, double* Y, int ldy, hipStream_t s);

@@ -254,12 +254,12 @@ constexpr int kLsqWaves = 16;  // wavefronts of the least-squares kernel
 // long (a column's rows below its diagonal are the r + cnt of its block step).
 __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int r, int nv,
                                                           const double* __restrict__ h, int ldh,
-                                                          const double* __restrict__ R, const int* __restrict__ cntp,
+                                                          const double* __restrict__ R, const int* __restrict__ cnts,
                                                           double* host_res, int* host_cnt) {
   __shared__ double vsh[64];
   __shared__ double bsh;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int cnt = *cntp;
+  const int cnt = cnts[1];
   const int rows = nv + cnt;
   const int s = L.s;
   const int64_t ld = L.ldH;
@@ -378,7 +378,8 @@ __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int 
     }
   }
   if (tid == 0) {
-    host_cnt[0] = cnt;
+    host_cnt[0] = cnts[0];
+    host_cnt[1] = cnt;
   }
 }
 
@@ -489,9 +490,9 @@ void launch_bg_chol(const double* G, int m, double drop, const int* cnt_in, cons
   hipLaunchKernelGGL(k_bg_chol, dim3(1), dim3(256), 0, s, G, m, drop, cnt_in, rprev, cnt, T, R);
 }
 
-void launch_bg_lsq(const BgLsq& L, int n0, int r, int nv, const double* h, int ldh, const double* R, const int* cnt,
-                   double* host_res, int* host_cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_bg_lsq, dim3(1), dim3(64 * kLsqWaves), 0, s, L, n0, r, nv, h, ldh, R, cnt, host_res,
+void launch_bg_lsq(const BgLsq& L, int n0, int r, int nv, const double* h, int ldh, const double* R,
+                   const int* cnts, double* host_res, int* host_cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_bg_lsq, dim3(1), dim3(64 * kLsqWaves), 0, s, L, n0, r, nv, h, ldh, R, cnts, host_res,
                      host_cnt);
 }
 
