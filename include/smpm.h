@@ -59,7 +59,7 @@
  * thread at a time.
  *
  * Errors.  Every int-returning call returns SMPM_OK (0) or a negative
- * smpm_status; smpm_last_error() gives a thread-local message.  A failed call
+ * smpm_status; smpm_last_error(ctx) gives a thread-local message.  A failed call
  * leaves outputs unspecified and the context valid.  Input and output
  * pointers must not alias (smpm_project may run in place).
  */
@@ -372,8 +372,11 @@ int smpm_autotune(smpm_ctx *ctx, int nrhs, void *stream, smpm_tune_result *out);
  * Device pointers; mu and dg must not alias. */
 int smpm_boundary_transpose(smpm_ctx *ctx, const double *mu, double *dg, int nrhs, void *stream);
 
-/* Thread-local text of the last error ("" if none). */
-const char *smpm_last_error(void);
+/* Text of the last error set on the calling thread ("" if none).  The message is
+ * kept per thread, not per context: ctx is accepted for the call shape of the other
+ * entry points and may be NULL (errors raised before a context exists, e.g. by a
+ * failed smpm_setup, are read the same way). */
+const char *smpm_last_error(const smpm_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -1579,7 +1579,7 @@ void smpm_default_opts(smpm_solve_opts* o) {
   o->block = 0;
 }
 
-const char* smpm_last_error(void) { return g_err.c_str(); }
+const char* smpm_last_error(const smpm_ctx*) { return g_err.c_str(); }
 
 int smpm_plan_robin(int m_y, int m_x, int n, const double* xb, const double* yb, double penalty, int robin,
                     smpm_ctx** out) {

@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib = C.CDLL(path)
     vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
     lib.smpm_last_error.restype = C.c_char_p
+    lib.smpm_last_error.argtypes = [C.c_void_p]
     lib.smpm_default_opts.argtypes = [C.POINTER(SolveOpts)]
     lib.smpm_default_opts.restype = None
     lib.smpm_plan.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_double, C.POINTER(vp)]
@@ -117,7 +118,7 @@ def load_library(path: str = LIB_PATH):
 
 def _check(rc):
     if rc != OK:
-        raise SmpmError(rc, _lib.smpm_last_error().decode())
+        raise SmpmError(rc, _lib.smpm_last_error(None).decode())
 
 
 def _dptr(a: np.ndarray):
