@@ -149,9 +149,18 @@ def test_c5_full_size_mixed_8rhs():
     u64, i64 = ctx.solve(Fd, Gd, tol=1e-10, maxit=600)
     print(f"[gpu-c5] fp64: {i64.iterations} iterations, residual {i64.rel_residual:.2e}", flush=True)
     assert im.rel_residual <= 1e-10 and i64.rel_residual <= 1e-10
-    um, u64 = um.cpu().numpy(), u64.cpu().numpy()
+    # block GMRES over the 8 columns, FP64 and as the inner solve of FP32 refinement
+    ub, ib = ctx.solve(Fd, Gd, tol=1e-10, maxit=200, block=True)
+    print(f"[gpu-c5] block fp64: {ib.iterations} block steps, residual {ib.rel_residual:.2e}", flush=True)
+    ubm, ibm = ctx.solve(Fd, Gd, tol=1e-10, maxit=200, block=True, precision=smpm.MIXED_FP32)
+    print(f"[gpu-c5] block mixed: {ibm.iterations} block steps, {ibm.refinements} refinements, "
+          f"residual {ibm.rel_residual:.2e}", flush=True)
+    assert ib.rel_residual <= 1e-10 and ibm.rel_residual <= 1e-10
+    um, u64, ub, ubm = um.cpu().numpy(), u64.cpu().numpy(), ub.cpu().numpy(), ubm.cpu().numpy()
     for c in range(8):
         assert rel(um[c], u64[c]) <= 1e-6
+        assert rel(ub[c], u64[c]) <= 1e-8  # both FP64 solves accepted at a 1e-10 residual
+        assert rel(ubm[c], u64[c]) <= 1e-6
     # the un-reduced equations at sampled elements: corners, walls, the narrowest
     # (most stretched) column and the interior
     grid = O.Grid(w.n, w.x_breaks, w.y_breaks)
@@ -172,6 +181,7 @@ def test_c5_full_size_mixed_8rhs():
     for c in (0, 5):
         rhs = F[c] + T @ G[c]
         ft = rhs - uL * (uL @ rhs)
-        be = _backward_error_at(grid, u64[c], ft, elems)
-        print(f"[gpu-c5] column {c}: sampled componentwise backward error {be:.2e}", flush=True)
-        assert be <= 1e-8
+        for label, u in (("batched", u64), ("block", ub)):
+            be = _backward_error_at(grid, u[c], ft, elems)
+            print(f"[gpu-c5] column {c}, {label}: sampled componentwise backward error {be:.2e}", flush=True)
+            assert be <= 1e-8
