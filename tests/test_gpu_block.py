@@ -61,7 +61,7 @@ def _check_against_oracle(meth, ctx, F, variant, tol):
         if ho[j] > 1e-8:
             assert abs(hg[j] - ho[j]) <= 1e-6 * ho[j], (j, hg[j], ho[j])
     for c in range(F.shape[1]):
-        err = np.linalg.norm(Ug[:, c] - Uo[:, c]) / np.linalg.norm(Uo[:, c])
+        err = np.linalg.norm(Ug[:, c] - Uo[:, c]) / max(np.linalg.norm(Uo[:, c]), 1e-300)
         assert err <= 1e-9, (c, err)
     assert ig.rel_residual <= tol
 
@@ -132,6 +132,30 @@ def test_mixed_precision_block(precision):
     assert ig.rel_residual <= 1e-10
     for c in range(F.shape[1]):
         assert np.linalg.norm(Ug[:, c] - Uo[:, c]) <= 1e-6 * np.linalg.norm(Uo[:, c]), c
+
+
+def test_zero_columns():
+    """A zero column inside the block adds no vector and returns u = 0; an all-zero
+    right-hand side returns u = 0 without a block step."""
+    meth, ctx = _pair(4, 6)
+    F = _sources(meth, 3, 150)
+    F[:, 1] = 0.0
+    _check_against_oracle(meth, ctx, F, 3, 1e-10)
+    U, _ = _gpu_solve(ctx, F, tol=1e-10)
+    assert np.abs(U[:, 1]).max() == 0.0
+    U0, i0 = _gpu_solve(ctx, np.zeros_like(F), tol=1e-10)
+    assert np.abs(U0).max() == 0.0 and i0.iterations == 0
+
+
+def test_non_finite_input_is_rejected():
+    meth, ctx = _pair(4, 6)
+    F = _sources(meth, 2, 160)
+    F[5, 1] = np.nan
+    with pytest.raises(smpm.SmpmError):
+        _gpu_solve(ctx, F, tol=1e-10)
+    # the context stays usable
+    U, info = _gpu_solve(ctx, _sources(meth, 2, 170), tol=1e-10)
+    assert info.rel_residual <= 1e-10
 
 
 def test_block_error_paths():
