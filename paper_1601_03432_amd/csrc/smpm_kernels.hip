@@ -1168,6 +1168,33 @@ __global__ __launch_bounds__(256) void k_precond(DevPlan P, const double* __rest
   block_jacobi_apply<1>(Mp, xs, 0, sb, part, [&](int, int r, Acc v) { yc[P.blk_slots[o + r]] = (double)v; });
 }
 
+// The same for NC columns per workgroup: each block inverse is read once for all of
+// them (block_jacobi_apply<NC> gives every column the bits of the one-column kernel).
+template <typename OpT, int NC>
+__global__ __launch_bounds__(256) void k_precond_n(DevPlan P, const double* __restrict__ x, double* __restrict__ y,
+                                                   int nrhs, int transpose, const int* __restrict__ active) {
+  using Acc = typename AccOf<OpT>::type;
+  __shared__ Acc xs[NC][8 * kMaxN];
+  __shared__ Acc part[NC * 256];
+  const int b = gridDim.x % 8 == 0 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int c0 = blockIdx.y * NC, tid = threadIdx.x;
+  const int o = P.blk_off[b], sb = P.blk_off[b + 1] - o;
+  const int bc = P.blk_cls[b];
+  bool on[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) on[c] = c0 + c < nrhs && (!active || active[c0 + c]);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double* xc = x + (int64_t)(on[c] ? c0 + c : 0) * P.k;
+    for (int i = tid; i < sb; i += 256) xs[c][i] = on[c] ? (Acc)xc[P.blk_slots[o + i]] : Acc(0);
+  }
+  __syncthreads();
+  const OpT* Mp = minv_op<OpT>(P, transpose != 0) + P.bcls_off[bc];
+  block_jacobi_apply<NC>(Mp, &xs[0][0], 8 * kMaxN, sb, part, [&](int c, int r, Acc v) {
+    if (on[c]) y[(int64_t)(c0 + c) * P.k + P.blk_slots[o + r]] = (double)v;
+  });
+}
+
 // ------------------------------------------------------------------ deflation
 
 // c_j = sum of t over the 2n slots of interface j: one wavefront per interface,
@@ -2065,6 +2092,18 @@ void launch_local_adj(const DevPlan& P, const double* c, double* out, int nrhs, 
 
 void launch_precond(const DevPlan& P, const double* x, double* y, int nrhs, bool transpose, const int* active,
                     hipStream_t s, int prec) {
+  if (nrhs > 1) {
+    // four columns per workgroup, each block inverse read once for them
+    const dim3 g4(P.nblk, (nrhs + 3) / 4);
+    const int tr = transpose ? 1 : 0;
+    if (prec == PREC_F32)
+      hipLaunchKernelGGL((k_precond_n<float, 4>), g4, dim3(256), 0, s, P, x, y, nrhs, tr, active);
+    else if (prec == PREC_BF16)
+      hipLaunchKernelGGL((k_precond_n<bf16s, 4>), g4, dim3(256), 0, s, P, x, y, nrhs, tr, active);
+    else
+      hipLaunchKernelGGL((k_precond_n<double, 4>), g4, dim3(256), 0, s, P, x, y, nrhs, tr, active);
+    return;
+  }
   const dim3 g(P.nblk, nrhs);
   if (prec == PREC_F32)
     hipLaunchKernelGGL(k_precond<float>, g, dim3(256), 0, s, P, x, y, transpose ? 1 : 0, active);
