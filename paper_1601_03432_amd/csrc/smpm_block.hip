@@ -43,12 +43,14 @@ void dot_chunks(int64_t len, int na, int* nch, int64_t* per) {
 // first store, clamped into the vectors and masked), then wavefront w multiplies
 // its 16 A rows against both 16-column B tiles in 16 matrix-core steps (step q takes
 // entries 4q .. 4q+3).  part[(b * na + a) * nch + chunk].
-constexpr int kDotLd = 68;  // LDS row stride in doubles (rows land 4 banks apart)
-template <typename AT>
+constexpr int kDotLd = 68;  // LDS row stride in elements (rows land apart in the banks)
+// BR: B rows staged (16 when nb <= 16, else 32); A is staged in its own precision
+template <typename AT, int BR>
 __global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na, const double* __restrict__ B,
                                                 int nb, int64_t len, int64_t per, int nch, int items,
                                                 double* __restrict__ part) {
-  __shared__ double As[64 * kDotLd], Bs[kBgMaxCols * kDotLd];
+  __shared__ AT As[64 * kDotLd];
+  __shared__ double Bs[BR * kDotLd];
   const int ablk = (na + 63) / 64;
   const int per_xcd = (int)(gridDim.x / 8);
   const int item = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
@@ -57,42 +59,43 @@ __global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t x0 = (int64_t)chunk * per;
   const int64_t x1 = min(len, x0 + per);
-  const bool two = nb > 16;
+  const bool two = BR > 16 && nb > 16;
   const bool active = ab * 64 + wave * 16 < na;
   bg_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   for (int64_t xb = x0; xb < x1; xb += 64) {
     const int64_t gx = xb + lane;
     const bool xok = gx < x1;
     const int64_t xc = xok ? gx : x0;
-    double av[16], bv[8];
+    AT av[16];
+    double bv[BR / 4];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int ar = ab * 64 + wave + 4 * i;
-      av[i] = (double)A[(int64_t)(ar < na ? ar : 0) * len + xc];
+      av[i] = A[(int64_t)(ar < na ? ar : 0) * len + xc];
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < BR / 4; ++i) {
       const int br = wave + 4 * i;
       bv[i] = B[(int64_t)(br < nb ? br : 0) * len + xc];
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int row = wave + 4 * i;
-      As[row * kDotLd + lane] = xok && ab * 64 + row < na ? av[i] : 0.0;
+      As[row * kDotLd + lane] = xok && ab * 64 + row < na ? av[i] : AT(0);
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < BR / 4; ++i) {
       const int row = wave + 4 * i;
       Bs[row * kDotLd + lane] = xok && row < nb ? bv[i] : 0.0;
     }
     __syncthreads();
     if (active) {
-      const double* ar = As + (wave * 16 + (lane & 15)) * kDotLd + (lane >> 4);
+      const AT* ar = As + (wave * 16 + (lane & 15)) * kDotLd + (lane >> 4);
       const double* b0 = Bs + (lane & 15) * kDotLd + (lane >> 4);
-      const double* b1 = Bs + (16 + (lane & 15)) * kDotLd + (lane >> 4);
+      const double* b1 = Bs + ((BR > 16 ? 16 : 0) + (lane & 15)) * kDotLd + (lane >> 4);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const double a = ar[4 * q];
+        const double a = (double)ar[4 * q];
         acc0 = bg_mma(a, b0[4 * q], acc0);
         if (two) acc1 = bg_mma(a, b1[4 * q], acc1);
       }
@@ -456,7 +459,10 @@ void launch_bg_dot(const AT* A, int na, const double* B, int nb, int64_t len, do
   dot_chunks(len, na, &nch, &per);
   const int items = nch * ((na + 63) / 64);
   const int grid = (items + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_bg_dot<AT>, dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
+  if (nb <= 16)
+    hipLaunchKernelGGL((k_bg_dot<AT, 16>), dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
+  else
+    hipLaunchKernelGGL((k_bg_dot<AT, 32>), dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
   const int tot = na * nb;
   hipLaunchKernelGGL(k_bg_dot_final, dim3((tot + 3) / 4), dim3(256), 0, s, part, na, nb, nch, out, ldo, beta, outT);
 }
