@@ -3,6 +3,7 @@
 #include "smpm_block.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace smpm {
 
@@ -180,6 +181,72 @@ __global__ __launch_bounds__(256) void k_bg_update(const AT* __restrict__ A, int
     if (two && b1ok) {
       const int64_t o = (int64_t)(16 + bc) * len + x;
       out[o] = (OT)(beta != 0.0 ? beta * (double)win[o] + alpha * acc1[v] : alpha * acc1[v]);
+    }
+  }
+}
+
+// The same product for an FP32 A over an even length: each wavefront takes 32
+// consecutive entries, lane m the pair x0 + 2m, x0 + 2m + 1 with one 8-byte load (so a
+// row load covers a whole 128-byte line), and runs the even entries and the odd ones
+// as two matrix-core tiles.
+template <typename OT>
+__global__ __launch_bounds__(256) void k_bg_update_f2(const float* __restrict__ A, int na,
+                                                      const double* __restrict__ H, int64_t sa, int64_t sb,
+                                                      double alpha, const OT* win, double beta, OT* out, int nb,
+                                                      int64_t len) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * 32;
+  if (x0 >= len) return;
+  const int64_t xp = x0 + 2 * (lane & 15);  // even, and len is even: xp < len covers the pair
+  const bool pok = xp < len;
+  const int64_t xc = pok ? xp : x0;
+  const int kq = lane >> 4, bc = lane & 15;
+  const bool two = nb > 16;
+  const bool b0ok = bc < nb, b1ok = 16 + bc < nb;
+  const double* h0 = H + (b0ok ? bc : 0) * sb;
+  const double* h1 = H + (b1ok ? 16 + bc : 0) * sb;
+  bg_v4d e0 = {0.0, 0.0, 0.0, 0.0}, o0 = {0.0, 0.0, 0.0, 0.0};
+  bg_v4d e1 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
+  for (int ab = 0; ab < na; ab += 16) {
+    float2 av[4];
+    double hv0[4], hv1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = ab + 4 * q + kq;
+      const int ac = a < na ? a : 0;
+      av[q] = *reinterpret_cast<const float2*>(A + (int64_t)ac * len + xc);
+      hv0[q] = h0[ac * sa];
+      hv1[q] = two ? h1[ac * sa] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = pok && ab + 4 * q + kq < na;
+      const double ae = ok ? (double)av[q].x : 0.0, ao = ok ? (double)av[q].y : 0.0;
+      const double g0 = b0ok ? hv0[q] : 0.0;
+      e0 = bg_mma(ae, g0, e0);
+      o0 = bg_mma(ao, g0, o0);
+      if (two) {
+        const double g1 = b1ok ? hv1[q] : 0.0;
+        e1 = bg_mma(ae, g1, e1);
+        o1 = bg_mma(ao, g1, o1);
+      }
+    }
+  }
+  auto put = [&](int b, int64_t x, double v) {
+    const int64_t o = (int64_t)b * len + x;
+    out[o] = (OT)(beta != 0.0 ? beta * (double)win[o] + alpha * v : alpha * v);
+  };
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t xe = x0 + 2 * ((lane >> 4) + 4 * v);
+    if (xe >= len) continue;  // len even: the odd partner is in range too
+    if (b0ok) {
+      put(bc, xe, e0[v]);
+      put(bc, xe + 1, o0[v]);
+    }
+    if (two && b1ok) {
+      put(16 + bc, xe, e1[v]);
+      put(16 + bc, xe + 1, o1[v]);
     }
   }
 }
@@ -471,6 +538,14 @@ template <typename AT, typename OT>
 void launch_bg_update(const AT* A, int na, const double* H, int64_t sa, int64_t sb, double alpha, const OT* win,
                       double beta, OT* out, int nb, int64_t len, hipStream_t s) {
   if (nb <= 0) return;
+  if constexpr (std::is_same<AT, float>::value) {
+    if (len % 2 == 0) {
+      const int64_t blocks2 = (len + 127) / 128;
+      hipLaunchKernelGGL((k_bg_update_f2<OT>), dim3((unsigned)blocks2), dim3(256), 0, s, A, na, H, sa, sb, alpha,
+                         win, beta, out, nb, len);
+      return;
+    }
+  }
   const int64_t blocks = (len + 63) / 64;
   hipLaunchKernelGGL((k_bg_update<AT, OT>), dim3((unsigned)blocks), dim3(256), 0, s, A, na, H, sa, sb, alpha, win,
                      beta, out, nb, len);
