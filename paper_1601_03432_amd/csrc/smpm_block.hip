@@ -114,6 +114,75 @@ __global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na
   }
 }
 
+// A^T B for na <= 16 (the Gram matrices of a block): 16 A rows are staged, and the
+// four wavefronts split every 64-entry step (wavefront w takes entries 16w .. 16w+15
+// in four matrix-core steps), each keeping its own sums: part[(b * na + a) * nch + 4
+// chunk + w] with nch four times the chunk count.
+template <typename AT, int BR>
+__global__ __launch_bounds__(256) void k_bg_dot16(const AT* __restrict__ A, int na, const double* __restrict__ B,
+                                                  int nb, int64_t len, int64_t per, int nch4, int items,
+                                                  double* __restrict__ part) {
+  __shared__ AT As[16 * kDotLd];
+  __shared__ double Bs[BR * kDotLd];
+  const int per_xcd = (int)(gridDim.x / 8);
+  const int chunk = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (chunk >= items) return;  // uniform over the workgroup
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t x0 = (int64_t)chunk * per;
+  const int64_t x1 = min(len, x0 + per);
+  const bool two = BR > 16 && nb > 16;
+  bg_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t xb = x0; xb < x1; xb += 64) {
+    const int64_t gx = xb + lane;
+    const bool xok = gx < x1;
+    const int64_t xc = xok ? gx : x0;
+    AT av[4];
+    double bv[BR / 4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ar = wave + 4 * i;
+      av[i] = A[(int64_t)(ar < na ? ar : 0) * len + xc];
+    }
+#pragma unroll
+    for (int i = 0; i < BR / 4; ++i) {
+      const int br = wave + 4 * i;
+      bv[i] = B[(int64_t)(br < nb ? br : 0) * len + xc];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wave + 4 * i;
+      As[row * kDotLd + lane] = xok && row < na ? av[i] : AT(0);
+    }
+#pragma unroll
+    for (int i = 0; i < BR / 4; ++i) {
+      const int row = wave + 4 * i;
+      Bs[row * kDotLd + lane] = xok && row < nb ? bv[i] : 0.0;
+    }
+    __syncthreads();
+    {
+      const int e0 = 16 * wave + (lane >> 4);
+      const AT* ar = As + (lane & 15) * kDotLd + e0;
+      const double* b0 = Bs + (lane & 15) * kDotLd + e0;
+      const double* b1 = Bs + ((BR > 16 ? 16 : 0) + (lane & 15)) * kDotLd + e0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double a = (double)ar[4 * q];
+        acc0 = bg_mma(a, b0[4 * q], acc0);
+        if (two) acc1 = bg_mma(a, b1[4 * q], acc1);
+      }
+    }
+    __syncthreads();
+  }
+  const int bc = lane & 15, slot = 4 * chunk + wave;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = (lane >> 4) + 4 * v;
+    if (a >= na) continue;
+    if (bc < nb) part[((int64_t)bc * na + a) * nch4 + slot] = acc0[v];
+    if (two && 16 + bc < nb) part[((int64_t)(16 + bc) * na + a) * nch4 + slot] = acc1[v];
+  }
+}
+
 // One wavefront per output: lanes take the chunks c = lane, lane + 64, ... in order,
 // then a fixed butterfly.  out[b * ldo + a] (and, with outT, outT[a * kBgMaxCols + b]).
 __global__ __launch_bounds__(256) void k_bg_dot_final(const double* __restrict__ part, int na, int nb, int nch,
@@ -524,13 +593,26 @@ void launch_bg_dot(const AT* A, int na, const double* B, int nb, int64_t len, do
   int nch;
   int64_t per;
   dot_chunks(len, na, &nch, &per);
+  const int tot = na * nb;
+  if (na <= 16) {
+    // the four wavefronts split each step; their sums stay apart (4 nch partial sums)
+    const int grid16 = (nch + 7) / 8 * 8;
+    if (nb <= 16)
+      hipLaunchKernelGGL((k_bg_dot16<AT, 16>), dim3(grid16), dim3(256), 0, s, A, na, B, nb, len, per, 4 * nch, nch,
+                         part);
+    else
+      hipLaunchKernelGGL((k_bg_dot16<AT, 32>), dim3(grid16), dim3(256), 0, s, A, na, B, nb, len, per, 4 * nch, nch,
+                         part);
+    hipLaunchKernelGGL(k_bg_dot_final, dim3((tot + 3) / 4), dim3(256), 0, s, part, na, nb, 4 * nch, out, ldo, beta,
+                       outT);
+    return;
+  }
   const int items = nch * ((na + 63) / 64);
   const int grid = (items + 7) / 8 * 8;
   if (nb <= 16)
     hipLaunchKernelGGL((k_bg_dot<AT, 16>), dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
   else
     hipLaunchKernelGGL((k_bg_dot<AT, 32>), dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
-  const int tot = na * nb;
   hipLaunchKernelGGL(k_bg_dot_final, dim3((tot + 3) / 4), dim3(256), 0, s, part, na, nb, nch, out, ldo, beta, outT);
 }
 
