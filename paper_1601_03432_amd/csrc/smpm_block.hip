@@ -397,6 +397,7 @@ __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int 
                                                           double* host_res, int* host_cnt) {
   __shared__ double vsh[64];
   __shared__ double bsh;
+  __shared__ double rgrp[64 * 64], bgrp[64];  // 64 earlier reflections at a time
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int cnt = cnts[1];
   const int rows = nv + cnt;
@@ -430,26 +431,27 @@ __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int 
       reg[u] = p + 64 < rows ? col[u][p + 64] : 0.0;
     }
   };
-  // earlier reflections on the new columns; the rows entering the windows during
-  // the next 64 reflections are loaded at once (row p0 + 64 + lane), and each
-  // reflection is loaded one ahead
+  // earlier reflections on the new columns, 64 at a time: the group's reflection
+  // vectors and factors are staged in LDS by the whole workgroup, and the rows
+  // entering the windows during the group are loaded at once (row p0 + 64 + lane)
   double nxt[4] = {0.0, 0.0, 0.0, 0.0};
-  double vn = n0 > 0 ? L.refl[lane] : 0.0;
-  double bn = n0 > 0 ? L.rbeta[0] : 0.0;
   for (int p = 0; p < n0; ++p) {
     if ((p & 63) == 0) {
+      __syncthreads();  // the previous group's reflections are applied
+      const int ng = min(64, n0 - p);
+      for (int i = tid; i < 64 * 64; i += 64 * kLsqWaves)
+        rgrp[i] = i < ng * 64 ? L.refl[(int64_t)p * 64 + i] : 0.0;
+      if (tid < 64) bgrp[tid] = tid < ng ? L.rbeta[p + tid] : 0.0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int q = wave + kLsqWaves * u;
         const int row = p + 64 + lane;
         nxt[u] = own[u] && q < r && row < rows ? col[u][row] : 0.0;
       }
+      __syncthreads();
     }
-    const double v = vn, be = bn;
-    if (p + 1 < n0) {
-      vn = L.refl[(int64_t)(p + 1) * 64 + ((lane - p - 1) & 63)];
-      bn = L.rbeta[p + 1];
-    }
+    const double v = rgrp[(p & 63) * 64 + ((lane - p) & 63)];
+    const double be = bgrp[p & 63];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int q = wave + kLsqWaves * u;
