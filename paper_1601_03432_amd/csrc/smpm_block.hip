@@ -26,9 +26,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int kTargetBlocks = 2048;  // workgroups a dot launch aims for
 constexpr int kMinChunk = 256;       // shortest x chunk of a dot workgroup
 
-void dot_chunks(int64_t len, int na, int* nch, int64_t* per) {
+void dot_chunks(int64_t len, int na, int* nch, int64_t* per, int target = kTargetBlocks) {
   const int64_t ablk = (na + 63) / 64;
-  int64_t want = std::max<int64_t>(1, kTargetBlocks / ablk);
+  int64_t want = std::max<int64_t>(1, target / ablk);
   want = std::min<int64_t>(want, std::max<int64_t>(1, (len + kMinChunk - 1) / kMinChunk));
   int64_t p = (len + want - 1) / want;
   p = (p + 63) / 64 * 64;
@@ -597,7 +597,9 @@ void launch_bg_dot(const AT* A, int na, const double* B, int nb, int64_t len, do
   dot_chunks(len, na, &nch, &per);
   const int tot = na * nb;
   if (na <= 16) {
-    // the four wavefronts split each step; their sums stay apart (4 nch partial sums)
+    // the four wavefronts split each step; their sums stay apart (4 nch partial sums,
+    // so a quarter of the chunks)
+    dot_chunks(len, na, &nch, &per, kTargetBlocks / 4);
     const int grid16 = (nch + 7) / 8 * 8;
     if (nb <= 16)
       hipLaunchKernelGGL((k_bg_dot16<AT, 16>), dim3(grid16), dim3(256), 0, s, A, na, B, nb, len, per, 4 * nch, nch,
