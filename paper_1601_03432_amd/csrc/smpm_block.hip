@@ -45,13 +45,15 @@ void dot_chunks(int64_t len, int na, int* nch, int64_t* per, int target = kTarge
 // its 16 A rows against both 16-column B tiles in 16 matrix-core steps (step q takes
 // entries 4q .. 4q+3).  part[(b * na + a) * nch + chunk].
 constexpr int kDotLd = 68;  // LDS row stride in elements (rows land apart in the banks)
-// BR: B rows staged (16 when nb <= 16, else 32); A is staged in its own precision
+// BR: B rows loaded (8, 16 or 32; the tile has max(BR, 16) rows, those past BR stay
+// zero); A is staged in its own precision
 template <typename AT, int BR>
 __global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na, const double* __restrict__ B,
                                                 int nb, int64_t len, int64_t per, int nch, int items,
                                                 double* __restrict__ part) {
+  constexpr int BT = BR < 16 ? 16 : BR;
   __shared__ AT As[64 * kDotLd];
-  __shared__ double Bs[BR * kDotLd];
+  __shared__ double Bs[BT * kDotLd];
   const int ablk = (na + 63) / 64;
   const int per_xcd = (int)(gridDim.x / 8);
   const int item = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
@@ -62,6 +64,8 @@ __global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na
   const int64_t x1 = min(len, x0 + per);
   const bool two = BR > 16 && nb > 16;
   const bool active = ab * 64 + wave * 16 < na;
+  if (BR < BT)
+    for (int i = tid; i < (BT - BR) * kDotLd; i += 256) Bs[BR * kDotLd + i] = 0.0;  // before the first barrier
   bg_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   for (int64_t xb = x0; xb < x1; xb += 64) {
     const int64_t gx = xb + lane;
@@ -613,7 +617,9 @@ void launch_bg_dot(const AT* A, int na, const double* B, int nb, int64_t len, do
   }
   const int items = nch * ((na + 63) / 64);
   const int grid = (items + 7) / 8 * 8;
-  if (nb <= 16)
+  if (nb <= 8)
+    hipLaunchKernelGGL((k_bg_dot<AT, 8>), dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
+  else if (nb <= 16)
     hipLaunchKernelGGL((k_bg_dot<AT, 16>), dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
   else
     hipLaunchKernelGGL((k_bg_dot<AT, 32>), dim3(grid), dim3(256), 0, s, A, na, B, nb, len, per, nch, items, part);
