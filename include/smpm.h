@@ -124,7 +124,7 @@ typedef struct smpm_solve_opts {
   double inner_tol;   /* mixed precision: inner GMRES tolerance of a refinement cycle (default
                          1e-5).  A cycle aims instead for the reduction that finishes the solve
                          (0.3 tol / residual) when one cycle at the current operator precision
-                         can attain it (down to 1e-7 with FP32 operators, 1e-3 with BF16), so
+                         can attain it (down to 1e-7 with FP32 operators, 1e-6 for block GMRES, 1e-3 with BF16), so
                          two cycles reach 1e-10 where the accuracy of the operators allows     */
   int max_refine;     /* mixed precision: maximum refinement cycles (default 20)                 */
   int graph;          /* 1: the Arnoldi steps run as replays of a captured hipGraph of 8 steps,
