@@ -156,6 +156,12 @@ def test_c5_full_size_mixed_8rhs():
     print(f"[gpu-c5] block mixed: {ibm.iterations} block steps, {ibm.refinements} refinements, "
           f"residual {ibm.rel_residual:.2e}", flush=True)
     assert ib.rel_residual <= 1e-10 and ibm.rel_residual <= 1e-10
+    # a loose inner tolerance must not leave a cycle aiming at a reduction the block
+    # inner solve cannot attain (it once ran that cycle to maxit)
+    _, ibl = ctx.solve(Fd, Gd, tol=1e-10, maxit=200, block=True, precision=smpm.MIXED_FP32, inner_tol=1e-4)
+    print(f"[gpu-c5] block mixed, inner_tol 1e-4: {ibl.iterations} block steps, cycle steps "
+          f"{ibl.cycle_iterations}", flush=True)
+    assert ibl.rel_residual <= 1e-10 and max(ibl.cycle_iterations) < 100
     um, u64, ub, ubm = um.cpu().numpy(), u64.cpu().numpy(), ub.cpu().numpy(), ubm.cpu().numpy()
     for c in range(8):
         assert rel(um[c], u64[c]) <= 1e-6
