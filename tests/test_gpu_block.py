@@ -117,6 +117,10 @@ def test_adjoint_block_equals_batched():
     Ub, _ = ctx.solve(Ft, tol=1e-11, transpose=True, block=True)
     Up, _ = ctx.solve(Ft, tol=1e-11, transpose=True)
     assert (Ub - Up).norm().item() <= 1e-9 * Up.norm().item()
+    # the adjoint with block GMRES as the inner solve of FP32 refinement
+    Um, im = ctx.solve(Ft, tol=1e-10, transpose=True, block=True, precision=smpm.MIXED_FP32)
+    assert im.rel_residual <= 1e-10
+    assert (Um - Up).norm().item() <= 1e-6 * Up.norm().item()
 
 
 @pytest.mark.parametrize("precision", ["MIXED_FP32", "MIXED_BF16"])
