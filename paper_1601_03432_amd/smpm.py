@@ -396,7 +396,7 @@ class Context:
 
 
 def solve_group(contexts, fs, gs=None, tol=1e-10, maxit=400, variant=3, precision=FP64, inner_tol=1e-5,
-                max_refine=20, stream=None, raise_on_noconv=True, graph=True):
+                max_refine=20, stream=None, raise_on_noconv=True, graph=True, block=False):
     """Solve independent problems concurrently (smpm_solve_group): problem i is
     contexts[i].solve(fs[i], gs[i] if gs else None, ...) with shared options.
     Returns [(u_i, Info_i)]."""
@@ -423,7 +423,7 @@ def solve_group(contexts, fs, gs=None, tol=1e-10, maxit=400, variant=3, precisio
     up = arr([u.data_ptr() for u in us])
     gp = None if gl is None else arr([None if g is None else g.data_ptr() for g in gl])
     nr = (C.c_int * n)(*[f.shape[0] for f in fs])
-    opts = SolveOpts(tol, maxit, precision, 0, variant, inner_tol, max_refine, int(graph), 0, 0)
+    opts = SolveOpts(tol, maxit, precision, 0, variant, inner_tol, max_refine, int(graph), 0, 0, int(block))
     infos = (SolveInfo * n)()
     rc = lib.smpm_solve_group(hs, n, fp, gp, up, nr, C.byref(opts), infos, _stream(torch, stream))
     if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
