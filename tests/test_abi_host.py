@@ -147,3 +147,38 @@ def test_dense_coarse_limit_is_capped(monkeypatch):
     st = ctx.stats()
     assert st["has_coarse"] == 1
     assert 0 < st["coarse_bytes"] < ctx.d * ctx.d * 8
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the header's field offsets and sizes
+    (a tiny C program compiled against include/smpm.h prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    mirrors = {"smpm_solve_opts": smpm.SolveOpts, "smpm_solve_info": smpm.SolveInfo,
+               "smpm_plan_stats": smpm.PlanStats, "smpm_tune_result": smpm.TuneResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "smpm.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            if field.endswith("_"):
+                continue  # explicit padding of the mirror
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        cname, field, value = line.split()
+        py = mirrors[cname]
+        want = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert int(value) == want, (cname, field, int(value), want)
+        seen += 1
+    assert seen >= sum(len(p._fields_) for p in mirrors.values())
