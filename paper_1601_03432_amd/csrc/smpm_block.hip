@@ -3,6 +3,7 @@
 #include "smpm_block.h"
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 namespace smpm {
@@ -17,10 +18,29 @@ __device__ __forceinline__ bg_v4d bg_mma(double a, double b, bg_v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Lane move of a double by a DPP control (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes, the same value on every lane.  Inside each row of 16 lanes a
+// butterfly on DPP lane moves (partners lane ^ 1, lane ^ 2, then the half-row and row
+// mirrors, 7 - i and 15 - i), then the four row sums are read as scalars.  Every lane
+// of the wavefront must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_move<0xB1>(v);   // quad permutation 1 0 3 2
+  v += dpp_move<0x4E>(v);   // quad permutation 2 3 0 1
+  v += dpp_move<0x141>(v);  // half-row mirror
+  v += dpp_move<0x140>(v);  // row mirror
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 constexpr int kTargetBlocks = 2048;  // workgroups a dot launch aims for
@@ -45,15 +65,14 @@ void dot_chunks(int64_t len, int na, int* nch, int64_t* per, int target = kTarge
 // its 16 A rows against both 16-column B tiles in 16 matrix-core steps (step q takes
 // entries 4q .. 4q+3).  part[(b * na + a) * nch + chunk].
 constexpr int kDotLd = 68;  // LDS row stride in elements (rows land apart in the banks)
-// BR: B rows loaded (8, 16 or 32; the tile has max(BR, 16) rows, those past BR stay
-// zero); A is staged in its own precision
+// BR: B rows loaded (8, 16 or 32; with 8 the lanes of tile columns 8 .. 15 feed zeros
+// to the matrix cores instead of reading LDS); A is staged in its own precision
 template <typename AT, int BR>
 __global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na, const double* __restrict__ B,
                                                 int nb, int64_t len, int64_t per, int nch, int items,
                                                 double* __restrict__ part) {
-  constexpr int BT = BR < 16 ? 16 : BR;
   __shared__ AT As[64 * kDotLd];
-  __shared__ double Bs[BT * kDotLd];
+  __shared__ double Bs[BR * kDotLd];
   const int ablk = (na + 63) / 64;
   const int per_xcd = (int)(gridDim.x / 8);
   const int item = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
@@ -64,8 +83,6 @@ __global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na
   const int64_t x1 = min(len, x0 + per);
   const bool two = BR > 16 && nb > 16;
   const bool active = ab * 64 + wave * 16 < na;
-  if (BR < BT)
-    for (int i = tid; i < (BT - BR) * kDotLd; i += 256) Bs[BR * kDotLd + i] = 0.0;  // before the first barrier
   bg_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   for (int64_t xb = x0; xb < x1; xb += 64) {
     const int64_t gx = xb + lane;
@@ -96,12 +113,13 @@ __global__ __launch_bounds__(256) void k_bg_dot(const AT* __restrict__ A, int na
     __syncthreads();
     if (active) {
       const AT* ar = As + (wave * 16 + (lane & 15)) * kDotLd + (lane >> 4);
-      const double* b0 = Bs + (lane & 15) * kDotLd + (lane >> 4);
+      const bool bz = BR < 16 && (lane & 15) >= BR;  // tile column past the loaded rows
+      const double* b0 = Bs + ((lane & 15) % BR) * kDotLd + (lane >> 4);
       const double* b1 = Bs + ((BR > 16 ? 16 : 0) + (lane & 15)) * kDotLd + (lane >> 4);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const double a = (double)ar[4 * q];
-        acc0 = bg_mma(a, b0[4 * q], acc0);
+        acc0 = bg_mma(a, bz ? 0.0 : b0[4 * q], acc0);
         if (two) acc1 = bg_mma(a, b1[4 * q], acc1);
       }
     }
@@ -131,7 +149,7 @@ __global__ __launch_bounds__(256) void k_bg_dot16(const AT* __restrict__ A, int 
   const int per_xcd = (int)(gridDim.x / 8);
   const int chunk = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
   if (chunk >= items) return;  // uniform over the workgroup
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int64_t x0 = (int64_t)chunk * per;
   const int64_t x1 = min(len, x0 + per);
   const bool two = BR > 16 && nb > 16;
@@ -214,7 +232,7 @@ template <typename AT, typename OT>
 __global__ __launch_bounds__(256) void k_bg_update(const AT* __restrict__ A, int na, const double* __restrict__ H,
                                                    int64_t sa, int64_t sb, double alpha, const OT* win,
                                                    double beta, OT* out, int nb, int64_t len) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
   if (x0 >= len) return;
   const int64_t xr = x0 + (lane & 15);
@@ -262,19 +280,19 @@ __global__ __launch_bounds__(256) void k_bg_update(const AT* __restrict__ A, int
 // consecutive entries, lane m the pair x0 + 2m, x0 + 2m + 1 with one 8-byte load (so a
 // row load covers a whole 128-byte line), and runs the even entries and the odd ones
 // as two matrix-core tiles.
-template <typename OT>
+template <typename OT, bool TWO>
 __global__ __launch_bounds__(256) void k_bg_update_f2(const float* __restrict__ A, int na,
                                                       const double* __restrict__ H, int64_t sa, int64_t sb,
                                                       double alpha, const OT* win, double beta, OT* out, int nb,
                                                       int64_t len) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * 32;
   if (x0 >= len) return;
   const int64_t xp = x0 + 2 * (lane & 15);  // even, and len is even: xp < len covers the pair
   const bool pok = xp < len;
   const int64_t xc = pok ? xp : x0;
   const int kq = lane >> 4, bc = lane & 15;
-  const bool two = nb > 16;
+  const bool two = TWO && nb > 16;  // a second 16-column tile (TWO false: none, fewer registers)
   const bool b0ok = bc < nb, b1ok = 16 + bc < nb;
   const double* h0 = H + (b0ok ? bc : 0) * sb;
   const double* h1 = H + (b1ok ? 16 + bc : 0) * sb;
@@ -592,13 +610,37 @@ __global__ void k_bg_lsq_start(BgLsq L, const double* __restrict__ R0, const int
 
 int64_t bg_dot_part_size() { return (int64_t)(kTargetBlocks + 64) * 64 * kBgMaxCols; }
 
+constexpr int kMaxDevices = 64;
+
+// Workgroup count a k_bg_dot<AT, BR> launch aims for: the largest whole number of
+// rounds of the workgroups the device holds at once that fits in kTargetBlocks (a
+// partial last round leaves most of the chip idle at the end).  Per device, computed
+// once; kTargetBlocks where the query fails.
+template <typename AT, int BR>
+int dot_target() {
+  static std::atomic<int> cache[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return kTargetBlocks;
+  int t = cache[dev].load(std::memory_order_relaxed);
+  if (t == 0) {
+    int per_cu = 0, ncu = 0;
+    t = kTargetBlocks;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bg_dot<AT, BR>, 256, 0) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+      const int cap = per_cu * ncu;
+      if (cap > 0 && cap <= kTargetBlocks) t = kTargetBlocks / cap * cap;
+    }
+    cache[dev].store(t, std::memory_order_relaxed);
+  }
+  return t;
+}
+
 template <typename AT>
 void launch_bg_dot(const AT* A, int na, const double* B, int nb, int64_t len, double* part, double* out, int ldo,
                    double beta, hipStream_t s, double* outT) {
   if (na <= 0 || nb <= 0) return;
   int nch;
   int64_t per;
-  dot_chunks(len, na, &nch, &per);
   const int tot = na * nb;
   if (na <= 16) {
     // the four wavefronts split each step; their sums stay apart (4 nch partial sums,
@@ -615,6 +657,8 @@ void launch_bg_dot(const AT* A, int na, const double* B, int nb, int64_t len, do
                        outT);
     return;
   }
+  const int target = nb <= 8 ? dot_target<AT, 8>() : nb <= 16 ? dot_target<AT, 16>() : dot_target<AT, 32>();
+  dot_chunks(len, na, &nch, &per, target);
   const int items = nch * ((na + 63) / 64);
   const int grid = (items + 7) / 8 * 8;
   if (nb <= 8)
@@ -633,8 +677,12 @@ void launch_bg_update(const AT* A, int na, const double* H, int64_t sa, int64_t 
   if constexpr (std::is_same<AT, float>::value) {
     if (len % 2 == 0) {
       const int64_t blocks2 = (len + 127) / 128;
-      hipLaunchKernelGGL((k_bg_update_f2<OT>), dim3((unsigned)blocks2), dim3(256), 0, s, A, na, H, sa, sb, alpha,
-                         win, beta, out, nb, len);
+      if (nb > 16)
+        hipLaunchKernelGGL((k_bg_update_f2<OT, true>), dim3((unsigned)blocks2), dim3(256), 0, s, A, na, H, sa, sb,
+                           alpha, win, beta, out, nb, len);
+      else
+        hipLaunchKernelGGL((k_bg_update_f2<OT, false>), dim3((unsigned)blocks2), dim3(256), 0, s, A, na, H, sa, sb,
+                           alpha, win, beta, out, nb, len);
       return;
     }
   }
