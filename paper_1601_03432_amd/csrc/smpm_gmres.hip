@@ -73,9 +73,29 @@ constexpr bool kNT = Tag::value;
 constexpr int kWaves = kThreads / 64;
 constexpr int kDotUnroll = 8;
 
+// Lane move of a double by a DPP control (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes, the same value on every lane: a butterfly inside each row of
+// 16 lanes on DPP lane moves (partners lane ^ 1, lane ^ 2, then the half-row and row
+// mirrors), then the four row sums read as scalars.  A fixed order, so every kernel
+// that reduces the same lanes gets the same bits.  All 64 lanes must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v += dpp_move<0xB1>(v);   // quad permutation 1 0 3 2
+  v += dpp_move<0x4E>(v);   // quad permutation 2 3 0 1
+  v += dpp_move<0x141>(v);  // half-row mirror
+  v += dpp_move<0x140>(v);  // row mirror
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
