@@ -17,6 +17,31 @@ namespace smpm {
 
 namespace {
 
+// Lane move of a double by a DPP control (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes, the same value on every lane: a butterfly inside each row of
+// 16 lanes on DPP lane moves (partners lane ^ 1, lane ^ 2, then the half-row and row
+// mirrors), then the four row sums read as scalars.  A fixed order.  All 64 lanes
+// must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad permutation 1 0 3 2
+  v += dpp_move<0x4E>(v);   // quad permutation 2 3 0 1
+  v += dpp_move<0x141>(v);  // half-row mirror
+  v += dpp_move<0x140>(v);  // row mirror
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 __device__ __forceinline__ int side_node(int n, int s, int t) {
   return s == 0 ? t * n : s == 1 ? t * n + (n - 1) : s == 2 ? t : (n - 1) * n + t;
 }
@@ -1224,7 +1249,7 @@ __global__ __launch_bounds__(256) void k_iface_sum(DevPlan P, const double* __re
   if (l == 0) c[(int64_t)col * P.d + j] = acc;
 }
 
-// c2 = G c (or G^T c): one wavefront per row, lanes over the row, fixed shuffle tree.
+// c2 = G c (or G^T c): one wavefront per row, lanes over the row, fixed reduction tree.
 __global__ __launch_bounds__(256) void k_coarse(DevPlan P, const double* __restrict__ c, double* __restrict__ c2,
                                                 int transpose, const int* __restrict__ active) {
   const int col = blockIdx.y;
@@ -1237,7 +1262,7 @@ __global__ __launch_bounds__(256) void k_coarse(DevPlan P, const double* __restr
   const double* cc = c + (int64_t)col * d;
   double acc = 0.0;
   for (int j = lane; j < d; j += 64) acc = fma(Gp[j], cc[j], acc);
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  acc = wave_sum(acc);
   if (lane == 0) c2[(int64_t)col * d + i] = acc;
 }
 
@@ -1471,7 +1496,7 @@ __global__ __launch_bounds__(256) void k_coarse_sides(DevPlan P, const double* _
     for (int u = 0; u < 8; ++u)
       if (j0 + u * 64 < d) acc = fma(g[u], cs[j0 + u * 64], acc);
   }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  acc = wave_sum(acc);
   if (lane == 0) c2[(int64_t)col * d + i] = acc;
 }
 
@@ -1569,7 +1594,7 @@ constexpr int kChunk = 2048;   // elements per reduction chunk (256 threads x 8)
 constexpr int kVecGroup = 8;   // vectors per block in the multi-dot
 
 __device__ __forceinline__ double block_sum_256(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  v = wave_sum(v);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
   if (lane == 0) red[wave] = v;
