@@ -446,17 +446,17 @@ __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int 
     const int row = base + ((lane - base) & 63);
     reg[u] = own[u] && row < rows ? col[u][row] : 0.0;
   }
-  // advance the window of slot u past row p
+  // advance the window of slot u past row p, to the row loaded ahead into nxt[u]
+  double nxt[4] = {0.0, 0.0, 0.0, 0.0};
   auto advance = [&](int u, int p) {
     if (lane == (p & 63)) {
       col[u][p] = reg[u];
-      reg[u] = p + 64 < rows ? col[u][p + 64] : 0.0;
+      reg[u] = nxt[u];
     }
   };
   // earlier reflections on the new columns, 64 at a time: the group's reflection
   // vectors and factors are staged in LDS by the whole workgroup, and the rows
   // entering the windows during the group are loaded at once (row p0 + 64 + lane)
-  double nxt[4] = {0.0, 0.0, 0.0, 0.0};
   for (int p = 0; p < n0; ++p) {
     if ((p & 63) == 0) {
       __syncthreads();  // the previous group's reflections are applied
@@ -488,7 +488,15 @@ __global__ __launch_bounds__(64 * kLsqWaves) void k_bg_lsq(BgLsq L, int n0, int 
       }
     }
   }
-  // the new columns' own reflections, applied to the later new columns and to G
+  // the new columns' own reflections, applied to the later new columns and to G.  The
+  // windows hold rows n0 .. n0+63 (lane l row n0 + ((l - n0) & 63)); the rows entering
+  // them during these r < 64 steps are p + 64 for p < n0 + r, which nothing here
+  // writes, so they are loaded at once
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int pl = n0 + ((lane - n0) & 63);
+    nxt[u] = own[u] && pl < n0 + r && pl + 64 < rows ? col[u][pl + 64] : 0.0;
+  }
   for (int c = 0; c < r; ++c) {
     const int p = n0 + c;
     const int t = (lane - p) & 63;
