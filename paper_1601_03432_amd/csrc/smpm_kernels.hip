@@ -1395,8 +1395,7 @@ __global__ __launch_bounds__(256) void k_sub_sep(DevPlan P, double* __restrict__
     const int a = a0 + q;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      double v = acc[q][c];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      const double v = wave_sum(acc[q][c]);
       if (lane == 0 && on[c] && a < nS) {
         if (a < P.sub_nsep)
           c2[(int64_t)(c0 + c) * P.d + P.sub_sep_iface[a]] = v;
