@@ -342,6 +342,54 @@ __global__ __launch_bounds__(256) void k_bg_update_f2(const float* __restrict__ 
   }
 }
 
+// The same product for an FP32 A, an even length and at most 8 columns, on FP64
+// vector FMAs: a 16-column matrix-core tile would spend half its products on absent
+// columns, and the vector units have the same FP64 rate.  Lane m takes the pair
+// 2m, 2m + 1 of its workgroup's 512 entries (one 8-byte load per row) and keeps both
+// entries' sums for every column; H is read as scalars (uniform over the
+// wavefront).  Each sum runs over the rows of A in increasing order.
+template <typename OT>
+__global__ __launch_bounds__(256) void k_bg_update_v8(const float* __restrict__ A, int na,
+                                                      const double* __restrict__ H, int64_t sa, int64_t sb,
+                                                      double alpha, const OT* win, double beta, OT* out, int nb,
+                                                      int64_t len) {
+  const int64_t xp = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
+  if (xp >= len) return;  // len even: xp + 1 < len as well
+  double e[8], o[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) e[b] = o[b] = 0.0;
+  auto rows = [&](const float2* av, int a0, int cnt) {
+    for (int u = 0; u < cnt; ++u) {
+      const double ae = (double)av[u].x, ao = (double)av[u].y;
+      const double* hr = H + (int64_t)(a0 + u) * sa;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const double h = b < nb ? hr[b * sb] : 0.0;
+        e[b] = fma(ae, h, e[b]);
+        o[b] = fma(ao, h, o[b]);
+      }
+    }
+  };
+  int a = 0;
+  for (; a + 8 <= na; a += 8) {
+    float2 av[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) av[u] = *reinterpret_cast<const float2*>(A + (int64_t)(a + u) * len + xp);
+    rows(av, a, 8);
+  }
+  for (; a < na; ++a) {
+    const float2 av = *reinterpret_cast<const float2*>(A + (int64_t)a * len + xp);
+    rows(&av, a, 1);
+  }
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    if (b >= nb) break;
+    const int64_t q = (int64_t)b * len + xp;
+    out[q] = (OT)(beta != 0.0 ? beta * (double)win[q] + alpha * e[b] : alpha * e[b]);
+    out[q + 1] = (OT)(beta != 0.0 ? beta * (double)win[q + 1] + alpha * o[b] : alpha * o[b]);
+  }
+}
+
 // Cholesky QR pass (one workgroup; see launch_bg_chol), right-looking: once column i
 // yields a vector, the remaining Gram entries and the remaining columns' coefficient
 // vectors (Es column l = e_l minus its parts on the kept vectors) are updated at once.
@@ -683,6 +731,11 @@ void launch_bg_update(const AT* A, int na, const double* H, int64_t sa, int64_t 
                       double beta, OT* out, int nb, int64_t len, hipStream_t s) {
   if (nb <= 0) return;
   if constexpr (std::is_same<AT, float>::value) {
+    if (len % 2 == 0 && nb <= 8) {
+      hipLaunchKernelGGL((k_bg_update_v8<OT>), dim3((unsigned)((len + 511) / 512)), dim3(256), 0, s, A, na, H, sa,
+                         sb, alpha, win, beta, out, nb, len);
+      return;
+    }
     if (len % 2 == 0) {
       const int64_t blocks2 = (len + 127) / 128;
       if (nb > 16)
