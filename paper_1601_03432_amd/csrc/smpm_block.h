@@ -1,7 +1,8 @@
 // Kernels of block GMRES: every right-hand side of the deflated Schur system
 // (Algorithm 3 step 4) in one block Krylov space.  The Gram-Schmidt sums and updates
-// of a block against the shared basis are tall-skinny products on FP64 matrix
-// cores; the block's own orthonormalization is Cholesky QR applied twice with rank
+// of a block against the shared basis are tall-skinny products on FP64 matrix cores
+// (the update of at most 8 columns against an FP32 basis on FP64 vector FMAs); the
+// block's own orthonormalization is Cholesky QR applied twice with rank
 // deflation; the block Hessenberg least-squares problem is updated by Householder
 // reflections in one workgroup.  Vectors are column-blocked: vector i of a set
 // starts at i * len.
