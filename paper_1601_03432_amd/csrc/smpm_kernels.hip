@@ -30,15 +30,21 @@ __device__ __forceinline__ double read_lane(double v, int l) {
                           __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// Sum over the 64 lanes, the same value on every lane: a butterfly inside each row of
-// 16 lanes on DPP lane moves (partners lane ^ 1, lane ^ 2, then the half-row and row
-// mirrors), then the four row sums read as scalars.  A fixed order.  All 64 lanes
-// must be active.
-__device__ __forceinline__ double wave_sum(double v) {
+// Sum over each row of 16 lanes, the same value on the row's lanes: a butterfly on
+// DPP lane moves (partners lane ^ 1, lane ^ 2, then the half-row and row mirrors,
+// 7 - i and 15 - i).  A fixed order.
+__device__ __forceinline__ double row_sum16(double v) {
   v += dpp_move<0xB1>(v);   // quad permutation 1 0 3 2
   v += dpp_move<0x4E>(v);   // quad permutation 2 3 0 1
   v += dpp_move<0x141>(v);  // half-row mirror
   v += dpp_move<0x140>(v);  // row mirror
+  return v;
+}
+
+// Sum over the 64 lanes, the same value on every lane: the row sums, then the four
+// of them read as scalars.  A fixed order.  All 64 lanes must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_sum16(v);
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
@@ -393,9 +399,7 @@ __global__ __launch_bounds__(256) void k_schur_mfma(DevPlan P, const double* __r
           for (int s = 0; s < 4; ++s)
             if (s < s_lo || s > s_hi) pp[s * kWaves + wave] = 0.0;
         for (int s = s_lo; s <= s_hi; ++s) {
-          double x = slot[v] >= 0 && srow == s ? tv : 0.0;
-#pragma unroll
-          for (int m = 1; m < 16; m <<= 1) x += __shfl_xor(x, m);
+          const double x = row_sum16(slot[v] >= 0 && srow == s ? tv : 0.0);
           if (row == 0) pp[s * kWaves + wave] = x;
         }
       }
